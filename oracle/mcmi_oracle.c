@@ -1,0 +1,764 @@
+/*
+ * mcmi_oracle.c - plain, slow, FP64 CPU oracle for the Monte Carlo sparse
+ * approximate inverse (Markov Chain Monte Carlo Matrix Inversion).
+ *
+ * TEST INFRASTRUCTURE ONLY. Only the tests, the smoke check and the benchmark's
+ * CPU-baseline leg may load this library. It shares no code, header, table or
+ * constant generator with the HIP library; the two meet only in the seeded
+ * input matrices.
+ *
+ * What it computes, in the paper's order (Section III-A, eq. (2); Section IV,
+ * phases 2-4; Section IV-A for the column scaling):
+ *   O1  iteration matrix   C = I - D^-1 B, c_ij = (-b_ij) / b_ii, zeros dropped
+ *   O2  transition CDF     p_ij proportional to |c_ij| (the paper never defines P;
+ *                          this is the "almost optimal" choice), quantized to
+ *                          integer weights so both sides sample the same Chat
+ *   O3  random numbers     Philox4x32-10 (Salmon et al., SC'11), counter-based
+ *   O4  walk               eq. (2): W_0 = 1 at s_0 = r, W_j = W_{j-1} c/p; stop
+ *                          when the next weight falls below delta (checked before
+ *                          the draw) or the row of C is empty
+ *   O5  accumulate         sum of W_j over chains per (r, s_j), long double
+ *   O6  finalize           N_rc = acc / N_r; keep iff c = r or |N_rc| >= eps;
+ *                          M_rc = N_rc / d_c (column scaling by the diagonal)
+ *   O7  apply              y = M x
+ * plus the two per-row side products of the learned allocation:
+ *   pilot variance (total variance of a chain's row estimate, mean chain length)
+ *   row features (8 per row).
+ *
+ * Every floating-point step is one IEEE operation in source order; build with
+ * -ffp-contract=off and without -ffast-math so nothing is fused or reordered.
+ * Parity of the pilot and feature side products against the paper is
+ * unpinned by any printed value (the paper has neither); they are pinned by
+ * closed forms in the tests.
+ */
+#include <math.h>
+#include <pthread.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define ORC_OK 0
+#define ORC_ERR_ARG -1
+#define ORC_ERR_CSR -2
+#define ORC_ERR_ZERO_DIAG -3
+#define ORC_ERR_NOT_CONTRACTIVE -4
+#define ORC_ERR_NOMEM -7
+
+#define ORC_LMAX_CAP 65536
+
+/* ------------------------------------------------------------------ Philox */
+/* Philox4x32 with 10 rounds as defined in Salmon, Moraes, Dror, Shaw,
+ * "Parallel random numbers: as easy as 1, 2, 3" (SC'11): each round multiplies
+ * words 0 and 2 by two fixed 32-bit multipliers, and rebuilds the block from
+ * the high/low halves xor'ed with words 1, 3 and the round key; the key is
+ * bumped by two Weyl constants between rounds. */
+static void orc_philox(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4])
+{
+    uint32_t x0 = ctr[0], x1 = ctr[1], x2 = ctr[2], x3 = ctr[3];
+    uint32_t k0 = key[0], k1 = key[1];
+    for (int round = 0; round < 10; ++round) {
+        if (round > 0) {
+            k0 += 0x9E3779B9u;
+            k1 += 0xBB67AE85u;
+        }
+        uint64_t p0 = (uint64_t)0xD2511F53u * (uint64_t)x0;
+        uint64_t p1 = (uint64_t)0xCD9E8D57u * (uint64_t)x2;
+        uint32_t hi0 = (uint32_t)(p0 >> 32), lo0 = (uint32_t)p0;
+        uint32_t hi1 = (uint32_t)(p1 >> 32), lo1 = (uint32_t)p1;
+        uint32_t y0 = hi1 ^ x1 ^ k0;
+        uint32_t y2 = hi0 ^ x3 ^ k1;
+        x0 = y0;
+        x1 = lo1;
+        x2 = y2;
+        x3 = lo0;
+    }
+    out[0] = x0;
+    out[1] = x1;
+    out[2] = x2;
+    out[3] = x3;
+}
+
+/* Exposed for the pin against an independent Philox implementation. */
+void orc_philox4x32_10(const uint32_t *ctr, const uint32_t *key, uint32_t *out)
+{
+    orc_philox(ctr, key, out);
+}
+
+/* -------------------------------------------------------- O1 + O2: C, CDF */
+/* The oracle's view of C and its sampling tables, natural column order. */
+typedef struct {
+    int64_t n;
+    int64_t *cptr;    /* n+1: row i of C is entries [cptr[i], cptr[i+1]) */
+    int32_t *ccol;    /* column of each entry, ascending within a row */
+    double *cval;     /* c_ij (exact, unquantized) */
+    uint32_t *cum;    /* inclusive prefix sum of the integer weights */
+    uint32_t *wsum;   /* n: W_i = total integer weight of row i */
+    double *shat;     /* n: Shat_i = a_max * W_i * 2^-Q (one rounding) */
+    double *diag;     /* n: d_i = b_ii */
+    double norm_inf;  /* max_i Shat_i */
+} orc_mat;
+
+static int ceil_log2_u64(uint64_t m)
+{
+    int q = 0;
+    while (((uint64_t)1 << q) < m)
+        ++q;
+    return q;
+}
+
+/* Count entries of C per row (for the caller's allocation). Validates B.
+ * Returns ORC_OK and *nnz_c, or an error code. */
+int orc_count_c(int64_t n, const int64_t *rp, const int32_t *ci, const double *v, int64_t *nnz_c)
+{
+    if (n <= 0 || !rp || !ci || !v || !nnz_c)
+        return ORC_ERR_ARG;
+    if (rp[0] != 0)
+        return ORC_ERR_CSR;
+    int64_t total = 0;
+    for (int64_t i = 0; i < n; ++i) {
+        if (rp[i + 1] < rp[i])
+            return ORC_ERR_CSR;
+        int have_diag = 0;
+        for (int64_t k = rp[i]; k < rp[i + 1]; ++k) {
+            if (ci[k] < 0 || ci[k] >= n)
+                return ORC_ERR_CSR;
+            if (k > rp[i] && ci[k] <= ci[k - 1])
+                return ORC_ERR_CSR;
+            if (ci[k] == i) {
+                have_diag = 1;
+                if (v[k] == 0.0)
+                    return ORC_ERR_ZERO_DIAG;
+            }
+        }
+        if (!have_diag)
+            return ORC_ERR_ZERO_DIAG;
+        for (int64_t k = rp[i]; k < rp[i + 1]; ++k)
+            if (ci[k] != i && v[k] != 0.0)
+                total += 1;
+    }
+    *nnz_c = total;
+    return ORC_OK;
+}
+
+/* Fill C and its CDF into caller-owned arrays sized by orc_count_c. */
+int orc_build(int64_t n, const int64_t *rp, const int32_t *ci, const double *v,
+              int64_t *cptr, int32_t *ccol, double *cval, uint32_t *cum,
+              uint32_t *wsum, double *shat, double *diag, double *norm_inf)
+{
+    int64_t nnz_c = 0;
+    int st = orc_count_c(n, rp, ci, v, &nnz_c);
+    if (st != ORC_OK)
+        return st;
+    double nrm = 0.0;
+    int64_t pos = 0;
+    for (int64_t i = 0; i < n; ++i) {
+        double d = 0.0;
+        for (int64_t k = rp[i]; k < rp[i + 1]; ++k)
+            if (ci[k] == i)
+                d = v[k];
+        diag[i] = d;
+        cptr[i] = pos;
+        /* O1: c_ij = (-b_ij) / b_ii, entries equal to zero are dropped */
+        for (int64_t k = rp[i]; k < rp[i + 1]; ++k) {
+            if (ci[k] == i)
+                continue;
+            double c = (-v[k]) / d;
+            if (c == 0.0)
+                continue;
+            ccol[pos] = ci[k];
+            cval[pos] = c;
+            ++pos;
+        }
+        int64_t m = pos - cptr[i];
+        if (m == 0) {
+            wsum[i] = 0;
+            shat[i] = 0.0;
+            continue;
+        }
+        /* O2: a_k = |c_k|, a_max, Q = 31 - ceil(log2 m),
+         *     w_k = max(1, floor(2^Q a_k / a_max)), cum = running sum. */
+        double amax = 0.0;
+        for (int64_t k = cptr[i]; k < pos; ++k)
+            if (fabs(cval[k]) > amax)
+                amax = fabs(cval[k]);
+        int q = 31 - ceil_log2_u64((uint64_t)m);
+        uint64_t run = 0;
+        for (int64_t k = cptr[i]; k < pos; ++k) {
+            double ratio = fabs(cval[k]) / amax;
+            double scaled = floor(ldexp(ratio, q));
+            uint64_t w = (uint64_t)scaled;
+            if (w < 1)
+                w = 1;
+            run += w;
+            cum[k] = (uint32_t)run;
+        }
+        if (run >= ((uint64_t)1 << 32))
+            return ORC_ERR_ARG; /* cannot happen: sum <= 2^31 */
+        wsum[i] = (uint32_t)run;
+        shat[i] = ldexp(amax * (double)run, -q);
+        if (shat[i] > nrm)
+            nrm = shat[i];
+    }
+    cptr[n] = pos;
+    *norm_inf = nrm;
+    return ORC_OK;
+}
+
+/* L_max: max_len if given; otherwise the smallest L with p_L < delta, where
+ * p_0 = 1 and p_j = p_{j-1} * ||Chat||_inf (one IEEE product per step). */
+int orc_lmax(double norm_inf, double delta, int max_len)
+{
+    if (max_len > 0)
+        return max_len > ORC_LMAX_CAP ? ORC_ERR_ARG : max_len;
+    if (!(norm_inf < 1.0))
+        return ORC_ERR_NOT_CONTRACTIVE;
+    if (!(delta > 0.0))
+        return ORC_ERR_ARG;
+    double p = 1.0;
+    int L = 0;
+    while (p >= delta) {
+        p = p * norm_inf;
+        ++L;
+        if (L > ORC_LMAX_CAP)
+            return ORC_ERR_ARG;
+    }
+    return L;
+}
+
+/* ------------------------------------------------------------- O3 + O4 */
+typedef struct {
+    uint64_t seed;
+    double delta, eps;
+    int32_t chains;       /* uniform N_r when chains_per_row is NULL */
+    int32_t fp32;         /* 1: binary32 weights, Shat32 and delta compare */
+    int32_t max_len;      /* 0: derive L_max from ||Chat||_inf */
+    uint32_t tag;         /* fourth Philox counter word */
+    int32_t threads;
+    int32_t filter_on_m;  /* 1: keep iff |M_rc| >= eps instead of |N_rc| >= eps */
+} orc_params;
+
+/* Draw step j >= 1 of chain c of row r: returns the chosen entry index of row s. */
+typedef struct {
+    uint32_t key[2];
+    uint32_t ctr[4];
+    uint32_t blk[4];
+    int64_t loaded;
+} orc_stream;
+
+static void stream_init(orc_stream *st, uint64_t seed, uint32_t chain, uint32_t row, uint32_t tag)
+{
+    st->key[0] = (uint32_t)(seed & 0xffffffffu);
+    st->key[1] = (uint32_t)(seed >> 32);
+    st->ctr[0] = 0;
+    st->ctr[1] = chain;
+    st->ctr[2] = row;
+    st->ctr[3] = tag;
+    st->loaded = -1;
+}
+
+static uint32_t stream_word(orc_stream *st, int j)
+{
+    int64_t q = (int64_t)((j - 1) >> 2);
+    if (q != st->loaded) {
+        st->ctr[0] = (uint32_t)q;
+        orc_philox(st->ctr, st->key, st->blk);
+        st->loaded = q;
+    }
+    return st->blk[(j - 1) & 3];
+}
+
+/* O3: t = floor(u * W_s / 2^32); k* = first k with t < cum_k (linear scan). */
+static int64_t draw_entry(const orc_mat *A, int64_t s, uint32_t u)
+{
+    uint64_t t = ((uint64_t)u * (uint64_t)A->wsum[s]) >> 32;
+    for (int64_t k = A->cptr[s]; k < A->cptr[s + 1]; ++k)
+        if (t < (uint64_t)A->cum[k])
+            return k;
+    return -1; /* unreachable: t < W_s = cum of the last entry */
+}
+
+/* One chain: calls visit(ctx, s, W) for every contribution (j = 0 included).
+ * Returns the number of transitions (draws). */
+typedef void (*visit_fn)(void *ctx, int64_t s, double w);
+
+static int64_t run_chain(const orc_mat *A, const orc_params *p, int lmax, int64_t r,
+                         uint32_t chain, uint32_t tag, visit_fn visit, void *ctx)
+{
+    orc_stream st;
+    stream_init(&st, p->seed, chain, (uint32_t)r, tag);
+    int64_t s = r;
+    int64_t steps = 0;
+    if (!p->fp32) {
+        double w = 1.0;
+        visit(ctx, s, w);
+        for (int j = 1; j <= lmax; ++j) {
+            if (A->cptr[s + 1] == A->cptr[s])
+                break;
+            double wn = w * A->shat[s];
+            if (fabs(wn) < p->delta)
+                break;
+            int64_t k = draw_entry(A, s, stream_word(&st, j));
+            w = (A->cval[k] < 0.0) ? -wn : wn;
+            s = A->ccol[k];
+            visit(ctx, s, w);
+            ++steps;
+        }
+    } else {
+        float w = 1.0f;
+        float delta32 = (float)p->delta;
+        visit(ctx, s, (double)w);
+        for (int j = 1; j <= lmax; ++j) {
+            if (A->cptr[s + 1] == A->cptr[s])
+                break;
+            float s32 = (float)A->shat[s];
+            float wn = w * s32;
+            if (fabsf(wn) < delta32)
+                break;
+            int64_t k = draw_entry(A, s, stream_word(&st, j));
+            w = (A->cval[k] < 0.0) ? -wn : wn;
+            s = A->ccol[k];
+            visit(ctx, s, (double)w);
+            ++steps;
+        }
+    }
+    return steps;
+}
+
+/* ------------------------------------------------------------- O5 + O6 */
+typedef struct {
+    long double *acc;
+    double *abssum;
+    uint32_t *cnt;
+    int32_t *touched;
+    int64_t ntouched;
+} row_accum;
+
+static void accum_visit(void *ctx, int64_t s, double w)
+{
+    row_accum *ra = (row_accum *)ctx;
+    if (ra->cnt[s] == 0)
+        ra->touched[ra->ntouched++] = (int32_t)s;
+    ra->acc[s] += (long double)w;
+    ra->abssum[s] += fabs(w);
+    ra->cnt[s] += 1;
+}
+
+static int cmp_i32(const void *a, const void *b)
+{
+    int32_t x = *(const int32_t *)a, y = *(const int32_t *)b;
+    return (x > y) - (x < y);
+}
+
+typedef struct {
+    int64_t nnz;
+    int32_t *col;
+    double *val;
+    double *abssum;
+    uint32_t *cnt;
+    int64_t guard;
+    int64_t transitions;
+} row_out;
+
+typedef struct {
+    const orc_mat *A;
+    const orc_params *p;
+    const int32_t *rows;
+    int64_t nrows;
+    const int32_t *chains_per_row;
+    int lmax;
+    row_out *out;
+    int64_t next;
+    pthread_mutex_t lock;
+    int failed;
+} spai_job;
+
+static int64_t take_rows(spai_job *job, int64_t want, int64_t *begin)
+{
+    pthread_mutex_lock(&job->lock);
+    int64_t b = job->next;
+    int64_t e = b + want;
+    if (e > job->nrows)
+        e = job->nrows;
+    job->next = e;
+    pthread_mutex_unlock(&job->lock);
+    *begin = b;
+    return e - b;
+}
+
+static void *spai_worker(void *arg)
+{
+    spai_job *job = (spai_job *)arg;
+    const orc_mat *A = job->A;
+    const orc_params *p = job->p;
+    int64_t n = A->n;
+    row_accum ra;
+    ra.acc = (long double *)calloc((size_t)n, sizeof(long double));
+    ra.abssum = (double *)calloc((size_t)n, sizeof(double));
+    ra.cnt = (uint32_t *)calloc((size_t)n, sizeof(uint32_t));
+    ra.touched = (int32_t *)malloc((size_t)n * sizeof(int32_t));
+    if (!ra.acc || !ra.abssum || !ra.cnt || !ra.touched) {
+        job->failed = 1;
+        goto done;
+    }
+    const double u = ldexp(1.0, -53);
+    for (;;) {
+        int64_t b;
+        int64_t cnt = take_rows(job, 8, &b);
+        if (cnt <= 0)
+            break;
+        for (int64_t t = b; t < b + cnt; ++t) {
+            int64_t r = job->rows ? job->rows[t] : t;
+            int32_t nr = job->chains_per_row ? job->chains_per_row[r] : p->chains;
+            ra.ntouched = 0;
+            int64_t steps = 0;
+            for (int32_t c = 0; c < nr; ++c)
+                steps += run_chain(A, p, job->lmax, r, (uint32_t)c, p->tag, accum_visit, &ra);
+            qsort(ra.touched, (size_t)ra.ntouched, sizeof(int32_t), cmp_i32);
+            row_out *ro = &job->out[t];
+            ro->transitions = steps;
+            ro->guard = 0;
+            ro->col = (int32_t *)malloc((size_t)(ra.ntouched + 1) * sizeof(int32_t));
+            ro->val = (double *)malloc((size_t)(ra.ntouched + 1) * sizeof(double));
+            ro->abssum = (double *)malloc((size_t)(ra.ntouched + 1) * sizeof(double));
+            ro->cnt = (uint32_t *)malloc((size_t)(ra.ntouched + 1) * sizeof(uint32_t));
+            if (!ro->col || !ro->val || !ro->abssum || !ro->cnt) {
+                job->failed = 1;
+                goto done;
+            }
+            int64_t kept = 0;
+            for (int64_t q = 0; q < ra.ntouched; ++q) {
+                int32_t col = ra.touched[q];
+                double acc = (double)ra.acc[col];
+                double nhat = acc / (double)nr;
+                double m = nhat / A->diag[col];
+                double test = p->filter_on_m ? fabs(m) : fabs(nhat);
+                int keep = (col == r) || (nhat != 0.0 && test >= p->eps);
+                /* guard band: a summation order other than this one can only flip
+                 * the decision inside |test - eps| <= band (standard recursive
+                 * summation bound with k terms, widened by a factor 4). */
+                double scale = p->filter_on_m ? 1.0 / fabs(A->diag[col]) : 1.0;
+                double band = 4.0 * ((double)ra.cnt[col] + 2.0) * u * ra.abssum[col] / (double)nr * scale
+                              + 4.0 * u * p->eps;
+                if (col != r && fabs(test - p->eps) <= band)
+                    ro->guard += 1;
+                if (keep) {
+                    ro->col[kept] = col;
+                    ro->val[kept] = m;
+                    ro->abssum[kept] = ra.abssum[col];
+                    ro->cnt[kept] = ra.cnt[col];
+                    ++kept;
+                }
+                ra.acc[col] = 0.0L;
+                ra.abssum[col] = 0.0;
+                ra.cnt[col] = 0;
+            }
+            ro->nnz = kept;
+        }
+    }
+done:
+    free(ra.acc);
+    free(ra.abssum);
+    free(ra.cnt);
+    free(ra.touched);
+    return NULL;
+}
+
+typedef struct {
+    int64_t nrows;
+    int64_t *row_ptr;     /* nrows + 1 */
+    int32_t *col;
+    double *val;
+    double *abssum;       /* per kept entry: sum of |W| of its contributions */
+    uint32_t *cnt;        /* per kept entry: number of contributions */
+    int64_t *row_transitions;
+    uint64_t transitions;
+    int64_t guard;
+    int32_t lmax;
+} orc_result;
+
+static int run_threads(void *(*fn)(void *), void *job, int threads)
+{
+    if (threads < 1)
+        threads = 1;
+    if (threads > 256)
+        threads = 256;
+    pthread_t tid[256];
+    int started = 0;
+    for (int t = 0; t < threads; ++t) {
+        if (pthread_create(&tid[t], NULL, fn, job) != 0)
+            break;
+        ++started;
+    }
+    if (started == 0) {
+        fn(job);
+        return ORC_OK;
+    }
+    for (int t = 0; t < started; ++t)
+        pthread_join(tid[t], NULL);
+    return ORC_OK;
+}
+
+/* O4-O6 for a list of rows (rows == NULL: all rows, in order). Output rows are
+ * in the order given. chains_per_row (nullable) is indexed by global row. */
+int orc_spai(const orc_mat *A, const orc_params *p, const int32_t *rows, int64_t nrows,
+             const int32_t *chains_per_row, orc_result *res)
+{
+    memset(res, 0, sizeof(*res));
+    if (!A || !p || A->n <= 0)
+        return ORC_ERR_ARG;
+    if (!rows)
+        nrows = A->n;
+    if (nrows < 0 || p->eps < 0.0 || !(p->delta >= 0.0))
+        return ORC_ERR_ARG;
+    if (!chains_per_row && p->chains < 1)
+        return ORC_ERR_ARG;
+    for (int64_t t = 0; rows && t < nrows; ++t)
+        if (rows[t] < 0 || rows[t] >= A->n)
+            return ORC_ERR_ARG;
+    if (chains_per_row)
+        for (int64_t i = 0; i < A->n; ++i)
+            if (chains_per_row[i] < 1)
+                return ORC_ERR_ARG;
+    int lmax = orc_lmax(A->norm_inf, p->delta, p->max_len);
+    if (lmax < 0)
+        return lmax;
+    spai_job job;
+    memset(&job, 0, sizeof(job));
+    job.A = A;
+    job.p = p;
+    job.rows = rows;
+    job.nrows = nrows;
+    job.chains_per_row = chains_per_row;
+    job.lmax = lmax;
+    job.out = (row_out *)calloc((size_t)(nrows > 0 ? nrows : 1), sizeof(row_out));
+    if (!job.out)
+        return ORC_ERR_NOMEM;
+    pthread_mutex_init(&job.lock, NULL);
+    run_threads(spai_worker, &job, p->threads);
+    pthread_mutex_destroy(&job.lock);
+    int status = job.failed ? ORC_ERR_NOMEM : ORC_OK;
+    int64_t total = 0;
+    for (int64_t t = 0; t < nrows; ++t)
+        total += job.out[t].nnz;
+    res->nrows = nrows;
+    res->lmax = lmax;
+    res->row_ptr = (int64_t *)malloc((size_t)(nrows + 1) * sizeof(int64_t));
+    res->col = (int32_t *)malloc((size_t)(total + 1) * sizeof(int32_t));
+    res->val = (double *)malloc((size_t)(total + 1) * sizeof(double));
+    res->abssum = (double *)malloc((size_t)(total + 1) * sizeof(double));
+    res->cnt = (uint32_t *)malloc((size_t)(total + 1) * sizeof(uint32_t));
+    res->row_transitions = (int64_t *)malloc((size_t)(nrows + 1) * sizeof(int64_t));
+    if (!res->row_ptr || !res->col || !res->val || !res->abssum || !res->cnt || !res->row_transitions)
+        status = ORC_ERR_NOMEM;
+    int64_t pos = 0;
+    for (int64_t t = 0; t < nrows; ++t) {
+        row_out *ro = &job.out[t];
+        if (status == ORC_OK) {
+            res->row_ptr[t] = pos;
+            if (ro->nnz > 0) {
+                memcpy(res->col + pos, ro->col, (size_t)ro->nnz * sizeof(int32_t));
+                memcpy(res->val + pos, ro->val, (size_t)ro->nnz * sizeof(double));
+                memcpy(res->abssum + pos, ro->abssum, (size_t)ro->nnz * sizeof(double));
+                memcpy(res->cnt + pos, ro->cnt, (size_t)ro->nnz * sizeof(uint32_t));
+            }
+            pos += ro->nnz;
+            res->row_transitions[t] = ro->transitions;
+            res->transitions += (uint64_t)ro->transitions;
+            res->guard += ro->guard;
+        }
+        free(ro->col);
+        free(ro->val);
+        free(ro->abssum);
+        free(ro->cnt);
+    }
+    if (status == ORC_OK)
+        res->row_ptr[nrows] = pos;
+    free(job.out);
+    return status;
+}
+
+void orc_result_free(orc_result *res)
+{
+    if (!res)
+        return;
+    free(res->row_ptr);
+    free(res->col);
+    free(res->val);
+    free(res->abssum);
+    free(res->cnt);
+    free(res->row_transitions);
+    memset(res, 0, sizeof(*res));
+}
+
+/* -------------------------------------------------------------------- O7 */
+/* y_i = sum_k M_ik x_k, ascending column order, plain FP64. */
+void orc_apply(int64_t n, const int64_t *rp, const int32_t *ci, const double *v,
+               const double *x, double *y)
+{
+    for (int64_t i = 0; i < n; ++i) {
+        double s = 0.0;
+        for (int64_t k = rp[i]; k < rp[i + 1]; ++k)
+            s += v[k] * x[ci[k]];
+        y[i] = s;
+    }
+}
+
+/* ------------------------------------------------------ pilot variance */
+/* Per row r with P pilot chains (Philox tag with bit 31 set): each chain's row
+ * estimate is the sparse vector X_c with X_c[s] = sum of its W_j at s. Returns
+ *   v_r  = mean_c ||X_c||^2 - ||mean_c X_c||^2   (total variance of one chain)
+ *   len_r = mean_c (number of transitions of chain c).
+ * Revisits inside one chain are merged before squaring. */
+typedef struct {
+    int64_t *cols;
+    double *vals;
+    int64_t n;
+} chain_list;
+
+static void list_visit(void *ctx, int64_t s, double w)
+{
+    chain_list *cl = (chain_list *)ctx;
+    for (int64_t k = 0; k < cl->n; ++k)
+        if (cl->cols[k] == s) {
+            cl->vals[k] += w;
+            return;
+        }
+    cl->cols[cl->n] = s;
+    cl->vals[cl->n] = w;
+    cl->n += 1;
+}
+
+typedef struct {
+    const orc_mat *A;
+    const orc_params *p;
+    int lmax;
+    int32_t pilot;
+    double *var;
+    double *len;
+    int64_t next;
+    pthread_mutex_t lock;
+    int failed;
+} pilot_job;
+
+static void *pilot_worker(void *arg)
+{
+    pilot_job *job = (pilot_job *)arg;
+    const orc_mat *A = job->A;
+    int64_t n = A->n;
+    chain_list cl;
+    cl.cols = (int64_t *)malloc((size_t)(job->lmax + 2) * sizeof(int64_t));
+    cl.vals = (double *)malloc((size_t)(job->lmax + 2) * sizeof(double));
+    long double *mean = (long double *)calloc((size_t)n, sizeof(long double));
+    int32_t *touched = (int32_t *)malloc((size_t)n * sizeof(int32_t));
+    uint8_t *seen = (uint8_t *)calloc((size_t)n, 1);
+    if (!cl.cols || !cl.vals || !mean || !touched || !seen) {
+        job->failed = 1;
+        goto done;
+    }
+    for (;;) {
+        pthread_mutex_lock(&job->lock);
+        int64_t r = job->next++;
+        pthread_mutex_unlock(&job->lock);
+        if (r >= n)
+            break;
+        int64_t nt = 0;
+        long double sq = 0.0L;
+        int64_t steps = 0;
+        for (int32_t c = 0; c < job->pilot; ++c) {
+            cl.n = 0;
+            steps += run_chain(A, job->p, job->lmax, r, (uint32_t)c, job->p->tag | 0x80000000u,
+                               list_visit, &cl);
+            for (int64_t k = 0; k < cl.n; ++k) {
+                int64_t s = cl.cols[k];
+                sq += (long double)cl.vals[k] * (long double)cl.vals[k];
+                if (!seen[s]) {
+                    seen[s] = 1;
+                    touched[nt++] = (int32_t)s;
+                }
+                mean[s] += (long double)cl.vals[k];
+            }
+        }
+        long double msq = 0.0L;
+        for (int64_t k = 0; k < nt; ++k) {
+            long double mu = mean[touched[k]] / (long double)job->pilot;
+            msq += mu * mu;
+            mean[touched[k]] = 0.0L;
+            seen[touched[k]] = 0;
+        }
+        job->var[r] = (double)(sq / (long double)job->pilot - msq);
+        job->len[r] = (double)steps / (double)job->pilot;
+    }
+done:
+    free(cl.cols);
+    free(cl.vals);
+    free(mean);
+    free(touched);
+    free(seen);
+    return NULL;
+}
+
+int orc_pilot(const orc_mat *A, const orc_params *p, int32_t pilot, double *var, double *len)
+{
+    if (!A || !p || pilot < 1 || !var || !len)
+        return ORC_ERR_ARG;
+    int lmax = orc_lmax(A->norm_inf, p->delta, p->max_len);
+    if (lmax < 0)
+        return lmax;
+    pilot_job job;
+    memset(&job, 0, sizeof(job));
+    job.A = A;
+    job.p = p;
+    job.lmax = lmax;
+    job.pilot = pilot;
+    job.var = var;
+    job.len = len;
+    pthread_mutex_init(&job.lock, NULL);
+    run_threads(pilot_worker, &job, p->threads);
+    pthread_mutex_destroy(&job.lock);
+    return job.failed ? ORC_ERR_NOMEM : ORC_OK;
+}
+
+/* --------------------------------------------------------- row features */
+/* Eight features per row i (p_ij = w_ij / W_i the quantized transition
+ * probabilities, S = Shat, m = entries of the row of C):
+ *   f0 = ln(max(m_i, 1))          f1 = S_i
+ *   f2 = a_max,i = max_j |c_ij|    f3 = sum_j p_ij S_j
+ *   f4 = max_j S_j                 f5 = sum_j p_ij m_j
+ *   f6 = |sum_j c_ij| / S_i        f7 = min(L_max, ln(delta) / ln(S_i))
+ * with f3..f6 = 0 for an empty row and f7 = 0 when S_i = 0. */
+void orc_features(const orc_mat *A, double delta, int lmax, double *feat)
+{
+    for (int64_t i = 0; i < A->n; ++i) {
+        double *f = feat + 8 * i;
+        int64_t b = A->cptr[i], e = A->cptr[i + 1];
+        int64_t m = e - b;
+        double s = A->shat[i];
+        f[0] = log((double)(m > 1 ? m : 1));
+        f[1] = s;
+        double amax = 0.0, ps = 0.0, smax = 0.0, pm = 0.0, csum = 0.0;
+        uint32_t prev = 0;
+        for (int64_t k = b; k < e; ++k) {
+            double pk = (double)(A->cum[k] - prev) / (double)A->wsum[i];
+            prev = A->cum[k];
+            int64_t j = A->ccol[k];
+            if (fabs(A->cval[k]) > amax)
+                amax = fabs(A->cval[k]);
+            ps += pk * A->shat[j];
+            if (A->shat[j] > smax)
+                smax = A->shat[j];
+            pm += pk * (double)(A->cptr[j + 1] - A->cptr[j]);
+            csum += A->cval[k];
+        }
+        f[2] = amax;
+        f[3] = ps;
+        f[4] = smax;
+        f[5] = pm;
+        f[6] = (m > 0 && s > 0.0) ? fabs(csum) / s : 0.0;
+        if (s > 0.0 && s < 1.0 && delta > 0.0) {
+            double l = log(delta) / log(s);
+            f[7] = l < (double)lmax ? l : (double)lmax;
+        } else {
+            f[7] = s > 0.0 ? (double)lmax : 0.0;
+        }
+    }
+}

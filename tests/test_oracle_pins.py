@@ -1,0 +1,394 @@
+"""Pins of the CPU oracle against facts fixed by the paper and by mathematics.
+
+Each test names the passage it follows. None of them re-types the oracle's
+arithmetic: they compare against library routines on the *original* matrix B
+(numpy inverse, triangular solve), closed forms, exact rational expectations
+from path enumeration (tests/golden), exact counts, invariants and an
+independent Philox implementation (rocRAND, built for the host).
+"""
+import json
+import math
+import os
+import shutil
+import subprocess
+from fractions import Fraction
+
+import numpy as np
+import pytest
+import scipy.linalg as sla
+
+import oracle as O
+from paper_2409_03095_amd import inputs as I
+
+GOLD = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def dense_M(res, n):
+    M = np.zeros((res["row_ptr"].size - 1, n))
+    for t in range(M.shape[0]):
+        b, e = res["row_ptr"][t], res["row_ptr"][t + 1]
+        M[t, res["col"][b:e]] = res["val"][b:e]
+    return M
+
+
+# ---------------------------------------------------------------- P1: C = 0
+def test_p1_diagonal_matrix_gives_exact_inverse_and_no_transitions():
+    """Section IV phases 2-4: with B diagonal, C = 0, every chain stops at once and
+    the column scaling gives M = D^-1 exactly."""
+    B = I.diag_only(50, seed=3)
+    o = O.Oracle(B)
+    assert o.nnz_c == 0 and o.norm_inf == 0.0
+    r = o.spai(seed=7, chains=33, delta=1e-3, eps=0.5)
+    assert r["transitions"] == 0
+    assert np.array_equal(r["row_ptr"], np.arange(51))
+    assert np.array_equal(r["col"], np.arange(50))
+    assert np.array_equal(r["val"], 1.0 / B.val)
+
+
+# ------------------------------------------------- P2: deterministic walks
+def test_p2_nilpotent_shift_equals_triangular_solve():
+    """eq. (2) with one entry per row of C: every chain follows the same path, so
+    the estimate is the exact Neumann sum; for nilpotent C and a negligible delta
+    it is B^-1 (scipy triangular solve on B itself)."""
+    n = 40
+    B = I.nilpotent_shift(n, seed=4, amax=0.95)
+    o = O.Oracle(B)
+    r = o.spai(seed=1, chains=16, delta=1e-300, eps=0.0)
+    M = dense_M(r, n)
+    ref = sla.solve_triangular(B.to_dense(), np.eye(n), lower=False)
+    nz = ref != 0
+    assert np.array_equal(M != 0, nz)
+    assert np.allclose(M[nz], ref[nz], rtol=1e-13, atol=0)
+    # each chain from row r walks to the last row: n - 1 - r transitions
+    assert np.array_equal(r["row_transitions"], 16 * (n - 1 - np.arange(n)))
+
+
+@pytest.mark.parametrize("a", [0.6, -0.7])
+def test_p2_scaled_cycle_closed_form(a):
+    """C = a P (cyclic shift): W_j = a^j at state r + j mod n; the chain stops once
+    |a|^(j+1) < delta, so N_{r, r+k} = sum of a^j over j = k mod n, j <= J."""
+    n, d, delta = 7, 2.0, 1e-6
+    B = I.scaled_cycle(n, a, d)
+    r = O.Oracle(B).spai(seed=3, chains=5, delta=delta, eps=0.0)
+    J = 0
+    while abs(a) ** (J + 1) >= delta:
+        J += 1
+    expect = np.zeros(n)
+    for j in range(J + 1):
+        expect[j % n] += a ** j
+    M = dense_M(r, n)
+    for row in range(n):
+        got = np.roll(M[row], -row) * d
+        assert np.allclose(got, expect, rtol=1e-13, atol=1e-300)
+    assert r["transitions"] == n * 5 * J
+
+
+# ----------------------------------------------- P3: constant row sums
+def test_p3_torus_row_sums_and_exact_transition_count():
+    """Periodic 5-point stencil, diagonal 5: every row of C has S = 0.8 and C >= 0,
+    so each chain makes exactly J transitions (0.8^J >= delta > 0.8^(J+1)) and each
+    row of the estimate sums to the geometric series sum_{j<=J} 0.8^j."""
+    B = I.grid2d_5pt(8, 8, 5.0, -1.0, periodic=True)
+    n, N, delta = 64, 50, 1e-3
+    r = O.Oracle(B).spai(seed=11, chains=N, delta=delta, eps=0.0)
+    J = 30  # 0.8^30 = 1.24e-3 >= 1e-3 > 0.8^31
+    assert 0.8 ** J >= delta > 0.8 ** (J + 1)
+    assert r["transitions"] == n * N * J
+    M = dense_M(r, n)
+    rowsum = M.sum(axis=1) * 5.0
+    geo = (1 - 0.8 ** (J + 1)) / (1 - 0.8)
+    assert np.allclose(rowsum, geo, rtol=1e-12)
+
+
+def test_p4_uniform_row_sum_matrix_exact_transitions():
+    """Every row of the random nonsymmetric family has |C| row sum 0.7, so with
+    delta = 1e-4 every chain makes exactly 25 transitions (0.7^25 >= 1e-4 > 0.7^26),
+    in FP64 and in FP32 walks. Checked on a row sample of a smaller instance."""
+    B = I.random_nonsym(4096, seed=2)
+    o = O.Oracle(B)
+    rows = np.random.default_rng(0).choice(4096, 300, replace=False)
+    for fp32 in (False, True):
+        r = o.spai(seed=0, chains=32, delta=1e-4, eps=1e-3, rows=rows, fp32=fp32)
+        assert np.all(r["row_transitions"] == 32 * 25)
+
+
+# ------------------------------------------------- P5: CLT vs the inverse
+@pytest.mark.parametrize("seed", [1, 2])
+def test_p5_converges_to_numpy_inverse(seed):
+    """eq. (2) is unbiased for the Neumann series of C; with delta = 1e-12 the
+    truncation bias is below 1e-11, so M must match numpy's inverse of B within a
+    Hoeffding bound (each chain's entry lies in [-R, R], R = 1/(1 - ||C||_inf))."""
+    n, N = 6, 400_000
+    B = I.dense_small(n, 0.5, seed)
+    o = O.Oracle(B)
+    r = o.spai(seed=seed, chains=N, delta=1e-12, eps=0.0)
+    M = dense_M(r, n)
+    ref = np.linalg.inv(B.to_dense())
+    R = 1.0 / (1.0 - o.norm_inf)
+    t = R * math.sqrt(2.0 * math.log(2.0 * n * n / 1e-9) / N)
+    d = np.abs(np.diag(B.to_dense()))
+    err = np.abs(M - ref) * d[None, :]
+    assert err.max() < t + 1e-9, (err.max(), t)
+
+
+# ---------------------------------------------- P6: exact path enumeration
+@pytest.mark.parametrize("name", ["tiny3_signed", "tiny4_absorbing"])
+def test_p6_matches_exact_rational_expectation(name):
+    """Exact expectations of eq. (2)'s estimator (tests/golden, enumerated with
+    rationals) including the j = 0 term, the stop-before-draw rule and the strict
+    delta test; the oracle's mean over 10^6 chains must lie within 6 standard
+    errors computed from the exact second moments."""
+    g = json.load(open(os.path.join(GOLD, name + ".json")))
+    B = np.array([[float(Fraction(x)) for x in row] for row in g["B"]])
+    n = B.shape[0]
+    N = 1_000_000
+    r = O.Oracle(I.from_dense(B)).spai(seed=5, chains=N, delta=float(Fraction(g["delta"])),
+                                       eps=0.0, max_len=g["lmax"])
+    M = dense_M(r, n)
+    d = np.array([float(Fraction(x)) for x in g["diag"]])
+    Nhat = M * d[None, :]
+    for row in range(n):
+        mean = np.array([float(Fraction(x)) for x in g["rows"][row]["mean"]])
+        second = np.array([float(Fraction(x)) for x in g["rows"][row]["second"]])
+        sd = np.sqrt(np.maximum(second - mean * mean, 0.0))
+        assert np.all(np.abs(Nhat[row] - mean) <= 6 * sd / math.sqrt(N) + 1e-12), (row, Nhat[row], mean)
+
+
+# --------------------------------------------------- P7: 1/sqrt(N) error
+def test_p7_error_decays_as_inverse_sqrt_chains():
+    """Monte Carlo error of eq. (2) falls as N^-1/2 (log-log slope -1/2)."""
+    B = I.grid2d_5pt(12, 12, 5.0, -1.0)
+    n = B.n
+    ref = np.linalg.inv(B.to_dense())
+    o = O.Oracle(B)
+    Ns = [64, 256, 1024, 4096]
+    errs = []
+    for N in Ns:
+        e = []
+        for seed in range(3):
+            M = dense_M(o.spai(seed=seed, chains=N, delta=1e-10, eps=0.0), n)
+            e.append(np.linalg.norm(M - ref))
+        errs.append(np.mean(e))
+    slope = np.polyfit(np.log(Ns), np.log(errs), 1)[0]
+    assert -0.6 < slope < -0.4, slope
+
+
+# ---------------------------------------------- P8: filter monotonicity
+def test_p8_filter_is_monotone_and_keeps_values():
+    """A larger eps keeps a subset of the entries with identical values; the
+    diagonal is always kept (Section III-A filter reading)."""
+    B = I.cfg1()
+    o = O.Oracle(B)
+    a = o.spai(seed=0, chains=200, delta=1e-3, eps=1e-3)
+    b = o.spai(seed=0, chains=200, delta=1e-3, eps=1e-2)
+    for row in range(B.n):
+        ca = dict(zip(a["col"][a["row_ptr"][row]:a["row_ptr"][row + 1]],
+                      a["val"][a["row_ptr"][row]:a["row_ptr"][row + 1]]))
+        cb = dict(zip(b["col"][b["row_ptr"][row]:b["row_ptr"][row + 1]],
+                      b["val"][b["row_ptr"][row]:b["row_ptr"][row + 1]]))
+        assert row in cb and set(cb) <= set(ca)
+        assert all(ca[k] == v for k, v in cb.items())
+
+
+# -------------------------------------------------------- P9: row purity
+def test_p9_row_purity_threads_and_order():
+    """Each row depends only on (C, seed, row, chains): one thread vs many, and a
+    shuffled row order, give bit-identical rows (the property that makes the
+    row partition of Section IV-A exact)."""
+    B = I.random_nonsym(2000, seed=9)
+    o = O.Oracle(B)
+    a = o.spai(seed=42, chains=40, delta=1e-4, eps=1e-3, threads=1)
+    perm = np.random.default_rng(1).permutation(B.n)
+    b = o.spai(seed=42, chains=40, delta=1e-4, eps=1e-3, rows=perm, threads=8)
+    for t, row in enumerate(perm):
+        sa = slice(a["row_ptr"][row], a["row_ptr"][row + 1])
+        sb = slice(b["row_ptr"][t], b["row_ptr"][t + 1])
+        assert np.array_equal(a["col"][sa], b["col"][sb])
+        assert np.array_equal(a["val"][sa].view(np.uint64), b["val"][sb].view(np.uint64))
+
+
+# ---------------------------------------------------------- P10: FP32 walks
+def test_p10_fp32_walks_follow_the_same_paths():
+    """FP32 weights pick the same transitions (integer CDF), so transition counts
+    match FP64 and the values agree to FP32 rounding (1e-5 relative)."""
+    B = I.random_nonsym(3000, seed=4)
+    o = O.Oracle(B)
+    a = o.spai(seed=1, chains=64, delta=1e-4, eps=1e-3)
+    b = o.spai(seed=1, chains=64, delta=1e-4, eps=1e-3, fp32=True)
+    assert np.array_equal(a["row_transitions"], b["row_transitions"])
+    Ma = O.spai_csr(a, B.n).toarray() if B.n <= 3000 else None
+    Mb = O.spai_csr(b, B.n).toarray()
+    both = (Ma != 0) & (Mb != 0)
+    rel = np.abs(Ma[both] - Mb[both]) / np.abs(Ma[both])
+    assert rel.max() < 1e-5
+    # pattern differences only where FP32 rounding moves |N| across eps
+    assert np.sum((Ma != 0) != (Mb != 0)) <= 5
+
+
+# ------------------------------------------------------------- P11: apply
+def test_p11_apply_matches_scipy():
+    B = I.cfg1()
+    r = O.Oracle(B).spai(seed=0, chains=50, delta=1e-3, eps=1e-3)
+    x = np.random.default_rng(0).standard_normal(B.n)
+    y = O.apply(r["row_ptr"], r["col"], r["val"], x)
+    ref = O.spai_csr(r, B.n) @ x
+    assert np.allclose(y, ref, rtol=1e-14, atol=1e-14 * np.abs(ref).max())
+
+
+# ---------------------------------------------------------- P12: Philox
+ROCRAND_PROBE = r"""
+#include <rocrand/rocrand_philox4x32_10.h>
+#include <cstdio>
+#include <cstdlib>
+int main(int argc, char** argv) {
+  unsigned long long seed = strtoull(argv[1], 0, 0);
+  for (int i = 2; i + 3 < argc; i += 4) {
+    unsigned long long c0 = strtoull(argv[i], 0, 0), c1 = strtoull(argv[i+1], 0, 0);
+    unsigned long long c2 = strtoull(argv[i+2], 0, 0), c3 = strtoull(argv[i+3], 0, 0);
+    rocrand_state_philox4x32_10 st;
+    rocrand_init(seed, c2 | (c3 << 32), 4ULL * (c0 | (c1 << 32)), &st);
+    uint4 v = rocrand4(&st);
+    printf("%u %u %u %u\n", v.x, v.y, v.z, v.w);
+  }
+  return 0;
+}
+"""
+
+
+@pytest.fixture(scope="module")
+def rocrand_probe(tmp_path_factory):
+    hipcc = shutil.which("hipcc") or "/opt/rocm/bin/hipcc"
+    if not os.path.exists(hipcc) or not os.path.exists("/opt/rocm/include/rocrand/rocrand_philox4x32_10.h"):
+        pytest.skip("rocRAND headers / hipcc not available")
+    d = tmp_path_factory.mktemp("rr")
+    src = d / "rr.cpp"
+    src.write_text(ROCRAND_PROBE)
+    exe = d / "rr"
+    subprocess.check_call([hipcc, "-O1", "-o", str(exe), str(src)])
+    return str(exe)
+
+
+def test_p12_philox_matches_rocrand(rocrand_probe):
+    """The oracle's Philox4x32-10 (written from Salmon et al., SC'11) equals the
+    independent rocRAND implementation for random counters and keys."""
+    rng = np.random.default_rng(123)
+    for _ in range(4):
+        seed = int(rng.integers(0, 2**63)) * 2 + int(rng.integers(0, 2))
+        ctrs = rng.integers(0, 2**32, size=(16, 4), dtype=np.uint64)
+        ctrs[:, 1] >>= 3  # rocrand_init takes the low counter words as offset/4 < 2^62
+        args = [rocrand_probe, str(seed)] + [str(int(v)) for v in ctrs.ravel()]
+        out = subprocess.check_output(args).decode().split("\n")
+        for k in range(16):
+            got = O.philox4x32_10(ctrs[k].astype(np.uint32), [seed & 0xFFFFFFFF, seed >> 32])
+            want = np.array([int(x) for x in out[k].split()], dtype=np.uint32)
+            assert np.array_equal(got, want)
+
+
+def test_p12_philox_word_statistics():
+    """Uniformity of the words the walks consume: chi-square over 256 bins."""
+    words = np.concatenate([O.philox4x32_10([q, 7, 9, 0], [1, 2]) for q in range(20000)])
+    h = np.bincount(words >> 24, minlength=256)
+    e = words.size / 256
+    chi2 = ((h - e) ** 2 / e).sum()
+    assert chi2 < 255 + 6 * math.sqrt(2 * 255)
+
+
+# ---------------------------------------------------------- CDF invariants
+def test_cdf_quantization_bounds():
+    """The integer weights are >= 1, sum below 2^32, and Shat = sum |chat| is within
+    the quantization error m * a_max * 2^-Q of the true |C| row sum."""
+    B = I.random_nonsym(5000, seed=7)
+    o = O.Oracle(B)
+    Bd = B.to_scipy()
+    d = Bd.diagonal()
+    Cabs = abs(Bd).sum(axis=1).A1 / np.abs(d) - 1.0
+    for i in range(0, 5000, 37):
+        w = o.row_weights(i)
+        m = w.size
+        assert w.min() >= 1 and int(o.wsum[i]) == w.sum() < 2**32
+        q = 31 - math.ceil(math.log2(m)) if m > 1 else 31
+        amax = np.abs(o.cval[o.cptr[i]:o.cptr[i + 1]]).max()
+        assert abs(o.shat[i] - Cabs[i]) <= m * amax * 2.0 ** -q + 1e-15
+
+
+def test_errors_on_bad_input():
+    B = I.grid2d_5pt(4, 4)
+    bad = I.Csr(B.n, B.row_ptr.copy(), B.col.copy(), B.val.copy())
+    bad.val[bad.col == 0] = 0.0  # zero diagonal in row 0
+    with pytest.raises(O.OracleError):
+        O.Oracle(bad)
+    # not contractive without max_len
+    o = O.Oracle(I.grid2d_5pt(4, 4, diag=2.0))
+    with pytest.raises(O.OracleError):
+        o.spai(seed=0, chains=2, delta=1e-3)
+    # with max_len it runs and caps the chain length
+    r = o.spai(seed=0, chains=2, delta=1e-3, eps=0.0, max_len=5)
+    assert r["row_transitions"].max() <= 2 * 5
+
+
+# ----------------------------------------------- pilot variance / features
+def test_pilot_variance_deterministic_walk_is_zero_and_torus_lengths():
+    """A deterministic chain (one entry per row) has zero variance; on the torus
+    every chain has exactly J transitions."""
+    B = I.scaled_cycle(9, 0.5)
+    v, ln = O.Oracle(B).pilot(seed=1, pilot=16, delta=1e-6)
+    assert np.allclose(v, 0.0, atol=1e-12) and np.all(ln == 19)
+    T = I.grid2d_5pt(6, 6, 5.0, -1.0, periodic=True)
+    v, ln = O.Oracle(T).pilot(seed=1, pilot=16, delta=1e-3)
+    assert np.all(ln == 30) and np.all(v > 0)
+
+
+def test_pilot_variance_matches_exact_second_moments():
+    """Total variance of one chain's estimate = sum_c (E[X_c^2] - E[X_c]^2), from the
+    rational enumeration."""
+    g = json.load(open(os.path.join(GOLD, "tiny3_signed.json")))
+    B = np.array([[float(Fraction(x)) for x in row] for row in g["B"]])
+    v, _ = O.Oracle(I.from_dense(B)).pilot(seed=2, pilot=400_000, delta=float(Fraction(g["delta"])),
+                                            max_len=g["lmax"])
+    for row in range(3):
+        mean = np.array([float(Fraction(x)) for x in g["rows"][row]["mean"]])
+        second = np.array([float(Fraction(x)) for x in g["rows"][row]["second"]])
+        exact = float((second - mean * mean).sum())
+        assert abs(v[row] - exact) < 0.02 * exact + 1e-3, (row, v[row], exact)
+
+
+def test_features_on_torus_closed_form():
+    T = I.grid2d_5pt(6, 6, 5.0, -1.0, periodic=True)
+    f = O.Oracle(T).features(delta=1e-3)
+    assert np.allclose(f[:, 0], math.log(4)) and np.allclose(f[:, 1], 0.8)
+    assert np.allclose(f[:, 2], 0.2) and np.allclose(f[:, 3], 0.8) and np.allclose(f[:, 4], 0.8)
+    assert np.allclose(f[:, 5], 4.0) and np.allclose(f[:, 6], 1.0)
+    assert np.allclose(f[:, 7], math.log(1e-3) / math.log(0.8))
+
+
+# ------------------------------------------------------------ MLP reference
+def test_mlp_reference_gradient_matches_finite_differences():
+    p = O.mlp_init(3)
+    for k in p:
+        p[k] = p[k].astype(np.float64)
+        if k.startswith("b"):
+            p[k] = np.random.default_rng(1).normal(0, 0.1, size=p[k].shape)
+    rng = np.random.default_rng(0)
+    x = rng.standard_normal((32, 8))
+    t = rng.standard_normal(32)
+    _, g = O.mlp_loss_grad(p, x, t)
+    h = 1e-6
+    for name in ("w1", "b1", "w2", "b2", "w3", "b3"):
+        flat = p[name].reshape(-1)
+        for idx in rng.choice(flat.size, min(6, flat.size), replace=False):
+            old = flat[idx]
+            flat[idx] = old + h
+            lp, _ = O.mlp_loss_grad(p, x, t)
+            flat[idx] = old - h
+            lm, _ = O.mlp_loss_grad(p, x, t)
+            flat[idx] = old
+            fd = (lp - lm) / (2 * h)
+            assert abs(fd - g[name].reshape(-1)[idx]) <= 1e-7 * max(1.0, abs(fd)), (name, idx)
+
+
+def test_neyman_allocation_budget():
+    pred = np.log(np.array([1.0, 2.0, 4.0, 8.0]))
+    cost = np.array([3, 3, 3, 3])
+    n_r, lam = O.allocate(pred, cost, 3 * 150)
+    assert (n_r * cost).sum() <= 450 and n_r.min() >= 1
+    assert np.all(np.diff(n_r) >= 0)
