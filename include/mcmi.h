@@ -1,0 +1,160 @@
+/*
+ * mcmi.h - C ABI of libmcmi.so: Markov Chain Monte Carlo sparse approximate
+ * inverse ((MC)^2MI) on AMD Instinct MI355X (gfx950).
+ *
+ * The library computes, for a sparse matrix B with a nonzero diagonal D, a
+ * sparse approximate inverse M of B:
+ *
+ *   C = I - D^-1 B                     (Section IV, phase 2: the iteration matrix
+ *                                       whose Neumann series gives (I - C)^-1)
+ *   N_r ~ row r of (I - C)^-1          (Section III-A, eq. (2): the mean over N_r
+ *                                       Markov chains started at r of the chain
+ *                                       weights W_j summed at the states visited)
+ *   M_rc = N_rc / d_c                  (Section IV-A, phase 4: column scaling by
+ *                                       the inverse diagonal, since B^-1 =
+ *                                       (I - C)^-1 D^-1)
+ *   keep (r, c) iff c == r or |N_rc| >= eps   (the filter that makes M sparse,
+ *                                       Section III-A "parallel filter")
+ *
+ * Sampling: transition probabilities p_ij proportional to |c_ij| (the paper
+ * leaves P undefined), quantized to integer weights per row so that every
+ * implementation samples the same quantized matrix Chat; weights W_j =
+ * W_{j-1} * sign(c) * Shat_s with Shat_s = sum_k |chat_sk|. A chain stops before
+ * a draw when the row of C is empty, when |W * Shat_s| < delta, or after L_max
+ * transitions. Random numbers: Philox4x32-10 with key (seed lo, seed hi) and
+ * counter (step block, chain, row, tag); step j >= 1 uses word (j-1) mod 4 of
+ * block (j-1) / 4.
+ *
+ * Conventions for every entry point:
+ *  - Pointers named *_dev are device pointers (hipMalloc'd or torch tensors'
+ *    data_ptr()); the caller owns them and keeps them valid until the work
+ *    queued on `stream` has finished. Pointers named *_host are host memory.
+ *  - `stream` is a hipStream_t (NULL = the default stream). Calls are
+ *    asynchronous on it except where a call states a host synchronisation.
+ *  - Every call returns an mcmi_status. On error, output structs are zeroed,
+ *    nothing stays allocated, and mcmi_last_error() (thread-local) describes the
+ *    failure. No C++ exception crosses this boundary.
+ *  - Layouts: CSR with int64 row pointers (n + 1), int32 column indices
+ *    (ascending and unique within a row) and float64 values.
+ */
+#ifndef MCMI_H
+#define MCMI_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    MCMI_OK = 0,
+    MCMI_ERR_ARG = -1,            /* bad argument (null pointer, bad size, bad parameter) */
+    MCMI_ERR_CSR = -2,            /* row pointers not monotone, columns unsorted, duplicated or out of range */
+    MCMI_ERR_ZERO_DIAG = -3,      /* a row lacks its diagonal entry or it is zero */
+    MCMI_ERR_NOT_CONTRACTIVE = -4,/* ||Chat||_inf >= 1 and no max_len given */
+    MCMI_ERR_CAPACITY = -5,       /* an internal table stayed too small after growing */
+    MCMI_ERR_HIP = -6,            /* a HIP runtime call failed */
+    MCMI_ERR_NOMEM = -7           /* device allocation failed */
+} mcmi_status;
+
+/* Input matrix B (borrowed device pointers). */
+typedef struct {
+    int64_t n;                 /* rows = columns */
+    int64_t nnz;               /* stored entries */
+    const int64_t *row_ptr_dev;/* n + 1 */
+    const int32_t *col_dev;    /* nnz */
+    const double *val_dev;     /* nnz */
+} mcmi_csr_in;
+
+/* Output matrix (device buffers allocated by the library; free with mcmi_csr_free). */
+typedef struct {
+    int64_t n;                 /* rows (the number of rows requested) */
+    int64_t nnz;
+    int64_t *row_ptr_dev;      /* n + 1 */
+    int32_t *col_dev;          /* nnz */
+    double *val_dev;           /* nnz */
+} mcmi_csr_out;
+
+/* Opaque: the packed per-row sampling records of C (library-owned device memory). */
+typedef struct mcmi_cdf mcmi_cdf;
+
+enum { MCMI_WALK_F64 = 64, MCMI_WALK_F32 = 32 };
+enum { MCMI_FILTER_N = 0, MCMI_FILTER_M = 1 };
+
+typedef struct {
+    uint64_t seed;        /* Philox key */
+    int32_t chains;       /* chains per row when no per-row array is given (>= 1) */
+    int32_t walk_prec;    /* MCMI_WALK_F64 or MCMI_WALK_F32 (binary32 weights, Shat and
+                             delta test; sums stay binary64) */
+    double delta;         /* weight cutoff: stop before a draw when |W * Shat_s| < delta */
+    double eps;           /* filter threshold (>= 0) */
+    int32_t max_len;      /* L_max; 0 = derive: smallest L with ||Chat||_inf^L < delta
+                             (one IEEE product per step); required when ||Chat||_inf >= 1 */
+    uint32_t stream_tag;  /* fourth Philox counter word (distinguishes independent runs) */
+    int32_t filter;       /* MCMI_FILTER_N: |N_rc| >= eps; MCMI_FILTER_M: |M_rc| >= eps */
+    int32_t lanes_per_row;/* 0 = automatic; else 64, 128, 256 or 512 lanes share a row */
+    int32_t hash_slots;   /* 0 = automatic; else LDS hash slots per row (power of two) */
+    int32_t reserved[3];  /* must be zero */
+} mcmi_params;
+
+typedef struct {
+    uint64_t transitions;     /* exact number of draws made */
+    uint64_t chains;          /* chains run */
+    uint64_t spilled;         /* contributions that went to the HBM spill table */
+    uint64_t retries;         /* reruns after a table or pool overflow */
+    int64_t nnz;              /* entries of M */
+    int32_t lmax;             /* L_max used */
+    float norm_inf;           /* ||Chat||_inf */
+    double ms_walk;           /* device time of the walk + finalize kernel(s) */
+    double ms_assemble;       /* device time of the CSR assembly */
+    double ms_total;          /* device time of the whole call */
+} mcmi_stats;
+
+/* Build the sampling records of C = I - D^-1 B (Section IV, phase 2 and the
+ * transition matrix P of Section IV-A). Validates B (sorted unique columns,
+ * nonzero diagonal) on the device. Synchronises the stream once to read the
+ * validation flags and the record sizes, and once more for ||Chat||_inf.
+ * *out is allocated by the library; free it with mcmi_cdf_free. */
+mcmi_status mcmi_build_cdf(const mcmi_csr_in *B, mcmi_cdf **out, void *stream);
+
+/* Copy the records to host memory (for inspection and tests; synchronises the
+ * stream). rec_host receives rec_units * 4 uint32 words (rec_units from
+ * mcmi_cdf_info), roff_host n record offsets (16-byte units) and diag_host the n
+ * diagonal values b_ii. Any of the three may be NULL. */
+mcmi_status mcmi_cdf_download(const mcmi_cdf *cdf, uint32_t *rec_host, uint32_t *roff_host, double *diag_host,
+                              void *stream);
+
+/* ||Chat||_inf, n and nnz(C) of built records. */
+mcmi_status mcmi_cdf_info(const mcmi_cdf *cdf, int64_t *n, int64_t *nnz_c, double *norm_inf,
+                          uint64_t *rec_units);
+
+/* The Monte Carlo SPAI (Section III-A eq. (2), Section IV phases 3-4):
+ * walks, per-row accumulation, eps filter, D^-1 column scaling, CSR assembly.
+ * chains_per_row_dev: NULL (every row gets p->chains) or a device int32 array of
+ * length n with values >= 1. rows_dev: NULL (all n rows) or a device int32 array
+ * of n_rows distinct row indices; M then holds those rows in that order.
+ * M's buffers are allocated by the library. Synchronises the stream to size M
+ * (and once more per retry after an overflow). st may be NULL. */
+mcmi_status mcmi_spai(const mcmi_cdf *cdf, const mcmi_params *p, const int32_t *chains_per_row_dev,
+                      const int32_t *rows_dev, int64_t n_rows, mcmi_csr_out *M, mcmi_stats *st,
+                      void *stream);
+
+/* y = M x (CSR SpMV, float64), asynchronous. x_dev has M's column count (the n of
+ * the cdf M came from), y_dev has M->n entries. Used to apply M as a
+ * preconditioner (Section III-A: the result is used directly as a preconditioner). */
+mcmi_status mcmi_apply(const mcmi_csr_out *M, int64_t n_cols, const double *x_dev, double *y_dev,
+                       void *stream);
+
+/* Copy M into caller-owned device buffers (row_ptr n+1, col nnz, val nnz). */
+mcmi_status mcmi_csr_copy(const mcmi_csr_out *M, int64_t *row_ptr_dev, int32_t *col_dev,
+                          double *val_dev, void *stream);
+
+void mcmi_cdf_free(mcmi_cdf *cdf);
+void mcmi_csr_free(mcmi_csr_out *M);
+const char *mcmi_last_error(void);
+const char *mcmi_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MCMI_H */

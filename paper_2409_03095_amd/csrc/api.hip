@@ -1,0 +1,326 @@
+// Host side of the C ABI: parameter checks, workspace sizing, launches and
+// the grow-and-rerun policy for the output pool and the hash tables.
+#include <string.h>
+
+#include <algorithm>
+#include <cmath>
+#include <string>
+
+#include "common.hpp"
+#include "walk_args.hpp"
+
+namespace mcmi {
+
+size_t walk_lds_bytes(int hash_slots, int waves);
+hipError_t launch_walk(const WalkArgs &a, bool f32, int blocks, int waves, hipStream_t s);
+hipError_t walk_occupancy(bool f32, int hash_slots, int waves, int *blocks_per_cu);
+hipError_t gather_rows(int64_t n_rows, const int64_t *row_start, const uint32_t *row_cnt, const int64_t *row_ptr,
+                       const int32_t *pool_col, const double *pool_val, int32_t *col, double *val, hipStream_t s);
+hipError_t validate_rows(const int32_t *rows, int64_t n_rows, const int32_t *cpr, int64_t n, uint32_t *bad,
+                         hipStream_t s);
+hipError_t spmv(int64_t n, const int64_t *rp, const int32_t *ci, const double *v, const double *x, double *y,
+                hipStream_t s);
+
+static thread_local std::string g_last_error;
+
+void set_error(const std::string &msg) { g_last_error = msg; }
+
+mcmi_status fail(mcmi_status st, const std::string &msg) {
+    set_error(msg);
+    return st;
+}
+
+// L_max: max_len if given, else the smallest L with p_L < delta where p_0 = 1
+// and p_j = p_{j-1} * ||Chat||_inf, one IEEE product per step.
+int derive_lmax(double norm_inf, double delta, int max_len) {
+    constexpr int kCap = 65536;
+    if (max_len > 0) return max_len <= kCap ? max_len : (int)MCMI_ERR_ARG;
+    if (!(norm_inf < 1.0)) return (int)MCMI_ERR_NOT_CONTRACTIVE;
+    if (!(delta > 0.0)) return (int)MCMI_ERR_ARG;
+    double prod = 1.0;
+    int steps = 0;
+    while (prod >= delta) {
+        prod = prod * norm_inf;
+        if (++steps > kCap) return (int)MCMI_ERR_ARG;
+    }
+    return steps;
+}
+
+int device_cus() {
+    static int cus = 0;
+    if (!cus) {
+        int dev = 0;
+        hipGetDevice(&dev);
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+        if (cus <= 0) cus = 256;
+    }
+    return cus;
+}
+
+}  // namespace mcmi
+
+using namespace mcmi;
+
+namespace {
+
+struct DevBuf {
+    void *p = nullptr;
+    hipStream_t s = nullptr;
+    ~DevBuf() {
+        if (p) hipFreeAsync(p, s);
+    }
+    hipError_t alloc(size_t bytes, hipStream_t st) {
+        if (p) hipFreeAsync(p, s);
+        p = nullptr;
+        s = st;
+        return hipMallocAsync(&p, bytes ? bytes : 16, st);
+    }
+    template <typename T>
+    T *as() const {
+        return (T *)p;
+    }
+};
+
+int pow2_at_least(int v) {
+    int p = 1;
+    while (p < v) p <<= 1;
+    return p;
+}
+
+}  // namespace
+
+extern "C" mcmi_status mcmi_spai(const mcmi_cdf *cdf, const mcmi_params *p, const int32_t *chains_per_row_dev,
+                                 const int32_t *rows_dev, int64_t n_rows, mcmi_csr_out *M, mcmi_stats *st,
+                                 void *stream) {
+    if (M) memset(M, 0, sizeof(*M));
+    if (st) memset(st, 0, sizeof(*st));
+    if (!cdf || !p || !M) return fail(MCMI_ERR_ARG, "mcmi_spai: null argument");
+    if (p->chains < 1 && !chains_per_row_dev) return fail(MCMI_ERR_ARG, "mcmi_spai: chains must be >= 1");
+    if (p->walk_prec != MCMI_WALK_F64 && p->walk_prec != MCMI_WALK_F32)
+        return fail(MCMI_ERR_ARG, "mcmi_spai: walk_prec must be 64 or 32");
+    if (!(p->eps >= 0.0) || !(p->delta >= 0.0)) return fail(MCMI_ERR_ARG, "mcmi_spai: eps and delta must be >= 0");
+    if (p->filter != MCMI_FILTER_N && p->filter != MCMI_FILTER_M) return fail(MCMI_ERR_ARG, "mcmi_spai: bad filter");
+    if (p->reserved[0] || p->reserved[1] || p->reserved[2]) return fail(MCMI_ERR_ARG, "mcmi_spai: reserved != 0");
+    if (p->hash_slots && (p->hash_slots < 64 || p->hash_slots > 8192 || (p->hash_slots & (p->hash_slots - 1))))
+        return fail(MCMI_ERR_ARG, "mcmi_spai: hash_slots must be a power of two in [64, 8192]");
+    const int64_t n_tasks = rows_dev ? n_rows : cdf->n;
+    if (rows_dev && (n_rows < 1 || n_rows > cdf->n)) return fail(MCMI_ERR_ARG, "mcmi_spai: bad n_rows");
+    const int lmax = derive_lmax(cdf->norm_inf, p->delta, p->max_len);
+    if (lmax < 0) {
+        if (lmax == (int)MCMI_ERR_NOT_CONTRACTIVE)
+            return fail(MCMI_ERR_NOT_CONTRACTIVE, "mcmi_spai: ||Chat||_inf >= 1; give max_len");
+        return fail(MCMI_ERR_ARG, "mcmi_spai: bad delta / max_len");
+    }
+    hipStream_t s = (hipStream_t)stream;
+    const bool f32 = p->walk_prec == MCMI_WALK_F32;
+
+    hipEvent_t ev0, ev1, ev2;
+    MCMI_HIP(hipEventCreate(&ev0));
+    MCMI_HIP(hipEventCreate(&ev1));
+    MCMI_HIP(hipEventCreate(&ev2));
+    struct EvGuard {
+        hipEvent_t a, b, c;
+        ~EvGuard() {
+            hipEventDestroy(a);
+            hipEventDestroy(b);
+            hipEventDestroy(c);
+        }
+    } evg{ev0, ev1, ev2};
+
+    // ---- sizing
+    int H = p->hash_slots ? p->hash_slots : 1024;
+    int waves = 4;
+    int spill_slots = 4096;
+    int64_t pool_cap = std::max<int64_t>(n_tasks * 64, 1 << 16);
+    const int cus = device_cus();
+    uint64_t retries = 0;
+
+    DevBuf row_start, row_cnt, pool_col, pool_val, sk, sv, su, ctrl, row_ptr, scan_tmp;
+    // ctrl: [0..7] queue counters (u32), then u64 pool_used, u64 stats[4], u32 flags
+    const size_t ctrl_bytes = 8 * 4 + 8 + 4 * 8 + 8;
+    MCMI_HIP(ctrl.alloc(ctrl_bytes, s));
+    MCMI_HIP(row_start.alloc(n_tasks * sizeof(int64_t), s));
+    MCMI_HIP(row_cnt.alloc(n_tasks * sizeof(uint32_t), s));
+    MCMI_HIP(row_ptr.alloc((n_tasks + 1) * sizeof(int64_t), s));
+    MCMI_HIP(scan_tmp.alloc(scan_tmp_bytes(n_tasks), s));
+    uint32_t *qctr = ctrl.as<uint32_t>();
+    unsigned long long *pool_used = (unsigned long long *)(ctrl.as<unsigned char>() + 32);
+    unsigned long long *stats = (unsigned long long *)(ctrl.as<unsigned char>() + 40);
+    uint32_t *flags = (uint32_t *)(ctrl.as<unsigned char>() + 72);
+
+    if (rows_dev || chains_per_row_dev) {
+        uint32_t hbad = 0;
+        MCMI_HIP(hipMemsetAsync(flags, 0, sizeof(uint32_t), s));
+        MCMI_HIP(validate_rows(rows_dev, rows_dev ? n_rows : 0, chains_per_row_dev, cdf->n, flags, s));
+        MCMI_HIP(hipMemcpyAsync(&hbad, flags, sizeof(hbad), hipMemcpyDeviceToHost, s));
+        MCMI_HIP(hipStreamSynchronize(s));
+        if (hbad & 1u) return fail(MCMI_ERR_ARG, "mcmi_spai: a row index is outside [0, n)");
+        if (hbad & 2u) return fail(MCMI_ERR_ARG, "mcmi_spai: chains_per_row holds a value < 1");
+    }
+
+    int64_t nnz = 0;
+    unsigned long long hstats[4] = {0, 0, 0, 0};
+    float ms_walk = 0.f;
+    MCMI_HIP(hipEventRecord(ev0, s));
+    for (;;) {
+        int bpc = 0;
+        MCMI_HIP(walk_occupancy(f32, H, waves, &bpc));
+        if (bpc < 1) {
+            if (waves > 1) {
+                waves >>= 1;
+                continue;
+            }
+            return fail(MCMI_ERR_CAPACITY, "mcmi_spai: hash table does not fit in LDS");
+        }
+        int64_t blocks = (int64_t)bpc * cus;
+        const int64_t need_waves = (n_tasks + 0);
+        if (blocks * waves > need_waves) blocks = std::max<int64_t>(1, (need_waves + waves - 1) / waves);
+        const int64_t total_waves = blocks * waves;
+        MCMI_HIP(pool_col.alloc((size_t)pool_cap * sizeof(int32_t), s));
+        MCMI_HIP(pool_val.alloc((size_t)pool_cap * sizeof(double), s));
+        MCMI_HIP(sk.alloc((size_t)total_waves * spill_slots * sizeof(int32_t), s));
+        MCMI_HIP(sv.alloc((size_t)total_waves * spill_slots * sizeof(double), s));
+        MCMI_HIP(su.alloc((size_t)total_waves * spill_slots * sizeof(int32_t), s));
+        MCMI_HIP(hipMemsetAsync(sk.p, 0xFF, (size_t)total_waves * spill_slots * sizeof(int32_t), s));
+        MCMI_HIP(hipMemsetAsync(sv.p, 0, (size_t)total_waves * spill_slots * sizeof(double), s));
+        MCMI_HIP(hipMemsetAsync(ctrl.p, 0, ctrl_bytes, s));
+
+        WalkArgs a;
+        memset(&a, 0, sizeof(a));
+        a.rec = cdf->rec;
+        a.roff = cdf->roff;
+        a.diag = cdf->diag;
+        a.rows = rows_dev;
+        a.n_tasks = n_tasks;
+        a.chains_per_row = chains_per_row_dev;
+        a.chains = p->chains;
+        a.key0 = (uint32_t)(p->seed & 0xffffffffu);
+        a.key1 = (uint32_t)(p->seed >> 32);
+        a.tag = p->stream_tag;
+        a.delta = p->delta;
+        a.delta32 = (float)p->delta;
+        a.eps = p->eps;
+        a.lmax = lmax;
+        a.filter_m = p->filter == MCMI_FILTER_M;
+        a.hash_slots = H;
+        a.hash_shift = 32 - __builtin_ctz((unsigned)H);
+        a.queue_ctr = qctr;
+        a.row_start = row_start.as<int64_t>();
+        a.row_cnt = row_cnt.as<uint32_t>();
+        a.pool_col = pool_col.as<int32_t>();
+        a.pool_val = pool_val.as<double>();
+        a.pool_cap = pool_cap;
+        a.pool_used = pool_used;
+        a.spill_keys = sk.as<int32_t>();
+        a.spill_vals = sv.as<double>();
+        a.spill_used = su.as<int32_t>();
+        a.spill_slots = spill_slots;
+        a.stats = stats;
+        a.flags = flags;
+        MCMI_HIP(hipEventRecord(ev1, s));
+        MCMI_HIP(launch_walk(a, f32, (int)blocks, waves, s));
+        MCMI_HIP(hipEventRecord(ev2, s));
+        MCMI_HIP(scan_exclusive_u32_to_i64(row_cnt.as<uint32_t>(), row_ptr.as<int64_t>(), n_tasks,
+                                           row_ptr.as<int64_t>() + n_tasks, scan_tmp.p, s));
+        uint32_t hflags = 0;
+        unsigned long long hused = 0;
+        MCMI_HIP(hipMemcpyAsync(&hflags, flags, sizeof(hflags), hipMemcpyDeviceToHost, s));
+        MCMI_HIP(hipMemcpyAsync(&hused, pool_used, sizeof(hused), hipMemcpyDeviceToHost, s));
+        MCMI_HIP(hipMemcpyAsync(hstats, stats, sizeof(hstats), hipMemcpyDeviceToHost, s));
+        MCMI_HIP(hipMemcpyAsync(&nnz, row_ptr.as<int64_t>() + n_tasks, sizeof(nnz), hipMemcpyDeviceToHost, s));
+        MCMI_HIP(hipStreamSynchronize(s));
+        MCMI_HIP(hipEventElapsedTime(&ms_walk, ev1, ev2));
+        if (!(hflags & (kFlagPool | kFlagSpill | kFlagStage))) break;
+        if (++retries > 6) return fail(MCMI_ERR_CAPACITY, "mcmi_spai: tables still overflow after 6 regrowths");
+        if (hflags & kFlagPool) pool_cap = (int64_t)hused + 1024;
+        if (hflags & kFlagSpill) spill_slots *= 4;
+        if (hflags & kFlagStage) {
+            if (H >= 8192) return fail(MCMI_ERR_CAPACITY, "mcmi_spai: more survivors per row than 8192 slots");
+            H *= 2;
+        }
+    }
+
+    // ---- CSR assembly
+    hipEvent_t ev3;
+    MCMI_HIP(hipEventCreate(&ev3));
+    int32_t *col = nullptr;
+    double *val = nullptr;
+    int64_t *rp = nullptr;
+    hipError_t e1 = hipMalloc(&col, (size_t)std::max<int64_t>(nnz, 1) * sizeof(int32_t));
+    hipError_t e2 = hipMalloc(&val, (size_t)std::max<int64_t>(nnz, 1) * sizeof(double));
+    hipError_t e3 = hipMalloc(&rp, (size_t)(n_tasks + 1) * sizeof(int64_t));
+    if (e1 != hipSuccess || e2 != hipSuccess || e3 != hipSuccess) {
+        hipFree(col);
+        hipFree(val);
+        hipFree(rp);
+        hipEventDestroy(ev3);
+        return fail(MCMI_ERR_NOMEM, "mcmi_spai: cannot allocate M");
+    }
+    hipError_t ge = hipMemcpyAsync(rp, row_ptr.p, (size_t)(n_tasks + 1) * sizeof(int64_t), hipMemcpyDeviceToDevice, s);
+    if (ge == hipSuccess)
+        ge = gather_rows(n_tasks, row_start.as<int64_t>(), row_cnt.as<uint32_t>(), rp, pool_col.as<int32_t>(),
+                         pool_val.as<double>(), col, val, s);
+    if (ge == hipSuccess) ge = hipEventRecord(ev3, s);
+    if (ge == hipSuccess) ge = hipEventSynchronize(ev3);
+    if (ge != hipSuccess) {
+        hipFree(col);
+        hipFree(val);
+        hipFree(rp);
+        hipEventDestroy(ev3);
+        return fail(MCMI_ERR_HIP, std::string("mcmi_spai: assembly: ") + hipGetErrorString(ge));
+    }
+    M->n = n_tasks;
+    M->nnz = nnz;
+    M->row_ptr_dev = rp;
+    M->col_dev = col;
+    M->val_dev = val;
+    if (st) {
+        float ms_tot = 0.f, ms_asm = 0.f;
+        hipEventElapsedTime(&ms_tot, ev0, ev3);
+        hipEventElapsedTime(&ms_asm, ev2, ev3);
+        st->transitions = hstats[0];
+        st->spilled = hstats[1];
+        st->chains = hstats[2];
+        st->retries = retries;
+        st->nnz = nnz;
+        st->lmax = lmax;
+        st->norm_inf = (float)cdf->norm_inf;
+        st->ms_walk = ms_walk;
+        st->ms_assemble = ms_asm;
+        st->ms_total = ms_tot;
+    }
+    hipEventDestroy(ev3);
+    return MCMI_OK;
+}
+
+extern "C" mcmi_status mcmi_apply(const mcmi_csr_out *M, int64_t n_cols, const double *x_dev, double *y_dev,
+                                  void *stream) {
+    if (!M || !x_dev || !y_dev || n_cols < 1) return fail(MCMI_ERR_ARG, "mcmi_apply: bad argument");
+    if (M->n < 0 || (M->n > 0 && !M->row_ptr_dev)) return fail(MCMI_ERR_ARG, "mcmi_apply: bad M");
+    MCMI_HIP(spmv(M->n, M->row_ptr_dev, M->col_dev, M->val_dev, x_dev, y_dev, (hipStream_t)stream));
+    return MCMI_OK;
+}
+
+extern "C" mcmi_status mcmi_csr_copy(const mcmi_csr_out *M, int64_t *row_ptr_dev, int32_t *col_dev,
+                                     double *val_dev, void *stream) {
+    if (!M || !row_ptr_dev || (M->nnz > 0 && (!col_dev || !val_dev))) return fail(MCMI_ERR_ARG, "mcmi_csr_copy: bad argument");
+    hipStream_t s = (hipStream_t)stream;
+    MCMI_HIP(hipMemcpyAsync(row_ptr_dev, M->row_ptr_dev, (size_t)(M->n + 1) * sizeof(int64_t), hipMemcpyDeviceToDevice, s));
+    if (M->nnz > 0) {
+        MCMI_HIP(hipMemcpyAsync(col_dev, M->col_dev, (size_t)M->nnz * sizeof(int32_t), hipMemcpyDeviceToDevice, s));
+        MCMI_HIP(hipMemcpyAsync(val_dev, M->val_dev, (size_t)M->nnz * sizeof(double), hipMemcpyDeviceToDevice, s));
+    }
+    return MCMI_OK;
+}
+
+extern "C" void mcmi_csr_free(mcmi_csr_out *M) {
+    if (!M) return;
+    hipFree(M->row_ptr_dev);
+    hipFree(M->col_dev);
+    hipFree(M->val_dev);
+    memset(M, 0, sizeof(*M));
+}
+
+extern "C" const char *mcmi_last_error(void) { return g_last_error.c_str(); }
+
+extern "C" const char *mcmi_version(void) { return "mcmi 0.1 gfx950"; }

@@ -1,0 +1,314 @@
+// Row records of C = I - D^-1 B and their integer CDFs (gfx950).
+//
+// Section IV, phase 2 forms the iteration matrix; the transition matrix P of
+// Section IV-A is, here, p_ij proportional to |c_ij|, quantized per row:
+//   a_k = |c_k|, a_max = max_k a_k, Q = 31 - ceil(log2 m),
+//   w_k = max(1, floor(2^Q a_k / a_max)), cum_k = w_1 + ... + w_k (exact uint32),
+//   W = cum_m, Shat = (a_max * W) * 2^-Q (one rounding).
+// The integer scan is order-free, so a wavefront prefix scan gives exactly the
+// sequential sums.
+#include <string.h>
+
+#include "common.hpp"
+
+namespace mcmi {
+
+namespace {
+
+__device__ __forceinline__ int ceil_log2_u32(uint32_t m) {
+    int q = 0;
+    while ((1u << q) < m) ++q;  // m < 2^31 here
+    return q;
+}
+
+// Validate row r of B, find its diagonal and count its nonzero off-diagonals.
+__global__ void __launch_bounds__(256) k_count(int64_t n, int64_t nnz, const int64_t *__restrict__ rp,
+                                               const int32_t *__restrict__ ci, const double *__restrict__ v,
+                                               uint32_t *__restrict__ mrow, uint32_t *__restrict__ units,
+                                               double *__restrict__ diag, uint32_t *__restrict__ flags) {
+    const int lane = threadIdx.x & 63;
+    const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
+    if (wave == 0 && lane == 0 && (rp[0] != 0 || rp[n] != nnz)) atomicOr(flags, kFlagCsr);
+    for (int64_t r = wave; r < n; r += nwaves) {
+        const int64_t b = rp[r], e = rp[r + 1];
+        if (b < 0 || e < b || e > nnz) {
+            if (lane == 0) {
+                atomicOr(flags, kFlagCsr);
+                mrow[r] = 0;
+                units[r] = record_units(0);
+                diag[r] = 0.0;
+            }
+            continue;
+        }
+        bool bad = false, found = false;
+        double dv = 0.0;
+        for (int64_t k = b + lane; k < e; k += 64) {
+            const int32_t c = ci[k];
+            bad |= (c < 0) || ((int64_t)c >= n) || (k > b && ci[k - 1] >= c);
+            if ((int64_t)c == r) {
+                found = true;
+                dv = v[k];
+            }
+        }
+        const uint64_t fb = ballot(found);
+        const uint64_t bb = ballot(bad);
+        const double d = fb ? __shfl(dv, __builtin_ctzll(fb), 64) : 0.0;
+        // entries of C: off-diagonals whose quotient (-b_ij) / b_ii is nonzero
+        uint32_t cnt = 0;
+        if (fb && d != 0.0)
+            for (int64_t k = b + lane; k < e; k += 64)
+                if ((int64_t)ci[k] != r && (-v[k]) / d != 0.0) ++cnt;
+        cnt = wave_sum(cnt);
+        if (lane == 0) {
+            if (bb) atomicOr(flags, kFlagCsr);
+            if (!fb || d == 0.0) atomicOr(flags, kFlagZeroDiag);
+            mrow[r] = cnt;
+            units[r] = record_units(cnt);
+            diag[r] = d;
+        }
+    }
+}
+
+// Write each row's header and its sorted {cum, target} nodes into `sorted`
+// (C-row order, at cptr[r]), and the row's record offset as 32 bits.
+__global__ void __launch_bounds__(256) k_fill(int64_t n, const int64_t *__restrict__ rp,
+                                              const int32_t *__restrict__ ci, const double *__restrict__ v,
+                                              const double *__restrict__ diag, const uint32_t *__restrict__ mrow,
+                                              const int64_t *__restrict__ roff64, const int64_t *__restrict__ cptr,
+                                              uint32_t *__restrict__ roff32, uint32_t *__restrict__ rec,
+                                              uint2 *__restrict__ sorted, unsigned long long *__restrict__ norm_bits) {
+    const int lane = threadIdx.x & 63;
+    const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
+    for (int64_t r = wave; r < n; r += nwaves) {
+        const int64_t b = rp[r], e = rp[r + 1];
+        const uint32_t m = mrow[r];
+        const double d = diag[r];
+        const uint32_t off = (uint32_t)roff64[r];
+        uint32_t *hdr = rec + (size_t)off * 4u;
+        if (lane == 0) roff32[r] = off;
+        if (m == 0) {
+            if (lane == 0) {
+                hdr[0] = (uint32_t)r;
+                hdr[1] = 0u;
+                hdr[2] = 0u;
+                hdr[3] = __float_as_uint(0.0f);
+                *(double *)(hdr + 4) = 0.0;
+            }
+            continue;
+        }
+        // a_max over the row (order-free)
+        double amax = 0.0;
+        for (int64_t k = b + lane; k < e; k += 64) {
+            const int32_t c = ci[k];
+            if ((int64_t)c != r) {
+                const double a = fabs((-v[k]) / d);
+                amax = a > amax ? a : amax;
+            }
+        }
+        amax = wave_max(amax);
+        const int q = 31 - ceil_log2_u32(m);
+        // quantize and scan in column order, 64 entries at a time
+        uint32_t carry = 0, placed = 0;
+        const int64_t base = cptr[r];
+        for (int64_t k0 = b; k0 < e; k0 += 64) {
+            const int64_t k = k0 + lane;
+            bool valid = false;
+            uint32_t w = 0, tgt = 0;
+            if (k < e) {
+                const int32_t c = ci[k];
+                if ((int64_t)c != r) {
+                    const double cv = (-v[k]) / d;
+                    if (cv != 0.0) {
+                        valid = true;
+                        const double scaled = floor(ldexp(fabs(cv) / amax, q));
+                        w = scaled < 1.0 ? 1u : (uint32_t)scaled;
+                        tgt = (uint32_t)roff64[c] | (cv < 0.0 ? kSignBit : 0u);
+                    }
+                }
+            }
+            const uint64_t vm = ballot(valid);
+            const uint32_t incl = wave_incl_scan(w);
+            if (valid) {
+                const uint32_t pos = placed + (uint32_t)mask_rank(vm);
+                sorted[base + pos] = make_uint2(carry + incl, tgt);
+            }
+            carry += __shfl(incl, 63, 64);
+            placed += (uint32_t)__popcll(vm);
+        }
+        if (lane == 0) {
+            const double shat = ldexp(amax * (double)carry, -q);
+            hdr[0] = (uint32_t)r;
+            hdr[1] = m;
+            hdr[2] = carry;
+            hdr[3] = __float_as_uint((float)shat);
+            *(double *)(hdr + 4) = shat;
+            atomicMax(norm_bits, (unsigned long long)__double_as_longlong(shat));
+        }
+    }
+}
+
+// number of nodes in the subtree of breadth-first position x of a complete
+// binary tree with m nodes (positions 1..m)
+__device__ __forceinline__ uint32_t subtree_size(uint64_t x, uint64_t m) {
+    uint64_t lo = x, hi = x, cnt = 0;
+    while (lo <= m) {
+        cnt += (hi < m ? hi : m) - lo + 1;
+        lo = 2 * lo;
+        hi = 2 * hi + 1;
+    }
+    return (uint32_t)cnt;
+}
+
+// in-order rank (0-based) of breadth-first position e
+__device__ __forceinline__ uint32_t inorder_rank(uint32_t e, uint32_t m) {
+    const int depth = 31 - __builtin_clz(e);
+    uint32_t rank = 0;
+    for (int i = depth - 1; i >= 0; --i) {
+        const uint32_t anc = e >> (i + 1);
+        if ((e >> i) & 1u) rank += subtree_size(2ull * anc, m) + 1u;
+    }
+    return rank + subtree_size(2ull * e, m);
+}
+
+// Place the sorted nodes of each row at their breadth-first positions.
+__global__ void __launch_bounds__(256) k_eytzinger(int64_t n, const uint32_t *__restrict__ mrow,
+                                                   const uint32_t *__restrict__ roff32,
+                                                   const int64_t *__restrict__ cptr,
+                                                   const uint2 *__restrict__ sorted, uint32_t *__restrict__ rec) {
+    const int lane = threadIdx.x & 63;
+    const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
+    for (int64_t r = wave; r < n; r += nwaves) {
+        const uint32_t m = mrow[r];
+        const int64_t base = cptr[r];
+        uint2 *nodes = (uint2 *)(rec + (size_t)roff32[r] * 4u + kHdrWords);
+        for (uint32_t e = 1u + lane; e <= m; e += 64) nodes[e - 1] = sorted[base + inorder_rank(e, m)];
+    }
+}
+
+unsigned grid_for_rows(int64_t n) {
+    int64_t blocks = (n + 3) / 4;  // 4 waves per block, one row per wave
+    if (blocks > 16384) blocks = 16384;
+    if (blocks < 1) blocks = 1;
+    return (unsigned)blocks;
+}
+
+}  // namespace
+}  // namespace mcmi
+
+using namespace mcmi;
+
+extern "C" mcmi_status mcmi_build_cdf(const mcmi_csr_in *B, mcmi_cdf **out, void *stream) {
+    if (out) *out = nullptr;
+    if (!B || !out) return fail(MCMI_ERR_ARG, "mcmi_build_cdf: null argument");
+    if (B->n <= 0 || B->n >= (int64_t)INT32_MAX || B->nnz < B->n || !B->row_ptr_dev || !B->col_dev || !B->val_dev)
+        return fail(MCMI_ERR_ARG, "mcmi_build_cdf: need 0 < n < 2^31, nnz >= n and device pointers");
+    hipStream_t s = (hipStream_t)stream;
+    const int64_t n = B->n;
+    mcmi_cdf *cdf = new mcmi_cdf();
+    cdf->n = n;
+    uint32_t *units = nullptr, *flags = nullptr;
+    int64_t *roff64 = nullptr, *cptr = nullptr, *totals = nullptr;
+    unsigned long long *norm_bits = nullptr;
+    void *tmp = nullptr;
+    uint2 *sorted = nullptr;
+    mcmi_status st = MCMI_OK;
+    auto cleanup = [&]() {
+        hipFree(units);
+        hipFree(flags);
+        hipFree(roff64);
+        hipFree(cptr);
+        hipFree(totals);
+        hipFree(norm_bits);
+        hipFree(tmp);
+        hipFree(sorted);
+    };
+    auto bail = [&](mcmi_status code, const std::string &msg) {
+        cleanup();
+        mcmi_cdf_free(cdf);
+        return fail(code, msg);
+    };
+#define TRY(call)                                                                             \
+    do {                                                                                      \
+        hipError_t _e = (call);                                                               \
+        if (_e != hipSuccess) return bail(MCMI_ERR_HIP, std::string(#call) + ": " + hipGetErrorString(_e)); \
+    } while (0)
+    TRY(hipMalloc(&cdf->mrow, n * sizeof(uint32_t)));
+    TRY(hipMalloc(&cdf->diag, n * sizeof(double)));
+    TRY(hipMalloc(&cdf->roff, n * sizeof(uint32_t)));
+    TRY(hipMalloc(&units, n * sizeof(uint32_t)));
+    TRY(hipMalloc(&flags, sizeof(uint32_t)));
+    TRY(hipMalloc(&roff64, n * sizeof(int64_t)));
+    TRY(hipMalloc(&cptr, n * sizeof(int64_t)));
+    TRY(hipMalloc(&totals, 2 * sizeof(int64_t)));
+    TRY(hipMalloc(&norm_bits, sizeof(unsigned long long)));
+    TRY(hipMalloc(&tmp, scan_tmp_bytes(n)));
+    TRY(hipMemsetAsync(flags, 0, sizeof(uint32_t), s));
+    TRY(hipMemsetAsync(norm_bits, 0, sizeof(unsigned long long), s));
+    const unsigned grid = grid_for_rows(n);
+    k_count<<<grid, 256, 0, s>>>(n, B->nnz, B->row_ptr_dev, B->col_dev, B->val_dev, cdf->mrow, units, cdf->diag,
+                                 flags);
+    TRY(hipGetLastError());
+    TRY(scan_exclusive_u32_to_i64(units, roff64, n, totals + 0, tmp, s));
+    TRY(scan_exclusive_u32_to_i64(cdf->mrow, cptr, n, totals + 1, tmp, s));
+    uint32_t hflags = 0;
+    int64_t htot[2] = {0, 0};
+    TRY(hipMemcpyAsync(&hflags, flags, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+    TRY(hipMemcpyAsync(htot, totals, sizeof(htot), hipMemcpyDeviceToHost, s));
+    TRY(hipStreamSynchronize(s));
+    if (hflags & kFlagCsr) return bail(MCMI_ERR_CSR, "mcmi_build_cdf: invalid CSR (row_ptr, column range or order)");
+    if (hflags & kFlagZeroDiag) return bail(MCMI_ERR_ZERO_DIAG, "mcmi_build_cdf: missing or zero diagonal");
+    if (htot[0] >= (int64_t)kSignBit) return bail(MCMI_ERR_CAPACITY, "mcmi_build_cdf: records exceed 32 GiB");
+    cdf->rec_units = (uint64_t)htot[0];
+    cdf->nnz_c = htot[1];
+    TRY(hipMalloc(&cdf->rec, (size_t)htot[0] * 16u + 16u));
+    TRY(hipMalloc(&sorted, (size_t)(htot[1] > 0 ? htot[1] : 1) * sizeof(uint2)));
+    k_fill<<<grid, 256, 0, s>>>(n, B->row_ptr_dev, B->col_dev, B->val_dev, cdf->diag, cdf->mrow, roff64, cptr,
+                                cdf->roff, cdf->rec, sorted, norm_bits);
+    TRY(hipGetLastError());
+    k_eytzinger<<<grid, 256, 0, s>>>(n, cdf->mrow, cdf->roff, cptr, sorted, cdf->rec);
+    TRY(hipGetLastError());
+    unsigned long long hnorm = 0;
+    TRY(hipMemcpyAsync(&hnorm, norm_bits, sizeof(hnorm), hipMemcpyDeviceToHost, s));
+    TRY(hipStreamSynchronize(s));
+    double nrm;
+    ::memcpy(&nrm, &hnorm, sizeof(nrm));
+    cdf->norm_inf = nrm;
+#undef TRY
+    cleanup();
+    *out = cdf;
+    return st;
+}
+
+extern "C" mcmi_status mcmi_cdf_info(const mcmi_cdf *cdf, int64_t *n, int64_t *nnz_c, double *norm_inf,
+                                     uint64_t *rec_units) {
+    if (!cdf) return fail(MCMI_ERR_ARG, "mcmi_cdf_info: null cdf");
+    if (n) *n = cdf->n;
+    if (nnz_c) *nnz_c = cdf->nnz_c;
+    if (norm_inf) *norm_inf = cdf->norm_inf;
+    if (rec_units) *rec_units = cdf->rec_units;
+    return MCMI_OK;
+}
+
+extern "C" mcmi_status mcmi_cdf_download(const mcmi_cdf *cdf, uint32_t *rec_host, uint32_t *roff_host,
+                                         double *diag_host, void *stream) {
+    if (!cdf) return fail(MCMI_ERR_ARG, "mcmi_cdf_download: null cdf");
+    hipStream_t s = (hipStream_t)stream;
+    if (rec_host)
+        MCMI_HIP(hipMemcpyAsync(rec_host, cdf->rec, (size_t)cdf->rec_units * 16u, hipMemcpyDeviceToHost, s));
+    if (roff_host) MCMI_HIP(hipMemcpyAsync(roff_host, cdf->roff, (size_t)cdf->n * 4u, hipMemcpyDeviceToHost, s));
+    if (diag_host) MCMI_HIP(hipMemcpyAsync(diag_host, cdf->diag, (size_t)cdf->n * 8u, hipMemcpyDeviceToHost, s));
+    MCMI_HIP(hipStreamSynchronize(s));
+    return MCMI_OK;
+}
+
+extern "C" void mcmi_cdf_free(mcmi_cdf *cdf) {
+    if (!cdf) return;
+    hipFree(cdf->rec);
+    hipFree(cdf->roff);
+    hipFree(cdf->diag);
+    hipFree(cdf->mrow);
+    delete cdf;
+}

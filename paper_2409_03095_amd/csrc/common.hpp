@@ -1,0 +1,143 @@
+// Internal header of libmcmi.so (gfx950). Not part of the public ABI.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+
+#include "../../include/mcmi.h"
+
+namespace mcmi {
+
+// ------------------------------------------------------------------ errors
+void set_error(const std::string &msg);
+mcmi_status fail(mcmi_status st, const std::string &msg);
+
+#define MCMI_HIP(call)                                                                     \
+    do {                                                                                   \
+        hipError_t _e = (call);                                                            \
+        if (_e != hipSuccess)                                                              \
+            return ::mcmi::fail(MCMI_ERR_HIP, std::string(#call) + ": " + hipGetErrorString(_e)); \
+    } while (0)
+
+// ----------------------------------------------------------- record layout
+// One record per row s of C, 16-byte aligned, addressed by its offset in
+// 16-byte units (31 bits, so up to 32 GiB of records):
+//   word 0  row index s               word 1  m = entries of row s of C
+//   word 2  W = total integer weight  word 3  Shat_s as binary32
+//   words 4-5  Shat_s as binary64
+//   words 6 + 2(e-1), 7 + 2(e-1), e = 1..m: node e of the row's CDF in
+//   Eytzinger (breadth-first) order: {cum, target}, where cum is the inclusive
+//   integer prefix sum of the weights in column order and target is the
+//   record offset of the column's row with bit 31 set when c < 0.
+constexpr int kHdrWords = 6;
+constexpr uint32_t kSignBit = 0x80000000u;
+
+__host__ __device__ inline uint32_t record_units(uint32_t m) { return (kHdrWords + 2u * m + 3u) / 4u; }
+
+// Error flags raised by device-side validation (bit set).
+enum : uint32_t {
+    kFlagCsr = 1u,        // unsorted / duplicate / out-of-range column or bad row_ptr
+    kFlagZeroDiag = 2u,   // missing or zero diagonal
+    kFlagTooBig = 4u,     // record area above 2^31 units
+    kFlagPool = 8u,       // output pool overflow
+    kFlagSpill = 16u,     // spill table overflow
+    kFlagStage = 32u,     // more survivors than the staging area holds
+};
+
+// ------------------------------------------------------------------ Philox
+// Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11): ten rounds; each round
+// takes the 64-bit products of counter words 0 and 2 with two fixed odd
+// multipliers and forms the next block from their halves, words 1 and 3 and the
+// round key; the key advances by two Weyl increments between rounds.
+struct u32x4 {
+    uint32_t x, y, z, w;
+};
+
+__device__ __forceinline__ u32x4 philox4x32_10(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
+                                                uint32_t k0, uint32_t k1) {
+    constexpr uint32_t kMulA = 0xD2511F53u, kMulB = 0xCD9E8D57u;
+    constexpr uint32_t kWeylA = 0x9E3779B9u, kWeylB = 0xBB67AE85u;
+#pragma unroll
+    for (int round = 0; round < 10; ++round) {
+        const uint32_t hiA = __umulhi(kMulA, c0), loA = kMulA * c0;
+        const uint32_t hiB = __umulhi(kMulB, c2), loB = kMulB * c2;
+        const uint32_t n0 = hiB ^ c1 ^ k0;
+        const uint32_t n2 = hiA ^ c3 ^ k1;
+        c0 = n0;
+        c1 = loB;
+        c2 = n2;
+        c3 = loA;
+        k0 += kWeylA;
+        k1 += kWeylB;
+    }
+    return {c0, c1, c2, c3};
+}
+
+// ---------------------------------------------------------- wave helpers
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+__device__ __forceinline__ int lane_id() { return __lane_id(); }
+
+__device__ __forceinline__ uint64_t ballot(bool p) { return __ballot(p); }
+
+// number of set bits of `mask` below this lane
+__device__ __forceinline__ int mask_rank(uint64_t mask) {
+    return __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0));
+}
+
+template <typename T>
+__device__ __forceinline__ T wave_sum(T v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+template <typename T>
+__device__ __forceinline__ T wave_max(T v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        T o = __shfl_xor(v, off, 64);
+        v = o > v ? o : v;
+    }
+    return v;
+}
+
+// inclusive prefix sum over the 64 lanes
+template <typename T>
+__device__ __forceinline__ T wave_incl_scan(T v) {
+    const int lane = lane_id();
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        T o = __shfl_up(v, off, 64);
+        if (lane >= off) v += o;
+    }
+    return v;
+}
+
+// --------------------------------------------------------------- scans
+// Exclusive prefix sum of n int64 values (out may alias in); writes the total
+// to *total_dev (device). Temporary memory comes from `tmp` (>= scan_tmp_bytes(n)).
+size_t scan_tmp_bytes(int64_t n);
+hipError_t scan_exclusive_i64(const int64_t *in, int64_t *out, int64_t n, int64_t *total_dev, void *tmp,
+                              hipStream_t s);
+hipError_t scan_exclusive_u32_to_i64(const uint32_t *in, int64_t *out, int64_t n, int64_t *total_dev, void *tmp,
+                                     hipStream_t s);
+
+}  // namespace mcmi
+
+// The opaque record set.
+struct mcmi_cdf {
+    int64_t n = 0;
+    int64_t nnz_c = 0;
+    double norm_inf = 0.0;
+    uint64_t rec_units = 0;
+    uint32_t *rec = nullptr;       // records, 4 words per unit
+    uint32_t *roff = nullptr;      // n: record offset (16-byte units) of each row
+    double *diag = nullptr;        // n: b_ii
+    uint32_t *mrow = nullptr;      // n: entries of each row of C
+};

@@ -1,0 +1,186 @@
+// Device prefix sums, CSR assembly helpers and the SpMV y = M x (gfx950).
+#include "common.hpp"
+
+namespace mcmi {
+
+namespace {
+constexpr int kScanThreads = 256;
+constexpr int kScanPer = 4;
+constexpr int kScanTile = kScanThreads * kScanPer;
+
+template <typename T>
+__device__ __forceinline__ int64_t load_as_i64(const T *p, int64_t i, int64_t n) {
+    return i < n ? (int64_t)p[i] : 0;
+}
+
+// block-wide exclusive scan of one int64 per thread; returns the block total
+__device__ int64_t block_excl_scan(int64_t v, int64_t *out_excl) {
+    __shared__ int64_t warp_tot[kScanThreads / 64];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    int64_t incl = wave_incl_scan(v);
+    if (lane == 63) warp_tot[w] = incl;
+    __syncthreads();
+    int64_t base = 0, total = 0;
+    for (int k = 0; k < kScanThreads / 64; ++k) {
+        if (k < w) base += warp_tot[k];
+        total += warp_tot[k];
+    }
+    __syncthreads();
+    *out_excl = base + incl - v;
+    return total;
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kScanThreads) k_tile_sums(const T *in, int64_t n, int64_t *sums) {
+    const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanPer;
+    int64_t v = 0;
+#pragma unroll
+    for (int k = 0; k < kScanPer; ++k) v += load_as_i64(in, base + k, n);
+    int64_t ex;
+    int64_t tot = block_excl_scan(v, &ex);
+    if (threadIdx.x == 0) sums[blockIdx.x] = tot;
+}
+
+__global__ void __launch_bounds__(kScanThreads) k_scan_sums(int64_t *sums, int64_t nb, int64_t *total) {
+    int64_t carry = 0;
+    for (int64_t b0 = 0; b0 < nb; b0 += kScanThreads) {
+        const int64_t i = b0 + threadIdx.x;
+        int64_t v = i < nb ? sums[i] : 0;
+        int64_t ex;
+        int64_t tot = block_excl_scan(v, &ex);
+        if (i < nb) sums[i] = carry + ex;
+        carry += tot;
+    }
+    if (threadIdx.x == 0 && total) *total = carry;
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kScanThreads) k_tile_scan(const T *in, int64_t *out, int64_t n,
+                                                           const int64_t *sums) {
+    const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanPer;
+    int64_t v[kScanPer];
+    int64_t tsum = 0;
+#pragma unroll
+    for (int k = 0; k < kScanPer; ++k) {
+        v[k] = load_as_i64(in, base + k, n);
+        tsum += v[k];
+    }
+    int64_t ex;
+    block_excl_scan(tsum, &ex);
+    int64_t run = sums[blockIdx.x] + ex;
+#pragma unroll
+    for (int k = 0; k < kScanPer; ++k) {
+        if (base + k < n) out[base + k] = run;
+        run += v[k];
+    }
+}
+
+template <typename T>
+hipError_t scan_impl(const T *in, int64_t *out, int64_t n, int64_t *total_dev, void *tmp, hipStream_t s) {
+    const int64_t nb = (n + kScanTile - 1) / kScanTile;
+    int64_t *sums = (int64_t *)tmp;
+    if (nb > 0) {
+        k_tile_sums<T><<<(unsigned)nb, kScanThreads, 0, s>>>(in, n, sums);
+    }
+    k_scan_sums<<<1, kScanThreads, 0, s>>>(sums, nb, total_dev);
+    if (nb > 0) {
+        k_tile_scan<T><<<(unsigned)nb, kScanThreads, 0, s>>>(in, out, n, sums);
+    }
+    return hipGetLastError();
+}
+}  // namespace
+
+size_t scan_tmp_bytes(int64_t n) { return (size_t)((n + kScanTile - 1) / kScanTile + 1) * sizeof(int64_t); }
+
+hipError_t scan_exclusive_i64(const int64_t *in, int64_t *out, int64_t n, int64_t *total_dev, void *tmp,
+                              hipStream_t s) {
+    return scan_impl<int64_t>(in, out, n, total_dev, tmp, s);
+}
+
+hipError_t scan_exclusive_u32_to_i64(const uint32_t *in, int64_t *out, int64_t n, int64_t *total_dev, void *tmp,
+                                     hipStream_t s) {
+    return scan_impl<uint32_t>(in, out, n, total_dev, tmp, s);
+}
+
+// ------------------------------------------------------------- assembly
+// Copy each row's survivors from the pool (row_start, row_cnt) into the CSR
+// arrays at row_ptr. One wave per row, lanes over entries (coalesced).
+__global__ void __launch_bounds__(256) k_gather_rows(int64_t n_rows, const int64_t *row_start,
+                                                     const uint32_t *row_cnt, const int64_t *row_ptr,
+                                                     const int32_t *pool_col, const double *pool_val,
+                                                     int32_t *col, double *val) {
+    const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const int lane = threadIdx.x & 63;
+    const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
+    for (int64_t r = wave; r < n_rows; r += nwaves) {
+        const int64_t src = row_start[r], dst = row_ptr[r];
+        const uint32_t cnt = row_cnt[r];
+        for (uint32_t k = lane; k < cnt; k += 64) {
+            col[dst + k] = pool_col[src + k];
+            val[dst + k] = pool_val[src + k];
+        }
+    }
+}
+
+hipError_t gather_rows(int64_t n_rows, const int64_t *row_start, const uint32_t *row_cnt, const int64_t *row_ptr,
+                       const int32_t *pool_col, const double *pool_val, int32_t *col, double *val,
+                       hipStream_t s) {
+    if (n_rows <= 0) return hipSuccess;
+    int64_t blocks = (n_rows + 3) / 4;
+    if (blocks > 65536) blocks = 65536;
+    k_gather_rows<<<(unsigned)blocks, 256, 0, s>>>(n_rows, row_start, row_cnt, row_ptr, pool_col, pool_val, col,
+                                                   val);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------ validation
+// rows[i] in [0, n) and chains_per_row[r] >= 1; sets bit 1 / bit 2 of *bad.
+__global__ void __launch_bounds__(256) k_validate(const int32_t *rows, int64_t n_rows, const int32_t *cpr,
+                                                  int64_t n, uint32_t *bad) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n_rows || i < n; i += stride) {
+        if (rows && i < n_rows && (rows[i] < 0 || (int64_t)rows[i] >= n)) atomicOr(bad, 1u);
+        if (cpr && i < n && cpr[i] < 1) atomicOr(bad, 2u);
+    }
+}
+
+hipError_t validate_rows(const int32_t *rows, int64_t n_rows, const int32_t *cpr, int64_t n, uint32_t *bad,
+                         hipStream_t s) {
+    const int64_t m = n_rows > n ? n_rows : n;
+    int64_t blocks = (m + 255) / 256;
+    if (blocks > 4096) blocks = 4096;
+    if (blocks < 1) blocks = 1;
+    k_validate<<<(unsigned)blocks, 256, 0, s>>>(rows, n_rows, cpr, n, bad);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ SpMV
+// y = M x, float64. A group of G lanes per row (G = 8: the rows of M hold tens
+// to hundreds of entries), strided partial sums then a butterfly reduction.
+template <int G>
+__global__ void __launch_bounds__(256) k_spmv(int64_t n, const int64_t *rp, const int32_t *ci, const double *v,
+                                              const double *x, double *y) {
+    const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t row = gid / G;
+    const int sub = (int)(gid % G);
+    double acc = 0.0;
+    if (row < n) {
+        const int64_t b = rp[row], e = rp[row + 1];
+        for (int64_t k = b + sub; k < e; k += G) acc += v[k] * x[ci[k]];
+    }
+#pragma unroll
+    for (int off = G / 2; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
+    if (row < n && sub == 0) y[row] = acc;
+}
+
+hipError_t spmv(int64_t n, const int64_t *rp, const int32_t *ci, const double *v, const double *x, double *y,
+                hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    constexpr int G = 8;
+    const int64_t threads = n * G;
+    const int64_t blocks = (threads + 255) / 256;
+    k_spmv<G><<<(unsigned)blocks, 256, 0, s>>>(n, rp, ci, v, x, y);
+    return hipGetLastError();
+}
+
+}  // namespace mcmi

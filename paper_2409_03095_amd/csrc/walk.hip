@@ -1,0 +1,365 @@
+// Monte Carlo walks, per-row accumulation and finalize (gfx950).
+//
+// Section III-A, eq. (2): row r of (I - C)^-1 is estimated by the mean over N_r
+// chains started at r of sum_j W_j e_{s_j}, with W_0 = 1 and
+// W_j = W_{j-1} * c_{s_{j-1} s_j} / p_{s_{j-1} s_j} = W_{j-1} * sign * Shat.
+// Section IV-A, phase 4 scales column c by 1 / d_c, and the filter keeps the
+// diagonal and every entry with |N_rc| >= eps.
+//
+// Design (one wavefront owns one row at a time, persistent grid):
+//  * rows come from eight work queues, one per XCD (workgroups are dispatched
+//    round-robin over the XCDs, so blockIdx % 8 picks the XCD), each a contiguous
+//    slice of the rows so that neighbouring rows share their L2; a wave whose
+//    queue is empty steals from the next queue;
+//  * each lane runs one chain at a time and starts the row's next unstarted chain
+//    as soon as its chain stops, so short and long chains do not wait for each
+//    other;
+//  * a step reads the 16-byte record header of the current state, draws one
+//    Philox word, and descends the row's CDF in breadth-first (Eytzinger) order,
+//    whose first levels share the header's cache line;
+//  * contributions go to an open-addressing hash per wave in LDS (key = column,
+//    value = float64 sum, LDS float64 atomics); a full neighbourhood spills to a
+//    per-wave hash in HBM;
+//  * at the end of the row the wave filters the slots with a ballot, compacts the
+//    survivors in place, scales them by 1 / d_c, sorts them by column with a
+//    bitonic network in LDS and appends them to an output pool.
+#include "common.hpp"
+#include "walk_args.hpp"
+
+namespace mcmi {
+
+
+namespace {
+
+constexpr int32_t kEmpty = -1;
+constexpr int kMaxLdsProbe = 32;
+
+__device__ __forceinline__ uint32_t hash_key(int32_t key, int shift) {
+    return ((uint32_t)key * 2654435761u) >> shift;
+}
+
+__device__ __forceinline__ bool lds_add(int32_t *keys, double *vals, uint32_t mask, uint32_t h, int32_t key,
+                                        double w) {
+    for (int p = 0; p < kMaxLdsProbe; ++p) {
+        int32_t k = __atomic_load_n(&keys[h], __ATOMIC_RELAXED);
+        if (k == kEmpty) {
+            const int32_t prev = atomicCAS(&keys[h], kEmpty, key);
+            k = prev == kEmpty ? key : prev;
+        }
+        if (k == key) {
+            atomicAdd(&vals[h], w);
+            return true;
+        }
+        h = (h + 1) & mask;
+    }
+    return false;
+}
+
+// per-wave HBM hash; returns false when the table is full
+__device__ __forceinline__ bool spill_add(int32_t *keys, double *vals, int32_t *used, int *used_cnt, uint32_t mask,
+                                          int32_t key, double w) {
+    uint32_t h = ((uint32_t)key * 0x85EBCA6Bu) & mask;
+    for (uint32_t p = 0; p <= mask; ++p) {
+        int32_t k = __atomic_load_n(&keys[h], __ATOMIC_RELAXED);
+        if (k == kEmpty) {
+            const int32_t prev = atomicCAS(&keys[h], kEmpty, key);
+            if (prev == kEmpty) {
+                const int u = atomicAdd(used_cnt, 1);
+                used[u] = (int32_t)h;
+                k = key;
+            } else {
+                k = prev;
+            }
+        }
+        if (k == key) {
+            atomicAdd(&vals[h], w);
+            return true;
+        }
+        h = (h + 1) & mask;
+    }
+    return false;
+}
+
+// Wave-uniform task fetch from the eight per-XCD queues.
+__device__ __forceinline__ int64_t next_task(const WalkArgs &a, int &queue) {
+    const int lane = lane_id();
+    int64_t task = -1;
+    if (lane == 0) {
+        for (int tries = 0; tries < 8; ++tries) {
+            const int q = (queue + tries) & 7;
+            const int64_t lo = a.n_tasks * q / 8, hi = a.n_tasks * (q + 1) / 8;
+            if (hi > lo && __atomic_load_n(&a.queue_ctr[q], __ATOMIC_RELAXED) < (uint32_t)(hi - lo)) {
+                const uint32_t idx = atomicAdd(&a.queue_ctr[q], 1u);
+                if ((int64_t)idx < hi - lo) {
+                    task = lo + idx;
+                    queue = q;
+                    break;
+                }
+            }
+        }
+    }
+    task = __shfl(task, 0, 64);
+    queue = __shfl(queue, 0, 64);
+    return task;
+}
+
+template <bool kF32>
+__device__ void walk_row(const WalkArgs &a, int64_t task, int32_t *keys, double *vals, int *spill_cnt,
+                         int32_t *skeys, double *svals, int32_t *sused) {
+    const int lane = lane_id();
+    const uint32_t hmask = (uint32_t)a.hash_slots - 1u;
+    const uint32_t smask = (uint32_t)a.spill_slots - 1u;
+    const int32_t r = a.rows ? a.rows[task] : (int32_t)task;
+    const int32_t N = a.chains_per_row ? a.chains_per_row[r] : a.chains;
+    const uint32_t r_off = a.roff[r];
+
+    // j = 0: every chain contributes W_0 = 1 at (r, r); N ones sum exactly to N.
+    if (lane == 0) lds_add(keys, vals, hmask, hash_key(r, a.hash_shift), r, (double)N);
+    wave_sync();
+
+    int32_t c = lane;
+    bool active = c < N;
+    uint32_t off = r_off;
+    uint32_t j = 0;
+    double w64 = 1.0;
+    float w32 = 1.0f;
+    u32x4 blk = {0, 0, 0, 0};
+    unsigned long long trans = 0, spilled = 0;
+    bool spill_full = false;
+
+    while (__any(active)) {
+        if (active) {
+            const uint32_t *recp = a.rec + (size_t)off * 4u;
+            const uint4 h = *(const uint4 *)recp;  // row, m, W, Shat32
+            double s64 = 0.0;
+            if (!kF32) s64 = *(const double *)(recp + 4);
+            if (j > 0) {
+                const int32_t key = (int32_t)h.x;
+                const double w = kF32 ? (double)w32 : w64;
+                if (!lds_add(keys, vals, hmask, hash_key(key, a.hash_shift), key, w)) {
+                    ++spilled;
+                    if (!spill_add(skeys, svals, sused, spill_cnt, smask, key, w)) spill_full = true;
+                }
+            }
+            bool stop = (h.y == 0u) || (j >= (uint32_t)a.lmax);
+            double wn64 = 0.0;
+            float wn32 = 0.0f;
+            if (kF32) {
+                wn32 = w32 * __uint_as_float(h.w);
+                stop = stop || (fabsf(wn32) < a.delta32);
+            } else {
+                wn64 = w64 * s64;
+                stop = stop || (fabs(wn64) < a.delta);
+            }
+            if (stop) {
+                trans += j;
+                c += 64;
+                if (c < N) {
+                    off = r_off;
+                    j = 0;
+                    w64 = 1.0;
+                    w32 = 1.0f;
+                } else {
+                    active = false;
+                }
+            } else {
+                // step j + 1 takes word j mod 4 of block j / 4: consume words in order
+                if ((j & 3u) == 0u) blk = philox4x32_10(j >> 2, (uint32_t)c, (uint32_t)r, a.tag, a.key0, a.key1);
+                const uint32_t u = blk.x;
+                blk.x = blk.y;
+                blk.y = blk.z;
+                blk.z = blk.w;
+                const uint32_t t = __umulhi(u, h.z);
+                const uint2 *nodes = (const uint2 *)(recp + kHdrWords);
+                const uint32_t m = h.y;
+                uint32_t e = 1, tgt = 0;
+                while (e <= m) {
+                    const uint2 nd = nodes[e - 1];
+                    const bool left = t < nd.x;
+                    tgt = left ? nd.y : tgt;
+                    e = 2u * e + (left ? 0u : 1u);
+                }
+                const bool neg = (tgt & kSignBit) != 0u;
+                if (kF32)
+                    w32 = neg ? -wn32 : wn32;
+                else
+                    w64 = neg ? -wn64 : wn64;
+                off = tgt & ~kSignBit;
+                ++j;
+            }
+        }
+    }
+    wave_sync();
+
+    // ---------------------------------------------------------- finalize
+    const double nd = (double)N;
+    int K = 0;
+    for (int base = 0; base < a.hash_slots; base += 64) {
+        const int s = base + lane;
+        const int32_t key = keys[s];
+        const double acc = vals[s];
+        bool keep = false;
+        double mval = 0.0;
+        if (key != kEmpty) {
+            const double nhat = acc / nd;
+            mval = nhat / a.diag[key];
+            const double test = a.filter_m ? fabs(mval) : fabs(nhat);
+            keep = key == r || (nhat != 0.0 && test >= a.eps);
+        }
+        const uint64_t km = ballot(keep);
+        wave_sync();
+        if (keep) {
+            const int pos = K + mask_rank(km);
+            keys[pos] = key;
+            vals[pos] = mval;
+        }
+        K += __popcll(km);
+    }
+    wave_sync();
+    const int nsp = *spill_cnt;
+    bool stage_full = false;
+    for (int base = 0; base < nsp; base += 64) {
+        const int u = base + lane;
+        bool keep = false;
+        int32_t key = kEmpty;
+        double mval = 0.0;
+        if (u < nsp) {
+            const int32_t slot = sused[u];
+            key = skeys[slot];
+            const double nhat = svals[slot] / nd;
+            mval = nhat / a.diag[key];
+            const double test = a.filter_m ? fabs(mval) : fabs(nhat);
+            keep = key == r || (nhat != 0.0 && test >= a.eps);
+            skeys[slot] = kEmpty;
+            svals[slot] = 0.0;
+        }
+        const uint64_t km = ballot(keep);
+        if (keep) {
+            const int pos = K + mask_rank(km);
+            if (pos < a.hash_slots) {
+                keys[pos] = key;
+                vals[pos] = mval;
+            } else {
+                stage_full = true;
+            }
+        }
+        K += __popcll(km);
+    }
+    if (K > a.hash_slots) K = a.hash_slots;
+    wave_sync();
+
+    // bitonic sort of keys[0..P) by column, padding with INT32_MAX
+    int P = 1;
+    while (P < K) P <<= 1;
+    for (int s = K + lane; s < P; s += 64) keys[s] = INT32_MAX;
+    wave_sync();
+    for (int k = 2; k <= P; k <<= 1) {
+        for (int jj = k >> 1; jj > 0; jj >>= 1) {
+            for (int i = lane; i < P; i += 64) {
+                const int ixj = i ^ jj;
+                if (ixj > i) {
+                    const int32_t ka = keys[i], kb = keys[ixj];
+                    const bool up = (i & k) == 0;
+                    if ((ka > kb) == up) {
+                        const double va = vals[i], vb = vals[ixj];
+                        keys[i] = kb;
+                        keys[ixj] = ka;
+                        vals[i] = vb;
+                        vals[ixj] = va;
+                    }
+                }
+            }
+            wave_sync();
+        }
+    }
+
+    // append to the pool
+    unsigned long long pos0 = 0;
+    if (lane == 0) pos0 = atomicAdd(a.pool_used, (unsigned long long)K);
+    pos0 = __shfl(pos0, 0, 64);
+    const bool fits = (int64_t)(pos0 + (unsigned long long)K) <= a.pool_cap;
+    if (fits) {
+        for (int i = lane; i < K; i += 64) {
+            a.pool_col[pos0 + i] = keys[i];
+            a.pool_val[pos0 + i] = vals[i];
+        }
+    }
+    if (lane == 0) {
+        a.row_start[task] = (int64_t)pos0;
+        a.row_cnt[task] = (uint32_t)K;
+        uint32_t f = 0;
+        if (!fits) f |= kFlagPool;
+        if (f) atomicOr(a.flags, f);
+    }
+    const bool any_spill_full = __any(spill_full);
+    const bool any_stage_full = __any(stage_full);
+    trans = wave_sum(trans);
+    spilled = wave_sum(spilled);
+    if (lane == 0) {
+        atomicAdd(&a.stats[0], trans);
+        if (spilled) atomicAdd(&a.stats[1], spilled);
+        atomicAdd(&a.stats[2], (unsigned long long)N);
+        if (any_spill_full) atomicOr(a.flags, kFlagSpill);
+        if (any_stage_full) atomicOr(a.flags, kFlagStage);
+    }
+    // clear for the next row
+    wave_sync();
+    for (int s = lane; s < a.hash_slots; s += 64) {
+        keys[s] = kEmpty;
+        vals[s] = 0.0;
+    }
+    if (lane == 0) *spill_cnt = 0;
+    wave_sync();
+}
+
+template <bool kF32>
+__global__ void __launch_bounds__(256) k_walk(WalkArgs a) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int waves = blockDim.x >> 6;
+    const int w = threadIdx.x >> 6;
+    const int lane = lane_id();
+    const int H = a.hash_slots;
+    // per wave: vals[H] (f64), keys[H] (i32), spill counter
+    const size_t per_wave = (size_t)H * 12u + 16u;
+    unsigned char *mine = smem + (size_t)w * per_wave;
+    double *vals = (double *)mine;
+    int32_t *keys = (int32_t *)(mine + (size_t)H * 8u);
+    int *spill_cnt = (int *)(mine + (size_t)H * 12u);
+    for (int s = lane; s < H; s += 64) {
+        keys[s] = kEmpty;
+        vals[s] = 0.0;
+    }
+    if (lane == 0) *spill_cnt = 0;
+    wave_sync();
+    const int64_t gw = (int64_t)blockIdx.x * waves + w;
+    int32_t *skeys = a.spill_keys + gw * a.spill_slots;
+    double *svals = a.spill_vals + gw * a.spill_slots;
+    int32_t *sused = a.spill_used + gw * a.spill_slots;
+    int queue = (int)(blockIdx.x & 7u);
+    for (;;) {
+        const int64_t task = next_task(a, queue);
+        if (task < 0) break;
+        walk_row<kF32>(a, task, keys, vals, spill_cnt, skeys, svals, sused);
+    }
+}
+
+}  // namespace
+
+size_t walk_lds_bytes(int hash_slots, int waves) { return (size_t)waves * ((size_t)hash_slots * 12u + 16u); }
+
+hipError_t launch_walk(const WalkArgs &a, bool f32, int blocks, int waves, hipStream_t s) {
+    const size_t lds = walk_lds_bytes(a.hash_slots, waves);
+    if (f32)
+        k_walk<true><<<blocks, waves * 64, lds, s>>>(a);
+    else
+        k_walk<false><<<blocks, waves * 64, lds, s>>>(a);
+    return hipGetLastError();
+}
+
+hipError_t walk_occupancy(bool f32, int hash_slots, int waves, int *blocks_per_cu) {
+    const size_t lds = walk_lds_bytes(hash_slots, waves);
+    if (f32) return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k_walk<true>, waves * 64, lds);
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k_walk<false>, waves * 64, lds);
+}
+
+}  // namespace mcmi

@@ -1,0 +1,38 @@
+// Kernel arguments of the walk kernels (internal).
+#pragma once
+#include "common.hpp"
+
+namespace mcmi {
+
+struct WalkArgs {
+    const uint32_t *rec;
+    const uint32_t *roff;
+    const double *diag;
+    const int32_t *rows;           // nullable: task t is row t
+    int64_t n_tasks;
+    const int32_t *chains_per_row; // nullable
+    int32_t chains;
+    uint32_t key0, key1, tag;
+    double delta;
+    float delta32;
+    double eps;
+    int32_t lmax;
+    int32_t filter_m;
+    int32_t hash_slots;            // power of two
+    int32_t hash_shift;            // 32 - log2(hash_slots)
+    uint32_t *queue_ctr;           // 8 counters
+    int64_t *row_start;
+    uint32_t *row_cnt;
+    int32_t *pool_col;
+    double *pool_val;
+    int64_t pool_cap;
+    unsigned long long *pool_used;
+    int32_t *spill_keys;
+    double *spill_vals;
+    int32_t *spill_used;
+    int32_t spill_slots;           // power of two, per wave
+    unsigned long long *stats;     // [0] transitions, [1] spilled, [2] chains
+    uint32_t *flags;
+};
+
+}  // namespace mcmi

@@ -1,0 +1,228 @@
+"""Python binding of libmcmi.so (argument marshalling only).
+
+Every step of the Monte Carlo SPAI path runs in the HIP library; this module
+moves pointers, sizes and parameters across the C ABI declared in
+``include/mcmi.h``. PyTorch provides device memory and the current stream.
+Importing this module fails loudly when the library has not been built: there
+is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import dataclasses
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libmcmi.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"libmcmi.so not found at {LIB_PATH}: build it with "
+                      "`python -c 'import __graft_entry__ as g; g.build()'` (hipcc, gfx950)")
+
+_lib = ctypes.CDLL(LIB_PATH)
+
+MCMI_OK = 0
+STATUS = {0: "ok", -1: "bad argument", -2: "bad CSR", -3: "zero or missing diagonal",
+          -4: "not contractive", -5: "capacity", -6: "HIP error", -7: "out of memory"}
+WALK_F64, WALK_F32 = 64, 32
+FILTER_N, FILTER_M = 0, 1
+
+
+class McmiError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"mcmi status {status} ({STATUS.get(status, '?')}): {msg}")
+        self.status = status
+
+
+class CsrIn(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int64), ("nnz", ctypes.c_int64), ("row_ptr_dev", ctypes.c_void_p),
+                ("col_dev", ctypes.c_void_p), ("val_dev", ctypes.c_void_p)]
+
+
+class CsrOut(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int64), ("nnz", ctypes.c_int64), ("row_ptr_dev", ctypes.c_void_p),
+                ("col_dev", ctypes.c_void_p), ("val_dev", ctypes.c_void_p)]
+
+
+class Params(ctypes.Structure):
+    _fields_ = [("seed", ctypes.c_uint64), ("chains", ctypes.c_int32), ("walk_prec", ctypes.c_int32),
+                ("delta", ctypes.c_double), ("eps", ctypes.c_double), ("max_len", ctypes.c_int32),
+                ("stream_tag", ctypes.c_uint32), ("filter", ctypes.c_int32), ("lanes_per_row", ctypes.c_int32),
+                ("hash_slots", ctypes.c_int32), ("reserved", ctypes.c_int32 * 3)]
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [("transitions", ctypes.c_uint64), ("chains", ctypes.c_uint64), ("spilled", ctypes.c_uint64),
+                ("retries", ctypes.c_uint64), ("nnz", ctypes.c_int64), ("lmax", ctypes.c_int32),
+                ("norm_inf", ctypes.c_float), ("ms_walk", ctypes.c_double), ("ms_assemble", ctypes.c_double),
+                ("ms_total", ctypes.c_double)]
+
+
+_P = ctypes.POINTER
+_v = ctypes.c_void_p
+_sig = {
+    "mcmi_build_cdf": [_P(CsrIn), _P(_v), _v],
+    "mcmi_cdf_info": [_v, _P(ctypes.c_int64), _P(ctypes.c_int64), _P(ctypes.c_double), _P(ctypes.c_uint64)],
+    "mcmi_cdf_download": [_v, _v, _v, _v, _v],
+    "mcmi_spai": [_v, _P(Params), _v, _v, ctypes.c_int64, _P(CsrOut), _P(Stats), _v],
+    "mcmi_apply": [_P(CsrOut), ctypes.c_int64, _v, _v, _v],
+    "mcmi_csr_copy": [_P(CsrOut), _v, _v, _v, _v],
+}
+for _name, _args in _sig.items():
+    getattr(_lib, _name).argtypes = _args
+    getattr(_lib, _name).restype = ctypes.c_int
+_lib.mcmi_cdf_free.argtypes = [_v]
+_lib.mcmi_cdf_free.restype = None
+_lib.mcmi_csr_free.argtypes = [_P(CsrOut)]
+_lib.mcmi_csr_free.restype = None
+_lib.mcmi_last_error.restype = ctypes.c_char_p
+_lib.mcmi_version.restype = ctypes.c_char_p
+
+EXPORTED = ["mcmi_build_cdf", "mcmi_cdf_info", "mcmi_cdf_download", "mcmi_spai", "mcmi_apply",
+            "mcmi_csr_copy", "mcmi_cdf_free", "mcmi_csr_free", "mcmi_last_error", "mcmi_version"]
+
+
+def _check(st):
+    if st != MCMI_OK:
+        raise McmiError(st, _lib.mcmi_last_error().decode(errors="replace"))
+
+
+def _stream(stream):
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def version() -> str:
+    return _lib.mcmi_version().decode()
+
+
+@dataclasses.dataclass
+class DeviceCsr:
+    """A CSR matrix whose arrays live in torch device tensors."""
+    n: int
+    row_ptr: object
+    col: object
+    val: object
+
+    @property
+    def nnz(self):
+        return int(self.col.numel())
+
+    @staticmethod
+    def from_host(B, device="cuda"):
+        import torch
+        return DeviceCsr(int(B.n),
+                         torch.from_numpy(np.ascontiguousarray(B.row_ptr, dtype=np.int64)).to(device),
+                         torch.from_numpy(np.ascontiguousarray(B.col, dtype=np.int32)).to(device),
+                         torch.from_numpy(np.ascontiguousarray(B.val, dtype=np.float64)).to(device))
+
+    def _struct(self):
+        return CsrIn(self.n, self.nnz, _ptr(self.row_ptr), _ptr(self.col), _ptr(self.val))
+
+
+class Cdf:
+    """Sampling records of C = I - D^-1 B (mcmi_build_cdf)."""
+
+    def __init__(self, B: DeviceCsr, stream=None):
+        self._h = ctypes.c_void_p()
+        self._B = B
+        s = B._struct()
+        _check(_lib.mcmi_build_cdf(ctypes.byref(s), ctypes.byref(self._h), _stream(stream)))
+        n, nnz_c, nrm, units = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_double(), ctypes.c_uint64()
+        _check(_lib.mcmi_cdf_info(self._h, ctypes.byref(n), ctypes.byref(nnz_c), ctypes.byref(nrm),
+                                  ctypes.byref(units)))
+        self.n, self.nnz_c, self.norm_inf, self.rec_units = n.value, nnz_c.value, nrm.value, units.value
+
+    def download(self, stream=None):
+        rec = np.zeros(self.rec_units * 4, dtype=np.uint32)
+        roff = np.zeros(self.n, dtype=np.uint32)
+        diag = np.zeros(self.n, dtype=np.float64)
+        _check(_lib.mcmi_cdf_download(self._h, rec.ctypes.data_as(_v), roff.ctypes.data_as(_v),
+                                      diag.ctypes.data_as(_v), _stream(stream)))
+        return rec, roff, diag
+
+    def free(self):
+        if self._h:
+            _lib.mcmi_cdf_free(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+
+class SpaiResult:
+    """Library-owned CSR M plus the run statistics."""
+
+    def __init__(self, out: CsrOut, stats: Stats, n_cols: int):
+        self._out = out
+        self.stats = stats
+        self.n_cols = n_cols
+
+    @property
+    def n(self):
+        return self._out.n
+
+    @property
+    def nnz(self):
+        return self._out.nnz
+
+    def to_torch(self, stream=None):
+        import torch
+        rp = torch.empty(self.n + 1, dtype=torch.int64, device="cuda")
+        col = torch.empty(max(self.nnz, 1), dtype=torch.int32, device="cuda")
+        val = torch.empty(max(self.nnz, 1), dtype=torch.float64, device="cuda")
+        _check(_lib.mcmi_csr_copy(ctypes.byref(self._out), _ptr(rp), _ptr(col), _ptr(val), _stream(stream)))
+        return rp, col[:self.nnz], val[:self.nnz]
+
+    def to_numpy(self, stream=None):
+        import torch
+        rp, col, val = self.to_torch(stream)
+        torch.cuda.current_stream().synchronize()
+        return rp.cpu().numpy(), col.cpu().numpy(), val.cpu().numpy()
+
+    def apply(self, x, y=None, stream=None):
+        """y = M x (mcmi_apply); x and y are float64 device tensors."""
+        import torch
+        if y is None:
+            y = torch.empty(self.n, dtype=torch.float64, device=x.device)
+        _check(_lib.mcmi_apply(ctypes.byref(self._out), ctypes.c_int64(self.n_cols), _ptr(x), _ptr(y),
+                               _stream(stream)))
+        return y
+
+    def free(self):
+        if self._out.row_ptr_dev:
+            _lib.mcmi_csr_free(ctypes.byref(self._out))
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+
+def params(seed=0, chains=16, delta=1e-3, eps=1e-3, walk_prec=WALK_F64, max_len=0, tag=0, filter=FILTER_N,
+           lanes_per_row=0, hash_slots=0) -> Params:
+    return Params(int(seed) & 0xFFFFFFFFFFFFFFFF, int(chains), int(walk_prec), float(delta), float(eps),
+                  int(max_len), int(tag) & 0xFFFFFFFF, int(filter), int(lanes_per_row), int(hash_slots),
+                  (ctypes.c_int32 * 3)(0, 0, 0))
+
+
+def spai(cdf: Cdf, p: Params, chains_per_row=None, rows=None, stream=None) -> SpaiResult:
+    """mcmi_spai: chains_per_row / rows are int32 device tensors or None."""
+    out = CsrOut()
+    st = Stats()
+    n_rows = int(rows.numel()) if rows is not None else 0
+    _check(_lib.mcmi_spai(cdf._h, ctypes.byref(p), _ptr(chains_per_row), _ptr(rows), ctypes.c_int64(n_rows),
+                          ctypes.byref(out), ctypes.byref(st), _stream(stream)))
+    return SpaiResult(out, st, cdf.n)

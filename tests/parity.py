@@ -1,0 +1,70 @@
+"""Helpers for comparing the HIP library with the oracle (test code only)."""
+import numpy as np
+
+U64 = 2.0 ** -53
+
+
+def decode_records(rec, roff, n):
+    """Decode the library's packed records into per-row (row, m, W, S32, S64,
+    cum[], col[], neg[]) in column order (in-order walk of the breadth-first tree)."""
+    inv = {int(o): i for i, o in enumerate(roff)}
+    out = []
+    for i in range(n):
+        base = int(roff[i]) * 4
+        row, m, W = int(rec[base]), int(rec[base + 1]), int(rec[base + 2])
+        s32 = rec[base + 3:base + 4].view(np.float32)[0]
+        s64 = rec[base + 4:base + 6].view(np.float64)[0]
+        nodes = rec[base + 6:base + 6 + 2 * m].reshape(m, 2) if m else np.zeros((0, 2), np.uint32)
+        order = []
+
+        def inorder(e):
+            stack, cur = [], e
+            while stack or cur <= m:
+                while cur <= m:
+                    stack.append(cur)
+                    cur = 2 * cur
+                cur = stack.pop()
+                order.append(cur)
+                cur = 2 * cur + 1
+
+        if m:
+            inorder(1)
+        cum = np.array([int(nodes[e - 1, 0]) for e in order], dtype=np.int64)
+        tgt = [int(nodes[e - 1, 1]) for e in order]
+        col = np.array([inv[t & 0x7FFFFFFF] for t in tgt], dtype=np.int64)
+        neg = np.array([(t >> 31) & 1 for t in tgt], dtype=bool)
+        out.append((row, m, W, s32, s64, cum, col, neg))
+    return out
+
+
+def compare_spai(gpu, orc, diag, chains, rel=1e-12, rows=None, check_pattern=True):
+    """Pattern must be identical; each value within rel * |oracle| or the FP64
+    summation-order bound 4 (k + 2) u sum|W| / (N |d_c|) (the two sides add the
+    same terms in different orders)."""
+    rp, col, val = gpu
+    assert rp.size == orc["row_ptr"].size
+    if check_pattern:
+        assert np.array_equal(rp, orc["row_ptr"]), "row lengths differ"
+        assert np.array_equal(col, orc["col"]), "columns differ"
+    nrows = rp.size - 1
+    N = np.broadcast_to(np.asarray(chains, dtype=np.float64), (diag.size,))
+    row_of_entry = np.repeat(np.arange(nrows), np.diff(orc["row_ptr"]))
+    grow = row_of_entry if rows is None else np.asarray(rows)[row_of_entry]
+    bound = 4.0 * (orc["cnt"] + 2.0) * U64 * orc["abssum"] / N[grow] / np.abs(diag[orc["col"]])
+    tol = np.maximum(rel * np.abs(orc["val"]), bound)
+    err = np.abs(val - orc["val"])
+    bad = np.nonzero(err > tol)[0]
+    assert bad.size == 0, f"{bad.size} values out of tolerance, worst {err[bad].max()} vs {tol[bad].min()}"
+    return float((err / np.maximum(np.abs(orc["val"]), 1e-300)).max()) if err.size else 0.0
+
+
+def common_entries(rp_a, col_a, val_a, rp_b, col_b, val_b):
+    """Values of two CSR matrices on their common pattern."""
+    va, vb = [], []
+    for r in range(rp_a.size - 1):
+        ca = col_a[rp_a[r]:rp_a[r + 1]]
+        cb = col_b[rp_b[r]:rp_b[r + 1]]
+        _, ia, ib = np.intersect1d(ca, cb, assume_unique=True, return_indices=True)
+        va.append(val_a[rp_a[r]:rp_a[r + 1]][ia])
+        vb.append(val_b[rp_b[r]:rp_b[r + 1]][ib])
+    return np.concatenate(va), np.concatenate(vb)
