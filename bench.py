@@ -1,0 +1,160 @@
+"""Benchmark: Monte Carlo SPAI throughput (transitions/s) on one MI355X.
+
+Workload (default): random nonsymmetric B, n = 262144, 5..30 off-diagonals per
+row at uniform columns, log-normal magnitudes with random signs, per-row
+diagonal so that every row of C = I - D^-1 B has |C| row sum 0.7; 512 chains
+per row, FP32 walk weights with FP64 sums, delta = 1e-4, eps = 1e-3, Philox
+seed 0. Every chain makes exactly 25 transitions, so one step is exactly
+262144 * 512 * 25 = 3,355,443,200 transitions.
+
+One step = the whole hot path over the matrix, through the C ABI:
+mcmi_build_cdf (records) + mcmi_spai (walks, accumulation, filter, scaling,
+CSR assembly) + mcmi_apply (one y = M x). Inputs are resident in HBM before the
+timed region starts.
+
+Prints one JSON line with, beside the throughput, the roofline of the walk
+kernel (algorithmic bytes per transition x transitions per launch / the walk
+kernel's event-timed duration, against 8 TB/s HBM) and the CPU oracle's rate on
+a bounded row sample.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "MC transitions/s; time to ‖I−MB‖_F≤0.3, learned vs uniform chains"
+HBM_PEAK_GBS = 8000.0
+# rocprofv3 FETCH_SIZE/WRITE_SIZE of the walk kernel, in bytes per launch, for
+# the default workload (None until measured for the current kernel)
+TRAFFIC_BYTES = None
+
+
+def algorithmic_bytes_per_transition(B, fp32: bool) -> float:
+    """Bytes one transition must read: the 16-byte record header of the state
+    (row, m, W, Shat32; +8 for Shat64 in FP64 mode) and one 8-byte {cum, target}
+    node per level of the breadth-first CDF tree, ceil(log2(m + 1)) levels. For
+    this workload the next state is a uniformly random column, so the mean is
+    taken over rows uniformly."""
+    m = np.diff(B.row_ptr) - 1
+    levels = np.ceil(np.log2(m + 1.0))
+    return float(np.mean((16.0 if fp32 else 24.0) + 8.0 * levels))
+
+
+def cpu_baseline(B, chains, delta, eps, fp32, budget_s=12.0):
+    """The oracle as it is, on the host cores, on a bounded sample of rows."""
+    import oracle as O
+    threads = O.default_threads()
+    o = O.Oracle(B)
+    rng = np.random.default_rng(123)
+    probe = rng.choice(B.n, 256, replace=False).astype(np.int32)
+    t0 = time.perf_counter()
+    r = o.spai(seed=0, chains=chains, delta=delta, eps=eps, fp32=fp32, rows=probe, threads=threads)
+    dt = time.perf_counter() - t0
+    rate = r["transitions"] / max(dt, 1e-9)
+    nrows = int(min(B.n, max(256, rate * budget_s / max(r["transitions"] / 256, 1))))
+    rows = rng.choice(B.n, nrows, replace=False).astype(np.int32)
+    t0 = time.perf_counter()
+    r = o.spai(seed=0, chains=chains, delta=delta, eps=eps, fp32=fp32, rows=rows, threads=threads)
+    dt = time.perf_counter() - t0
+    return {"value": r["transitions"] / dt, "unit": "transitions/s", "cores": threads, "kind": "oracle",
+            "sample": f"{nrows} uniformly sampled rows of the same matrix ({r['transitions']} transitions, "
+                      f"{dt:.1f} s, {threads} threads)"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--n", type=int, default=262144)
+    ap.add_argument("--chains", type=int, default=512)
+    ap.add_argument("--prec", type=int, default=32, choices=[32, 64])
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--hash-slots", type=int, default=0)
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU: the Monte Carlo rows shard across GPUs without communication "
+              "(see the design notes), but this build runs and reports a single MI355X only.", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    from paper_2409_03095_amd import inputs as I
+    from paper_2409_03095_amd import mcmi
+
+    delta, eps, seed = 1e-4, 1e-3, 0
+    B = I.cfg2(args.n)
+    dB = mcmi.DeviceCsr.from_host(B)
+    x = torch.ones(B.n, dtype=torch.float64, device="cuda")
+    y = torch.empty(B.n, dtype=torch.float64, device="cuda")
+    p = mcmi.params(seed=seed, chains=args.chains, delta=delta, eps=eps, walk_prec=args.prec,
+                    hash_slots=args.hash_slots)
+    torch.cuda.synchronize()
+
+    def step():
+        cdf = mcmi.Cdf(dB)
+        res = mcmi.spai(cdf, p)
+        res.apply(x, y)
+        return cdf, res
+
+    for _ in range(args.warmup):
+        cdf, res = step()
+        del cdf, res
+    torch.cuda.synchronize()
+    walk_ms, trans = [], []
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        cdf, res = step()
+        walk_ms.append(res.stats.ms_walk)
+        trans.append(res.stats.transitions)
+        retries = res.stats.retries
+        nnz = res.nnz
+        spilled = res.stats.spilled
+        del cdf, res
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    total_trans = float(sum(trans))
+    value = total_trans / elapsed
+
+    bpt = algorithmic_bytes_per_transition(B, args.prec == 32)
+    walk_s = float(np.mean(walk_ms)) / 1e3
+    achieved = bpt * trans[-1] / walk_s / 1e9
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": TRAFFIC_BYTES,
+                "kernel": "k_walk", "bytes_per_transition": round(bpt, 2),
+                "walk_ms": round(walk_s * 1e3, 3), "walk_transitions_per_s": trans[-1] / walk_s}
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "transitions/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": elapsed / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32" if args.prec == 32 else "f64",
+        "data": "synthetic",
+        "config": {"workload": f"random nonsymmetric n={B.n}, 5-30 off-diagonals/row, ||C||_inf=0.7, "
+                               f"{args.chains} chains/row, delta=1e-4, eps=1e-3, FP{args.prec} walks + FP64 sums",
+                   "n": B.n, "nnz_B": B.nnz, "chains_per_row": args.chains, "transitions_per_step": trans[-1],
+                   "nnz_M": nnz, "spilled_contributions": spilled, "retries": retries},
+        "roofline": roofline,
+    }
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(B, args.chains, delta, eps, args.prec == 32)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -92,9 +92,17 @@ typedef struct {
                              (one IEEE product per step); required when ||Chat||_inf >= 1 */
     uint32_t stream_tag;  /* fourth Philox counter word (distinguishes independent runs) */
     int32_t filter;       /* MCMI_FILTER_N: |N_rc| >= eps; MCMI_FILTER_M: |M_rc| >= eps */
-    int32_t lanes_per_row;/* 0 = automatic; else 64, 128, 256 or 512 lanes share a row */
+    int32_t lanes_per_row;/* 0 = automatic; 64 = one wavefront per row; 256, 512 or 1024 =
+                             one workgroup of that many lanes per row */
     int32_t hash_slots;   /* 0 = automatic; else LDS hash slots per row (power of two) */
-    int32_t reserved[3];  /* must be zero */
+    int32_t sketch_slots; /* 0 = automatic; else count-sketch buckets per row (power of two) */
+    int32_t reserved;     /* must be zero */
+    double heavy_weight;  /* workgroup-per-row kernel only. 0 = automatic; < 0 = track every
+                             contribution in the row hash; > 0 (<= 1): contributions with
+                             |W| >= heavy_weight are tracked, lighter ones are added to
+                             tracked columns or to a count sketch that certifies that no
+                             untracked column reaches the filter threshold (rows that fail
+                             the certificate are replayed exactly). Needs ||Chat||_inf < 1. */
 } mcmi_params;
 
 typedef struct {
@@ -102,12 +110,18 @@ typedef struct {
     uint64_t chains;          /* chains run */
     uint64_t spilled;         /* contributions that went to the HBM spill table */
     uint64_t retries;         /* reruns after a table or pool overflow */
+    uint64_t refined;         /* rows whose sketch certificate failed and were replayed */
     int64_t nnz;              /* entries of M */
     int32_t lmax;             /* L_max used */
     float norm_inf;           /* ||Chat||_inf */
     double ms_walk;           /* device time of the walk + finalize kernel(s) */
     double ms_assemble;       /* device time of the CSR assembly */
     double ms_total;          /* device time of the whole call */
+    int32_t lanes_per_row;    /* kernel shape used */
+    int32_t hash_slots;
+    int32_t sketch_slots;
+    int32_t pad;
+    double heavy_weight;      /* tau used (0: every contribution tracked) */
 } mcmi_stats;
 
 /* Build the sampling records of C = I - D^-1 B (Section IV, phase 2 and the

@@ -14,6 +14,10 @@ namespace mcmi {
 size_t walk_lds_bytes(int hash_slots, int waves);
 hipError_t launch_walk(const WalkArgs &a, bool f32, int blocks, int waves, hipStream_t s);
 hipError_t walk_occupancy(bool f32, int hash_slots, int waves, int *blocks_per_cu);
+size_t walk_block_lds_bytes(int hash_slots, int sketch_slots);
+bool walk_block_supported(int lanes, int hash_slots);
+hipError_t launch_walk_block(const WalkArgs &a, bool f32, int lanes, int blocks, hipStream_t s);
+hipError_t walk_block_occupancy(bool f32, int lanes, int hash_slots, int sketch_slots, int *bpc);
 hipError_t gather_rows(int64_t n_rows, const int64_t *row_start, const uint32_t *row_cnt, const int64_t *row_ptr,
                        const int32_t *pool_col, const double *pool_val, int32_t *col, double *val, hipStream_t s);
 hipError_t validate_rows(const int32_t *rows, int64_t n_rows, const int32_t *cpr, int64_t n, uint32_t *bad,
@@ -100,9 +104,16 @@ extern "C" mcmi_status mcmi_spai(const mcmi_cdf *cdf, const mcmi_params *p, cons
         return fail(MCMI_ERR_ARG, "mcmi_spai: walk_prec must be 64 or 32");
     if (!(p->eps >= 0.0) || !(p->delta >= 0.0)) return fail(MCMI_ERR_ARG, "mcmi_spai: eps and delta must be >= 0");
     if (p->filter != MCMI_FILTER_N && p->filter != MCMI_FILTER_M) return fail(MCMI_ERR_ARG, "mcmi_spai: bad filter");
-    if (p->reserved[0] || p->reserved[1] || p->reserved[2]) return fail(MCMI_ERR_ARG, "mcmi_spai: reserved != 0");
+    if (p->reserved) return fail(MCMI_ERR_ARG, "mcmi_spai: reserved != 0");
     if (p->hash_slots && (p->hash_slots < 64 || p->hash_slots > 8192 || (p->hash_slots & (p->hash_slots - 1))))
         return fail(MCMI_ERR_ARG, "mcmi_spai: hash_slots must be a power of two in [64, 8192]");
+    if (p->sketch_slots && (p->sketch_slots < 64 || p->sketch_slots > 16384 ||
+                            (p->sketch_slots & (p->sketch_slots - 1))))
+        return fail(MCMI_ERR_ARG, "mcmi_spai: sketch_slots must be a power of two in [64, 16384]");
+    if (p->lanes_per_row && p->lanes_per_row != 64 && p->lanes_per_row != 256 && p->lanes_per_row != 512 &&
+        p->lanes_per_row != 1024)
+        return fail(MCMI_ERR_ARG, "mcmi_spai: lanes_per_row must be 0, 64, 256, 512 or 1024");
+    if (!(p->heavy_weight <= 1.0)) return fail(MCMI_ERR_ARG, "mcmi_spai: heavy_weight must be <= 1");
     const int64_t n_tasks = rows_dev ? n_rows : cdf->n;
     if (rows_dev && (n_rows < 1 || n_rows > cdf->n)) return fail(MCMI_ERR_ARG, "mcmi_spai: bad n_rows");
     const int lmax = derive_lmax(cdf->norm_inf, p->delta, p->max_len);
@@ -127,12 +138,48 @@ extern "C" mcmi_status mcmi_spai(const mcmi_cdf *cdf, const mcmi_params *p, cons
         }
     } evg{ev0, ev1, ev2};
 
-    // ---- sizing
-    int H = p->hash_slots ? p->hash_slots : 1024;
-    int waves = 4;
-    int spill_slots = 4096;
-    int64_t pool_cap = std::max<int64_t>(n_tasks * 64, 1 << 16);
+    // ---- kernel shape and heavy threshold
     const int cus = device_cus();
+    const double m_bar = cdf->n > 0 ? (double)cdf->nnz_c / (double)cdf->n : 0.0;
+    const int n_hint = p->chains >= 1 ? p->chains : 64;
+    int lanes = p->lanes_per_row;
+    if (lanes == 0) lanes = n_hint >= 384 ? 512 : (n_hint >= 192 ? 256 : 64);
+    const bool block_kernel = lanes > 64;
+    int H = p->hash_slots ? p->hash_slots : (block_kernel ? 4096 : 1024);
+    if (block_kernel && !walk_block_supported(lanes, H))
+        return fail(MCMI_ERR_ARG, "mcmi_spai: unsupported (lanes_per_row, hash_slots) for the workgroup kernel");
+    int sketch = 0;
+    double tau = 0.0;
+    if (block_kernel && cdf->norm_inf < 1.0 && p->heavy_weight >= 0.0) {
+        if (p->heavy_weight > 0.0) {
+            tau = p->heavy_weight;
+        } else {
+            // distinct columns reached by step j are at most min(N, m^j, n); track every
+            // contribution when all steps fit in half the table, else the first J steps
+            const double S = cdf->norm_inf;
+            const int steps = S > 0.0 ? std::min(lmax, (int)std::ceil(std::log(p->delta > 0 ? p->delta : 1e-300) /
+                                                                        std::log(S))) : 0;
+            double reach = 1.0, total = 1.0, fit = 1.0;
+            int J = 0;
+            bool fits = true;
+            for (int jj = 1; jj <= steps; ++jj) {
+                reach = std::min({reach * std::max(m_bar, 1.0), (double)n_hint, (double)cdf->n});
+                total += reach;
+                if (fits && total <= 0.55 * H) {
+                    fit = total;
+                    J = jj;
+                } else {
+                    fits = false;
+                }
+            }
+            if (std::min(total, (double)cdf->n) > 0.5 * H) tau = std::pow(S, std::max(J, 1)) * (1.0 - 1.0 / 1048576.0);
+            (void)fit;
+        }
+        if (tau > 0.0) sketch = p->sketch_slots ? p->sketch_slots : 4096;
+    }
+    int waves = 4;
+    int spill_slots = block_kernel ? 16384 : 4096;
+    int64_t pool_cap = std::max<int64_t>(n_tasks * 64, 1 << 16);
     uint64_t retries = 0;
 
     DevBuf row_start, row_cnt, pool_col, pool_val, sk, sv, su, ctrl, row_ptr, scan_tmp;
@@ -164,18 +211,26 @@ extern "C" mcmi_status mcmi_spai(const mcmi_cdf *cdf, const mcmi_params *p, cons
     MCMI_HIP(hipEventRecord(ev0, s));
     for (;;) {
         int bpc = 0;
-        MCMI_HIP(walk_occupancy(f32, H, waves, &bpc));
-        if (bpc < 1) {
-            if (waves > 1) {
-                waves >>= 1;
-                continue;
+        int64_t blocks = 0, regions = 0;
+        if (block_kernel) {
+            MCMI_HIP(walk_block_occupancy(f32, lanes, H, sketch, &bpc));
+            if (bpc < 1) return fail(MCMI_ERR_CAPACITY, "mcmi_spai: workgroup kernel does not fit in LDS");
+            blocks = std::min<int64_t>((int64_t)bpc * cus, n_tasks);
+            regions = blocks;
+        } else {
+            MCMI_HIP(walk_occupancy(f32, H, waves, &bpc));
+            if (bpc < 1) {
+                if (waves > 1) {
+                    waves >>= 1;
+                    continue;
+                }
+                return fail(MCMI_ERR_CAPACITY, "mcmi_spai: hash table does not fit in LDS");
             }
-            return fail(MCMI_ERR_CAPACITY, "mcmi_spai: hash table does not fit in LDS");
+            blocks = (int64_t)bpc * cus;
+            if (blocks * waves > n_tasks) blocks = std::max<int64_t>(1, (n_tasks + waves - 1) / waves);
+            regions = blocks * waves;
         }
-        int64_t blocks = (int64_t)bpc * cus;
-        const int64_t need_waves = (n_tasks + 0);
-        if (blocks * waves > need_waves) blocks = std::max<int64_t>(1, (need_waves + waves - 1) / waves);
-        const int64_t total_waves = blocks * waves;
+        const int64_t total_waves = regions;
         MCMI_HIP(pool_col.alloc((size_t)pool_cap * sizeof(int32_t), s));
         MCMI_HIP(pool_val.alloc((size_t)pool_cap * sizeof(double), s));
         MCMI_HIP(sk.alloc((size_t)total_waves * spill_slots * sizeof(int32_t), s));
@@ -217,8 +272,15 @@ extern "C" mcmi_status mcmi_spai(const mcmi_cdf *cdf, const mcmi_params *p, cons
         a.spill_slots = spill_slots;
         a.stats = stats;
         a.flags = flags;
+        a.tau = tau;
+        a.tau32 = (float)tau;
+        a.sketch_slots = sketch;
+        a.sketch_shift = sketch ? 32 - __builtin_ctz((unsigned)sketch) : 0;
         MCMI_HIP(hipEventRecord(ev1, s));
-        MCMI_HIP(launch_walk(a, f32, (int)blocks, waves, s));
+        if (block_kernel)
+            MCMI_HIP(launch_walk_block(a, f32, lanes, (int)blocks, s));
+        else
+            MCMI_HIP(launch_walk(a, f32, (int)blocks, waves, s));
         MCMI_HIP(hipEventRecord(ev2, s));
         MCMI_HIP(scan_exclusive_u32_to_i64(row_cnt.as<uint32_t>(), row_ptr.as<int64_t>(), n_tasks,
                                            row_ptr.as<int64_t>() + n_tasks, scan_tmp.p, s));
@@ -235,8 +297,14 @@ extern "C" mcmi_status mcmi_spai(const mcmi_cdf *cdf, const mcmi_params *p, cons
         if (hflags & kFlagPool) pool_cap = (int64_t)hused + 1024;
         if (hflags & kFlagSpill) spill_slots *= 4;
         if (hflags & kFlagStage) {
-            if (H >= 8192) return fail(MCMI_ERR_CAPACITY, "mcmi_spai: more survivors per row than 8192 slots");
-            H *= 2;
+            if (block_kernel) {
+                if (!walk_block_supported(lanes, H * 2))
+                    return fail(MCMI_ERR_CAPACITY, "mcmi_spai: more survivors per row than the workgroup table holds");
+                H *= 2;
+            } else {
+                if (H >= 8192) return fail(MCMI_ERR_CAPACITY, "mcmi_spai: more survivors per row than 8192 slots");
+                H *= 2;
+            }
         }
     }
 
@@ -282,6 +350,11 @@ extern "C" mcmi_status mcmi_spai(const mcmi_cdf *cdf, const mcmi_params *p, cons
         st->spilled = hstats[1];
         st->chains = hstats[2];
         st->retries = retries;
+        st->refined = hstats[3];
+        st->lanes_per_row = lanes;
+        st->hash_slots = H;
+        st->sketch_slots = sketch;
+        st->heavy_weight = tau;
         st->nnz = nnz;
         st->lmax = lmax;
         st->norm_inf = (float)cdf->norm_inf;

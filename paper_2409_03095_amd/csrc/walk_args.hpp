@@ -31,8 +31,14 @@ struct WalkArgs {
     double *spill_vals;
     int32_t *spill_used;
     int32_t spill_slots;           // power of two, per wave
-    unsigned long long *stats;     // [0] transitions, [1] spilled, [2] chains
+    unsigned long long *stats;     // [0] transitions, [1] spilled, [2] chains, [3] rows refined
     uint32_t *flags;
+    // workgroup-per-row kernel: contributions with |W| >= tau are tracked in the
+    // LDS hash; lighter ones only update tracked columns or the count sketch
+    double tau;                    // 0: track every contribution
+    float tau32;
+    int32_t sketch_slots;          // power of two (0 when tau == 0)
+    int32_t sketch_shift;          // 32 - log2(sketch_slots)
 };
 
 }  // namespace mcmi

@@ -1,0 +1,539 @@
+// Workgroup-per-row Monte Carlo walks with heavy/light accumulation (gfx950).
+//
+// Same estimator as the wavefront-per-row kernel (Section III-A, eq. (2);
+// Section IV-A phase 4 scaling; the eps filter), for rows whose chains touch
+// more distinct columns than an LDS hash can hold (random sparsity: with m
+// entries per row, a row's chains reach ~m^j columns at step j).
+//
+// A contribution is heavy when |W| >= tau, light otherwise. With ||Chat||_inf < 1
+// weights never grow along a chain, so each chain's heavy contributions form a
+// prefix. The row is processed in phases, each over all N_r chains:
+//   H  heavy contributions are accumulated in the LDS hash (spilling to HBM);
+//      a chain pauses at its first light contribution;
+//   L  light contributions are added to the column's slot when the column is
+//      tracked; otherwise |W| is added to a count sketch bucket chosen by hashing
+//      the column. An untracked column's |sum| is at most its bucket total, so
+//      when every bucket stays below eps * N_r (with a 1/16 margin that covers
+//      binary32 bucket sums) no untracked column can pass the filter, and every
+//      tracked column has its complete sum;
+//   R  only if some bucket fails that bound: replay every chain from its start
+//      (counter-based random numbers make the replay exact) and track the light
+//      contributions whose bucket failed, as new columns.
+// The kept set and the values are then those of full accumulation.
+//
+// With N_r <= lanes each lane keeps its chain's state in registers across H and
+// L; otherwise phase L replays chains from their start, skipping the heavy prefix.
+#include "common.hpp"
+#include "walk_args.hpp"
+#include "walk_common.hpp"
+
+namespace mcmi {
+
+namespace {
+
+using namespace walkdev;
+
+constexpr uint32_t kRBit = 0x80000000u;  // marks columns first tracked in phase R
+
+enum Mode { kAll = 0, kHeavy = 1, kLight = 2, kRefine = 3 };
+
+struct Chain {
+    int32_t c;
+    uint32_t off, j;
+    double w64;
+    float w32;
+    u32x4 blk;
+    bool active;
+};
+
+struct RowCtx {
+    int32_t r, N;
+    uint32_t r_off;
+    int32_t *keys;
+    double *vals;
+    float *sketch;
+    int *spill_cnt;
+    int32_t *skeys;
+    double *svals;
+    int32_t *sused;
+    bool row_spilled;  // phase H spilled at least one column
+    float hot_thr;     // bucket total that fails the certificate
+};
+
+__device__ __forceinline__ void chain_start(Chain &st, int32_t c, const RowCtx &rc) {
+    st.c = c;
+    st.off = rc.r_off;
+    st.j = 0;
+    st.w64 = 1.0;
+    st.w32 = 1.0f;
+    st.active = c < rc.N;
+}
+
+// light contribution: add to the tracked column, else to its sketch bucket
+__device__ __forceinline__ void light_add(const WalkArgs &a, const RowCtx &rc, int32_t key, double w,
+                                          unsigned long long &spilled) {
+    const uint32_t hmask = (uint32_t)a.hash_slots - 1u;
+    uint32_t h = hash_key(key, a.hash_shift);
+    bool full_run = true;
+    for (int p = 0; p < kMaxLdsProbe; ++p) {
+        const int32_t k = __atomic_load_n(&rc.keys[h], __ATOMIC_RELAXED);
+        if (k == key) {
+            atomicAdd(&rc.vals[h], w);
+            return;
+        }
+        if (k == kEmpty) {
+            full_run = false;
+            break;
+        }
+        h = (h + 1) & hmask;
+    }
+    if (full_run && rc.row_spilled) {
+        const uint32_t smask = (uint32_t)a.spill_slots - 1u;
+        uint32_t g = ((uint32_t)key * 0x85EBCA6Bu) & smask;
+        for (uint32_t p = 0; p <= smask; ++p) {
+            const int32_t k = __atomic_load_n(&rc.skeys[g], __ATOMIC_RELAXED);
+            if (k == key) {
+                atomicAdd(&rc.svals[g], w);
+                ++spilled;
+                return;
+            }
+            if (k == kEmpty) break;
+            g = (g + 1) & smask;
+        }
+    }
+    double mag = fabs(w);
+    if (a.filter_m) mag = mag / fabs(a.diag[key]);
+    atomicAdd(&rc.sketch[bucket_of(key, a.sketch_shift)], (float)mag);
+}
+
+// refine: track light contributions of columns whose bucket failed the bound
+__device__ __forceinline__ void refine_add(const WalkArgs &a, const RowCtx &rc, int32_t key, double w,
+                                           bool &spill_full, unsigned long long &spilled) {
+    if (rc.sketch[bucket_of(key, a.sketch_shift)] < rc.hot_thr) return;
+    const int32_t rkey = (int32_t)((uint32_t)key | kRBit);
+    const uint32_t hmask = (uint32_t)a.hash_slots - 1u;
+    uint32_t h = hash_key(key, a.hash_shift);
+    for (int p = 0; p < kMaxLdsProbe; ++p) {
+        int32_t k = __atomic_load_n(&rc.keys[h], __ATOMIC_RELAXED);
+        if (k == kEmpty) {
+            const int32_t prev = atomicCAS(&rc.keys[h], kEmpty, rkey);
+            k = prev == kEmpty ? rkey : prev;
+        }
+        if (k == key) return;  // tracked since phase H: already complete
+        if (k == rkey) {
+            atomicAdd(&rc.vals[h], w);
+            return;
+        }
+        h = (h + 1) & hmask;
+    }
+    // HBM table: a heavy column may live there; else track the light column there
+    const uint32_t smask = (uint32_t)a.spill_slots - 1u;
+    uint32_t g = ((uint32_t)key * 0x85EBCA6Bu) & smask;
+    ++spilled;
+    for (uint32_t p = 0; p <= smask; ++p) {
+        int32_t k = __atomic_load_n(&rc.skeys[g], __ATOMIC_RELAXED);
+        if (k == kEmpty) {
+            const int32_t prev = atomicCAS(&rc.skeys[g], kEmpty, rkey);
+            if (prev == kEmpty) {
+                const int u = atomicAdd(rc.spill_cnt, 1);
+                rc.sused[u] = (int32_t)g;
+                k = rkey;
+            } else {
+                k = prev;
+            }
+        }
+        if (k == key) return;
+        if (k == rkey) {
+            atomicAdd(&rc.svals[g], w);
+            return;
+        }
+        g = (g + 1) & smask;
+    }
+    spill_full = true;
+}
+
+// Run this lane's chains (c, c + stride, ...) in one phase. In kHeavy mode a
+// chain pauses (stays active, state kept) at its first light contribution.
+template <bool kF32, int kMode>
+__device__ void run_chains(const WalkArgs &a, const RowCtx &rc, Chain &st, int stride, bool count,
+                           unsigned long long &trans, unsigned long long &spilled, bool &spill_full,
+                           bool &paused) {
+    const uint32_t hmask = (uint32_t)a.hash_slots - 1u;
+    const uint32_t smask = (uint32_t)a.spill_slots - 1u;
+    paused = false;
+    while (st.active) {
+        const uint32_t *recp = a.rec + (size_t)st.off * 4u;
+        const uint4 h = *(const uint4 *)recp;
+        double s64 = 0.0;
+        if (!kF32) s64 = *(const double *)(recp + 4);
+        if (st.j > 0) {
+            const int32_t key = (int32_t)h.x;
+            const double w = kF32 ? (double)st.w32 : st.w64;
+            const bool heavy = kF32 ? (fabsf(st.w32) >= a.tau32) : (fabs(st.w64) >= a.tau);
+            if (kMode == kAll || (kMode == kHeavy && heavy)) {
+                if (!lds_add(rc.keys, rc.vals, hmask, hash_key(key, a.hash_shift), key, w)) {
+                    ++spilled;
+                    if (!spill_add(rc.skeys, rc.svals, rc.sused, rc.spill_cnt, smask, key, w)) spill_full = true;
+                }
+            } else if (kMode == kHeavy) {
+                paused = true;
+                break;
+            } else if (kMode == kLight) {
+                if (!heavy) light_add(a, rc, key, w, spilled);
+            } else {
+                if (!heavy) refine_add(a, rc, key, w, spill_full, spilled);
+            }
+        }
+        bool stop = (h.y == 0u) || (st.j >= (uint32_t)a.lmax);
+        double wn64 = 0.0;
+        float wn32 = 0.0f;
+        if (kF32) {
+            wn32 = st.w32 * __uint_as_float(h.w);
+            stop = stop || (fabsf(wn32) < a.delta32);
+        } else {
+            wn64 = st.w64 * s64;
+            stop = stop || (fabs(wn64) < a.delta);
+        }
+        if (stop) {
+            if (count) trans += st.j;
+            chain_start(st, st.c + stride, rc);
+        } else {
+            if ((st.j & 3u) == 0u)
+                st.blk = philox4x32_10(st.j >> 2, (uint32_t)st.c, (uint32_t)rc.r, a.tag, a.key0, a.key1);
+            const uint32_t u = st.blk.x;
+            st.blk.x = st.blk.y;
+            st.blk.y = st.blk.z;
+            st.blk.z = st.blk.w;
+            const uint32_t t = __umulhi(u, h.z);
+            const uint2 *nodes = (const uint2 *)(recp + kHdrWords);
+            const uint32_t m = h.y;
+            uint32_t e = 1, tgt = 0;
+            while (e <= m) {
+                const uint2 nd = nodes[e - 1];
+                const bool left = t < nd.x;
+                tgt = left ? nd.y : tgt;
+                e = 2u * e + (left ? 0u : 1u);
+            }
+            const bool neg = (tgt & kSignBit) != 0u;
+            if (kF32)
+                st.w32 = neg ? -wn32 : wn32;
+            else
+                st.w64 = neg ? -wn64 : wn64;
+            st.off = tgt & ~kSignBit;
+            ++st.j;
+        }
+    }
+}
+
+template <int kLPR>
+__device__ __forceinline__ float block_max(float v, float *red) {
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    v = wave_max(v);
+    if (lane == 0) red[w] = v;
+    __syncthreads();
+    float m = red[0];
+#pragma unroll
+    for (int k = 1; k < kLPR / 64; ++k) m = red[k] > m ? red[k] : m;
+    __syncthreads();
+    return m;
+}
+
+// exclusive scan of one int per thread over the block; *total receives the sum
+template <int kLPR>
+__device__ __forceinline__ int block_scan(int v, int *red, int *total) {
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int incl = wave_incl_scan(v);
+    if (lane == 63) red[w] = incl;
+    __syncthreads();
+    int base = 0, tot = 0;
+#pragma unroll
+    for (int k = 0; k < kLPR / 64; ++k) {
+        base += k < w ? red[k] : 0;
+        tot += red[k];
+    }
+    __syncthreads();
+    *total = tot;
+    return base + incl - v;
+}
+
+template <bool kF32, int kLPR, int kQ>
+__device__ void block_row(const WalkArgs &a, int64_t task, RowCtx &rc, int *ctl, float *redf, int *redi,
+                          unsigned long long &trans, unsigned long long &spilled, bool &spill_full,
+                          bool &stage_full) {
+    constexpr int H = kLPR * kQ;
+    const int tid = threadIdx.x;
+    const int32_t r = a.rows ? a.rows[task] : (int32_t)task;
+    const int32_t N = a.chains_per_row ? a.chains_per_row[r] : a.chains;
+    rc.r = r;
+    rc.N = N;
+    rc.r_off = a.roff[r];
+    const bool split = a.tau > 0.0;
+    const bool reg = N <= kLPR;
+    if (tid == 0) lds_add(rc.keys, rc.vals, H - 1u, hash_key(r, a.hash_shift), r, (double)N);
+    __syncthreads();
+
+    Chain st;
+    bool paused;
+    chain_start(st, tid, rc);
+    if (!split) {
+        run_chains<kF32, kAll>(a, rc, st, kLPR, true, trans, spilled, spill_full, paused);
+        __syncthreads();
+    } else {
+        run_chains<kF32, kHeavy>(a, rc, st, kLPR, reg, trans, spilled, spill_full, paused);
+        if (!reg) {
+            // the other chains of this lane must finish phase H before any light sum
+            for (;;) {
+                if (paused) chain_start(st, st.c + kLPR, rc);
+                if (!st.active) break;
+                run_chains<kF32, kHeavy>(a, rc, st, kLPR, false, trans, spilled, spill_full, paused);
+            }
+        }
+        __syncthreads();
+        rc.row_spilled = *rc.spill_cnt > 0;  // some heavy column lives in the HBM table
+        if (!reg) chain_start(st, tid, rc);
+        run_chains<kF32, kLight>(a, rc, st, kLPR, true, trans, spilled, spill_full, paused);
+        __syncthreads();
+        // certificate: every untracked column is bounded by its bucket total
+        float mx = 0.f;
+        for (int b = tid; b < a.sketch_slots; b += kLPR) mx = fmaxf(mx, rc.sketch[b]);
+        mx = block_max<kLPR>(mx, redf);
+        const float thr = (float)(a.eps * (double)N) * (15.0f / 16.0f);
+        if (mx >= thr) {
+            rc.hot_thr = thr;
+            chain_start(st, tid, rc);
+            run_chains<kF32, kRefine>(a, rc, st, kLPR, false, trans, spilled, spill_full, paused);
+            if (tid == 0) atomicAdd(&a.stats[3], 1ull);
+            __syncthreads();
+        }
+    }
+
+    // ------------------------------------------------------------ finalize
+    const double nd = (double)N;
+    int32_t kk[kQ];
+    double mv[kQ];
+    int cnt = 0;
+#pragma unroll
+    for (int i = 0; i < kQ; ++i) {
+        const int s = tid * kQ + i;
+        const int32_t raw = rc.keys[s];
+        const double acc = rc.vals[s];
+        kk[i] = kEmpty;
+        mv[i] = 0.0;
+        if (raw != kEmpty) {
+            const int32_t key = (int32_t)((uint32_t)raw & ~kRBit);
+            const double nhat = acc / nd;
+            const double m = nhat / a.diag[key];
+            const double test = a.filter_m ? fabs(m) : fabs(nhat);
+            if (key == r || (nhat != 0.0 && test >= a.eps)) {
+                kk[i] = key;
+                mv[i] = m;
+                ++cnt;
+            }
+        }
+    }
+    int K;
+    int pos = block_scan<kLPR>(cnt, redi, &K);
+#pragma unroll
+    for (int i = 0; i < kQ; ++i) {
+        if (kk[i] != kEmpty) {
+            rc.keys[pos] = kk[i];
+            rc.vals[pos] = mv[i];
+            ++pos;
+        }
+    }
+    __syncthreads();
+    // spilled columns
+    const int nsp = *rc.spill_cnt;
+    for (int base = 0; base < nsp; base += kLPR) {
+        const int u = base + tid;
+        int32_t key = kEmpty;
+        double m = 0.0;
+        int keep = 0;
+        if (u < nsp) {
+            const int32_t slot = rc.sused[u];
+            key = (int32_t)((uint32_t)rc.skeys[slot] & ~kRBit);
+            const double nhat = rc.svals[slot] / nd;
+            m = nhat / a.diag[key];
+            const double test = a.filter_m ? fabs(m) : fabs(nhat);
+            keep = (key == r || (nhat != 0.0 && test >= a.eps)) ? 1 : 0;
+            rc.skeys[slot] = kEmpty;
+            rc.svals[slot] = 0.0;
+        }
+        int added;
+        const int p = K + block_scan<kLPR>(keep, redi, &added);
+        if (keep) {
+            if (p < H) {
+                rc.keys[p] = key;
+                rc.vals[p] = m;
+            } else {
+                stage_full = true;
+            }
+        }
+        K += added;
+    }
+    if (K > H) K = H;
+    int P = 1;
+    while (P < K) P <<= 1;
+    for (int s = K + tid; s < P; s += kLPR) rc.keys[s] = INT32_MAX;
+    __syncthreads();
+    for (int k = 2; k <= P; k <<= 1) {
+        for (int jj = k >> 1; jj > 0; jj >>= 1) {
+            for (int i = tid; i < P; i += kLPR) {
+                const int ixj = i ^ jj;
+                if (ixj > i) {
+                    const int32_t ka = rc.keys[i], kb = rc.keys[ixj];
+                    const bool up = (i & k) == 0;
+                    if ((ka > kb) == up) {
+                        const double va = rc.vals[i], vb = rc.vals[ixj];
+                        rc.keys[i] = kb;
+                        rc.keys[ixj] = ka;
+                        rc.vals[i] = vb;
+                        rc.vals[ixj] = va;
+                    }
+                }
+            }
+            __syncthreads();
+        }
+    }
+    unsigned long long *pool_pos = (unsigned long long *)(ctl + 4);
+    if (tid == 0) *pool_pos = atomicAdd(a.pool_used, (unsigned long long)K);
+    __syncthreads();
+    const unsigned long long pos0 = *pool_pos;
+    const bool fits = (int64_t)(pos0 + (unsigned long long)K) <= a.pool_cap;
+    if (fits) {
+        for (int i = tid; i < K; i += kLPR) {
+            a.pool_col[pos0 + i] = rc.keys[i];
+            a.pool_val[pos0 + i] = rc.vals[i];
+        }
+    }
+    if (tid == 0) {
+        a.row_start[task] = (int64_t)pos0;
+        a.row_cnt[task] = (uint32_t)K;
+        if (!fits) atomicOr(a.flags, kFlagPool);
+        atomicAdd(&a.stats[2], (unsigned long long)N);
+    }
+    __syncthreads();
+    for (int s = tid; s < H; s += kLPR) {
+        rc.keys[s] = kEmpty;
+        rc.vals[s] = 0.0;
+    }
+    for (int b = tid; b < a.sketch_slots; b += kLPR) rc.sketch[b] = 0.f;
+    if (tid == 0) *rc.spill_cnt = 0;
+    __syncthreads();
+}
+
+template <bool kF32, int kLPR, int kQ>
+__global__ void __launch_bounds__(kLPR) k_walk_block(WalkArgs a) {
+    constexpr int H = kLPR * kQ;
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int tid = threadIdx.x;
+    double *vals = (double *)smem;
+    int32_t *keys = (int32_t *)(smem + (size_t)H * 8u);
+    float *sketch = (float *)(smem + (size_t)H * 12u);
+    int *ctl = (int *)(smem + (size_t)H * 12u + (size_t)a.sketch_slots * 4u);  // 16 ints
+    float *redf = (float *)(ctl + 16);
+    int *redi = (int *)(redf + 16);
+    for (int s = tid; s < H; s += kLPR) {
+        keys[s] = kEmpty;
+        vals[s] = 0.0;
+    }
+    for (int b = tid; b < a.sketch_slots; b += kLPR) sketch[b] = 0.f;
+    if (tid < 16) ctl[tid] = 0;
+    __syncthreads();
+    RowCtx rc;
+    rc.keys = keys;
+    rc.vals = vals;
+    rc.sketch = sketch;
+    rc.spill_cnt = &ctl[0];
+    rc.skeys = a.spill_keys + (int64_t)blockIdx.x * a.spill_slots;
+    rc.svals = a.spill_vals + (int64_t)blockIdx.x * a.spill_slots;
+    rc.sused = a.spill_used + (int64_t)blockIdx.x * a.spill_slots;
+    rc.row_spilled = false;
+    rc.hot_thr = 0.f;
+    unsigned long long trans = 0, spilled = 0;
+    bool spill_full = false, stage_full = false;
+    int queue = (int)(blockIdx.x & 7u);
+    for (;;) {
+        if (tid == 0) {
+            int64_t task = -1;
+            for (int tries = 0; tries < 8; ++tries) {
+                const int q = (queue + tries) & 7;
+                const int64_t lo = a.n_tasks * q / 8, hi = a.n_tasks * (q + 1) / 8;
+                if (hi > lo && __atomic_load_n(&a.queue_ctr[q], __ATOMIC_RELAXED) < (uint32_t)(hi - lo)) {
+                    const uint32_t idx = atomicAdd(&a.queue_ctr[q], 1u);
+                    if ((int64_t)idx < hi - lo) {
+                        task = lo + idx;
+                        queue = q;
+                        break;
+                    }
+                }
+            }
+            ctl[2] = (int)(task & 0xffffffff);
+            ctl[3] = (int)(task >> 32);
+        }
+        __syncthreads();
+        const int64_t task = (int64_t)(((uint64_t)(uint32_t)ctl[3] << 32) | (uint32_t)ctl[2]);
+        __syncthreads();
+        if (task < 0) break;
+        block_row<kF32, kLPR, kQ>(a, task, rc, ctl, redf, redi, trans, spilled, spill_full, stage_full);
+    }
+    // one set of atomics per workgroup
+    trans = wave_sum(trans);
+    spilled = wave_sum(spilled);
+    const bool sf = __any(spill_full), gf = __any(stage_full);
+    if ((tid & 63) == 0) {
+        if (trans) atomicAdd(&a.stats[0], trans);
+        if (spilled) atomicAdd(&a.stats[1], spilled);
+        if (sf) atomicOr(a.flags, kFlagSpill);
+        if (gf) atomicOr(a.flags, kFlagStage);
+    }
+}
+
+template <bool kF32, int kLPR, int kQ>
+hipError_t launch_one(const WalkArgs &a, int blocks, hipStream_t s, size_t lds) {
+    k_walk_block<kF32, kLPR, kQ><<<blocks, kLPR, lds, s>>>(a);
+    return hipGetLastError();
+}
+
+template <bool kF32, int kLPR, int kQ>
+hipError_t occ_one(int *bpc, size_t lds) {
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(bpc, k_walk_block<kF32, kLPR, kQ>, kLPR, lds);
+}
+
+}  // namespace
+
+size_t walk_block_lds_bytes(int hash_slots, int sketch_slots) {
+    return (size_t)hash_slots * 12u + (size_t)sketch_slots * 4u + 16 * 4 + 16 * 4 + 16 * 4;
+}
+
+// Supported shapes: lanes in {256, 512, 1024}, slots per lane in {2, 4, 8, 16}.
+#define MCMI_BLOCK_SHAPES(X) \
+    X(256, 4) X(256, 8) X(256, 16) X(512, 2) X(512, 4) X(512, 8) X(1024, 2) X(1024, 4)
+
+bool walk_block_supported(int lanes, int hash_slots) {
+#define X(L, Q) if (lanes == L && hash_slots == L * Q) return true;
+    MCMI_BLOCK_SHAPES(X)
+#undef X
+    return false;
+}
+
+hipError_t launch_walk_block(const WalkArgs &a, bool f32, int lanes, int blocks, hipStream_t s) {
+    const size_t lds = walk_block_lds_bytes(a.hash_slots, a.sketch_slots);
+#define X(L, Q)                                                                   \
+    if (lanes == L && a.hash_slots == L * Q)                                      \
+        return f32 ? launch_one<true, L, Q>(a, blocks, s, lds) : launch_one<false, L, Q>(a, blocks, s, lds);
+    MCMI_BLOCK_SHAPES(X)
+#undef X
+    return hipErrorInvalidValue;
+}
+
+hipError_t walk_block_occupancy(bool f32, int lanes, int hash_slots, int sketch_slots, int *bpc) {
+    const size_t lds = walk_block_lds_bytes(hash_slots, sketch_slots);
+#define X(L, Q) \
+    if (lanes == L && hash_slots == L * Q) return f32 ? occ_one<true, L, Q>(bpc, lds) : occ_one<false, L, Q>(bpc, lds);
+    MCMI_BLOCK_SHAPES(X)
+#undef X
+    return hipErrorInvalidValue;
+}
+
+}  // namespace mcmi

@@ -119,8 +119,6 @@ def test_edge_cases(mc, case, prec):
     kw = dict(kw)
     gkw = {k: kw.pop(k) for k in ("hash_slots", "filter") if k in kw}
     okw = dict(kw)
-    if "tag" in okw:
-        pass
     if "filter" in gkw:
         okw["filter_on_m"] = bool(gkw["filter"])
     (rp, col, val), res, _ = run(mc, B, prec=prec, **kw, **gkw)
@@ -209,3 +207,41 @@ def test_cfg2_full_size_sampled_rows(mc):
     orc64, _ = oracle_run(B, seed=0, chains=512, delta=1e-4, eps=1e-3, rows=rows)
     va, vb = common_entries(sub_rp, sub_col, sub_val, orc64["row_ptr"], orc64["col"], orc64["val"])
     assert np.max(np.abs(va - vb) / np.abs(vb)) < 1e-5
+
+
+# ------------------------------------- workgroup-per-row kernel (heavy/light)
+BLOCK_CASES = {
+    # name: (matrix, chains, gpu params, fp32)
+    "auto_split_register": (lambda: I.random_nonsym(6000, seed=21), 512, dict(lanes_per_row=512), False),
+    "auto_split_register_f32": (lambda: I.random_nonsym(6000, seed=21), 512, dict(lanes_per_row=512), True),
+    "replay_mode_forced_tau": (lambda: I.random_nonsym(3000, seed=22), 700,
+                               dict(lanes_per_row=256, heavy_weight=0.3), False),
+    "refine_tiny_sketch": (lambda: I.random_nonsym(3000, seed=23), 512,
+                           dict(lanes_per_row=512, heavy_weight=0.5, sketch_slots=64), False),
+    "refine_tiny_sketch_f32": (lambda: I.random_nonsym(3000, seed=23), 512,
+                               dict(lanes_per_row=512, heavy_weight=0.5, sketch_slots=64), True),
+    "spill_and_refine": (lambda: I.random_nonsym(3000, seed=24), 300,
+                         dict(lanes_per_row=256, hash_slots=1024, heavy_weight=0.05, sketch_slots=64), False),
+    "track_all_block": (lambda: I.cfg1(), 1000, dict(lanes_per_row=512, heavy_weight=-1.0), False),
+    "m_filter_split": (lambda: I.random_nonsym(2500, seed=25), 512,
+                       dict(lanes_per_row=512, heavy_weight=0.2, sketch_slots=128, filter=1), False),
+    "lanes1024": (lambda: I.random_nonsym(2000, seed=26), 1024, dict(lanes_per_row=1024), True),
+}
+
+
+@pytest.mark.parametrize("case", sorted(BLOCK_CASES))
+def test_block_kernel_paths(mc, case):
+    make, N, gkw, f32 = BLOCK_CASES[case]
+    B = make()
+    prec = 32 if f32 else 64
+    (rp, col, val), res, _ = run(mc, B, seed=2, chains=N, delta=1e-4, eps=1e-3, prec=prec, **gkw)
+    print(f"[gpu] {case}: lanes={res.stats.lanes_per_row} H={res.stats.hash_slots} "
+          f"sketch={res.stats.sketch_slots} tau={res.stats.heavy_weight} refined={res.stats.refined} "
+          f"spilled={res.stats.spilled} retries={res.stats.retries}", flush=True)
+    orc, o = oracle_run(B, seed=2, chains=N, delta=1e-4, eps=1e-3, prec=prec,
+                        filter_on_m=bool(gkw.get("filter", 0)))
+    assert orc["guard"] == 0
+    assert res.stats.transitions == orc["transitions"]
+    compare_spai((rp, col, val), orc, o.diag, N)
+    if "sketch_slots" in gkw:
+        assert res.stats.refined > 0, "the tiny sketch should have forced replays"
