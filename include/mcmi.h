@@ -96,13 +96,17 @@ typedef struct {
                              one workgroup of that many lanes per row */
     int32_t hash_slots;   /* 0 = automatic; else LDS hash slots per row (power of two) */
     int32_t sketch_slots; /* 0 = automatic; else count-sketch buckets per row (power of two) */
-    int32_t reserved;     /* must be zero */
+    int32_t pool_per_row; /* 0 = automatic; else first guess of kept entries per row: rows that
+                             do not fit are rerun into a second pool sized exactly */
     double heavy_weight;  /* workgroup-per-row kernel only. 0 = automatic; < 0 = track every
                              contribution in the row hash; > 0 (<= 1): contributions with
                              |W| >= heavy_weight are tracked, lighter ones are added to
                              tracked columns or to a count sketch that certifies that no
                              untracked column reaches the filter threshold (rows that fail
                              the certificate are replayed exactly). Needs ||Chat||_inf < 1. */
+    int32_t spill_slots;  /* 0 = automatic; else HBM overflow-table slots per row in flight
+                             (power of two); rows that overflow it are rerun with it grown */
+    int32_t reserved;     /* must be zero */
 } mcmi_params;
 
 typedef struct {

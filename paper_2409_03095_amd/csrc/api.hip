@@ -19,7 +19,9 @@ bool walk_block_supported(int lanes, int hash_slots);
 hipError_t launch_walk_block(const WalkArgs &a, bool f32, int lanes, int blocks, hipStream_t s);
 hipError_t walk_block_occupancy(bool f32, int lanes, int hash_slots, int sketch_slots, int *bpc);
 hipError_t gather_rows(int64_t n_rows, const int64_t *row_start, const uint32_t *row_cnt, const int64_t *row_ptr,
-                       const int32_t *pool_col, const double *pool_val, int32_t *col, double *val, hipStream_t s);
+                       const PoolSet &pools, int32_t *col, double *val, hipStream_t s);
+hipError_t collect_failed(int64_t n_slots, const int64_t *row_start, const uint32_t *row_cnt, int32_t *list,
+                          unsigned long long *ctr, hipStream_t s);
 hipError_t validate_rows(const int32_t *rows, int64_t n_rows, const int32_t *cpr, int64_t n, uint32_t *bad,
                          hipStream_t s);
 hipError_t spmv(int64_t n, const int64_t *rp, const int32_t *ci, const double *v, const double *x, double *y,
@@ -105,6 +107,9 @@ extern "C" mcmi_status mcmi_spai(const mcmi_cdf *cdf, const mcmi_params *p, cons
     if (!(p->eps >= 0.0) || !(p->delta >= 0.0)) return fail(MCMI_ERR_ARG, "mcmi_spai: eps and delta must be >= 0");
     if (p->filter != MCMI_FILTER_N && p->filter != MCMI_FILTER_M) return fail(MCMI_ERR_ARG, "mcmi_spai: bad filter");
     if (p->reserved) return fail(MCMI_ERR_ARG, "mcmi_spai: reserved != 0");
+    if (p->pool_per_row < 0) return fail(MCMI_ERR_ARG, "mcmi_spai: pool_per_row must be >= 0");
+    if (p->spill_slots && (p->spill_slots < 16 || (p->spill_slots & (p->spill_slots - 1))))
+        return fail(MCMI_ERR_ARG, "mcmi_spai: spill_slots must be a power of two >= 16");
     if (p->hash_slots && (p->hash_slots < 64 || p->hash_slots > 8192 || (p->hash_slots & (p->hash_slots - 1))))
         return fail(MCMI_ERR_ARG, "mcmi_spai: hash_slots must be a power of two in [64, 8192]");
     if (p->sketch_slots && (p->sketch_slots < 64 || p->sketch_slots > 16384 ||
@@ -178,13 +183,19 @@ extern "C" mcmi_status mcmi_spai(const mcmi_cdf *cdf, const mcmi_params *p, cons
         if (tau > 0.0) sketch = p->sketch_slots ? p->sketch_slots : 4096;
     }
     int waves = 4;
-    int spill_slots = block_kernel ? 16384 : 4096;
-    int64_t pool_cap = std::max<int64_t>(n_tasks * 64, 1 << 16);
+    int spill_slots = p->spill_slots ? p->spill_slots : (block_kernel ? 16384 : 4096);
+    // first guess of the output size; rows that do not fit are rerun into a new pool
+    int64_t pool_cap = n_tasks * (p->pool_per_row ? p->pool_per_row
+                                                  : (block_kernel ? std::min(H, 256) : std::min(H / 2, 128)));
+    pool_cap = std::min<int64_t>(pool_cap, (int64_t)1 << 30);
+    if (!p->pool_per_row) pool_cap = std::max<int64_t>(pool_cap, 1 << 16);
+    pool_cap = std::max<int64_t>(pool_cap, 1);
     uint64_t retries = 0;
 
-    DevBuf row_start, row_cnt, pool_col, pool_val, sk, sv, su, ctrl, row_ptr, scan_tmp;
-    // ctrl: [0..7] queue counters (u32), then u64 pool_used, u64 stats[4], u32 flags
-    const size_t ctrl_bytes = 8 * 4 + 8 + 4 * 8 + 8;
+    DevBuf row_start, row_cnt, sk, sv, su, ctrl, row_ptr, scan_tmp, failed;
+    DevBuf pool_col[kMaxPools], pool_val[kMaxPools];
+    // ctrl: [0..7] queue counters (u32), then u64 pool_used, u64 stats[4], u32 flags, u64 collect[2]
+    const size_t ctrl_bytes = 8 * 4 + 8 + 4 * 8 + 8 + 16;
     MCMI_HIP(ctrl.alloc(ctrl_bytes, s));
     MCMI_HIP(row_start.alloc(n_tasks * sizeof(int64_t), s));
     MCMI_HIP(row_cnt.alloc(n_tasks * sizeof(uint32_t), s));
@@ -194,6 +205,7 @@ extern "C" mcmi_status mcmi_spai(const mcmi_cdf *cdf, const mcmi_params *p, cons
     unsigned long long *pool_used = (unsigned long long *)(ctrl.as<unsigned char>() + 32);
     unsigned long long *stats = (unsigned long long *)(ctrl.as<unsigned char>() + 40);
     uint32_t *flags = (uint32_t *)(ctrl.as<unsigned char>() + 72);
+    unsigned long long *collect = (unsigned long long *)(ctrl.as<unsigned char>() + 80);
 
     if (rows_dev || chains_per_row_dev) {
         uint32_t hbad = 0;
@@ -206,38 +218,42 @@ extern "C" mcmi_status mcmi_spai(const mcmi_cdf *cdf, const mcmi_params *p, cons
     }
 
     int64_t nnz = 0;
-    unsigned long long hstats[4] = {0, 0, 0, 0};
+    unsigned long long tot_stats[4] = {0, 0, 0, 0};
     float ms_walk = 0.f;
+    PoolSet pools;
+    memset(&pools, 0, sizeof(pools));
+    const int32_t *task_map = nullptr;
+    int64_t pass_tasks = n_tasks;
     MCMI_HIP(hipEventRecord(ev0, s));
-    for (;;) {
+    for (int pass = 0;; ++pass) {
+        if (pass >= kMaxPools) return fail(MCMI_ERR_CAPACITY, "mcmi_spai: rows still overflow after regrowing tables");
         int bpc = 0;
         int64_t blocks = 0, regions = 0;
         if (block_kernel) {
             MCMI_HIP(walk_block_occupancy(f32, lanes, H, sketch, &bpc));
             if (bpc < 1) return fail(MCMI_ERR_CAPACITY, "mcmi_spai: workgroup kernel does not fit in LDS");
-            blocks = std::min<int64_t>((int64_t)bpc * cus, n_tasks);
+            blocks = std::min<int64_t>((int64_t)bpc * cus, pass_tasks);
             regions = blocks;
         } else {
             MCMI_HIP(walk_occupancy(f32, H, waves, &bpc));
-            if (bpc < 1) {
-                if (waves > 1) {
-                    waves >>= 1;
-                    continue;
-                }
-                return fail(MCMI_ERR_CAPACITY, "mcmi_spai: hash table does not fit in LDS");
+            while (bpc < 1 && waves > 1) {
+                waves >>= 1;
+                MCMI_HIP(walk_occupancy(f32, H, waves, &bpc));
             }
+            if (bpc < 1) return fail(MCMI_ERR_CAPACITY, "mcmi_spai: hash table does not fit in LDS");
             blocks = (int64_t)bpc * cus;
-            if (blocks * waves > n_tasks) blocks = std::max<int64_t>(1, (n_tasks + waves - 1) / waves);
+            if (blocks * waves > pass_tasks) blocks = std::max<int64_t>(1, (pass_tasks + waves - 1) / waves);
             regions = blocks * waves;
         }
-        const int64_t total_waves = regions;
-        MCMI_HIP(pool_col.alloc((size_t)pool_cap * sizeof(int32_t), s));
-        MCMI_HIP(pool_val.alloc((size_t)pool_cap * sizeof(double), s));
-        MCMI_HIP(sk.alloc((size_t)total_waves * spill_slots * sizeof(int32_t), s));
-        MCMI_HIP(sv.alloc((size_t)total_waves * spill_slots * sizeof(double), s));
-        MCMI_HIP(su.alloc((size_t)total_waves * spill_slots * sizeof(int32_t), s));
-        MCMI_HIP(hipMemsetAsync(sk.p, 0xFF, (size_t)total_waves * spill_slots * sizeof(int32_t), s));
-        MCMI_HIP(hipMemsetAsync(sv.p, 0, (size_t)total_waves * spill_slots * sizeof(double), s));
+        MCMI_HIP(pool_col[pass].alloc((size_t)pool_cap * sizeof(int32_t), s));
+        MCMI_HIP(pool_val[pass].alloc((size_t)pool_cap * sizeof(double), s));
+        pools.col[pass] = pool_col[pass].as<int32_t>();
+        pools.val[pass] = pool_val[pass].as<double>();
+        MCMI_HIP(sk.alloc((size_t)regions * spill_slots * sizeof(int32_t), s));
+        MCMI_HIP(sv.alloc((size_t)regions * spill_slots * sizeof(double), s));
+        MCMI_HIP(su.alloc((size_t)regions * spill_slots * sizeof(int32_t), s));
+        MCMI_HIP(hipMemsetAsync(sk.p, 0xFF, (size_t)regions * spill_slots * sizeof(int32_t), s));
+        MCMI_HIP(hipMemsetAsync(sv.p, 0, (size_t)regions * spill_slots * sizeof(double), s));
         MCMI_HIP(hipMemsetAsync(ctrl.p, 0, ctrl_bytes, s));
 
         WalkArgs a;
@@ -246,7 +262,9 @@ extern "C" mcmi_status mcmi_spai(const mcmi_cdf *cdf, const mcmi_params *p, cons
         a.roff = cdf->roff;
         a.diag = cdf->diag;
         a.rows = rows_dev;
-        a.n_tasks = n_tasks;
+        a.n_tasks = pass_tasks;
+        a.task_map = task_map;
+        a.pool_tag = (int64_t)pass << kPoolShift;
         a.chains_per_row = chains_per_row_dev;
         a.chains = p->chains;
         a.key0 = (uint32_t)(p->seed & 0xffffffffu);
@@ -262,8 +280,8 @@ extern "C" mcmi_status mcmi_spai(const mcmi_cdf *cdf, const mcmi_params *p, cons
         a.queue_ctr = qctr;
         a.row_start = row_start.as<int64_t>();
         a.row_cnt = row_cnt.as<uint32_t>();
-        a.pool_col = pool_col.as<int32_t>();
-        a.pool_val = pool_val.as<double>();
+        a.pool_col = pool_col[pass].as<int32_t>();
+        a.pool_val = pool_val[pass].as<double>();
         a.pool_cap = pool_cap;
         a.pool_used = pool_used;
         a.spill_keys = sk.as<int32_t>();
@@ -276,37 +294,52 @@ extern "C" mcmi_status mcmi_spai(const mcmi_cdf *cdf, const mcmi_params *p, cons
         a.tau32 = (float)tau;
         a.sketch_slots = sketch;
         a.sketch_shift = sketch ? 32 - __builtin_ctz((unsigned)sketch) : 0;
-        MCMI_HIP(hipEventRecord(ev1, s));
+        if (pass == 0) MCMI_HIP(hipEventRecord(ev1, s));
         if (block_kernel)
             MCMI_HIP(launch_walk_block(a, f32, lanes, (int)blocks, s));
         else
             MCMI_HIP(launch_walk(a, f32, (int)blocks, waves, s));
         MCMI_HIP(hipEventRecord(ev2, s));
-        MCMI_HIP(scan_exclusive_u32_to_i64(row_cnt.as<uint32_t>(), row_ptr.as<int64_t>(), n_tasks,
-                                           row_ptr.as<int64_t>() + n_tasks, scan_tmp.p, s));
         uint32_t hflags = 0;
-        unsigned long long hused = 0;
+        unsigned long long hstats[4] = {0, 0, 0, 0};
         MCMI_HIP(hipMemcpyAsync(&hflags, flags, sizeof(hflags), hipMemcpyDeviceToHost, s));
-        MCMI_HIP(hipMemcpyAsync(&hused, pool_used, sizeof(hused), hipMemcpyDeviceToHost, s));
         MCMI_HIP(hipMemcpyAsync(hstats, stats, sizeof(hstats), hipMemcpyDeviceToHost, s));
-        MCMI_HIP(hipMemcpyAsync(&nnz, row_ptr.as<int64_t>() + n_tasks, sizeof(nnz), hipMemcpyDeviceToHost, s));
         MCMI_HIP(hipStreamSynchronize(s));
-        MCMI_HIP(hipEventElapsedTime(&ms_walk, ev1, ev2));
+        for (int k = 0; k < 4; ++k) tot_stats[k] += hstats[k];
         if (!(hflags & (kFlagPool | kFlagSpill | kFlagStage))) break;
-        if (++retries > 6) return fail(MCMI_ERR_CAPACITY, "mcmi_spai: tables still overflow after 6 regrowths");
-        if (hflags & kFlagPool) pool_cap = (int64_t)hused + 1024;
+        // rerun only the rows that overflowed, with the overflowing tables grown
+        ++retries;
+        if (!failed.p) MCMI_HIP(failed.alloc((size_t)n_tasks * sizeof(int32_t), s));
+        unsigned long long hcol[2] = {0, 0};
+        MCMI_HIP(collect_failed(n_tasks, row_start.as<int64_t>(), row_cnt.as<uint32_t>(), failed.as<int32_t>(),
+                                collect, s));
+        MCMI_HIP(hipMemcpyAsync(hcol, collect, sizeof(hcol), hipMemcpyDeviceToHost, s));
+        MCMI_HIP(hipStreamSynchronize(s));
+        // the failed list is read by the next pass while `collect` is cleared with ctrl
+        DevBuf next_map;
+        MCMI_HIP(next_map.alloc((size_t)std::max<unsigned long long>(hcol[0], 1) * sizeof(int32_t), s));
+        MCMI_HIP(hipMemcpyAsync(next_map.p, failed.p, (size_t)hcol[0] * sizeof(int32_t), hipMemcpyDeviceToDevice, s));
+        std::swap(failed.p, next_map.p);
+        task_map = failed.as<int32_t>();
+        pass_tasks = (int64_t)hcol[0];
+        pool_cap = std::max<int64_t>((int64_t)(hcol[1] + hcol[1] / 4) + 1024, pass_tasks * 64);
         if (hflags & kFlagSpill) spill_slots *= 4;
         if (hflags & kFlagStage) {
             if (block_kernel) {
                 if (!walk_block_supported(lanes, H * 2))
                     return fail(MCMI_ERR_CAPACITY, "mcmi_spai: more survivors per row than the workgroup table holds");
-                H *= 2;
-            } else {
-                if (H >= 8192) return fail(MCMI_ERR_CAPACITY, "mcmi_spai: more survivors per row than 8192 slots");
-                H *= 2;
+            } else if (H >= 8192) {
+                return fail(MCMI_ERR_CAPACITY, "mcmi_spai: more survivors per row than 8192 slots");
             }
+            H *= 2;
         }
     }
+    MCMI_HIP(hipEventElapsedTime(&ms_walk, ev1, ev2));
+    MCMI_HIP(scan_exclusive_u32_to_i64(row_cnt.as<uint32_t>(), row_ptr.as<int64_t>(), n_tasks,
+                                       row_ptr.as<int64_t>() + n_tasks, scan_tmp.p, s));
+    MCMI_HIP(hipMemcpyAsync(&nnz, row_ptr.as<int64_t>() + n_tasks, sizeof(nnz), hipMemcpyDeviceToHost, s));
+    MCMI_HIP(hipStreamSynchronize(s));
+    unsigned long long *hstats = tot_stats;
 
     // ---- CSR assembly
     hipEvent_t ev3;
@@ -326,8 +359,7 @@ extern "C" mcmi_status mcmi_spai(const mcmi_cdf *cdf, const mcmi_params *p, cons
     }
     hipError_t ge = hipMemcpyAsync(rp, row_ptr.p, (size_t)(n_tasks + 1) * sizeof(int64_t), hipMemcpyDeviceToDevice, s);
     if (ge == hipSuccess)
-        ge = gather_rows(n_tasks, row_start.as<int64_t>(), row_cnt.as<uint32_t>(), rp, pool_col.as<int32_t>(),
-                         pool_val.as<double>(), col, val, s);
+        ge = gather_rows(n_tasks, row_start.as<int64_t>(), row_cnt.as<uint32_t>(), rp, pools, col, val, s);
     if (ge == hipSuccess) ge = hipEventRecord(ev3, s);
     if (ge == hipSuccess) ge = hipEventSynchronize(ev3);
     if (ge != hipSuccess) {

@@ -44,6 +44,12 @@ enum : uint32_t {
     kFlagSpill = 16u,     // spill table overflow
     kFlagStage = 32u,     // more survivors than the staging area holds
 };
+constexpr int kPoolShift = 56;   // row_start = position | (pool index << kPoolShift)
+constexpr int kMaxPools = 8;
+struct PoolSet {
+    const int32_t *col[kMaxPools];
+    const double *val[kMaxPools];
+};
 
 // ------------------------------------------------------------------ Philox
 // Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11): ten rounds; each round

@@ -103,33 +103,60 @@ hipError_t scan_exclusive_u32_to_i64(const uint32_t *in, int64_t *out, int64_t n
 }
 
 // ------------------------------------------------------------- assembly
-// Copy each row's survivors from the pool (row_start, row_cnt) into the CSR
-// arrays at row_ptr. One wave per row, lanes over entries (coalesced).
+// Copy each row's survivors from its pool into the CSR arrays at row_ptr. One
+// wave per row, lanes over entries (coalesced). row_start holds the position in
+// the low 56 bits and the pool index above.
 __global__ void __launch_bounds__(256) k_gather_rows(int64_t n_rows, const int64_t *row_start,
-                                                     const uint32_t *row_cnt, const int64_t *row_ptr,
-                                                     const int32_t *pool_col, const double *pool_val,
+                                                     const uint32_t *row_cnt, const int64_t *row_ptr, PoolSet pools,
                                                      int32_t *col, double *val) {
     const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
     const int lane = threadIdx.x & 63;
     const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
+    constexpr int64_t kPosMask = ((int64_t)1 << kPoolShift) - 1;
     for (int64_t r = wave; r < n_rows; r += nwaves) {
-        const int64_t src = row_start[r], dst = row_ptr[r];
+        const int64_t tagged = row_start[r], dst = row_ptr[r];
+        const int pool = (int)(tagged >> kPoolShift);
+        const int64_t src = tagged & kPosMask;
         const uint32_t cnt = row_cnt[r];
+        const int32_t *pc = pools.col[pool];
+        const double *pv = pools.val[pool];
         for (uint32_t k = lane; k < cnt; k += 64) {
-            col[dst + k] = pool_col[src + k];
-            val[dst + k] = pool_val[src + k];
+            col[dst + k] = pc[src + k];
+            val[dst + k] = pv[src + k];
         }
     }
 }
 
 hipError_t gather_rows(int64_t n_rows, const int64_t *row_start, const uint32_t *row_cnt, const int64_t *row_ptr,
-                       const int32_t *pool_col, const double *pool_val, int32_t *col, double *val,
-                       hipStream_t s) {
+                       const PoolSet &pools, int32_t *col, double *val, hipStream_t s) {
     if (n_rows <= 0) return hipSuccess;
     int64_t blocks = (n_rows + 3) / 4;
     if (blocks > 65536) blocks = 65536;
-    k_gather_rows<<<(unsigned)blocks, 256, 0, s>>>(n_rows, row_start, row_cnt, row_ptr, pool_col, pool_val, col,
-                                                   val);
+    k_gather_rows<<<(unsigned)blocks, 256, 0, s>>>(n_rows, row_start, row_cnt, row_ptr, pools, col, val);
+    return hipGetLastError();
+}
+
+// Slots whose row must be rerun (row_start < 0): appended to `list`, count in
+// ctr[0], their survivor counts summed in ctr[1] (pool overflows know theirs).
+__global__ void __launch_bounds__(256) k_collect_failed(int64_t n_slots, const int64_t *row_start,
+                                                        const uint32_t *row_cnt, int32_t *list,
+                                                        unsigned long long *ctr) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n_slots; i += stride) {
+        if (row_start[i] < 0) {
+            const unsigned long long k = atomicAdd(&ctr[0], 1ull);
+            list[k] = (int32_t)i;
+            atomicAdd(&ctr[1], (unsigned long long)row_cnt[i]);
+        }
+    }
+}
+
+hipError_t collect_failed(int64_t n_slots, const int64_t *row_start, const uint32_t *row_cnt, int32_t *list,
+                          unsigned long long *ctr, hipStream_t s) {
+    int64_t blocks = (n_slots + 255) / 256;
+    if (blocks > 4096) blocks = 4096;
+    if (blocks < 1) blocks = 1;
+    k_collect_failed<<<(unsigned)blocks, 256, 0, s>>>(n_slots, row_start, row_cnt, list, ctr);
     return hipGetLastError();
 }
 

@@ -62,7 +62,8 @@ __device__ void walk_row(const WalkArgs &a, int64_t task, int32_t *keys, double 
     const int lane = lane_id();
     const uint32_t hmask = (uint32_t)a.hash_slots - 1u;
     const uint32_t smask = (uint32_t)a.spill_slots - 1u;
-    const int32_t r = a.rows ? a.rows[task] : (int32_t)task;
+    const int64_t slot = a.task_map ? (int64_t)a.task_map[task] : task;
+    const int32_t r = a.rows ? a.rows[slot] : (int32_t)slot;
     const int32_t N = a.chains_per_row ? a.chains_per_row[r] : a.chains;
     const uint32_t r_off = a.roff[r];
 
@@ -226,34 +227,35 @@ __device__ void walk_row(const WalkArgs &a, int64_t task, int32_t *keys, double 
         }
     }
 
-    // append to the pool
+    // append to the pool unless a table overflowed for this row (then it is rerun)
+    const bool row_spill_full = __any(spill_full);
+    const bool row_stage_full = __any(stage_full);
     unsigned long long pos0 = 0;
-    if (lane == 0) pos0 = atomicAdd(a.pool_used, (unsigned long long)K);
+    if (lane == 0 && !row_spill_full && !row_stage_full) pos0 = atomicAdd(a.pool_used, (unsigned long long)K);
     pos0 = __shfl(pos0, 0, 64);
     const bool fits = (int64_t)(pos0 + (unsigned long long)K) <= a.pool_cap;
-    if (fits) {
+    const bool ok = fits && !row_spill_full && !row_stage_full;
+    if (ok) {
         for (int i = lane; i < K; i += 64) {
             a.pool_col[pos0 + i] = keys[i];
             a.pool_val[pos0 + i] = vals[i];
         }
     }
-    if (lane == 0) {
-        a.row_start[task] = (int64_t)pos0;
-        a.row_cnt[task] = (uint32_t)K;
-        uint32_t f = 0;
-        if (!fits) f |= kFlagPool;
-        if (f) atomicOr(a.flags, f);
-    }
-    const bool any_spill_full = __any(spill_full);
-    const bool any_stage_full = __any(stage_full);
     trans = wave_sum(trans);
     spilled = wave_sum(spilled);
     if (lane == 0) {
-        atomicAdd(&a.stats[0], trans);
+        a.row_start[slot] = ok ? ((int64_t)pos0 | a.pool_tag) : -1;
+        a.row_cnt[slot] = (uint32_t)K;
+        uint32_t f = 0;
+        if (!fits && !row_spill_full && !row_stage_full) f |= kFlagPool;
+        if (row_spill_full) f |= kFlagSpill;
+        if (row_stage_full) f |= kFlagStage;
+        if (f) atomicOr(a.flags, f);
+        if (ok) {
+            atomicAdd(&a.stats[0], trans);
+            atomicAdd(&a.stats[2], (unsigned long long)N);
+        }
         if (spilled) atomicAdd(&a.stats[1], spilled);
-        atomicAdd(&a.stats[2], (unsigned long long)N);
-        if (any_spill_full) atomicOr(a.flags, kFlagSpill);
-        if (any_stage_full) atomicOr(a.flags, kFlagStage);
     }
     // clear for the next row
     wave_sync();

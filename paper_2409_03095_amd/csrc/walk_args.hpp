@@ -8,8 +8,10 @@ struct WalkArgs {
     const uint32_t *rec;
     const uint32_t *roff;
     const double *diag;
-    const int32_t *rows;           // nullable: task t is row t
+    const int32_t *rows;           // nullable: output slot t is row t
     int64_t n_tasks;
+    const int32_t *task_map;       // nullable: task k works on output slot task_map[k]
+    int64_t pool_tag;              // (pool index) << 56, or-ed into row_start
     const int32_t *chains_per_row; // nullable
     int32_t chains;
     uint32_t key0, key1, tag;
@@ -21,7 +23,7 @@ struct WalkArgs {
     int32_t hash_slots;            // power of two
     int32_t hash_shift;            // 32 - log2(hash_slots)
     uint32_t *queue_ctr;           // 8 counters
-    int64_t *row_start;
+    int64_t *row_start;            // pool position | pool_tag, or -1 when the row must be rerun
     uint32_t *row_cnt;
     int32_t *pool_col;
     double *pool_val;

@@ -262,8 +262,12 @@ __device__ void block_row(const WalkArgs &a, int64_t task, RowCtx &rc, int *ctl,
                           bool &stage_full) {
     constexpr int H = kLPR * kQ;
     const int tid = threadIdx.x;
-    const int32_t r = a.rows ? a.rows[task] : (int32_t)task;
+    const int64_t slot = a.task_map ? (int64_t)a.task_map[task] : task;
+    const int32_t r = a.rows ? a.rows[slot] : (int32_t)slot;
     const int32_t N = a.chains_per_row ? a.chains_per_row[r] : a.chains;
+    unsigned long long row_trans = 0;
+    spill_full = false;
+    stage_full = false;
     rc.r = r;
     rc.N = N;
     rc.r_off = a.roff[r];
@@ -276,22 +280,22 @@ __device__ void block_row(const WalkArgs &a, int64_t task, RowCtx &rc, int *ctl,
     bool paused;
     chain_start(st, tid, rc);
     if (!split) {
-        run_chains<kF32, kAll>(a, rc, st, kLPR, true, trans, spilled, spill_full, paused);
+        run_chains<kF32, kAll>(a, rc, st, kLPR, true, row_trans, spilled, spill_full, paused);
         __syncthreads();
     } else {
-        run_chains<kF32, kHeavy>(a, rc, st, kLPR, reg, trans, spilled, spill_full, paused);
+        run_chains<kF32, kHeavy>(a, rc, st, kLPR, reg, row_trans, spilled, spill_full, paused);
         if (!reg) {
             // the other chains of this lane must finish phase H before any light sum
             for (;;) {
                 if (paused) chain_start(st, st.c + kLPR, rc);
                 if (!st.active) break;
-                run_chains<kF32, kHeavy>(a, rc, st, kLPR, false, trans, spilled, spill_full, paused);
+                run_chains<kF32, kHeavy>(a, rc, st, kLPR, false, row_trans, spilled, spill_full, paused);
             }
         }
         __syncthreads();
         rc.row_spilled = *rc.spill_cnt > 0;  // some heavy column lives in the HBM table
         if (!reg) chain_start(st, tid, rc);
-        run_chains<kF32, kLight>(a, rc, st, kLPR, true, trans, spilled, spill_full, paused);
+        run_chains<kF32, kLight>(a, rc, st, kLPR, true, row_trans, spilled, spill_full, paused);
         __syncthreads();
         // certificate: every untracked column is bounded by its bucket total
         float mx = 0.f;
@@ -301,7 +305,7 @@ __device__ void block_row(const WalkArgs &a, int64_t task, RowCtx &rc, int *ctl,
         if (mx >= thr) {
             rc.hot_thr = thr;
             chain_start(st, tid, rc);
-            run_chains<kF32, kRefine>(a, rc, st, kLPR, false, trans, spilled, spill_full, paused);
+            run_chains<kF32, kRefine>(a, rc, st, kLPR, false, row_trans, spilled, spill_full, paused);
             if (tid == 0) atomicAdd(&a.stats[3], 1ull);
             __syncthreads();
         }
@@ -350,14 +354,14 @@ __device__ void block_row(const WalkArgs &a, int64_t task, RowCtx &rc, int *ctl,
         double m = 0.0;
         int keep = 0;
         if (u < nsp) {
-            const int32_t slot = rc.sused[u];
-            key = (int32_t)((uint32_t)rc.skeys[slot] & ~kRBit);
-            const double nhat = rc.svals[slot] / nd;
+            const int32_t sl = rc.sused[u];
+            key = (int32_t)((uint32_t)rc.skeys[sl] & ~kRBit);
+            const double nhat = rc.svals[sl] / nd;
             m = nhat / a.diag[key];
             const double test = a.filter_m ? fabs(m) : fabs(nhat);
             keep = (key == r || (nhat != 0.0 && test >= a.eps)) ? 1 : 0;
-            rc.skeys[slot] = kEmpty;
-            rc.svals[slot] = 0.0;
+            rc.skeys[sl] = kEmpty;
+            rc.svals[sl] = 0.0;
         }
         int added;
         const int p = K + block_scan<kLPR>(keep, redi, &added);
@@ -395,22 +399,34 @@ __device__ void block_row(const WalkArgs &a, int64_t task, RowCtx &rc, int *ctl,
             __syncthreads();
         }
     }
+    // row-wide overflow flags: a row whose tables overflowed is rerun, not written
+    if (spill_full) atomicOr(&ctl[6], 1);
+    if (stage_full) atomicOr(&ctl[6], 2);
+    __syncthreads();
+    const int row_fail = ctl[6];
     unsigned long long *pool_pos = (unsigned long long *)(ctl + 4);
-    if (tid == 0) *pool_pos = atomicAdd(a.pool_used, (unsigned long long)K);
+    if (tid == 0) *pool_pos = row_fail ? 0ull : atomicAdd(a.pool_used, (unsigned long long)K);
     __syncthreads();
     const unsigned long long pos0 = *pool_pos;
     const bool fits = (int64_t)(pos0 + (unsigned long long)K) <= a.pool_cap;
-    if (fits) {
+    const bool ok = fits && !row_fail;
+    if (ok) {
         for (int i = tid; i < K; i += kLPR) {
             a.pool_col[pos0 + i] = rc.keys[i];
             a.pool_val[pos0 + i] = rc.vals[i];
         }
+        trans += row_trans;
     }
     if (tid == 0) {
-        a.row_start[task] = (int64_t)pos0;
-        a.row_cnt[task] = (uint32_t)K;
-        if (!fits) atomicOr(a.flags, kFlagPool);
-        atomicAdd(&a.stats[2], (unsigned long long)N);
+        a.row_start[slot] = ok ? ((int64_t)pos0 | a.pool_tag) : -1;
+        a.row_cnt[slot] = (uint32_t)K;
+        uint32_t f = 0;
+        if (!fits && !row_fail) f |= kFlagPool;
+        if (row_fail & 1) f |= kFlagSpill;
+        if (row_fail & 2) f |= kFlagStage;
+        if (f) atomicOr(a.flags, f);
+        if (ok) atomicAdd(&a.stats[2], (unsigned long long)N);
+        ctl[6] = 0;
     }
     __syncthreads();
     for (int s = tid; s < H; s += kLPR) {
@@ -480,12 +496,9 @@ __global__ void __launch_bounds__(kLPR) k_walk_block(WalkArgs a) {
     // one set of atomics per workgroup
     trans = wave_sum(trans);
     spilled = wave_sum(spilled);
-    const bool sf = __any(spill_full), gf = __any(stage_full);
     if ((tid & 63) == 0) {
         if (trans) atomicAdd(&a.stats[0], trans);
         if (spilled) atomicAdd(&a.stats[1], spilled);
-        if (sf) atomicOr(a.flags, kFlagSpill);
-        if (gf) atomicOr(a.flags, kFlagStage);
     }
 }
 

@@ -50,8 +50,8 @@ class Params(ctypes.Structure):
     _fields_ = [("seed", ctypes.c_uint64), ("chains", ctypes.c_int32), ("walk_prec", ctypes.c_int32),
                 ("delta", ctypes.c_double), ("eps", ctypes.c_double), ("max_len", ctypes.c_int32),
                 ("stream_tag", ctypes.c_uint32), ("filter", ctypes.c_int32), ("lanes_per_row", ctypes.c_int32),
-                ("hash_slots", ctypes.c_int32), ("sketch_slots", ctypes.c_int32), ("reserved", ctypes.c_int32),
-                ("heavy_weight", ctypes.c_double)]
+                ("hash_slots", ctypes.c_int32), ("sketch_slots", ctypes.c_int32), ("pool_per_row", ctypes.c_int32),
+                ("heavy_weight", ctypes.c_double), ("spill_slots", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 class Stats(ctypes.Structure):
@@ -215,10 +215,11 @@ class SpaiResult:
 
 
 def params(seed=0, chains=16, delta=1e-3, eps=1e-3, walk_prec=WALK_F64, max_len=0, tag=0, filter=FILTER_N,
-           lanes_per_row=0, hash_slots=0, sketch_slots=0, heavy_weight=0.0) -> Params:
+           lanes_per_row=0, hash_slots=0, sketch_slots=0, heavy_weight=0.0, pool_per_row=0,
+           spill_slots=0) -> Params:
     return Params(int(seed) & 0xFFFFFFFFFFFFFFFF, int(chains), int(walk_prec), float(delta), float(eps),
                   int(max_len), int(tag) & 0xFFFFFFFF, int(filter), int(lanes_per_row), int(hash_slots),
-                  int(sketch_slots), 0, float(heavy_weight))
+                  int(sketch_slots), int(pool_per_row), float(heavy_weight), int(spill_slots), 0)
 
 
 def spai(cdf: Cdf, p: Params, chains_per_row=None, rows=None, stream=None) -> SpaiResult:

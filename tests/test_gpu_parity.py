@@ -245,3 +245,31 @@ def test_block_kernel_paths(mc, case):
     compare_spai((rp, col, val), orc, o.diag, N)
     if case.startswith(("refine", "spill_and_refine")):
         assert res.stats.refined > 0, "the tiny sketch should have forced replays"
+
+
+# ------------------------------------------------ overflow and rerun of rows
+RERUN_CASES = {
+    "pool_wave": (lambda: I.random_nonsym(3000, seed=31), 64, dict(lanes_per_row=64, pool_per_row=2), 1e-3),
+    "pool_block": (lambda: I.random_nonsym(3000, seed=32), 512, dict(lanes_per_row=512, pool_per_row=3), 1e-3),
+    "spill_table_wave": (lambda: I.random_nonsym(1500, seed=33), 128,
+                         dict(lanes_per_row=64, hash_slots=64, spill_slots=16), 1e-3),
+    "spill_table_block": (lambda: I.random_nonsym(1500, seed=34), 512,
+                          dict(lanes_per_row=256, hash_slots=1024, heavy_weight=-1.0, spill_slots=16), 1e-3),
+    "stage_block_eps0": (lambda: I.grid2d_5pt(40, 40), 300,
+                         dict(lanes_per_row=256, hash_slots=1024, heavy_weight=-1.0), 0.0),
+}
+
+
+@pytest.mark.parametrize("prec", [64, 32])
+@pytest.mark.parametrize("case", sorted(RERUN_CASES))
+def test_overflow_rows_are_rerun(mc, case, prec):
+    make, N, gkw, eps = RERUN_CASES[case]
+    B = make()
+    (rp, col, val), res, _ = run(mc, B, seed=4, chains=N, delta=1e-4, eps=eps, prec=prec, **gkw)
+    print(f"[gpu] {case}: retries={res.stats.retries} H={res.stats.hash_slots} spilled={res.stats.spilled}",
+          flush=True)
+    assert res.stats.retries >= 1
+    orc, o = oracle_run(B, seed=4, chains=N, delta=1e-4, eps=eps, prec=prec)
+    assert orc["guard"] == 0
+    assert res.stats.transitions == orc["transitions"]
+    compare_spai((rp, col, val), orc, o.diag, N)
