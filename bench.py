@@ -80,6 +80,11 @@ def main():
     ap.add_argument("--prec", type=int, default=32, choices=[32, 64])
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--hash-slots", type=int, default=0)
+    ap.add_argument("--lanes", type=int, default=0)
+    ap.add_argument("--sketch-slots", type=int, default=0)
+    ap.add_argument("--heavy-weight", type=float, default=0.0)
+    ap.add_argument("--calib-copy", action="store_true",
+                    help="first run one plain 1 GiB device copy (reference for rocprofv3 byte counters)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: the Monte Carlo rows shard across GPUs without communication "
@@ -97,8 +102,15 @@ def main():
     x = torch.ones(B.n, dtype=torch.float64, device="cuda")
     y = torch.empty(B.n, dtype=torch.float64, device="cuda")
     p = mcmi.params(seed=seed, chains=args.chains, delta=delta, eps=eps, walk_prec=args.prec,
-                    hash_slots=args.hash_slots)
+                    hash_slots=args.hash_slots, lanes_per_row=args.lanes, sketch_slots=args.sketch_slots,
+                    heavy_weight=args.heavy_weight)
     torch.cuda.synchronize()
+    if args.calib_copy:
+        src = torch.ones(1 << 27, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
 
     def step():
         cdf = mcmi.Cdf(dB)
@@ -119,6 +131,8 @@ def main():
         retries = res.stats.retries
         nnz = res.nnz
         spilled = res.stats.spilled
+        lanes, hslots, sslots = res.stats.lanes_per_row, res.stats.hash_slots, res.stats.sketch_slots
+        tau, refined = res.stats.heavy_weight, res.stats.refined
         del cdf, res
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
@@ -148,7 +162,9 @@ def main():
         "config": {"workload": f"random nonsymmetric n={B.n}, 5-30 off-diagonals/row, ||C||_inf=0.7, "
                                f"{args.chains} chains/row, delta=1e-4, eps=1e-3, FP{args.prec} walks + FP64 sums",
                    "n": B.n, "nnz_B": B.nnz, "chains_per_row": args.chains, "transitions_per_step": trans[-1],
-                   "nnz_M": nnz, "spilled_contributions": spilled, "retries": retries},
+                   "nnz_M": nnz, "spilled_contributions": spilled, "retries": retries,
+                   "lanes_per_row": lanes, "hash_slots": hslots, "sketch_slots": sslots,
+                   "heavy_weight": tau, "rows_replayed": refined},
         "roofline": roofline,
     }
     if not args.no_cpu:

@@ -57,7 +57,7 @@ __device__ __forceinline__ int64_t next_task(const WalkArgs &a, int &queue) {
 }
 
 template <bool kF32>
-__device__ void walk_row(const WalkArgs &a, int64_t task, int32_t *keys, double *vals, int *spill_cnt,
+__device__ __forceinline__ void walk_row(const WalkArgs &a, int64_t task, int32_t *keys, double *vals, int *spill_cnt,
                          int32_t *skeys, double *svals, int32_t *sused) {
     const int lane = lane_id();
     const uint32_t hmask = (uint32_t)a.hash_slots - 1u;

@@ -155,7 +155,7 @@ __device__ __forceinline__ void refine_add(const WalkArgs &a, const RowCtx &rc, 
 // Run this lane's chains (c, c + stride, ...) in one phase. In kHeavy mode a
 // chain pauses (stays active, state kept) at its first light contribution.
 template <bool kF32, int kMode>
-__device__ void run_chains(const WalkArgs &a, const RowCtx &rc, Chain &st, int stride, bool count,
+__device__ __forceinline__ void run_chains(const WalkArgs &a, const RowCtx &rc, Chain &st, int stride, bool count,
                            unsigned long long &trans, unsigned long long &spilled, bool &spill_full,
                            bool &paused) {
     const uint32_t hmask = (uint32_t)a.hash_slots - 1u;
@@ -257,7 +257,7 @@ __device__ __forceinline__ int block_scan(int v, int *red, int *total) {
 }
 
 template <bool kF32, int kLPR, int kQ>
-__device__ void block_row(const WalkArgs &a, int64_t task, RowCtx &rc, int *ctl, float *redf, int *redi,
+__device__ __forceinline__ void block_row(const WalkArgs &a, int64_t task, RowCtx &rc, int *ctl, float *redf, int *redi,
                           unsigned long long &trans, unsigned long long &spilled, bool &spill_full,
                           bool &stage_full) {
     constexpr int H = kLPR * kQ;
@@ -313,37 +313,31 @@ __device__ void block_row(const WalkArgs &a, int64_t task, RowCtx &rc, int *ctl,
 
     // ------------------------------------------------------------ finalize
     const double nd = (double)N;
-    int32_t kk[kQ];
-    double mv[kQ];
-    int cnt = 0;
-#pragma unroll
-    for (int i = 0; i < kQ; ++i) {
-        const int s = tid * kQ + i;
+    // in-place compaction, one slot per lane per round: a survivor moves to
+    // position K + (survivors before it in this round) <= its own slot, and every
+    // lane has read its slot of the round before anyone writes
+    int K = 0;
+    for (int base = 0; base < H; base += kLPR) {
+        const int s = base + tid;
         const int32_t raw = rc.keys[s];
         const double acc = rc.vals[s];
-        kk[i] = kEmpty;
-        mv[i] = 0.0;
+        int32_t key = kEmpty;
+        double m = 0.0;
+        int keep = 0;
         if (raw != kEmpty) {
-            const int32_t key = (int32_t)((uint32_t)raw & ~kRBit);
+            key = (int32_t)((uint32_t)raw & ~kRBit);
             const double nhat = acc / nd;
-            const double m = nhat / a.diag[key];
+            m = nhat / a.diag[key];
             const double test = a.filter_m ? fabs(m) : fabs(nhat);
-            if (key == r || (nhat != 0.0 && test >= a.eps)) {
-                kk[i] = key;
-                mv[i] = m;
-                ++cnt;
-            }
+            keep = (key == r || (nhat != 0.0 && test >= a.eps)) ? 1 : 0;
         }
-    }
-    int K;
-    int pos = block_scan<kLPR>(cnt, redi, &K);
-#pragma unroll
-    for (int i = 0; i < kQ; ++i) {
-        if (kk[i] != kEmpty) {
-            rc.keys[pos] = kk[i];
-            rc.vals[pos] = mv[i];
-            ++pos;
+        int added;
+        const int pos = K + block_scan<kLPR>(keep, redi, &added);
+        if (keep) {
+            rc.keys[pos] = key;
+            rc.vals[pos] = m;
         }
+        K += added;
     }
     __syncthreads();
     // spilled columns
@@ -439,7 +433,7 @@ __device__ void block_row(const WalkArgs &a, int64_t task, RowCtx &rc, int *ctl,
 }
 
 template <bool kF32, int kLPR, int kQ>
-__global__ void __launch_bounds__(kLPR) k_walk_block(WalkArgs a) {
+__global__ void __launch_bounds__(kLPR, 4) k_walk_block(WalkArgs a) {
     constexpr int H = kLPR * kQ;
     extern __shared__ __align__(16) unsigned char smem[];
     const int tid = threadIdx.x;
