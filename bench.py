@@ -39,14 +39,14 @@ TRAFFIC_BYTES = None
 
 
 def algorithmic_bytes_per_transition(B, fp32: bool) -> float:
-    """Bytes one transition must read: the 16-byte record header of the state
-    (row, m, W, Shat32; +8 for Shat64 in FP64 mode) and one 8-byte {cum, target}
-    node per level of the breadth-first CDF tree, ceil(log2(m + 1)) levels. For
-    this workload the next state is a uniformly random column, so the mean is
-    taken over rows uniformly."""
-    m = np.diff(B.row_ptr) - 1
-    levels = np.ceil(np.log2(m + 1.0))
-    return float(np.mean((16.0 if fp32 else 24.0) + 8.0 * levels))
+    """Bytes one transition must read, independent of the record layout: the
+    state's header (row, m, W, Shat32: 16 B; +8 B Shat64 in FP64 mode), the CDF
+    words a binary search inspects ((ceil(log2 m) + 1) x 4 B) and the chosen
+    target (4 B). For this workload the next state is a uniformly random column,
+    so the mean is taken over rows uniformly."""
+    m = np.maximum(np.diff(B.row_ptr) - 1, 1)
+    probes = np.ceil(np.log2(m)) + 1.0
+    return float(np.mean((16.0 if fp32 else 24.0) + 4.0 * probes + 4.0))
 
 
 def cpu_baseline(B, chains, delta, eps, fp32, budget_s=12.0):

@@ -136,8 +136,8 @@ typedef struct {
 mcmi_status mcmi_build_cdf(const mcmi_csr_in *B, mcmi_cdf **out, void *stream);
 
 /* Copy the records to host memory (for inspection and tests; synchronises the
- * stream). rec_host receives rec_units * 4 uint32 words (rec_units from
- * mcmi_cdf_info), roff_host n record offsets (16-byte units) and diag_host the n
+ * stream). rec_host receives rec_units * 16 uint32 words (rec_units from
+ * mcmi_cdf_info), roff_host n record offsets (64-byte units) and diag_host the n
  * diagonal values b_ii. Any of the three may be NULL. */
 mcmi_status mcmi_cdf_download(const mcmi_cdf *cdf, uint32_t *rec_host, uint32_t *roff_host, double *diag_host,
                               void *stream);

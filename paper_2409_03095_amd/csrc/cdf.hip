@@ -86,7 +86,7 @@ __global__ void __launch_bounds__(256) k_fill(int64_t n, const int64_t *__restri
         const uint32_t m = mrow[r];
         const double d = diag[r];
         const uint32_t off = (uint32_t)roff64[r];
-        uint32_t *hdr = rec + (size_t)off * 4u;
+        uint32_t *hdr = rec + (size_t)off * kUnitWords;
         if (lane == 0) roff32[r] = off;
         if (m == 0) {
             if (lane == 0) {
@@ -149,42 +149,40 @@ __global__ void __launch_bounds__(256) k_fill(int64_t n, const int64_t *__restri
     }
 }
 
-// number of nodes in the subtree of breadth-first position x of a complete
-// binary tree with m nodes (positions 1..m)
-__device__ __forceinline__ uint32_t subtree_size(uint64_t x, uint64_t m) {
-    uint64_t lo = x, hi = x, cnt = 0;
-    while (lo <= m) {
-        cnt += (hi < m ? hi : m) - lo + 1;
-        lo = 2 * lo;
-        hi = 2 * hi + 1;
-    }
-    return (uint32_t)cnt;
-}
-
-// in-order rank (0-based) of breadth-first position e
-__device__ __forceinline__ uint32_t inorder_rank(uint32_t e, uint32_t m) {
-    const int depth = 31 - __builtin_clz(e);
-    uint32_t rank = 0;
-    for (int i = depth - 1; i >= 0; --i) {
-        const uint32_t anc = e >> (i + 1);
-        if ((e >> i) & 1u) rank += subtree_size(2ull * anc, m) + 1u;
-    }
-    return rank + subtree_size(2ull * e, m);
-}
-
-// Place the sorted nodes of each row at their breadth-first positions.
-__global__ void __launch_bounds__(256) k_eytzinger(int64_t n, const uint32_t *__restrict__ mrow,
-                                                   const uint32_t *__restrict__ roff32,
-                                                   const int64_t *__restrict__ cptr,
-                                                   const uint2 *__restrict__ sorted, uint32_t *__restrict__ rec) {
+// Write each row's group summary (header words 6..) and its groups of 8
+// {cum, target} from the sorted nodes; padding as described in common.hpp.
+__global__ void __launch_bounds__(256) k_groups(int64_t n, const uint32_t *__restrict__ mrow,
+                                                const uint32_t *__restrict__ roff32,
+                                                const int64_t *__restrict__ cptr,
+                                                const uint2 *__restrict__ sorted, uint32_t *__restrict__ rec) {
     const int lane = threadIdx.x & 63;
     const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
     const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
     for (int64_t r = wave; r < n; r += nwaves) {
         const uint32_t m = mrow[r];
+        const uint32_t G = record_groups(m), hb = header_units(m);
         const int64_t base = cptr[r];
-        uint2 *nodes = (uint2 *)(rec + (size_t)roff32[r] * 4u + kHdrWords);
-        for (uint32_t e = 1u + lane; e <= m; e += 64) nodes[e - 1] = sorted[base + inorder_rank(e, m)];
+        uint32_t *recp = rec + (size_t)roff32[r] * kUnitWords;
+        const uint32_t nsum = hb * kUnitWords - kHdrWords;
+        for (uint32_t i = lane; i < nsum; i += 64) {
+            uint32_t v = kPad;
+            if (i < G) {
+                const uint32_t last = (i + 1u) * kGroup < m ? (i + 1u) * kGroup - 1u : m - 1u;
+                v = sorted[base + last].x;
+            }
+            recp[kHdrWords + i] = v;
+        }
+        uint32_t *grp = recp + (size_t)hb * kUnitWords;
+        for (uint32_t q = lane; q < G * kUnitWords; q += 64) {
+            const uint32_t g = q / kUnitWords, w = q % kUnitWords;
+            const uint32_t k = g * kGroup + (w % kGroup);
+            uint32_t v;
+            if (w < (uint32_t)kGroup)
+                v = k < m ? sorted[base + k].x : kPad;
+            else
+                v = k < m ? sorted[base + k].y : 0u;
+            grp[q] = v;
+        }
     }
 }
 
@@ -260,15 +258,15 @@ extern "C" mcmi_status mcmi_build_cdf(const mcmi_csr_in *B, mcmi_cdf **out, void
     TRY(hipStreamSynchronize(s));
     if (hflags & kFlagCsr) return bail(MCMI_ERR_CSR, "mcmi_build_cdf: invalid CSR (row_ptr, column range or order)");
     if (hflags & kFlagZeroDiag) return bail(MCMI_ERR_ZERO_DIAG, "mcmi_build_cdf: missing or zero diagonal");
-    if (htot[0] >= (int64_t)kSignBit) return bail(MCMI_ERR_CAPACITY, "mcmi_build_cdf: records exceed 32 GiB");
+    if (htot[0] >= (int64_t)kSignBit) return bail(MCMI_ERR_CAPACITY, "mcmi_build_cdf: records exceed 128 GiB");
     cdf->rec_units = (uint64_t)htot[0];
     cdf->nnz_c = htot[1];
-    TRY(hipMalloc(&cdf->rec, (size_t)htot[0] * 16u + 16u));
+    TRY(hipMalloc(&cdf->rec, (size_t)htot[0] * kUnitWords * 4u + 64u));
     TRY(hipMalloc(&sorted, (size_t)(htot[1] > 0 ? htot[1] : 1) * sizeof(uint2)));
     k_fill<<<grid, 256, 0, s>>>(n, B->row_ptr_dev, B->col_dev, B->val_dev, cdf->diag, cdf->mrow, roff64, cptr,
                                 cdf->roff, cdf->rec, sorted, norm_bits);
     TRY(hipGetLastError());
-    k_eytzinger<<<grid, 256, 0, s>>>(n, cdf->mrow, cdf->roff, cptr, sorted, cdf->rec);
+    k_groups<<<grid, 256, 0, s>>>(n, cdf->mrow, cdf->roff, cptr, sorted, cdf->rec);
     TRY(hipGetLastError());
     unsigned long long hnorm = 0;
     TRY(hipMemcpyAsync(&hnorm, norm_bits, sizeof(hnorm), hipMemcpyDeviceToHost, s));
@@ -297,7 +295,7 @@ extern "C" mcmi_status mcmi_cdf_download(const mcmi_cdf *cdf, uint32_t *rec_host
     if (!cdf) return fail(MCMI_ERR_ARG, "mcmi_cdf_download: null cdf");
     hipStream_t s = (hipStream_t)stream;
     if (rec_host)
-        MCMI_HIP(hipMemcpyAsync(rec_host, cdf->rec, (size_t)cdf->rec_units * 16u, hipMemcpyDeviceToHost, s));
+        MCMI_HIP(hipMemcpyAsync(rec_host, cdf->rec, (size_t)cdf->rec_units * kUnitWords * 4u, hipMemcpyDeviceToHost, s));
     if (roff_host) MCMI_HIP(hipMemcpyAsync(roff_host, cdf->roff, (size_t)cdf->n * 4u, hipMemcpyDeviceToHost, s));
     if (diag_host) MCMI_HIP(hipMemcpyAsync(diag_host, cdf->diag, (size_t)cdf->n * 8u, hipMemcpyDeviceToHost, s));
     MCMI_HIP(hipStreamSynchronize(s));

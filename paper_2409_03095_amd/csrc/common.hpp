@@ -21,19 +21,33 @@ mcmi_status fail(mcmi_status st, const std::string &msg);
     } while (0)
 
 // ----------------------------------------------------------- record layout
-// One record per row s of C, 16-byte aligned, addressed by its offset in
-// 16-byte units (31 bits, so up to 32 GiB of records):
-//   word 0  row index s               word 1  m = entries of row s of C
+// One record per row s of C, 64-byte aligned, addressed by its offset in
+// 64-byte units (31 bits: up to 128 GiB of records). With m entries the row has
+// G = ceil(m / 8) groups of 8 consecutive entries (column order) and a header
+// block of hb = ceil((6 + G) / 16) units:
+//   word 0  row index s               word 1  m
 //   word 2  W = total integer weight  word 3  Shat_s as binary32
 //   words 4-5  Shat_s as binary64
-//   words 6 + 2(e-1), 7 + 2(e-1), e = 1..m: node e of the row's CDF in
-//   Eytzinger (breadth-first) order: {cum, target}, where cum is the inclusive
-//   integer prefix sum of the weights in column order and target is the
-//   record offset of the column's row with bit 31 set when c < 0.
+//   words 6 .. 6+G-1  the inclusive cum of each group's last entry (the group
+//                     summary); the rest of the block holds 0xFFFFFFFF
+// then G group units of 16 words: cum of the group's 8 entries (inclusive
+// integer prefix sums of the weights), then their targets: the record offset of
+// the column's row with bit 31 set when c < 0. The last group is padded with
+// cum = 0xFFFFFFFF and target 0. A draw t < W selects the first entry with
+// t < cum: the group is the number of summaries <= t, the entry inside it the
+// number of the group's cums <= t; both searches run in registers, so one step
+// reads one header unit and one group unit.
+constexpr int kUnitWords = 16;
 constexpr int kHdrWords = 6;
+constexpr int kGroup = 8;
 constexpr uint32_t kSignBit = 0x80000000u;
+constexpr uint32_t kPad = 0xFFFFFFFFu;
 
-__host__ __device__ inline uint32_t record_units(uint32_t m) { return (kHdrWords + 2u * m + 3u) / 4u; }
+__host__ __device__ inline uint32_t record_groups(uint32_t m) { return (m + kGroup - 1u) / kGroup; }
+__host__ __device__ inline uint32_t header_units(uint32_t m) {
+    return (kHdrWords + record_groups(m) + kUnitWords - 1u) / kUnitWords;
+}
+__host__ __device__ inline uint32_t record_units(uint32_t m) { return header_units(m) + record_groups(m); }
 
 // Error flags raised by device-side validation (bit set).
 enum : uint32_t {
@@ -142,8 +156,8 @@ struct mcmi_cdf {
     int64_t nnz_c = 0;
     double norm_inf = 0.0;
     uint64_t rec_units = 0;
-    uint32_t *rec = nullptr;       // records, 4 words per unit
-    uint32_t *roff = nullptr;      // n: record offset (16-byte units) of each row
+    uint32_t *rec = nullptr;       // records, 16 words per unit
+    uint32_t *roff = nullptr;      // n: record offset (64-byte units) of each row
     double *diag = nullptr;        // n: b_ii
     uint32_t *mrow = nullptr;      // n: entries of each row of C
 };

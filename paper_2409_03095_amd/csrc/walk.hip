@@ -14,9 +14,9 @@
 //  * each lane runs one chain at a time and starts the row's next unstarted chain
 //    as soon as its chain stops, so short and long chains do not wait for each
 //    other;
-//  * a step reads the 16-byte record header of the current state, draws one
-//    Philox word, and descends the row's CDF in breadth-first (Eytzinger) order,
-//    whose first levels share the header's cache line;
+//  * a step reads the 64-byte header unit of the current state, draws one
+//    Philox word, picks the group of 8 entries from the header's group summaries
+//    and the entry from that group's 64-byte unit: two dependent requests;
 //  * contributions go to an open-addressing hash per wave in LDS (key = column,
 //    value = float64 sum, LDS float64 atomics); a full neighbourhood spills to a
 //    per-wave hash in HBM;
@@ -83,10 +83,10 @@ __device__ __forceinline__ void walk_row(const WalkArgs &a, int64_t task, int32_
 
     while (__any(active)) {
         if (active) {
-            const uint32_t *recp = a.rec + (size_t)off * 4u;
-            const uint4 h = *(const uint4 *)recp;  // row, m, W, Shat32
-            double s64 = 0.0;
-            if (!kF32) s64 = *(const double *)(recp + 4);
+            StepHdr H;
+            load_header(a.rec, off, H);
+            const uint4 h = H.h0;  // row, m, W, Shat32
+            const double s64 = kF32 ? 0.0 : header_shat64(H);
             if (j > 0) {
                 const int32_t key = (int32_t)h.x;
                 const double w = kF32 ? (double)w32 : w64;
@@ -124,15 +124,7 @@ __device__ __forceinline__ void walk_row(const WalkArgs &a, int64_t task, int32_
                 blk.y = blk.z;
                 blk.z = blk.w;
                 const uint32_t t = __umulhi(u, h.z);
-                const uint2 *nodes = (const uint2 *)(recp + kHdrWords);
-                const uint32_t m = h.y;
-                uint32_t e = 1, tgt = 0;
-                while (e <= m) {
-                    const uint2 nd = nodes[e - 1];
-                    const bool left = t < nd.x;
-                    tgt = left ? nd.y : tgt;
-                    e = 2u * e + (left ? 0u : 1u);
-                }
+                const uint32_t tgt = draw_target(a.rec, off, H, t);
                 const bool neg = (tgt & kSignBit) != 0u;
                 if (kF32)
                     w32 = neg ? -wn32 : wn32;

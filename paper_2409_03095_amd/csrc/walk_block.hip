@@ -162,10 +162,10 @@ __device__ __forceinline__ void run_chains(const WalkArgs &a, const RowCtx &rc, 
     const uint32_t smask = (uint32_t)a.spill_slots - 1u;
     paused = false;
     while (st.active) {
-        const uint32_t *recp = a.rec + (size_t)st.off * 4u;
-        const uint4 h = *(const uint4 *)recp;
-        double s64 = 0.0;
-        if (!kF32) s64 = *(const double *)(recp + 4);
+        StepHdr H;
+        load_header(a.rec, st.off, H);
+        const uint4 h = H.h0;  // row, m, W, Shat32
+        const double s64 = kF32 ? 0.0 : header_shat64(H);
         if (st.j > 0) {
             const int32_t key = (int32_t)h.x;
             const double w = kF32 ? (double)st.w32 : st.w64;
@@ -205,15 +205,7 @@ __device__ __forceinline__ void run_chains(const WalkArgs &a, const RowCtx &rc, 
             st.blk.y = st.blk.z;
             st.blk.z = st.blk.w;
             const uint32_t t = __umulhi(u, h.z);
-            const uint2 *nodes = (const uint2 *)(recp + kHdrWords);
-            const uint32_t m = h.y;
-            uint32_t e = 1, tgt = 0;
-            while (e <= m) {
-                const uint2 nd = nodes[e - 1];
-                const bool left = t < nd.x;
-                tgt = left ? nd.y : tgt;
-                e = 2u * e + (left ? 0u : 1u);
-            }
+            const uint32_t tgt = draw_target(a.rec, st.off, H, t);
             const bool neg = (tgt & kSignBit) != 0u;
             if (kF32)
                 st.w32 = neg ? -wn32 : wn32;

@@ -145,7 +145,7 @@ class Cdf:
         self.n, self.nnz_c, self.norm_inf, self.rec_units = n.value, nnz_c.value, nrm.value, units.value
 
     def download(self, stream=None):
-        rec = np.zeros(self.rec_units * 4, dtype=np.uint32)
+        rec = np.zeros(self.rec_units * 16, dtype=np.uint32)
         roff = np.zeros(self.n, dtype=np.uint32)
         diag = np.zeros(self.n, dtype=np.float64)
         _check(_lib.mcmi_cdf_download(self._h, rec.ctypes.data_as(_v), roff.ctypes.data_as(_v),

@@ -5,34 +5,35 @@ U64 = 2.0 ** -53
 
 
 def decode_records(rec, roff, n):
-    """Decode the library's packed records into per-row (row, m, W, S32, S64,
-    cum[], col[], neg[]) in column order (in-order walk of the breadth-first tree)."""
+    """Decode the library's records (64-byte units: header unit with the group
+    summaries, then groups of 8 {cum, target}) into per-row (row, m, W, S32, S64,
+    cum[], col[], neg[]) in column order, checking the summaries and padding."""
     inv = {int(o): i for i, o in enumerate(roff)}
     out = []
     for i in range(n):
-        base = int(roff[i]) * 4
+        base = int(roff[i]) * 16
         row, m, W = int(rec[base]), int(rec[base + 1]), int(rec[base + 2])
         s32 = rec[base + 3:base + 4].view(np.float32)[0]
         s64 = rec[base + 4:base + 6].view(np.float64)[0]
-        nodes = rec[base + 6:base + 6 + 2 * m].reshape(m, 2) if m else np.zeros((0, 2), np.uint32)
-        order = []
-
-        def inorder(e):
-            stack, cur = [], e
-            while stack or cur <= m:
-                while cur <= m:
-                    stack.append(cur)
-                    cur = 2 * cur
-                cur = stack.pop()
-                order.append(cur)
-                cur = 2 * cur + 1
-
+        G = (m + 7) // 8
+        hb = (6 + G + 15) // 16
+        summ = rec[base + 6:base + 16 * hb].astype(np.int64)
+        cum, tgt = [], []
+        for g in range(G):
+            u = base + 16 * (hb + g)
+            cum.extend(int(x) for x in rec[u:u + 8])
+            tgt.extend(int(x) for x in rec[u + 8:u + 16])
+        cum = np.array(cum[:m] if m else [], dtype=np.int64)
+        tg = tgt[:m]
         if m:
-            inorder(1)
-        cum = np.array([int(nodes[e - 1, 0]) for e in order], dtype=np.int64)
-        tgt = [int(nodes[e - 1, 1]) for e in order]
-        col = np.array([inv[t & 0x7FFFFFFF] for t in tgt], dtype=np.int64)
-        neg = np.array([(t >> 31) & 1 for t in tgt], dtype=bool)
+            last = [cum[min(8 * g + 7, m - 1)] for g in range(G)]
+            assert list(summ[:G]) == last, ("group summaries", i)
+            assert all(x == 0xFFFFFFFF for x in summ[G:]), ("summary padding", i)
+            tail = rec[base + 16 * (hb + G - 1):base + 16 * (hb + G)]
+            k = m - 8 * (G - 1)
+            assert all(x == 0xFFFFFFFF for x in tail[k:8]), ("cum padding", i)
+        col = np.array([inv[t & 0x7FFFFFFF] for t in tg], dtype=np.int64)
+        neg = np.array([(t >> 31) & 1 for t in tg], dtype=bool)
         out.append((row, m, W, s32, s64, cum, col, neg))
     return out
 
