@@ -163,6 +163,25 @@ mcmi_status mcmi_spai(const mcmi_cdf *cdf, const mcmi_params *p, const int32_t *
 mcmi_status mcmi_apply(const mcmi_csr_out *M, int64_t n_cols, const double *x_dev, double *y_dev,
                        void *stream);
 
+/* ---------------------------------------------------- learned allocation */
+
+/* Eight binary32 features per row of C (feat_dev: n x 8, row-major), the input of
+ * the chain-allocation network, computed from the records (p_ij = w_ij / W_i the
+ * quantized transition probabilities, S = Shat):
+ *   f0 ln max(m_i, 1), f1 S_i, f2 max_j |chat_ij|, f3 sum_j p_ij S_j, f4 max_j S_j,
+ *   f5 sum_j p_ij m_j, f6 |sum_j chat_ij| / S_i, f7 min(L_max, ln delta / ln S_i).
+ * L_max as in mcmi_params (max_len, or derived from delta). Asynchronous. */
+mcmi_status mcmi_row_features(const mcmi_cdf *cdf, double delta, int32_t max_len, float *feat_dev, void *stream);
+
+/* Pilot run for the allocation target: pilot_chains chains per row on Philox
+ * streams whose tag has bit 31 set (independent of the main walks). Writes, per
+ * row, var_dev = mean_c ||X_c||^2 - ||mean_c X_c||^2 (X_c = chain c's row
+ * estimate, revisits merged; the total variance of one chain, eq. (2)) and
+ * len_dev = mean transitions per chain (both float64, n). Uses seed, delta,
+ * walk_prec, max_len and stream_tag of p. Synchronises the stream. */
+mcmi_status mcmi_pilot_variance(const mcmi_cdf *cdf, const mcmi_params *p, int32_t pilot_chains, double *var_dev,
+                                double *len_dev, void *stream);
+
 /* Copy M into caller-owned device buffers (row_ptr n+1, col nnz, val nnz). */
 mcmi_status mcmi_csr_copy(const mcmi_csr_out *M, int64_t *row_ptr_dev, int32_t *col_dev,
                           double *val_dev, void *stream);

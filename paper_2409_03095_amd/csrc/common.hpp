@@ -139,6 +139,10 @@ __device__ __forceinline__ T wave_incl_scan(T v) {
     return v;
 }
 
+// Shared host helpers (api.hip)
+int derive_lmax(double norm_inf, double delta, int max_len);
+int device_cus();
+
 // --------------------------------------------------------------- scans
 // Exclusive prefix sum of n int64 values (out may alias in); writes the total
 // to *total_dev (device). Temporary memory comes from `tmp` (>= scan_tmp_bytes(n)).

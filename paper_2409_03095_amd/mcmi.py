@@ -72,6 +72,8 @@ _sig = {
     "mcmi_spai": [_v, _P(Params), _v, _v, ctypes.c_int64, _P(CsrOut), _P(Stats), _v],
     "mcmi_apply": [_P(CsrOut), ctypes.c_int64, _v, _v, _v],
     "mcmi_csr_copy": [_P(CsrOut), _v, _v, _v, _v],
+    "mcmi_row_features": [_v, ctypes.c_double, ctypes.c_int32, _v, _v],
+    "mcmi_pilot_variance": [_v, _P(Params), ctypes.c_int32, _v, _v, _v],
 }
 for _name, _args in _sig.items():
     getattr(_lib, _name).argtypes = _args
@@ -84,7 +86,8 @@ _lib.mcmi_last_error.restype = ctypes.c_char_p
 _lib.mcmi_version.restype = ctypes.c_char_p
 
 EXPORTED = ["mcmi_build_cdf", "mcmi_cdf_info", "mcmi_cdf_download", "mcmi_spai", "mcmi_apply",
-            "mcmi_csr_copy", "mcmi_cdf_free", "mcmi_csr_free", "mcmi_last_error", "mcmi_version"]
+            "mcmi_csr_copy", "mcmi_cdf_free", "mcmi_csr_free", "mcmi_last_error", "mcmi_version",
+            "mcmi_row_features", "mcmi_pilot_variance"]
 
 
 def _check(st):
@@ -230,3 +233,22 @@ def spai(cdf: Cdf, p: Params, chains_per_row=None, rows=None, stream=None) -> Sp
     _check(_lib.mcmi_spai(cdf._h, ctypes.byref(p), _ptr(chains_per_row), _ptr(rows), ctypes.c_int64(n_rows),
                           ctypes.byref(out), ctypes.byref(st), _stream(stream)))
     return SpaiResult(out, st, cdf.n)
+
+
+def row_features(cdf: Cdf, delta: float, max_len: int = 0, stream=None):
+    """mcmi_row_features: (n, 8) float32 device tensor."""
+    import torch
+    f = torch.empty((cdf.n, 8), dtype=torch.float32, device="cuda")
+    _check(_lib.mcmi_row_features(cdf._h, ctypes.c_double(delta), ctypes.c_int32(max_len), _ptr(f),
+                                  _stream(stream)))
+    return f
+
+
+def pilot_variance(cdf: Cdf, p: Params, pilot_chains: int = 64, stream=None):
+    """mcmi_pilot_variance: per-row (variance, mean length), float64 device tensors."""
+    import torch
+    var = torch.empty(cdf.n, dtype=torch.float64, device="cuda")
+    ln = torch.empty(cdf.n, dtype=torch.float64, device="cuda")
+    _check(_lib.mcmi_pilot_variance(cdf._h, ctypes.byref(p), ctypes.c_int32(pilot_chains), _ptr(var), _ptr(ln),
+                                    _stream(stream)))
+    return var, ln
