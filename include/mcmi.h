@@ -182,6 +182,47 @@ mcmi_status mcmi_row_features(const mcmi_cdf *cdf, double delta, int32_t max_len
 mcmi_status mcmi_pilot_variance(const mcmi_cdf *cdf, const mcmi_params *p, int32_t pilot_chains, double *var_dev,
                                 double *len_dev, void *stream);
 
+/* The allocation network: 8 -> 64 -> 64 -> 1 ReLU MLP (4,801 parameters) that maps
+ * z-scored row features to the log of a row's chain share. Parameters are FP32
+ * masters packed as W1 (64 x 8, row = output), b1 (64), W2 (64 x 64), b2 (64),
+ * w3 (64), b3 (1); the forward and backward use BF16 copies of W1, W2, w3 with
+ * FP32 accumulation (64 x 64 products on the matrix cores). Library-owned. */
+typedef struct mcmi_mlp mcmi_mlp;
+mcmi_status mcmi_mlp_create(mcmi_mlp **out);
+void mcmi_mlp_free(mcmi_mlp *net);
+/* Load parameters (4801 floats) and, if non-NULL, the feature normalisation
+ * (mean[8] then 1/std[8]); reset_optimizer != 0 clears the Adam state. Synchronises. */
+mcmi_status mcmi_mlp_set_params(mcmi_mlp *net, const float *params_host, const float *norm_host,
+                                int32_t reset_optimizer);
+/* Copy parameters, normalisation, Adam moments and step count to the host (each
+ * pointer nullable; a checkpoint). Synchronises the device. */
+mcmi_status mcmi_mlp_get_params(const mcmi_mlp *net, float *params_host, float *norm_host, float *adam_m_host,
+                                float *adam_v_host, int64_t *adam_step);
+mcmi_status mcmi_mlp_set_adam_state(mcmi_mlp *net, const float *adam_m_host, const float *adam_v_host,
+                                    int64_t adam_step);
+/* Normalisation from the training features (feat_dev n x 8): per-column mean and
+ * 1/std (population std; 1 for a constant column). Asynchronous. */
+mcmi_status mcmi_mlp_fit_normalization(mcmi_mlp *net, const float *feat_dev, int64_t n, void *stream);
+/* out_dev[r] = network(feat_dev[r]) for n rows. Asynchronous. */
+mcmi_status mcmi_mlp_predict(const mcmi_mlp *net, const float *feat_dev, int64_t n, float *out_dev, void *stream);
+/* Mean-squared-error gradient over the samples idx_dev[0..batch) of (feat_dev,
+ * target_dev) at the current parameters, to grad_host (4801 floats) and the loss
+ * to loss_host (for checks against a reference). Synchronises. */
+mcmi_status mcmi_mlp_gradient(mcmi_mlp *net, const float *feat_dev, const float *target_dev, const int32_t *idx_dev,
+                              int64_t batch, int64_t n, float *grad_host, float *loss_host, void *stream);
+/* `steps` Adam steps (beta1 0.9, beta2 0.999, eps 1e-8, learning rate lr) on
+ * minibatches of `batch` samples drawn with replacement by Philox (key = seed,
+ * counter = (step, slot, 'MLP', 0)); loss_host (nullable) receives each step's
+ * loss. Synchronises at the end. */
+mcmi_status mcmi_mlp_train(mcmi_mlp *net, const float *feat_dev, const float *target_dev, int64_t n, int32_t steps,
+                           int32_t batch, float lr, uint64_t seed, float *loss_host, void *stream);
+/* Chains per row from predicted log shares: N_r = max(1, rint(lambda exp(pred_r)))
+ * with lambda (bisection) giving the largest sum_r N_r cost_r <= budget; any
+ * non-finite prediction selects the uniform allocation max(1, budget / sum cost)
+ * (*fallback_host = 1). cost_dev: int32 per-row chain cost (>= 1). Synchronises. */
+mcmi_status mcmi_allocate(const float *pred_dev, const int32_t *cost_dev, int64_t n, int64_t budget,
+                          int32_t *chains_dev, double *lambda_host, int32_t *fallback_host, void *stream);
+
 /* Copy M into caller-owned device buffers (row_ptr n+1, col nnz, val nnz). */
 mcmi_status mcmi_csr_copy(const mcmi_csr_out *M, int64_t *row_ptr_dev, int32_t *col_dev,
                           double *val_dev, void *stream);

@@ -74,12 +74,24 @@ _sig = {
     "mcmi_csr_copy": [_P(CsrOut), _v, _v, _v, _v],
     "mcmi_row_features": [_v, ctypes.c_double, ctypes.c_int32, _v, _v],
     "mcmi_pilot_variance": [_v, _P(Params), ctypes.c_int32, _v, _v, _v],
+    "mcmi_mlp_create": [_P(_v)],
+    "mcmi_mlp_set_params": [_v, _v, _v, ctypes.c_int32],
+    "mcmi_mlp_get_params": [_v, _v, _v, _v, _v, _P(ctypes.c_int64)],
+    "mcmi_mlp_set_adam_state": [_v, _v, _v, ctypes.c_int64],
+    "mcmi_mlp_fit_normalization": [_v, _v, ctypes.c_int64, _v],
+    "mcmi_mlp_predict": [_v, _v, ctypes.c_int64, _v, _v],
+    "mcmi_mlp_gradient": [_v, _v, _v, _v, ctypes.c_int64, ctypes.c_int64, _v, _P(ctypes.c_float), _v],
+    "mcmi_mlp_train": [_v, _v, _v, ctypes.c_int64, ctypes.c_int32, ctypes.c_int32, ctypes.c_float, ctypes.c_uint64,
+                       _v, _v],
+    "mcmi_allocate": [_v, _v, ctypes.c_int64, ctypes.c_int64, _v, _P(ctypes.c_double), _P(ctypes.c_int32), _v],
 }
 for _name, _args in _sig.items():
     getattr(_lib, _name).argtypes = _args
     getattr(_lib, _name).restype = ctypes.c_int
 _lib.mcmi_cdf_free.argtypes = [_v]
 _lib.mcmi_cdf_free.restype = None
+_lib.mcmi_mlp_free.argtypes = [_v]
+_lib.mcmi_mlp_free.restype = None
 _lib.mcmi_csr_free.argtypes = [_P(CsrOut)]
 _lib.mcmi_csr_free.restype = None
 _lib.mcmi_last_error.restype = ctypes.c_char_p
@@ -87,7 +99,9 @@ _lib.mcmi_version.restype = ctypes.c_char_p
 
 EXPORTED = ["mcmi_build_cdf", "mcmi_cdf_info", "mcmi_cdf_download", "mcmi_spai", "mcmi_apply",
             "mcmi_csr_copy", "mcmi_cdf_free", "mcmi_csr_free", "mcmi_last_error", "mcmi_version",
-            "mcmi_row_features", "mcmi_pilot_variance"]
+            "mcmi_row_features", "mcmi_pilot_variance", "mcmi_mlp_create", "mcmi_mlp_free",
+            "mcmi_mlp_set_params", "mcmi_mlp_get_params", "mcmi_mlp_set_adam_state", "mcmi_mlp_fit_normalization",
+            "mcmi_mlp_predict", "mcmi_mlp_gradient", "mcmi_mlp_train", "mcmi_allocate"]
 
 
 def _check(st):
@@ -252,3 +266,82 @@ def pilot_variance(cdf: Cdf, p: Params, pilot_chains: int = 64, stream=None):
     _check(_lib.mcmi_pilot_variance(cdf._h, ctypes.byref(p), ctypes.c_int32(pilot_chains), _ptr(var), _ptr(ln),
                                     _stream(stream)))
     return var, ln
+
+
+MLP_PARAMS = 4801
+
+
+class Mlp:
+    """The allocation network (library-owned parameters and Adam state)."""
+
+    def __init__(self):
+        self._h = ctypes.c_void_p()
+        _check(_lib.mcmi_mlp_create(ctypes.byref(self._h)))
+
+    def set_params(self, params, norm=None, reset_optimizer=True):
+        p = np.ascontiguousarray(params, dtype=np.float32)
+        assert p.size == MLP_PARAMS
+        nm = None if norm is None else np.ascontiguousarray(norm, dtype=np.float32)
+        _check(_lib.mcmi_mlp_set_params(self._h, p.ctypes.data_as(_v), None if nm is None else nm.ctypes.data_as(_v),
+                                        int(bool(reset_optimizer))))
+
+    def get_params(self):
+        p = np.zeros(MLP_PARAMS, np.float32)
+        nm = np.zeros(16, np.float32)
+        m = np.zeros(MLP_PARAMS, np.float32)
+        v = np.zeros(MLP_PARAMS, np.float32)
+        t = ctypes.c_int64()
+        _check(_lib.mcmi_mlp_get_params(self._h, p.ctypes.data_as(_v), nm.ctypes.data_as(_v), m.ctypes.data_as(_v),
+                                        v.ctypes.data_as(_v), ctypes.byref(t)))
+        return {"params": p, "norm": nm, "adam_m": m, "adam_v": v, "step": t.value}
+
+    def set_adam_state(self, m, v, step):
+        m = np.ascontiguousarray(m, np.float32)
+        v = np.ascontiguousarray(v, np.float32)
+        _check(_lib.mcmi_mlp_set_adam_state(self._h, m.ctypes.data_as(_v), v.ctypes.data_as(_v), int(step)))
+
+    def fit_normalization(self, feat, stream=None):
+        _check(_lib.mcmi_mlp_fit_normalization(self._h, _ptr(feat), ctypes.c_int64(feat.shape[0]), _stream(stream)))
+
+    def predict(self, feat, stream=None):
+        import torch
+        out = torch.empty(feat.shape[0], dtype=torch.float32, device=feat.device)
+        _check(_lib.mcmi_mlp_predict(self._h, _ptr(feat), ctypes.c_int64(feat.shape[0]), _ptr(out), _stream(stream)))
+        return out
+
+    def gradient(self, feat, target, idx, stream=None):
+        g = np.zeros(MLP_PARAMS, np.float32)
+        loss = ctypes.c_float()
+        _check(_lib.mcmi_mlp_gradient(self._h, _ptr(feat), _ptr(target), _ptr(idx), ctypes.c_int64(idx.numel()),
+                                      ctypes.c_int64(feat.shape[0]), g.ctypes.data_as(_v), ctypes.byref(loss),
+                                      _stream(stream)))
+        return g, loss.value
+
+    def train(self, feat, target, steps, batch=4096, lr=1e-3, seed=0, stream=None):
+        losses = np.zeros(max(steps, 1), np.float32)
+        _check(_lib.mcmi_mlp_train(self._h, _ptr(feat), _ptr(target), ctypes.c_int64(feat.shape[0]),
+                                   ctypes.c_int32(steps), ctypes.c_int32(batch), ctypes.c_float(lr),
+                                   ctypes.c_uint64(seed), losses.ctypes.data_as(_v), _stream(stream)))
+        return losses[:steps]
+
+    def free(self):
+        if self._h:
+            _lib.mcmi_mlp_free(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+
+def allocate(pred, cost, budget, stream=None):
+    """mcmi_allocate: chains per row (int32 device tensor), lambda, fallback flag."""
+    import torch
+    chains = torch.empty(pred.numel(), dtype=torch.int32, device=pred.device)
+    lam = ctypes.c_double()
+    fb = ctypes.c_int32()
+    _check(_lib.mcmi_allocate(_ptr(pred), _ptr(cost), ctypes.c_int64(pred.numel()), ctypes.c_int64(int(budget)),
+                              _ptr(chains), ctypes.byref(lam), ctypes.byref(fb), _stream(stream)))
+    return chains, lam.value, bool(fb.value)

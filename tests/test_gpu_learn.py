@@ -49,3 +49,108 @@ def test_pilot_variance(mc, name, prec):
     assert np.array_equal(ln, rl)
     scale = np.maximum(np.abs(rv), 1e-300)
     assert np.all(np.abs(var - rv) <= 1e-10 * scale + 1e-12), np.max(np.abs(var - rv) / scale)
+
+
+# ---------------------------------------------------------------- MLP (a13)
+def flat(p):
+    return np.concatenate([p[k].reshape(-1) for k, _ in O.MLP_SHAPES]).astype(np.float32)
+
+
+def unflat(v):
+    out, o = {}, 0
+    for k, shape in O.MLP_SHAPES:
+        size = int(np.prod(shape))
+        out[k] = v[o:o + size].reshape(shape)
+        o += size
+    return out
+
+
+def bf16_params(p):
+    q = {k: v.astype(np.float64) for k, v in p.items()}
+    for k in ("w1", "w2", "w3"):
+        q[k] = O.bf16_round(p[k]).astype(np.float64)
+    return q
+
+
+@pytest.fixture(scope="module")
+def net_case():
+    rng = np.random.default_rng(5)
+    p = O.mlp_init(11)
+    for k in ("b1", "b2", "b3"):
+        p[k] = rng.normal(0, 0.1, size=p[k].shape).astype(np.float32)
+    n = 1000  # not a multiple of the 16-sample tile
+    x = rng.normal(1.0, 2.0, size=(n, 8)).astype(np.float32)
+    mean = x.mean(axis=0).astype(np.float32)
+    inv = (1.0 / x.std(axis=0)).astype(np.float32)
+    t = rng.normal(0, 1, size=n).astype(np.float32)
+    xn = O.bf16_round(((x - mean) * inv).astype(np.float32)).astype(np.float64)
+    return p, x, mean, inv, t, xn
+
+
+def test_mlp_forward_matches_reference(mc, net_case):
+    p, x, mean, inv, t, xn = net_case
+    net = mc.Mlp()
+    net.set_params(flat(p), np.concatenate([mean, inv]))
+    y = net.predict(torch.from_numpy(x).cuda()).cpu().numpy()
+    ref, _ = O.mlp_forward(bf16_params(p), xn)
+    err = np.abs(y - ref)
+    assert err.max() <= 2e-2 * np.abs(ref).max(), (err.max(), np.abs(ref).max())
+    assert np.linalg.norm(y - ref) <= 1e-2 * np.linalg.norm(ref)
+
+
+def test_mlp_gradient_matches_reference(mc, net_case):
+    """BF16 forward/backward on the matrix cores vs the FP64 reference on the same
+    BF16-rounded weights and inputs: relative error in norm per parameter block."""
+    p, x, mean, inv, t, xn = net_case
+    net = mc.Mlp()
+    net.set_params(flat(p), np.concatenate([mean, inv]))
+    idx = np.random.default_rng(3).choice(x.shape[0], 333, replace=False).astype(np.int32)
+    g, loss = net.gradient(torch.from_numpy(x).cuda(), torch.from_numpy(t).cuda(), torch.from_numpy(idx).cuda())
+    rl, rg = O.mlp_loss_grad(bf16_params(p), xn[idx], t[idx])
+    assert abs(loss - rl) <= 1e-2 * rl
+    gg = unflat(g)
+    for k, _ in O.MLP_SHAPES:
+        num = np.linalg.norm(gg[k].reshape(-1) - rg[k].reshape(-1))
+        den = np.linalg.norm(rg[k].reshape(-1))
+        assert num <= 2e-2 * den + 1e-7, (k, num / max(den, 1e-30))
+
+
+def test_mlp_training_reduces_loss_and_checkpoints(mc):
+    rng = np.random.default_rng(8)
+    n = 20000
+    x = rng.normal(0, 1, size=(n, 8)).astype(np.float32)
+    t = (np.sin(x[:, 0]) + 0.5 * x[:, 1] * x[:, 2] - 0.3 * np.abs(x[:, 3])).astype(np.float32)
+    net = mc.Mlp()
+    net.set_params(flat(O.mlp_init(2)))
+    xd, td = torch.from_numpy(x).cuda(), torch.from_numpy(t).cuda()
+    net.fit_normalization(xd)
+    losses = net.train(xd, td, steps=600, batch=1024, lr=3e-3, seed=4)
+    assert np.all(np.isfinite(losses))
+    assert losses[-50:].mean() < 0.25 * losses[:10].mean(), (losses[:10].mean(), losses[-50:].mean())
+    ck = net.get_params()
+    assert ck["step"] == 600
+    net2 = mc.Mlp()
+    net2.set_params(ck["params"], ck["norm"])
+    net2.set_adam_state(ck["adam_m"], ck["adam_v"], ck["step"])
+    y1 = net.predict(xd).cpu().numpy()
+    y2 = net2.predict(xd).cpu().numpy()
+    assert np.array_equal(y1, y2)
+
+
+def test_allocation_matches_reference(mc):
+    rng = np.random.default_rng(9)
+    n = 5000
+    pred = rng.normal(0, 0.7, size=n).astype(np.float32)
+    cost = rng.integers(5, 40, size=n).astype(np.int32)
+    budget = int(24 * cost.sum())
+    chains, lam, fb = mc.allocate(torch.from_numpy(pred).cuda(), torch.from_numpy(cost).cuda(), budget)
+    chains = chains.cpu().numpy()
+    assert not fb
+    ref, rlam = O.allocate(pred.astype(np.float64), cost, budget)
+    assert (chains.astype(np.int64) * cost).sum() <= budget
+    assert abs(lam - rlam) <= 1e-9 * rlam
+    assert np.mean(chains != ref) < 1e-3 and np.max(np.abs(chains - ref)) <= 1
+    bad = pred.copy()
+    bad[7] = np.nan
+    chains, lam, fb = mc.allocate(torch.from_numpy(bad).cuda(), torch.from_numpy(cost).cuda(), budget)
+    assert fb and np.all(chains.cpu().numpy() == budget // cost.sum())
