@@ -83,6 +83,11 @@ def main():
     ap.add_argument("--lanes", type=int, default=0)
     ap.add_argument("--sketch-slots", type=int, default=0)
     ap.add_argument("--heavy-weight", type=float, default=0.0)
+    ap.add_argument("--learned", action="store_true",
+                    help="learned vs uniform chains to ||I-MB||_F/sqrt(n) <= 0.3 (allocation-network workload)")
+    ap.add_argument("--train-mats", type=int, default=2000)
+    ap.add_argument("--heldout", type=int, default=1024, help="held-out grid side (n = side^2)")
+    ap.add_argument("--train-steps", type=int, default=3000)
     ap.add_argument("--calib-copy", action="store_true",
                     help="first run one plain 1 GiB device copy (reference for rocprofv3 byte counters)")
     args = ap.parse_args()
@@ -95,6 +100,9 @@ def main():
 
     from paper_2409_03095_amd import inputs as I
     from paper_2409_03095_amd import mcmi
+
+    if args.learned:
+        return learned_main(args)
 
     delta, eps, seed = 1e-4, 1e-3, 0
     B = I.cfg2(args.n)
@@ -169,6 +177,38 @@ def main():
     }
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(B, args.chains, delta, eps, args.prec == 32)
+    print(json.dumps(out), flush=True)
+
+
+def learned_main(args):
+    """Allocation-network workload: train on the 5-point family with pilot-run
+    variance, then time-to-quality of learned vs uniform chains on a held-out
+    instance (delta = eps = 1e-3, FP64 walks)."""
+    from paper_2409_03095_amd import inputs as I
+    from paper_2409_03095_amd import learned as L
+    delta, eps = 1e-3, 1e-3
+    t0 = time.perf_counter()
+    mats = I.cfg4_train(args.train_mats)
+    print(f"[learned] generated {len(mats)} training matrices in {time.perf_counter() - t0:.1f} s", flush=True)
+    net, info = L.train_allocator(mats, delta, steps=args.train_steps)
+    print(f"[learned] trained: {json.dumps(info)}", flush=True)
+    B = I.cfg4_heldout(args.heldout)
+    budgets = [2, 3, 4, 6, 8, 12, 16, 24, 32]
+    pts = L.compare(net, B, delta, eps, budgets)
+    for p in pts:
+        print(f"[learned] budget {p['mean_chains']}: learned r={p['learned']['r_norm']:.4f} "
+              f"T={p['learned']['transitions']} | uniform r={p['uniform']['r_norm']:.4f} "
+              f"T={p['uniform']['transitions']}", flush=True)
+    lt = L.crossing([p["learned"] for p in pts], "transitions")
+    ut = L.crossing([p["uniform"] for p in pts], "transitions")
+    ls = L.crossing([p["learned"] for p in pts], "wall_s")
+    us = L.crossing([p["uniform"] for p in pts], "wall_s")
+    out = {"metric": METRIC, "value": lt, "unit": "transitions to ||I-MB||_F/sqrt(n) <= 0.3 (learned)",
+           "uniform_value": ut, "learned_seconds": ls, "uniform_seconds": us,
+           "higher_is_better": False, "n_gpus": 1, "dtype": "f64", "data": "synthetic",
+           "config": {"workload": f"5-point family with smooth rho field: {args.train_mats} training matrices, "
+                                  f"held-out {args.heldout}x{args.heldout}", "n": B.n, "train": info},
+           "points": pts}
     print(json.dumps(out), flush=True)
 
 

@@ -135,6 +135,19 @@ typedef struct {
  * *out is allocated by the library; free it with mcmi_cdf_free. */
 mcmi_status mcmi_build_cdf(const mcmi_csr_in *B, mcmi_cdf **out, void *stream);
 
+/* Records of `count` matrices in one block-diagonal row space (the batched
+ * launch): matrix k occupies rows [base_k, base_k + n_k) and its columns are
+ * shifted by base_k. Walks never leave their matrix; in mcmi_spai the Philox row
+ * word is the row inside its matrix and the tag word is stream_tag + k, so each
+ * matrix gets exactly the result of its own single-matrix run with that tag.
+ * Bs[k] are borrowed device CSR matrices (validated as in mcmi_build_cdf; each
+ * column must lie in [0, n_k)). Synchronises. */
+mcmi_status mcmi_build_cdf_batched(const mcmi_csr_in *Bs, int32_t count, mcmi_cdf **out, void *stream);
+
+/* Number of matrices of a record set (0 for a single-matrix set), their first
+ * rows (count + 1 values; for a single matrix {0, n}) and ||Chat_k||_inf. */
+mcmi_status mcmi_cdf_batch_info(const mcmi_cdf *cdf, int32_t *count, int64_t *row_base_host, double *norm_host);
+
 /* Copy the records to host memory (for inspection and tests; synchronises the
  * stream). rec_host receives rec_units * 16 uint32 words (rec_units from
  * mcmi_cdf_info), roff_host n record offsets (64-byte units) and diag_host the n

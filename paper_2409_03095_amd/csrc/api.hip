@@ -217,12 +217,47 @@ extern "C" mcmi_status mcmi_spai(const mcmi_cdf *cdf, const mcmi_params *p, cons
         if (hbad & 2u) return fail(MCMI_ERR_ARG, "mcmi_spai: chains_per_row holds a value < 1");
     }
 
+    // batched record sets: longest-processing-time order. Per-row cost N (L_k + 1)
+    // with L_k the chain-length bound of matrix k; blocks of 64 consecutive rows in
+    // decreasing cost, dealt round-robin to the eight XCD queue slices.
+    DevBuf lpt;
+    const int32_t *task_map = nullptr;
+    if (cdf->batch > 0 && !rows_dev) {
+        const int K = cdf->batch;
+        std::vector<double> cost(K);
+        for (int k = 0; k < K; ++k) {
+            const double S = cdf->mat_norm[k];
+            double L = (double)lmax;
+            if (S > 0.0 && S < 1.0 && p->delta > 0.0) L = std::min(L, std::ceil(std::log(p->delta) / std::log(S)));
+            if (S == 0.0) L = 0.0;
+            cost[k] = (double)n_hint * (L + 1.0);
+        }
+        std::vector<int> ord(K);
+        for (int k = 0; k < K; ++k) ord[k] = k;
+        std::stable_sort(ord.begin(), ord.end(), [&](int x, int y) { return cost[x] > cost[y]; });
+        std::vector<std::vector<int32_t>> lists(8);
+        int64_t blk = 0;
+        for (int k : ord) {
+            for (int64_t r0 = cdf->mat_base_host[k]; r0 < cdf->mat_base_host[k + 1]; r0 += 64, ++blk) {
+                auto &L = lists[blk % 8];
+                const int64_t r1 = std::min<int64_t>(r0 + 64, cdf->mat_base_host[k + 1]);
+                for (int64_t r = r0; r < r1; ++r) L.push_back((int32_t)r);
+            }
+        }
+        std::vector<int32_t> all;
+        all.reserve(n_tasks);
+        for (auto &L : lists) all.insert(all.end(), L.begin(), L.end());
+        MCMI_HIP(lpt.alloc(all.size() * sizeof(int32_t), s));
+        MCMI_HIP(hipMemcpyAsync(lpt.p, all.data(), all.size() * sizeof(int32_t), hipMemcpyHostToDevice, s));
+        MCMI_HIP(hipStreamSynchronize(s));
+        task_map = lpt.as<int32_t>();
+    }
+
     int64_t nnz = 0;
     unsigned long long tot_stats[4] = {0, 0, 0, 0};
     float ms_walk = 0.f;
     PoolSet pools;
     memset(&pools, 0, sizeof(pools));
-    const int32_t *task_map = nullptr;
     int64_t pass_tasks = n_tasks;
     MCMI_HIP(hipEventRecord(ev0, s));
     for (int pass = 0;; ++pass) {
@@ -265,6 +300,8 @@ extern "C" mcmi_status mcmi_spai(const mcmi_cdf *cdf, const mcmi_params *p, cons
         a.n_tasks = pass_tasks;
         a.task_map = task_map;
         a.pool_tag = (int64_t)pass << kPoolShift;
+        a.row_mat = cdf->batch > 0 ? cdf->row_mat : nullptr;
+        a.mat_base = cdf->batch > 0 ? cdf->mat_base : nullptr;
         a.chains_per_row = chains_per_row_dev;
         a.chains = p->chains;
         a.key0 = (uint32_t)(p->seed & 0xffffffffu);

@@ -302,8 +302,167 @@ extern "C" mcmi_status mcmi_cdf_download(const mcmi_cdf *cdf, uint32_t *rec_host
     return MCMI_OK;
 }
 
+// ------------------------------------------------------------ batched sets
+namespace mcmi {
+namespace {
+
+// rows of matrix k into the block-diagonal row space; checks its row pointers
+__global__ void __launch_bounds__(256) k_concat_rows(const int64_t *rp, int64_t nk, int64_t nnzk, int64_t row_base,
+                                                     int64_t nnz_base, int32_t k, int64_t *rp_out, int32_t *row_mat,
+                                                     uint32_t *flags) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nk; i += stride) {
+        rp_out[row_base + i] = rp[i] + nnz_base;
+        row_mat[row_base + i] = k;
+        if (i == 0 && (rp[0] != 0 || rp[nk] != nnzk)) atomicOr(flags, kFlagCsr);
+    }
+}
+
+// columns of matrix k shifted by its first row; each must lie in [0, n_k)
+__global__ void __launch_bounds__(256) k_concat_cols(const int32_t *col, int64_t nnzk, int64_t nk, int64_t row_base,
+                                                     int64_t nnz_base, int32_t *col_out, uint32_t *flags) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < nnzk; j += stride) {
+        const int32_t c = col[j];
+        if (c < 0 || (int64_t)c >= nk) atomicOr(flags, kFlagCsr);
+        col_out[nnz_base + j] = (int32_t)(c + row_base);
+    }
+}
+
+__global__ void __launch_bounds__(256) k_matrix_norms(int64_t n, const uint32_t *rec, const uint32_t *roff,
+                                                      const int32_t *row_mat, unsigned long long *bits) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < n; r += stride) {
+        const uint32_t *h = rec + (size_t)roff[r] * kUnitWords;
+        const unsigned long long b = ((unsigned long long)h[5] << 32) | h[4];
+        atomicMax(&bits[row_mat[r]], b);
+    }
+}
+
+unsigned grid_for(int64_t n) {
+    int64_t b = (n + 255) / 256;
+    if (b > 8192) b = 8192;
+    return (unsigned)(b < 1 ? 1 : b);
+}
+
+}  // namespace
+}  // namespace mcmi
+
+extern "C" mcmi_status mcmi_build_cdf_batched(const mcmi_csr_in *Bs, int32_t count, mcmi_cdf **out, void *stream) {
+    if (out) *out = nullptr;
+    if (!Bs || !out || count < 1) return fail(MCMI_ERR_ARG, "mcmi_build_cdf_batched: bad argument");
+    hipStream_t s = (hipStream_t)stream;
+    std::vector<int64_t> rb(count + 1, 0), zb(count + 1, 0);
+    for (int32_t k = 0; k < count; ++k) {
+        if (Bs[k].n <= 0 || Bs[k].nnz < Bs[k].n || !Bs[k].row_ptr_dev || !Bs[k].col_dev || !Bs[k].val_dev)
+            return fail(MCMI_ERR_ARG, "mcmi_build_cdf_batched: matrix " + std::to_string(k) + " is malformed");
+        rb[k + 1] = rb[k] + Bs[k].n;
+        zb[k + 1] = zb[k] + Bs[k].nnz;
+    }
+    if (rb[count] >= (int64_t)INT32_MAX) return fail(MCMI_ERR_ARG, "mcmi_build_cdf_batched: more than 2^31 rows");
+    const int64_t n = rb[count], nnz = zb[count];
+    int64_t *rp = nullptr;
+    int32_t *col = nullptr, *row_mat = nullptr;
+    double *val = nullptr;
+    uint32_t *flags = nullptr;
+    int64_t *base_dev = nullptr;
+    unsigned long long *nb = nullptr;
+    auto cleanup = [&]() {
+        (void)hipFree(rp);
+        (void)hipFree(col);
+        (void)hipFree(val);
+        (void)hipFree(flags);
+        (void)hipFree(nb);
+    };
+#define TRYB(call)                                                                          \
+    do {                                                                                    \
+        hipError_t _e = (call);                                                             \
+        if (_e != hipSuccess) {                                                             \
+            cleanup();                                                                      \
+            (void)hipFree(row_mat);                                                         \
+            (void)hipFree(base_dev);                                                        \
+            return fail(MCMI_ERR_HIP, std::string(#call) + ": " + hipGetErrorString(_e));   \
+        }                                                                                   \
+    } while (0)
+    TRYB(hipMalloc(&rp, (n + 1) * sizeof(int64_t)));
+    TRYB(hipMalloc(&col, nnz * sizeof(int32_t)));
+    TRYB(hipMalloc(&val, nnz * sizeof(double)));
+    TRYB(hipMalloc(&row_mat, n * sizeof(int32_t)));
+    TRYB(hipMalloc(&base_dev, (count + 1) * sizeof(int64_t)));
+    TRYB(hipMalloc(&flags, sizeof(uint32_t)));
+    TRYB(hipMalloc(&nb, count * sizeof(unsigned long long)));
+    TRYB(hipMemsetAsync(flags, 0, sizeof(uint32_t), s));
+    TRYB(hipMemsetAsync(nb, 0, count * sizeof(unsigned long long), s));
+    for (int32_t k = 0; k < count; ++k) {
+        k_concat_rows<<<grid_for(Bs[k].n), 256, 0, s>>>(Bs[k].row_ptr_dev, Bs[k].n, Bs[k].nnz, rb[k], zb[k], k, rp,
+                                                         row_mat, flags);
+        k_concat_cols<<<grid_for(Bs[k].nnz), 256, 0, s>>>(Bs[k].col_dev, Bs[k].nnz, Bs[k].n, rb[k], zb[k], col, flags);
+        TRYB(hipMemcpyAsync(val + zb[k], Bs[k].val_dev, Bs[k].nnz * sizeof(double), hipMemcpyDeviceToDevice, s));
+    }
+    TRYB(hipGetLastError());
+    TRYB(hipMemcpyAsync(rp + n, &nnz, sizeof(int64_t), hipMemcpyHostToDevice, s));
+    TRYB(hipMemcpyAsync(base_dev, rb.data(), (count + 1) * sizeof(int64_t), hipMemcpyHostToDevice, s));
+    uint32_t hflags = 0;
+    TRYB(hipMemcpyAsync(&hflags, flags, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+    TRYB(hipStreamSynchronize(s));
+    if (hflags & kFlagCsr) {
+        cleanup();
+        (void)hipFree(row_mat);
+        (void)hipFree(base_dev);
+        return fail(MCMI_ERR_CSR, "mcmi_build_cdf_batched: a matrix has bad row pointers or columns");
+    }
+    mcmi_csr_in all{n, nnz, rp, col, val};
+    mcmi_cdf *cdf = nullptr;
+    mcmi_status st = mcmi_build_cdf(&all, &cdf, stream);
+    if (st != MCMI_OK) {
+        cleanup();
+        (void)hipFree(row_mat);
+        (void)hipFree(base_dev);
+        return st;
+    }
+    cdf->batch = count;
+    cdf->row_mat = row_mat;
+    cdf->mat_base = base_dev;
+    cdf->mat_base_host = rb;
+    k_matrix_norms<<<grid_for(n), 256, 0, s>>>(n, cdf->rec, cdf->roff, row_mat, nb);
+    std::vector<unsigned long long> hb(count);
+    hipError_t e = hipMemcpyAsync(hb.data(), nb, count * sizeof(unsigned long long), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+#undef TRYB
+    cleanup();
+    if (e != hipSuccess) {
+        mcmi_cdf_free(cdf);
+        return fail(MCMI_ERR_HIP, std::string("mcmi_build_cdf_batched: ") + hipGetErrorString(e));
+    }
+    cdf->mat_norm.resize(count);
+    for (int32_t k = 0; k < count; ++k) ::memcpy(&cdf->mat_norm[k], &hb[k], sizeof(double));
+    *out = cdf;
+    return MCMI_OK;
+}
+
+extern "C" mcmi_status mcmi_cdf_batch_info(const mcmi_cdf *cdf, int32_t *count, int64_t *row_base_host,
+                                           double *norm_host) {
+    if (!cdf) return fail(MCMI_ERR_ARG, "mcmi_cdf_batch_info: null cdf");
+    const int32_t k = cdf->batch;
+    if (count) *count = k;
+    if (row_base_host) {
+        if (k) ::memcpy(row_base_host, cdf->mat_base_host.data(), (k + 1) * sizeof(int64_t));
+        else {
+            row_base_host[0] = 0;
+            row_base_host[1] = cdf->n;
+        }
+    }
+    if (norm_host) {
+        if (k) ::memcpy(norm_host, cdf->mat_norm.data(), k * sizeof(double));
+        else norm_host[0] = cdf->norm_inf;
+    }
+    return MCMI_OK;
+}
+
 extern "C" void mcmi_cdf_free(mcmi_cdf *cdf) {
     if (!cdf) return;
+    (void)hipFree(cdf->row_mat);
+    (void)hipFree(cdf->mat_base);
     hipFree(cdf->rec);
     hipFree(cdf->roff);
     hipFree(cdf->diag);

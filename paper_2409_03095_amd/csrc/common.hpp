@@ -155,6 +155,7 @@ hipError_t scan_exclusive_u32_to_i64(const uint32_t *in, int64_t *out, int64_t n
 }  // namespace mcmi
 
 // The opaque record set.
+#include <vector>
 struct mcmi_cdf {
     int64_t n = 0;
     int64_t nnz_c = 0;
@@ -164,4 +165,10 @@ struct mcmi_cdf {
     uint32_t *roff = nullptr;      // n: record offset (64-byte units) of each row
     double *diag = nullptr;        // n: b_ii
     uint32_t *mrow = nullptr;      // n: entries of each row of C
+    // batched record sets (several matrices, block-diagonal row space)
+    int32_t batch = 0;                   // number of matrices (0: a single matrix)
+    int32_t *row_mat = nullptr;          // n: matrix of each row
+    int64_t *mat_base = nullptr;         // batch + 1: first row of each matrix (device)
+    std::vector<int64_t> mat_base_host;  // same, on the host
+    std::vector<double> mat_norm;        // ||Chat_k||_inf per matrix
 };

@@ -66,6 +66,8 @@ __device__ __forceinline__ void walk_row(const WalkArgs &a, int64_t task, int32_
     const int32_t r = a.rows ? a.rows[slot] : (int32_t)slot;
     const int32_t N = a.chains_per_row ? a.chains_per_row[r] : a.chains;
     const uint32_t r_off = a.roff[r];
+    uint32_t prow, ptag;
+    philox_ids(a, r, prow, ptag);
 
     // j = 0: every chain contributes W_0 = 1 at (r, r); N ones sum exactly to N.
     if (lane == 0) lds_add(keys, vals, hmask, hash_key(r, a.hash_shift), r, (double)N);
@@ -118,7 +120,7 @@ __device__ __forceinline__ void walk_row(const WalkArgs &a, int64_t task, int32_
                 }
             } else {
                 // step j + 1 takes word j mod 4 of block j / 4: consume words in order
-                if ((j & 3u) == 0u) blk = philox4x32_10(j >> 2, (uint32_t)c, (uint32_t)r, a.tag, a.key0, a.key1);
+                if ((j & 3u) == 0u) blk = philox4x32_10(j >> 2, (uint32_t)c, prow, ptag, a.key0, a.key1);
                 const uint32_t u = blk.x;
                 blk.x = blk.y;
                 blk.y = blk.z;

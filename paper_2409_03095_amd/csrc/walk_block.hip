@@ -48,6 +48,7 @@ struct Chain {
 
 struct RowCtx {
     int32_t r, N;
+    uint32_t prow, ptag;  // Philox row and tag words
     uint32_t r_off;
     int32_t *keys;
     double *vals;
@@ -199,7 +200,7 @@ __device__ __forceinline__ void run_chains(const WalkArgs &a, const RowCtx &rc, 
             chain_start(st, st.c + stride, rc);
         } else {
             if ((st.j & 3u) == 0u)
-                st.blk = philox4x32_10(st.j >> 2, (uint32_t)st.c, (uint32_t)rc.r, a.tag, a.key0, a.key1);
+                st.blk = philox4x32_10(st.j >> 2, (uint32_t)st.c, rc.prow, rc.ptag, a.key0, a.key1);
             const uint32_t u = st.blk.x;
             st.blk.x = st.blk.y;
             st.blk.y = st.blk.z;
@@ -262,6 +263,7 @@ __device__ __forceinline__ void block_row(const WalkArgs &a, int64_t task, RowCt
     stage_full = false;
     rc.r = r;
     rc.N = N;
+    philox_ids(a, r, rc.prow, rc.ptag);
     rc.r_off = a.roff[r];
     const bool split = a.tau > 0.0;
     const bool reg = N <= kLPR;

@@ -61,6 +61,18 @@ __device__ __forceinline__ uint32_t bucket_of(int32_t key, int shift) {
     return ((uint32_t)key * 0x9E3779B1u ^ 0x5bd1e995u) * 0x85EBCA77u >> shift;
 }
 
+// Philox row and tag words of the chains of global row r
+__device__ __forceinline__ void philox_ids(const WalkArgs &a, int32_t r, uint32_t &prow, uint32_t &ptag) {
+    if (a.row_mat) {
+        const int32_t k = a.row_mat[r];
+        prow = (uint32_t)((int64_t)r - a.mat_base[k]);
+        ptag = a.tag + (uint32_t)k;
+    } else {
+        prow = (uint32_t)r;
+        ptag = a.tag;
+    }
+}
+
 // ------------------------------------------------------------- one step
 // The header unit of the current state: h0 = {row, m, W, Shat32},
 // h1 = {Shat64 lo, Shat64 hi, summary 0, summary 1}, h2/h3 = summaries 2..9.

@@ -69,6 +69,8 @@ _sig = {
     "mcmi_build_cdf": [_P(CsrIn), _P(_v), _v],
     "mcmi_cdf_info": [_v, _P(ctypes.c_int64), _P(ctypes.c_int64), _P(ctypes.c_double), _P(ctypes.c_uint64)],
     "mcmi_cdf_download": [_v, _v, _v, _v, _v],
+    "mcmi_build_cdf_batched": [_P(CsrIn), ctypes.c_int32, _P(_v), _v],
+    "mcmi_cdf_batch_info": [_v, _P(ctypes.c_int32), _v, _v],
     "mcmi_spai": [_v, _P(Params), _v, _v, ctypes.c_int64, _P(CsrOut), _P(Stats), _v],
     "mcmi_apply": [_P(CsrOut), ctypes.c_int64, _v, _v, _v],
     "mcmi_csr_copy": [_P(CsrOut), _v, _v, _v, _v],
@@ -101,7 +103,8 @@ EXPORTED = ["mcmi_build_cdf", "mcmi_cdf_info", "mcmi_cdf_download", "mcmi_spai",
             "mcmi_csr_copy", "mcmi_cdf_free", "mcmi_csr_free", "mcmi_last_error", "mcmi_version",
             "mcmi_row_features", "mcmi_pilot_variance", "mcmi_mlp_create", "mcmi_mlp_free",
             "mcmi_mlp_set_params", "mcmi_mlp_get_params", "mcmi_mlp_set_adam_state", "mcmi_mlp_fit_normalization",
-            "mcmi_mlp_predict", "mcmi_mlp_gradient", "mcmi_mlp_train", "mcmi_allocate"]
+            "mcmi_mlp_predict", "mcmi_mlp_gradient", "mcmi_mlp_train", "mcmi_allocate",
+            "mcmi_build_cdf_batched", "mcmi_cdf_batch_info"]
 
 
 def _check(st):
@@ -149,17 +152,36 @@ class DeviceCsr:
 
 
 class Cdf:
-    """Sampling records of C = I - D^-1 B (mcmi_build_cdf)."""
+    """Sampling records of C = I - D^-1 B (mcmi_build_cdf), or of several matrices
+    in one block-diagonal row space (Cdf.batched -> mcmi_build_cdf_batched)."""
 
-    def __init__(self, B: DeviceCsr, stream=None):
+    def __init__(self, B: DeviceCsr = None, stream=None, _batch=None):
         self._h = ctypes.c_void_p()
-        self._B = B
-        s = B._struct()
-        _check(_lib.mcmi_build_cdf(ctypes.byref(s), ctypes.byref(self._h), _stream(stream)))
+        self._B = B if B is not None else _batch
+        if _batch is None:
+            s = B._struct()
+            _check(_lib.mcmi_build_cdf(ctypes.byref(s), ctypes.byref(self._h), _stream(stream)))
+        else:
+            arr = (CsrIn * len(_batch))(*[m._struct() for m in _batch])
+            _check(_lib.mcmi_build_cdf_batched(arr, ctypes.c_int32(len(_batch)), ctypes.byref(self._h),
+                                               _stream(stream)))
         n, nnz_c, nrm, units = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_double(), ctypes.c_uint64()
         _check(_lib.mcmi_cdf_info(self._h, ctypes.byref(n), ctypes.byref(nnz_c), ctypes.byref(nrm),
                                   ctypes.byref(units)))
         self.n, self.nnz_c, self.norm_inf, self.rec_units = n.value, nnz_c.value, nrm.value, units.value
+
+    @staticmethod
+    def batched(mats, stream=None):
+        return Cdf(None, stream, _batch=list(mats))
+
+    def batch_info(self):
+        k = ctypes.c_int32()
+        _check(_lib.mcmi_cdf_batch_info(self._h, ctypes.byref(k), None, None))
+        cnt = max(k.value, 1)
+        base = np.zeros(cnt + 1, dtype=np.int64)
+        nrm = np.zeros(cnt, dtype=np.float64)
+        _check(_lib.mcmi_cdf_batch_info(self._h, ctypes.byref(k), base.ctypes.data_as(_v), nrm.ctypes.data_as(_v)))
+        return k.value, base, nrm
 
     def download(self, stream=None):
         rec = np.zeros(self.rec_units * 16, dtype=np.uint32)
