@@ -236,6 +236,35 @@ mcmi_status mcmi_mlp_train(mcmi_mlp *net, const float *feat_dev, const float *ta
 mcmi_status mcmi_allocate(const float *pred_dev, const int32_t *cost_dev, int64_t n, int64_t budget,
                           int32_t *chains_dev, double *lambda_host, int32_t *fallback_host, void *stream);
 
+/* ------------------------------------------------------ tuning and plans */
+
+/* Autotuner: times candidate kernel shapes (lanes per row, LDS hash slots,
+ * sketch buckets, heavy threshold automatic or off) with mcmi_spai on a strided
+ * sample of sample_rows rows (0: 8192) and writes the fastest into *best (a copy
+ * of *base with lanes_per_row, hash_slots, sketch_slots, heavy_weight set) and its
+ * walk time to *best_ms. cache_path (nullable): a JSON file keyed by the workload
+ * class (architecture, log2 of n, mean row length, chains and L_max, precision,
+ * batched, filter); a cached class is returned without timing, a new one is
+ * added. Synchronises. */
+mcmi_status mcmi_tune(const mcmi_cdf *cdf, const mcmi_params *base, int64_t sample_rows, const char *cache_path,
+                      mcmi_params *best, double *best_ms, void *stream);
+
+/* A plan owns every buffer of one SPAI configuration (cdf, parameters, per-row
+ * chains, output capacity nnz_capacity) and a hipGraph of its device work: counter
+ * reset, walk + finalize, row-count scan, gather into the plan's CSR buffers. For
+ * callers that repeat the SPAI (time stepping, serving). mcmi_plan_launch replays
+ * the graph with a new seed (asynchronous); mcmi_plan_result synchronises and
+ * returns a view of the plan-owned CSR (valid until the next launch or
+ * mcmi_plan_free) and *overflow = 1 when a table or the capacity overflowed (the
+ * view is then empty: rerun with mcmi_spai or a larger plan). Rows are not rerun
+ * inside a plan. The cdf must outlive the plan. */
+typedef struct mcmi_plan mcmi_plan;
+mcmi_status mcmi_plan_create(const mcmi_cdf *cdf, const mcmi_params *p, const int32_t *chains_per_row_dev,
+                             int64_t nnz_capacity, mcmi_plan **out, void *stream);
+mcmi_status mcmi_plan_launch(mcmi_plan *plan, uint64_t seed, void *stream);
+mcmi_status mcmi_plan_result(mcmi_plan *plan, mcmi_csr_out *M_view, mcmi_stats *st, int32_t *overflow, void *stream);
+void mcmi_plan_free(mcmi_plan *plan);
+
 /* Copy M into caller-owned device buffers (row_ptr n+1, col nnz, val nnz). */
 mcmi_status mcmi_csr_copy(const mcmi_csr_out *M, int64_t *row_ptr_dev, int32_t *col_dev,
                           double *val_dev, void *stream);

@@ -63,6 +63,51 @@ int device_cus() {
     return cus;
 }
 
+
+// Kernel shape of a run: lanes per row (64 = wavefront kernel), LDS hash slots,
+// count-sketch buckets and heavy threshold tau (0 = track every contribution).
+mcmi_status choose_shape(const mcmi_cdf *cdf, const mcmi_params *p, int lmax, KernelShape &out) {
+    const double m_bar = cdf->n > 0 ? (double)cdf->nnz_c / (double)cdf->n : 0.0;
+    const int n_hint = p->chains >= 1 ? p->chains : 64;
+    int lanes = p->lanes_per_row;
+    if (lanes == 0) lanes = n_hint >= 384 ? 512 : (n_hint >= 192 ? 256 : 64);
+    const bool block_kernel = lanes > 64;
+    int H = p->hash_slots ? p->hash_slots : (block_kernel ? 4096 : 1024);
+    if (block_kernel && !walk_block_supported(lanes, H))
+        return fail(MCMI_ERR_ARG, "mcmi_spai: unsupported (lanes_per_row, hash_slots) for the workgroup kernel");
+    int sketch = 0;
+    double tau = 0.0;
+    if (block_kernel && cdf->norm_inf < 1.0 && p->heavy_weight >= 0.0) {
+        if (p->heavy_weight > 0.0) {
+            tau = p->heavy_weight;
+        } else {
+            // distinct columns reached by step j are at most min(N, m^j, n); track every
+            // contribution when all steps fit in half the table, else the first J steps
+            const double S = cdf->norm_inf;
+            const int steps = S > 0.0 ? std::min(lmax, (int)std::ceil(std::log(p->delta > 0 ? p->delta : 1e-300) /
+                                                                        std::log(S))) : 0;
+            double reach = 1.0, total = 1.0;
+            int J = 0;
+            bool fits = true;
+            for (int jj = 1; jj <= steps; ++jj) {
+                reach = std::min({reach * std::max(m_bar, 1.0), (double)n_hint, (double)cdf->n});
+                total += reach;
+                if (fits && total <= 0.55 * H)
+                    J = jj;
+                else
+                    fits = false;
+            }
+            if (std::min(total, (double)cdf->n) > 0.5 * H) tau = std::pow(S, std::max(J, 1)) * (1.0 - 1.0 / 1048576.0);
+        }
+        if (tau > 0.0) sketch = p->sketch_slots ? p->sketch_slots : 8192;
+    }
+    out.lanes = lanes;
+    out.hash = H;
+    out.sketch = sketch;
+    out.tau = tau;
+    return MCMI_OK;
+}
+
 }  // namespace mcmi
 
 using namespace mcmi;
@@ -145,43 +190,17 @@ extern "C" mcmi_status mcmi_spai(const mcmi_cdf *cdf, const mcmi_params *p, cons
 
     // ---- kernel shape and heavy threshold
     const int cus = device_cus();
-    const double m_bar = cdf->n > 0 ? (double)cdf->nnz_c / (double)cdf->n : 0.0;
     const int n_hint = p->chains >= 1 ? p->chains : 64;
-    int lanes = p->lanes_per_row;
-    if (lanes == 0) lanes = n_hint >= 384 ? 512 : (n_hint >= 192 ? 256 : 64);
-    const bool block_kernel = lanes > 64;
-    int H = p->hash_slots ? p->hash_slots : (block_kernel ? 4096 : 1024);
-    if (block_kernel && !walk_block_supported(lanes, H))
-        return fail(MCMI_ERR_ARG, "mcmi_spai: unsupported (lanes_per_row, hash_slots) for the workgroup kernel");
-    int sketch = 0;
-    double tau = 0.0;
-    if (block_kernel && cdf->norm_inf < 1.0 && p->heavy_weight >= 0.0) {
-        if (p->heavy_weight > 0.0) {
-            tau = p->heavy_weight;
-        } else {
-            // distinct columns reached by step j are at most min(N, m^j, n); track every
-            // contribution when all steps fit in half the table, else the first J steps
-            const double S = cdf->norm_inf;
-            const int steps = S > 0.0 ? std::min(lmax, (int)std::ceil(std::log(p->delta > 0 ? p->delta : 1e-300) /
-                                                                        std::log(S))) : 0;
-            double reach = 1.0, total = 1.0, fit = 1.0;
-            int J = 0;
-            bool fits = true;
-            for (int jj = 1; jj <= steps; ++jj) {
-                reach = std::min({reach * std::max(m_bar, 1.0), (double)n_hint, (double)cdf->n});
-                total += reach;
-                if (fits && total <= 0.55 * H) {
-                    fit = total;
-                    J = jj;
-                } else {
-                    fits = false;
-                }
-            }
-            if (std::min(total, (double)cdf->n) > 0.5 * H) tau = std::pow(S, std::max(J, 1)) * (1.0 - 1.0 / 1048576.0);
-            (void)fit;
-        }
-        if (tau > 0.0) sketch = p->sketch_slots ? p->sketch_slots : 4096;
+    KernelShape shape;
+    {
+        const mcmi_status sst = choose_shape(cdf, p, lmax, shape);
+        if (sst != MCMI_OK) return sst;
     }
+    const int lanes = shape.lanes;
+    const bool block_kernel = lanes > 64;
+    int H = shape.hash;
+    const int sketch = shape.sketch;
+    const double tau = shape.tau;
     int waves = 4;
     int spill_slots = p->spill_slots ? p->spill_slots : (block_kernel ? 16384 : 4096);
     // first guess of the output size; rows that do not fit are rerun into a new pool

@@ -154,6 +154,16 @@ hipError_t scan_exclusive_u32_to_i64(const uint32_t *in, int64_t *out, int64_t n
 
 }  // namespace mcmi
 
+// Kernel shape of a walk launch (api.hip: choose_shape)
+struct KernelShape {
+    int lanes = 64, hash = 1024, sketch = 0;
+    double tau = 0.0;
+};
+struct mcmi_cdf;
+namespace mcmi {
+mcmi_status choose_shape(const mcmi_cdf *cdf, const mcmi_params *p, int lmax, KernelShape &out);
+}
+
 // The opaque record set.
 #include <vector>
 struct mcmi_cdf {

@@ -1,0 +1,407 @@
+// Autotuner and captured plans (gfx950).
+//
+// mcmi_tune: times candidate kernel shapes (lanes per row, LDS hash slots,
+// count-sketch buckets, heavy threshold) on a strided sample of rows and keeps the
+// fastest walk; results are cached in a JSON file keyed by the workload class
+// (architecture, log2 buckets of n, mean entries per row, chains, chain length,
+// precision, batched or not).
+//
+// mcmi_plan: everything of one SPAI configuration allocated once and its device
+// work captured in a hipGraph (counter reset kernel -> walk -> row-count scan ->
+// gather into fixed-capacity CSR buffers); each launch replays the graph with a
+// new seed. No memset node is recorded: counters are cleared by a kernel, and the
+// walk leaves its HBM overflow tables clean.
+#include <string.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <map>
+#include <string>
+#include <vector>
+
+#include "common.hpp"
+#include "walk_args.hpp"
+
+namespace mcmi {
+
+size_t walk_lds_bytes(int hash_slots, int waves);
+hipError_t launch_walk(const WalkArgs &a, bool f32, int blocks, int waves, hipStream_t s);
+hipError_t walk_occupancy(bool f32, int hash_slots, int waves, int *blocks_per_cu);
+bool walk_block_supported(int lanes, int hash_slots);
+hipError_t launch_walk_block(const WalkArgs &a, bool f32, int lanes, int blocks, hipStream_t s);
+hipError_t walk_block_occupancy(bool f32, int lanes, int hash_slots, int sketch_slots, int *bpc);
+
+namespace {
+
+__global__ void k_zero_words(uint32_t *p, int n) {
+    for (int i = threadIdx.x; i < n; i += blockDim.x) p[i] = 0u;
+}
+
+// seed from device memory so that each graph replay can use a new one
+__global__ void k_set_keys(const uint64_t *seed, uint32_t *keys) {
+    if (threadIdx.x == 0) {
+        keys[0] = (uint32_t)(*seed & 0xffffffffu);
+        keys[1] = (uint32_t)(*seed >> 32);
+    }
+}
+
+// Gather for plans: rows that could not be written (row_start < 0) and rows past
+// the output capacity are skipped (the result then reports an overflow).
+__global__ void __launch_bounds__(256) k_gather_capped(int64_t n_rows, const int64_t *row_start,
+                                                       const uint32_t *row_cnt, const int64_t *row_ptr,
+                                                       const int32_t *pool_col, const double *pool_val,
+                                                       int64_t cap, int32_t *col, double *val) {
+    const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const int lane = threadIdx.x & 63;
+    const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
+    for (int64_t r = wave; r < n_rows; r += nwaves) {
+        const int64_t src = row_start[r], dst = row_ptr[r];
+        const uint32_t cnt = row_cnt[r];
+        if (src < 0 || dst + (int64_t)cnt > cap) continue;
+        const int64_t pos = src & (((int64_t)1 << kPoolShift) - 1);
+        for (uint32_t k = lane; k < cnt; k += 64) {
+            col[dst + k] = pool_col[pos + k];
+            val[dst + k] = pool_val[pos + k];
+        }
+    }
+}
+
+std::string tune_key(const mcmi_cdf *cdf, const mcmi_params *p, int lmax) {
+    auto lg = [](double x) { return x > 0 ? (int)std::floor(std::log2(x)) : -1; };
+    char buf[256];
+    const double m_bar = cdf->n ? (double)cdf->nnz_c / (double)cdf->n : 0.0;
+    snprintf(buf, sizeof(buf), "gfx950|n%d|m%d|N%d|L%d|p%d|b%d|f%d", lg((double)cdf->n), lg(m_bar),
+             lg((double)std::max(p->chains, 1)), lg((double)lmax), p->walk_prec, cdf->batch > 0 ? 1 : 0, p->filter);
+    return buf;
+}
+
+struct TuneEntry {
+    int lanes, hash, sketch;
+    double tau, ms;
+};
+
+std::map<std::string, TuneEntry> read_cache(const char *path) {
+    std::map<std::string, TuneEntry> out;
+    if (!path) return out;
+    FILE *f = fopen(path, "r");
+    if (!f) return out;
+    char line[512];
+    while (fgets(line, sizeof(line), f)) {
+        char key[256];
+        TuneEntry e;
+        if (sscanf(line, " \"%255[^\"]\" : [ %d , %d , %d , %lf , %lf ]", key, &e.lanes, &e.hash, &e.sketch, &e.tau,
+                   &e.ms) == 6)
+            out[key] = e;
+    }
+    fclose(f);
+    return out;
+}
+
+bool write_cache(const char *path, const std::map<std::string, TuneEntry> &m) {
+    if (!path) return true;
+    const std::string tmp = std::string(path) + ".tmp";
+    FILE *f = fopen(tmp.c_str(), "w");
+    if (!f) return false;
+    fprintf(f, "{\n");
+    size_t k = 0;
+    for (const auto &kv : m) {
+        fprintf(f, "  \"%s\": [%d, %d, %d, %.17g, %.6f]%s\n", kv.first.c_str(), kv.second.lanes, kv.second.hash,
+                kv.second.sketch, kv.second.tau, kv.second.ms, ++k < m.size() ? "," : "");
+    }
+    fprintf(f, "}\n");
+    fclose(f);
+    return rename(tmp.c_str(), path) == 0;
+}
+
+}  // namespace
+}  // namespace mcmi
+
+using namespace mcmi;
+
+extern "C" mcmi_status mcmi_tune(const mcmi_cdf *cdf, const mcmi_params *base, int64_t sample_rows,
+                                 const char *cache_path, mcmi_params *best, double *best_ms, void *stream) {
+    if (!cdf || !base || !best) return fail(MCMI_ERR_ARG, "mcmi_tune: null argument");
+    if (base->chains < 1) return fail(MCMI_ERR_ARG, "mcmi_tune: needs a uniform chain count (chains >= 1)");
+    const int lmax = derive_lmax(cdf->norm_inf, base->delta, base->max_len);
+    if (lmax < 0) return fail(MCMI_ERR_ARG, "mcmi_tune: bad delta / max_len or not contractive");
+    const std::string key = tune_key(cdf, base, lmax);
+    auto cache = read_cache(cache_path);
+    *best = *base;
+    auto it = cache.find(key);
+    if (it != cache.end()) {
+        best->lanes_per_row = it->second.lanes;
+        best->hash_slots = it->second.hash;
+        best->sketch_slots = it->second.sketch;
+        best->heavy_weight = it->second.tau;
+        if (best_ms) *best_ms = it->second.ms;
+        return MCMI_OK;
+    }
+    hipStream_t s = (hipStream_t)stream;
+    // strided row sample (for batched sets it spans every matrix)
+    const int64_t ns = std::max<int64_t>(1, std::min<int64_t>(sample_rows > 0 ? sample_rows : 8192, cdf->n));
+    std::vector<int32_t> rows(ns);
+    for (int64_t k = 0; k < ns; ++k) rows[k] = (int32_t)((k * cdf->n) / ns);
+    int32_t *rows_dev = nullptr;
+    MCMI_HIP(hipMalloc(&rows_dev, ns * sizeof(int32_t)));
+    MCMI_HIP(hipMemcpy(rows_dev, rows.data(), ns * sizeof(int32_t), hipMemcpyHostToDevice));
+    struct Cand {
+        int lanes, hash, sketch;
+        double tau;
+    };
+    std::vector<Cand> cands = {{64, 512, 0, 0}, {64, 1024, 0, 0}, {64, 2048, 0, 0}};
+    for (int lanes : {256, 512, 1024})
+        for (int hash : {2048, 4096})
+            if (walk_block_supported(lanes, hash))
+                for (int sk : {4096, 8192}) {
+                    cands.push_back({lanes, hash, sk, 0.0});  // automatic tau
+                    cands.push_back({lanes, hash, sk, -1.0}); // track everything
+                }
+    double best_t = 1e300;
+    Cand win = cands[0];
+    for (const Cand &c : cands) {
+        mcmi_params q = *base;
+        q.lanes_per_row = c.lanes;
+        q.hash_slots = c.hash;
+        q.sketch_slots = c.sketch;
+        q.heavy_weight = c.tau;
+        double t = 0.0;
+        bool ok = true;
+        for (int rep = 0; rep < 2 && ok; ++rep) {
+            mcmi_csr_out M;
+            mcmi_stats st;
+            if (mcmi_spai(cdf, &q, nullptr, rows_dev, ns, &M, &st, s) != MCMI_OK) {
+                ok = false;
+                break;
+            }
+            mcmi_csr_free(&M);
+            t = st.ms_walk;  // second run's time
+        }
+        if (ok && t < best_t) {
+            best_t = t;
+            win = c;
+        }
+    }
+    (void)hipFree(rows_dev);
+    if (best_t >= 1e300) return fail(MCMI_ERR_CAPACITY, "mcmi_tune: no candidate ran");
+    best->lanes_per_row = win.lanes;
+    best->hash_slots = win.hash;
+    best->sketch_slots = win.sketch;
+    best->heavy_weight = win.tau;
+    if (best_ms) *best_ms = best_t;
+    cache[key] = TuneEntry{win.lanes, win.hash, win.sketch, win.tau, best_t};
+    if (!write_cache(cache_path, cache)) return fail(MCMI_ERR_ARG, "mcmi_tune: cannot write the cache file");
+    set_error("");
+    return MCMI_OK;
+}
+
+// ---------------------------------------------------------------- plans
+struct mcmi_plan {
+    const mcmi_cdf *cdf = nullptr;
+    int64_t n = 0, cap = 0, pool_cap = 0;
+    void *ctrl = nullptr;       // queue counters, pool_used, stats, flags, keys
+    int64_t *row_start = nullptr, *row_ptr = nullptr;
+    uint32_t *row_cnt = nullptr;
+    int32_t *pool_col = nullptr, *col = nullptr, *sk = nullptr, *su = nullptr;
+    double *pool_val = nullptr, *val = nullptr, *sv = nullptr;
+    uint64_t *seed = nullptr;
+    void *scan_tmp = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    int lmax = 0;
+    KernelShape shape;
+};
+
+extern "C" void mcmi_plan_free(mcmi_plan *pl) {
+    if (!pl) return;
+    if (pl->exec) (void)hipGraphExecDestroy(pl->exec);
+    if (pl->graph) (void)hipGraphDestroy(pl->graph);
+    for (void *p : {(void *)pl->ctrl, (void *)pl->row_start, (void *)pl->row_ptr, (void *)pl->row_cnt,
+                    (void *)pl->pool_col, (void *)pl->col, (void *)pl->sk, (void *)pl->su, (void *)pl->pool_val,
+                    (void *)pl->val, (void *)pl->sv, (void *)pl->seed, pl->scan_tmp})
+        (void)hipFree(p);
+    delete pl;
+}
+
+extern "C" mcmi_status mcmi_plan_create(const mcmi_cdf *cdf, const mcmi_params *p, const int32_t *chains_per_row_dev,
+                                        int64_t nnz_capacity, mcmi_plan **out, void *stream) {
+    if (out) *out = nullptr;
+    if (!cdf || !p || !out || nnz_capacity < 1) return fail(MCMI_ERR_ARG, "mcmi_plan_create: bad argument");
+    if (p->chains < 1 && !chains_per_row_dev) return fail(MCMI_ERR_ARG, "mcmi_plan_create: chains must be >= 1");
+    if (p->walk_prec != MCMI_WALK_F64 && p->walk_prec != MCMI_WALK_F32)
+        return fail(MCMI_ERR_ARG, "mcmi_plan_create: walk_prec must be 64 or 32");
+    const int lmax = derive_lmax(cdf->norm_inf, p->delta, p->max_len);
+    if (lmax < 0) return fail(MCMI_ERR_ARG, "mcmi_plan_create: bad delta / max_len or not contractive");
+    mcmi_plan *pl = new mcmi_plan();
+    pl->cdf = cdf;
+    pl->n = cdf->n;
+    pl->cap = nnz_capacity;
+    pl->pool_cap = nnz_capacity;
+    pl->lmax = lmax;
+    mcmi_status sst = choose_shape(cdf, p, lmax, pl->shape);
+    if (sst != MCMI_OK) {
+        delete pl;
+        return sst;
+    }
+    const bool f32 = p->walk_prec == MCMI_WALK_F32;
+    const bool block_kernel = pl->shape.lanes > 64;
+    const int waves = 4;
+    int bpc = 0;
+    hipError_t e = block_kernel ? walk_block_occupancy(f32, pl->shape.lanes, pl->shape.hash, pl->shape.sketch, &bpc)
+                                : walk_occupancy(f32, pl->shape.hash, waves, &bpc);
+    if (e != hipSuccess || bpc < 1) {
+        mcmi_plan_free(pl);
+        return fail(MCMI_ERR_CAPACITY, "mcmi_plan_create: kernel does not fit");
+    }
+    int64_t blocks = (int64_t)bpc * device_cus();
+    int64_t regions;
+    if (block_kernel) {
+        blocks = std::min<int64_t>(blocks, pl->n);
+        regions = blocks;
+    } else {
+        if (blocks * waves > pl->n) blocks = std::max<int64_t>(1, (pl->n + waves - 1) / waves);
+        regions = blocks * waves;
+    }
+    const int spill_slots = p->spill_slots ? p->spill_slots : (block_kernel ? 16384 : 4096);
+    const size_t ctrl_bytes = 128;
+    hipStream_t s = (hipStream_t)stream;
+#define TRYP(call)                                                                           \
+    do {                                                                                     \
+        hipError_t _e = (call);                                                              \
+        if (_e != hipSuccess) {                                                              \
+            mcmi_plan_free(pl);                                                              \
+            return fail(MCMI_ERR_HIP, std::string(#call) + ": " + hipGetErrorString(_e));    \
+        }                                                                                    \
+    } while (0)
+    TRYP(hipMalloc(&pl->ctrl, ctrl_bytes));
+    TRYP(hipMalloc(&pl->row_start, pl->n * sizeof(int64_t)));
+    TRYP(hipMalloc(&pl->row_ptr, (pl->n + 1) * sizeof(int64_t)));
+    TRYP(hipMalloc(&pl->row_cnt, pl->n * sizeof(uint32_t)));
+    TRYP(hipMalloc(&pl->pool_col, pl->pool_cap * sizeof(int32_t)));
+    TRYP(hipMalloc(&pl->pool_val, pl->pool_cap * sizeof(double)));
+    TRYP(hipMalloc(&pl->col, pl->cap * sizeof(int32_t)));
+    TRYP(hipMalloc(&pl->val, pl->cap * sizeof(double)));
+    TRYP(hipMalloc(&pl->sk, (size_t)regions * spill_slots * sizeof(int32_t)));
+    TRYP(hipMalloc(&pl->sv, (size_t)regions * spill_slots * sizeof(double)));
+    TRYP(hipMalloc(&pl->su, (size_t)regions * spill_slots * sizeof(int32_t)));
+    TRYP(hipMalloc(&pl->seed, sizeof(uint64_t)));
+    TRYP(hipMalloc(&pl->scan_tmp, scan_tmp_bytes(pl->n)));
+    // overflow tables start clean once; every walk leaves them clean again
+    TRYP(hipMemsetAsync(pl->sk, 0xFF, (size_t)regions * spill_slots * sizeof(int32_t), s));
+    TRYP(hipMemsetAsync(pl->sv, 0, (size_t)regions * spill_slots * sizeof(double), s));
+    TRYP(hipStreamSynchronize(s));
+
+    unsigned char *ctrl = (unsigned char *)pl->ctrl;
+    WalkArgs a;
+    memset(&a, 0, sizeof(a));
+    a.rec = cdf->rec;
+    a.roff = cdf->roff;
+    a.diag = cdf->diag;
+    a.n_tasks = pl->n;
+    a.chains_per_row = chains_per_row_dev;
+    a.chains = p->chains;
+    a.keys_dev = (const uint32_t *)(ctrl + 96);
+    a.tag = p->stream_tag;
+    a.row_mat = cdf->batch > 0 ? cdf->row_mat : nullptr;
+    a.mat_base = cdf->batch > 0 ? cdf->mat_base : nullptr;
+    a.delta = p->delta;
+    a.delta32 = (float)p->delta;
+    a.eps = p->eps;
+    a.lmax = lmax;
+    a.filter_m = p->filter == MCMI_FILTER_M;
+    a.hash_slots = pl->shape.hash;
+    a.hash_shift = 32 - __builtin_ctz((unsigned)pl->shape.hash);
+    a.queue_ctr = (uint32_t *)ctrl;
+    a.row_start = pl->row_start;
+    a.row_cnt = pl->row_cnt;
+    a.pool_col = pl->pool_col;
+    a.pool_val = pl->pool_val;
+    a.pool_cap = pl->pool_cap;
+    a.pool_used = (unsigned long long *)(ctrl + 32);
+    a.spill_keys = pl->sk;
+    a.spill_vals = pl->sv;
+    a.spill_used = pl->su;
+    a.spill_slots = spill_slots;
+    a.stats = (unsigned long long *)(ctrl + 40);
+    a.flags = (uint32_t *)(ctrl + 72);
+    a.tau = pl->shape.tau;
+    a.tau32 = (float)pl->shape.tau;
+    a.sketch_slots = pl->shape.sketch;
+    a.sketch_shift = pl->shape.sketch ? 32 - __builtin_ctz((unsigned)pl->shape.sketch) : 0;
+
+    hipStream_t cs;
+    TRYP(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+    hipError_t ce = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+    if (ce == hipSuccess) {
+        k_zero_words<<<1, 64, 0, cs>>>((uint32_t *)ctrl, 24);  // counters, stats, flags (not the keys)
+        k_set_keys<<<1, 64, 0, cs>>>(pl->seed, (uint32_t *)(ctrl + 96));
+        if (block_kernel)
+            ce = launch_walk_block(a, f32, pl->shape.lanes, (int)blocks, cs);
+        else
+            ce = launch_walk(a, f32, (int)blocks, waves, cs);
+        if (ce == hipSuccess)
+            ce = scan_exclusive_u32_to_i64(pl->row_cnt, pl->row_ptr, pl->n, pl->row_ptr + pl->n, pl->scan_tmp, cs);
+        int64_t gb = (pl->n + 3) / 4;
+        if (gb > 65536) gb = 65536;
+        k_gather_capped<<<(unsigned)gb, 256, 0, cs>>>(pl->n, pl->row_start, pl->row_cnt, pl->row_ptr, pl->pool_col,
+                                                     pl->pool_val, pl->cap, pl->col, pl->val);
+        hipError_t ee = hipStreamEndCapture(cs, &pl->graph);
+        if (ce == hipSuccess) ce = ee;
+    }
+    if (ce == hipSuccess) ce = hipGraphInstantiate(&pl->exec, pl->graph, nullptr, nullptr, 0);
+    (void)hipStreamDestroy(cs);
+#undef TRYP
+    if (ce != hipSuccess) {
+        mcmi_plan_free(pl);
+        return fail(MCMI_ERR_HIP, std::string("mcmi_plan_create: capture: ") + hipGetErrorString(ce));
+    }
+    *out = pl;
+    return MCMI_OK;
+}
+
+extern "C" mcmi_status mcmi_plan_launch(mcmi_plan *pl, uint64_t seed, void *stream) {
+    if (!pl || !pl->exec) return fail(MCMI_ERR_ARG, "mcmi_plan_launch: bad plan");
+    hipStream_t s = (hipStream_t)stream;
+    MCMI_HIP(hipMemcpyAsync(pl->seed, &seed, sizeof(seed), hipMemcpyHostToDevice, s));
+    MCMI_HIP(hipGraphLaunch(pl->exec, s));
+    return MCMI_OK;
+}
+
+extern "C" mcmi_status mcmi_plan_result(mcmi_plan *pl, mcmi_csr_out *M_view, mcmi_stats *st, int32_t *overflow,
+                                        void *stream) {
+    if (!pl) return fail(MCMI_ERR_ARG, "mcmi_plan_result: bad plan");
+    hipStream_t s = (hipStream_t)stream;
+    unsigned char h[128];
+    int64_t nnz = 0;
+    MCMI_HIP(hipMemcpyAsync(h, pl->ctrl, sizeof(h), hipMemcpyDeviceToHost, s));
+    MCMI_HIP(hipMemcpyAsync(&nnz, pl->row_ptr + pl->n, sizeof(nnz), hipMemcpyDeviceToHost, s));
+    MCMI_HIP(hipStreamSynchronize(s));
+    uint32_t flags;
+    unsigned long long stats[4];
+    memcpy(&flags, h + 72, 4);
+    memcpy(stats, h + 40, sizeof(stats));
+    const int ovf = (flags & (kFlagPool | kFlagSpill | kFlagStage)) || nnz > pl->cap ? 1 : 0;
+    if (overflow) *overflow = ovf;
+    if (M_view) {
+        M_view->n = pl->n;
+        M_view->nnz = ovf ? 0 : nnz;
+        M_view->row_ptr_dev = pl->row_ptr;
+        M_view->col_dev = pl->col;
+        M_view->val_dev = pl->val;
+    }
+    if (st) {
+        memset(st, 0, sizeof(*st));
+        st->transitions = stats[0];
+        st->spilled = stats[1];
+        st->chains = stats[2];
+        st->refined = stats[3];
+        st->nnz = nnz;
+        st->lmax = pl->lmax;
+        st->norm_inf = (float)pl->cdf->norm_inf;
+        st->lanes_per_row = pl->shape.lanes;
+        st->hash_slots = pl->shape.hash;
+        st->sketch_slots = pl->shape.sketch;
+        st->heavy_weight = pl->shape.tau;
+    }
+    return MCMI_OK;
+}

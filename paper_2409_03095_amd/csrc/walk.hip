@@ -58,7 +58,7 @@ __device__ __forceinline__ int64_t next_task(const WalkArgs &a, int &queue) {
 
 template <bool kF32>
 __device__ __forceinline__ void walk_row(const WalkArgs &a, int64_t task, int32_t *keys, double *vals, int *spill_cnt,
-                         int32_t *skeys, double *svals, int32_t *sused) {
+                         int32_t *skeys, double *svals, int32_t *sused, uint32_t k0, uint32_t k1) {
     const int lane = lane_id();
     const uint32_t hmask = (uint32_t)a.hash_slots - 1u;
     const uint32_t smask = (uint32_t)a.spill_slots - 1u;
@@ -120,7 +120,7 @@ __device__ __forceinline__ void walk_row(const WalkArgs &a, int64_t task, int32_
                 }
             } else {
                 // step j + 1 takes word j mod 4 of block j / 4: consume words in order
-                if ((j & 3u) == 0u) blk = philox4x32_10(j >> 2, (uint32_t)c, prow, ptag, a.key0, a.key1);
+                if ((j & 3u) == 0u) blk = philox4x32_10(j >> 2, (uint32_t)c, prow, ptag, k0, k1);
                 const uint32_t u = blk.x;
                 blk.x = blk.y;
                 blk.y = blk.z;
@@ -285,10 +285,12 @@ __global__ void __launch_bounds__(256) k_walk(WalkArgs a) {
     double *svals = a.spill_vals + gw * a.spill_slots;
     int32_t *sused = a.spill_used + gw * a.spill_slots;
     int queue = (int)(blockIdx.x & 7u);
+    const uint32_t k0 = a.keys_dev ? a.keys_dev[0] : a.key0;
+    const uint32_t k1 = a.keys_dev ? a.keys_dev[1] : a.key1;
     for (;;) {
         const int64_t task = next_task(a, queue);
         if (task < 0) break;
-        walk_row<kF32>(a, task, keys, vals, spill_cnt, skeys, svals, sused);
+        walk_row<kF32>(a, task, keys, vals, spill_cnt, skeys, svals, sused, k0, k1);
     }
 }
 

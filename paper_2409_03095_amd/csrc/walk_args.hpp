@@ -15,6 +15,7 @@ struct WalkArgs {
     const int32_t *chains_per_row; // nullable
     int32_t chains;
     uint32_t key0, key1, tag;
+    const uint32_t *keys_dev;      // nullable: read the Philox key from device memory (graph replays)
     // batched record sets: the Philox row word is the row inside its matrix and the
     // tag word is tag + matrix index (nullable: row word = global row, tag word = tag)
     const int32_t *row_mat;

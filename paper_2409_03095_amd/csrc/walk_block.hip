@@ -49,6 +49,7 @@ struct Chain {
 struct RowCtx {
     int32_t r, N;
     uint32_t prow, ptag;  // Philox row and tag words
+    uint32_t k0, k1;      // Philox key
     uint32_t r_off;
     int32_t *keys;
     double *vals;
@@ -200,7 +201,7 @@ __device__ __forceinline__ void run_chains(const WalkArgs &a, const RowCtx &rc, 
             chain_start(st, st.c + stride, rc);
         } else {
             if ((st.j & 3u) == 0u)
-                st.blk = philox4x32_10(st.j >> 2, (uint32_t)st.c, rc.prow, rc.ptag, a.key0, a.key1);
+                st.blk = philox4x32_10(st.j >> 2, (uint32_t)st.c, rc.prow, rc.ptag, rc.k0, rc.k1);
             const uint32_t u = st.blk.x;
             st.blk.x = st.blk.y;
             st.blk.y = st.blk.z;
@@ -454,6 +455,8 @@ __global__ void __launch_bounds__(kLPR, 4) k_walk_block(WalkArgs a) {
     rc.sused = a.spill_used + (int64_t)blockIdx.x * a.spill_slots;
     rc.row_spilled = false;
     rc.hot_thr = 0.f;
+    rc.k0 = a.keys_dev ? a.keys_dev[0] : a.key0;
+    rc.k1 = a.keys_dev ? a.keys_dev[1] : a.key1;
     unsigned long long trans = 0, spilled = 0;
     bool spill_full = false, stage_full = false;
     int queue = (int)(blockIdx.x & 7u);

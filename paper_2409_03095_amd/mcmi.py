@@ -70,6 +70,10 @@ _sig = {
     "mcmi_cdf_info": [_v, _P(ctypes.c_int64), _P(ctypes.c_int64), _P(ctypes.c_double), _P(ctypes.c_uint64)],
     "mcmi_cdf_download": [_v, _v, _v, _v, _v],
     "mcmi_build_cdf_batched": [_P(CsrIn), ctypes.c_int32, _P(_v), _v],
+    "mcmi_tune": [_v, _P(Params), ctypes.c_int64, ctypes.c_char_p, _P(Params), _P(ctypes.c_double), _v],
+    "mcmi_plan_create": [_v, _P(Params), _v, ctypes.c_int64, _P(_v), _v],
+    "mcmi_plan_launch": [_v, ctypes.c_uint64, _v],
+    "mcmi_plan_result": [_v, _P(CsrOut), _P(Stats), _P(ctypes.c_int32), _v],
     "mcmi_cdf_batch_info": [_v, _P(ctypes.c_int32), _v, _v],
     "mcmi_spai": [_v, _P(Params), _v, _v, ctypes.c_int64, _P(CsrOut), _P(Stats), _v],
     "mcmi_apply": [_P(CsrOut), ctypes.c_int64, _v, _v, _v],
@@ -92,6 +96,8 @@ for _name, _args in _sig.items():
     getattr(_lib, _name).restype = ctypes.c_int
 _lib.mcmi_cdf_free.argtypes = [_v]
 _lib.mcmi_cdf_free.restype = None
+_lib.mcmi_plan_free.argtypes = [_v]
+_lib.mcmi_plan_free.restype = None
 _lib.mcmi_mlp_free.argtypes = [_v]
 _lib.mcmi_mlp_free.restype = None
 _lib.mcmi_csr_free.argtypes = [_P(CsrOut)]
@@ -104,7 +110,8 @@ EXPORTED = ["mcmi_build_cdf", "mcmi_cdf_info", "mcmi_cdf_download", "mcmi_spai",
             "mcmi_row_features", "mcmi_pilot_variance", "mcmi_mlp_create", "mcmi_mlp_free",
             "mcmi_mlp_set_params", "mcmi_mlp_get_params", "mcmi_mlp_set_adam_state", "mcmi_mlp_fit_normalization",
             "mcmi_mlp_predict", "mcmi_mlp_gradient", "mcmi_mlp_train", "mcmi_allocate",
-            "mcmi_build_cdf_batched", "mcmi_cdf_batch_info"]
+            "mcmi_build_cdf_batched", "mcmi_cdf_batch_info", "mcmi_tune", "mcmi_plan_create", "mcmi_plan_launch",
+            "mcmi_plan_result", "mcmi_plan_free"]
 
 
 def _check(st):
@@ -367,3 +374,52 @@ def allocate(pred, cost, budget, stream=None):
     _check(_lib.mcmi_allocate(_ptr(pred), _ptr(cost), ctypes.c_int64(pred.numel()), ctypes.c_int64(int(budget)),
                               _ptr(chains), ctypes.byref(lam), ctypes.byref(fb), _stream(stream)))
     return chains, lam.value, bool(fb.value)
+
+
+def tune(cdf: Cdf, p: Params, sample_rows=8192, cache_path=None, stream=None):
+    """mcmi_tune: (best Params, walk ms of the best candidate)."""
+    best = Params()
+    ms = ctypes.c_double()
+    _check(_lib.mcmi_tune(cdf._h, ctypes.byref(p), ctypes.c_int64(sample_rows),
+                          None if cache_path is None else str(cache_path).encode(), ctypes.byref(best),
+                          ctypes.byref(ms), _stream(stream)))
+    return best, ms.value
+
+
+class Plan:
+    """mcmi_plan: preallocated SPAI with its device work captured in a hipGraph."""
+
+    def __init__(self, cdf: Cdf, p: Params, nnz_capacity, chains_per_row=None, stream=None):
+        self._h = ctypes.c_void_p()
+        self._cdf = cdf
+        self._cpr = chains_per_row
+        _check(_lib.mcmi_plan_create(cdf._h, ctypes.byref(p), _ptr(chains_per_row), ctypes.c_int64(nnz_capacity),
+                                     ctypes.byref(self._h), _stream(stream)))
+
+    def launch(self, seed, stream=None):
+        _check(_lib.mcmi_plan_launch(self._h, ctypes.c_uint64(seed), _stream(stream)))
+
+    def result(self, stream=None):
+        """(rp, col, val) numpy copies, stats, overflow flag."""
+        import torch
+        out, st, ovf = CsrOut(), Stats(), ctypes.c_int32()
+        _check(_lib.mcmi_plan_result(self._h, ctypes.byref(out), ctypes.byref(st), ctypes.byref(ovf), _stream(stream)))
+        if ovf.value:
+            return None, st, True
+        rp = torch.empty(out.n + 1, dtype=torch.int64, device="cuda")
+        col = torch.empty(max(out.nnz, 1), dtype=torch.int32, device="cuda")
+        val = torch.empty(max(out.nnz, 1), dtype=torch.float64, device="cuda")
+        _check(_lib.mcmi_csr_copy(ctypes.byref(out), _ptr(rp), _ptr(col), _ptr(val), _stream(stream)))
+        torch.cuda.current_stream().synchronize()
+        return (rp.cpu().numpy(), col[:out.nnz].cpu().numpy(), val[:out.nnz].cpu().numpy()), st, False
+
+    def free(self):
+        if self._h:
+            _lib.mcmi_plan_free(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass

@@ -43,3 +43,58 @@ def test_batched_blocks_equal_single_matrix_runs(mc, prec, kw):
         sub_val = val[rp[r0]:rp[r1]]
         compare_spai((sub_rp, sub_col, sub_val), orc, o.diag, N)
     assert res.stats.transitions == total
+
+
+# ------------------------------------------------------------ autotuner
+def test_tune_selects_a_valid_shape_and_caches(mc, tmp_path):
+    B = I.random_nonsym(20000, seed=51)
+    cdf = mc.Cdf(mc.DeviceCsr.from_host(B))
+    base = mc.params(seed=3, chains=512, delta=1e-4, eps=1e-3, walk_prec=32)
+    cache = tmp_path / "tune.json"
+    best, ms = mc.tune(cdf, base, sample_rows=2048, cache_path=cache)
+    print(f"[gpu] tuned: lanes={best.lanes_per_row} H={best.hash_slots} sketch={best.sketch_slots} "
+          f"tau={best.heavy_weight} ms={ms:.3f}", flush=True)
+    assert best.lanes_per_row in (64, 256, 512, 1024) and ms > 0
+    assert cache.exists() and "gfx950" in cache.read_text()
+    best2, ms2 = mc.tune(cdf, base, sample_rows=2048, cache_path=cache)
+    assert (best2.lanes_per_row, best2.hash_slots, best2.sketch_slots) == \
+           (best.lanes_per_row, best.hash_slots, best.sketch_slots) and ms2 == pytest.approx(ms, rel=1e-6)
+    rows = np.arange(0, B.n, 97, dtype=np.int32)
+    res = mc.spai(cdf, best, rows=torch.from_numpy(rows).cuda())
+    rp, col, val = res.to_numpy()
+    o = O.Oracle(B)
+    orc = o.spai(seed=3, chains=512, delta=1e-4, eps=1e-3, fp32=True, rows=rows)
+    assert orc["guard"] == 0 and res.stats.transitions == orc["transitions"]
+    compare_spai((rp, col, val), orc, o.diag, 512, rows=rows)
+
+
+# ------------------------------------------------------------ hipGraph plans
+@pytest.mark.parametrize("chains", [64, 512])
+def test_plan_replays_match_eager_runs(mc, chains):
+    """The captured plan is replayed several times with new seeds, with eager
+    library work and synchronisations in between; every replay must equal the
+    eager mcmi_spai result for its seed (same pattern, values to the FP64 bar)."""
+    B = I.random_nonsym(6000, seed=52)
+    cdf = mc.Cdf(mc.DeviceCsr.from_host(B))
+    plan = mc.Plan(cdf, mc.params(seed=0, chains=chains, delta=1e-4, eps=1e-3), nnz_capacity=B.n * 400)
+    for seed in (11, 12, 13):
+        plan.launch(seed)
+        got, st, ovf = plan.result()
+        assert not ovf
+        eager = mc.spai(cdf, mc.params(seed=seed, chains=chains, delta=1e-4, eps=1e-3))
+        rp, col, val = eager.to_numpy()
+        torch.cuda.synchronize()
+        assert st.transitions == eager.stats.transitions
+        assert np.array_equal(got[0], rp) and np.array_equal(got[1], col)
+        assert np.allclose(got[2], val, rtol=1e-12, atol=1e-15)
+    orc = O.Oracle(B).spai(seed=13, chains=chains, delta=1e-4, eps=1e-3)
+    compare_spai(got, orc, O.Oracle(B).diag, chains)
+
+
+def test_plan_reports_overflow(mc):
+    B = I.random_nonsym(3000, seed=53)
+    cdf = mc.Cdf(mc.DeviceCsr.from_host(B))
+    plan = mc.Plan(cdf, mc.params(seed=0, chains=64, delta=1e-4, eps=1e-3), nnz_capacity=1000)
+    plan.launch(5)
+    got, st, ovf = plan.result()
+    assert ovf and got is None
