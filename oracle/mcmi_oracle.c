@@ -277,6 +277,15 @@ static int64_t draw_entry(const orc_mat *A, int64_t s, uint32_t u)
     return -1; /* unreachable: t < W_s = cum of the last entry */
 }
 
+/* Exposed for the pins: the entry of row s (0-based within the row) chosen by
+ * the random word u, or -1 for an empty row. */
+int64_t orc_draw(const orc_mat *A, int64_t s, uint32_t u)
+{
+    if (A->cptr[s + 1] == A->cptr[s])
+        return -1;
+    return draw_entry(A, s, u) - A->cptr[s];
+}
+
 /* One chain: calls visit(ctx, s, W) for every contribution (j = 0 included).
  * Returns the number of transitions (draws). */
 typedef void (*visit_fn)(void *ctx, int64_t s, double w);

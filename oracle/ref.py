@@ -56,6 +56,8 @@ def lib():
         L.orc_features.restype = None
         L.orc_features.argtypes = [ctypes.c_void_p, ctypes.c_double, ctypes.c_int, ctypes.c_void_p]
         L.orc_apply.restype = None
+        L.orc_draw.restype = ctypes.c_int64
+        L.orc_draw.argtypes = [ctypes.c_void_p, ctypes.c_int64, ctypes.c_uint32]
         del i64p
         _lib = L
     return _lib
@@ -145,6 +147,10 @@ class Oracle:
             w = self.row_weights(i).astype(np.float64)
             out[i, self.ccol[b:e]] = np.sign(self.cval[b:e]) * self.shat[i] * w / float(self.wsum[i])
         return out
+
+    def draw(self, row, u):
+        """Entry of `row` (0-based inside the row) chosen by the 32-bit word u."""
+        return int(lib().orc_draw(ctypes.byref(self._mat), int(row), int(u) & 0xFFFFFFFF))
 
     def lmax(self, delta, max_len=0):
         r = lib().orc_lmax(self.norm_inf, float(delta), int(max_len))

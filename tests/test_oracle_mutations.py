@@ -1,0 +1,92 @@
+"""Plant plausible mistakes in a copy of the oracle (on the CPU) and check that the
+pins catch every one: a dropped term, a wrong sign or index, a transposed
+scaling, a non-strict cutoff, a wrong quantization, a wrong Philox constant."""
+import os
+import shutil
+import subprocess
+import sys
+import textwrap
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+MUTATIONS = {
+    "drop_j0_term": ("        double w = 1.0;\n        visit(ctx, s, w);", "        double w = 1.0;\n"),
+    "ignore_sign": ("            w = (A->cval[k] < 0.0) ? -wn : wn;\n            s = A->ccol[k];\n            visit(ctx, s, w);\n            ++steps;\n        }\n    } else {",
+                    "            w = wn;\n            s = A->ccol[k];\n            visit(ctx, s, w);\n            ++steps;\n        }\n    } else {"),
+    "scale_by_row_diag": ("double m = nhat / A->diag[col];", "double m = nhat / A->diag[r];"),
+    "cutoff_not_strict": ("if (fabs(wn) < p->delta)", "if (fabs(wn) <= p->delta)"),
+    "quantize_ceil": ("double scaled = floor(ldexp(ratio, q));", "double scaled = ceil(ldexp(ratio, q));"),
+    "draw_off_by_one": ("if (t < (uint64_t)A->cum[k])", "if (t <= (uint64_t)A->cum[k])"),
+    "shat_is_amax": ("shat[i] = ldexp(amax * (double)run, -q);", "shat[i] = amax;"),
+    "philox_multiplier": ("0xD2511F53u", "0xD2511F55u"),
+}
+
+DRIVER = textwrap.dedent('''
+    import importlib.util, sys, traceback, os, shutil, subprocess, tempfile
+    sys.path.insert(0, sys.argv[1])   # the mutated oracle first
+    sys.path.insert(1, sys.argv[2])   # the repository (inputs)
+    import oracle
+    oracle.build(force=True)
+    spec = importlib.util.spec_from_file_location("pins", os.path.join(sys.argv[2], "tests", "test_oracle_pins.py"))
+    pins = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(pins)
+    calls = [
+        ("p1", lambda: pins.test_p1_diagonal_matrix_gives_exact_inverse_and_no_transitions()),
+        ("p2_nil", lambda: pins.test_p2_nilpotent_shift_equals_triangular_solve()),
+        ("p2_cyc", lambda: pins.test_p2_scaled_cycle_closed_form(-0.7)),
+        ("p3", lambda: pins.test_p3_torus_row_sums_and_exact_transition_count()),
+        ("p5", lambda: pins.test_p5_converges_to_numpy_inverse(1)),
+        ("p6", lambda: pins.test_p6_matches_exact_rational_expectation("tiny3_signed")),
+        ("quant", lambda: pins.test_cdf_quantization_bounds()),
+        ("quant_exact", lambda: pins.test_integer_weights_are_exact_floors()),
+        ("strict", lambda: pins.test_cutoff_is_strict_when_weight_equals_delta()),
+        ("draw", lambda: pins.test_draw_boundaries_match_closed_form()),
+    ]
+    hipcc = shutil.which("hipcc") or "/opt/rocm/bin/hipcc"
+    if os.path.exists(hipcc):
+        d = tempfile.mkdtemp()
+        src = os.path.join(d, "rr.cpp")
+        open(src, "w").write(pins.ROCRAND_PROBE)
+        exe = os.path.join(d, "rr")
+        if subprocess.call([hipcc, "-O1", "-o", exe, src], stdout=subprocess.DEVNULL, stderr=subprocess.DEVNULL) == 0:
+            calls.append(("p12", lambda: pins.test_p12_philox_matches_rocrand(exe)))
+    failed = []
+    for name, fn in calls:
+        try:
+            fn()
+        except Exception:
+            failed.append(name)
+    print("FAILED:" + ",".join(failed))
+''')
+
+
+@pytest.mark.slow
+@pytest.mark.parametrize("name", sorted(MUTATIONS))
+def test_planted_mistake_is_caught(name, tmp_path):
+    old, new = MUTATIONS[name]
+    dst = tmp_path / "oracle"
+    shutil.copytree(os.path.join(ROOT, "oracle"), dst, ignore=shutil.ignore_patterns("*.so", "__pycache__"))
+    src = (dst / "mcmi_oracle.c").read_text()
+    assert src.count(old) >= 1, "mutation anchor not found"
+    (dst / "mcmi_oracle.c").write_text(src.replace(old, new, 1))
+    drv = tmp_path / "drive.py"
+    drv.write_text(DRIVER)
+    out = subprocess.run([sys.executable, str(drv), str(tmp_path), ROOT], capture_output=True, text=True,
+                         timeout=600)
+    line = [l for l in out.stdout.splitlines() if l.startswith("FAILED:")]
+    assert line, out.stdout[-2000:] + out.stderr[-2000:]
+    caught = [x for x in line[-1][len("FAILED:"):].split(",") if x]
+    print(f"{name}: caught by {caught}")
+    assert caught, f"mutation {name} passed every pin"
+
+
+def test_unmutated_oracle_passes_the_driver(tmp_path):
+    dst = tmp_path / "oracle"
+    shutil.copytree(os.path.join(ROOT, "oracle"), dst, ignore=shutil.ignore_patterns("*.so", "__pycache__"))
+    drv = tmp_path / "drive.py"
+    drv.write_text(DRIVER)
+    out = subprocess.run([sys.executable, str(drv), str(tmp_path), ROOT], capture_output=True, text=True,
+                         timeout=600)
+    assert "FAILED:" in out.stdout and out.stdout.strip().splitlines()[-1] == "FAILED:", out.stdout[-2000:]

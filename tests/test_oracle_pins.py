@@ -392,3 +392,51 @@ def test_neyman_allocation_budget():
     n_r, lam = O.allocate(pred, cost, 3 * 150)
     assert (n_r * cost).sum() <= 450 and n_r.min() >= 1
     assert np.all(np.diff(n_r) >= 0)
+
+
+# ------------------------------------------------- exact rules of the sampler
+def test_cutoff_is_strict_when_weight_equals_delta():
+    """Every row of C has |C| row sum exactly 1/2 (dyadic entries, so Chat = C) and
+    delta = 1/8: weights 1/2, 1/4, 1/8 continue (1/8 is not < 1/8) and the chain
+    stops before the draw that would give 1/16: exactly 3 transitions per chain,
+    and each row of the estimate sums to 1 + 1/2 + 1/4 + 1/8."""
+    C = np.array([[0, 0.25, 0.25], [0.5, 0, 0], [0.25, 0.25, 0]])
+    d = np.array([2.0, -1.0, 4.0])
+    B = I.from_dense(d[:, None] * (np.eye(3) - C))
+    N = 40
+    r = O.Oracle(B).spai(seed=3, chains=N, delta=0.125, eps=0.0)
+    assert np.all(r["row_transitions"] == 3 * N)
+    M = dense_M(r, 3)
+    assert np.allclose((M * d[None, :]).sum(axis=1), 1.875, rtol=1e-15)
+
+
+def test_draw_boundaries_match_closed_form():
+    """The draw picks the first k with t < cum_k, t = floor(u W / 2^32): the smallest
+    u reaching cum_k is u* = ceil(cum_k 2^32 / W) (integer arithmetic), so u* - 1
+    must give entry k and u* entry k + 1."""
+    B = I.random_nonsym(50, seed=17)
+    o = O.Oracle(B)
+    for row in range(0, 50, 7):
+        b, e = o.cptr[row], o.cptr[row + 1]
+        W = int(o.wsum[row])
+        cum = [int(x) for x in o.cum[b:e]]
+        for k in range(len(cum) - 1):
+            ustar = -(-(cum[k] << 32) // W)
+            assert o.draw(row, ustar - 1) == k
+            assert o.draw(row, ustar) == k + 1
+        assert o.draw(row, 0) == 0 and o.draw(row, 0xFFFFFFFF) == len(cum) - 1
+
+
+def test_integer_weights_are_exact_floors():
+    """w_k = max(1, floor(2^Q a_k / a_max)) checked in exact rational arithmetic on
+    the binary64 values of |c_k| and a_max (rows with non-dyadic ratios)."""
+    B = I.random_nonsym(300, seed=19)
+    o = O.Oracle(B)
+    for row in range(0, 300, 11):
+        b, e = o.cptr[row], o.cptr[row + 1]
+        a = [Fraction(abs(float(x))) for x in o.cval[b:e]]
+        amax = max(a)
+        m = len(a)
+        q = 31 - (m - 1).bit_length()
+        want = [max(1, int(x / amax * 2 ** q)) for x in a]
+        assert list(o.row_weights(row)) == want
