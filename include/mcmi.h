@@ -95,7 +95,7 @@ typedef struct {
     int32_t lanes_per_row;/* 0 = automatic; 64 = one wavefront per row; 256, 512 or 1024 =
                              one workgroup of that many lanes per row */
     int32_t hash_slots;   /* 0 = automatic; else LDS hash slots per row (power of two) */
-    int32_t sketch_slots; /* 0 = automatic; else count-sketch buckets per row (power of two) */
+    int32_t sketch_slots; /* 0 = automatic; else count-sketch buckets per row (64..16384) */
     int32_t pool_per_row; /* 0 = automatic; else first guess of kept entries per row: rows that
                              do not fit are rerun into a second pool sized exactly */
     double heavy_weight;  /* workgroup-per-row kernel only. 0 = automatic; < 0 = track every

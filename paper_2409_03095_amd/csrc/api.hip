@@ -99,7 +99,10 @@ mcmi_status choose_shape(const mcmi_cdf *cdf, const mcmi_params *p, int lmax, Ke
             }
             if (std::min(total, (double)cdf->n) > 0.5 * H) tau = std::pow(S, std::max(J, 1)) * (1.0 - 1.0 / 1048576.0);
         }
-        if (tau > 0.0) sketch = p->sketch_slots ? p->sketch_slots : 8192;
+        // default sketch: the largest that still lets two workgroups share a CU's LDS
+        if (tau > 0.0)
+            sketch = p->sketch_slots ? p->sketch_slots
+                                     : (int)std::max<int64_t>(1024, ((int64_t)81920 - (int64_t)H * 12 - 256) / 4);
     }
     out.lanes = lanes;
     out.hash = H;
@@ -157,9 +160,8 @@ extern "C" mcmi_status mcmi_spai(const mcmi_cdf *cdf, const mcmi_params *p, cons
         return fail(MCMI_ERR_ARG, "mcmi_spai: spill_slots must be a power of two >= 16");
     if (p->hash_slots && (p->hash_slots < 64 || p->hash_slots > 8192 || (p->hash_slots & (p->hash_slots - 1))))
         return fail(MCMI_ERR_ARG, "mcmi_spai: hash_slots must be a power of two in [64, 8192]");
-    if (p->sketch_slots && (p->sketch_slots < 64 || p->sketch_slots > 16384 ||
-                            (p->sketch_slots & (p->sketch_slots - 1))))
-        return fail(MCMI_ERR_ARG, "mcmi_spai: sketch_slots must be a power of two in [64, 16384]");
+    if (p->sketch_slots && (p->sketch_slots < 64 || p->sketch_slots > 16384))
+        return fail(MCMI_ERR_ARG, "mcmi_spai: sketch_slots must be in [64, 16384]");
     if (p->lanes_per_row && p->lanes_per_row != 64 && p->lanes_per_row != 256 && p->lanes_per_row != 512 &&
         p->lanes_per_row != 1024)
         return fail(MCMI_ERR_ARG, "mcmi_spai: lanes_per_row must be 0, 64, 256, 512 or 1024");
@@ -349,7 +351,6 @@ extern "C" mcmi_status mcmi_spai(const mcmi_cdf *cdf, const mcmi_params *p, cons
         a.tau = tau;
         a.tau32 = (float)tau;
         a.sketch_slots = sketch;
-        a.sketch_shift = sketch ? 32 - __builtin_ctz((unsigned)sketch) : 0;
         if (pass == 0) MCMI_HIP(hipEventRecord(ev1, s));
         if (block_kernel)
             MCMI_HIP(launch_walk_block(a, f32, lanes, (int)blocks, s));

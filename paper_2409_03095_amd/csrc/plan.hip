@@ -153,9 +153,9 @@ extern "C" mcmi_status mcmi_tune(const mcmi_cdf *cdf, const mcmi_params *base, i
     for (int lanes : {256, 512, 1024})
         for (int hash : {2048, 4096})
             if (walk_block_supported(lanes, hash))
-                for (int sk : {4096, 8192}) {
+                for (int sk : {0, 4096, 8192}) {       // 0: the largest sketch leaving 2 workgroups per CU
                     cands.push_back({lanes, hash, sk, 0.0});  // automatic tau
-                    cands.push_back({lanes, hash, sk, -1.0}); // track everything
+                    if (sk == 0) cands.push_back({lanes, hash, sk, -1.0});  // track everything
                 }
     double best_t = 1e300;
     Cand win = cands[0];
@@ -327,7 +327,6 @@ extern "C" mcmi_status mcmi_plan_create(const mcmi_cdf *cdf, const mcmi_params *
     a.tau = pl->shape.tau;
     a.tau32 = (float)pl->shape.tau;
     a.sketch_slots = pl->shape.sketch;
-    a.sketch_shift = pl->shape.sketch ? 32 - __builtin_ctz((unsigned)pl->shape.sketch) : 0;
 
     hipStream_t cs;
     TRYP(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));

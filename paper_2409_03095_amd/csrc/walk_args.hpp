@@ -44,8 +44,7 @@ struct WalkArgs {
     // LDS hash; lighter ones only update tracked columns or the count sketch
     double tau;                    // 0: track every contribution
     float tau32;
-    int32_t sketch_slots;          // power of two (0 when tau == 0)
-    int32_t sketch_shift;          // 32 - log2(sketch_slots)
+    int32_t sketch_slots;          // count-sketch buckets (0 when tau == 0)
 };
 
 }  // namespace mcmi

@@ -105,13 +105,13 @@ __device__ __forceinline__ void light_add(const WalkArgs &a, const RowCtx &rc, i
     }
     double mag = fabs(w);
     if (a.filter_m) mag = mag / fabs(a.diag[key]);
-    atomicAdd(&rc.sketch[bucket_of(key, a.sketch_shift)], (float)mag);
+    atomicAdd(&rc.sketch[bucket_of(key, (uint32_t)a.sketch_slots)], (float)mag);
 }
 
 // refine: track light contributions of columns whose bucket failed the bound
 __device__ __forceinline__ void refine_add(const WalkArgs &a, const RowCtx &rc, int32_t key, double w,
                                            bool &spill_full, unsigned long long &spilled) {
-    if (rc.sketch[bucket_of(key, a.sketch_shift)] < rc.hot_thr) return;
+    if (rc.sketch[bucket_of(key, (uint32_t)a.sketch_slots)] < rc.hot_thr) return;
     const int32_t rkey = (int32_t)((uint32_t)key | kRBit);
     const uint32_t hmask = (uint32_t)a.hash_slots - 1u;
     uint32_t h = hash_key(key, a.hash_shift);

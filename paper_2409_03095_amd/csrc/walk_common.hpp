@@ -55,10 +55,11 @@ __device__ __forceinline__ bool spill_add(int32_t *keys, double *vals, int32_t *
     return false;
 }
 
-// Fibonacci hash of a column into the count-sketch buckets (independent of the
-// slot hash, which uses a different multiplier).
-__device__ __forceinline__ uint32_t bucket_of(int32_t key, int shift) {
-    return ((uint32_t)key * 0x9E3779B1u ^ 0x5bd1e995u) * 0x85EBCA77u >> shift;
+// Hash of a column onto the count-sketch buckets [0, nb) by a multiply-high
+// (any bucket count, independent of the slot hash's multiplier).
+__device__ __forceinline__ uint32_t bucket_of(int32_t key, uint32_t nb) {
+    const uint32_t h = ((uint32_t)key * 0x9E3779B1u ^ 0x5bd1e995u) * 0x85EBCA77u;
+    return __umulhi(h, nb);
 }
 
 // Philox row and tag words of the chains of global row r
