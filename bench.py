@@ -83,6 +83,10 @@ def main():
     ap.add_argument("--lanes", type=int, default=0)
     ap.add_argument("--sketch-slots", type=int, default=0)
     ap.add_argument("--heavy-weight", type=float, default=0.0)
+    ap.add_argument("--workload", default="random", choices=["random", "aniso27"],
+                    help="random: n=262144 random nonsymmetric (default); aniso27: 160^3 27-point anisotropic")
+    ap.add_argument("--nx", type=int, default=160, help="grid side of the aniso27 workload")
+    ap.add_argument("--bicgstab", action="store_true", help="aniso27: host BiCGstab iterations with and without M")
     ap.add_argument("--learned", action="store_true",
                     help="learned vs uniform chains to ||I-MB||_F/sqrt(n) <= 0.3 (allocation-network workload)")
     ap.add_argument("--train-mats", type=int, default=2000)
@@ -105,6 +109,8 @@ def main():
         return learned_main(args)
 
     delta, eps, seed = 1e-4, 1e-3, 0
+    if args.workload == "aniso27":
+        return aniso_main(args)
     B = I.cfg2(args.n)
     dB = mcmi.DeviceCsr.from_host(B)
     x = torch.ones(B.n, dtype=torch.float64, device="cuda")
@@ -147,13 +153,25 @@ def main():
     total_trans = float(sum(trans))
     value = total_trans / elapsed
 
+    # memory ceiling of the access pattern: dependent pointer chase over a buffer of
+    # the record set's size with the walk's two 64-byte requests per step
+    probe = {}
+    cdf0 = mcmi.Cdf(dB)
+    for wpc in (8, 16, 32):
+        ms_p, rate = mcmi.gather_probe(cdf0.rec_units, 2, 256, wpc)
+        probe[str(wpc)] = rate
+    del cdf0
+    ceiling = max(probe.values())
+
     bpt = algorithmic_bytes_per_transition(B, args.prec == 32)
     walk_s = float(np.mean(walk_ms)) / 1e3
     achieved = bpt * trans[-1] / walk_s / 1e9
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": TRAFFIC_BYTES,
                 "kernel": "k_walk", "bytes_per_transition": round(bpt, 2),
-                "walk_ms": round(walk_s * 1e3, 3), "walk_transitions_per_s": trans[-1] / walk_s}
+                "walk_ms": round(walk_s * 1e3, 3), "walk_transitions_per_s": trans[-1] / walk_s,
+                "gather_ceiling_steps_per_s": ceiling, "gather_probe_by_waves_per_cu": probe,
+                "frac_of_gather_ceiling": round(trans[-1] / walk_s / ceiling, 4)}
     out = {
         "metric": METRIC,
         "value": value,
@@ -177,6 +195,76 @@ def main():
     }
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(B, args.chains, delta, eps, args.prec == 32)
+    print(json.dumps(out), flush=True)
+
+
+def aniso_main(args):
+    """3D 27-point anisotropic diffusion (1:10:100, +-10 % noise, ||C||_inf = 0.75) on
+    an nx^3 grid, 64 chains/row, FP32 walks + FP64 sums, delta = 1e-4, eps = 1e-3."""
+    import torch
+
+    from paper_2409_03095_amd import inputs as I
+    from paper_2409_03095_amd import mcmi
+    t0 = time.perf_counter()
+    B = I.cfg5(args.nx)
+    print(f"[aniso27] generated n={B.n} nnz={B.nnz} in {time.perf_counter() - t0:.1f} s", flush=True)
+    dB = mcmi.DeviceCsr.from_host(B)
+    chains = args.chains if args.chains != 512 else 64
+    p = mcmi.params(seed=0, chains=chains, delta=1e-4, eps=1e-3, walk_prec=args.prec, lanes_per_row=args.lanes,
+                    hash_slots=args.hash_slots, sketch_slots=args.sketch_slots, heavy_weight=args.heavy_weight)
+    x = torch.ones(B.n, dtype=torch.float64, device="cuda")
+    y = torch.empty(B.n, dtype=torch.float64, device="cuda")
+    for _ in range(args.warmup):
+        cdf = mcmi.Cdf(dB)
+        res = mcmi.spai(cdf, p)
+        del cdf, res
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    walk_ms = []
+    for _ in range(args.steps):
+        cdf = mcmi.Cdf(dB)
+        res = mcmi.spai(cdf, p)
+        res.apply(x, y)
+        walk_ms.append(res.stats.ms_walk)
+        last = res
+        rec_units = cdf.rec_units
+        del cdf
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    st = last.stats
+    ms_p, ceiling = mcmi.gather_probe(rec_units, 2, 128, 16)
+    m = np.maximum(np.diff(B.row_ptr) - 1, 1)
+    bpt = float(np.mean((16.0 if args.prec == 32 else 24.0) + 4.0 * (np.ceil(np.log2(m)) + 1.0) + 4.0))
+    walk_s = float(np.mean(walk_ms)) / 1e3
+    out = {"metric": METRIC, "value": st.transitions * args.steps / elapsed, "unit": "transitions/s", "n_gpus": 1,
+           "steps": args.steps, "warmup": args.warmup, "ms_per_step": elapsed / args.steps * 1e3,
+           "higher_is_better": True, "dtype": "f32" if args.prec == 32 else "f64", "data": "synthetic",
+           "config": {"workload": f"3D 27-point anisotropic {args.nx}^3", "n": B.n, "nnz_B": B.nnz,
+                      "chains_per_row": chains, "transitions_per_step": int(st.transitions), "nnz_M": int(last.nnz),
+                      "lanes_per_row": st.lanes_per_row, "hash_slots": st.hash_slots, "spilled": int(st.spilled),
+                      "retries": int(st.retries), "record_bytes": int(rec_units) * 64},
+           "roofline": {"bound": "hbm", "achieved": round(bpt * st.transitions / walk_s / 1e9, 1), "peak": HBM_PEAK_GBS,
+                        "unit": "GB/s", "frac": round(bpt * st.transitions / walk_s / 1e9 / HBM_PEAK_GBS, 4),
+                        "bytes_per_transition": round(bpt, 2), "walk_ms": round(walk_s * 1e3, 3),
+                        "walk_transitions_per_s": st.transitions / walk_s, "gather_ceiling_steps_per_s": ceiling}}
+    if args.bicgstab:
+        import scipy.sparse as sp
+        import scipy.sparse.linalg as spla
+        rp, col, val = last.to_numpy()
+        M = sp.csr_matrix((val, col, rp), shape=(B.n, B.n))
+        Bs = B.to_scipy()
+        b = Bs @ np.ones(B.n)
+        res_it = {}
+        for name, pre in (("none", None), ("mcmi", spla.LinearOperator(Bs.shape, matvec=lambda v: M @ v)),
+                          ("jacobi", spla.LinearOperator(Bs.shape, matvec=lambda v: v / Bs.diagonal()))):
+            it = [0]
+            t1 = time.perf_counter()
+            xs, info = spla.bicgstab(Bs, b, x0=np.zeros(B.n), rtol=1e-8, maxiter=5000, M=pre,
+                                     callback=lambda _: it.__setitem__(0, it[0] + 1))
+            res_it[name] = {"iterations": it[0], "info": int(info), "seconds": time.perf_counter() - t1,
+                            "rel_residual": float(np.linalg.norm(b - Bs @ xs) / np.linalg.norm(b))}
+            print(f"[aniso27] bicgstab {name}: {res_it[name]}", flush=True)
+        out["bicgstab"] = res_it
     print(json.dumps(out), flush=True)
 
 

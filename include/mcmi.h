@@ -265,6 +265,15 @@ mcmi_status mcmi_plan_launch(mcmi_plan *plan, uint64_t seed, void *stream);
 mcmi_status mcmi_plan_result(mcmi_plan *plan, mcmi_csr_out *M_view, mcmi_stats *st, int32_t *overflow, void *stream);
 void mcmi_plan_free(mcmi_plan *plan);
 
+/* Memory ceiling of the walk's access pattern: a pointer chase over `units`
+ * random 64-byte units (a buffer the size of a record set) in which every step
+ * makes reqs_per_step dependent 64-byte reads, on waves_per_cu wavefronts per CU,
+ * without the method's arithmetic. Returns the kernel time and the steps per
+ * second (the rate a walk with that many dependent requests per transition can
+ * at most reach). Allocates and synchronises. */
+mcmi_status mcmi_gather_probe(uint64_t units, int32_t reqs_per_step, int32_t steps, int32_t waves_per_cu,
+                              double *ms_out, double *steps_per_s_out);
+
 /* Copy M into caller-owned device buffers (row_ptr n+1, col nnz, val nnz). */
 mcmi_status mcmi_csr_copy(const mcmi_csr_out *M, int64_t *row_ptr_dev, int32_t *col_dev,
                           double *val_dev, void *stream);

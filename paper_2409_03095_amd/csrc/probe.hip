@@ -1,0 +1,82 @@
+// Dependent random-gather probe (gfx950): the memory ceiling of the walk's
+// access pattern without the method's arithmetic.
+//
+// A buffer of `units` 64-byte units holds random unit indices. Each lane runs a
+// pointer chase in which every step issues `reqs` dependent 64-byte reads (one
+// 16-byte load each, at the unit the previous read named), exactly like a walk
+// step reads its header unit and then its group unit. The measured steps per
+// second is the ceiling a walk with the same number of dependent requests per
+// transition can reach on this chip, for a record set of the same size.
+#include <string>
+
+#include "common.hpp"
+
+namespace mcmi {
+namespace {
+
+__global__ void k_probe_fill(uint4 *buf, uint64_t units, uint32_t seed) {
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t u = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; u < units; u += stride) {
+        const u32x4 r = philox4x32_10((uint32_t)u, (uint32_t)(u >> 32), 0x50524F42u, 0u, seed, 0x9E3779B9u);
+        const uint32_t next = (uint32_t)(((uint64_t)r.x * units) >> 32);
+        uint4 *p = buf + u * 4;
+        p[0] = make_uint4(next, r.y, r.z, r.w);
+        p[1] = make_uint4(next, 0u, 0u, 0u);
+        p[2] = make_uint4(next, 0u, 0u, 0u);
+        p[3] = make_uint4(next, 0u, 0u, 0u);
+    }
+}
+
+__global__ void __launch_bounds__(256) k_probe_chase(const uint4 *buf, uint64_t units, int reqs, int steps,
+                                                     unsigned long long *sink) {
+    const uint64_t tid = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    uint32_t cur = (uint32_t)((tid * 2654435761ull) % units);
+    uint32_t acc = 0;
+    for (int s = 0; s < steps; ++s) {
+        for (int q = 0; q < reqs; ++q) {
+            const uint4 v = buf[(uint64_t)cur * 4 + (q & 3)];
+            cur = v.x ^ (acc & 1u);      // dependent next index (acc keeps it live)
+            if (cur >= units) cur -= (uint32_t)units;
+            acc += v.y;
+        }
+    }
+    if (acc == 0xFFFFFFFFu) atomicAdd(sink, 1ull);
+}
+
+}  // namespace
+}  // namespace mcmi
+
+using namespace mcmi;
+
+extern "C" mcmi_status mcmi_gather_probe(uint64_t units, int32_t reqs_per_step, int32_t steps, int32_t waves_per_cu,
+                                         double *ms_out, double *steps_per_s_out) {
+    if (units < 1024 || units >= (1ull << 32) || reqs_per_step < 1 || steps < 1 || waves_per_cu < 1)
+        return fail(MCMI_ERR_ARG, "mcmi_gather_probe: bad argument");
+    uint4 *buf = nullptr;
+    unsigned long long *sink = nullptr;
+    MCMI_HIP(hipMalloc(&buf, units * 64));
+    if (hipMalloc(&sink, 8) != hipSuccess) {
+        (void)hipFree(buf);
+        return fail(MCMI_ERR_NOMEM, "mcmi_gather_probe: alloc");
+    }
+    k_probe_fill<<<4096, 256>>>(buf, units, 12345u);
+    const int blocks = device_cus() * waves_per_cu / 4;
+    hipEvent_t a, b;
+    (void)hipEventCreate(&a);
+    (void)hipEventCreate(&b);
+    k_probe_chase<<<blocks, 256>>>(buf, units, reqs_per_step, steps / 4 + 1, sink);  // warm-up
+    (void)hipEventRecord(a, nullptr);
+    k_probe_chase<<<blocks, 256>>>(buf, units, reqs_per_step, steps, sink);
+    (void)hipEventRecord(b, nullptr);
+    hipError_t e = hipEventSynchronize(b);
+    float ms = 0.f;
+    (void)hipEventElapsedTime(&ms, a, b);
+    (void)hipEventDestroy(a);
+    (void)hipEventDestroy(b);
+    (void)hipFree(buf);
+    (void)hipFree(sink);
+    if (e != hipSuccess) return fail(MCMI_ERR_HIP, std::string("mcmi_gather_probe: ") + hipGetErrorString(e));
+    if (ms_out) *ms_out = ms;
+    if (steps_per_s_out) *steps_per_s_out = (double)blocks * 256.0 * (double)steps / (ms * 1e-3);
+    return MCMI_OK;
+}
