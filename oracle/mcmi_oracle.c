@@ -21,7 +21,9 @@
  *   O6  finalize           N_rc = acc / N_r; keep iff c = r or |N_rc| >= eps;
  *                          M_rc = N_rc / d_c (column scaling by the diagonal)
  *   O7  apply              y = M x
- * plus the two per-row side products of the learned allocation:
+ * an optional pre-pass before O1 (orc_prepare: the alpha-augmented diagonal of
+ * Section III-B / V-C and the matrix reduction of Algorithm 1 step 2), and
+ * the two per-row side products of the learned allocation:
  *   pilot variance (total variance of a chain's row estimate, mean chain length)
  *   row features (8 per row).
  *
@@ -137,6 +139,132 @@ int orc_count_c(int64_t n, const int64_t *rp, const int32_t *ci, const double *v
                 total += 1;
     }
     *nnz_c = total;
+    return ORC_OK;
+}
+
+/* ----------------------------------------- phase 1 and matrix reduction
+ * Optional pre-pass that turns B into B' before O1 (B' is CSR with ascending
+ * columns and a stored diagonal in every row; capacity of ci2/v2: nnz + n):
+ *  - augmentation, the splitting of Section III-B (b^_ii = b_ii + alpha ||B||)
+ *    with the sign rule of Section V-C:
+ *        b'_ii = b_ii + s_i * (alpha * ||B||_inf),  s_i = -1 if b_ii < 0, else +1,
+ *    a missing diagonal counting as b_ii = 0; ||B||_inf = max over rows of the
+ *    row's sum of |b_ij| taken in column order. alpha = 0 leaves B alone.
+ *  - reduction, Algorithm 1 step 2 and Section V-A (drop a set share of the
+ *    smallest entries of the iteration matrix): the K = floor(drop_frac * cnt)
+ *    smallest of the cnt nonzero off-diagonal |c_ij| = |(-b_ij) / b'_ii| go; the
+ *    cut is the (K+1)-th smallest value, entries strictly below it are removed
+ *    and entries equal to it stay (so ties never split). drop_frac = 0 keeps all.
+ * Explicit zeros off the diagonal are removed (they give c = 0 anyway). */
+static int cmp_f64(const void *a, const void *b)
+{
+    double x = *(const double *)a, y = *(const double *)b;
+    return (x > y) - (x < y);
+}
+
+int orc_prepare(int64_t n, const int64_t *rp, const int32_t *ci, const double *v, double alpha,
+                double drop_frac, int64_t *rp2, int32_t *ci2, double *v2, double *norm_b,
+                double *thr_out, int64_t *dropped)
+{
+    if (n <= 0 || !rp || !ci || !v || !rp2 || !ci2 || !v2)
+        return ORC_ERR_ARG;
+    if (!(alpha >= 0.0) || !(drop_frac >= 0.0 && drop_frac < 1.0))
+        return ORC_ERR_ARG;
+    if (rp[0] != 0)
+        return ORC_ERR_CSR;
+    for (int64_t i = 0; i < n; ++i) {
+        if (rp[i + 1] < rp[i])
+            return ORC_ERR_CSR;
+        for (int64_t k = rp[i]; k < rp[i + 1]; ++k) {
+            if (ci[k] < 0 || ci[k] >= n)
+                return ORC_ERR_CSR;
+            if (k > rp[i] && ci[k] <= ci[k - 1])
+                return ORC_ERR_CSR;
+        }
+    }
+    double nrm = 0.0;
+    for (int64_t i = 0; i < n; ++i) {
+        double s = 0.0;
+        for (int64_t k = rp[i]; k < rp[i + 1]; ++k)
+            s += fabs(v[k]);
+        if (s > nrm)
+            nrm = s;
+    }
+    double aug = alpha * nrm;
+    double *dh = (double *)malloc((size_t)n * sizeof(double));
+    if (!dh)
+        return ORC_ERR_NOMEM;
+    for (int64_t i = 0; i < n; ++i) {
+        double d = 0.0;
+        for (int64_t k = rp[i]; k < rp[i + 1]; ++k)
+            if (ci[k] == i)
+                d = v[k];
+        if (alpha > 0.0)
+            d = d + (d < 0.0 ? -aug : aug);
+        if (d == 0.0) {
+            free(dh);
+            return ORC_ERR_ZERO_DIAG;
+        }
+        dh[i] = d;
+    }
+    double thr = 0.0;
+    if (drop_frac > 0.0) {
+        int64_t cnt = 0;
+        double *mag = (double *)malloc((size_t)(rp[n] > 0 ? rp[n] : 1) * sizeof(double));
+        if (!mag) {
+            free(dh);
+            return ORC_ERR_NOMEM;
+        }
+        for (int64_t i = 0; i < n; ++i)
+            for (int64_t k = rp[i]; k < rp[i + 1]; ++k) {
+                if (ci[k] == i)
+                    continue;
+                double c = (-v[k]) / dh[i];
+                if (c != 0.0)
+                    mag[cnt++] = fabs(c);
+            }
+        if (cnt > 0) {
+            qsort(mag, (size_t)cnt, sizeof(double), cmp_f64);
+            int64_t K = (int64_t)floor(drop_frac * (double)cnt);
+            thr = mag[K];
+        }
+        free(mag);
+    }
+    int64_t pos = 0, nd = 0;
+    for (int64_t i = 0; i < n; ++i) {
+        rp2[i] = pos;
+        int placed = 0;
+        for (int64_t k = rp[i]; k < rp[i + 1]; ++k) {
+            if (ci[k] == i)
+                continue;
+            if (!placed && ci[k] > i) {
+                ci2[pos] = (int32_t)i;
+                v2[pos++] = dh[i];
+                placed = 1;
+            }
+            double c = (-v[k]) / dh[i];
+            if (c == 0.0)
+                continue;
+            if (fabs(c) < thr) {
+                ++nd;
+                continue;
+            }
+            ci2[pos] = ci[k];
+            v2[pos++] = v[k];
+        }
+        if (!placed) {
+            ci2[pos] = (int32_t)i;
+            v2[pos++] = dh[i];
+        }
+    }
+    rp2[n] = pos;
+    free(dh);
+    if (norm_b)
+        *norm_b = nrm;
+    if (thr_out)
+        *thr_out = thr;
+    if (dropped)
+        *dropped = nd;
     return ORC_OK;
 }
 

@@ -58,6 +58,10 @@ def lib():
         L.orc_apply.restype = None
         L.orc_draw.restype = ctypes.c_int64
         L.orc_draw.argtypes = [ctypes.c_void_p, ctypes.c_int64, ctypes.c_uint32]
+        L.orc_prepare.restype = ctypes.c_int
+        L.orc_prepare.argtypes = [ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_double,
+                                  ctypes.c_double, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                  ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]
         del i64p
         _lib = L
     return _lib
@@ -100,15 +104,38 @@ def default_threads() -> int:
     return max(1, min(16, os.cpu_count() or 1))
 
 
-class Oracle:
-    """Iteration matrix C and its integer CDF for one input B (O1, O2)."""
+def prepare(B, alpha=0.0, drop_frac=0.0):
+    """orc_prepare: B' (row_ptr, col, val) with the augmented diagonal and the
+    reduced entries, plus (||B||_inf, cut, number dropped)."""
+    L = lib()
+    n = int(B.n)
+    rp = np.ascontiguousarray(B.row_ptr, dtype=np.int64)
+    ci = np.ascontiguousarray(B.col, dtype=np.int32)
+    v = np.ascontiguousarray(B.val, dtype=np.float64)
+    rp2 = np.zeros(n + 1, dtype=np.int64)
+    ci2 = np.zeros(rp[-1] + n, dtype=np.int32)
+    v2 = np.zeros(rp[-1] + n, dtype=np.float64)
+    nrm, thr, nd = ctypes.c_double(0.0), ctypes.c_double(0.0), ctypes.c_int64(0)
+    _check(L.orc_prepare(ctypes.c_int64(n), _p(rp), _p(ci), _p(v), float(alpha), float(drop_frac), _p(rp2), _p(ci2),
+                         _p(v2), ctypes.byref(nrm), ctypes.byref(thr), ctypes.byref(nd)))
+    e = int(rp2[-1])
+    return (rp2, ci2[:e].copy(), v2[:e].copy()), (nrm.value, thr.value, nd.value)
 
-    def __init__(self, B):
+
+class Oracle:
+    """Iteration matrix C and its integer CDF for one input B (O1, O2), after the
+    optional pre-pass (alpha-augmented diagonal, matrix reduction)."""
+
+    def __init__(self, B, alpha=0.0, drop_frac=0.0):
         L = lib()
         self.n = int(B.n)
-        rp = np.ascontiguousarray(B.row_ptr, dtype=np.int64)
-        ci = np.ascontiguousarray(B.col, dtype=np.int32)
-        v = np.ascontiguousarray(B.val, dtype=np.float64)
+        self.norm_b, self.drop_thr, self.dropped = 0.0, 0.0, 0
+        if alpha or drop_frac:
+            (rp, ci, v), (self.norm_b, self.drop_thr, self.dropped) = prepare(B, alpha, drop_frac)
+        else:
+            rp = np.ascontiguousarray(B.row_ptr, dtype=np.int64)
+            ci = np.ascontiguousarray(B.col, dtype=np.int32)
+            v = np.ascontiguousarray(B.val, dtype=np.float64)
         nnz_c = ctypes.c_int64(0)
         _check(L.orc_count_c(ctypes.c_int64(self.n), _p(rp), _p(ci), _p(v), ctypes.byref(nnz_c)))
         m = nnz_c.value

@@ -272,6 +272,29 @@ def block_diag(mats) -> Csr:
 
 
 # ---------------------------------------------------------------- pin matrices
+def nonddm(n: int, seed: int, k: int = 6) -> Csr:
+    """A general (not diagonally dominant) sparse B for the augmented splitting:
+    k off-diagonals per row at distinct random columns, lognormal(0, 1) magnitudes
+    with random signs, diagonals of random sign and magnitude in [0.1, 1]; row 1
+    stores an explicit zero diagonal and row 2 stores no diagonal at all."""
+    rng = np.random.default_rng(seed)
+    rows, cols, vals = [], [], []
+    for i in range(n):
+        others = rng.choice(n - 1, size=min(k, n - 1), replace=False)
+        others = others + (others >= i)
+        mags = rng.lognormal(0.0, 1.0, size=others.size) * np.where(rng.random(others.size) < 0.5, -1.0, 1.0)
+        rows.extend([i] * others.size)
+        cols.extend(others.tolist())
+        vals.extend(mags.tolist())
+        if i == 2:
+            continue
+        d = 0.0 if i == 1 else rng.uniform(0.1, 1.0) * (-1.0 if rng.random() < 0.5 else 1.0)
+        rows.append(i)
+        cols.append(i)
+        vals.append(d)
+    return from_coo(n, np.array(rows), np.array(cols), np.array(vals))
+
+
 def diag_only(n: int, seed: int = 0) -> Csr:
     """B diagonal (so C = 0), diagonal values of both signs."""
     rng = np.random.default_rng(seed)

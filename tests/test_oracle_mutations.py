@@ -1,6 +1,8 @@
 """Plant plausible mistakes in a copy of the oracle (on the CPU) and check that the
 pins catch every one: a dropped term, a wrong sign or index, a transposed
-scaling, a non-strict cutoff, a wrong quantization, a wrong Philox constant."""
+scaling, a non-strict cutoff, a wrong quantization, a wrong Philox constant,
+a pre-pass that ignores the diagonal's sign, uses another norm or cuts at the
+wrong rank."""
 import os
 import shutil
 import subprocess
@@ -21,6 +23,10 @@ MUTATIONS = {
     "draw_off_by_one": ("if (t < (uint64_t)A->cum[k])", "if (t <= (uint64_t)A->cum[k])"),
     "shat_is_amax": ("shat[i] = ldexp(amax * (double)run, -q);", "shat[i] = amax;"),
     "philox_multiplier": ("0xD2511F53u", "0xD2511F55u"),
+    "aug_ignores_sign": ("d = d + (d < 0.0 ? -aug : aug);", "d = d + aug;"),
+    "aug_norm_is_max_entry": ("s += fabs(v[k]);", "s = fabs(v[k]) > s ? fabs(v[k]) : s;"),
+    "drop_cut_off_by_one": ("thr = mag[K];", "thr = mag[K > 0 ? K - 1 : 0];"),
+    "drop_keeps_ties_out": ("if (fabs(c) < thr) {", "if (fabs(c) <= thr && thr > 0.0) {"),
 }
 
 DRIVER = textwrap.dedent('''
@@ -43,6 +49,9 @@ DRIVER = textwrap.dedent('''
         ("quant_exact", lambda: pins.test_integer_weights_are_exact_floors()),
         ("strict", lambda: pins.test_cutoff_is_strict_when_weight_equals_delta()),
         ("draw", lambda: pins.test_draw_boundaries_match_closed_form()),
+        ("aug", lambda: pins.test_augmented_splitting_equals_the_hand_built_matrix()),
+        ("reduce", lambda: pins.test_reduction_drops_the_smallest_share_of_the_iteration_matrix()),
+        ("compose", lambda: pins.test_augmentation_then_reduction_compose()),
     ]
     hipcc = shutil.which("hipcc") or "/opt/rocm/bin/hipcc"
     if os.path.exists(hipcc):

@@ -440,3 +440,115 @@ def test_integer_weights_are_exact_floors():
         q = 31 - (m - 1).bit_length()
         want = [max(1, int(x / amax * 2 ** q)) for x in a]
         assert list(o.row_weights(row)) == want
+
+
+# ------------------------------- pre-pass: augmented diagonal and reduction
+def _csr_rows(B):
+    for i in range(B.n):
+        b, e = int(B.row_ptr[i]), int(B.row_ptr[i + 1])
+        yield i, B.col[b:e], B.val[b:e]
+
+
+def _hand_augmented(B, alpha):
+    """B-hat of the Section III-B splitting with the Section V-C sign rule, built
+    entry by entry in Python: ||B||_inf as plain sequential sums of |b_ij| in column
+    order, b_ii + alpha ||B|| for b_ii >= 0 (a missing diagonal is 0), b_ii - alpha
+    ||B|| for b_ii < 0."""
+    nrm = 0.0
+    for _, _, v in _csr_rows(B):
+        s = 0.0
+        for x in v:
+            s += abs(float(x))
+        nrm = max(nrm, s)
+    a = alpha * nrm
+    rows, cols, vals = [], [], []
+    for i, c, v in _csr_rows(B):
+        d = 0.0
+        for cc, vv in zip(c, v):
+            if cc == i:
+                d = float(vv)
+            else:
+                rows.append(i)
+                cols.append(int(cc))
+                vals.append(float(vv))
+        rows.append(i)
+        cols.append(i)
+        vals.append(d - a if d < 0.0 else d + a)
+    return I.from_coo(B.n, np.array(rows), np.array(cols), np.array(vals)), nrm
+
+
+def _same_records(o1, o2):
+    assert o1.nnz_c == o2.nnz_c
+    for f in ("cptr", "ccol", "cval", "cum", "wsum", "shat", "diag"):
+        assert np.array_equal(getattr(o1, f), getattr(o2, f)), f
+    assert o1.norm_inf == o2.norm_inf
+
+
+def test_augmented_splitting_equals_the_hand_built_matrix():
+    """Section III-B splitting B = B-hat - (B-hat - B) with b-hat_ii = b_ii + alpha
+    ||B|| sgn(b_ii) (Section V-C): the pre-pass must give exactly the records and
+    the estimate of the matrix built by hand, and C of B-hat is contractive with
+    ||C||_inf <= 1/alpha because every off-diagonal row sum is at most ||B||_inf."""
+    B = I.nonddm(60, seed=4)
+    with pytest.raises(O.OracleError):
+        O.Oracle(B)  # zero and missing diagonals: phase 1 is required
+    for alpha in (1.5, 5.0):
+        Bh, nrm = _hand_augmented(B, alpha)
+        o1, o2 = O.Oracle(B, alpha=alpha), O.Oracle(Bh)
+        assert o1.norm_b == nrm and o1.dropped == 0
+        _same_records(o1, o2)
+        assert o1.norm_inf <= 1.0 / alpha
+        r1 = o1.spai(seed=3, chains=64, delta=1e-6, eps=1e-3)
+        r2 = o2.spai(seed=3, chains=64, delta=1e-6, eps=1e-3)
+        for f in ("row_ptr", "col", "val"):
+            assert np.array_equal(r1[f], r2[f]), f
+    # a mixed-sign diagonal keeps its sign and moves away from zero
+    d = np.array([float(v[c == i][0]) if (c == i).any() else 0.0 for i, c, v in _csr_rows(B)])
+    oh = O.Oracle(B, alpha=5.0)
+    assert np.all(np.sign(oh.diag) == np.where(d < 0.0, -1.0, 1.0))
+    assert np.all(np.abs(oh.diag) >= 5.0 * oh.norm_b)
+
+
+def _hand_reduced(B, frac):
+    """Algorithm 1 step 2 on the iteration matrix: rank the nonzero off-diagonal
+    |c_ij| = |(-b_ij) / b_ii| (numpy), K = floor(frac * count), cut = the (K+1)-th
+    smallest, remove entries below the cut."""
+    d = np.zeros(B.n)
+    r_of = np.repeat(np.arange(B.n), np.diff(B.row_ptr))
+    on = B.col == r_of
+    d[r_of[on]] = B.val[on]
+    c = (-B.val) / d[r_of]
+    off = (~on) & (c != 0.0)
+    mags = np.sort(np.abs(c[off]))
+    K = int(math.floor(frac * float(mags.size)))
+    cut = mags[K]
+    keep = on | (off & (np.abs(c) >= cut))
+    return I.from_coo(B.n, r_of[keep], B.col[keep], B.val[keep]), cut, K, mags
+
+
+def test_reduction_drops_the_smallest_share_of_the_iteration_matrix():
+    """Algorithm 1 step 2 / Section V-A: with distinct magnitudes exactly K =
+    floor(frac * nnz(C)) entries go, namely the smallest |c|; the pre-pass equals
+    running on the hand-reduced matrix; ties at the cut are kept (a uniform stencil
+    loses nothing)."""
+    B = I.random_nonsym(3000, seed=7)
+    for frac in (0.02, 0.1, 0.5):
+        Br, cut, K, mags = _hand_reduced(B, frac)
+        assert np.unique(mags).size == mags.size  # distinct: the closed form K holds
+        o1, o2 = O.Oracle(B, drop_frac=frac), O.Oracle(Br)
+        assert o1.dropped == K and o1.drop_thr == cut
+        assert o1.nnz_c == mags.size - K
+        _same_records(o1, o2)
+    g = I.cfg1()
+    og = O.Oracle(g, drop_frac=0.5)
+    assert og.dropped == 0 and og.nnz_c == O.Oracle(g).nnz_c
+
+
+def test_augmentation_then_reduction_compose():
+    """Both pre-passes together: the cut is taken on C of the augmented matrix."""
+    B = I.nonddm(80, seed=9)
+    Bh, _ = _hand_augmented(B, 5.0)
+    Br, cut, K, _ = _hand_reduced(Bh, 0.25)
+    o1, o2 = O.Oracle(B, alpha=5.0, drop_frac=0.25), O.Oracle(Br)
+    assert o1.dropped == K and o1.drop_thr == cut
+    _same_records(o1, o2)
