@@ -154,23 +154,25 @@ def main():
     value = total_trans / elapsed
 
     # memory ceiling of the access pattern: dependent pointer chase over a buffer of
-    # the record set's size with the walk's two 64-byte requests per step
+    # the record set's size with the walk's two 64-byte requests per step, reading
+    # one 16-byte quarter (loads=1) or the whole unit (loads=4) per request
     probe = {}
     cdf0 = mcmi.Cdf(dB)
-    for wpc in (8, 16, 32):
-        ms_p, rate = mcmi.gather_probe(cdf0.rec_units, 2, 256, wpc)
-        probe[str(wpc)] = rate
+    for loads in (1, 4):
+        for wpc in (8, 16, 32):
+            ms_p, rate = mcmi.gather_probe(cdf0.rec_units, 2, 256, wpc, loads)
+            probe[f"loads{loads}_wpc{wpc}"] = rate
     del cdf0
-    ceiling = max(probe.values())
+    ceiling = max(v for k, v in probe.items() if k.startswith("loads1_"))
 
     bpt = algorithmic_bytes_per_transition(B, args.prec == 32)
     walk_s = float(np.mean(walk_ms)) / 1e3
     achieved = bpt * trans[-1] / walk_s / 1e9
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": TRAFFIC_BYTES,
-                "kernel": "k_walk", "bytes_per_transition": round(bpt, 2),
+                "kernel": "k_walk_block", "bytes_per_transition": round(bpt, 2),
                 "walk_ms": round(walk_s * 1e3, 3), "walk_transitions_per_s": trans[-1] / walk_s,
-                "gather_ceiling_steps_per_s": ceiling, "gather_probe_by_waves_per_cu": probe,
+                "gather_ceiling_steps_per_s": ceiling, "gather_probe": probe,
                 "frac_of_gather_ceiling": round(trans[-1] / walk_s / ceiling, 4)}
     out = {
         "metric": METRIC,

@@ -106,7 +106,11 @@ typedef struct {
                              the certificate are replayed exactly). Needs ||Chat||_inf < 1. */
     int32_t spill_slots;  /* 0 = automatic; else HBM overflow-table slots per row in flight
                              (power of two); rows that overflow it are rerun with it grown */
-    int32_t reserved;     /* must be zero */
+    int32_t topk;         /* 0 = off; > 0: top-k retention (Section IV-B keeps a prescribed
+                             number of the entries largest in magnitude): of the entries that
+                             pass the eps filter, the diagonal and the topk - 1 off-diagonal
+                             entries with the largest filter value (|N_rc|, or |M_rc| under
+                             MCMI_FILTER_M) are kept, equal values by ascending column */
 } mcmi_params;
 
 typedef struct {
@@ -134,6 +138,32 @@ typedef struct {
  * validation flags and the record sizes, and once more for ||Chat||_inf.
  * *out is allocated by the library; free it with mcmi_cdf_free. */
 mcmi_status mcmi_build_cdf(const mcmi_csr_in *B, mcmi_cdf **out, void *stream);
+
+/* Optional pre-pass on B before the records are built (both off when zero). */
+typedef struct {
+    /* Phase 1, the splitting B = B^ - (B^ - B) of Section III-B with the sign rule
+     * of Section V-C: b^_ii = b_ii + s_i * (alpha * ||B||_inf), s_i = -1 when
+     * b_ii < 0, else +1; a missing diagonal counts as 0, so such rows are allowed.
+     * ||B||_inf is the largest row sum of |b_ij| (each row summed in column order).
+     * C of B^ then has ||C||_inf <= 1/alpha, and M approximates the inverse of B^
+     * (the paper's recovery phase 5 is not applied). */
+    double alpha;
+    /* Matrix reduction (Algorithm 1 step 2, Section V-A): with cnt nonzero
+     * off-diagonal entries of C and K = floor(drop_frac * cnt), the cut is the
+     * (K+1)-th smallest |c_ij|; entries with |c_ij| below it are removed before the
+     * CDF is built (entries equal to the cut stay). 0 <= drop_frac < 1. */
+    double drop_frac;
+    int64_t reserved[2]; /* must be 0 */
+} mcmi_cdf_opts;
+
+/* mcmi_build_cdf with the pre-pass of `opts` (NULL: none). The augmentation adds
+ * one stream synchronisation, the reduction an 8-pass radix selection over a
+ * temporary key per entry of B and one more. */
+mcmi_status mcmi_build_cdf_ex(const mcmi_csr_in *B, const mcmi_cdf_opts *opts, mcmi_cdf **out, void *stream);
+
+/* What the pre-pass did: ||B||_inf (0 without augmentation), the reduction cut on
+ * |c| (0 without reduction) and the number of entries of C it removed. */
+mcmi_status mcmi_cdf_prep_info(const mcmi_cdf *cdf, double *norm_b, double *drop_thr, int64_t *dropped);
 
 /* Records of `count` matrices in one block-diagonal row space (the batched
  * launch): matrix k occupies rows [base_k, base_k + n_k) and its columns are
@@ -267,12 +297,35 @@ void mcmi_plan_free(mcmi_plan *plan);
 
 /* Memory ceiling of the walk's access pattern: a pointer chase over `units`
  * random 64-byte units (a buffer the size of a record set) in which every step
- * makes reqs_per_step dependent 64-byte reads, on waves_per_cu wavefronts per CU,
- * without the method's arithmetic. Returns the kernel time and the steps per
- * second (the rate a walk with that many dependent requests per transition can
- * at most reach). Allocates and synchronises. */
-mcmi_status mcmi_gather_probe(uint64_t units, int32_t reqs_per_step, int32_t steps, int32_t waves_per_cu,
-                              double *ms_out, double *steps_per_s_out);
+ * makes reqs_per_step dependent reads of one unit each, a read being
+ * loads_per_req (1..4) 16-byte loads of that unit, on waves_per_cu wavefronts per
+ * CU, without the method's arithmetic. Returns the kernel time and the steps per
+ * second (the rate a walk with that many dependent requests and loads per
+ * transition can at most reach). Allocates and synchronises. */
+mcmi_status mcmi_gather_probe(uint64_t units, int32_t reqs_per_step, int32_t loads_per_req, int32_t steps,
+                              int32_t waves_per_cu, double *ms_out, double *steps_per_s_out);
+
+/* Result of mcmi_bicgstab. */
+typedef struct {
+    int64_t iterations;   /* BiCGstab iterations made (a converged half step counts as one) */
+    double rel_residual;  /* ||r|| / ||b|| of the recurrence residual at exit */
+    double ms;            /* device time of the solve */
+    int32_t converged;    /* 1 when ||r|| <= rtol ||b|| was reached */
+    int32_t pad;
+} mcmi_solve_stats;
+
+/* Solve B x = b with BiCGstab (van der Vorst), M applied on the right as the
+ * preconditioner (the use of M that Section III-B and the solver experiments of
+ * Section VI make of it); M = NULL solves without one. B is a borrowed device
+ * CSR (as for mcmi_build_cdf), M a result of mcmi_spai; b_dev (n, read) and
+ * x_dev (n, in: initial guess, out: solution) are device float64 vectors. Stops
+ * when ||r|| <= rtol ||b|| for the recurrence residual r, or after maxiter
+ * iterations, or on a breakdown (a zero inner product); then converged = 0 and x
+ * holds the last iterate. Dot products reduce in a fixed order, so a rerun gives
+ * the same iterates. Allocates 8 n float64 of workspace; synchronises the stream
+ * once per inner product. */
+mcmi_status mcmi_bicgstab(const mcmi_csr_in *B, const mcmi_csr_out *M, const double *b_dev, double *x_dev,
+                          double rtol, int32_t maxiter, mcmi_solve_stats *st, void *stream);
 
 /* Copy M into caller-owned device buffers (row_ptr n+1, col nnz, val nnz). */
 mcmi_status mcmi_csr_copy(const mcmi_csr_out *M, int64_t *row_ptr_dev, int32_t *col_dev,

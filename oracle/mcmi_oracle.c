@@ -19,7 +19,8 @@
  *                          the draw) or the row of C is empty
  *   O5  accumulate         sum of W_j over chains per (r, s_j), long double
  *   O6  finalize           N_rc = acc / N_r; keep iff c = r or |N_rc| >= eps;
- *                          M_rc = N_rc / d_c (column scaling by the diagonal)
+ *                          M_rc = N_rc / d_c (column scaling by the diagonal);
+ *                          optionally only the k largest per row (Section IV-B)
  *   O7  apply              y = M x
  * an optional pre-pass before O1 (orc_prepare: the alpha-augmented diagonal of
  * Section III-B / V-C and the matrix reduction of Algorithm 1 step 2), and
@@ -363,6 +364,7 @@ typedef struct {
     uint32_t tag;         /* fourth Philox counter word */
     int32_t threads;
     int32_t filter_on_m;  /* 1: keep iff |M_rc| >= eps instead of |N_rc| >= eps */
+    int32_t topk;         /* > 0: keep at most topk entries per row (see O6) */
 } orc_params;
 
 /* Draw step j >= 1 of chain c of row r: returns the chosen entry index of row s. */
@@ -494,6 +496,7 @@ typedef struct {
     uint32_t *cnt;
     int64_t guard;
     int64_t transitions;
+    int32_t ambig;
 } row_out;
 
 typedef struct {
@@ -520,6 +523,84 @@ static int64_t take_rows(spai_job *job, int64_t want, int64_t *begin)
     pthread_mutex_unlock(&job->lock);
     *begin = b;
     return e - b;
+}
+
+/* Top-k retention (Section IV-B: only a prescribed number of the entries
+ * largest in magnitude are retained per row). Of the entries that passed the
+ * eps rule, the diagonal stays and the topk - 1 off-diagonal entries with the
+ * largest test value (|N_rc|, or |M_rc| with filter_on_m) stay; equal values go
+ * by ascending column. The row is marked ambiguous when the last kept and the
+ * first dropped entry are within the sum-order band of each other (sums of at
+ * most two terms are order-free and have no band), so that another summation
+ * order could swap them. Entries stay in column order. */
+typedef struct {
+    double test;
+    int32_t col;
+    int64_t idx;
+} top_item;
+
+static int cmp_top(const void *a, const void *b)
+{
+    const top_item *x = (const top_item *)a, *y = (const top_item *)b;
+    if (x->test != y->test)
+        return x->test > y->test ? -1 : 1;
+    return (x->col > y->col) - (x->col < y->col);
+}
+
+static double order_band(uint32_t cnt, double abssum, int32_t nr, double scale)
+{
+    if (cnt <= 2)
+        return 0.0;
+    return 4.0 * ((double)cnt + 2.0) * ldexp(1.0, -53) * abssum / (double)nr * scale;
+}
+
+static int keep_top(const orc_mat *A, const orc_params *p, int64_t r, int32_t nr, row_out *ro, const double *tv)
+{
+    int64_t nc = 0;
+    top_item *it = (top_item *)malloc((size_t)(ro->nnz + 1) * sizeof(top_item));
+    char *sel = (char *)calloc((size_t)(ro->nnz + 1), 1);
+    if (!it || !sel) {
+        free(it);
+        free(sel);
+        return -1;
+    }
+    for (int64_t q = 0; q < ro->nnz; ++q) {
+        if (ro->col[q] == r) {
+            sel[q] = 1;
+            continue;
+        }
+        it[nc].test = tv[q];
+        it[nc].col = ro->col[q];
+        it[nc].idx = q;
+        ++nc;
+    }
+    qsort(it, (size_t)nc, sizeof(top_item), cmp_top);
+    int64_t want = (int64_t)p->topk - 1;
+    for (int64_t q = 0; q < nc && q < want; ++q)
+        sel[it[q].idx] = 1;
+    if (want >= 1 && nc > want) {
+        const top_item *a = &it[want - 1], *b = &it[want];
+        double sa = p->filter_on_m ? 1.0 / fabs(A->diag[a->col]) : 1.0;
+        double sb = p->filter_on_m ? 1.0 / fabs(A->diag[b->col]) : 1.0;
+        double band = order_band(ro->cnt[a->idx], ro->abssum[a->idx], nr, sa) +
+                      order_band(ro->cnt[b->idx], ro->abssum[b->idx], nr, sb);
+        if (band > 0.0 && fabs(a->test - b->test) <= band)
+            ro->ambig = 1;
+    }
+    int64_t w = 0;
+    for (int64_t q = 0; q < ro->nnz; ++q) {
+        if (!sel[q])
+            continue;
+        ro->col[w] = ro->col[q];
+        ro->val[w] = ro->val[q];
+        ro->abssum[w] = ro->abssum[q];
+        ro->cnt[w] = ro->cnt[q];
+        ++w;
+    }
+    ro->nnz = w;
+    free(it);
+    free(sel);
+    return 0;
 }
 
 static void *spai_worker(void *arg)
@@ -558,7 +639,9 @@ static void *spai_worker(void *arg)
             ro->val = (double *)malloc((size_t)(ra.ntouched + 1) * sizeof(double));
             ro->abssum = (double *)malloc((size_t)(ra.ntouched + 1) * sizeof(double));
             ro->cnt = (uint32_t *)malloc((size_t)(ra.ntouched + 1) * sizeof(uint32_t));
-            if (!ro->col || !ro->val || !ro->abssum || !ro->cnt) {
+            double *tv = (double *)malloc((size_t)(ra.ntouched + 1) * sizeof(double));
+            if (!ro->col || !ro->val || !ro->abssum || !ro->cnt || !tv) {
+                free(tv);
                 job->failed = 1;
                 goto done;
             }
@@ -579,6 +662,7 @@ static void *spai_worker(void *arg)
                 if (col != r && fabs(test - p->eps) <= band)
                     ro->guard += 1;
                 if (keep) {
+                    tv[kept] = test;
                     ro->col[kept] = col;
                     ro->val[kept] = m;
                     ro->abssum[kept] = ra.abssum[col];
@@ -590,6 +674,13 @@ static void *spai_worker(void *arg)
                 ra.cnt[col] = 0;
             }
             ro->nnz = kept;
+            ro->ambig = 0;
+            int top_failed = p->topk > 0 && keep_top(A, p, r, nr, ro, tv) != 0;
+            free(tv);
+            if (top_failed) {
+                job->failed = 1;
+                goto done;
+            }
         }
     }
 done:
@@ -611,6 +702,7 @@ typedef struct {
     uint64_t transitions;
     int64_t guard;
     int32_t lmax;
+    int32_t *row_ambig;   /* nrows: 1 where the top-k boundary is order-dependent */
 } orc_result;
 
 static int run_threads(void *(*fn)(void *), void *job, int threads)
@@ -645,7 +737,7 @@ int orc_spai(const orc_mat *A, const orc_params *p, const int32_t *rows, int64_t
         return ORC_ERR_ARG;
     if (!rows)
         nrows = A->n;
-    if (nrows < 0 || p->eps < 0.0 || !(p->delta >= 0.0))
+    if (nrows < 0 || p->eps < 0.0 || !(p->delta >= 0.0) || p->topk < 0)
         return ORC_ERR_ARG;
     if (!chains_per_row && p->chains < 1)
         return ORC_ERR_ARG;
@@ -685,7 +777,9 @@ int orc_spai(const orc_mat *A, const orc_params *p, const int32_t *rows, int64_t
     res->abssum = (double *)malloc((size_t)(total + 1) * sizeof(double));
     res->cnt = (uint32_t *)malloc((size_t)(total + 1) * sizeof(uint32_t));
     res->row_transitions = (int64_t *)malloc((size_t)(nrows + 1) * sizeof(int64_t));
-    if (!res->row_ptr || !res->col || !res->val || !res->abssum || !res->cnt || !res->row_transitions)
+    res->row_ambig = (int32_t *)malloc((size_t)(nrows + 1) * sizeof(int32_t));
+    if (!res->row_ptr || !res->col || !res->val || !res->abssum || !res->cnt || !res->row_transitions ||
+        !res->row_ambig)
         status = ORC_ERR_NOMEM;
     int64_t pos = 0;
     for (int64_t t = 0; t < nrows; ++t) {
@@ -700,6 +794,7 @@ int orc_spai(const orc_mat *A, const orc_params *p, const int32_t *rows, int64_t
             }
             pos += ro->nnz;
             res->row_transitions[t] = ro->transitions;
+            res->row_ambig[t] = ro->ambig;
             res->transitions += (uint64_t)ro->transitions;
             res->guard += ro->guard;
         }
@@ -724,6 +819,7 @@ void orc_result_free(orc_result *res)
     free(res->abssum);
     free(res->cnt);
     free(res->row_transitions);
+    free(res->row_ambig);
     memset(res, 0, sizeof(*res));
 }
 

@@ -80,7 +80,8 @@ class _Mat(ctypes.Structure):
 class _Params(ctypes.Structure):
     _fields_ = [("seed", ctypes.c_uint64), ("delta", ctypes.c_double), ("eps", ctypes.c_double),
                 ("chains", ctypes.c_int32), ("fp32", ctypes.c_int32), ("max_len", ctypes.c_int32),
-                ("tag", ctypes.c_uint32), ("threads", ctypes.c_int32), ("filter_on_m", ctypes.c_int32)]
+                ("tag", ctypes.c_uint32), ("threads", ctypes.c_int32), ("filter_on_m", ctypes.c_int32),
+                ("topk", ctypes.c_int32)]
 
 
 class _Result(ctypes.Structure):
@@ -88,7 +89,7 @@ class _Result(ctypes.Structure):
                 ("col", ctypes.POINTER(ctypes.c_int32)), ("val", ctypes.POINTER(ctypes.c_double)),
                 ("abssum", ctypes.POINTER(ctypes.c_double)), ("cnt", ctypes.POINTER(ctypes.c_uint32)),
                 ("row_transitions", ctypes.POINTER(ctypes.c_int64)), ("transitions", ctypes.c_uint64),
-                ("guard", ctypes.c_int64), ("lmax", ctypes.c_int32)]
+                ("guard", ctypes.c_int64), ("lmax", ctypes.c_int32), ("row_ambig", ctypes.POINTER(ctypes.c_int32))]
 
 
 class OracleError(RuntimeError):
@@ -184,18 +185,19 @@ class Oracle:
         _check(r if r < 0 else 0)
         return r
 
-    def _params(self, seed, chains, delta, eps, fp32, max_len, tag, threads, filter_on_m):
+    def _params(self, seed, chains, delta, eps, fp32, max_len, tag, threads, filter_on_m, topk=0):
         return _Params(int(seed) & 0xFFFFFFFFFFFFFFFF, float(delta), float(eps), int(chains), int(bool(fp32)),
                        int(max_len), int(tag) & 0xFFFFFFFF,
-                       int(threads if threads else default_threads()), int(bool(filter_on_m)))
+                       int(threads if threads else default_threads()), int(bool(filter_on_m)), int(topk))
 
     def spai(self, seed=0, chains=16, delta=1e-3, eps=1e-3, fp32=False, max_len=0, tag=0,
-             rows=None, chains_per_row=None, threads=None, filter_on_m=False):
+             rows=None, chains_per_row=None, threads=None, filter_on_m=False, topk=0):
         """O3-O6 for all rows (rows=None) or the listed rows, in the given order.
 
         Returns a dict: row_ptr, col, val (M rows), abssum/cnt (per kept entry: sum of
-        |W| and number of contributions), row_transitions, transitions, guard, lmax."""
-        prm = self._params(seed, chains, delta, eps, fp32, max_len, tag, threads, filter_on_m)
+        |W| and number of contributions), row_transitions, transitions, guard, lmax,
+        row_ambig (top-k boundary order-dependent, per row)."""
+        prm = self._params(seed, chains, delta, eps, fp32, max_len, tag, threads, filter_on_m, topk)
         rows_arr = None if rows is None else np.ascontiguousarray(rows, dtype=np.int32)
         cpr = None if chains_per_row is None else np.ascontiguousarray(chains_per_row, dtype=np.int32)
         res = _Result()
@@ -218,6 +220,7 @@ class Oracle:
                 "transitions": int(res.transitions),
                 "guard": int(res.guard),
                 "lmax": int(res.lmax),
+                "row_ambig": np.ctypeslib.as_array(res.row_ambig, shape=(max(nr, 1),))[:nr].copy(),
             }
         finally:
             lib().orc_result_free(ctypes.byref(res))

@@ -154,7 +154,7 @@ extern "C" mcmi_status mcmi_spai(const mcmi_cdf *cdf, const mcmi_params *p, cons
         return fail(MCMI_ERR_ARG, "mcmi_spai: walk_prec must be 64 or 32");
     if (!(p->eps >= 0.0) || !(p->delta >= 0.0)) return fail(MCMI_ERR_ARG, "mcmi_spai: eps and delta must be >= 0");
     if (p->filter != MCMI_FILTER_N && p->filter != MCMI_FILTER_M) return fail(MCMI_ERR_ARG, "mcmi_spai: bad filter");
-    if (p->reserved) return fail(MCMI_ERR_ARG, "mcmi_spai: reserved != 0");
+    if (p->topk < 0) return fail(MCMI_ERR_ARG, "mcmi_spai: topk < 0");
     if (p->pool_per_row < 0) return fail(MCMI_ERR_ARG, "mcmi_spai: pool_per_row must be >= 0");
     if (p->spill_slots && (p->spill_slots < 16 || (p->spill_slots & (p->spill_slots - 1))))
         return fail(MCMI_ERR_ARG, "mcmi_spai: spill_slots must be a power of two >= 16");
@@ -206,8 +206,9 @@ extern "C" mcmi_status mcmi_spai(const mcmi_cdf *cdf, const mcmi_params *p, cons
     int waves = 4;
     int spill_slots = p->spill_slots ? p->spill_slots : (block_kernel ? 16384 : 4096);
     // first guess of the output size; rows that do not fit are rerun into a new pool
-    int64_t pool_cap = n_tasks * (p->pool_per_row ? p->pool_per_row
-                                                  : (block_kernel ? std::min(H, 256) : std::min(H / 2, 128)));
+    int64_t per_row = p->pool_per_row ? p->pool_per_row : (block_kernel ? std::min(H, 256) : std::min(H / 2, 128));
+    if (!p->pool_per_row && p->topk > 0) per_row = std::min<int64_t>(per_row, p->topk);  // exact bound
+    int64_t pool_cap = n_tasks * per_row;
     pool_cap = std::min<int64_t>(pool_cap, (int64_t)1 << 30);
     if (!p->pool_per_row) pool_cap = std::max<int64_t>(pool_cap, 1 << 16);
     pool_cap = std::max<int64_t>(pool_cap, 1);
@@ -333,6 +334,7 @@ extern "C" mcmi_status mcmi_spai(const mcmi_cdf *cdf, const mcmi_params *p, cons
         a.eps = p->eps;
         a.lmax = lmax;
         a.filter_m = p->filter == MCMI_FILTER_M;
+        a.topk = p->topk;
         a.hash_slots = H;
         a.hash_shift = 32 - __builtin_ctz((unsigned)H);
         a.queue_ctr = qctr;

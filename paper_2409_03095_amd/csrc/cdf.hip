@@ -21,9 +21,88 @@ __device__ __forceinline__ int ceil_log2_u32(uint32_t m) {
     return q;
 }
 
+// An off-diagonal quotient c is an entry of C when it is nonzero and, with a
+// reduction cut, |c| is not below the cut (compared as the bits of |c|, which
+// order non-negative doubles like their values).
+__device__ __forceinline__ bool keep_c(double c, const unsigned long long *cut) {
+    return c != 0.0 && (!cut || (unsigned long long)__double_as_longlong(fabs(c)) >= *cut);
+}
+
+// ||B||_inf for the augmented splitting: each thread sums one row's |b_ij| in
+// column order (one IEEE add at a time, so the sums are those of a sequential
+// loop), the maximum is an integer max on the bits of the non-negative sums.
+__global__ void __launch_bounds__(256) k_row_abs_max(int64_t n, const int64_t *__restrict__ rp,
+                                                     const double *__restrict__ v, unsigned long long *bits) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    double best = 0.0;
+    for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < n; r += stride) {
+        double sum = 0.0;
+        for (int64_t k = rp[r]; k < rp[r + 1]; ++k) sum += fabs(v[k]);
+        best = sum > best ? sum : best;
+    }
+    best = wave_max(best);
+    if ((threadIdx.x & 63) == 0) atomicMax(bits, (unsigned long long)__double_as_longlong(best));
+}
+
+// Reduction keys: the bits of |c| for every entry of C, all ones for the rest
+// (diagonal, zero quotients), in B's entry order.
+__global__ void __launch_bounds__(256) k_cut_keys(int64_t n, const int64_t *__restrict__ rp,
+                                                  const int32_t *__restrict__ ci, const double *__restrict__ v,
+                                                  const double *__restrict__ diag, unsigned long long *__restrict__ keys) {
+    const int lane = threadIdx.x & 63;
+    const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
+    for (int64_t r = wave; r < n; r += nwaves) {
+        const double d = diag[r];
+        for (int64_t k = rp[r] + lane; k < rp[r + 1]; k += 64) {
+            const double c = (int64_t)ci[k] != r ? (-v[k]) / d : 0.0;
+            keys[k] = c != 0.0 ? (unsigned long long)__double_as_longlong(fabs(c)) : ~0ull;
+        }
+    }
+}
+
+// Radix selection of the key of rank sel[1] (0-based), 8 bits per pass from the
+// top: sel[0] holds the bits fixed so far. Each pass histograms the next digit of
+// the keys that match them (LDS histogram per workgroup), then one thread fixes
+// the digit and the rank inside it.
+__global__ void __launch_bounds__(256) k_radix_hist(const unsigned long long *__restrict__ keys, int64_t nk,
+                                                    int shift, const unsigned long long *__restrict__ sel,
+                                                    unsigned long long *__restrict__ hist) {
+    __shared__ unsigned int h[256];
+    for (int i = threadIdx.x; i < 256; i += blockDim.x) h[i] = 0u;
+    __syncthreads();
+    const unsigned long long prefix = sel[0];
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nk; i += stride) {
+        const unsigned long long key = keys[i];
+        if (shift == 56 || (key >> (shift + 8)) == (prefix >> (shift + 8)))
+            atomicAdd(&h[(key >> shift) & 255u], 1u);
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < 256; i += blockDim.x)
+        if (h[i]) atomicAdd(&hist[i], (unsigned long long)h[i]);
+}
+
+__global__ void k_radix_pick(unsigned long long *sel, unsigned long long *hist, int shift) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    const unsigned long long rank = sel[1];
+    unsigned long long below = 0;
+    for (int dgt = 0; dgt < 256; ++dgt) {
+        const unsigned long long c = hist[dgt];
+        if (rank < below + c) {
+            sel[0] |= (unsigned long long)dgt << shift;
+            sel[1] = rank - below;
+            break;
+        }
+        below += c;
+    }
+    for (int dgt = 0; dgt < 256; ++dgt) hist[dgt] = 0ull;
+}
+
 // Validate row r of B, find its diagonal and count its nonzero off-diagonals.
 __global__ void __launch_bounds__(256) k_count(int64_t n, int64_t nnz, const int64_t *__restrict__ rp,
                                                const int32_t *__restrict__ ci, const double *__restrict__ v,
+                                               double aug, const unsigned long long *__restrict__ cut,
                                                uint32_t *__restrict__ mrow, uint32_t *__restrict__ units,
                                                double *__restrict__ diag, uint32_t *__restrict__ flags) {
     const int lane = threadIdx.x & 63;
@@ -53,16 +132,18 @@ __global__ void __launch_bounds__(256) k_count(int64_t n, int64_t nnz, const int
         }
         const uint64_t fb = ballot(found);
         const uint64_t bb = ballot(bad);
-        const double d = fb ? __shfl(dv, __builtin_ctzll(fb), 64) : 0.0;
+        double d = fb ? __shfl(dv, __builtin_ctzll(fb), 64) : 0.0;
+        if (aug > 0.0) d = d + (d < 0.0 ? -aug : aug);  // augmented splitting (a missing diagonal is 0)
         // entries of C: off-diagonals whose quotient (-b_ij) / b_ii is nonzero
+        // and not below the reduction cut
         uint32_t cnt = 0;
-        if (fb && d != 0.0)
+        if (d != 0.0)
             for (int64_t k = b + lane; k < e; k += 64)
-                if ((int64_t)ci[k] != r && (-v[k]) / d != 0.0) ++cnt;
+                if ((int64_t)ci[k] != r && keep_c((-v[k]) / d, cut)) ++cnt;
         cnt = wave_sum(cnt);
         if (lane == 0) {
             if (bb) atomicOr(flags, kFlagCsr);
-            if (!fb || d == 0.0) atomicOr(flags, kFlagZeroDiag);
+            if (d == 0.0) atomicOr(flags, kFlagZeroDiag);
             mrow[r] = cnt;
             units[r] = record_units(cnt);
             diag[r] = d;
@@ -76,6 +157,7 @@ __global__ void __launch_bounds__(256) k_fill(int64_t n, const int64_t *__restri
                                               const int32_t *__restrict__ ci, const double *__restrict__ v,
                                               const double *__restrict__ diag, const uint32_t *__restrict__ mrow,
                                               const int64_t *__restrict__ roff64, const int64_t *__restrict__ cptr,
+                                              const unsigned long long *__restrict__ cut,
                                               uint32_t *__restrict__ roff32, uint32_t *__restrict__ rec,
                                               uint2 *__restrict__ sorted, unsigned long long *__restrict__ norm_bits) {
     const int lane = threadIdx.x & 63;
@@ -98,12 +180,13 @@ __global__ void __launch_bounds__(256) k_fill(int64_t n, const int64_t *__restri
             }
             continue;
         }
-        // a_max over the row (order-free)
+        // a_max over the row's entries of C (order-free)
         double amax = 0.0;
         for (int64_t k = b + lane; k < e; k += 64) {
             const int32_t c = ci[k];
             if ((int64_t)c != r) {
-                const double a = fabs((-v[k]) / d);
+                const double cv = (-v[k]) / d;
+                const double a = keep_c(cv, cut) ? fabs(cv) : 0.0;
                 amax = a > amax ? a : amax;
             }
         }
@@ -120,7 +203,7 @@ __global__ void __launch_bounds__(256) k_fill(int64_t n, const int64_t *__restri
                 const int32_t c = ci[k];
                 if ((int64_t)c != r) {
                     const double cv = (-v[k]) / d;
-                    if (cv != 0.0) {
+                    if (keep_c(cv, cut)) {
                         valid = true;
                         const double scaled = floor(ldexp(fabs(cv) / amax, q));
                         w = scaled < 1.0 ? 1u : (uint32_t)scaled;
@@ -149,7 +232,7 @@ __global__ void __launch_bounds__(256) k_fill(int64_t n, const int64_t *__restri
     }
 }
 
-// Write each row's group summary (header words 6..) and its groups of 8
+// Write each row's group summary (header words 6..) and its groups of 4
 // {cum, target} from the sorted nodes; padding as described in common.hpp.
 __global__ void __launch_bounds__(256) k_groups(int64_t n, const uint32_t *__restrict__ mrow,
                                                 const uint32_t *__restrict__ roff32,
@@ -173,8 +256,8 @@ __global__ void __launch_bounds__(256) k_groups(int64_t n, const uint32_t *__res
             recp[kHdrWords + i] = v;
         }
         uint32_t *grp = recp + (size_t)hb * kUnitWords;
-        for (uint32_t q = lane; q < G * kUnitWords; q += 64) {
-            const uint32_t g = q / kUnitWords, w = q % kUnitWords;
+        for (uint32_t q = lane; q < group_units(m) * kUnitWords; q += 64) {
+            const uint32_t g = q / kGroupWords, w = q % kGroupWords;
             const uint32_t k = g * kGroup + (w % kGroup);
             uint32_t v;
             if (w < (uint32_t)kGroup)
@@ -184,6 +267,12 @@ __global__ void __launch_bounds__(256) k_groups(int64_t n, const uint32_t *__res
             grp[q] = v;
         }
     }
+}
+
+unsigned grid_for(int64_t n) {
+    int64_t b = (n + 255) / 256;
+    if (b > 8192) b = 8192;
+    return (unsigned)(b < 1 ? 1 : b);
 }
 
 unsigned grid_for_rows(int64_t n) {
@@ -199,10 +288,20 @@ unsigned grid_for_rows(int64_t n) {
 using namespace mcmi;
 
 extern "C" mcmi_status mcmi_build_cdf(const mcmi_csr_in *B, mcmi_cdf **out, void *stream) {
+    return mcmi_build_cdf_ex(B, nullptr, out, stream);
+}
+
+extern "C" mcmi_status mcmi_build_cdf_ex(const mcmi_csr_in *B, const mcmi_cdf_opts *opts, mcmi_cdf **out,
+                                         void *stream) {
     if (out) *out = nullptr;
     if (!B || !out) return fail(MCMI_ERR_ARG, "mcmi_build_cdf: null argument");
-    if (B->n <= 0 || B->n >= (int64_t)INT32_MAX || B->nnz < B->n || !B->row_ptr_dev || !B->col_dev || !B->val_dev)
-        return fail(MCMI_ERR_ARG, "mcmi_build_cdf: need 0 < n < 2^31, nnz >= n and device pointers");
+    const double alpha = opts ? opts->alpha : 0.0;
+    const double drop_frac = opts ? opts->drop_frac : 0.0;
+    if (!(alpha >= 0.0) || !(alpha < 1e300) || !(drop_frac >= 0.0) || !(drop_frac < 1.0))
+        return fail(MCMI_ERR_ARG, "mcmi_build_cdf_ex: need alpha >= 0 and 0 <= drop_frac < 1");
+    if (B->n <= 0 || B->n >= (int64_t)INT32_MAX || B->nnz < (alpha > 0.0 ? 0 : B->n) || !B->row_ptr_dev ||
+        !B->col_dev || !B->val_dev)
+        return fail(MCMI_ERR_ARG, "mcmi_build_cdf: need 0 < n < 2^31, nnz >= n (or alpha > 0) and device pointers");
     hipStream_t s = (hipStream_t)stream;
     const int64_t n = B->n;
     mcmi_cdf *cdf = new mcmi_cdf();
@@ -212,8 +311,11 @@ extern "C" mcmi_status mcmi_build_cdf(const mcmi_csr_in *B, mcmi_cdf **out, void
     unsigned long long *norm_bits = nullptr;
     void *tmp = nullptr;
     uint2 *sorted = nullptr;
+    unsigned long long *cut_keys = nullptr, *sel = nullptr;
     mcmi_status st = MCMI_OK;
     auto cleanup = [&]() {
+        hipFree(cut_keys);
+        hipFree(sel);
         hipFree(units);
         hipFree(flags);
         hipFree(roff64);
@@ -246,25 +348,67 @@ extern "C" mcmi_status mcmi_build_cdf(const mcmi_csr_in *B, mcmi_cdf **out, void
     TRY(hipMemsetAsync(flags, 0, sizeof(uint32_t), s));
     TRY(hipMemsetAsync(norm_bits, 0, sizeof(unsigned long long), s));
     const unsigned grid = grid_for_rows(n);
-    k_count<<<grid, 256, 0, s>>>(n, B->nnz, B->row_ptr_dev, B->col_dev, B->val_dev, cdf->mrow, units, cdf->diag,
-                                 flags);
-    TRY(hipGetLastError());
-    TRY(scan_exclusive_u32_to_i64(units, roff64, n, totals + 0, tmp, s));
-    TRY(scan_exclusive_u32_to_i64(cdf->mrow, cptr, n, totals + 1, tmp, s));
+    // phase 1 (optional): ||B||_inf for the augmented diagonal
+    double aug = 0.0;
+    if (alpha > 0.0) {
+        k_row_abs_max<<<grid_for(n), 256, 0, s>>>(n, B->row_ptr_dev, B->val_dev, norm_bits);
+        TRY(hipGetLastError());
+        unsigned long long hb = 0;
+        TRY(hipMemcpyAsync(&hb, norm_bits, sizeof(hb), hipMemcpyDeviceToHost, s));
+        TRY(hipStreamSynchronize(s));
+        ::memcpy(&cdf->norm_b, &hb, sizeof(double));
+        aug = alpha * cdf->norm_b;
+        TRY(hipMemsetAsync(norm_bits, 0, sizeof(unsigned long long), s));
+    }
     uint32_t hflags = 0;
     int64_t htot[2] = {0, 0};
-    TRY(hipMemcpyAsync(&hflags, flags, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
-    TRY(hipMemcpyAsync(htot, totals, sizeof(htot), hipMemcpyDeviceToHost, s));
-    TRY(hipStreamSynchronize(s));
+    auto count_pass = [&](const unsigned long long *cut) -> hipError_t {
+        k_count<<<grid, 256, 0, s>>>(n, B->nnz, B->row_ptr_dev, B->col_dev, B->val_dev, aug, cut, cdf->mrow, units,
+                                     cdf->diag, flags);
+        hipError_t e = hipGetLastError();
+        if (e == hipSuccess) e = scan_exclusive_u32_to_i64(units, roff64, n, totals + 0, tmp, s);
+        if (e == hipSuccess) e = scan_exclusive_u32_to_i64(cdf->mrow, cptr, n, totals + 1, tmp, s);
+        if (e == hipSuccess) e = hipMemcpyAsync(&hflags, flags, sizeof(uint32_t), hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess) e = hipMemcpyAsync(htot, totals, sizeof(htot), hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+        return e;
+    };
+    TRY(count_pass(nullptr));
     if (hflags & kFlagCsr) return bail(MCMI_ERR_CSR, "mcmi_build_cdf: invalid CSR (row_ptr, column range or order)");
     if (hflags & kFlagZeroDiag) return bail(MCMI_ERR_ZERO_DIAG, "mcmi_build_cdf: missing or zero diagonal");
+    // matrix reduction (optional): the cut is the key of rank K among the |c|
+    const unsigned long long *cut = nullptr;
+    if (drop_frac > 0.0 && htot[1] > 0) {
+        const int64_t cnt = htot[1];
+        const int64_t K = (int64_t)floor(drop_frac * (double)cnt);
+        const int64_t nk = B->nnz;
+        TRY(hipMalloc(&cut_keys, (size_t)(nk > 0 ? nk : 1) * sizeof(unsigned long long)));
+        TRY(hipMalloc(&sel, (2 + 256) * sizeof(unsigned long long)));
+        const unsigned long long init[2] = {0ull, (unsigned long long)K};
+        TRY(hipMemcpyAsync(sel, init, sizeof(init), hipMemcpyHostToDevice, s));
+        TRY(hipMemsetAsync(sel + 2, 0, 256 * sizeof(unsigned long long), s));
+        k_cut_keys<<<grid, 256, 0, s>>>(n, B->row_ptr_dev, B->col_dev, B->val_dev, cdf->diag, cut_keys);
+        TRY(hipGetLastError());
+        for (int shift = 56; shift >= 0; shift -= 8) {
+            k_radix_hist<<<grid_for(nk), 256, 0, s>>>(cut_keys, nk, shift, sel, sel + 2);
+            TRY(hipGetLastError());
+            k_radix_pick<<<1, 64, 0, s>>>(sel, sel + 2, shift);
+            TRY(hipGetLastError());
+        }
+        unsigned long long hcut = 0;
+        TRY(hipMemcpyAsync(&hcut, sel, sizeof(hcut), hipMemcpyDeviceToHost, s));
+        cut = sel;
+        TRY(count_pass(cut));
+        ::memcpy(&cdf->drop_thr, &hcut, sizeof(double));
+        cdf->dropped = cnt - htot[1];
+    }
     if (htot[0] >= (int64_t)kSignBit) return bail(MCMI_ERR_CAPACITY, "mcmi_build_cdf: records exceed 128 GiB");
     cdf->rec_units = (uint64_t)htot[0];
     cdf->nnz_c = htot[1];
     TRY(hipMalloc(&cdf->rec, (size_t)htot[0] * kUnitWords * 4u + 64u));
     TRY(hipMalloc(&sorted, (size_t)(htot[1] > 0 ? htot[1] : 1) * sizeof(uint2)));
     k_fill<<<grid, 256, 0, s>>>(n, B->row_ptr_dev, B->col_dev, B->val_dev, cdf->diag, cdf->mrow, roff64, cptr,
-                                cdf->roff, cdf->rec, sorted, norm_bits);
+                                cut, cdf->roff, cdf->rec, sorted, norm_bits);
     TRY(hipGetLastError());
     k_groups<<<grid, 256, 0, s>>>(n, cdf->mrow, cdf->roff, cptr, sorted, cdf->rec);
     TRY(hipGetLastError());
@@ -278,6 +422,15 @@ extern "C" mcmi_status mcmi_build_cdf(const mcmi_csr_in *B, mcmi_cdf **out, void
     cleanup();
     *out = cdf;
     return st;
+}
+
+extern "C" mcmi_status mcmi_cdf_prep_info(const mcmi_cdf *cdf, double *norm_b, double *drop_thr,
+                                          int64_t *dropped) {
+    if (!cdf) return fail(MCMI_ERR_ARG, "mcmi_cdf_prep_info: null cdf");
+    if (norm_b) *norm_b = cdf->norm_b;
+    if (drop_thr) *drop_thr = cdf->drop_thr;
+    if (dropped) *dropped = cdf->dropped;
+    return MCMI_OK;
 }
 
 extern "C" mcmi_status mcmi_cdf_info(const mcmi_cdf *cdf, int64_t *n, int64_t *nnz_c, double *norm_inf,
@@ -339,11 +492,6 @@ __global__ void __launch_bounds__(256) k_matrix_norms(int64_t n, const uint32_t 
     }
 }
 
-unsigned grid_for(int64_t n) {
-    int64_t b = (n + 255) / 256;
-    if (b > 8192) b = 8192;
-    return (unsigned)(b < 1 ? 1 : b);
-}
 
 }  // namespace
 }  // namespace mcmi

@@ -23,23 +23,27 @@ mcmi_status fail(mcmi_status st, const std::string &msg);
 // ----------------------------------------------------------- record layout
 // One record per row s of C, 64-byte aligned, addressed by its offset in
 // 64-byte units (31 bits: up to 128 GiB of records). With m entries the row has
-// G = ceil(m / 8) groups of 8 consecutive entries (column order) and a header
+// G = ceil(m / 4) groups of 4 consecutive entries (column order) and a header
 // block of hb = ceil((6 + G) / 16) units:
 //   word 0  row index s               word 1  m
 //   word 2  W = total integer weight  word 3  Shat_s as binary32
 //   words 4-5  Shat_s as binary64
 //   words 6 .. 6+G-1  the inclusive cum of each group's last entry (the group
 //                     summary); the rest of the block holds 0xFFFFFFFF
-// then G group units of 16 words: cum of the group's 8 entries (inclusive
-// integer prefix sums of the weights), then their targets: the record offset of
-// the column's row with bit 31 set when c < 0. The last group is padded with
-// cum = 0xFFFFFFFF and target 0. A draw t < W selects the first entry with
-// t < cum: the group is the number of summaries <= t, the entry inside it the
-// number of the group's cums <= t; both searches run in registers, so one step
-// reads one header unit and one group unit.
+// then ceil(G / 2) units holding the groups, 8 words (32 bytes) each: the cums
+// of the group's 4 entries (inclusive integer prefix sums of the weights), then
+// their targets: the record offset of the column's row with bit 31 set when
+// c < 0. Missing entries (the last group's tail, the unused half of the last
+// unit) have cum = 0xFFFFFFFF and target 0. A draw t < W selects the first
+// entry with t < cum: the group is the number of summaries <= t, the entry
+// inside it the number of the group's cums <= t; both searches run in
+// registers. A step reads the first 48 bytes of the header unit (three 16-byte
+// loads issued together) and one 32-byte group (two loads issued together):
+// few loads per random unit keep the unit in the L1 cache until its last load.
 constexpr int kUnitWords = 16;
 constexpr int kHdrWords = 6;
-constexpr int kGroup = 8;
+constexpr int kGroup = 4;
+constexpr int kGroupWords = 2 * kGroup;
 constexpr uint32_t kSignBit = 0x80000000u;
 constexpr uint32_t kPad = 0xFFFFFFFFu;
 
@@ -47,7 +51,10 @@ __host__ __device__ inline uint32_t record_groups(uint32_t m) { return (m + kGro
 __host__ __device__ inline uint32_t header_units(uint32_t m) {
     return (kHdrWords + record_groups(m) + kUnitWords - 1u) / kUnitWords;
 }
-__host__ __device__ inline uint32_t record_units(uint32_t m) { return header_units(m) + record_groups(m); }
+__host__ __device__ inline uint32_t group_units(uint32_t m) {
+    return (record_groups(m) * kGroupWords + kUnitWords - 1u) / kUnitWords;
+}
+__host__ __device__ inline uint32_t record_units(uint32_t m) { return header_units(m) + group_units(m); }
 
 // Error flags raised by device-side validation (bit set).
 enum : uint32_t {
@@ -170,6 +177,9 @@ struct mcmi_cdf {
     int64_t n = 0;
     int64_t nnz_c = 0;
     double norm_inf = 0.0;
+    double norm_b = 0.0;    // ||B||_inf when the diagonal was augmented
+    double drop_thr = 0.0;  // reduction cut on |c| (0: none)
+    int64_t dropped = 0;    // entries of C removed by the reduction
     uint64_t rec_units = 0;
     uint32_t *rec = nullptr;       // records, 16 words per unit
     uint32_t *roff = nullptr;      // n: record offset (64-byte units) of each row

@@ -42,7 +42,7 @@ __global__ void __launch_bounds__(256) k_features(int64_t n, const uint32_t *__r
         uint32_t wmax = 0;
         for (uint32_t k = lane; k < m; k += 64) {
             const uint32_t g = k / kGroup, sl = k % kGroup;
-            const uint32_t *grp = recp + (size_t)(hb + g) * kUnitWords;
+            const uint32_t *grp = recp + (size_t)hb * kUnitWords + (size_t)g * kGroupWords;
             const uint32_t cum = grp[sl];
             const uint32_t prev = sl ? grp[sl - 1] : (g ? recp[kHdrWords + g - 1] : 0u);
             const uint32_t w = cum - prev;

@@ -309,6 +309,7 @@ extern "C" mcmi_status mcmi_plan_create(const mcmi_cdf *cdf, const mcmi_params *
     a.eps = p->eps;
     a.lmax = lmax;
     a.filter_m = p->filter == MCMI_FILTER_M;
+    a.topk = p->topk;
     a.hash_slots = pl->shape.hash;
     a.hash_shift = 32 - __builtin_ctz((unsigned)pl->shape.hash);
     a.queue_ctr = (uint32_t *)ctrl;

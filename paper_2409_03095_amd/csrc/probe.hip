@@ -2,11 +2,13 @@
 // access pattern without the method's arithmetic.
 //
 // A buffer of `units` 64-byte units holds random unit indices. Each lane runs a
-// pointer chase in which every step issues `reqs` dependent 64-byte reads (one
-// 16-byte load each, at the unit the previous read named), exactly like a walk
-// step reads its header unit and then its group unit. The measured steps per
-// second is the ceiling a walk with the same number of dependent requests per
-// transition can reach on this chip, for a record set of the same size.
+// pointer chase in which every step issues `reqs` dependent reads of one unit
+// each (the unit the previous read named), like a walk step reads its header
+// unit and then its group unit. A read is `loads` 16-byte loads of the unit's
+// first quarters (1: only the word that names the next unit; 4: the whole
+// unit). The measured steps per second is the ceiling a walk with the same
+// number of dependent requests and loads per transition can reach on this chip,
+// for a record set of the same size.
 #include <string>
 
 #include "common.hpp"
@@ -27,17 +29,22 @@ __global__ void k_probe_fill(uint4 *buf, uint64_t units, uint32_t seed) {
     }
 }
 
-__global__ void __launch_bounds__(256) k_probe_chase(const uint4 *buf, uint64_t units, int reqs, int steps,
-                                                     unsigned long long *sink) {
+__global__ void __launch_bounds__(256) k_probe_chase(const uint4 *buf, uint64_t units, int reqs, int loads,
+                                                     int steps, unsigned long long *sink) {
     const uint64_t tid = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
     uint32_t cur = (uint32_t)((tid * 2654435761ull) % units);
     uint32_t acc = 0;
     for (int s = 0; s < steps; ++s) {
         for (int q = 0; q < reqs; ++q) {
-            const uint4 v = buf[(uint64_t)cur * 4 + (q & 3)];
+            const uint4 *u = buf + (uint64_t)cur * 4;
+            const uint4 v = u[0];
+            uint32_t extra = 0;
+            if (loads > 1) extra += u[1].y;
+            if (loads > 2) extra += u[2].z;
+            if (loads > 3) extra += u[3].w;
             cur = v.x ^ (acc & 1u);      // dependent next index (acc keeps it live)
             if (cur >= units) cur -= (uint32_t)units;
-            acc += v.y;
+            acc += v.y + extra;
         }
     }
     if (acc == 0xFFFFFFFFu) atomicAdd(sink, 1ull);
@@ -48,9 +55,10 @@ __global__ void __launch_bounds__(256) k_probe_chase(const uint4 *buf, uint64_t 
 
 using namespace mcmi;
 
-extern "C" mcmi_status mcmi_gather_probe(uint64_t units, int32_t reqs_per_step, int32_t steps, int32_t waves_per_cu,
-                                         double *ms_out, double *steps_per_s_out) {
-    if (units < 1024 || units >= (1ull << 32) || reqs_per_step < 1 || steps < 1 || waves_per_cu < 1)
+extern "C" mcmi_status mcmi_gather_probe(uint64_t units, int32_t reqs_per_step, int32_t loads_per_req, int32_t steps,
+                                         int32_t waves_per_cu, double *ms_out, double *steps_per_s_out) {
+    if (units < 1024 || units >= (1ull << 32) || reqs_per_step < 1 || loads_per_req < 1 || loads_per_req > 4 ||
+        steps < 1 || waves_per_cu < 1)
         return fail(MCMI_ERR_ARG, "mcmi_gather_probe: bad argument");
     uint4 *buf = nullptr;
     unsigned long long *sink = nullptr;
@@ -64,9 +72,9 @@ extern "C" mcmi_status mcmi_gather_probe(uint64_t units, int32_t reqs_per_step, 
     hipEvent_t a, b;
     (void)hipEventCreate(&a);
     (void)hipEventCreate(&b);
-    k_probe_chase<<<blocks, 256>>>(buf, units, reqs_per_step, steps / 4 + 1, sink);  // warm-up
+    k_probe_chase<<<blocks, 256>>>(buf, units, reqs_per_step, loads_per_req, steps / 4 + 1, sink);  // warm-up
     (void)hipEventRecord(a, nullptr);
-    k_probe_chase<<<blocks, 256>>>(buf, units, reqs_per_step, steps, sink);
+    k_probe_chase<<<blocks, 256>>>(buf, units, reqs_per_step, loads_per_req, steps, sink);
     (void)hipEventRecord(b, nullptr);
     hipError_t e = hipEventSynchronize(b);
     float ms = 0.f;

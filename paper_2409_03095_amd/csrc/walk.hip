@@ -14,9 +14,10 @@
 //  * each lane runs one chain at a time and starts the row's next unstarted chain
 //    as soon as its chain stops, so short and long chains do not wait for each
 //    other;
-//  * a step reads the 64-byte header unit of the current state, draws one
-//    Philox word, picks the group of 8 entries from the header's group summaries
-//    and the entry from that group's 64-byte unit: two dependent requests;
+//  * a step reads the header of the current state (48 bytes of one 64-byte
+//    unit), draws one Philox word, picks the group of 4 entries from the
+//    header's group summaries and the entry from that group's 32 bytes: two
+//    dependent requests;
 //  * contributions go to an open-addressing hash per wave in LDS (key = column,
 //    value = float64 sum, LDS float64 atomics); a full neighbourhood spills to a
 //    per-wave hash in HBM;
@@ -159,7 +160,7 @@ __device__ __forceinline__ void walk_row(const WalkArgs &a, int64_t task, int32_
         if (keep) {
             const int pos = K + mask_rank(km);
             keys[pos] = key;
-            vals[pos] = mval;
+            vals[pos] = a.topk > 0 ? acc / nd : mval;  // top-k ranks by N_rc first
         }
         K += __popcll(km);
     }
@@ -170,11 +171,11 @@ __device__ __forceinline__ void walk_row(const WalkArgs &a, int64_t task, int32_
         const int u = base + lane;
         bool keep = false;
         int32_t key = kEmpty;
-        double mval = 0.0;
+        double mval = 0.0, nhat = 0.0;
         if (u < nsp) {
             const int32_t slot = sused[u];
             key = skeys[slot];
-            const double nhat = svals[slot] / nd;
+            nhat = svals[slot] / nd;
             mval = nhat / a.diag[key];
             const double test = a.filter_m ? fabs(mval) : fabs(nhat);
             keep = key == r || (nhat != 0.0 && test >= a.eps);
@@ -186,7 +187,7 @@ __device__ __forceinline__ void walk_row(const WalkArgs &a, int64_t task, int32_
             const int pos = K + mask_rank(km);
             if (pos < a.hash_slots) {
                 keys[pos] = key;
-                vals[pos] = mval;
+                vals[pos] = a.topk > 0 ? nhat : mval;
             } else {
                 stage_full = true;
             }
@@ -195,6 +196,38 @@ __device__ __forceinline__ void walk_row(const WalkArgs &a, int64_t task, int32_
     }
     if (K > a.hash_slots) K = a.hash_slots;
     wave_sync();
+
+    // top-k retention: bitonic sort in retention order, keep the first topk,
+    // then turn N_rc into M_rc = N_rc / d_c
+    if (a.topk > 0) {
+        if (K > a.topk) {
+            int PT = 1;
+            while (PT < K) PT <<= 1;
+            for (int s = K + lane; s < PT; s += 64) keys[s] = INT32_MAX;
+            wave_sync();
+            for (int k = 2; k <= PT; k <<= 1) {
+                for (int jj = k >> 1; jj > 0; jj >>= 1) {
+                    for (int i = lane; i < PT; i += 64) {
+                        const int ixj = i ^ jj;
+                        if (ixj > i) {
+                            const int32_t ka = keys[i], kb = keys[ixj];
+                            const double va = vals[i], vb = vals[ixj];
+                            if (top_after(a, r, ka, va, kb, vb) == ((i & k) == 0)) {
+                                keys[i] = kb;
+                                keys[ixj] = ka;
+                                vals[i] = vb;
+                                vals[ixj] = va;
+                            }
+                        }
+                    }
+                    wave_sync();
+                }
+            }
+            K = a.topk;
+        }
+        for (int i = lane; i < K; i += 64) vals[i] = vals[i] / a.diag[keys[i]];
+        wave_sync();
+    }
 
     // bitonic sort of keys[0..P) by column, padding with INT32_MAX
     int P = 1;

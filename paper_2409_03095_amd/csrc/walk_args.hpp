@@ -25,6 +25,7 @@ struct WalkArgs {
     double eps;
     int32_t lmax;
     int32_t filter_m;
+    int32_t topk;
     int32_t hash_slots;            // power of two
     int32_t hash_shift;            // 32 - log2(hash_slots)
     uint32_t *queue_ctr;           // 8 counters

@@ -75,19 +75,22 @@ __device__ __forceinline__ void chain_start(Chain &st, int32_t c, const RowCtx &
 __device__ __forceinline__ void light_add(const WalkArgs &a, const RowCtx &rc, int32_t key, double w,
                                           unsigned long long &spilled) {
     const uint32_t hmask = (uint32_t)a.hash_slots - 1u;
-    uint32_t h = hash_key(key, a.hash_shift);
+    uint32_t b = hash_key(key, a.hash_shift) & ~3u;
     bool full_run = true;
-    for (int p = 0; p < kMaxLdsProbe; ++p) {
-        const int32_t k = __atomic_load_n(&rc.keys[h], __ATOMIC_RELAXED);
-        if (k == key) {
-            atomicAdd(&rc.vals[h], w);
+    for (int nb = 0; nb < kMaxLdsProbe / 4; ++nb) {
+        int32_t k[4];
+        read_bucket(rc.keys, b, k);
+        int hit, emp;
+        scan_bucket(k, key, hit, emp);
+        if (hit >= 0) {
+            atomicAdd(&rc.vals[b + hit], w);
             return;
         }
-        if (k == kEmpty) {
+        if (emp >= 0) {
             full_run = false;
             break;
         }
-        h = (h + 1) & hmask;
+        b = (b + 4u) & hmask;
     }
     if (full_run && rc.row_spilled) {
         const uint32_t smask = (uint32_t)a.spill_slots - 1u;
@@ -114,19 +117,30 @@ __device__ __forceinline__ void refine_add(const WalkArgs &a, const RowCtx &rc, 
     if (rc.sketch[bucket_of(key, (uint32_t)a.sketch_slots)] < rc.hot_thr) return;
     const int32_t rkey = (int32_t)((uint32_t)key | kRBit);
     const uint32_t hmask = (uint32_t)a.hash_slots - 1u;
-    uint32_t h = hash_key(key, a.hash_shift);
-    for (int p = 0; p < kMaxLdsProbe; ++p) {
-        int32_t k = __atomic_load_n(&rc.keys[h], __ATOMIC_RELAXED);
-        if (k == kEmpty) {
-            const int32_t prev = atomicCAS(&rc.keys[h], kEmpty, rkey);
-            k = prev == kEmpty ? rkey : prev;
-        }
-        if (k == key) return;  // tracked since phase H: already complete
-        if (k == rkey) {
-            atomicAdd(&rc.vals[h], w);
+    uint32_t b = hash_key(key, a.hash_shift) & ~3u;
+    int nb = 0;
+    while (nb < kMaxLdsProbe / 4) {
+        int32_t k[4];
+        read_bucket(rc.keys, b, k);
+        int hit, emp, rhit, remp;
+        scan_bucket(k, key, hit, emp);
+        if (hit >= 0) return;  // tracked since phase H: already complete
+        scan_bucket(k, rkey, rhit, remp);
+        if (rhit >= 0) {
+            atomicAdd(&rc.vals[b + rhit], w);
             return;
         }
-        h = (h + 1) & hmask;
+        if (emp < 0) {
+            b = (b + 4u) & hmask;
+            ++nb;
+            continue;
+        }
+        const int32_t prev = atomicCAS(&rc.keys[b + emp], kEmpty, rkey);
+        if (prev == kEmpty || prev == rkey) {
+            atomicAdd(&rc.vals[b + emp], w);
+            return;
+        }
+        // another column took the slot: read the bucket again
     }
     // HBM table: a heavy column may live there; else track the light column there
     const uint32_t smask = (uint32_t)a.spill_slots - 1u;
@@ -317,11 +331,11 @@ __device__ __forceinline__ void block_row(const WalkArgs &a, int64_t task, RowCt
         const int32_t raw = rc.keys[s];
         const double acc = rc.vals[s];
         int32_t key = kEmpty;
-        double m = 0.0;
+        double m = 0.0, nhat = 0.0;
         int keep = 0;
         if (raw != kEmpty) {
             key = (int32_t)((uint32_t)raw & ~kRBit);
-            const double nhat = acc / nd;
+            nhat = acc / nd;
             m = nhat / a.diag[key];
             const double test = a.filter_m ? fabs(m) : fabs(nhat);
             keep = (key == r || (nhat != 0.0 && test >= a.eps)) ? 1 : 0;
@@ -330,7 +344,7 @@ __device__ __forceinline__ void block_row(const WalkArgs &a, int64_t task, RowCt
         const int pos = K + block_scan<kLPR>(keep, redi, &added);
         if (keep) {
             rc.keys[pos] = key;
-            rc.vals[pos] = m;
+            rc.vals[pos] = a.topk > 0 ? nhat : m;  // top-k ranks by N_rc first
         }
         K += added;
     }
@@ -340,12 +354,12 @@ __device__ __forceinline__ void block_row(const WalkArgs &a, int64_t task, RowCt
     for (int base = 0; base < nsp; base += kLPR) {
         const int u = base + tid;
         int32_t key = kEmpty;
-        double m = 0.0;
+        double m = 0.0, nhat = 0.0;
         int keep = 0;
         if (u < nsp) {
             const int32_t sl = rc.sused[u];
             key = (int32_t)((uint32_t)rc.skeys[sl] & ~kRBit);
-            const double nhat = rc.svals[sl] / nd;
+            nhat = rc.svals[sl] / nd;
             m = nhat / a.diag[key];
             const double test = a.filter_m ? fabs(m) : fabs(nhat);
             keep = (key == r || (nhat != 0.0 && test >= a.eps)) ? 1 : 0;
@@ -357,7 +371,7 @@ __device__ __forceinline__ void block_row(const WalkArgs &a, int64_t task, RowCt
         if (keep) {
             if (p < H) {
                 rc.keys[p] = key;
-                rc.vals[p] = m;
+                rc.vals[p] = a.topk > 0 ? nhat : m;
             } else {
                 stage_full = true;
             }
@@ -365,6 +379,38 @@ __device__ __forceinline__ void block_row(const WalkArgs &a, int64_t task, RowCt
         K += added;
     }
     if (K > H) K = H;
+    __syncthreads();
+    // top-k retention: bitonic sort in retention order, keep the first topk,
+    // then turn N_rc into M_rc = N_rc / d_c
+    if (a.topk > 0) {
+        if (K > a.topk) {
+            int PT = 1;
+            while (PT < K) PT <<= 1;
+            for (int s = K + tid; s < PT; s += kLPR) rc.keys[s] = INT32_MAX;
+            __syncthreads();
+            for (int k = 2; k <= PT; k <<= 1) {
+                for (int jj = k >> 1; jj > 0; jj >>= 1) {
+                    for (int i = tid; i < PT; i += kLPR) {
+                        const int ixj = i ^ jj;
+                        if (ixj > i) {
+                            const int32_t ka = rc.keys[i], kb = rc.keys[ixj];
+                            const double va = rc.vals[i], vb = rc.vals[ixj];
+                            if (top_after(a, r, ka, va, kb, vb) == ((i & k) == 0)) {
+                                rc.keys[i] = kb;
+                                rc.keys[ixj] = ka;
+                                rc.vals[i] = vb;
+                                rc.vals[ixj] = va;
+                            }
+                        }
+                    }
+                    __syncthreads();
+                }
+            }
+            K = a.topk;
+        }
+        for (int i = tid; i < K; i += kLPR) rc.vals[i] = rc.vals[i] / a.diag[rc.keys[i]];
+        __syncthreads();
+    }
     int P = 1;
     while (P < K) P <<= 1;
     for (int s = K + tid; s < P; s += kLPR) rc.keys[s] = INT32_MAX;

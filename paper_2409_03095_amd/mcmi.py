@@ -41,6 +41,15 @@ class CsrIn(ctypes.Structure):
                 ("col_dev", ctypes.c_void_p), ("val_dev", ctypes.c_void_p)]
 
 
+class CdfOpts(ctypes.Structure):
+    _fields_ = [("alpha", ctypes.c_double), ("drop_frac", ctypes.c_double), ("reserved", ctypes.c_int64 * 2)]
+
+
+class SolveStats(ctypes.Structure):
+    _fields_ = [("iterations", ctypes.c_int64), ("rel_residual", ctypes.c_double), ("ms", ctypes.c_double),
+                ("converged", ctypes.c_int32), ("pad", ctypes.c_int32)]
+
+
 class CsrOut(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int64), ("nnz", ctypes.c_int64), ("row_ptr_dev", ctypes.c_void_p),
                 ("col_dev", ctypes.c_void_p), ("val_dev", ctypes.c_void_p)]
@@ -51,7 +60,7 @@ class Params(ctypes.Structure):
                 ("delta", ctypes.c_double), ("eps", ctypes.c_double), ("max_len", ctypes.c_int32),
                 ("stream_tag", ctypes.c_uint32), ("filter", ctypes.c_int32), ("lanes_per_row", ctypes.c_int32),
                 ("hash_slots", ctypes.c_int32), ("sketch_slots", ctypes.c_int32), ("pool_per_row", ctypes.c_int32),
-                ("heavy_weight", ctypes.c_double), ("spill_slots", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("heavy_weight", ctypes.c_double), ("spill_slots", ctypes.c_int32), ("topk", ctypes.c_int32)]
 
 
 class Stats(ctypes.Structure):
@@ -67,6 +76,9 @@ _P = ctypes.POINTER
 _v = ctypes.c_void_p
 _sig = {
     "mcmi_build_cdf": [_P(CsrIn), _P(_v), _v],
+    "mcmi_build_cdf_ex": [_P(CsrIn), _P(CdfOpts), _P(_v), _v],
+    "mcmi_bicgstab": [_P(CsrIn), _P(CsrOut), _v, _v, ctypes.c_double, ctypes.c_int32, _P(SolveStats), _v],
+    "mcmi_cdf_prep_info": [_v, _P(ctypes.c_double), _P(ctypes.c_double), _P(ctypes.c_int64)],
     "mcmi_cdf_info": [_v, _P(ctypes.c_int64), _P(ctypes.c_int64), _P(ctypes.c_double), _P(ctypes.c_uint64)],
     "mcmi_cdf_download": [_v, _v, _v, _v, _v],
     "mcmi_build_cdf_batched": [_P(CsrIn), ctypes.c_int32, _P(_v), _v],
@@ -74,7 +86,8 @@ _sig = {
     "mcmi_plan_create": [_v, _P(Params), _v, ctypes.c_int64, _P(_v), _v],
     "mcmi_plan_launch": [_v, ctypes.c_uint64, _v],
     "mcmi_plan_result": [_v, _P(CsrOut), _P(Stats), _P(ctypes.c_int32), _v],
-    "mcmi_gather_probe": [ctypes.c_uint64, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, _P(ctypes.c_double),
+    "mcmi_gather_probe": [ctypes.c_uint64, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+                          _P(ctypes.c_double),
                           _P(ctypes.c_double)],
     "mcmi_cdf_batch_info": [_v, _P(ctypes.c_int32), _v, _v],
     "mcmi_spai": [_v, _P(Params), _v, _v, ctypes.c_int64, _P(CsrOut), _P(Stats), _v],
@@ -107,7 +120,7 @@ _lib.mcmi_csr_free.restype = None
 _lib.mcmi_last_error.restype = ctypes.c_char_p
 _lib.mcmi_version.restype = ctypes.c_char_p
 
-EXPORTED = ["mcmi_build_cdf", "mcmi_cdf_info", "mcmi_cdf_download", "mcmi_spai", "mcmi_apply",
+EXPORTED = ["mcmi_bicgstab", "mcmi_build_cdf", "mcmi_build_cdf_ex", "mcmi_cdf_prep_info", "mcmi_cdf_info", "mcmi_cdf_download", "mcmi_spai", "mcmi_apply",
             "mcmi_csr_copy", "mcmi_cdf_free", "mcmi_csr_free", "mcmi_last_error", "mcmi_version",
             "mcmi_row_features", "mcmi_pilot_variance", "mcmi_mlp_create", "mcmi_mlp_free",
             "mcmi_mlp_set_params", "mcmi_mlp_get_params", "mcmi_mlp_set_adam_state", "mcmi_mlp_fit_normalization",
@@ -164,12 +177,17 @@ class Cdf:
     """Sampling records of C = I - D^-1 B (mcmi_build_cdf), or of several matrices
     in one block-diagonal row space (Cdf.batched -> mcmi_build_cdf_batched)."""
 
-    def __init__(self, B: DeviceCsr = None, stream=None, _batch=None):
+    def __init__(self, B: DeviceCsr = None, stream=None, _batch=None, alpha=0.0, drop_frac=0.0):
         self._h = ctypes.c_void_p()
         self._B = B if B is not None else _batch
         if _batch is None:
             s = B._struct()
-            _check(_lib.mcmi_build_cdf(ctypes.byref(s), ctypes.byref(self._h), _stream(stream)))
+            if alpha or drop_frac:
+                opts = CdfOpts(float(alpha), float(drop_frac), (ctypes.c_int64 * 2)(0, 0))
+                _check(_lib.mcmi_build_cdf_ex(ctypes.byref(s), ctypes.byref(opts), ctypes.byref(self._h),
+                                              _stream(stream)))
+            else:
+                _check(_lib.mcmi_build_cdf(ctypes.byref(s), ctypes.byref(self._h), _stream(stream)))
         else:
             arr = (CsrIn * len(_batch))(*[m._struct() for m in _batch])
             _check(_lib.mcmi_build_cdf_batched(arr, ctypes.c_int32(len(_batch)), ctypes.byref(self._h),
@@ -178,6 +196,12 @@ class Cdf:
         _check(_lib.mcmi_cdf_info(self._h, ctypes.byref(n), ctypes.byref(nnz_c), ctypes.byref(nrm),
                                   ctypes.byref(units)))
         self.n, self.nnz_c, self.norm_inf, self.rec_units = n.value, nnz_c.value, nrm.value, units.value
+
+    def prep_info(self):
+        """(||B||_inf, reduction cut, entries removed) of the pre-pass."""
+        nb, cut, nd = ctypes.c_double(), ctypes.c_double(), ctypes.c_int64()
+        _check(_lib.mcmi_cdf_prep_info(self._h, ctypes.byref(nb), ctypes.byref(cut), ctypes.byref(nd)))
+        return nb.value, cut.value, nd.value
 
     @staticmethod
     def batched(mats, stream=None):
@@ -264,10 +288,10 @@ class SpaiResult:
 
 def params(seed=0, chains=16, delta=1e-3, eps=1e-3, walk_prec=WALK_F64, max_len=0, tag=0, filter=FILTER_N,
            lanes_per_row=0, hash_slots=0, sketch_slots=0, heavy_weight=0.0, pool_per_row=0,
-           spill_slots=0) -> Params:
+           spill_slots=0, topk=0) -> Params:
     return Params(int(seed) & 0xFFFFFFFFFFFFFFFF, int(chains), int(walk_prec), float(delta), float(eps),
                   int(max_len), int(tag) & 0xFFFFFFFF, int(filter), int(lanes_per_row), int(hash_slots),
-                  int(sketch_slots), int(pool_per_row), float(heavy_weight), int(spill_slots), 0)
+                  int(sketch_slots), int(pool_per_row), float(heavy_weight), int(spill_slots), int(topk))
 
 
 def spai(cdf: Cdf, p: Params, chains_per_row=None, rows=None, stream=None) -> SpaiResult:
@@ -427,9 +451,22 @@ class Plan:
             pass
 
 
-def gather_probe(units, reqs_per_step=2, steps=256, waves_per_cu=16):
+def gather_probe(units, reqs_per_step=2, steps=256, waves_per_cu=16, loads_per_req=1):
     """mcmi_gather_probe: (kernel ms, dependent-gather steps per second)."""
     ms, rate = ctypes.c_double(), ctypes.c_double()
-    _check(_lib.mcmi_gather_probe(ctypes.c_uint64(units), ctypes.c_int32(reqs_per_step), ctypes.c_int32(steps),
+    _check(_lib.mcmi_gather_probe(ctypes.c_uint64(units), ctypes.c_int32(reqs_per_step),
+                                  ctypes.c_int32(loads_per_req), ctypes.c_int32(steps),
                                   ctypes.c_int32(waves_per_cu), ctypes.byref(ms), ctypes.byref(rate)))
     return ms.value, rate.value
+
+
+def bicgstab(B: DeviceCsr, M=None, b=None, x0=None, rtol=1e-8, maxiter=5000, stream=None):
+    """mcmi_bicgstab: solve B x = b on the device, M (a SpaiResult) applied on the
+    right. b, x0: float64 device tensors (x0 defaults to zeros). Returns (x, SolveStats)."""
+    import torch
+    x = torch.zeros(B.n, dtype=torch.float64, device="cuda") if x0 is None else x0.clone()
+    st = SolveStats()
+    s = B._struct()
+    _check(_lib.mcmi_bicgstab(ctypes.byref(s), None if M is None else ctypes.byref(M._out), _ptr(b), _ptr(x),
+                              ctypes.c_double(rtol), ctypes.c_int32(maxiter), ctypes.byref(st), _stream(stream)))
+    return x, st

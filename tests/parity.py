@@ -6,8 +6,9 @@ U64 = 2.0 ** -53
 
 def decode_records(rec, roff, n):
     """Decode the library's records (64-byte units: header unit with the group
-    summaries, then groups of 8 {cum, target}) into per-row (row, m, W, S32, S64,
-    cum[], col[], neg[]) in column order, checking the summaries and padding."""
+    summaries, then groups of 4 {cum, target}, two per unit) into per-row (row, m,
+    W, S32, S64, cum[], col[], neg[]) in column order, checking the summaries and
+    padding."""
     inv = {int(o): i for i, o in enumerate(roff)}
     out = []
     for i in range(n):
@@ -15,23 +16,23 @@ def decode_records(rec, roff, n):
         row, m, W = int(rec[base]), int(rec[base + 1]), int(rec[base + 2])
         s32 = rec[base + 3:base + 4].view(np.float32)[0]
         s64 = rec[base + 4:base + 6].view(np.float64)[0]
-        G = (m + 7) // 8
+        G = (m + 3) // 4
         hb = (6 + G + 15) // 16
+        gu = (8 * G + 15) // 16
         summ = rec[base + 6:base + 16 * hb].astype(np.int64)
+        area = rec[base + 16 * hb:base + 16 * (hb + gu)]
         cum, tgt = [], []
-        for g in range(G):
-            u = base + 16 * (hb + g)
-            cum.extend(int(x) for x in rec[u:u + 8])
-            tgt.extend(int(x) for x in rec[u + 8:u + 16])
+        for g in range(2 * gu):
+            cum.extend(int(x) for x in area[8 * g:8 * g + 4])
+            tgt.extend(int(x) for x in area[8 * g + 4:8 * g + 8])
+        assert all(x == 0xFFFFFFFF for x in cum[m:]), ("cum padding", i)
+        assert all(x == 0 for x in tgt[m:]), ("target padding", i)
         cum = np.array(cum[:m] if m else [], dtype=np.int64)
         tg = tgt[:m]
         if m:
-            last = [cum[min(8 * g + 7, m - 1)] for g in range(G)]
+            last = [cum[min(4 * g + 3, m - 1)] for g in range(G)]
             assert list(summ[:G]) == last, ("group summaries", i)
             assert all(x == 0xFFFFFFFF for x in summ[G:]), ("summary padding", i)
-            tail = rec[base + 16 * (hb + G - 1):base + 16 * (hb + G)]
-            k = m - 8 * (G - 1)
-            assert all(x == 0xFFFFFFFF for x in tail[k:8]), ("cum padding", i)
         col = np.array([inv[t & 0x7FFFFFFF] for t in tg], dtype=np.int64)
         neg = np.array([(t >> 31) & 1 for t in tg], dtype=bool)
         out.append((row, m, W, s32, s64, cum, col, neg))
@@ -69,3 +70,33 @@ def common_entries(rp_a, col_a, val_a, rp_b, col_b, val_b):
         va.append(val_a[rp_a[r]:rp_a[r + 1]][ia])
         vb.append(val_b[rp_b[r]:rp_b[r + 1]][ib])
     return np.concatenate(va), np.concatenate(vb)
+
+
+def compare_topk(gpu, orc, diag, chains):
+    """Top-k retention: rows whose boundary the oracle marks order-dependent
+    (row_ambig) must keep as many entries, with equal values on the columns both
+    keep; every other row must match as in compare_spai."""
+    rp, col, val = gpu
+    orp = orc["row_ptr"]
+    amb = orc["row_ambig"].astype(bool)
+    assert np.array_equal(np.diff(rp), np.diff(orp)), "row lengths differ"
+    clean = np.nonzero(~amb)[0]
+
+    def sub(r_p, arrays, rows):
+        lens = r_p[rows + 1] - r_p[rows]
+        idx = np.concatenate([np.arange(r_p[r], r_p[r + 1]) for r in rows]) if rows.size else np.zeros(0, int)
+        return np.concatenate([[0], np.cumsum(lens)]), [a[idx] for a in arrays]
+
+    g_rp, (g_col, g_val) = sub(rp, [col, val], clean)
+    o_rp, (o_col, o_val, o_abs, o_cnt) = sub(orp, [orc["col"], orc["val"], orc["abssum"], orc["cnt"]], clean)
+    ref = {"row_ptr": o_rp, "col": o_col, "val": o_val, "abssum": o_abs, "cnt": o_cnt}
+    err = compare_spai((g_rp, g_col, g_val), ref, diag, chains, rows=clean)
+    for r in np.nonzero(amb)[0]:
+        gc, gv = col[rp[r]:rp[r + 1]], val[rp[r]:rp[r + 1]]
+        sl = slice(orp[r], orp[r + 1])
+        oc, ov = orc["col"][sl], orc["val"][sl]
+        _, ia, ib = np.intersect1d(gc, oc, return_indices=True)
+        bound = 4.0 * (orc["cnt"][sl][ib] + 2.0) * U64 * orc["abssum"][sl][ib] / chains / np.abs(diag[oc[ib]])
+        tol = np.maximum(1e-12 * np.abs(ov[ib]), bound)
+        assert np.all(np.abs(gv[ia] - ov[ib]) <= tol), ("ambiguous row values", r)
+    return err, int(amb.sum())

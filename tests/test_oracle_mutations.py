@@ -2,7 +2,7 @@
 pins catch every one: a dropped term, a wrong sign or index, a transposed
 scaling, a non-strict cutoff, a wrong quantization, a wrong Philox constant,
 a pre-pass that ignores the diagonal's sign, uses another norm or cuts at the
-wrong rank."""
+wrong rank, a top-k selection that keeps the wrong number or the wrong end."""
 import os
 import shutil
 import subprocess
@@ -27,6 +27,8 @@ MUTATIONS = {
     "aug_norm_is_max_entry": ("s += fabs(v[k]);", "s = fabs(v[k]) > s ? fabs(v[k]) : s;"),
     "drop_cut_off_by_one": ("thr = mag[K];", "thr = mag[K > 0 ? K - 1 : 0];"),
     "drop_keeps_ties_out": ("if (fabs(c) < thr) {", "if (fabs(c) <= thr && thr > 0.0) {"),
+    "topk_ignores_diagonal_slot": ("int64_t want = (int64_t)p->topk - 1;", "int64_t want = (int64_t)p->topk;"),
+    "topk_keeps_smallest": ("return x->test > y->test ? -1 : 1;", "return x->test < y->test ? -1 : 1;"),
 }
 
 DRIVER = textwrap.dedent('''
@@ -52,6 +54,7 @@ DRIVER = textwrap.dedent('''
         ("aug", lambda: pins.test_augmented_splitting_equals_the_hand_built_matrix()),
         ("reduce", lambda: pins.test_reduction_drops_the_smallest_share_of_the_iteration_matrix()),
         ("compose", lambda: pins.test_augmentation_then_reduction_compose()),
+        ("topk", lambda: pins.test_topk_keeps_the_largest_entries_of_the_eps_set()),
     ]
     hipcc = shutil.which("hipcc") or "/opt/rocm/bin/hipcc"
     if os.path.exists(hipcc):

@@ -552,3 +552,34 @@ def test_augmentation_then_reduction_compose():
     o1, o2 = O.Oracle(B, alpha=5.0, drop_frac=0.25), O.Oracle(Br)
     assert o1.dropped == K and o1.drop_thr == cut
     _same_records(o1, o2)
+
+
+# ------------------------------------------------ top-k retention (Section IV-B)
+def test_topk_keeps_the_largest_entries_of_the_eps_set():
+    """Only a prescribed number of the largest entries per row stay: the kept set
+    is the diagonal plus the k - 1 off-diagonal entries of the eps set with the
+    largest |N_rc| (values unchanged); no dropped entry is larger than a kept one;
+    k = 1 keeps the diagonal alone; k above every row length keeps the eps set."""
+    B = I.random_nonsym(400, seed=21)
+    o = O.Oracle(B)
+    kw = dict(seed=5, chains=64, delta=1e-4, eps=1e-3)
+    full = o.spai(**kw)
+    for k in (1, 5, 17):
+        top = o.spai(topk=k, **kw)
+        for r in range(B.n):
+            fc = full["col"][full["row_ptr"][r]:full["row_ptr"][r + 1]]
+            fv = full["val"][full["row_ptr"][r]:full["row_ptr"][r + 1]]
+            tc = top["col"][top["row_ptr"][r]:top["row_ptr"][r + 1]]
+            tv = top["val"][top["row_ptr"][r]:top["row_ptr"][r + 1]]
+            assert r in tc and tc.size == min(k, fc.size)
+            assert np.all(np.diff(tc) > 0)
+            pos = np.searchsorted(fc, tc)
+            assert np.array_equal(fc[pos], tc) and np.array_equal(fv[pos], tv)
+            nh = np.abs(fv * o.diag[fc])  # |N_rc| to within two roundings
+            kept = np.isin(fc, tc) & (fc != r)
+            dropped = ~np.isin(fc, tc)
+            if kept.any() and dropped.any():
+                assert nh[kept].min() >= nh[dropped].max() * (1.0 - 1e-15)
+    big = o.spai(topk=10 ** 6, **kw)
+    for f in ("row_ptr", "col", "val"):
+        assert np.array_equal(big[f], full[f])
