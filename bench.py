@@ -83,10 +83,11 @@ def main():
     ap.add_argument("--lanes", type=int, default=0)
     ap.add_argument("--sketch-slots", type=int, default=0)
     ap.add_argument("--heavy-weight", type=float, default=0.0)
-    ap.add_argument("--workload", default="random", choices=["random", "aniso27"],
-                    help="random: n=262144 random nonsymmetric (default); aniso27: 160^3 27-point anisotropic")
+    ap.add_argument("--workload", default="random", choices=["random", "aniso27", "batched"],
+                    help="random: n=262144 random nonsymmetric (default); aniso27: 160^3 27-point anisotropic; "
+                         "batched: 256 3D 7-point convection-diffusion matrices in one launch")
     ap.add_argument("--nx", type=int, default=160, help="grid side of the aniso27 workload")
-    ap.add_argument("--bicgstab", action="store_true", help="aniso27: host BiCGstab iterations with and without M")
+    ap.add_argument("--bicgstab", action="store_true", help="aniso27: device BiCGstab iterations with and without M")
     ap.add_argument("--learned", action="store_true",
                     help="learned vs uniform chains to ||I-MB||_F/sqrt(n) <= 0.3 (allocation-network workload)")
     ap.add_argument("--train-mats", type=int, default=2000)
@@ -111,6 +112,8 @@ def main():
     delta, eps, seed = 1e-4, 1e-3, 0
     if args.workload == "aniso27":
         return aniso_main(args)
+    if args.workload == "batched":
+        return batched_main(args)
     B = I.cfg2(args.n)
     dB = mcmi.DeviceCsr.from_host(B)
     x = torch.ones(B.n, dtype=torch.float64, device="cuda")
@@ -250,23 +253,71 @@ def aniso_main(args):
                         "bytes_per_transition": round(bpt, 2), "walk_ms": round(walk_s * 1e3, 3),
                         "walk_transitions_per_s": st.transitions / walk_s, "gather_ceiling_steps_per_s": ceiling}}
     if args.bicgstab:
-        import scipy.sparse as sp
-        import scipy.sparse.linalg as spla
-        rp, col, val = last.to_numpy()
-        M = sp.csr_matrix((val, col, rp), shape=(B.n, B.n))
-        Bs = B.to_scipy()
-        b = Bs @ np.ones(B.n)
+        # device BiCGstab (b = B 1, x0 = 0, rtol 1e-8): no preconditioner vs M
+        Bs_ones = torch.from_numpy(B.to_scipy() @ np.ones(B.n)).cuda()
         res_it = {}
-        for name, pre in (("none", None), ("mcmi", spla.LinearOperator(Bs.shape, matvec=lambda v: M @ v)),
-                          ("jacobi", spla.LinearOperator(Bs.shape, matvec=lambda v: v / Bs.diagonal()))):
-            it = [0]
-            t1 = time.perf_counter()
-            xs, info = spla.bicgstab(Bs, b, x0=np.zeros(B.n), rtol=1e-8, maxiter=5000, M=pre,
-                                     callback=lambda _: it.__setitem__(0, it[0] + 1))
-            res_it[name] = {"iterations": it[0], "info": int(info), "seconds": time.perf_counter() - t1,
-                            "rel_residual": float(np.linalg.norm(b - Bs @ xs) / np.linalg.norm(b))}
+        for name, M in (("none", None), ("mcmi", last)):
+            _, st_s = mcmi.bicgstab(dB, M, Bs_ones, rtol=1e-8, maxiter=5000)
+            res_it[name] = {"iterations": int(st_s.iterations), "converged": int(st_s.converged),
+                            "rel_residual": st_s.rel_residual, "solve_ms": st_s.ms}
             print(f"[aniso27] bicgstab {name}: {res_it[name]}", flush=True)
+        res_it["mcmi"]["preconditioner_plus_solve_ms"] = elapsed / args.steps * 1e3 + res_it["mcmi"]["solve_ms"]
         out["bicgstab"] = res_it
+    print(json.dumps(out), flush=True)
+
+
+def batched_main(args):
+    """256 3D 7-point convection-diffusion matrices (n log-uniform in [1e3, 1e5],
+    Peclet U[0, 5], ||C||_inf U[0.5, 0.85]; seed 3) in one batched launch: 128
+    chains/row, delta = 1e-4, eps = 1e-3. Also times the same matrices one launch
+    each (records built once) for comparison."""
+    import torch
+
+    from paper_2409_03095_amd import inputs as I
+    from paper_2409_03095_amd import mcmi
+    t0 = time.perf_counter()
+    mats, _ = I.convdiff_batch(256, seed=3)
+    print(f"[batched] generated {len(mats)} matrices, {sum(m.n for m in mats)} rows in "
+          f"{time.perf_counter() - t0:.1f} s", flush=True)
+    devs = [mcmi.DeviceCsr.from_host(B) for B in mats]
+    chains = args.chains if args.chains != 512 else 128
+    p = mcmi.params(seed=0, chains=chains, delta=1e-4, eps=1e-3, walk_prec=args.prec)
+    for _ in range(args.warmup):
+        res = mcmi.spai(mcmi.Cdf.batched(devs), p)
+        del res
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    walk_ms, trans = [], 0
+    for _ in range(args.steps):
+        cdf = mcmi.Cdf.batched(devs)
+        res = mcmi.spai(cdf, p)
+        walk_ms.append(res.stats.ms_walk)
+        trans += res.stats.transitions
+        last = res
+        del cdf
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    # one launch per matrix (records built once per matrix), same chains and seed
+    cdfs = [mcmi.Cdf(d) for d in devs]
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    single_trans = 0
+    for i, c in enumerate(cdfs):
+        r = mcmi.spai(c, mcmi.params(seed=0, chains=chains, delta=1e-4, eps=1e-3, walk_prec=args.prec, tag=i))
+        single_trans += r.stats.transitions
+    torch.cuda.synchronize()
+    single_s = time.perf_counter() - t1
+    st = last.stats
+    out = {"metric": METRIC, "value": trans / elapsed, "unit": "transitions/s", "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "ms_per_step": elapsed / args.steps * 1e3, "higher_is_better": True,
+           "dtype": "f32" if args.prec == 32 else "f64", "data": "synthetic",
+           "config": {"workload": "batched 256 x 3D 7-point convection-diffusion", "matrices": len(mats),
+                      "rows": int(sum(m.n for m in mats)), "chains_per_row": chains,
+                      "transitions_per_step": int(st.transitions), "nnz_M": int(last.nnz),
+                      "lanes_per_row": st.lanes_per_row, "hash_slots": st.hash_slots},
+           "walk_ms": float(np.mean(walk_ms)),
+           "one_launch_per_matrix": {"seconds": single_s, "transitions": int(single_trans),
+                                     "transitions_per_s": single_trans / single_s}}
     print(json.dumps(out), flush=True)
 
 

@@ -261,7 +261,7 @@ int orc_prepare(int64_t n, const int64_t *rp, const int32_t *ci, const double *v
     rp2[n] = pos;
     free(dh);
     if (norm_b)
-        *norm_b = nrm;
+        *norm_b = alpha > 0.0 ? nrm : 0.0; /* reported only when it was used */
     if (thr_out)
         *thr_out = thr;
     if (dropped)

@@ -74,20 +74,33 @@ def init_params(seed):
     return np.concatenate([p.reshape(-1) for p in parts])
 
 
-def residual_sample(B, M_rp, M_col, M_val, rows):
-    """||e_r - M_r B||_2^2 for the sampled rows (exact sparse products)."""
+def sample_rows(res, rows):
+    """The listed rows of M (a SpaiResult) as host CSR arrays, gathered on the
+    device so that only the sample crosses PCIe."""
+    import torch
+    rp, col, val = res.to_torch()
+    r = torch.as_tensor(np.asarray(rows, dtype=np.int64), device="cuda")
+    starts, lens = rp[r], rp[r + 1] - rp[r]
+    sub_rp = torch.zeros(r.numel() + 1, dtype=torch.int64, device="cuda")
+    sub_rp[1:] = torch.cumsum(lens, 0)
+    total = int(sub_rp[-1].item())
+    pos = torch.arange(total, device="cuda") - torch.repeat_interleave(sub_rp[:-1], lens, output_size=total)
+    idx = torch.repeat_interleave(starts, lens, output_size=total) + pos
+    return sub_rp.cpu().numpy(), col[idx].cpu().numpy(), val[idx].cpu().numpy()
+
+
+def residual_sample(B, sub_rp, sub_col, sub_val, rows):
+    """||e_r - M_r B||_2^2 for the sampled rows (exact sparse products); the
+    sub_* arrays hold M's sampled rows in the order of `rows`."""
     import scipy.sparse as sp
     Bs = B.to_scipy()
-    sub_rp = np.concatenate([[0], np.cumsum(M_rp[rows + 1] - M_rp[rows])])
-    sub_col = np.concatenate([M_col[M_rp[r]:M_rp[r + 1]] for r in rows])
-    sub_val = np.concatenate([M_val[M_rp[r]:M_rp[r + 1]] for r in rows])
     Ms = sp.csr_matrix((sub_val, sub_col, sub_rp), shape=(len(rows), B.n))
     E = sp.csr_matrix((np.ones(len(rows)), (np.arange(len(rows)), rows)), shape=(len(rows), B.n))
     R = (Ms @ Bs - E).tocsr()
     return np.asarray(R.multiply(R).sum(axis=1)).ravel()
 
 
-def evaluate(B, chains_per_row, delta, eps, seed=0, sample_rows=None, prec=64, cdf=None):
+def evaluate(B, chains_per_row, delta, eps, seed=0, rows_sample=None, prec=64, cdf=None):
     """Run mcmi_spai with the given per-row chains; return transitions, GPU time and
     the normalised residual estimate with its 95 % half-width."""
     import torch
@@ -99,9 +112,8 @@ def evaluate(B, chains_per_row, delta, eps, seed=0, sample_rows=None, prec=64, c
     res = mcmi.spai(cdf, mcmi.params(seed=seed, chains=1, delta=delta, eps=eps, walk_prec=prec), chains_per_row=cpr)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    rp, col, val = res.to_numpy()
-    rows = sample_rows if sample_rows is not None else np.arange(B.n)
-    sq = residual_sample(B, rp, col, val, rows)
+    rows = rows_sample if rows_sample is not None else np.arange(B.n)
+    sq = residual_sample(B, *sample_rows(res, rows), rows)
     mean = float(sq.mean())
     half = 1.96 * float(sq.std(ddof=1)) / math.sqrt(len(rows)) if len(rows) > 1 else 0.0
     return {"transitions": int(res.stats.transitions), "wall_s": wall, "ms_walk": float(res.stats.ms_walk),

@@ -154,3 +154,24 @@ def test_allocation_matches_reference(mc):
     bad[7] = np.nan
     chains, lam, fb = mc.allocate(torch.from_numpy(bad).cuda(), torch.from_numpy(cost).cuda(), budget)
     assert fb and np.all(chains.cpu().numpy() == budget // cost.sum())
+
+
+def test_quality_sample_matches_oracle_residual(mc):
+    """The learned-allocation quality estimate: rows of M gathered on the device
+    equal the full download's rows, and the sampled ||e_r - M_r B||^2 equals the
+    oracle's residual rows of the same M."""
+    import scipy.sparse as sp
+    from paper_2409_03095_amd import learned as L
+    B = I.family_5pt(7, 30, 34)
+    dB = mc.DeviceCsr.from_host(B)
+    res = mc.spai(mc.Cdf(dB), mc.params(seed=2, chains=24, delta=1e-3, eps=1e-3))
+    rp, col, val = res.to_numpy()
+    rows = np.sort(np.random.default_rng(0).choice(B.n, 200, replace=False))
+    srp, scol, sval = L.sample_rows(res, rows)
+    for t, r in enumerate(rows):
+        assert np.array_equal(scol[srp[t]:srp[t + 1]], col[rp[r]:rp[r + 1]])
+        assert np.array_equal(sval[srp[t]:srp[t + 1]], val[rp[r]:rp[r + 1]])
+    got = L.residual_sample(B, srp, scol, sval, rows)
+    Msub = sp.csr_matrix((sval, scol, srp), shape=(rows.size, B.n))
+    ref = O.residual_rows(B, Msub, rows)
+    assert np.allclose(got, ref, rtol=1e-12, atol=1e-15)
