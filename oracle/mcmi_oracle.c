@@ -13,7 +13,9 @@
  *   O2  transition CDF     p_ij proportional to |c_ij| (the paper never defines P;
  *                          this is the "almost optimal" choice), quantized to
  *                          integer weights so both sides sample the same Chat
- *   O3  random numbers     Philox4x32-10 (Salmon et al., SC'11), counter-based
+ *   O3  random numbers     Philox4x32-10 (Salmon et al., SC'11), counter-based;
+ *                          a word picks the next state by the alias method
+ *                          (Walker; Vose's exact-integer tables)
  *   O4  walk               eq. (2): W_0 = 1 at s_0 = r, W_j = W_{j-1} c/p; stop
  *                          when the next weight falls below delta (checked before
  *                          the draw) or the row of C is empty
@@ -99,6 +101,8 @@ typedef struct {
     double *shat;     /* n: Shat_i = a_max * W_i * 2^-Q (one rounding) */
     double *diag;     /* n: d_i = b_ii */
     double norm_inf;  /* max_i Shat_i */
+    uint32_t *athr;   /* alias table: threshold T of each entry's bucket (O3) */
+    int32_t *aidx;    /* alias table: alias of each entry's bucket, 0-based within the row */
 } orc_mat;
 
 static int ceil_log2_u64(uint64_t m)
@@ -333,6 +337,73 @@ int orc_build(int64_t n, const int64_t *rp, const int32_t *ci, const double *v,
     return ORC_OK;
 }
 
+/* O3 tables: the alias method of Walker in the exact-integer construction of
+ * Vose ("A linear algorithm for generating random numbers with a given
+ * distribution", IEEE TSE 17(9), 1991), one table per row. With m entries,
+ * weights w_k (from cum) and W = sum w_k, entry k has the integer mass
+ * q_k = m w_k and every one of the m buckets holds W units. The entries are
+ * put, in column order, on a `small` stack (q < W) or a `large` stack (q >= W).
+ * While both stacks are non-empty, the top s of small and the top l of large are
+ * popped; bucket s keeps T_s = q_s units for entry s and gives the other W - q_s
+ * to l (A_s = l, q_l -= W - q_s), and l is pushed back on small if now q_l < W,
+ * else on large. Buckets left over hold exactly W for their own entry
+ * (T = W, A = self). Each entry's mass is conserved exactly:
+ * T_k + sum over buckets j with A_j = k of (W - T_j) = m w_k. */
+int orc_build_alias(int64_t n, const int64_t *cptr, const uint32_t *cum, const uint32_t *wsum,
+                    uint32_t *athr, int32_t *aidx)
+{
+    int64_t mmax = 0;
+    for (int64_t i = 0; i < n; ++i)
+        if (cptr[i + 1] - cptr[i] > mmax)
+            mmax = cptr[i + 1] - cptr[i];
+    uint64_t *q = (uint64_t *)malloc((size_t)(mmax + 1) * sizeof(uint64_t));
+    int64_t *small = (int64_t *)malloc((size_t)(mmax + 1) * sizeof(int64_t));
+    int64_t *large = (int64_t *)malloc((size_t)(mmax + 1) * sizeof(int64_t));
+    if (!q || !small || !large) {
+        free(q);
+        free(small);
+        free(large);
+        return ORC_ERR_NOMEM;
+    }
+    for (int64_t i = 0; i < n; ++i) {
+        int64_t b = cptr[i], m = cptr[i + 1] - cptr[i];
+        uint64_t W = wsum[i];
+        int64_t ns = 0, nl = 0;
+        for (int64_t k = 0; k < m; ++k) {
+            uint64_t w = (uint64_t)cum[b + k] - (k ? (uint64_t)cum[b + k - 1] : 0);
+            q[k] = (uint64_t)m * w;
+            if (q[k] < W)
+                small[ns++] = k;
+            else
+                large[nl++] = k;
+        }
+        while (ns > 0 && nl > 0) {
+            int64_t sm = small[--ns], lg = large[--nl];
+            athr[b + sm] = (uint32_t)q[sm];
+            aidx[b + sm] = (int32_t)lg;
+            q[lg] -= W - q[sm];
+            if (q[lg] < W)
+                small[ns++] = lg;
+            else
+                large[nl++] = lg;
+        }
+        while (nl > 0) {
+            int64_t k = large[--nl];
+            athr[b + k] = (uint32_t)W;
+            aidx[b + k] = (int32_t)k;
+        }
+        while (ns > 0) { /* cannot happen with exact masses */
+            int64_t k = small[--ns];
+            athr[b + k] = (uint32_t)W;
+            aidx[b + k] = (int32_t)k;
+        }
+    }
+    free(q);
+    free(small);
+    free(large);
+    return ORC_OK;
+}
+
 /* L_max: max_len if given; otherwise the smallest L with p_L < delta, where
  * p_0 = 1 and p_j = p_{j-1} * ||Chat||_inf (one IEEE product per step). */
 int orc_lmax(double norm_inf, double delta, int max_len)
@@ -397,14 +468,22 @@ static uint32_t stream_word(orc_stream *st, int j)
     return st->blk[(j - 1) & 3];
 }
 
-/* O3: t = floor(u * W_s / 2^32); k* = first k with t < cum_k (linear scan). */
+/* O3: with m entries, the product u m < m 2^32 names the bucket j = floor(u m / 2^32)
+ * (uniform over the m buckets) and its low 32 bits f the position inside it:
+ * r = floor(f W_s / 2^32) is uniform over the bucket's W_s units; units r < T_j
+ * belong to entry j, the others to its alias A_j. Entry k is drawn with
+ * probability m w_k / (m W_s) = w_k / W_s, up to the 2^-32 grain of u. */
 static int64_t draw_entry(const orc_mat *A, int64_t s, uint32_t u)
 {
-    uint64_t t = ((uint64_t)u * (uint64_t)A->wsum[s]) >> 32;
-    for (int64_t k = A->cptr[s]; k < A->cptr[s + 1]; ++k)
-        if (t < (uint64_t)A->cum[k])
-            return k;
-    return -1; /* unreachable: t < W_s = cum of the last entry */
+    int64_t b = A->cptr[s];
+    uint64_t m = (uint64_t)(A->cptr[s + 1] - b);
+    uint64_t um = (uint64_t)u * m;
+    uint64_t j = um >> 32;
+    uint64_t f = um & 0xFFFFFFFFull;
+    uint64_t r = (f * (uint64_t)A->wsum[s]) >> 32;
+    if (r < (uint64_t)A->athr[b + (int64_t)j])
+        return b + (int64_t)j;
+    return b + A->aidx[b + (int64_t)j];
 }
 
 /* Exposed for the pins: the entry of row s (0-based within the row) chosen by

@@ -58,6 +58,7 @@ def lib():
         L.orc_apply.restype = None
         L.orc_draw.restype = ctypes.c_int64
         L.orc_draw.argtypes = [ctypes.c_void_p, ctypes.c_int64, ctypes.c_uint32]
+        L.orc_build_alias.restype = ctypes.c_int
         L.orc_prepare.restype = ctypes.c_int
         L.orc_prepare.argtypes = [ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_double,
                                   ctypes.c_double, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
@@ -74,7 +75,8 @@ def _p(a):
 class _Mat(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int64), ("cptr", ctypes.c_void_p), ("ccol", ctypes.c_void_p),
                 ("cval", ctypes.c_void_p), ("cum", ctypes.c_void_p), ("wsum", ctypes.c_void_p),
-                ("shat", ctypes.c_void_p), ("diag", ctypes.c_void_p), ("norm_inf", ctypes.c_double)]
+                ("shat", ctypes.c_void_p), ("diag", ctypes.c_void_p), ("norm_inf", ctypes.c_double),
+                ("athr", ctypes.c_void_p), ("aidx", ctypes.c_void_p)]
 
 
 class _Params(ctypes.Structure):
@@ -153,9 +155,13 @@ class Oracle:
                            ctypes.byref(nrm)))
         self.norm_inf = nrm.value
         self.nnz_c = m
+        self.athr = np.zeros(max(m, 1), dtype=np.uint32)
+        self.aidx = np.zeros(max(m, 1), dtype=np.int32)
+        _check(L.orc_build_alias(ctypes.c_int64(self.n), _p(self.cptr), _p(self.cum), _p(self.wsum),
+                                 _p(self.athr), _p(self.aidx)))
         self._mat = _Mat(self.n, _p(self.cptr).value, _p(self.ccol).value, _p(self.cval).value,
                          _p(self.cum).value, _p(self.wsum).value, _p(self.shat).value,
-                         _p(self.diag).value, self.norm_inf)
+                         _p(self.diag).value, self.norm_inf, _p(self.athr).value, _p(self.aidx).value)
 
     # ---- derived views (used by tests; all from the oracle's own arrays)
     def row_weights(self, i):

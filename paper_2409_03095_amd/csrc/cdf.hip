@@ -6,7 +6,8 @@
 //   w_k = max(1, floor(2^Q a_k / a_max)), cum_k = w_1 + ... + w_k (exact uint32),
 //   W = cum_m, Shat = (a_max * W) * 2^-Q (one rounding).
 // The integer scan is order-free, so a wavefront prefix scan gives exactly the
-// sequential sums.
+// sequential sums. Each row's alias table (the sampler of a step) is then built
+// from the weights by Vose's exact-integer construction.
 #include <string.h>
 
 #include "common.hpp"
@@ -177,6 +178,8 @@ __global__ void __launch_bounds__(256) k_fill(int64_t n, const int64_t *__restri
                 hdr[2] = 0u;
                 hdr[3] = __float_as_uint(0.0f);
                 *(double *)(hdr + 4) = 0.0;
+                hdr[6] = 0u;
+                hdr[7] = 0u;
             }
             continue;
         }
@@ -227,44 +230,65 @@ __global__ void __launch_bounds__(256) k_fill(int64_t n, const int64_t *__restri
             hdr[2] = carry;
             hdr[3] = __float_as_uint((float)shat);
             *(double *)(hdr + 4) = shat;
+            hdr[6] = 0u;
+            hdr[7] = 0u;
             atomicMax(norm_bits, (unsigned long long)__double_as_longlong(shat));
         }
     }
 }
 
-// Write each row's group summary (header words 6..) and its groups of 4
-// {cum, target} from the sorted nodes; padding as described in common.hpp.
-__global__ void __launch_bounds__(256) k_groups(int64_t n, const uint32_t *__restrict__ mrow,
-                                                const uint32_t *__restrict__ roff32,
-                                                const int64_t *__restrict__ cptr,
-                                                const uint2 *__restrict__ sorted, uint32_t *__restrict__ rec) {
-    const int lane = threadIdx.x & 63;
-    const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
-    const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
-    for (int64_t r = wave; r < n; r += nwaves) {
+// Alias table of each row (Walker's method, Vose's exact-integer construction;
+// one thread per row, as the construction is sequential): masses q_k = m w_k
+// (w_k from the row's cums), bucket capacity W. Entries go, in column order, on
+// a `small` (q < W) or `large` stack; while both are non-empty the tops s and l
+// are popped, bucket s keeps T_s = q_s and gives W - q_s to l (A_s = l,
+// q_l -= W - q_s), and l goes back on small if q_l < W, else on large. Leftover
+// buckets keep all W units (T = W, A = self). Every entry's final q is its
+// threshold. Both stacks live in one scratch array of the row's length (small
+// grows up from the front, large down from the back), q in another.
+__global__ void __launch_bounds__(256) k_alias(int64_t n, const uint32_t *__restrict__ mrow,
+                                               const uint32_t *__restrict__ roff32, const int64_t *__restrict__ cptr,
+                                               const uint2 *__restrict__ sorted, uint32_t *__restrict__ qs,
+                                               int32_t *__restrict__ stk, uint32_t *__restrict__ rec) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < n; r += stride) {
         const uint32_t m = mrow[r];
-        const uint32_t G = record_groups(m), hb = header_units(m);
+        if (m == 0) continue;
         const int64_t base = cptr[r];
-        uint32_t *recp = rec + (size_t)roff32[r] * kUnitWords;
-        const uint32_t nsum = hb * kUnitWords - kHdrWords;
-        for (uint32_t i = lane; i < nsum; i += 64) {
-            uint32_t v = kPad;
-            if (i < G) {
-                const uint32_t last = (i + 1u) * kGroup < m ? (i + 1u) * kGroup - 1u : m - 1u;
-                v = sorted[base + last].x;
-            }
-            recp[kHdrWords + i] = v;
-        }
-        uint32_t *grp = recp + (size_t)hb * kUnitWords;
-        for (uint32_t q = lane; q < group_units(m) * kUnitWords; q += 64) {
-            const uint32_t g = q / kGroupWords, w = q % kGroupWords;
-            const uint32_t k = g * kGroup + (w % kGroup);
-            uint32_t v;
-            if (w < (uint32_t)kGroup)
-                v = k < m ? sorted[base + k].x : kPad;
+        uint32_t *ent = rec + ((size_t)roff32[r] + kHdrUnits) * kUnitWords;
+        const uint32_t W = sorted[base + m - 1].x;
+        uint32_t *q = qs + base;
+        int32_t *st = stk + base;
+        int ns = 0, nl = 0;
+        uint32_t prev = 0;
+        for (uint32_t k = 0; k < m; ++k) {
+            const uint2 node = sorted[base + k];
+            const uint32_t w = node.x - prev;
+            prev = node.x;
+            const uint32_t qk = m * w;  // <= m 2^Q <= 2^31
+            q[k] = qk;
+            ent[k * kUnitWords + 1] = node.y;  // own target
+            ent[k * kUnitWords + 2] = k;       // alias index (self until paired)
+            ent[k * kUnitWords + 3] = w;
+            if (qk < W)
+                st[ns++] = (int32_t)k;
             else
-                v = k < m ? sorted[base + k].y : 0u;
-            grp[q] = v;
+                st[m - 1 - nl++] = (int32_t)k;
+        }
+        while (ns > 0 && nl > 0) {
+            const int32_t sm = st[--ns];
+            const int32_t lg = st[m - nl--];
+            ent[sm * kUnitWords + 2] = (uint32_t)lg;
+            const uint32_t ql = q[lg] - (W - q[sm]);
+            q[lg] = ql;
+            if (ql < W)
+                st[ns++] = lg;
+            else
+                st[m - 1 - nl++] = lg;
+        }
+        for (uint32_t k = 0; k < m; ++k) {
+            ent[k * kUnitWords + 0] = q[k];
+            ent[k * kUnitWords + 2] = sorted[base + ent[k * kUnitWords + 2]].y;  // alias index -> its target
         }
     }
 }
@@ -311,6 +335,8 @@ extern "C" mcmi_status mcmi_build_cdf_ex(const mcmi_csr_in *B, const mcmi_cdf_op
     unsigned long long *norm_bits = nullptr;
     void *tmp = nullptr;
     uint2 *sorted = nullptr;
+    uint32_t *qs = nullptr;
+    int32_t *stk = nullptr;
     unsigned long long *cut_keys = nullptr, *sel = nullptr;
     mcmi_status st = MCMI_OK;
     auto cleanup = [&]() {
@@ -324,6 +350,8 @@ extern "C" mcmi_status mcmi_build_cdf_ex(const mcmi_csr_in *B, const mcmi_cdf_op
         hipFree(norm_bits);
         hipFree(tmp);
         hipFree(sorted);
+        hipFree(qs);
+        hipFree(stk);
     };
     auto bail = [&](mcmi_status code, const std::string &msg) {
         cleanup();
@@ -402,7 +430,7 @@ extern "C" mcmi_status mcmi_build_cdf_ex(const mcmi_csr_in *B, const mcmi_cdf_op
         ::memcpy(&cdf->drop_thr, &hcut, sizeof(double));
         cdf->dropped = cnt - htot[1];
     }
-    if (htot[0] >= (int64_t)kSignBit) return bail(MCMI_ERR_CAPACITY, "mcmi_build_cdf: records exceed 128 GiB");
+    if (htot[0] >= (int64_t)kSignBit) return bail(MCMI_ERR_CAPACITY, "mcmi_build_cdf: records exceed 32 GiB");
     cdf->rec_units = (uint64_t)htot[0];
     cdf->nnz_c = htot[1];
     TRY(hipMalloc(&cdf->rec, (size_t)htot[0] * kUnitWords * 4u + 64u));
@@ -410,7 +438,9 @@ extern "C" mcmi_status mcmi_build_cdf_ex(const mcmi_csr_in *B, const mcmi_cdf_op
     k_fill<<<grid, 256, 0, s>>>(n, B->row_ptr_dev, B->col_dev, B->val_dev, cdf->diag, cdf->mrow, roff64, cptr,
                                 cut, cdf->roff, cdf->rec, sorted, norm_bits);
     TRY(hipGetLastError());
-    k_groups<<<grid, 256, 0, s>>>(n, cdf->mrow, cdf->roff, cptr, sorted, cdf->rec);
+    TRY(hipMalloc(&qs, (size_t)(htot[1] > 0 ? htot[1] : 1) * sizeof(uint32_t)));
+    TRY(hipMalloc(&stk, (size_t)(htot[1] > 0 ? htot[1] : 1) * sizeof(int32_t)));
+    k_alias<<<grid_for(n), 256, 0, s>>>(n, cdf->mrow, cdf->roff, cptr, sorted, qs, stk, cdf->rec);
     TRY(hipGetLastError());
     unsigned long long hnorm = 0;
     TRY(hipMemcpyAsync(&hnorm, norm_bits, sizeof(hnorm), hipMemcpyDeviceToHost, s));

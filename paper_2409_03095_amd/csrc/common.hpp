@@ -21,40 +21,25 @@ mcmi_status fail(mcmi_status st, const std::string &msg);
     } while (0)
 
 // ----------------------------------------------------------- record layout
-// One record per row s of C, 64-byte aligned, addressed by its offset in
-// 64-byte units (31 bits: up to 128 GiB of records). With m entries the row has
-// G = ceil(m / 4) groups of 4 consecutive entries (column order) and a header
-// block of hb = ceil((6 + G) / 16) units:
-//   word 0  row index s               word 1  m
-//   word 2  W = total integer weight  word 3  Shat_s as binary32
-//   words 4-5  Shat_s as binary64
-//   words 6 .. 6+G-1  the inclusive cum of each group's last entry (the group
-//                     summary); the rest of the block holds 0xFFFFFFFF
-// then ceil(G / 2) units holding the groups, 8 words (32 bytes) each: the cums
-// of the group's 4 entries (inclusive integer prefix sums of the weights), then
-// their targets: the record offset of the column's row with bit 31 set when
-// c < 0. Missing entries (the last group's tail, the unused half of the last
-// unit) have cum = 0xFFFFFFFF and target 0. A draw t < W selects the first
-// entry with t < cum: the group is the number of summaries <= t, the entry
-// inside it the number of the group's cums <= t; both searches run in
-// registers. A step reads the first 48 bytes of the header unit (three 16-byte
-// loads issued together) and one 32-byte group (two loads issued together):
-// few loads per random unit keep the unit in the L1 cache until its last load.
-constexpr int kUnitWords = 16;
-constexpr int kHdrWords = 6;
-constexpr int kGroup = 4;
-constexpr int kGroupWords = 2 * kGroup;
+// One record per row s of C, 16-byte aligned, addressed by its offset in 16-byte
+// units (31 bits: up to 32 GiB of records). With m entries (column order) it is
+// 2 + m units:
+//   unit 0   {row index s, m, W = total integer weight, Shat_s as binary32}
+//   unit 1   {Shat_s as binary64 (2 words), 0, 0}
+//   unit 2+j {T_j, target_j, target_{A_j}, w_j}  for bucket j = 0 .. m-1
+// where (T, A) is the row's alias table (Walker's method in Vose's exact-integer
+// construction: bucket j keeps T_j of its W units for entry j and gives the rest
+// to entry A_j) and a target is the record offset of the column's row with bit
+// 31 set when c < 0. A draw with the 32-bit word u takes bucket j = (u m) >> 32
+// and r = ((u m mod 2^32) W) >> 32: the next state is target_j if r < T_j, else
+// target_{A_j}. A step therefore reads one 16-byte header (plus unit 1 for FP64
+// weights) and one 16-byte bucket: one load per random unit, so a unit is never
+// needed in the L1 after its single load.
+constexpr int kUnitWords = 4;
+constexpr int kHdrUnits = 2;
 constexpr uint32_t kSignBit = 0x80000000u;
-constexpr uint32_t kPad = 0xFFFFFFFFu;
 
-__host__ __device__ inline uint32_t record_groups(uint32_t m) { return (m + kGroup - 1u) / kGroup; }
-__host__ __device__ inline uint32_t header_units(uint32_t m) {
-    return (kHdrWords + record_groups(m) + kUnitWords - 1u) / kUnitWords;
-}
-__host__ __device__ inline uint32_t group_units(uint32_t m) {
-    return (record_groups(m) * kGroupWords + kUnitWords - 1u) / kUnitWords;
-}
-__host__ __device__ inline uint32_t record_units(uint32_t m) { return header_units(m) + group_units(m); }
+__host__ __device__ inline uint32_t record_units(uint32_t m) { return (uint32_t)kHdrUnits + m; }
 
 // Error flags raised by device-side validation (bit set).
 enum : uint32_t {
@@ -182,7 +167,7 @@ struct mcmi_cdf {
     int64_t dropped = 0;    // entries of C removed by the reduction
     uint64_t rec_units = 0;
     uint32_t *rec = nullptr;       // records, 16 words per unit
-    uint32_t *roff = nullptr;      // n: record offset (64-byte units) of each row
+    uint32_t *roff = nullptr;      // n: record offset (16-byte units) of each row
     double *diag = nullptr;        // n: b_ii
     uint32_t *mrow = nullptr;      // n: entries of each row of C
     // batched record sets (several matrices, block-diagonal row space)

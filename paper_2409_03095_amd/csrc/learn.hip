@@ -37,16 +37,12 @@ __global__ void __launch_bounds__(256) k_features(int64_t n, const uint32_t *__r
         const uint32_t *recp = rec + (size_t)roff[r] * kUnitWords;
         const uint32_t m = recp[1], W = recp[2];
         const double S = __hiloint2double((int)recp[5], (int)recp[4]);
-        const uint32_t hb = header_units(m);
         double ps = 0.0, pm = 0.0, sgn = 0.0, smax = 0.0;
         uint32_t wmax = 0;
         for (uint32_t k = lane; k < m; k += 64) {
-            const uint32_t g = k / kGroup, sl = k % kGroup;
-            const uint32_t *grp = recp + (size_t)hb * kUnitWords + (size_t)g * kGroupWords;
-            const uint32_t cum = grp[sl];
-            const uint32_t prev = sl ? grp[sl - 1] : (g ? recp[kHdrWords + g - 1] : 0u);
-            const uint32_t w = cum - prev;
-            const uint32_t tgt = grp[kGroup + sl];
+            const uint4 e = ((const uint4 *)recp)[kHdrUnits + k];  // {T, target, alias target, w}
+            const uint32_t w = e.w;
+            const uint32_t tgt = e.y;
             const uint32_t *trec = rec + (size_t)(tgt & ~kSignBit) * kUnitWords;
             const double St = __hiloint2double((int)trec[5], (int)trec[4]);
             const double mt = (double)trec[1];
@@ -143,7 +139,7 @@ __global__ void __launch_bounds__(64) k_pilot(WalkArgs a, int pilot, int cap, do
         while (__any(active)) {
             if (active) {
                 StepHdr Hd;
-                load_header(a.rec, off, Hd);
+                load_header<kF32>(a.rec, off, Hd);
                 const uint4 h = Hd.h0;
                 const double s64 = kF32 ? 0.0 : header_shat64(Hd);
                 // contribution (j = 0 included: the start state gets W_0 = 1)
@@ -191,7 +187,7 @@ __global__ void __launch_bounds__(64) k_pilot(WalkArgs a, int pilot, int cap, do
                     blk.x = blk.y;
                     blk.y = blk.z;
                     blk.z = blk.w;
-                    const uint32_t tgt = draw_target(a.rec, off, Hd, __umulhi(u, h.z));
+                    const uint32_t tgt = draw_target(a.rec, off, Hd, u);
                     const bool neg = (tgt & kSignBit) != 0u;
                     if (kF32)
                         w32 = neg ? -wn32 : wn32;

@@ -14,10 +14,8 @@
 //  * each lane runs one chain at a time and starts the row's next unstarted chain
 //    as soon as its chain stops, so short and long chains do not wait for each
 //    other;
-//  * a step reads the header of the current state (48 bytes of one 64-byte
-//    unit), draws one Philox word, picks the group of 4 entries from the
-//    header's group summaries and the entry from that group's 32 bytes: two
-//    dependent requests;
+//  * a step reads the 16-byte header of the current state, draws one Philox word
+//    and reads the one 16-byte alias bucket it names: two dependent requests;
 //  * contributions go to an open-addressing hash per wave in LDS (key = column,
 //    value = float64 sum, LDS float64 atomics); a full neighbourhood spills to a
 //    per-wave hash in HBM;
@@ -87,7 +85,7 @@ __device__ __forceinline__ void walk_row(const WalkArgs &a, int64_t task, int32_
     while (__any(active)) {
         if (active) {
             StepHdr H;
-            load_header(a.rec, off, H);
+            load_header<kF32>(a.rec, off, H);
             const uint4 h = H.h0;  // row, m, W, Shat32
             const double s64 = kF32 ? 0.0 : header_shat64(H);
             if (j > 0) {
@@ -126,8 +124,7 @@ __device__ __forceinline__ void walk_row(const WalkArgs &a, int64_t task, int32_
                 blk.x = blk.y;
                 blk.y = blk.z;
                 blk.z = blk.w;
-                const uint32_t t = __umulhi(u, h.z);
-                const uint32_t tgt = draw_target(a.rec, off, H, t);
+                const uint32_t tgt = draw_target(a.rec, off, H, u);
                 const bool neg = (tgt & kSignBit) != 0u;
                 if (kF32)
                     w32 = neg ? -wn32 : wn32;

@@ -179,7 +179,7 @@ __device__ __forceinline__ void run_chains(const WalkArgs &a, const RowCtx &rc, 
     paused = false;
     while (st.active) {
         StepHdr H;
-        load_header(a.rec, st.off, H);
+        load_header<kF32>(a.rec, st.off, H);
         const uint4 h = H.h0;  // row, m, W, Shat32
         const double s64 = kF32 ? 0.0 : header_shat64(H);
         if (st.j > 0) {
@@ -220,8 +220,7 @@ __device__ __forceinline__ void run_chains(const WalkArgs &a, const RowCtx &rc, 
             st.blk.x = st.blk.y;
             st.blk.y = st.blk.z;
             st.blk.z = st.blk.w;
-            const uint32_t t = __umulhi(u, h.z);
-            const uint32_t tgt = draw_target(a.rec, st.off, H, t);
+            const uint32_t tgt = draw_target(a.rec, st.off, H, u);
             const bool neg = (tgt & kSignBit) != 0u;
             if (kF32)
                 st.w32 = neg ? -wn32 : wn32;

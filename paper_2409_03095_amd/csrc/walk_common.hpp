@@ -129,66 +129,34 @@ __device__ __forceinline__ void philox_ids(const WalkArgs &a, int32_t r, uint32_
 }
 
 // ------------------------------------------------------------- one step
-// The header unit of the current state: h0 = {row, m, W, Shat32},
-// h1 = {Shat64 lo, Shat64 hi, summary 0, summary 1}, h2/h3 = summaries 2..9.
-// Summary i is the cumulative weight at the end of group i; the last group's
-// summary equals W, which no draw t < W reaches, so a row with G groups needs
-// summaries 0..G-2 only.
+// The header of the current state: h0 = {row, m, W, Shat32}; s64 = Shat as
+// binary64 (read in FP64 mode only).
 struct StepHdr {
-    uint4 h0, h1, h2, h3;
+    uint4 h0;
+    uint2 s64;
 };
 
-// h0..h2 are loaded together (a dependent load of a random unit waits a full
-// memory latency when the line has left the L1 meanwhile); h3 only when the row
-// needs summaries 6..9. Words not loaded read as padding.
+template <bool kF32>
 __device__ __forceinline__ void load_header(const uint32_t *rec, uint32_t off, StepHdr &H) {
-    const uint4 *u = (const uint4 *)(rec + (size_t)off * kUnitWords);
+    const uint4 *u = (const uint4 *)rec + off;
     H.h0 = u[0];
-    H.h1 = u[1];
-    H.h2 = u[2];
-    H.h3 = make_uint4(kPad, kPad, kPad, kPad);
-    const uint32_t G = record_groups(H.h0.y);
-    if (G >= 8u && G <= (uint32_t)(kUnitWords - kHdrWords)) H.h3 = u[3];
+    H.s64 = kF32 ? make_uint2(0u, 0u) : *(const uint2 *)(u + 1);
 }
 
 __device__ __forceinline__ double header_shat64(const StepHdr &H) {
-    return __hiloint2double((int)H.h1.y, (int)H.h1.x);
+    return __hiloint2double((int)H.s64.y, (int)H.s64.x);
 }
 
-__device__ __forceinline__ uint32_t count_le(const uint4 &v, uint32_t t) {
-    return (uint32_t)(v.x <= t) + (uint32_t)(v.y <= t) + (uint32_t)(v.z <= t) + (uint32_t)(v.w <= t);
-}
-
-// Target word (record offset | sign bit) of the first entry of the row with
-// t < cum: group = number of group summaries <= t, entry = number of the
-// group's cums <= t (padding words never compare <= t because t < W <= 2^31).
-// The group's cums and targets are loaded together.
-__device__ __forceinline__ uint32_t draw_target(const uint32_t *rec, uint32_t off, const StepHdr &H, uint32_t t) {
-    const uint32_t m = H.h0.y;
-    const uint32_t G = record_groups(m);
-    uint32_t g;
-    if (G <= (uint32_t)(kUnitWords - kHdrWords)) {
-        g = (uint32_t)(H.h1.z <= t) + (uint32_t)(H.h1.w <= t) + count_le(H.h2, t) + count_le(H.h3, t);
-    } else {
-        const uint32_t *summ = rec + (size_t)off * kUnitWords + kHdrWords;
-        uint32_t lo = 0, hi = G;
-        while (lo < hi) {
-            const uint32_t mid = (lo + hi) >> 1;
-            if (summ[mid] <= t)
-                lo = mid + 1;
-            else
-                hi = mid;
-        }
-        g = lo;
-    }
-    const uint4 *grp = (const uint4 *)(rec + ((size_t)off + header_units(m)) * kUnitWords + (size_t)g * kGroupWords);
-    const uint4 c = grp[0], tg = grp[1];
-    const uint32_t k = count_le(c, t);
-    uint32_t r = tg.x;
-    r = k == 1u ? tg.y : r;
-    r = k == 2u ? tg.z : r;
-    r = k == 3u ? tg.w : r;
-    return r;
+// Target word (record offset | sign bit) drawn by the 32-bit word u: bucket
+// j = (u m) >> 32, position r = ((u m mod 2^32) W) >> 32 among its W units; the
+// bucket's own entry if r < T_j, else its alias. One 16-byte load.
+__device__ __forceinline__ uint32_t draw_target(const uint32_t *rec, uint32_t off, const StepHdr &H, uint32_t u) {
+    const uint32_t m = H.h0.y, W = H.h0.z;
+    const uint32_t j = __umulhi(u, m);
+    const uint32_t f = u * m;
+    const uint32_t r = __umulhi(f, W);
+    const uint4 e = ((const uint4 *)rec)[(size_t)off + kHdrUnits + j];
+    return r < e.x ? e.y : e.z;
 }
 
 }  // namespace walkdev

@@ -5,37 +5,26 @@ U64 = 2.0 ** -53
 
 
 def decode_records(rec, roff, n):
-    """Decode the library's records (64-byte units: header unit with the group
-    summaries, then groups of 4 {cum, target}, two per unit) into per-row (row, m,
-    W, S32, S64, cum[], col[], neg[]) in column order, checking the summaries and
-    padding."""
+    """Decode the library's records (16-byte units: {row, m, W, S32}, {S64, 0, 0},
+    then one bucket {T, target, alias target, w} per entry) into per-row (row, m,
+    W, S32, S64, cum[], col[], neg[], thr[], alias_col[], alias_neg[]) in column
+    order, checking the padding words."""
     inv = {int(o): i for i, o in enumerate(roff)}
     out = []
     for i in range(n):
-        base = int(roff[i]) * 16
+        base = int(roff[i]) * 4
         row, m, W = int(rec[base]), int(rec[base + 1]), int(rec[base + 2])
         s32 = rec[base + 3:base + 4].view(np.float32)[0]
         s64 = rec[base + 4:base + 6].view(np.float64)[0]
-        G = (m + 3) // 4
-        hb = (6 + G + 15) // 16
-        gu = (8 * G + 15) // 16
-        summ = rec[base + 6:base + 16 * hb].astype(np.int64)
-        area = rec[base + 16 * hb:base + 16 * (hb + gu)]
-        cum, tgt = [], []
-        for g in range(2 * gu):
-            cum.extend(int(x) for x in area[8 * g:8 * g + 4])
-            tgt.extend(int(x) for x in area[8 * g + 4:8 * g + 8])
-        assert all(x == 0xFFFFFFFF for x in cum[m:]), ("cum padding", i)
-        assert all(x == 0 for x in tgt[m:]), ("target padding", i)
-        cum = np.array(cum[:m] if m else [], dtype=np.int64)
-        tg = tgt[:m]
-        if m:
-            last = [cum[min(4 * g + 3, m - 1)] for g in range(G)]
-            assert list(summ[:G]) == last, ("group summaries", i)
-            assert all(x == 0xFFFFFFFF for x in summ[G:]), ("summary padding", i)
+        assert rec[base + 6] == 0 and rec[base + 7] == 0, ("header padding", i)
+        ent = rec[base + 8:base + 8 + 4 * m].reshape(m, 4).astype(np.int64)
+        thr, tg, al, w = ent[:, 0], ent[:, 1], ent[:, 2], ent[:, 3]
+        cum = np.cumsum(w)
         col = np.array([inv[t & 0x7FFFFFFF] for t in tg], dtype=np.int64)
-        neg = np.array([(t >> 31) & 1 for t in tg], dtype=bool)
-        out.append((row, m, W, s32, s64, cum, col, neg))
+        neg = (tg >> 31) & 1 == 1
+        acol = np.array([inv[t & 0x7FFFFFFF] for t in al], dtype=np.int64)
+        aneg = (al >> 31) & 1 == 1
+        out.append((row, m, W, s32, s64, cum, col, neg, thr, acol, aneg))
     return out
 
 

@@ -58,13 +58,18 @@ def test_records_bit_identical(mc, name):
     rec, roff, diag = cdf.download()
     assert np.array_equal(diag, o.diag)
     recs = decode_records(rec, roff, B.n)
-    for i, (row, m, W, s32, s64, cum, col, neg) in enumerate(recs):
+    for i, (row, m, W, s32, s64, cum, col, neg, thr, acol, aneg) in enumerate(recs):
         b, e = o.cptr[i], o.cptr[i + 1]
         assert row == i and m == e - b and W == int(o.wsum[i])
         assert s64 == o.shat[i] and s32 == np.float32(o.shat[i])
         assert np.array_equal(cum, o.cum[b:e].astype(np.int64))
         assert np.array_equal(col, o.ccol[b:e])
         assert np.array_equal(neg, o.cval[b:e] < 0)
+        # alias tables: thresholds and aliases exactly the oracle's
+        assert np.array_equal(thr, o.athr[b:e].astype(np.int64))
+        ai = o.aidx[b:e]
+        assert np.array_equal(acol, o.ccol[b:e][ai])
+        assert np.array_equal(aneg, o.cval[b:e][ai] < 0)
 
 
 # ------------------------------------------------------------ cfg1 in full

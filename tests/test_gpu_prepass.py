@@ -48,13 +48,15 @@ def test_prepass_records_bit_identical(mc, name):
     assert cdf.nnz_c == o.nnz_c and cdf.norm_inf == o.norm_inf
     rec, roff, diag = cdf.download()
     assert np.array_equal(diag, o.diag)
-    for i, (row, m, W, s32, s64, cum, col, neg) in enumerate(decode_records(rec, roff, B.n)):
+    for i, (row, m, W, s32, s64, cum, col, neg, thr, acol, aneg) in enumerate(decode_records(rec, roff, B.n)):
         b, e = o.cptr[i], o.cptr[i + 1]
         assert row == i and m == e - b and W == int(o.wsum[i])
         assert s64 == o.shat[i]
         assert np.array_equal(cum, o.cum[b:e].astype(np.int64))
         assert np.array_equal(col, o.ccol[b:e])
         assert np.array_equal(neg, o.cval[b:e] < 0)
+        assert np.array_equal(thr, o.athr[b:e].astype(np.int64))
+        assert np.array_equal(acol, o.ccol[b:e][o.aidx[b:e]])
 
 
 @pytest.mark.parametrize("prec", [64, 32])

@@ -20,7 +20,10 @@ MUTATIONS = {
     "scale_by_row_diag": ("double m = nhat / A->diag[col];", "double m = nhat / A->diag[r];"),
     "cutoff_not_strict": ("if (fabs(wn) < p->delta)", "if (fabs(wn) <= p->delta)"),
     "quantize_ceil": ("double scaled = floor(ldexp(ratio, q));", "double scaled = ceil(ldexp(ratio, q));"),
-    "draw_off_by_one": ("if (t < (uint64_t)A->cum[k])", "if (t <= (uint64_t)A->cum[k])"),
+    "alias_threshold_inclusive": ("if (r < (uint64_t)A->athr[b + (int64_t)j])",
+                                  "if (r <= (uint64_t)A->athr[b + (int64_t)j])"),
+    "alias_gives_away_too_much": ("q[lg] -= W - q[sm];", "q[lg] -= W;"),
+    "alias_bucket_off_by_one": ("uint64_t j = um >> 32;", "uint64_t j = ((uint64_t)u * (m - 1)) >> 32;"),
     "shat_is_amax": ("shat[i] = ldexp(amax * (double)run, -q);", "shat[i] = amax;"),
     "philox_multiplier": ("0xD2511F53u", "0xD2511F55u"),
     "aug_ignores_sign": ("d = d + (d < 0.0 ? -aug : aug);", "d = d + aug;"),
@@ -50,7 +53,8 @@ DRIVER = textwrap.dedent('''
         ("quant", lambda: pins.test_cdf_quantization_bounds()),
         ("quant_exact", lambda: pins.test_integer_weights_are_exact_floors()),
         ("strict", lambda: pins.test_cutoff_is_strict_when_weight_equals_delta()),
-        ("draw", lambda: pins.test_draw_boundaries_match_closed_form()),
+        ("alias_mass", lambda: pins.test_alias_tables_conserve_every_entry_mass()),
+        ("alias_draw", lambda: pins.test_alias_draw_probabilities_and_boundaries()),
         ("aug", lambda: pins.test_augmented_splitting_equals_the_hand_built_matrix()),
         ("reduce", lambda: pins.test_reduction_drops_the_smallest_share_of_the_iteration_matrix()),
         ("compose", lambda: pins.test_augmentation_then_reduction_compose()),

@@ -410,21 +410,71 @@ def test_cutoff_is_strict_when_weight_equals_delta():
     assert np.allclose((M * d[None, :]).sum(axis=1), 1.875, rtol=1e-15)
 
 
-def test_draw_boundaries_match_closed_form():
-    """The draw picks the first k with t < cum_k, t = floor(u W / 2^32): the smallest
-    u reaching cum_k is u* = ceil(cum_k 2^32 / W) (integer arithmetic), so u* - 1
-    must give entry k and u* entry k + 1."""
-    B = I.random_nonsym(50, seed=17)
+def _alias_word_counts(m, W, T, A):
+    """Exact number of 32-bit words u that draw each entry under the alias rule,
+    by interval arithmetic on the integers: bucket j holds the u with
+    j 2^32 <= u m < (j + 1) 2^32; inside it, f = u m - j 2^32 runs over an
+    arithmetic progression with step m, and f < F_j = ceil(T_j 2^32 / W) (that is,
+    floor(f W / 2^32) < T_j) keeps entry j, the rest go to A_j."""
+    cnt = [0] * m
+    for j in range(m):
+        u0 = -(-(j << 32) // m)
+        u1 = -(-((j + 1) << 32) // m)
+        F = -(-(T[j] << 32) // W)
+        # u in [u0, u1) with u m - j 2^32 < F  <=>  u < (j 2^32 + F) / m
+        ucut = min(u1, max(u0, -(-((j << 32) + F) // m)))
+        cnt[j] += ucut - u0
+        cnt[A[j]] += u1 - ucut
+    return cnt
+
+
+def test_alias_tables_conserve_every_entry_mass():
+    """Vose's tables are exact: for each entry k, the units it keeps in its own
+    bucket plus the units every bucket aliasing to it gives away add up to m w_k;
+    every threshold lies in [1, W]."""
+    B = I.random_nonsym(400, seed=23)
     o = O.Oracle(B)
-    for row in range(0, 50, 7):
+    for row in range(B.n):
         b, e = o.cptr[row], o.cptr[row + 1]
-        W = int(o.wsum[row])
-        cum = [int(x) for x in o.cum[b:e]]
-        for k in range(len(cum) - 1):
-            ustar = -(-(cum[k] << 32) // W)
-            assert o.draw(row, ustar - 1) == k
-            assert o.draw(row, ustar) == k + 1
-        assert o.draw(row, 0) == 0 and o.draw(row, 0xFFFFFFFF) == len(cum) - 1
+        m, W = int(e - b), int(o.wsum[row])
+        T = [int(x) for x in o.athr[b:e]]
+        A = [int(x) for x in o.aidx[b:e]]
+        w = list(o.row_weights(row))
+        got = list(T)
+        for j in range(m):
+            got[A[j]] += W - T[j] if A[j] != j else 0
+        assert got == [m * x for x in w], row
+        assert all(1 <= t <= W for t in T) and all(0 <= x < m for x in A)
+
+
+def test_alias_draw_probabilities_and_boundaries():
+    """The draw of the oracle follows the alias rule exactly: (i) counted over all
+    2^32 words, entry k is drawn by 2^32 w_k / W words up to the grain of the
+    buckets; (ii) at every bucket's cut the word just below draws the bucket's own
+    entry and the word at the cut draws its alias; (iii) the first word of each
+    bucket draws its own entry."""
+    B = I.random_nonsym(60, seed=17)
+    o = O.Oracle(B)
+    for row in range(0, 60, 3):
+        b, e = o.cptr[row], o.cptr[row + 1]
+        m, W = int(e - b), int(o.wsum[row])
+        T = [int(x) for x in o.athr[b:e]]
+        A = [int(x) for x in o.aidx[b:e]]
+        w = [int(x) for x in o.row_weights(row)]
+        cnt = _alias_word_counts(m, W, T, A)
+        assert sum(cnt) == 1 << 32
+        for k in range(m):
+            assert abs(cnt[k] * W - (w[k] << 32)) <= 2 * (m + 1) * W, (row, k)
+        for j in range(m):
+            u0 = -(-(j << 32) // m)
+            assert o.draw(row, u0) == j
+            F = -(-(T[j] << 32) // W)
+            ucut = -(-((j << 32) + F) // m)
+            u1 = -(-((j + 1) << 32) // m)
+            if u0 < ucut < u1:
+                assert o.draw(row, ucut - 1) == j
+                assert o.draw(row, ucut) == A[j]
+        assert o.draw(row, 0xFFFFFFFF) in (m - 1, A[m - 1])
 
 
 def test_integer_weights_are_exact_floors():
