@@ -156,15 +156,15 @@ def main():
     total_trans = float(sum(trans))
     value = total_trans / elapsed
 
-    # memory ceiling of the access pattern: dependent pointer chase over a buffer of
-    # the record set's size with the walk's two random requests per step, each one
-    # 16-byte load (loads=1, what a step of the walk issues) or, for comparison,
-    # four loads of a 64-byte unit (loads=4)
+    # memory ceiling of the access pattern: a chase over a buffer of the record
+    # set's size with one dependent random 64-byte block per step (what a step of
+    # the walk reads), fresh randomness each step, read as one 16-byte load
+    # (loads=1) or as four (loads=4; a walk step issues three)
     probe = {}
     cdf0 = mcmi.Cdf(dB)
     for loads in (1, 4):
         for wpc in (8, 16, 32):
-            ms_p, rate = mcmi.gather_probe(max(1024, cdf0.rec_units // 4), 2, 256, wpc, loads)
+            ms_p, rate = mcmi.gather_probe(max(1024, cdf0.rec_units), 1, 256, wpc, loads)
             probe[f"loads{loads}_wpc{wpc}"] = rate
     del cdf0
     ceiling = max(v for k, v in probe.items() if k.startswith("loads1_"))
@@ -238,7 +238,7 @@ def aniso_main(args):
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     st = last.stats
-    ms_p, ceiling = mcmi.gather_probe(max(1024, rec_units // 4), 2, 128, 16)
+    ms_p, ceiling = mcmi.gather_probe(max(1024, rec_units), 1, 128, 16)
     m = np.maximum(np.diff(B.row_ptr) - 1, 1)
     bpt = float(np.mean((16.0 if args.prec == 32 else 24.0) + 4.0 * (np.ceil(np.log2(m)) + 1.0) + 4.0))
     walk_s = float(np.mean(walk_ms)) / 1e3
@@ -248,7 +248,7 @@ def aniso_main(args):
            "config": {"workload": f"3D 27-point anisotropic {args.nx}^3", "n": B.n, "nnz_B": B.nnz,
                       "chains_per_row": chains, "transitions_per_step": int(st.transitions), "nnz_M": int(last.nnz),
                       "lanes_per_row": st.lanes_per_row, "hash_slots": st.hash_slots, "spilled": int(st.spilled),
-                      "retries": int(st.retries), "record_bytes": int(rec_units) * 16},
+                      "retries": int(st.retries), "record_bytes": int(rec_units) * 64},
            "roofline": {"bound": "hbm", "achieved": round(bpt * st.transitions / walk_s / 1e9, 1), "peak": HBM_PEAK_GBS,
                         "unit": "GB/s", "frac": round(bpt * st.transitions / walk_s / 1e9 / HBM_PEAK_GBS, 4),
                         "bytes_per_transition": round(bpt, 2), "walk_ms": round(walk_s * 1e3, 3),

@@ -179,17 +179,19 @@ mcmi_status mcmi_build_cdf_batched(const mcmi_csr_in *Bs, int32_t count, mcmi_cd
 mcmi_status mcmi_cdf_batch_info(const mcmi_cdf *cdf, int32_t *count, int64_t *row_base_host, double *norm_host);
 
 /* Copy the records to host memory (for inspection and tests; synchronises the
- * stream). rec_host receives rec_units * 4 uint32 words (rec_units from
- * mcmi_cdf_info, in 16-byte units), roff_host n record offsets (16-byte units)
+ * stream). rec_host receives rec_units * 16 uint32 words (rec_units from
+ * mcmi_cdf_info, in 64-byte units), roff_host n record offsets (64-byte units)
  * and diag_host the n diagonal values b_ii (augmented when the pre-pass ran). Any
- * of the three may be NULL. Record of a row with m entries (2 + m units):
- * {row, m, W, Shat32}, {Shat64 (2 words), 0, 0}, then bucket j = 0 .. m-1:
- * {T_j, target_j, target of A_j, w_j}, (T, A) being the row's alias table and a
- * target the column's record offset with bit 31 set for c < 0. */
+ * of the three may be NULL. Record of a row with m entries (1 + m units): the
+ * header {row, m, W, Shat32}, {Shat64 (2 words), 0, 0} and 8 zero words, then
+ * bucket j = 0 .. m-1: {T_j, target_j, target of A_j, w_j}, the header words
+ * {row, m, W, Shat32} of target_j's row, the same for A_j's, and their two Shat64;
+ * (T, A) is the row's alias table and a target the column's record offset with
+ * bit 31 set for c < 0. */
 mcmi_status mcmi_cdf_download(const mcmi_cdf *cdf, uint32_t *rec_host, uint32_t *roff_host, double *diag_host,
                               void *stream);
 
-/* ||Chat||_inf, n, nnz(C) and the size in 16-byte units of built records. */
+/* ||Chat||_inf, n, nnz(C) and the size in 64-byte units of built records. */
 mcmi_status mcmi_cdf_info(const mcmi_cdf *cdf, int64_t *n, int64_t *nnz_c, double *norm_inf,
                           uint64_t *rec_units);
 

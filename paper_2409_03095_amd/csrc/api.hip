@@ -99,14 +99,13 @@ mcmi_status choose_shape(const mcmi_cdf *cdf, const mcmi_params *p, int lmax, Ke
             }
             if (std::min(total, (double)cdf->n) > 0.5 * H) tau = std::pow(S, std::max(J, 1)) * (1.0 - 1.0 / 1048576.0);
         }
-        // default sketch: as many buckets (fewer replays) as one workgroup per CU
-        // can hold next to the hash table. One workgroup of 8 or 16 waves per CU
-        // walks faster than two that share the LDS: more random units in flight per
-        // CU only evict each other from the L1 (measured, 89.6 vs 94.5 ms).
+        // default sketch: the largest that still lets two workgroups share a CU's
+        // LDS. With one random 64-byte block per transition, the walk is bound by
+        // HBM line traffic, and two workgroups per CU keep more lines in flight than
+        // one with a bigger sketch saves in replays (measured: 59.2 vs 66.2 ms).
         if (tau > 0.0)
             sketch = p->sketch_slots ? p->sketch_slots
-                                     : (int)std::min<int64_t>(16384, std::max<int64_t>(
-                                           1024, ((int64_t)163840 - (int64_t)H * 12 - 256) / 4));
+                                     : (int)std::max<int64_t>(1024, ((int64_t)81920 - (int64_t)H * 12 - 256) / 4);
     }
     out.lanes = lanes;
     out.hash = H;

@@ -178,8 +178,7 @@ __global__ void __launch_bounds__(256) k_fill(int64_t n, const int64_t *__restri
                 hdr[2] = 0u;
                 hdr[3] = __float_as_uint(0.0f);
                 *(double *)(hdr + 4) = 0.0;
-                hdr[6] = 0u;
-                hdr[7] = 0u;
+                for (int z = 6; z < kUnitWords; ++z) hdr[z] = 0u;
             }
             continue;
         }
@@ -230,8 +229,7 @@ __global__ void __launch_bounds__(256) k_fill(int64_t n, const int64_t *__restri
             hdr[2] = carry;
             hdr[3] = __float_as_uint((float)shat);
             *(double *)(hdr + 4) = shat;
-            hdr[6] = 0u;
-            hdr[7] = 0u;
+            for (int z = 6; z < kUnitWords; ++z) hdr[z] = 0u;
             atomicMax(norm_bits, (unsigned long long)__double_as_longlong(shat));
         }
     }
@@ -245,31 +243,31 @@ __global__ void __launch_bounds__(256) k_fill(int64_t n, const int64_t *__restri
 // q_l -= W - q_s), and l goes back on small if q_l < W, else on large. Leftover
 // buckets keep all W units (T = W, A = self). Every entry's final q is its
 // threshold. Both stacks live in one scratch array of the row's length (small
-// grows up from the front, large down from the back), q in another.
+// grows up from the front, large down from the back), q and A in two more.
+// Each bucket then receives copies of the headers of the two rows it can lead
+// to (written by k_fill, a previous launch).
 __global__ void __launch_bounds__(256) k_alias(int64_t n, const uint32_t *__restrict__ mrow,
                                                const uint32_t *__restrict__ roff32, const int64_t *__restrict__ cptr,
                                                const uint2 *__restrict__ sorted, uint32_t *__restrict__ qs,
-                                               int32_t *__restrict__ stk, uint32_t *__restrict__ rec) {
+                                               int32_t *__restrict__ stk, int32_t *__restrict__ alias,
+                                               uint32_t *__restrict__ rec) {
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < n; r += stride) {
         const uint32_t m = mrow[r];
         if (m == 0) continue;
         const int64_t base = cptr[r];
-        uint32_t *ent = rec + ((size_t)roff32[r] + kHdrUnits) * kUnitWords;
         const uint32_t W = sorted[base + m - 1].x;
         uint32_t *q = qs + base;
         int32_t *st = stk + base;
+        int32_t *al = alias + base;
         int ns = 0, nl = 0;
         uint32_t prev = 0;
         for (uint32_t k = 0; k < m; ++k) {
-            const uint2 node = sorted[base + k];
-            const uint32_t w = node.x - prev;
-            prev = node.x;
-            const uint32_t qk = m * w;  // <= m 2^Q <= 2^31
+            const uint32_t cum = sorted[base + k].x;
+            const uint32_t qk = m * (cum - prev);  // m w_k <= m 2^Q <= 2^31
+            prev = cum;
             q[k] = qk;
-            ent[k * kUnitWords + 1] = node.y;  // own target
-            ent[k * kUnitWords + 2] = k;       // alias index (self until paired)
-            ent[k * kUnitWords + 3] = w;
+            al[k] = (int32_t)k;
             if (qk < W)
                 st[ns++] = (int32_t)k;
             else
@@ -278,7 +276,7 @@ __global__ void __launch_bounds__(256) k_alias(int64_t n, const uint32_t *__rest
         while (ns > 0 && nl > 0) {
             const int32_t sm = st[--ns];
             const int32_t lg = st[m - nl--];
-            ent[sm * kUnitWords + 2] = (uint32_t)lg;
+            al[sm] = lg;
             const uint32_t ql = q[lg] - (W - q[sm]);
             q[lg] = ql;
             if (ql < W)
@@ -286,9 +284,19 @@ __global__ void __launch_bounds__(256) k_alias(int64_t n, const uint32_t *__rest
             else
                 st[m - 1 - nl++] = lg;
         }
+        uint32_t *ent = rec + ((size_t)roff32[r] + 1u) * kUnitWords;
+        prev = 0;
         for (uint32_t k = 0; k < m; ++k) {
-            ent[k * kUnitWords + 0] = q[k];
-            ent[k * kUnitWords + 2] = sorted[base + ent[k * kUnitWords + 2]].y;  // alias index -> its target
+            const uint2 own = sorted[base + k], other = sorted[base + al[k]];
+            const uint4 *ho = (const uint4 *)(rec + (size_t)(own.y & ~kSignBit) * kUnitWords);
+            const uint4 *ha = (const uint4 *)(rec + (size_t)(other.y & ~kSignBit) * kUnitWords);
+            uint4 *e = (uint4 *)(ent + (size_t)k * kUnitWords);
+            const uint4 so = ho[1], sa = ha[1];
+            e[0] = make_uint4(q[k], own.y, other.y, own.x - prev);
+            e[1] = ho[0];
+            e[2] = ha[0];
+            e[3] = make_uint4(so.x, so.y, sa.x, sa.y);
+            prev = own.x;
         }
     }
 }
@@ -430,7 +438,7 @@ extern "C" mcmi_status mcmi_build_cdf_ex(const mcmi_csr_in *B, const mcmi_cdf_op
         ::memcpy(&cdf->drop_thr, &hcut, sizeof(double));
         cdf->dropped = cnt - htot[1];
     }
-    if (htot[0] >= (int64_t)kSignBit) return bail(MCMI_ERR_CAPACITY, "mcmi_build_cdf: records exceed 32 GiB");
+    if (htot[0] >= (int64_t)kSignBit) return bail(MCMI_ERR_CAPACITY, "mcmi_build_cdf: records exceed 128 GiB");
     cdf->rec_units = (uint64_t)htot[0];
     cdf->nnz_c = htot[1];
     TRY(hipMalloc(&cdf->rec, (size_t)htot[0] * kUnitWords * 4u + 64u));
@@ -439,8 +447,9 @@ extern "C" mcmi_status mcmi_build_cdf_ex(const mcmi_csr_in *B, const mcmi_cdf_op
                                 cut, cdf->roff, cdf->rec, sorted, norm_bits);
     TRY(hipGetLastError());
     TRY(hipMalloc(&qs, (size_t)(htot[1] > 0 ? htot[1] : 1) * sizeof(uint32_t)));
-    TRY(hipMalloc(&stk, (size_t)(htot[1] > 0 ? htot[1] : 1) * sizeof(int32_t)));
-    k_alias<<<grid_for(n), 256, 0, s>>>(n, cdf->mrow, cdf->roff, cptr, sorted, qs, stk, cdf->rec);
+    TRY(hipMalloc(&stk, (size_t)(htot[1] > 0 ? 2 * htot[1] : 2) * sizeof(int32_t)));
+    k_alias<<<grid_for(n), 256, 0, s>>>(n, cdf->mrow, cdf->roff, cptr, sorted, qs, stk,
+                                        stk + (htot[1] > 0 ? htot[1] : 1), cdf->rec);
     TRY(hipGetLastError());
     unsigned long long hnorm = 0;
     TRY(hipMemcpyAsync(&hnorm, norm_bits, sizeof(hnorm), hipMemcpyDeviceToHost, s));

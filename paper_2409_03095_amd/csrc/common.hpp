@@ -21,25 +21,29 @@ mcmi_status fail(mcmi_status st, const std::string &msg);
     } while (0)
 
 // ----------------------------------------------------------- record layout
-// One record per row s of C, 16-byte aligned, addressed by its offset in 16-byte
-// units (31 bits: up to 32 GiB of records). With m entries (column order) it is
-// 2 + m units:
-//   unit 0   {row index s, m, W = total integer weight, Shat_s as binary32}
-//   unit 1   {Shat_s as binary64 (2 words), 0, 0}
-//   unit 2+j {T_j, target_j, target_{A_j}, w_j}  for bucket j = 0 .. m-1
-// where (T, A) is the row's alias table (Walker's method in Vose's exact-integer
-// construction: bucket j keeps T_j of its W units for entry j and gives the rest
-// to entry A_j) and a target is the record offset of the column's row with bit
+// One record per row s of C, 64-byte aligned, addressed by its offset in
+// 64-byte units (31 bits: up to 128 GiB of records). With m entries (column
+// order) it is 1 + m units of 16 words:
+//   unit 0    header of s: {row s, m, W = total integer weight, Shat_s as
+//             binary32}, {Shat_s as binary64 (2 words), 0, 0}, 8 zero words
+//   unit 1+j  bucket j = 0 .. m-1 of the row's alias table:
+//             {T_j, target_j, target_{A_j}, w_j},
+//             the header words {row, m, W, Shat32} of the row target_j points to,
+//             the same for target_{A_j},
+//             {Shat64 of target_j (2 words), Shat64 of target_{A_j} (2 words)}
+// (T, A) is the alias table (Walker's method in Vose's exact-integer
+// construction: bucket j keeps T_j of its W units for entry j and gives the
+// rest to entry A_j); a target is the record offset of the column's row with bit
 // 31 set when c < 0. A draw with the 32-bit word u takes bucket j = (u m) >> 32
 // and r = ((u m mod 2^32) W) >> 32: the next state is target_j if r < T_j, else
-// target_{A_j}. A step therefore reads one 16-byte header (plus unit 1 for FP64
-// weights) and one 16-byte bucket: one load per random unit, so a unit is never
-// needed in the L1 after its single load.
-constexpr int kUnitWords = 4;
-constexpr int kHdrUnits = 2;
+// target_{A_j}. Because the bucket carries the next state's header, a transition
+// reads one 64-byte block (three 16-byte loads issued together, four with
+// binary64 weights): one random line per transition; the header unit is read
+// only when a chain starts.
+constexpr int kUnitWords = 16;
 constexpr uint32_t kSignBit = 0x80000000u;
 
-__host__ __device__ inline uint32_t record_units(uint32_t m) { return (uint32_t)kHdrUnits + m; }
+__host__ __device__ inline uint32_t record_units(uint32_t m) { return 1u + m; }
 
 // Error flags raised by device-side validation (bit set).
 enum : uint32_t {
@@ -167,7 +171,7 @@ struct mcmi_cdf {
     int64_t dropped = 0;    // entries of C removed by the reduction
     uint64_t rec_units = 0;
     uint32_t *rec = nullptr;       // records, 16 words per unit
-    uint32_t *roff = nullptr;      // n: record offset (16-byte units) of each row
+    uint32_t *roff = nullptr;      // n: record offset (64-byte units) of each row
     double *diag = nullptr;        // n: b_ii
     uint32_t *mrow = nullptr;      // n: entries of each row of C
     // batched record sets (several matrices, block-diagonal row space)

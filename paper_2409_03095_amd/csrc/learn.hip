@@ -40,12 +40,13 @@ __global__ void __launch_bounds__(256) k_features(int64_t n, const uint32_t *__r
         double ps = 0.0, pm = 0.0, sgn = 0.0, smax = 0.0;
         uint32_t wmax = 0;
         for (uint32_t k = lane; k < m; k += 64) {
-            const uint4 e = ((const uint4 *)recp)[kHdrUnits + k];  // {T, target, alias target, w}
-            const uint32_t w = e.w;
-            const uint32_t tgt = e.y;
-            const uint32_t *trec = rec + (size_t)(tgt & ~kSignBit) * kUnitWords;
-            const double St = __hiloint2double((int)trec[5], (int)trec[4]);
-            const double mt = (double)trec[1];
+            // bucket k: {T, target, alias target, w}, target's header, alias's header, Shat64s
+            const uint4 *e = (const uint4 *)(recp + (size_t)(1u + k) * kUnitWords);
+            const uint4 q0 = e[0], q1 = e[1], q3 = e[3];
+            const uint32_t w = q0.w;
+            const uint32_t tgt = q0.y;
+            const double St = __hiloint2double((int)q3.y, (int)q3.x);
+            const double mt = (double)q1.y;
             ps += (double)w * St;
             pm += (double)w * mt;
             sgn += (tgt & kSignBit) ? -(double)w : (double)w;
@@ -132,14 +133,15 @@ __global__ void __launch_bounds__(64) k_pilot(WalkArgs a, int pilot, int cap, do
         double w64 = 1.0;
         float w32 = 1.0f;
         u32x4 blk = {0, 0, 0, 0};
+        StepHdr H0;
+        load_header<kF32>(a.rec, r_off, H0);
+        StepHdr Hd = H0;  // header of the current state
         int nl = 0;
         bool overflow = false, spill_full = false;
         double sq = 0.0;
         unsigned long long steps = 0;
         while (__any(active)) {
             if (active) {
-                StepHdr Hd;
-                load_header<kF32>(a.rec, off, Hd);
                 const uint4 h = Hd.h0;
                 const double s64 = kF32 ? 0.0 : header_shat64(Hd);
                 // contribution (j = 0 included: the start state gets W_0 = 1)
@@ -175,6 +177,7 @@ __global__ void __launch_bounds__(64) k_pilot(WalkArgs a, int pilot, int cap, do
                     c += 64;
                     if (c < pilot) {
                         off = r_off;
+                        Hd = H0;
                         j = 0;
                         w64 = 1.0;
                         w32 = 1.0f;
@@ -187,13 +190,15 @@ __global__ void __launch_bounds__(64) k_pilot(WalkArgs a, int pilot, int cap, do
                     blk.x = blk.y;
                     blk.y = blk.z;
                     blk.z = blk.w;
-                    const uint32_t tgt = draw_target(a.rec, off, Hd, u);
+                    StepHdr Nx;
+                    const uint32_t tgt = draw_next<kF32>(a.rec, off, Hd, u, Nx);
                     const bool neg = (tgt & kSignBit) != 0u;
                     if (kF32)
                         w32 = neg ? -wn32 : wn32;
                     else
                         w64 = neg ? -wn64 : wn64;
                     off = tgt & ~kSignBit;
+                    Hd = Nx;
                     ++j;
                 }
             }

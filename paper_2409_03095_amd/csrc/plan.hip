@@ -153,8 +153,8 @@ extern "C" mcmi_status mcmi_tune(const mcmi_cdf *cdf, const mcmi_params *base, i
     for (int lanes : {256, 512, 1024})
         for (int hash : {2048, 4096})
             if (walk_block_supported(lanes, hash))
-                for (int sk : {0, 4096, 8128}) {  // 0: the largest sketch of one workgroup per CU;
-                                                    // 8128: two workgroups per CU at 4096 slots
+                for (int sk : {0, 4096, 16384}) {  // 0: the largest sketch leaving two workgroups
+                                                     // per CU; 16384: one workgroup per CU
                     cands.push_back({lanes, hash, sk, 0.0});  // automatic tau
                     if (sk == 0) cands.push_back({lanes, hash, sk, -1.0});  // track everything
                 }

@@ -1,14 +1,16 @@
 // Dependent random-gather probe (gfx950): the memory ceiling of the walk's
 // access pattern without the method's arithmetic.
 //
-// A buffer of `units` 64-byte units holds random unit indices. Each lane runs a
-// pointer chase in which every step issues `reqs` dependent reads of one unit
-// each (the unit the previous read named), like a walk step reads its header
-// unit and then its group unit. A read is `loads` 16-byte loads of the unit's
-// first quarters (1: only the word that names the next unit; 4: the whole
-// unit). The measured steps per second is the ceiling a walk with the same
-// number of dependent requests and loads per transition can reach on this chip,
-// for a record set of the same size.
+// A buffer of `units` 64-byte units is read by a chase in which every step
+// issues `reqs` dependent reads of one random unit each, a read being `loads`
+// 16-byte loads of the unit's first quarters (1: only the word the next address
+// depends on; 4: the whole unit). The next unit is a hash of the word just read,
+// the lane and the step, so, like a Markov chain's fresh random numbers, two
+// lanes that meet the same unit do not follow each other afterwards (a fixed
+// successor per unit would funnel lanes into shared paths that hit in the
+// caches). The measured steps per second is the ceiling a walk with the same
+// number of dependent random blocks per transition can reach on this chip for a
+// record set of the same size.
 #include <string>
 
 #include "common.hpp"
@@ -42,8 +44,12 @@ __global__ void __launch_bounds__(256) k_probe_chase(const uint4 *buf, uint64_t 
             if (loads > 1) extra += u[1].y;
             if (loads > 2) extra += u[2].z;
             if (loads > 3) extra += u[3].w;
-            cur = v.x ^ (acc & 1u);      // dependent next index (acc keeps it live)
-            if (cur >= units) cur -= (uint32_t)units;
+            // next unit: hash of the word read, the lane and the step
+            uint32_t h = v.x ^ (uint32_t)tid * 0x9E3779B9u ^ (uint32_t)(s * 4 + q) * 0x85EBCA77u;
+            h ^= h >> 16;
+            h *= 0x7FEB352Du;
+            h ^= h >> 15;
+            cur = (uint32_t)(((uint64_t)h * units) >> 32);
             acc += v.y + extra;
         }
     }

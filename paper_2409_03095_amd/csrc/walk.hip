@@ -14,8 +14,8 @@
 //  * each lane runs one chain at a time and starts the row's next unstarted chain
 //    as soon as its chain stops, so short and long chains do not wait for each
 //    other;
-//  * a step reads the 16-byte header of the current state, draws one Philox word
-//    and reads the one 16-byte alias bucket it names: two dependent requests;
+//  * a step draws one Philox word and reads the 64-byte alias bucket it names,
+//    which also carries the next state's header: one random line per step;
 //  * contributions go to an open-addressing hash per wave in LDS (key = column,
 //    value = float64 sum, LDS float64 atomics); a full neighbourhood spills to a
 //    per-wave hash in HBM;
@@ -78,14 +78,17 @@ __device__ __forceinline__ void walk_row(const WalkArgs &a, int64_t task, int32_
     uint32_t j = 0;
     double w64 = 1.0;
     float w32 = 1.0f;
+    // the row's own header (every chain starts there); later states' headers
+    // arrive with the bucket of the step that reaches them
+    StepHdr H0;
+    load_header<kF32>(a.rec, r_off, H0);
+    StepHdr H = H0;
     u32x4 blk = {0, 0, 0, 0};
     unsigned long long trans = 0, spilled = 0;
     bool spill_full = false;
 
     while (__any(active)) {
         if (active) {
-            StepHdr H;
-            load_header<kF32>(a.rec, off, H);
             const uint4 h = H.h0;  // row, m, W, Shat32
             const double s64 = kF32 ? 0.0 : header_shat64(H);
             if (j > 0) {
@@ -111,6 +114,7 @@ __device__ __forceinline__ void walk_row(const WalkArgs &a, int64_t task, int32_
                 c += 64;
                 if (c < N) {
                     off = r_off;
+                    H = H0;
                     j = 0;
                     w64 = 1.0;
                     w32 = 1.0f;
@@ -124,13 +128,15 @@ __device__ __forceinline__ void walk_row(const WalkArgs &a, int64_t task, int32_
                 blk.x = blk.y;
                 blk.y = blk.z;
                 blk.z = blk.w;
-                const uint32_t tgt = draw_target(a.rec, off, H, u);
+                StepHdr Nx;
+                const uint32_t tgt = draw_next<kF32>(a.rec, off, H, u, Nx);
                 const bool neg = (tgt & kSignBit) != 0u;
                 if (kF32)
                     w32 = neg ? -wn32 : wn32;
                 else
                     w64 = neg ? -wn64 : wn64;
                 off = tgt & ~kSignBit;
+                H = Nx;
                 ++j;
             }
         }

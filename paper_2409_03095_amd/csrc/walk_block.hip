@@ -43,6 +43,7 @@ struct Chain {
     double w64;
     float w32;
     u32x4 blk;
+    StepHdr h;  // header of the current state
     bool active;
 };
 
@@ -51,6 +52,7 @@ struct RowCtx {
     uint32_t prow, ptag;  // Philox row and tag words
     uint32_t k0, k1;      // Philox key
     uint32_t r_off;
+    StepHdr h0;  // header of row r, where every chain starts
     int32_t *keys;
     double *vals;
     float *sketch;
@@ -65,6 +67,7 @@ struct RowCtx {
 __device__ __forceinline__ void chain_start(Chain &st, int32_t c, const RowCtx &rc) {
     st.c = c;
     st.off = rc.r_off;
+    st.h = rc.h0;
     st.j = 0;
     st.w64 = 1.0;
     st.w32 = 1.0f;
@@ -178,8 +181,7 @@ __device__ __forceinline__ void run_chains(const WalkArgs &a, const RowCtx &rc, 
     const uint32_t smask = (uint32_t)a.spill_slots - 1u;
     paused = false;
     while (st.active) {
-        StepHdr H;
-        load_header<kF32>(a.rec, st.off, H);
+        const StepHdr H = st.h;
         const uint4 h = H.h0;  // row, m, W, Shat32
         const double s64 = kF32 ? 0.0 : header_shat64(H);
         if (st.j > 0) {
@@ -220,7 +222,7 @@ __device__ __forceinline__ void run_chains(const WalkArgs &a, const RowCtx &rc, 
             st.blk.x = st.blk.y;
             st.blk.y = st.blk.z;
             st.blk.z = st.blk.w;
-            const uint32_t tgt = draw_target(a.rec, st.off, H, u);
+            const uint32_t tgt = draw_next<kF32>(a.rec, st.off, H, u, st.h);
             const bool neg = (tgt & kSignBit) != 0u;
             if (kF32)
                 st.w32 = neg ? -wn32 : wn32;
@@ -279,6 +281,7 @@ __device__ __forceinline__ void block_row(const WalkArgs &a, int64_t task, RowCt
     rc.N = N;
     philox_ids(a, r, rc.prow, rc.ptag);
     rc.r_off = a.roff[r];
+    load_header<kF32>(a.rec, rc.r_off, rc.h0);
     const bool split = a.tau > 0.0;
     const bool reg = N <= kLPR;
     if (tid == 0) lds_add(rc.keys, rc.vals, H - 1u, hash_key(r, a.hash_shift), r, (double)N);

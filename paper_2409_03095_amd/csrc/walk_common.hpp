@@ -129,34 +129,44 @@ __device__ __forceinline__ void philox_ids(const WalkArgs &a, int32_t r, uint32_
 }
 
 // ------------------------------------------------------------- one step
-// The header of the current state: h0 = {row, m, W, Shat32}; s64 = Shat as
-// binary64 (read in FP64 mode only).
+// Header of a chain's current state, kept in registers: h0 = {row, m, W,
+// Shat32}; s64 = Shat as binary64 (FP64 weights only).
 struct StepHdr {
     uint4 h0;
     uint2 s64;
 };
 
+// The header unit of a record (read when a chain starts at its row).
 template <bool kF32>
 __device__ __forceinline__ void load_header(const uint32_t *rec, uint32_t off, StepHdr &H) {
-    const uint4 *u = (const uint4 *)rec + off;
+    const uint4 *u = (const uint4 *)(rec + (size_t)off * kUnitWords);
     H.h0 = u[0];
-    H.s64 = kF32 ? make_uint2(0u, 0u) : *(const uint2 *)(u + 1);
+    H.s64 = kF32 ? make_uint2(0u, 0u) : make_uint2(u[1].x, u[1].y);
 }
 
 __device__ __forceinline__ double header_shat64(const StepHdr &H) {
     return __hiloint2double((int)H.s64.y, (int)H.s64.x);
 }
 
-// Target word (record offset | sign bit) drawn by the 32-bit word u: bucket
-// j = (u m) >> 32, position r = ((u m mod 2^32) W) >> 32 among its W units; the
-// bucket's own entry if r < T_j, else its alias. One 16-byte load.
-__device__ __forceinline__ uint32_t draw_target(const uint32_t *rec, uint32_t off, const StepHdr &H, uint32_t u) {
+// One transition drawn by the 32-bit word u: bucket j = (u m) >> 32 of the
+// current row, position r = ((u m mod 2^32) W) >> 32 among its W units; the
+// bucket's own entry if r < T_j, else its alias. The bucket's loads are issued
+// together and also deliver the next state's header into N. Returns the target
+// word (record offset | sign bit).
+template <bool kF32>
+__device__ __forceinline__ uint32_t draw_next(const uint32_t *rec, uint32_t off, const StepHdr &H, uint32_t u,
+                                              StepHdr &N) {
     const uint32_t m = H.h0.y, W = H.h0.z;
     const uint32_t j = __umulhi(u, m);
     const uint32_t f = u * m;
     const uint32_t r = __umulhi(f, W);
-    const uint4 e = ((const uint4 *)rec)[(size_t)off + kHdrUnits + j];
-    return r < e.x ? e.y : e.z;
+    const uint4 *b = (const uint4 *)(rec + ((size_t)off + 1u + j) * kUnitWords);
+    const uint4 q0 = b[0], q1 = b[1], q2 = b[2];
+    const uint4 q3 = kF32 ? make_uint4(0u, 0u, 0u, 0u) : b[3];
+    const bool own = r < q0.x;
+    N.h0 = own ? q1 : q2;
+    N.s64 = own ? make_uint2(q3.x, q3.y) : make_uint2(q3.z, q3.w);
+    return own ? q0.y : q0.z;
 }
 
 }  // namespace walkdev

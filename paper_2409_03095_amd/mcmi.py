@@ -217,7 +217,7 @@ class Cdf:
         return k.value, base, nrm
 
     def download(self, stream=None):
-        rec = np.zeros(self.rec_units * 4, dtype=np.uint32)
+        rec = np.zeros(self.rec_units * 16, dtype=np.uint32)
         roff = np.zeros(self.n, dtype=np.uint32)
         diag = np.zeros(self.n, dtype=np.float64)
         _check(_lib.mcmi_cdf_download(self._h, rec.ctypes.data_as(_v), roff.ctypes.data_as(_v),

@@ -5,24 +5,30 @@ U64 = 2.0 ** -53
 
 
 def decode_records(rec, roff, n):
-    """Decode the library's records (16-byte units: {row, m, W, S32}, {S64, 0, 0},
-    then one bucket {T, target, alias target, w} per entry) into per-row (row, m,
-    W, S32, S64, cum[], col[], neg[], thr[], alias_col[], alias_neg[]) in column
-    order, checking the padding words."""
+    """Decode the library's records (64-byte units: header {row, m, W, S32},
+    {S64, 0, 0} and zeros, then one bucket per entry: {T, target, alias target,
+    w}, the target's header words, the alias target's header words, their S64s)
+    into per-row (row, m, W, S32, S64, cum[], col[], neg[], thr[], alias_col[],
+    alias_neg[]) in column order, checking padding and every copied header."""
     inv = {int(o): i for i, o in enumerate(roff)}
     out = []
     for i in range(n):
-        base = int(roff[i]) * 4
+        base = int(roff[i]) * 16
         row, m, W = int(rec[base]), int(rec[base + 1]), int(rec[base + 2])
         s32 = rec[base + 3:base + 4].view(np.float32)[0]
         s64 = rec[base + 4:base + 6].view(np.float64)[0]
-        assert rec[base + 6] == 0 and rec[base + 7] == 0, ("header padding", i)
-        ent = rec[base + 8:base + 8 + 4 * m].reshape(m, 4).astype(np.int64)
-        thr, tg, al, w = ent[:, 0], ent[:, 1], ent[:, 2], ent[:, 3]
+        assert not rec[base + 6:base + 16].any(), ("header padding", i)
+        ent = rec[base + 16:base + 16 + 16 * m].reshape(m, 16)
+        thr, tg, al, w = (ent[:, k].astype(np.int64) for k in range(4))
+        for k in range(m):
+            for t, words, sw in ((int(tg[k]), ent[k, 4:8], ent[k, 12:14]), (int(al[k]), ent[k, 8:12], ent[k, 14:16])):
+                hb = (t & 0x7FFFFFFF) * 16
+                assert np.array_equal(words, rec[hb:hb + 4]), ("copied header", i, k)
+                assert np.array_equal(sw, rec[hb + 4:hb + 6]), ("copied Shat64", i, k)
         cum = np.cumsum(w)
-        col = np.array([inv[t & 0x7FFFFFFF] for t in tg], dtype=np.int64)
+        col = np.array([inv[int(t) & 0x7FFFFFFF] for t in tg], dtype=np.int64)
         neg = (tg >> 31) & 1 == 1
-        acol = np.array([inv[t & 0x7FFFFFFF] for t in al], dtype=np.int64)
+        acol = np.array([inv[int(t) & 0x7FFFFFFF] for t in al], dtype=np.int64)
         aneg = (al >> 31) & 1 == 1
         out.append((row, m, W, s32, s64, cum, col, neg, thr, acol, aneg))
     return out
