@@ -209,11 +209,18 @@ extern "C" mcmi_status mcmi_spai(const mcmi_cdf *cdf, const mcmi_params *p, cons
     int waves = 4;
     int spill_slots = p->spill_slots ? p->spill_slots : (block_kernel ? 16384 : 4096);
     // first guess of the output size; rows that do not fit are rerun into a new pool
-    int64_t per_row = p->pool_per_row ? p->pool_per_row : (block_kernel ? std::min(H, 256) : std::min(H / 2, 128));
+    // a quarter of the row table per row: rows that overflow the first pool are
+    // walked again, so a generous first guess (HBM is large) is the cheap side
+    int64_t per_row = p->pool_per_row ? p->pool_per_row : std::max(H / 4, 64);
     if (!p->pool_per_row && p->topk > 0) per_row = std::min<int64_t>(per_row, p->topk);  // exact bound
     int64_t pool_cap = n_tasks * per_row;
-    pool_cap = std::min<int64_t>(pool_cap, (int64_t)1 << 30);
-    if (!p->pool_per_row) pool_cap = std::max<int64_t>(pool_cap, 1 << 16);
+    pool_cap = std::min<int64_t>(pool_cap, (int64_t)1 << 31);
+    if (!p->pool_per_row) {
+        size_t free_b = 0, total_b = 0;
+        if (hipMemGetInfo(&free_b, &total_b) == hipSuccess && free_b > 0)
+            pool_cap = std::min<int64_t>(pool_cap, (int64_t)(free_b / 4 / 12));  // at most a quarter of free HBM
+        pool_cap = std::max<int64_t>(pool_cap, 1 << 16);
+    }
     pool_cap = std::max<int64_t>(pool_cap, 1);
     uint64_t retries = 0;
 
@@ -347,6 +354,7 @@ extern "C" mcmi_status mcmi_spai(const mcmi_cdf *cdf, const mcmi_params *p, cons
         a.pool_val = pool_val[pass].as<double>();
         a.pool_cap = pool_cap;
         a.pool_used = pool_used;
+        a.pool_chunk = (pass == 0 && !block_kernel) ? 2048 : 0;  // reruns size their pool exactly
         a.spill_keys = sk.as<int32_t>();
         a.spill_vals = sv.as<double>();
         a.spill_used = su.as<int32_t>();

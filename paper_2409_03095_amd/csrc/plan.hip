@@ -319,6 +319,7 @@ extern "C" mcmi_status mcmi_plan_create(const mcmi_cdf *cdf, const mcmi_params *
     a.pool_col = pl->pool_col;
     a.pool_val = pl->pool_val;
     a.pool_cap = pl->pool_cap;
+    a.pool_chunk = 0;
     a.pool_used = (unsigned long long *)(ctrl + 32);
     a.spill_keys = pl->sk;
     a.spill_vals = pl->sv;

@@ -57,7 +57,8 @@ __device__ __forceinline__ int64_t next_task(const WalkArgs &a, int &queue) {
 
 template <bool kF32>
 __device__ __forceinline__ void walk_row(const WalkArgs &a, int64_t task, int32_t *keys, double *vals, int *spill_cnt,
-                         int32_t *skeys, double *svals, int32_t *sused, uint32_t k0, uint32_t k1) {
+                         int32_t *skeys, double *svals, int32_t *sused, uint32_t k0, uint32_t k1,
+                         unsigned long long &pcur, unsigned long long &pend, unsigned long long *wstats) {
     const int lane = lane_id();
     const uint32_t hmask = (uint32_t)a.hash_slots - 1u;
     const uint32_t smask = (uint32_t)a.spill_slots - 1u;
@@ -151,11 +152,10 @@ __device__ __forceinline__ void walk_row(const WalkArgs &a, int64_t task, int32_
         const int32_t key = keys[s];
         const double acc = vals[s];
         bool keep = false;
-        double mval = 0.0;
+        double nhat = 0.0;
         if (key != kEmpty) {
-            const double nhat = acc / nd;
-            mval = nhat / a.diag[key];
-            const double test = a.filter_m ? fabs(mval) : fabs(nhat);
+            nhat = acc / nd;  // N_rc; scaled by 1 / d_c once the kept set is final
+            const double test = a.filter_m ? fabs(nhat / a.diag[key]) : fabs(nhat);
             keep = key == r || (nhat != 0.0 && test >= a.eps);
         }
         const uint64_t km = ballot(keep);
@@ -163,7 +163,7 @@ __device__ __forceinline__ void walk_row(const WalkArgs &a, int64_t task, int32_
         if (keep) {
             const int pos = K + mask_rank(km);
             keys[pos] = key;
-            vals[pos] = a.topk > 0 ? acc / nd : mval;  // top-k ranks by N_rc first
+            vals[pos] = nhat;
         }
         K += __popcll(km);
     }
@@ -174,13 +174,12 @@ __device__ __forceinline__ void walk_row(const WalkArgs &a, int64_t task, int32_
         const int u = base + lane;
         bool keep = false;
         int32_t key = kEmpty;
-        double mval = 0.0, nhat = 0.0;
+        double nhat = 0.0;
         if (u < nsp) {
             const int32_t slot = sused[u];
             key = skeys[slot];
             nhat = svals[slot] / nd;
-            mval = nhat / a.diag[key];
-            const double test = a.filter_m ? fabs(mval) : fabs(nhat);
+            const double test = a.filter_m ? fabs(nhat / a.diag[key]) : fabs(nhat);
             keep = key == r || (nhat != 0.0 && test >= a.eps);
             skeys[slot] = kEmpty;
             svals[slot] = 0.0;
@@ -190,7 +189,7 @@ __device__ __forceinline__ void walk_row(const WalkArgs &a, int64_t task, int32_
             const int pos = K + mask_rank(km);
             if (pos < a.hash_slots) {
                 keys[pos] = key;
-                vals[pos] = a.topk > 0 ? nhat : mval;
+                vals[pos] = nhat;
             } else {
                 stage_full = true;
             }
@@ -228,9 +227,18 @@ __device__ __forceinline__ void walk_row(const WalkArgs &a, int64_t task, int32_
             }
             K = a.topk;
         }
-        for (int i = lane; i < K; i += 64) vals[i] = vals[i] / a.diag[keys[i]];
-        wave_sync();
     }
+    // M_rc = N_rc / d_c for the kept entries only, four independent loads per lane
+    // in flight (the eps test on N_rc needs no diagonal)
+    for (int i0 = lane; i0 < K; i0 += 256) {
+        double d[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) d[q] = i0 + 64 * q < K ? a.diag[keys[i0 + 64 * q]] : 1.0;
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+            if (i0 + 64 * q < K) vals[i0 + 64 * q] = vals[i0 + 64 * q] / d[q];
+    }
+    wave_sync();
 
     // bitonic sort of keys[0..P) by column, padding with INT32_MAX
     int P = 1;
@@ -261,7 +269,20 @@ __device__ __forceinline__ void walk_row(const WalkArgs &a, int64_t task, int32_
     const bool row_spill_full = __any(spill_full);
     const bool row_stage_full = __any(stage_full);
     unsigned long long pos0 = 0;
-    if (lane == 0 && !row_spill_full && !row_stage_full) pos0 = atomicAdd(a.pool_used, (unsigned long long)K);
+    if (lane == 0 && !row_spill_full && !row_stage_full) {
+        if (a.pool_chunk > 0) {
+            // the wave's reservation: one global atomic per pool_chunk entries
+            if (pcur + (unsigned long long)K > pend) {
+                const unsigned long long grab = (unsigned long long)(K > a.pool_chunk ? K : a.pool_chunk);
+                pcur = atomicAdd(a.pool_used, grab);
+                pend = pcur + grab;
+            }
+            pos0 = pcur;
+            pcur += (unsigned long long)K;
+        } else {
+            pos0 = atomicAdd(a.pool_used, (unsigned long long)K);
+        }
+    }
     pos0 = __shfl(pos0, 0, 64);
     const bool fits = (int64_t)(pos0 + (unsigned long long)K) <= a.pool_cap;
     const bool ok = fits && !row_spill_full && !row_stage_full;
@@ -282,10 +303,10 @@ __device__ __forceinline__ void walk_row(const WalkArgs &a, int64_t task, int32_
         if (row_stage_full) f |= kFlagStage;
         if (f) atomicOr(a.flags, f);
         if (ok) {
-            atomicAdd(&a.stats[0], trans);
-            atomicAdd(&a.stats[2], (unsigned long long)N);
+            wstats[0] += trans;
+            wstats[2] += (unsigned long long)N;
         }
-        if (spilled) atomicAdd(&a.stats[1], spilled);
+        wstats[1] += spilled;
     }
     // clear for the next row
     wave_sync();
@@ -323,10 +344,17 @@ __global__ void __launch_bounds__(256) k_walk(WalkArgs a) {
     int queue = (int)(blockIdx.x & 7u);
     const uint32_t k0 = a.keys_dev ? a.keys_dev[0] : a.key0;
     const uint32_t k1 = a.keys_dev ? a.keys_dev[1] : a.key1;
+    unsigned long long pcur = 0, pend = 0, wstats[3] = {0, 0, 0};
     for (;;) {
         const int64_t task = next_task(a, queue);
         if (task < 0) break;
-        walk_row<kF32>(a, task, keys, vals, spill_cnt, skeys, svals, sused, k0, k1);
+        walk_row<kF32>(a, task, keys, vals, spill_cnt, skeys, svals, sused, k0, k1, pcur, pend, wstats);
+    }
+    // statistics: one set of atomics per wave
+    if (lane == 0) {
+        if (wstats[0]) atomicAdd(&a.stats[0], wstats[0]);
+        if (wstats[1]) atomicAdd(&a.stats[1], wstats[1]);
+        if (wstats[2]) atomicAdd(&a.stats[2], wstats[2]);
     }
 }
 

@@ -26,6 +26,7 @@ struct WalkArgs {
     int32_t lmax;
     int32_t filter_m;
     int32_t topk;
+    int32_t pool_chunk;  // > 0: a wave reserves pool space this many entries at a time
     int32_t hash_slots;            // power of two
     int32_t hash_shift;            // 32 - log2(hash_slots)
     uint32_t *queue_ctr;           // 8 counters

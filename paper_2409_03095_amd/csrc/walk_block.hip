@@ -333,20 +333,19 @@ __device__ __forceinline__ void block_row(const WalkArgs &a, int64_t task, RowCt
         const int32_t raw = rc.keys[s];
         const double acc = rc.vals[s];
         int32_t key = kEmpty;
-        double m = 0.0, nhat = 0.0;
+        double nhat = 0.0;
         int keep = 0;
         if (raw != kEmpty) {
             key = (int32_t)((uint32_t)raw & ~kRBit);
-            nhat = acc / nd;
-            m = nhat / a.diag[key];
-            const double test = a.filter_m ? fabs(m) : fabs(nhat);
+            nhat = acc / nd;  // N_rc; scaled by 1 / d_c once the kept set is final
+            const double test = a.filter_m ? fabs(nhat / a.diag[key]) : fabs(nhat);
             keep = (key == r || (nhat != 0.0 && test >= a.eps)) ? 1 : 0;
         }
         int added;
         const int pos = K + block_scan<kLPR>(keep, redi, &added);
         if (keep) {
             rc.keys[pos] = key;
-            rc.vals[pos] = a.topk > 0 ? nhat : m;  // top-k ranks by N_rc first
+            rc.vals[pos] = nhat;
         }
         K += added;
     }
@@ -356,14 +355,13 @@ __device__ __forceinline__ void block_row(const WalkArgs &a, int64_t task, RowCt
     for (int base = 0; base < nsp; base += kLPR) {
         const int u = base + tid;
         int32_t key = kEmpty;
-        double m = 0.0, nhat = 0.0;
+        double nhat = 0.0;
         int keep = 0;
         if (u < nsp) {
             const int32_t sl = rc.sused[u];
             key = (int32_t)((uint32_t)rc.skeys[sl] & ~kRBit);
             nhat = rc.svals[sl] / nd;
-            m = nhat / a.diag[key];
-            const double test = a.filter_m ? fabs(m) : fabs(nhat);
+            const double test = a.filter_m ? fabs(nhat / a.diag[key]) : fabs(nhat);
             keep = (key == r || (nhat != 0.0 && test >= a.eps)) ? 1 : 0;
             rc.skeys[sl] = kEmpty;
             rc.svals[sl] = 0.0;
@@ -373,7 +371,7 @@ __device__ __forceinline__ void block_row(const WalkArgs &a, int64_t task, RowCt
         if (keep) {
             if (p < H) {
                 rc.keys[p] = key;
-                rc.vals[p] = a.topk > 0 ? nhat : m;
+                rc.vals[p] = nhat;
             } else {
                 stage_full = true;
             }
@@ -410,9 +408,11 @@ __device__ __forceinline__ void block_row(const WalkArgs &a, int64_t task, RowCt
             }
             K = a.topk;
         }
-        for (int i = tid; i < K; i += kLPR) rc.vals[i] = rc.vals[i] / a.diag[rc.keys[i]];
-        __syncthreads();
     }
+    // M_rc = N_rc / d_c for the kept entries only (the eps test on N_rc needs no
+    // diagonal)
+    for (int i = tid; i < K; i += kLPR) rc.vals[i] = rc.vals[i] / a.diag[rc.keys[i]];
+    __syncthreads();
     int P = 1;
     while (P < K) P <<= 1;
     for (int s = K + tid; s < P; s += kLPR) rc.keys[s] = INT32_MAX;
