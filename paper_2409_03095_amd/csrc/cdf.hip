@@ -164,6 +164,7 @@ __global__ void __launch_bounds__(256) k_fill(int64_t n, const int64_t *__restri
     const int lane = threadIdx.x & 63;
     const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
     const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
+    double best = 0.0;  // the wave's largest Shat (one atomic per wave, not per row)
     for (int64_t r = wave; r < n; r += nwaves) {
         const int64_t b = rp[r], e = rp[r + 1];
         const uint32_t m = mrow[r];
@@ -230,9 +231,10 @@ __global__ void __launch_bounds__(256) k_fill(int64_t n, const int64_t *__restri
             hdr[3] = __float_as_uint((float)shat);
             *(double *)(hdr + 4) = shat;
             for (int z = 6; z < kUnitWords; ++z) hdr[z] = 0u;
-            atomicMax(norm_bits, (unsigned long long)__double_as_longlong(shat));
+            best = shat > best ? shat : best;
         }
     }
+    if (lane == 0 && best > 0.0) atomicMax(norm_bits, (unsigned long long)__double_as_longlong(best));
 }
 
 // Alias table of each row (Walker's method, Vose's exact-integer construction;
@@ -243,56 +245,69 @@ __global__ void __launch_bounds__(256) k_fill(int64_t n, const int64_t *__restri
 // q_l -= W - q_s), and l goes back on small if q_l < W, else on large. Leftover
 // buckets keep all W units (T = W, A = self). Every entry's final q is its
 // threshold. Both stacks live in one scratch array of the row's length (small
-// grows up from the front, large down from the back), q and A in two more.
+// grows up from the front, large down from the back), q and A in two more; one
+// thread per row, the scratch in LDS for rows of up to kAliasLds entries (in the
+// row's slice of a global scratch otherwise).
 // Each bucket then receives copies of the headers of the two rows it can lead
 // to (written by k_fill, a previous launch).
-__global__ void __launch_bounds__(256) k_alias(int64_t n, const uint32_t *__restrict__ mrow,
-                                               const uint32_t *__restrict__ roff32, const int64_t *__restrict__ cptr,
-                                               const uint2 *__restrict__ sorted, uint32_t *__restrict__ qs,
-                                               int32_t *__restrict__ stk, int32_t *__restrict__ alias,
-                                               uint32_t *__restrict__ rec) {
+constexpr int kAliasLds = 32;  // rows up to this long keep their scratch in LDS
+
+__global__ void __launch_bounds__(64) k_alias(int64_t n, const uint32_t *__restrict__ mrow,
+                                              const uint32_t *__restrict__ roff32, const int64_t *__restrict__ cptr,
+                                              const uint2 *__restrict__ sorted, uint32_t *__restrict__ qs_g,
+                                              int32_t *__restrict__ stk_g, int32_t *__restrict__ alias_g,
+                                              uint32_t *__restrict__ rec) {
+    // per-lane scratch, interleaved so that the lanes of a wave hit distinct banks
+    __shared__ uint32_t q_l[kAliasLds * 64];
+    __shared__ int32_t st_l[kAliasLds * 64];
+    __shared__ int32_t al_l[kAliasLds * 64];
+    const int lane = threadIdx.x;
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < n; r += stride) {
         const uint32_t m = mrow[r];
         if (m == 0) continue;
         const int64_t base = cptr[r];
         const uint32_t W = sorted[base + m - 1].x;
-        uint32_t *q = qs + base;
-        int32_t *st = stk + base;
-        int32_t *al = alias + base;
+        // scratch element k of this lane: LDS for short rows, the row's own slice of
+        // the global scratch (indexed like C) otherwise
+        const bool lds = m <= (uint32_t)kAliasLds;
+        uint32_t *q = lds ? q_l + lane : qs_g + base;
+        int32_t *st = lds ? st_l + lane : stk_g + base;
+        int32_t *al = lds ? al_l + lane : alias_g + base;
+        const int sc = lds ? 64 : 1;
         int ns = 0, nl = 0;
         uint32_t prev = 0;
         for (uint32_t k = 0; k < m; ++k) {
             const uint32_t cum = sorted[base + k].x;
             const uint32_t qk = m * (cum - prev);  // m w_k <= m 2^Q <= 2^31
             prev = cum;
-            q[k] = qk;
-            al[k] = (int32_t)k;
+            q[k * sc] = qk;
+            al[k * sc] = (int32_t)k;
             if (qk < W)
-                st[ns++] = (int32_t)k;
+                st[(ns++) * sc] = (int32_t)k;
             else
-                st[m - 1 - nl++] = (int32_t)k;
+                st[(m - 1 - nl++) * sc] = (int32_t)k;
         }
         while (ns > 0 && nl > 0) {
-            const int32_t sm = st[--ns];
-            const int32_t lg = st[m - nl--];
-            al[sm] = lg;
-            const uint32_t ql = q[lg] - (W - q[sm]);
-            q[lg] = ql;
+            const int32_t sm = st[(--ns) * sc];
+            const int32_t lg = st[(m - nl--) * sc];
+            al[sm * sc] = lg;
+            const uint32_t ql = q[lg * sc] - (W - q[sm * sc]);
+            q[lg * sc] = ql;
             if (ql < W)
-                st[ns++] = lg;
+                st[(ns++) * sc] = lg;
             else
-                st[m - 1 - nl++] = lg;
+                st[(m - 1 - nl++) * sc] = lg;
         }
         uint32_t *ent = rec + ((size_t)roff32[r] + 1u) * kUnitWords;
         prev = 0;
         for (uint32_t k = 0; k < m; ++k) {
-            const uint2 own = sorted[base + k], other = sorted[base + al[k]];
+            const uint2 own = sorted[base + k], other = sorted[base + al[k * sc]];
             const uint4 *ho = (const uint4 *)(rec + (size_t)(own.y & ~kSignBit) * kUnitWords);
             const uint4 *ha = (const uint4 *)(rec + (size_t)(other.y & ~kSignBit) * kUnitWords);
             uint4 *e = (uint4 *)(ent + (size_t)k * kUnitWords);
             const uint4 so = ho[1], sa = ha[1];
-            e[0] = make_uint4(q[k], own.y, other.y, own.x - prev);
+            e[0] = make_uint4(q[k * sc], own.y, other.y, own.x - prev);
             e[1] = ho[0];
             e[2] = ha[0];
             e[3] = make_uint4(so.x, so.y, sa.x, sa.y);
@@ -448,8 +463,12 @@ extern "C" mcmi_status mcmi_build_cdf_ex(const mcmi_csr_in *B, const mcmi_cdf_op
     TRY(hipGetLastError());
     TRY(hipMalloc(&qs, (size_t)(htot[1] > 0 ? htot[1] : 1) * sizeof(uint32_t)));
     TRY(hipMalloc(&stk, (size_t)(htot[1] > 0 ? 2 * htot[1] : 2) * sizeof(int32_t)));
-    k_alias<<<grid_for(n), 256, 0, s>>>(n, cdf->mrow, cdf->roff, cptr, sorted, qs, stk,
-                                        stk + (htot[1] > 0 ? htot[1] : 1), cdf->rec);
+    {
+        int64_t ab = (n + 63) / 64;
+        if (ab > 32768) ab = 32768;
+        k_alias<<<(unsigned)ab, 64, 0, s>>>(n, cdf->mrow, cdf->roff, cptr, sorted, qs, stk,
+                                            stk + (htot[1] > 0 ? htot[1] : 1), cdf->rec);
+    }
     TRY(hipGetLastError());
     unsigned long long hnorm = 0;
     TRY(hipMemcpyAsync(&hnorm, norm_bits, sizeof(hnorm), hipMemcpyDeviceToHost, s));
