@@ -33,39 +33,73 @@ namespace {
 using namespace walkdev;
 
 // Wave-uniform task fetch from the eight per-XCD queues.
-__device__ __forceinline__ int64_t next_task(const WalkArgs &a, int &queue) {
+// Rows are taken from the XCD queues kTaskChunk at a time (one atomic per chunk);
+// [lo, hi) is the wave's current chunk.
+constexpr int kTaskChunk = 8;
+
+__device__ __forceinline__ int64_t next_task(const WalkArgs &a, int &queue, int64_t &lo, int64_t &hi) {
+    if (lo < hi) return lo++;
     const int lane = lane_id();
-    int64_t task = -1;
+    int64_t clo = -1, chi = -1;
     if (lane == 0) {
         for (int tries = 0; tries < 8; ++tries) {
             const int q = (queue + tries) & 7;
-            const int64_t lo = a.n_tasks * q / 8, hi = a.n_tasks * (q + 1) / 8;
-            if (hi > lo && __atomic_load_n(&a.queue_ctr[q], __ATOMIC_RELAXED) < (uint32_t)(hi - lo)) {
-                const uint32_t idx = atomicAdd(&a.queue_ctr[q], 1u);
-                if ((int64_t)idx < hi - lo) {
-                    task = lo + idx;
+            const int64_t qlo = a.n_tasks * q / 8, qhi = a.n_tasks * (q + 1) / 8;
+            if (qhi > qlo && __atomic_load_n(&a.queue_ctr[q], __ATOMIC_RELAXED) < (uint32_t)(qhi - qlo)) {
+                const uint32_t idx = atomicAdd(&a.queue_ctr[q], (uint32_t)kTaskChunk);
+                if ((int64_t)idx < qhi - qlo) {
+                    clo = qlo + idx;
+                    chi = qlo + (int64_t)idx + kTaskChunk < qhi ? qlo + (int64_t)idx + kTaskChunk : qhi;
                     queue = q;
                     break;
                 }
             }
         }
     }
-    task = __shfl(task, 0, 64);
+    clo = __shfl(clo, 0, 64);
+    chi = __shfl(chi, 0, 64);
     queue = __shfl(queue, 0, 64);
-    return task;
+    if (clo < 0) return -1;
+    lo = clo + 1;
+    hi = chi;
+    return clo;
+}
+
+// A row's ids, record offset and header, loaded ahead of its walk: row_ids issues
+// the offset load, row_hdr (later, once that has arrived) the header load.
+struct RowPre {
+    int64_t task, slot;
+    int32_t r, N;
+    uint32_t r_off;
+    StepHdr h0;
+};
+
+__device__ __forceinline__ void row_ids(const WalkArgs &a, int64_t task, RowPre &p) {
+    p.task = task;
+    if (task < 0) return;
+    p.slot = a.task_map ? (int64_t)a.task_map[task] : task;
+    p.r = a.rows ? a.rows[p.slot] : (int32_t)p.slot;
+    p.N = a.chains_per_row ? a.chains_per_row[p.r] : a.chains;
+    p.r_off = a.roff[p.r];
 }
 
 template <bool kF32>
-__device__ __forceinline__ void walk_row(const WalkArgs &a, int64_t task, int32_t *keys, double *vals, int *spill_cnt,
+__device__ __forceinline__ void row_hdr(const WalkArgs &a, RowPre &p) {
+    if (p.task >= 0) load_header<kF32>(a.rec, p.r_off, p.h0);
+}
+
+template <bool kF32>
+__device__ __forceinline__ void walk_row(const WalkArgs &a, const RowPre &cur, RowPre &nxt, int &queue, int64_t &tlo,
+                         int64_t &thi, int32_t *keys, double *vals, int *spill_cnt,
                          int32_t *skeys, double *svals, int32_t *sused, uint32_t k0, uint32_t k1,
                          unsigned long long &pcur, unsigned long long &pend, unsigned long long *wstats) {
     const int lane = lane_id();
     const uint32_t hmask = (uint32_t)a.hash_slots - 1u;
     const uint32_t smask = (uint32_t)a.spill_slots - 1u;
-    const int64_t slot = a.task_map ? (int64_t)a.task_map[task] : task;
-    const int32_t r = a.rows ? a.rows[slot] : (int32_t)slot;
-    const int32_t N = a.chains_per_row ? a.chains_per_row[r] : a.chains;
-    const uint32_t r_off = a.roff[r];
+    const int64_t slot = cur.slot;
+    const int32_t r = cur.r;
+    const int32_t N = cur.N;
+    const uint32_t r_off = cur.r_off;
     uint32_t prow, ptag;
     philox_ids(a, r, prow, ptag);
 
@@ -79,10 +113,9 @@ __device__ __forceinline__ void walk_row(const WalkArgs &a, int64_t task, int32_
     uint32_t j = 0;
     double w64 = 1.0;
     float w32 = 1.0f;
-    // the row's own header (every chain starts there); later states' headers
-    // arrive with the bucket of the step that reaches them
-    StepHdr H0;
-    load_header<kF32>(a.rec, r_off, H0);
+    // the row's own header (every chain starts there, loaded ahead); later
+    // states' headers arrive with the bucket of the step that reaches them
+    const StepHdr H0 = cur.h0;
     StepHdr H = H0;
     u32x4 blk = {0, 0, 0, 0};
     unsigned long long trans = 0, spilled = 0;
@@ -143,6 +176,9 @@ __device__ __forceinline__ void walk_row(const WalkArgs &a, int64_t task, int32_
         }
     }
     wave_sync();
+    // the next row's ids and record offset load now, its header during the
+    // finalize: both latencies hide behind this row's finalize
+    row_ids(a, next_task(a, queue, tlo, thi), nxt);
 
     // ---------------------------------------------------------- finalize
     const double nd = (double)N;
@@ -168,6 +204,7 @@ __device__ __forceinline__ void walk_row(const WalkArgs &a, int64_t task, int32_
         K += __popcll(km);
     }
     wave_sync();
+    row_hdr<kF32>(a, nxt);
     const int nsp = *spill_cnt;
     bool stage_full = false;
     for (int base = 0; base < nsp; base += 64) {
@@ -345,10 +382,15 @@ __global__ void __launch_bounds__(256) k_walk(WalkArgs a) {
     const uint32_t k0 = a.keys_dev ? a.keys_dev[0] : a.key0;
     const uint32_t k1 = a.keys_dev ? a.keys_dev[1] : a.key1;
     unsigned long long pcur = 0, pend = 0, wstats[3] = {0, 0, 0};
-    for (;;) {
-        const int64_t task = next_task(a, queue);
-        if (task < 0) break;
-        walk_row<kF32>(a, task, keys, vals, spill_cnt, skeys, svals, sused, k0, k1, pcur, pend, wstats);
+    int64_t tlo = 0, thi = 0;
+    RowPre cur;
+    row_ids(a, next_task(a, queue, tlo, thi), cur);
+    row_hdr<kF32>(a, cur);
+    while (cur.task >= 0) {
+        RowPre nxt;
+        walk_row<kF32>(a, cur, nxt, queue, tlo, thi, keys, vals, spill_cnt, skeys, svals, sused, k0, k1, pcur, pend,
+                       wstats);
+        cur = nxt;
     }
     // statistics: one set of atomics per wave
     if (lane == 0) {
