@@ -265,14 +265,53 @@ __device__ __forceinline__ int block_scan(int v, int *red, int *total) {
     return base + incl - v;
 }
 
+// Next row from the XCD queues (called by one thread; -1 when all are drained).
+__device__ __forceinline__ int64_t grab_task(const WalkArgs &a, int &queue) {
+    for (int tries = 0; tries < 8; ++tries) {
+        const int q = (queue + tries) & 7;
+        const int64_t lo = a.n_tasks * q / 8, hi = a.n_tasks * (q + 1) / 8;
+        if (hi > lo && __atomic_load_n(&a.queue_ctr[q], __ATOMIC_RELAXED) < (uint32_t)(hi - lo)) {
+            const uint32_t idx = atomicAdd(&a.queue_ctr[q], 1u);
+            if ((int64_t)idx < hi - lo) {
+                queue = q;
+                return lo + idx;
+            }
+        }
+    }
+    return -1;
+}
+
+__device__ __forceinline__ void put_task(int *ctl, int64_t task) {
+    ctl[8] = (int)(task & 0xffffffff);
+    ctl[9] = (int)(task >> 32);
+}
+
+__device__ __forceinline__ int64_t get_task(const int *ctl) {
+    return (int64_t)(((uint64_t)(uint32_t)ctl[9] << 32) | (uint32_t)ctl[8]);
+}
+
+// A row's record offset and header, loaded ahead of its walk.
+struct RowPre {
+    int64_t task;
+    uint32_t r_off;
+    StepHdr h0;
+};
+
+__device__ __forceinline__ int32_t task_row(const WalkArgs &a, int64_t task, int64_t &slot) {
+    slot = a.task_map ? (int64_t)a.task_map[task] : task;
+    return a.rows ? a.rows[slot] : (int32_t)slot;
+}
+
 template <bool kF32, int kLPR, int kQ>
-__device__ __forceinline__ void block_row(const WalkArgs &a, int64_t task, RowCtx &rc, int *ctl, float *redf, int *redi,
+__device__ __forceinline__ void block_row(const WalkArgs &a, const RowPre &cur, RowPre &nxt, int &queue, RowCtx &rc,
+                          int *ctl, float *redf, int *redi,
                           unsigned long long &trans, unsigned long long &spilled, bool &spill_full,
                           bool &stage_full) {
     constexpr int H = kLPR * kQ;
     const int tid = threadIdx.x;
-    const int64_t slot = a.task_map ? (int64_t)a.task_map[task] : task;
-    const int32_t r = a.rows ? a.rows[slot] : (int32_t)slot;
+    const int64_t task = cur.task;
+    int64_t slot;
+    const int32_t r = task_row(a, task, slot);
     const int32_t N = a.chains_per_row ? a.chains_per_row[r] : a.chains;
     unsigned long long row_trans = 0;
     spill_full = false;
@@ -280,8 +319,8 @@ __device__ __forceinline__ void block_row(const WalkArgs &a, int64_t task, RowCt
     rc.r = r;
     rc.N = N;
     philox_ids(a, r, rc.prow, rc.ptag);
-    rc.r_off = a.roff[r];
-    load_header<kF32>(a.rec, rc.r_off, rc.h0);
+    rc.r_off = cur.r_off;
+    rc.h0 = cur.h0;
     const bool split = a.tau > 0.0;
     const bool reg = N <= kLPR;
     if (tid == 0) lds_add(rc.keys, rc.vals, H - 1u, hash_key(r, a.hash_shift), r, (double)N);
@@ -323,33 +362,47 @@ __device__ __forceinline__ void block_row(const WalkArgs &a, int64_t task, RowCt
     }
 
     // ------------------------------------------------------------ finalize
+    // the next row: taken now, its offset and header loaded during this finalize
+    if (tid == 0) put_task(ctl, grab_task(a, queue));
     const double nd = (double)N;
-    // in-place compaction, one slot per lane per round: a survivor moves to
-    // position K + (survivors before it in this round) <= its own slot, and every
-    // lane has read its slot of the round before anyone writes
-    int K = 0;
-    for (int base = 0; base < H; base += kLPR) {
-        const int s = base + tid;
+    // compaction in one pass: each lane reads its kQ consecutive slots, one block
+    // scan places the survivors (all reads precede the scan's barrier, so writing
+    // in place is safe)
+    int32_t ks[kQ];
+    double vs[kQ];
+    int cnt = 0;
+#pragma unroll
+    for (int q = 0; q < kQ; ++q) {
+        const int s = tid * kQ + q;
         const int32_t raw = rc.keys[s];
         const double acc = rc.vals[s];
-        int32_t key = kEmpty;
-        double nhat = 0.0;
-        int keep = 0;
+        ks[q] = kEmpty;
+        vs[q] = 0.0;
         if (raw != kEmpty) {
-            key = (int32_t)((uint32_t)raw & ~kRBit);
-            nhat = acc / nd;  // N_rc; scaled by 1 / d_c once the kept set is final
+            const int32_t key = (int32_t)((uint32_t)raw & ~kRBit);
+            const double nhat = acc / nd;  // N_rc; scaled by 1 / d_c once the kept set is final
             const double test = a.filter_m ? fabs(nhat / a.diag[key]) : fabs(nhat);
-            keep = (key == r || (nhat != 0.0 && test >= a.eps)) ? 1 : 0;
+            if (key == r || (nhat != 0.0 && test >= a.eps)) {
+                ks[q] = key;
+                vs[q] = nhat;
+                ++cnt;
+            }
         }
-        int added;
-        const int pos = K + block_scan<kLPR>(keep, redi, &added);
-        if (keep) {
-            rc.keys[pos] = key;
-            rc.vals[pos] = nhat;
-        }
-        K += added;
     }
+    int K;
+    int pos = block_scan<kLPR>(cnt, redi, &K);
+#pragma unroll
+    for (int q = 0; q < kQ; ++q)
+        if (ks[q] != kEmpty) {
+            rc.keys[pos] = ks[q];
+            rc.vals[pos] = vs[q];
+            ++pos;
+        }
     __syncthreads();
+    nxt.task = get_task(ctl);
+    int64_t nslot = 0;
+    const int32_t nr = nxt.task >= 0 ? task_row(a, nxt.task, nslot) : 0;
+    nxt.r_off = nxt.task >= 0 ? a.roff[nr] : 0u;
     // spilled columns
     const int nsp = *rc.spill_cnt;
     for (int base = 0; base < nsp; base += kLPR) {
@@ -380,6 +433,7 @@ __device__ __forceinline__ void block_row(const WalkArgs &a, int64_t task, RowCt
     }
     if (K > H) K = H;
     __syncthreads();
+    if (nxt.task >= 0) load_header<kF32>(a.rec, nxt.r_off, nxt.h0);
     // top-k retention: bitonic sort in retention order, keep the first topk,
     // then turn N_rc into M_rc = N_rc / d_c
     if (a.topk > 0) {
@@ -508,29 +562,20 @@ __global__ void __launch_bounds__(kLPR, 4) k_walk_block(WalkArgs a) {
     unsigned long long trans = 0, spilled = 0;
     bool spill_full = false, stage_full = false;
     int queue = (int)(blockIdx.x & 7u);
-    for (;;) {
-        if (tid == 0) {
-            int64_t task = -1;
-            for (int tries = 0; tries < 8; ++tries) {
-                const int q = (queue + tries) & 7;
-                const int64_t lo = a.n_tasks * q / 8, hi = a.n_tasks * (q + 1) / 8;
-                if (hi > lo && __atomic_load_n(&a.queue_ctr[q], __ATOMIC_RELAXED) < (uint32_t)(hi - lo)) {
-                    const uint32_t idx = atomicAdd(&a.queue_ctr[q], 1u);
-                    if ((int64_t)idx < hi - lo) {
-                        task = lo + idx;
-                        queue = q;
-                        break;
-                    }
-                }
-            }
-            ctl[2] = (int)(task & 0xffffffff);
-            ctl[3] = (int)(task >> 32);
-        }
-        __syncthreads();
-        const int64_t task = (int64_t)(((uint64_t)(uint32_t)ctl[3] << 32) | (uint32_t)ctl[2]);
-        __syncthreads();
-        if (task < 0) break;
-        block_row<kF32, kLPR, kQ>(a, task, rc, ctl, redf, redi, trans, spilled, spill_full, stage_full);
+    RowPre cur;
+    if (tid == 0) put_task(ctl, grab_task(a, queue));
+    __syncthreads();
+    cur.task = get_task(ctl);
+    __syncthreads();
+    if (cur.task >= 0) {
+        int64_t slot;
+        cur.r_off = a.roff[task_row(a, cur.task, slot)];
+        load_header<kF32>(a.rec, cur.r_off, cur.h0);
+    }
+    while (cur.task >= 0) {
+        RowPre nxt;
+        block_row<kF32, kLPR, kQ>(a, cur, nxt, queue, rc, ctl, redf, redi, trans, spilled, spill_full, stage_full);
+        cur = nxt;
     }
     // one set of atomics per workgroup
     trans = wave_sum(trans);
