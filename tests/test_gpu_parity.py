@@ -214,6 +214,23 @@ def test_cfg2_full_size_sampled_rows(mc):
     assert np.max(np.abs(va - vb) / np.abs(vb)) < 1e-5
 
 
+def test_aniso27_full_size_sampled_rows(mc):
+    """3D 27-point anisotropic 160^3 (n = 4,096,000, 7 GB of records), 64 chains,
+    FP32 walks + FP64 sums, delta = 1e-4, eps = 1e-3: whole-matrix run through the
+    wavefront kernel, 2048 sampled rows compared with the oracle's runs of those
+    rows (each row's result depends only on its own chains)."""
+    B = I.cfg5(160)
+    (rp, col, val), res, _ = run(mc, B, seed=0, chains=64, delta=1e-4, eps=1e-3, prec=32)
+    assert res.stats.lanes_per_row == 64
+    rows = np.sort(np.random.default_rng(11).choice(B.n, 2048, replace=False)).astype(np.int32)
+    orc32, o = oracle_run(B, seed=0, chains=64, delta=1e-4, eps=1e-3, prec=32, rows=rows)
+    assert orc32["guard"] == 0
+    sub_rp = np.concatenate([[0], np.cumsum(rp[rows + 1] - rp[rows])])
+    sub_col = np.concatenate([col[rp[r]:rp[r + 1]] for r in rows])
+    sub_val = np.concatenate([val[rp[r]:rp[r + 1]] for r in rows])
+    compare_spai((sub_rp, sub_col, sub_val), orc32, o.diag, 64, rows=rows)
+
+
 # ------------------------------------- workgroup-per-row kernel (heavy/light)
 BLOCK_CASES = {
     # name: (matrix, chains, gpu params, fp32)
