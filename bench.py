@@ -49,7 +49,7 @@ def algorithmic_bytes_per_transition(B, fp32: bool) -> float:
     return float(np.mean((16.0 if fp32 else 24.0) + 4.0 * probes + 4.0))
 
 
-def cpu_baseline(B, chains, delta, eps, fp32, budget_s=12.0):
+def cpu_baseline(B, chains, delta, eps, fp32, budget_s=20.0):
     """The oracle as it is, on the host cores, on a bounded sample of rows."""
     import oracle as O
     threads = O.default_threads()
