@@ -337,6 +337,12 @@ mcmi_status mcmi_bicgstab(const mcmi_csr_in *B, const mcmi_csr_out *M, const dou
 mcmi_status mcmi_csr_copy(const mcmi_csr_out *M, int64_t *row_ptr_dev, int32_t *col_dev,
                           double *val_dev, void *stream);
 
+/* Device memory that the library's calls free is kept for reuse by later calls
+ * (each device keeps at most a quarter of its memory; a block released with a
+ * stream is reused only on that stream). This returns all of it to the driver;
+ * it synchronises every device that holds cached memory. */
+void mcmi_cache_trim(void);
+
 void mcmi_cdf_free(mcmi_cdf *cdf);
 void mcmi_csr_free(mcmi_csr_out *M);
 const char *mcmi_last_error(void);

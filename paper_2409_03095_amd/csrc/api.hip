@@ -124,13 +124,13 @@ struct DevBuf {
     void *p = nullptr;
     hipStream_t s = nullptr;
     ~DevBuf() {
-        if (p) hipFreeAsync(p, s);
+        if (p) dev_release(p, s);
     }
     hipError_t alloc(size_t bytes, hipStream_t st) {
-        if (p) hipFreeAsync(p, s);
+        if (p) dev_release(p, s);
         p = nullptr;
         s = st;
-        return hipMallocAsync(&p, bytes ? bytes : 16, st);
+        return dev_alloc(&p, bytes ? bytes : 16, st);
     }
     template <typename T>
     T *as() const {
@@ -417,13 +417,13 @@ extern "C" mcmi_status mcmi_spai(const mcmi_cdf *cdf, const mcmi_params *p, cons
     int32_t *col = nullptr;
     double *val = nullptr;
     int64_t *rp = nullptr;
-    hipError_t e1 = hipMalloc(&col, (size_t)std::max<int64_t>(nnz, 1) * sizeof(int32_t));
-    hipError_t e2 = hipMalloc(&val, (size_t)std::max<int64_t>(nnz, 1) * sizeof(double));
-    hipError_t e3 = hipMalloc(&rp, (size_t)(n_tasks + 1) * sizeof(int64_t));
+    hipError_t e1 = dev_alloc((void **)&col, (size_t)std::max<int64_t>(nnz, 1) * sizeof(int32_t), s);
+    hipError_t e2 = dev_alloc((void **)&val, (size_t)std::max<int64_t>(nnz, 1) * sizeof(double), s);
+    hipError_t e3 = dev_alloc((void **)&rp, (size_t)(n_tasks + 1) * sizeof(int64_t), s);
     if (e1 != hipSuccess || e2 != hipSuccess || e3 != hipSuccess) {
-        hipFree(col);
-        hipFree(val);
-        hipFree(rp);
+        dev_release(col, s);
+        dev_release(val, s);
+        dev_release(rp, s);
         hipEventDestroy(ev3);
         return fail(MCMI_ERR_NOMEM, "mcmi_spai: cannot allocate M");
     }
@@ -433,9 +433,9 @@ extern "C" mcmi_status mcmi_spai(const mcmi_cdf *cdf, const mcmi_params *p, cons
     if (ge == hipSuccess) ge = hipEventRecord(ev3, s);
     if (ge == hipSuccess) ge = hipEventSynchronize(ev3);
     if (ge != hipSuccess) {
-        hipFree(col);
-        hipFree(val);
-        hipFree(rp);
+        dev_release(col, s);
+        dev_release(val, s);
+        dev_release(rp, s);
         hipEventDestroy(ev3);
         return fail(MCMI_ERR_HIP, std::string("mcmi_spai: assembly: ") + hipGetErrorString(ge));
     }
@@ -490,9 +490,9 @@ extern "C" mcmi_status mcmi_csr_copy(const mcmi_csr_out *M, int64_t *row_ptr_dev
 
 extern "C" void mcmi_csr_free(mcmi_csr_out *M) {
     if (!M) return;
-    hipFree(M->row_ptr_dev);
-    hipFree(M->col_dev);
-    hipFree(M->val_dev);
+    dev_release_idle(M->row_ptr_dev);
+    dev_release_idle(M->col_dev);
+    dev_release_idle(M->val_dev);
     memset(M, 0, sizeof(*M));
 }
 

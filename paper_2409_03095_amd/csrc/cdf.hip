@@ -366,7 +366,7 @@ extern "C" mcmi_status mcmi_build_cdf_ex(const mcmi_csr_in *B, const mcmi_cdf_op
         // temporaries are stream-ordered: released behind the last kernel that uses them
         for (void *t : {(void *)cut_keys, (void *)sel, (void *)units, (void *)flags, (void *)roff64, (void *)cptr,
                         (void *)totals, (void *)norm_bits, tmp, (void *)sorted, (void *)qs, (void *)stk})
-            if (t) (void)hipFreeAsync(t, s);
+            if (t) dev_release(t, s);
     };
     auto bail = [&](mcmi_status code, const std::string &msg) {
         cleanup();
@@ -378,16 +378,16 @@ extern "C" mcmi_status mcmi_build_cdf_ex(const mcmi_csr_in *B, const mcmi_cdf_op
         hipError_t _e = (call);                                                               \
         if (_e != hipSuccess) return bail(MCMI_ERR_HIP, std::string(#call) + ": " + hipGetErrorString(_e)); \
     } while (0)
-    TRY(hipMalloc(&cdf->mrow, n * sizeof(uint32_t)));
-    TRY(hipMalloc(&cdf->diag, n * sizeof(double)));
-    TRY(hipMalloc(&cdf->roff, n * sizeof(uint32_t)));
-    TRY(hipMallocAsync((void **)&units, n * sizeof(uint32_t), s));
-    TRY(hipMallocAsync((void **)&flags, sizeof(uint32_t), s));
-    TRY(hipMallocAsync((void **)&roff64, n * sizeof(int64_t), s));
-    TRY(hipMallocAsync((void **)&cptr, n * sizeof(int64_t), s));
-    TRY(hipMallocAsync((void **)&totals, 2 * sizeof(int64_t), s));
-    TRY(hipMallocAsync((void **)&norm_bits, sizeof(unsigned long long), s));
-    TRY(hipMallocAsync((void **)&tmp, scan_tmp_bytes(n), s));
+    TRY(dev_alloc((void **)&cdf->mrow, n * sizeof(uint32_t), s));
+    TRY(dev_alloc((void **)&cdf->diag, n * sizeof(double), s));
+    TRY(dev_alloc((void **)&cdf->roff, n * sizeof(uint32_t), s));
+    TRY(dev_alloc((void **)&units, n * sizeof(uint32_t), s));
+    TRY(dev_alloc((void **)&flags, sizeof(uint32_t), s));
+    TRY(dev_alloc((void **)&roff64, n * sizeof(int64_t), s));
+    TRY(dev_alloc((void **)&cptr, n * sizeof(int64_t), s));
+    TRY(dev_alloc((void **)&totals, 2 * sizeof(int64_t), s));
+    TRY(dev_alloc((void **)&norm_bits, sizeof(unsigned long long), s));
+    TRY(dev_alloc((void **)&tmp, scan_tmp_bytes(n), s));
     TRY(hipMemsetAsync(flags, 0, sizeof(uint32_t), s));
     TRY(hipMemsetAsync(norm_bits, 0, sizeof(unsigned long long), s));
     const unsigned grid = grid_for_rows(n);
@@ -425,8 +425,8 @@ extern "C" mcmi_status mcmi_build_cdf_ex(const mcmi_csr_in *B, const mcmi_cdf_op
         const int64_t cnt = htot[1];
         const int64_t K = (int64_t)floor(drop_frac * (double)cnt);
         const int64_t nk = B->nnz;
-        TRY(hipMallocAsync((void **)&cut_keys, (size_t)(nk > 0 ? nk : 1) * sizeof(unsigned long long), s));
-        TRY(hipMallocAsync((void **)&sel, (2 + 256) * sizeof(unsigned long long), s));
+        TRY(dev_alloc((void **)&cut_keys, (size_t)(nk > 0 ? nk : 1) * sizeof(unsigned long long), s));
+        TRY(dev_alloc((void **)&sel, (2 + 256) * sizeof(unsigned long long), s));
         const unsigned long long init[2] = {0ull, (unsigned long long)K};
         TRY(hipMemcpyAsync(sel, init, sizeof(init), hipMemcpyHostToDevice, s));
         TRY(hipMemsetAsync(sel + 2, 0, 256 * sizeof(unsigned long long), s));
@@ -448,13 +448,13 @@ extern "C" mcmi_status mcmi_build_cdf_ex(const mcmi_csr_in *B, const mcmi_cdf_op
     if (htot[0] >= (int64_t)kSignBit) return bail(MCMI_ERR_CAPACITY, "mcmi_build_cdf: records exceed 128 GiB");
     cdf->rec_units = (uint64_t)htot[0];
     cdf->nnz_c = htot[1];
-    TRY(hipMalloc(&cdf->rec, (size_t)htot[0] * kUnitWords * 4u + 64u));
-    TRY(hipMallocAsync((void **)&sorted, (size_t)(htot[1] > 0 ? htot[1] : 1) * sizeof(uint2), s));
+    TRY(dev_alloc((void **)&cdf->rec, (size_t)htot[0] * kUnitWords * 4u + 64u, s));
+    TRY(dev_alloc((void **)&sorted, (size_t)(htot[1] > 0 ? htot[1] : 1) * sizeof(uint2), s));
     k_fill<<<grid, 256, 0, s>>>(n, B->row_ptr_dev, B->col_dev, B->val_dev, cdf->diag, cdf->mrow, roff64, cptr,
                                 cut, cdf->roff, cdf->rec, sorted, norm_bits);
     TRY(hipGetLastError());
-    TRY(hipMallocAsync((void **)&qs, (size_t)(htot[1] > 0 ? htot[1] : 1) * sizeof(uint32_t), s));
-    TRY(hipMallocAsync((void **)&stk, (size_t)(htot[1] > 0 ? 2 * htot[1] : 2) * sizeof(int32_t), s));
+    TRY(dev_alloc((void **)&qs, (size_t)(htot[1] > 0 ? htot[1] : 1) * sizeof(uint32_t), s));
+    TRY(dev_alloc((void **)&stk, (size_t)(htot[1] > 0 ? 2 * htot[1] : 2) * sizeof(int32_t), s));
     {
         int64_t ab = (n + 63) / 64;
         if (ab > 32768) ab = 32768;
@@ -661,9 +661,9 @@ extern "C" void mcmi_cdf_free(mcmi_cdf *cdf) {
     if (!cdf) return;
     (void)hipFree(cdf->row_mat);
     (void)hipFree(cdf->mat_base);
-    hipFree(cdf->rec);
-    hipFree(cdf->roff);
-    hipFree(cdf->diag);
-    hipFree(cdf->mrow);
+    dev_release_idle(cdf->rec);
+    dev_release_idle(cdf->roff);
+    dev_release_idle(cdf->diag);
+    dev_release_idle(cdf->mrow);
     delete cdf;
 }

@@ -160,6 +160,15 @@ namespace mcmi {
 mcmi_status choose_shape(const mcmi_cdf *cdf, const mcmi_params *p, int lmax, KernelShape &out);
 }
 
+// Device-memory cache (alloc.hip): dev_alloc reuses a block released on the
+// same stream (dev_release, stream-ordered) or released idle (dev_release_idle,
+// which synchronises the device first); otherwise it calls hipMalloc.
+namespace mcmi {
+hipError_t dev_alloc(void **p, size_t bytes, hipStream_t s);
+void dev_release(void *p, hipStream_t s);
+void dev_release_idle(void *p);
+}  // namespace mcmi
+
 // The opaque record set.
 #include <vector>
 struct mcmi_cdf {

@@ -110,6 +110,8 @@ for _name, _args in _sig.items():
     getattr(_lib, _name).argtypes = _args
     getattr(_lib, _name).restype = ctypes.c_int
 _lib.mcmi_cdf_free.argtypes = [_v]
+_lib.mcmi_cache_trim.argtypes = []
+_lib.mcmi_cache_trim.restype = None
 _lib.mcmi_cdf_free.restype = None
 _lib.mcmi_plan_free.argtypes = [_v]
 _lib.mcmi_plan_free.restype = None
@@ -120,7 +122,7 @@ _lib.mcmi_csr_free.restype = None
 _lib.mcmi_last_error.restype = ctypes.c_char_p
 _lib.mcmi_version.restype = ctypes.c_char_p
 
-EXPORTED = ["mcmi_bicgstab", "mcmi_build_cdf", "mcmi_build_cdf_ex", "mcmi_cdf_prep_info", "mcmi_cdf_info", "mcmi_cdf_download", "mcmi_spai", "mcmi_apply",
+EXPORTED = ["mcmi_cache_trim", "mcmi_bicgstab", "mcmi_build_cdf", "mcmi_build_cdf_ex", "mcmi_cdf_prep_info", "mcmi_cdf_info", "mcmi_cdf_download", "mcmi_spai", "mcmi_apply",
             "mcmi_csr_copy", "mcmi_cdf_free", "mcmi_csr_free", "mcmi_last_error", "mcmi_version",
             "mcmi_row_features", "mcmi_pilot_variance", "mcmi_mlp_create", "mcmi_mlp_free",
             "mcmi_mlp_set_params", "mcmi_mlp_get_params", "mcmi_mlp_set_adam_state", "mcmi_mlp_fit_normalization",
@@ -470,3 +472,8 @@ def bicgstab(B: DeviceCsr, M=None, b=None, x0=None, rtol=1e-8, maxiter=5000, str
     _check(_lib.mcmi_bicgstab(ctypes.byref(s), None if M is None else ctypes.byref(M._out), _ptr(b), _ptr(x),
                               ctypes.c_double(rtol), ctypes.c_int32(maxiter), ctypes.byref(st), _stream(stream)))
     return x, st
+
+
+def cache_trim():
+    """mcmi_cache_trim: return the library's cached device memory to the driver."""
+    _lib.mcmi_cache_trim()

@@ -295,3 +295,26 @@ def test_overflow_rows_are_rerun(mc, case, prec):
     assert orc["guard"] == 0
     assert res.stats.transitions == orc["transitions"]
     compare_spai((rp, col, val), orc, o.diag, N)
+
+
+def test_memory_cache_reuse_across_streams_and_trim(mc):
+    """Blocks the library caches between calls are reused on the same stream or
+    after an idle release; results stay identical on another stream, after many
+    calls, and after returning the cache to the driver."""
+    B = I.random_nonsym(5000, seed=61)
+    dB = mc.DeviceCsr.from_host(B)
+    p = mc.params(seed=4, chains=64, delta=1e-4, eps=1e-3, walk_prec=32)
+    ref = mc.spai(mc.Cdf(dB), p).to_numpy()
+    side = torch.cuda.Stream()
+    for it in range(6):
+        if it % 2:
+            with torch.cuda.stream(side):
+                cdf = mc.Cdf(dB, stream=side)
+                out = mc.spai(cdf, p, stream=side).to_numpy(stream=side)
+                side.synchronize()
+        else:
+            out = mc.spai(mc.Cdf(dB), p).to_numpy()
+        for a, b in zip(out, ref):
+            assert np.array_equal(a, b), it
+        if it == 3:
+            mc.cache_trim()
