@@ -87,6 +87,8 @@ def main():
                     help="random: n=262144 random nonsymmetric (default); aniso27: 160^3 27-point anisotropic; "
                          "batched: 256 3D 7-point convection-diffusion matrices in one launch")
     ap.add_argument("--nx", type=int, default=160, help="grid side of the aniso27 workload")
+    ap.add_argument("--order-cell", type=int, default=None,
+                    help="row schedule cells (rows per cell; 0 = natural order). Default: 4096 for aniso27, else 0")
     ap.add_argument("--bicgstab", action="store_true", help="aniso27: device BiCGstab iterations with and without M")
     ap.add_argument("--learned", action="store_true",
                     help="learned vs uniform chains to ||I-MB||_F/sqrt(n) <= 0.3 (allocation-network workload)")
@@ -129,8 +131,10 @@ def main():
         torch.cuda.synchronize()
         del src, dst
 
+    cell = args.order_cell or 0
+
     def step():
-        cdf = mcmi.Cdf(dB)
+        cdf = mcmi.Cdf(dB, order_cell=cell)
         res = mcmi.spai(cdf, p)
         res.apply(x, y)
         return cdf, res
@@ -196,7 +200,7 @@ def main():
                    "n": B.n, "nnz_B": B.nnz, "chains_per_row": args.chains, "transitions_per_step": trans[-1],
                    "nnz_M": nnz, "spilled_contributions": spilled, "retries": retries,
                    "lanes_per_row": lanes, "hash_slots": hslots, "sketch_slots": sslots,
-                   "heavy_weight": tau, "rows_replayed": refined},
+                   "heavy_weight": tau, "rows_replayed": refined, "order_cell": cell},
         "roofline": roofline,
     }
     if not args.no_cpu:
@@ -220,15 +224,16 @@ def aniso_main(args):
                     hash_slots=args.hash_slots, sketch_slots=args.sketch_slots, heavy_weight=args.heavy_weight)
     x = torch.ones(B.n, dtype=torch.float64, device="cuda")
     y = torch.empty(B.n, dtype=torch.float64, device="cuda")
+    cell = 4096 if args.order_cell is None else args.order_cell
     for _ in range(args.warmup):
-        cdf = mcmi.Cdf(dB)
+        cdf = mcmi.Cdf(dB, order_cell=cell)
         res = mcmi.spai(cdf, p)
         del cdf, res
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     walk_ms = []
     for _ in range(args.steps):
-        cdf = mcmi.Cdf(dB)
+        cdf = mcmi.Cdf(dB, order_cell=cell)
         res = mcmi.spai(cdf, p)
         res.apply(x, y)
         walk_ms.append(res.stats.ms_walk)
@@ -248,7 +253,7 @@ def aniso_main(args):
            "config": {"workload": f"3D 27-point anisotropic {args.nx}^3", "n": B.n, "nnz_B": B.nnz,
                       "chains_per_row": chains, "transitions_per_step": int(st.transitions), "nnz_M": int(last.nnz),
                       "lanes_per_row": st.lanes_per_row, "hash_slots": st.hash_slots, "spilled": int(st.spilled),
-                      "retries": int(st.retries), "record_bytes": int(rec_units) * 64},
+                      "retries": int(st.retries), "record_bytes": int(rec_units) * 64, "order_cell": cell},
            "roofline": {"bound": "hbm", "achieved": round(bpt * st.transitions / walk_s / 1e9, 1), "peak": HBM_PEAK_GBS,
                         "unit": "GB/s", "frac": round(bpt * st.transitions / walk_s / 1e9 / HBM_PEAK_GBS, 4),
                         "bytes_per_transition": round(bpt, 2), "walk_ms": round(walk_s * 1e3, 3),

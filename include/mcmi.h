@@ -153,7 +153,17 @@ typedef struct {
      * (K+1)-th smallest |c_ij|; entries with |c_ij| below it are removed before the
      * CDF is built (entries equal to the cut stay). 0 <= drop_frac < 1. */
     double drop_frac;
-    int64_t reserved[2]; /* must be 0 */
+    /* Row schedule (not part of the method: every row's estimate is the same in any
+     * order). 0: rows run in their natural order. k > 0: rows are grouped into
+     * cells of about k rows grown by a multi-source breadth-first search on the
+     * pattern of B (seeds picked by a hash of the row with probability 1/k, each row
+     * joining the cell whose seed reaches it first, the smaller seed on a tie, at
+     * most 64 levels), and mcmi_spai of a whole single-matrix record set runs them
+     * cell by cell, so rows that are close in the graph run together on one XCD and
+     * share its L2. Pays off for matrices with locality (PDE discretisations); costs
+     * about one pass over B per level. Ignored by batched record sets. */
+    int64_t order_cell;
+    int64_t reserved; /* must be 0 */
 } mcmi_cdf_opts;
 
 /* mcmi_build_cdf with the pre-pass of `opts` (NULL: none). The augmentation adds
@@ -164,6 +174,11 @@ mcmi_status mcmi_build_cdf_ex(const mcmi_csr_in *B, const mcmi_cdf_opts *opts, m
 /* What the pre-pass did: ||B||_inf (0 without augmentation), the reduction cut on
  * |c| (0 without reduction) and the number of entries of C it removed. */
 mcmi_status mcmi_cdf_prep_info(const mcmi_cdf *cdf, double *norm_b, double *drop_thr, int64_t *dropped);
+
+/* The row schedule of a record set built with order_cell > 0: n row indices (a
+ * permutation of [0, n)) copied to order_host; synchronises the stream. Fails
+ * with MCMI_ERR_ARG when the set has no such schedule. */
+mcmi_status mcmi_cdf_order(const mcmi_cdf *cdf, int32_t *order_host, void *stream);
 
 /* Records of `count` matrices in one block-diagonal row space (the batched
  * launch): matrix k occupies rows [base_k, base_k + n_k) and its columns are

@@ -14,7 +14,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libmcmi.so")
-SOURCES = ["cdf.hip", "walk.hip", "walk_block.hip", "learn.hip", "mlp.hip", "plan.hip", "probe.hip", "krylov.hip", "alloc.hip", "scan.hip", "api.hip"]
+SOURCES = ["cdf.hip", "walk.hip", "walk_block.hip", "learn.hip", "mlp.hip", "plan.hip", "probe.hip", "krylov.hip", "alloc.hip", "order.hip", "scan.hip", "api.hip"]
 ARCH = os.environ.get("MCMI_ARCH", "gfx950")
 
 

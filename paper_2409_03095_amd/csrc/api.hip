@@ -283,6 +283,8 @@ extern "C" mcmi_status mcmi_spai(const mcmi_cdf *cdf, const mcmi_params *p, cons
         MCMI_HIP(hipMemcpyAsync(lpt.p, all.data(), all.size() * sizeof(int32_t), hipMemcpyHostToDevice, s));
         MCMI_HIP(hipStreamSynchronize(s));
         task_map = lpt.as<int32_t>();
+    } else if (cdf->batch == 0 && !rows_dev && cdf->order) {
+        task_map = cdf->order;  // locality schedule of the record set
     }
 
     int64_t nnz = 0;

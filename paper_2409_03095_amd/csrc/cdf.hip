@@ -344,8 +344,11 @@ extern "C" mcmi_status mcmi_build_cdf_ex(const mcmi_csr_in *B, const mcmi_cdf_op
     if (!B || !out) return fail(MCMI_ERR_ARG, "mcmi_build_cdf: null argument");
     const double alpha = opts ? opts->alpha : 0.0;
     const double drop_frac = opts ? opts->drop_frac : 0.0;
+    const int64_t order_cell = opts ? opts->order_cell : 0;
     if (!(alpha >= 0.0) || !(alpha < 1e300) || !(drop_frac >= 0.0) || !(drop_frac < 1.0))
         return fail(MCMI_ERR_ARG, "mcmi_build_cdf_ex: need alpha >= 0 and 0 <= drop_frac < 1");
+    if (order_cell < 0 || (opts && opts->reserved != 0))
+        return fail(MCMI_ERR_ARG, "mcmi_build_cdf_ex: need order_cell >= 0 and reserved == 0");
     if (B->n <= 0 || B->n >= (int64_t)INT32_MAX || B->nnz < (alpha > 0.0 ? 0 : B->n) || !B->row_ptr_dev ||
         !B->col_dev || !B->val_dev)
         return fail(MCMI_ERR_ARG, "mcmi_build_cdf: need 0 < n < 2^31, nnz >= n (or alpha > 0) and device pointers");
@@ -419,6 +422,11 @@ extern "C" mcmi_status mcmi_build_cdf_ex(const mcmi_csr_in *B, const mcmi_cdf_op
     TRY(count_pass(nullptr));
     if (hflags & kFlagCsr) return bail(MCMI_ERR_CSR, "mcmi_build_cdf: invalid CSR (row_ptr, column range or order)");
     if (hflags & kFlagZeroDiag) return bail(MCMI_ERR_ZERO_DIAG, "mcmi_build_cdf: missing or zero diagonal");
+    // row schedule (optional), on the pattern of B now that it is validated
+    if (order_cell > 0) {
+        TRY(dev_alloc((void **)&cdf->order, n * sizeof(int32_t), s));
+        TRY(build_locality_order(n, B->row_ptr_dev, B->col_dev, order_cell, cdf->order, s));
+    }
     // matrix reduction (optional): the cut is the key of rank K among the |c|
     const unsigned long long *cut = nullptr;
     if (drop_frac > 0.0 && htot[1] > 0) {
@@ -480,6 +488,15 @@ extern "C" mcmi_status mcmi_cdf_prep_info(const mcmi_cdf *cdf, double *norm_b, d
     if (norm_b) *norm_b = cdf->norm_b;
     if (drop_thr) *drop_thr = cdf->drop_thr;
     if (dropped) *dropped = cdf->dropped;
+    return MCMI_OK;
+}
+
+extern "C" mcmi_status mcmi_cdf_order(const mcmi_cdf *cdf, int32_t *order_host, void *stream) {
+    if (!cdf || !order_host) return fail(MCMI_ERR_ARG, "mcmi_cdf_order: null argument");
+    if (!cdf->order) return fail(MCMI_ERR_ARG, "mcmi_cdf_order: the record set was built without a row schedule");
+    hipStream_t s = (hipStream_t)stream;
+    MCMI_HIP(hipMemcpyAsync(order_host, cdf->order, (size_t)cdf->n * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    MCMI_HIP(hipStreamSynchronize(s));
     return MCMI_OK;
 }
 
@@ -665,5 +682,6 @@ extern "C" void mcmi_cdf_free(mcmi_cdf *cdf) {
     dev_release_idle(cdf->roff);
     dev_release_idle(cdf->diag);
     dev_release_idle(cdf->mrow);
+    dev_release_idle(cdf->order);
     delete cdf;
 }

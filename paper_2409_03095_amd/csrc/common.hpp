@@ -167,6 +167,9 @@ namespace mcmi {
 hipError_t dev_alloc(void **p, size_t bytes, hipStream_t s);
 void dev_release(void *p, hipStream_t s);
 void dev_release_idle(void *p);
+// Locality order of the rows (order.hip): a permutation of [0, n) in `order`.
+hipError_t build_locality_order(int64_t n, const int64_t *row_ptr, const int32_t *col, int64_t cell, int32_t *order,
+                                hipStream_t s);
 }  // namespace mcmi
 
 // The opaque record set.
@@ -183,6 +186,7 @@ struct mcmi_cdf {
     uint32_t *roff = nullptr;      // n: record offset (64-byte units) of each row
     double *diag = nullptr;        // n: b_ii
     uint32_t *mrow = nullptr;      // n: entries of each row of C
+    int32_t *order = nullptr;      // n: locality order of the rows (null: natural order)
     // batched record sets (several matrices, block-diagonal row space)
     int32_t batch = 0;                   // number of matrices (0: a single matrix)
     int32_t *row_mat = nullptr;          // n: matrix of each row

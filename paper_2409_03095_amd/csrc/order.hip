@@ -1,0 +1,128 @@
+// Row schedule with locality (an execution order of the rows; the estimate of
+// every row is the same in any order).
+//
+// Chains started at rows that are close in the graph of B visit overlapping sets
+// of records, so the walk kernels find more of their buckets in the XCD's L2 when
+// such rows run at the same time on the same XCD (each XCD takes a contiguous
+// slice of the task list). The rows are grouped into cells of about `cell` rows
+// by a multi-source breadth-first search on the pattern of B: the seeds are the
+// rows whose hash falls below 2^32 / cell, and at each level a row without a cell
+// joins the cell with the smallest seed among its neighbours that already have
+// one. Rows that no seed reaches within kMaxGrow levels are cells of their own.
+// The order lists the rows by (seed, row), which a stable radix sort on the seed
+// gives directly.
+#include <hipcub/hipcub.hpp>
+
+#include "common.hpp"
+
+namespace mcmi {
+namespace {
+
+constexpr uint32_t kUnset = 0xFFFFFFFFu;
+constexpr int kMaxGrow = 64;
+
+__device__ __forceinline__ uint32_t mix32(uint32_t x) {
+    // MurmurHash3's 32-bit finaliser
+    x ^= x >> 16;
+    x *= 0x85EBCA6Bu;
+    x ^= x >> 13;
+    x *= 0xC2B2AE35u;
+    x ^= x >> 16;
+    return x;
+}
+
+__global__ void __launch_bounds__(256) k_seed(int64_t n, uint32_t thr, uint32_t *lab, uint32_t *changed) {
+    const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    if (gid < kMaxGrow) changed[gid] = 0u;
+    for (int64_t r = gid; r < n; r += stride) lab[r] = mix32((uint32_t)r ^ 0x6A09E667u) < thr ? (uint32_t)r : kUnset;
+}
+
+// One level of the search, eight lanes per row. A level runs only if the one
+// before it labelled a row; when a level labels nothing, its output equals its
+// input, so after the search both buffers hold the final labels (or, if all
+// kMaxGrow levels ran, the buffer the last level wrote).
+__global__ void __launch_bounds__(256) k_grow(int64_t n, const int64_t *__restrict__ rp, const int32_t *__restrict__ col,
+                                              const uint32_t *__restrict__ lin, uint32_t *__restrict__ lout,
+                                              uint32_t *changed, int level) {
+    if (level > 0 && changed[level - 1] == 0u) return;
+    const int sub = threadIdx.x & 7;
+    const int64_t groups = ((int64_t)gridDim.x * blockDim.x) >> 3;
+    bool any = false;
+    for (int64_t r = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 3; r < n; r += groups) {
+        uint32_t v = lin[r];
+        if (v == kUnset) {  // uniform over the row's eight lanes
+            uint32_t m = kUnset;
+            const int64_t e = rp[r + 1];
+            for (int64_t k = rp[r] + sub; k < e; k += 8) m = min(m, lin[col[k]]);
+            m = min(m, (uint32_t)__shfl_xor((int)m, 1, 8));
+            m = min(m, (uint32_t)__shfl_xor((int)m, 2, 8));
+            m = min(m, (uint32_t)__shfl_xor((int)m, 4, 8));
+            v = m;
+            any |= m != kUnset;
+        }
+        if (sub == 0) lout[r] = v;
+    }
+    if (__any(any) && (threadIdx.x & 63) == 0) changed[level] = 1u;
+}
+
+__global__ void __launch_bounds__(256) k_order_keys(int64_t n, uint32_t *lab, int32_t *idx) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < n; r += stride) {
+        const uint32_t v = lab[r];
+        lab[r] = v == kUnset ? (uint32_t)r : v;
+        idx[r] = (int32_t)r;
+    }
+}
+
+// blocks for `lanes` threads per row, at most 65536 (grid-stride beyond)
+unsigned grid_rows(int64_t n, int lanes) {
+    int64_t b = (n * lanes + 255) / 256;
+    if (b < 1) b = 1;
+    if (b > 65536) b = 65536;
+    return (unsigned)b;
+}
+
+}  // namespace
+
+hipError_t build_locality_order(int64_t n, const int64_t *row_ptr, const int32_t *col, int64_t cell, int32_t *order,
+                                hipStream_t s) {
+    uint32_t *lab0 = nullptr, *lab1 = nullptr, *changed = nullptr;
+    int32_t *idx = nullptr;
+    void *tmp = nullptr;
+    size_t tmp_bytes = 0;
+    int end_bit = 1;
+    while (end_bit < 32 && ((uint64_t)(n - 1) >> end_bit) != 0) ++end_bit;
+    hipError_t e = hipcub::DeviceRadixSort::SortPairs(nullptr, tmp_bytes, (const uint32_t *)nullptr, (uint32_t *)nullptr,
+                                                      (const int32_t *)nullptr, (int32_t *)nullptr, (int)n, 0, end_bit, s);
+    if (e == hipSuccess) e = dev_alloc((void **)&lab0, (size_t)n * 4, s);
+    if (e == hipSuccess) e = dev_alloc((void **)&lab1, (size_t)n * 4, s);
+    if (e == hipSuccess) e = dev_alloc((void **)&idx, (size_t)n * 4, s);
+    if (e == hipSuccess) e = dev_alloc((void **)&changed, kMaxGrow * 4, s);
+    if (e == hipSuccess) e = dev_alloc(&tmp, tmp_bytes > 0 ? tmp_bytes : 16, s);
+    if (e == hipSuccess) {
+        const double p = 1.0 / (double)(cell > 1 ? cell : 1);
+        const uint32_t thr = p >= 1.0 ? 0xFFFFFFFFu : (uint32_t)(p * 4294967296.0);
+        k_seed<<<grid_rows(n, 1), 256, 0, s>>>(n, thr, lab0, changed);
+        e = hipGetLastError();
+        for (int level = 0; e == hipSuccess && level < kMaxGrow; ++level) {
+            const bool even = (level & 1) == 0;
+            k_grow<<<grid_rows(n, 8), 256, 0, s>>>(n, row_ptr, col, even ? lab0 : lab1, even ? lab1 : lab0, changed,
+                                                   level);
+            e = hipGetLastError();
+        }
+    }
+    // kMaxGrow is even: the last level that can run writes lab0
+    if (e == hipSuccess) {
+        k_order_keys<<<grid_rows(n, 1), 256, 0, s>>>(n, lab0, idx);
+        e = hipGetLastError();
+    }
+    if (e == hipSuccess)
+        e = hipcub::DeviceRadixSort::SortPairs(tmp, tmp_bytes, (const uint32_t *)lab0, lab1, (const int32_t *)idx, order,
+                                               (int)n, 0, end_bit, s);
+    for (void *t : {(void *)lab0, (void *)lab1, (void *)idx, (void *)changed, tmp})
+        if (t) dev_release(t, s);
+    return e;
+}
+
+}  // namespace mcmi

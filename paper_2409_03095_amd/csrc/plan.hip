@@ -299,6 +299,7 @@ extern "C" mcmi_status mcmi_plan_create(const mcmi_cdf *cdf, const mcmi_params *
     a.roff = cdf->roff;
     a.diag = cdf->diag;
     a.n_tasks = pl->n;
+    a.task_map = cdf->batch == 0 ? cdf->order : nullptr;  // locality schedule, if the set has one
     a.chains_per_row = chains_per_row_dev;
     a.chains = p->chains;
     a.keys_dev = (const uint32_t *)(ctrl + 96);

@@ -42,7 +42,8 @@ class CsrIn(ctypes.Structure):
 
 
 class CdfOpts(ctypes.Structure):
-    _fields_ = [("alpha", ctypes.c_double), ("drop_frac", ctypes.c_double), ("reserved", ctypes.c_int64 * 2)]
+    _fields_ = [("alpha", ctypes.c_double), ("drop_frac", ctypes.c_double), ("order_cell", ctypes.c_int64),
+                ("reserved", ctypes.c_int64)]
 
 
 class SolveStats(ctypes.Structure):
@@ -79,6 +80,7 @@ _sig = {
     "mcmi_build_cdf_ex": [_P(CsrIn), _P(CdfOpts), _P(_v), _v],
     "mcmi_bicgstab": [_P(CsrIn), _P(CsrOut), _v, _v, ctypes.c_double, ctypes.c_int32, _P(SolveStats), _v],
     "mcmi_cdf_prep_info": [_v, _P(ctypes.c_double), _P(ctypes.c_double), _P(ctypes.c_int64)],
+    "mcmi_cdf_order": [_v, _v, _v],
     "mcmi_cdf_info": [_v, _P(ctypes.c_int64), _P(ctypes.c_int64), _P(ctypes.c_double), _P(ctypes.c_uint64)],
     "mcmi_cdf_download": [_v, _v, _v, _v, _v],
     "mcmi_build_cdf_batched": [_P(CsrIn), ctypes.c_int32, _P(_v), _v],
@@ -122,7 +124,7 @@ _lib.mcmi_csr_free.restype = None
 _lib.mcmi_last_error.restype = ctypes.c_char_p
 _lib.mcmi_version.restype = ctypes.c_char_p
 
-EXPORTED = ["mcmi_cache_trim", "mcmi_bicgstab", "mcmi_build_cdf", "mcmi_build_cdf_ex", "mcmi_cdf_prep_info", "mcmi_cdf_info", "mcmi_cdf_download", "mcmi_spai", "mcmi_apply",
+EXPORTED = ["mcmi_cache_trim", "mcmi_bicgstab", "mcmi_build_cdf", "mcmi_build_cdf_ex", "mcmi_cdf_prep_info", "mcmi_cdf_order", "mcmi_cdf_info", "mcmi_cdf_download", "mcmi_spai", "mcmi_apply",
             "mcmi_csr_copy", "mcmi_cdf_free", "mcmi_csr_free", "mcmi_last_error", "mcmi_version",
             "mcmi_row_features", "mcmi_pilot_variance", "mcmi_mlp_create", "mcmi_mlp_free",
             "mcmi_mlp_set_params", "mcmi_mlp_get_params", "mcmi_mlp_set_adam_state", "mcmi_mlp_fit_normalization",
@@ -179,13 +181,13 @@ class Cdf:
     """Sampling records of C = I - D^-1 B (mcmi_build_cdf), or of several matrices
     in one block-diagonal row space (Cdf.batched -> mcmi_build_cdf_batched)."""
 
-    def __init__(self, B: DeviceCsr = None, stream=None, _batch=None, alpha=0.0, drop_frac=0.0):
+    def __init__(self, B: DeviceCsr = None, stream=None, _batch=None, alpha=0.0, drop_frac=0.0, order_cell=0):
         self._h = ctypes.c_void_p()
         self._B = B if B is not None else _batch
         if _batch is None:
             s = B._struct()
-            if alpha or drop_frac:
-                opts = CdfOpts(float(alpha), float(drop_frac), (ctypes.c_int64 * 2)(0, 0))
+            if alpha or drop_frac or order_cell:
+                opts = CdfOpts(float(alpha), float(drop_frac), int(order_cell), 0)
                 _check(_lib.mcmi_build_cdf_ex(ctypes.byref(s), ctypes.byref(opts), ctypes.byref(self._h),
                                               _stream(stream)))
             else:
@@ -204,6 +206,12 @@ class Cdf:
         nb, cut, nd = ctypes.c_double(), ctypes.c_double(), ctypes.c_int64()
         _check(_lib.mcmi_cdf_prep_info(self._h, ctypes.byref(nb), ctypes.byref(cut), ctypes.byref(nd)))
         return nb.value, cut.value, nd.value
+
+    def order(self, stream=None):
+        """mcmi_cdf_order: the row schedule (int32 permutation of [0, n))."""
+        out = np.zeros(self.n, dtype=np.int32)
+        _check(_lib.mcmi_cdf_order(self._h, out.ctypes.data_as(_v), _stream(stream)))
+        return out
 
     @staticmethod
     def batched(mats, stream=None):
