@@ -24,8 +24,8 @@ hipError_t collect_failed(int64_t n_slots, const int64_t *row_start, const uint3
                           unsigned long long *ctr, hipStream_t s);
 hipError_t validate_rows(const int32_t *rows, int64_t n_rows, const int32_t *cpr, int64_t n, uint32_t *bad,
                          hipStream_t s);
-hipError_t spmv(int64_t n, const int64_t *rp, const int32_t *ci, const double *v, const double *x, double *y,
-                hipStream_t s);
+hipError_t spmv(int64_t n, int64_t nnz, const int64_t *rp, const int32_t *ci, const double *v, const double *x,
+                double *y, hipStream_t s);
 
 static thread_local std::string g_last_error;
 
@@ -474,7 +474,7 @@ extern "C" mcmi_status mcmi_apply(const mcmi_csr_out *M, int64_t n_cols, const d
                                   void *stream) {
     if (!M || !x_dev || !y_dev || n_cols < 1) return fail(MCMI_ERR_ARG, "mcmi_apply: bad argument");
     if (M->n < 0 || (M->n > 0 && !M->row_ptr_dev)) return fail(MCMI_ERR_ARG, "mcmi_apply: bad M");
-    MCMI_HIP(spmv(M->n, M->row_ptr_dev, M->col_dev, M->val_dev, x_dev, y_dev, (hipStream_t)stream));
+    MCMI_HIP(spmv(M->n, M->nnz, M->row_ptr_dev, M->col_dev, M->val_dev, x_dev, y_dev, (hipStream_t)stream));
     return MCMI_OK;
 }
 

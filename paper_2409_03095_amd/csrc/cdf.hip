@@ -29,6 +29,49 @@ __device__ __forceinline__ bool keep_c(double c, const unsigned long long *cut) 
     return c != 0.0 && (!cut || (unsigned long long)__double_as_longlong(fabs(c)) >= *cut);
 }
 
+// Groups of G lanes (G divides 64), each owning one row at a time: reductions,
+// scans and broadcasts stay inside the group; a ballot is the wave's ballot
+// masked to the group's lanes (so mask_rank counts the group's lanes below).
+template <int G>
+struct Group {
+    int sub;        // lane inside the group
+    uint64_t mask;  // the group's lanes in a wave ballot
+    __device__ __forceinline__ Group() {
+        const int lane = threadIdx.x & 63;
+        sub = lane & (G - 1);
+        mask = G == 64 ? ~0ull : (((1ull << (G & 63)) - 1ull) << (lane & ~(G - 1)));
+    }
+    __device__ __forceinline__ uint64_t ballot(bool p) const { return __ballot(p) & mask; }
+    template <typename T>
+    __device__ __forceinline__ T sum(T v) const {
+#pragma unroll
+        for (int off = G / 2; off > 0; off >>= 1) v += __shfl_xor(v, off, G);
+        return v;
+    }
+    template <typename T>
+    __device__ __forceinline__ T max(T v) const {
+#pragma unroll
+        for (int off = G / 2; off > 0; off >>= 1) {
+            T o = __shfl_xor(v, off, G);
+            v = o > v ? o : v;
+        }
+        return v;
+    }
+    template <typename T>
+    __device__ __forceinline__ T incl_scan(T v) const {
+#pragma unroll
+        for (int off = 1; off < G; off <<= 1) {
+            T o = __shfl_up(v, off, G);
+            if (sub >= off) v += o;
+        }
+        return v;
+    }
+    template <typename T>
+    __device__ __forceinline__ T bcast(T v, int src) const { return __shfl(v, src, G); }
+    // lane (inside the group) of the lowest set bit of a group ballot
+    __device__ __forceinline__ int first(uint64_t b) const { return (__builtin_ctzll(b)) & (G - 1); }
+};
+
 // ||B||_inf for the augmented splitting: each thread sums one row's |b_ij| in
 // column order (one IEEE add at a time, so the sums are those of a sequential
 // loop), the maximum is an integer max on the bits of the non-negative sums.
@@ -101,19 +144,21 @@ __global__ void k_radix_pick(unsigned long long *sel, unsigned long long *hist, 
 }
 
 // Validate row r of B, find its diagonal and count its nonzero off-diagonals.
+template <int G>
 __global__ void __launch_bounds__(256) k_count(int64_t n, int64_t nnz, const int64_t *__restrict__ rp,
                                                const int32_t *__restrict__ ci, const double *__restrict__ v,
                                                double aug, const unsigned long long *__restrict__ cut,
                                                uint32_t *__restrict__ mrow, uint32_t *__restrict__ units,
                                                double *__restrict__ diag, uint32_t *__restrict__ flags) {
-    const int lane = threadIdx.x & 63;
-    const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
-    const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
-    if (wave == 0 && lane == 0 && (rp[0] != 0 || rp[n] != nnz)) atomicOr(flags, kFlagCsr);
-    for (int64_t r = wave; r < n; r += nwaves) {
+    const Group<G> g;
+    const int sub = g.sub;
+    const int64_t grp = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / G;
+    const int64_t ngrp = ((int64_t)gridDim.x * blockDim.x) / G;
+    if (grp == 0 && sub == 0 && (rp[0] != 0 || rp[n] != nnz)) atomicOr(flags, kFlagCsr);
+    for (int64_t r = grp; r < n; r += ngrp) {
         const int64_t b = rp[r], e = rp[r + 1];
         if (b < 0 || e < b || e > nnz) {
-            if (lane == 0) {
+            if (sub == 0) {
                 atomicOr(flags, kFlagCsr);
                 mrow[r] = 0;
                 units[r] = record_units(0);
@@ -123,7 +168,7 @@ __global__ void __launch_bounds__(256) k_count(int64_t n, int64_t nnz, const int
         }
         bool bad = false, found = false;
         double dv = 0.0;
-        for (int64_t k = b + lane; k < e; k += 64) {
+        for (int64_t k = b + sub; k < e; k += G) {
             const int32_t c = ci[k];
             bad |= (c < 0) || ((int64_t)c >= n) || (k > b && ci[k - 1] >= c);
             if ((int64_t)c == r) {
@@ -131,18 +176,19 @@ __global__ void __launch_bounds__(256) k_count(int64_t n, int64_t nnz, const int
                 dv = v[k];
             }
         }
-        const uint64_t fb = ballot(found);
-        const uint64_t bb = ballot(bad);
-        double d = fb ? __shfl(dv, __builtin_ctzll(fb), 64) : 0.0;
+        const uint64_t fb = g.ballot(found);
+        const uint64_t bb = g.ballot(bad);
+        double d = g.bcast(dv, fb ? g.first(fb) : 0);
+        if (!fb) d = 0.0;
         if (aug > 0.0) d = d + (d < 0.0 ? -aug : aug);  // augmented splitting (a missing diagonal is 0)
         // entries of C: off-diagonals whose quotient (-b_ij) / b_ii is nonzero
         // and not below the reduction cut
         uint32_t cnt = 0;
         if (d != 0.0)
-            for (int64_t k = b + lane; k < e; k += 64)
+            for (int64_t k = b + sub; k < e; k += G)
                 if ((int64_t)ci[k] != r && keep_c((-v[k]) / d, cut)) ++cnt;
-        cnt = wave_sum(cnt);
-        if (lane == 0) {
+        cnt = g.sum(cnt);
+        if (sub == 0) {
             if (bb) atomicOr(flags, kFlagCsr);
             if (d == 0.0) atomicOr(flags, kFlagZeroDiag);
             mrow[r] = cnt;
@@ -154,6 +200,7 @@ __global__ void __launch_bounds__(256) k_count(int64_t n, int64_t nnz, const int
 
 // Write each row's header and its sorted {cum, target} nodes into `sorted`
 // (C-row order, at cptr[r]), and the row's record offset as 32 bits.
+template <int G>
 __global__ void __launch_bounds__(256) k_fill(int64_t n, const int64_t *__restrict__ rp,
                                               const int32_t *__restrict__ ci, const double *__restrict__ v,
                                               const double *__restrict__ diag, const uint32_t *__restrict__ mrow,
@@ -161,19 +208,20 @@ __global__ void __launch_bounds__(256) k_fill(int64_t n, const int64_t *__restri
                                               const unsigned long long *__restrict__ cut,
                                               uint32_t *__restrict__ roff32, uint32_t *__restrict__ rec,
                                               uint2 *__restrict__ sorted, unsigned long long *__restrict__ norm_bits) {
-    const int lane = threadIdx.x & 63;
-    const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
-    const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
+    const Group<G> g;
+    const int sub = g.sub;
+    const int64_t grp = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / G;
+    const int64_t ngrp = ((int64_t)gridDim.x * blockDim.x) / G;
     double best = 0.0;  // the wave's largest Shat (one atomic per wave, not per row)
-    for (int64_t r = wave; r < n; r += nwaves) {
+    for (int64_t r = grp; r < n; r += ngrp) {
         const int64_t b = rp[r], e = rp[r + 1];
         const uint32_t m = mrow[r];
         const double d = diag[r];
         const uint32_t off = (uint32_t)roff64[r];
         uint32_t *hdr = rec + (size_t)off * kUnitWords;
-        if (lane == 0) roff32[r] = off;
+        if (sub == 0) roff32[r] = off;
         if (m == 0) {
-            if (lane == 0) {
+            if (sub == 0) {
                 hdr[0] = (uint32_t)r;
                 hdr[1] = 0u;
                 hdr[2] = 0u;
@@ -185,7 +233,7 @@ __global__ void __launch_bounds__(256) k_fill(int64_t n, const int64_t *__restri
         }
         // a_max over the row's entries of C (order-free)
         double amax = 0.0;
-        for (int64_t k = b + lane; k < e; k += 64) {
+        for (int64_t k = b + sub; k < e; k += G) {
             const int32_t c = ci[k];
             if ((int64_t)c != r) {
                 const double cv = (-v[k]) / d;
@@ -193,13 +241,13 @@ __global__ void __launch_bounds__(256) k_fill(int64_t n, const int64_t *__restri
                 amax = a > amax ? a : amax;
             }
         }
-        amax = wave_max(amax);
+        amax = g.max(amax);
         const int q = 31 - ceil_log2_u32(m);
-        // quantize and scan in column order, 64 entries at a time
+        // quantize and scan in column order, G entries at a time
         uint32_t carry = 0, placed = 0;
         const int64_t base = cptr[r];
-        for (int64_t k0 = b; k0 < e; k0 += 64) {
-            const int64_t k = k0 + lane;
+        for (int64_t k0 = b; k0 < e; k0 += G) {
+            const int64_t k = k0 + sub;
             bool valid = false;
             uint32_t w = 0, tgt = 0;
             if (k < e) {
@@ -214,16 +262,16 @@ __global__ void __launch_bounds__(256) k_fill(int64_t n, const int64_t *__restri
                     }
                 }
             }
-            const uint64_t vm = ballot(valid);
-            const uint32_t incl = wave_incl_scan(w);
+            const uint64_t vm = g.ballot(valid);
+            const uint32_t incl = g.incl_scan(w);
             if (valid) {
                 const uint32_t pos = placed + (uint32_t)mask_rank(vm);
                 sorted[base + pos] = make_uint2(carry + incl, tgt);
             }
-            carry += __shfl(incl, 63, 64);
+            carry += g.bcast(incl, G - 1);
             placed += (uint32_t)__popcll(vm);
         }
-        if (lane == 0) {
+        if (sub == 0) {
             const double shat = ldexp(amax * (double)carry, -q);
             hdr[0] = (uint32_t)r;
             hdr[1] = m;
@@ -234,47 +282,44 @@ __global__ void __launch_bounds__(256) k_fill(int64_t n, const int64_t *__restri
             best = shat > best ? shat : best;
         }
     }
-    if (lane == 0 && best > 0.0) atomicMax(norm_bits, (unsigned long long)__double_as_longlong(best));
+    best = wave_max(best);
+    if ((threadIdx.x & 63) == 0 && best > 0.0) atomicMax(norm_bits, (unsigned long long)__double_as_longlong(best));
 }
 
 // Alias table of each row (Walker's method, Vose's exact-integer construction;
-// one thread per row, as the construction is sequential): masses q_k = m w_k
+// one lane per row, as the construction is sequential): masses q_k = m w_k
 // (w_k from the row's cums), bucket capacity W. Entries go, in column order, on
 // a `small` (q < W) or `large` stack; while both are non-empty the tops s and l
 // are popped, bucket s keeps T_s = q_s and gives W - q_s to l (A_s = l,
 // q_l -= W - q_s), and l goes back on small if q_l < W, else on large. Leftover
 // buckets keep all W units (T = W, A = self). Every entry's final q is its
 // threshold. Both stacks live in one scratch array of the row's length (small
-// grows up from the front, large down from the back), q and A in two more; one
-// thread per row, the scratch in LDS for rows of up to kAliasLds entries (in the
-// row's slice of a global scratch otherwise).
-// Each bucket then receives copies of the headers of the two rows it can lead
-// to (written by k_fill, a previous launch).
-constexpr int kAliasLds = 32;  // rows up to this long keep their scratch in LDS
+// grows up from the front, large down from the back), q and A in two more; the
+// scratch is in LDS for rows of up to kAliasLds entries (in the row's slice of a
+// global scratch otherwise). The thresholds and alias indices end in thr_g and
+// ali_g, indexed like the entries of C.
+constexpr int kAliasLds = 32;    // rows up to this long keep their scratch in LDS
+constexpr int kAliasPitch = 65;  // LDS words per entry index: the lanes of a wave hit distinct banks
 
 __global__ void __launch_bounds__(64) k_alias(int64_t n, const uint32_t *__restrict__ mrow,
-                                              const uint32_t *__restrict__ roff32, const int64_t *__restrict__ cptr,
-                                              const uint2 *__restrict__ sorted, uint32_t *__restrict__ qs_g,
-                                              int32_t *__restrict__ stk_g, int32_t *__restrict__ alias_g,
-                                              uint32_t *__restrict__ rec) {
-    // per-lane scratch, interleaved so that the lanes of a wave hit distinct banks
-    __shared__ uint32_t q_l[kAliasLds * 64];
-    __shared__ int32_t st_l[kAliasLds * 64];
-    __shared__ int32_t al_l[kAliasLds * 64];
+                                              const int64_t *__restrict__ cptr, const uint2 *__restrict__ sorted,
+                                              uint32_t *__restrict__ thr_g, int32_t *__restrict__ stk_g,
+                                              int32_t *__restrict__ ali_g) {
+    __shared__ uint32_t q_l[kAliasLds * kAliasPitch];
+    __shared__ int32_t st_l[kAliasLds * kAliasPitch];
+    __shared__ int32_t al_l[kAliasLds * kAliasPitch];
     const int lane = threadIdx.x;
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < n; r += stride) {
+    for (int64_t r = (int64_t)blockIdx.x * blockDim.x + lane; r < n; r += stride) {
         const uint32_t m = mrow[r];
         if (m == 0) continue;
         const int64_t base = cptr[r];
-        const uint32_t W = sorted[base + m - 1].x;
-        // scratch element k of this lane: LDS for short rows, the row's own slice of
-        // the global scratch (indexed like C) otherwise
         const bool lds = m <= (uint32_t)kAliasLds;
-        uint32_t *q = lds ? q_l + lane : qs_g + base;
+        uint32_t *q = lds ? q_l + lane : thr_g + base;
         int32_t *st = lds ? st_l + lane : stk_g + base;
-        int32_t *al = lds ? al_l + lane : alias_g + base;
-        const int sc = lds ? 64 : 1;
+        int32_t *al = lds ? al_l + lane : ali_g + base;
+        const int sc = lds ? kAliasPitch : 1;
+        const uint32_t W = sorted[base + m - 1].x;
         int ns = 0, nl = 0;
         uint32_t prev = 0;
         for (uint32_t k = 0; k < m; ++k) {
@@ -299,20 +344,87 @@ __global__ void __launch_bounds__(64) k_alias(int64_t n, const uint32_t *__restr
             else
                 st[(m - 1 - nl++) * sc] = lg;
         }
-        uint32_t *ent = rec + ((size_t)roff32[r] + 1u) * kUnitWords;
-        prev = 0;
-        for (uint32_t k = 0; k < m; ++k) {
-            const uint2 own = sorted[base + k], other = sorted[base + al[k * sc]];
-            const uint4 *ho = (const uint4 *)(rec + (size_t)(own.y & ~kSignBit) * kUnitWords);
-            const uint4 *ha = (const uint4 *)(rec + (size_t)(other.y & ~kSignBit) * kUnitWords);
-            uint4 *e = (uint4 *)(ent + (size_t)k * kUnitWords);
-            const uint4 so = ho[1], sa = ha[1];
-            e[0] = make_uint4(q[k * sc], own.y, other.y, own.x - prev);
-            e[1] = ho[0];
-            e[2] = ha[0];
-            e[3] = make_uint4(so.x, so.y, sa.x, sa.y);
-            prev = own.x;
+        if (lds)
+            for (uint32_t k = 0; k < m; ++k) {
+                thr_g[base + k] = q[k * sc];
+                ali_g[base + k] = al[k * sc];
+            }
+    }
+}
+
+// The buckets: a wave takes 64 consecutive rows and writes their buckets as one
+// run, four lanes per 64-byte bucket and 64 buckets per pass (each store
+// instruction writes 16 buckets, nearly all consecutive in the records; the loads
+// of a lane's four buckets are issued together). Each bucket is {T_j, target_j,
+// target_{A_j}, w_j} followed by copies of the headers of the two rows it can
+// lead to (written by k_fill, a previous launch) and their Shat64.
+constexpr int kBucketSlots = 4;
+
+__global__ void __launch_bounds__(256) k_buckets(int64_t n, const uint32_t *__restrict__ mrow,
+                                                 const uint32_t *__restrict__ roff32, const int64_t *__restrict__ cptr,
+                                                 const uint2 *__restrict__ sorted, const uint32_t *__restrict__ thr_g,
+                                                 const int32_t *__restrict__ ali_g, uint32_t *__restrict__ rec) {
+    __shared__ uint32_t pm_s[4][65];
+    __shared__ int64_t pb_s[4][64];
+    __shared__ uint32_t po_s[4][64];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    uint32_t *pm = pm_s[wv];
+    int64_t *pb = pb_s[wv];
+    uint32_t *po = po_s[wv];
+    const int64_t wstride = (int64_t)gridDim.x * 4 * 64;
+    for (int64_t r0 = ((int64_t)blockIdx.x * 4 + wv) * 64; r0 < n; r0 += wstride) {
+        const int64_t r = r0 + lane;
+        const uint32_t m = r < n ? mrow[r] : 0u;
+        // the 64 rows' buckets as one run: row i owns [pm[i], pm[i + 1])
+        const uint32_t incl = wave_incl_scan(m);
+        pm[lane + 1] = incl;
+        if (lane == 0) pm[0] = 0u;
+        pb[lane] = r < n ? cptr[r] : 0;
+        po[lane] = r < n ? roff32[r] : 0u;
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        const uint32_t total = (uint32_t)__shfl((int)incl, 63, 64);
+        const int part = lane & 3;
+        int row[kBucketSlots];
+#pragma unroll
+        for (int j = 0; j < kBucketSlots; ++j) row[j] = 0;
+        for (uint32_t t0 = 0; t0 < total; t0 += 16 * kBucketSlots) {
+            uint4 v[kBucketSlots];
+            size_t dst[kBucketSlots];
+#pragma unroll
+            for (int j = 0; j < kBucketSlots; ++j) {
+                const uint32_t t = t0 + (uint32_t)(j * 16 + (lane >> 2));
+                dst[j] = ~(size_t)0;
+                if (t >= total) continue;
+                while (pm[row[j] + 1] <= t) ++row[j];
+                const int i = row[j];
+                const uint32_t k = t - pm[i];
+                const int64_t e = pb[i] + k;
+                const uint2 own = sorted[e];
+                if (part == 0) {
+                    const uint32_t prev = k > 0 ? sorted[e - 1].x : 0u;
+                    v[j] = make_uint4(thr_g[e], own.y, sorted[pb[i] + ali_g[e]].y, own.x - prev);
+                } else if (part == 1) {
+                    v[j] = *(const uint4 *)(rec + (size_t)(own.y & ~kSignBit) * kUnitWords);
+                } else if (part == 2) {
+                    v[j] = *(const uint4 *)(rec + (size_t)(sorted[pb[i] + ali_g[e]].y & ~kSignBit) * kUnitWords);
+                } else {
+                    const uint2 so = *(const uint2 *)(rec + (size_t)(own.y & ~kSignBit) * kUnitWords + 4);
+                    const uint2 sa =
+                        *(const uint2 *)(rec + (size_t)(sorted[pb[i] + ali_g[e]].y & ~kSignBit) * kUnitWords + 4);
+                    v[j] = make_uint4(so.x, so.y, sa.x, sa.y);
+                }
+                dst[j] = ((size_t)po[i] + 1u + k) * kUnitWords + (size_t)part * 4u;
+            }
+#pragma unroll
+            for (int j = 0; j < kBucketSlots; ++j)
+                if (dst[j] != ~(size_t)0) *(uint4 *)(rec + dst[j]) = v[j];
         }
+        // the row table is rewritten by the next batch only after every lane is done with it
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     }
 }
 
@@ -408,9 +520,19 @@ extern "C" mcmi_status mcmi_build_cdf_ex(const mcmi_csr_in *B, const mcmi_cdf_op
     }
     uint32_t hflags = 0;
     int64_t htot[2] = {0, 0};
+    // lanes per row in k_count and k_fill: about one lane per entry of an average row
+    const double per_row = (double)B->nnz / (double)n;
+    const int lanes = per_row <= 12.0 ? 16 : per_row <= 40.0 ? 32 : 64;
     auto count_pass = [&](const unsigned long long *cut) -> hipError_t {
-        k_count<<<grid, 256, 0, s>>>(n, B->nnz, B->row_ptr_dev, B->col_dev, B->val_dev, aug, cut, cdf->mrow, units,
-                                     cdf->diag, flags);
+        if (lanes == 16)
+            k_count<16><<<grid, 256, 0, s>>>(n, B->nnz, B->row_ptr_dev, B->col_dev, B->val_dev, aug, cut, cdf->mrow,
+                                             units, cdf->diag, flags);
+        else if (lanes == 32)
+            k_count<32><<<grid, 256, 0, s>>>(n, B->nnz, B->row_ptr_dev, B->col_dev, B->val_dev, aug, cut, cdf->mrow,
+                                             units, cdf->diag, flags);
+        else
+            k_count<64><<<grid, 256, 0, s>>>(n, B->nnz, B->row_ptr_dev, B->col_dev, B->val_dev, aug, cut, cdf->mrow,
+                                             units, cdf->diag, flags);
         hipError_t e = hipGetLastError();
         if (e == hipSuccess) e = scan_exclusive_u32_to_i64(units, roff64, n, totals + 0, tmp, s);
         if (e == hipSuccess) e = scan_exclusive_u32_to_i64(cdf->mrow, cptr, n, totals + 1, tmp, s);
@@ -458,16 +580,27 @@ extern "C" mcmi_status mcmi_build_cdf_ex(const mcmi_csr_in *B, const mcmi_cdf_op
     cdf->nnz_c = htot[1];
     TRY(dev_alloc((void **)&cdf->rec, (size_t)htot[0] * kUnitWords * 4u + 64u, s));
     TRY(dev_alloc((void **)&sorted, (size_t)(htot[1] > 0 ? htot[1] : 1) * sizeof(uint2), s));
-    k_fill<<<grid, 256, 0, s>>>(n, B->row_ptr_dev, B->col_dev, B->val_dev, cdf->diag, cdf->mrow, roff64, cptr,
-                                cut, cdf->roff, cdf->rec, sorted, norm_bits);
+    if (lanes == 16)
+        k_fill<16><<<grid, 256, 0, s>>>(n, B->row_ptr_dev, B->col_dev, B->val_dev, cdf->diag, cdf->mrow, roff64, cptr,
+                                        cut, cdf->roff, cdf->rec, sorted, norm_bits);
+    else if (lanes == 32)
+        k_fill<32><<<grid, 256, 0, s>>>(n, B->row_ptr_dev, B->col_dev, B->val_dev, cdf->diag, cdf->mrow, roff64, cptr,
+                                        cut, cdf->roff, cdf->rec, sorted, norm_bits);
+    else
+        k_fill<64><<<grid, 256, 0, s>>>(n, B->row_ptr_dev, B->col_dev, B->val_dev, cdf->diag, cdf->mrow, roff64, cptr,
+                                        cut, cdf->roff, cdf->rec, sorted, norm_bits);
     TRY(hipGetLastError());
     TRY(dev_alloc((void **)&qs, (size_t)(htot[1] > 0 ? htot[1] : 1) * sizeof(uint32_t), s));
     TRY(dev_alloc((void **)&stk, (size_t)(htot[1] > 0 ? 2 * htot[1] : 2) * sizeof(int32_t), s));
     {
         int64_t ab = (n + 63) / 64;
         if (ab > 32768) ab = 32768;
-        k_alias<<<(unsigned)ab, 64, 0, s>>>(n, cdf->mrow, cdf->roff, cptr, sorted, qs, stk,
-                                            stk + (htot[1] > 0 ? htot[1] : 1), cdf->rec);
+        int32_t *ali = stk + (htot[1] > 0 ? htot[1] : 1);
+        k_alias<<<(unsigned)ab, 64, 0, s>>>(n, cdf->mrow, cptr, sorted, qs, stk, ali);
+        TRY(hipGetLastError());
+        int64_t bb = (n + 255) / 256;
+        if (bb > 16384) bb = 16384;
+        k_buckets<<<(unsigned)bb, 256, 0, s>>>(n, cdf->mrow, cdf->roff, cptr, sorted, qs, ali, cdf->rec);
     }
     TRY(hipGetLastError());
     unsigned long long hnorm = 0;

@@ -16,8 +16,8 @@
 #include "common.hpp"
 
 namespace mcmi {
-hipError_t spmv(int64_t n, const int64_t *rp, const int32_t *ci, const double *v, const double *x, double *y,
-                hipStream_t s);
+hipError_t spmv(int64_t n, int64_t nnz, const int64_t *rp, const int32_t *ci, const double *v, const double *x,
+                double *y, hipStream_t s);
 
 namespace {
 
@@ -109,12 +109,12 @@ struct Solver {
         return hipStreamSynchronize(s);
     }
     hipError_t applyB(const double *x, double *y) {
-        return spmv(n, B->row_ptr_dev, B->col_dev, B->val_dev, x, y, s);
+        return spmv(n, B->nnz, B->row_ptr_dev, B->col_dev, B->val_dev, x, y, s);
     }
     // y = M x, or a copy without a preconditioner
     hipError_t applyM(const double *x, double *y) {
         if (!M) return hipMemcpyAsync(y, x, (size_t)n * sizeof(double), hipMemcpyDeviceToDevice, s);
-        return spmv(n, M->row_ptr_dev, M->col_dev, M->val_dev, x, y, s);
+        return spmv(n, M->nnz, M->row_ptr_dev, M->col_dev, M->val_dev, x, y, s);
     }
 };
 

@@ -75,11 +75,11 @@ __global__ void __launch_bounds__(256) k_order_keys(int64_t n, uint32_t *lab, in
     }
 }
 
-// blocks for `lanes` threads per row, at most 65536 (grid-stride beyond)
-unsigned grid_rows(int64_t n, int lanes) {
+// blocks for `lanes` threads per row, at most `cap` (grid-stride beyond)
+unsigned grid_rows(int64_t n, int lanes, int64_t cap) {
     int64_t b = (n * lanes + 255) / 256;
     if (b < 1) b = 1;
-    if (b > 65536) b = 65536;
+    if (b > cap) b = cap;
     return (unsigned)b;
 }
 
@@ -103,18 +103,19 @@ hipError_t build_locality_order(int64_t n, const int64_t *row_ptr, const int32_t
     if (e == hipSuccess) {
         const double p = 1.0 / (double)(cell > 1 ? cell : 1);
         const uint32_t thr = p >= 1.0 ? 0xFFFFFFFFu : (uint32_t)(p * 4294967296.0);
-        k_seed<<<grid_rows(n, 1), 256, 0, s>>>(n, thr, lab0, changed);
+        k_seed<<<grid_rows(n, 1, 65536), 256, 0, s>>>(n, thr, lab0, changed);
         e = hipGetLastError();
         for (int level = 0; e == hipSuccess && level < kMaxGrow; ++level) {
             const bool even = (level & 1) == 0;
-            k_grow<<<grid_rows(n, 8), 256, 0, s>>>(n, row_ptr, col, even ? lab0 : lab1, even ? lab1 : lab0, changed,
+            // a modest grid: the levels after the last one that labels a row return at once
+            k_grow<<<grid_rows(n, 8, 4096), 256, 0, s>>>(n, row_ptr, col, even ? lab0 : lab1, even ? lab1 : lab0, changed,
                                                    level);
             e = hipGetLastError();
         }
     }
     // kMaxGrow is even: the last level that can run writes lab0
     if (e == hipSuccess) {
-        k_order_keys<<<grid_rows(n, 1), 256, 0, s>>>(n, lab0, idx);
+        k_order_keys<<<grid_rows(n, 1, 65536), 256, 0, s>>>(n, lab0, idx);
         e = hipGetLastError();
     }
     if (e == hipSuccess)

@@ -182,32 +182,41 @@ hipError_t validate_rows(const int32_t *rows, int64_t n_rows, const int32_t *cpr
 }
 
 // ------------------------------------------------------------------ SpMV
-// y = M x, float64. A group of G lanes per row (G = 8: the rows of M hold tens
-// to hundreds of entries), strided partial sums then a butterfly reduction.
+// y = M x, float64. A group of G lanes per row (G from the average row length:
+// about one lane per entry, 8 to 64), strided partial sums then a butterfly
+// reduction inside the group; grid-stride over rows.
 template <int G>
 __global__ void __launch_bounds__(256) k_spmv(int64_t n, const int64_t *rp, const int32_t *ci, const double *v,
                                               const double *x, double *y) {
-    const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const int64_t row = gid / G;
-    const int sub = (int)(gid % G);
-    double acc = 0.0;
-    if (row < n) {
+    const int sub = threadIdx.x & (G - 1);
+    const int64_t groups = ((int64_t)gridDim.x * blockDim.x) / G;
+    for (int64_t row = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / G; row < n; row += groups) {
         const int64_t b = rp[row], e = rp[row + 1];
+        double acc = 0.0;
         for (int64_t k = b + sub; k < e; k += G) acc += v[k] * x[ci[k]];
-    }
 #pragma unroll
-    for (int off = G / 2; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
-    if (row < n && sub == 0) y[row] = acc;
+        for (int off = G / 2; off > 0; off >>= 1) acc += __shfl_xor(acc, off, G);
+        if (sub == 0) y[row] = acc;
+    }
 }
 
-hipError_t spmv(int64_t n, const int64_t *rp, const int32_t *ci, const double *v, const double *x, double *y,
-                hipStream_t s) {
-    if (n <= 0) return hipSuccess;
-    constexpr int G = 8;
-    const int64_t threads = n * G;
-    const int64_t blocks = (threads + 255) / 256;
+template <int G>
+hipError_t launch_spmv(int64_t n, const int64_t *rp, const int32_t *ci, const double *v, const double *x, double *y,
+                       hipStream_t s) {
+    int64_t blocks = (n * G + 255) / 256;
+    if (blocks > 65536) blocks = 65536;
     k_spmv<G><<<(unsigned)blocks, 256, 0, s>>>(n, rp, ci, v, x, y);
     return hipGetLastError();
+}
+
+hipError_t spmv(int64_t n, int64_t nnz, const int64_t *rp, const int32_t *ci, const double *v, const double *x,
+                double *y, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    const double per_row = (double)nnz / (double)n;
+    if (per_row < 12.0) return launch_spmv<8>(n, rp, ci, v, x, y, s);
+    if (per_row < 24.0) return launch_spmv<16>(n, rp, ci, v, x, y, s);
+    if (per_row < 96.0) return launch_spmv<32>(n, rp, ci, v, x, y, s);
+    return launch_spmv<64>(n, rp, ci, v, x, y, s);
 }
 
 }  // namespace mcmi
