@@ -288,14 +288,15 @@ def batched_main(args):
     devs = [mcmi.DeviceCsr.from_host(B) for B in mats]
     chains = args.chains if args.chains != 512 else 128
     p = mcmi.params(seed=0, chains=chains, delta=1e-4, eps=1e-3, walk_prec=args.prec)
+    cell = 0 if args.order_cell is None else args.order_cell
     for _ in range(args.warmup):
-        res = mcmi.spai(mcmi.Cdf.batched(devs), p)
+        res = mcmi.spai(mcmi.Cdf.batched(devs, order_cell=cell), p)
         del res
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     walk_ms, trans = [], 0
     for _ in range(args.steps):
-        cdf = mcmi.Cdf.batched(devs)
+        cdf = mcmi.Cdf.batched(devs, order_cell=cell)
         res = mcmi.spai(cdf, p)
         walk_ms.append(res.stats.ms_walk)
         trans += res.stats.transitions
@@ -320,7 +321,7 @@ def batched_main(args):
            "config": {"workload": "batched 256 x 3D 7-point convection-diffusion", "matrices": len(mats),
                       "rows": int(sum(m.n for m in mats)), "chains_per_row": chains,
                       "transitions_per_step": int(st.transitions), "nnz_M": int(last.nnz),
-                      "lanes_per_row": st.lanes_per_row, "hash_slots": st.hash_slots},
+                      "lanes_per_row": st.lanes_per_row, "hash_slots": st.hash_slots, "order_cell": cell},
            "walk_ms": float(np.mean(walk_ms)),
            "one_launch_per_matrix": {"seconds": single_s, "transitions": int(single_trans),
                                      "transitions_per_s": single_trans / single_s}}

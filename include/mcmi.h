@@ -189,6 +189,14 @@ mcmi_status mcmi_cdf_order(const mcmi_cdf *cdf, int32_t *order_host, void *strea
  * column must lie in [0, n_k)). Synchronises. */
 mcmi_status mcmi_build_cdf_batched(const mcmi_csr_in *Bs, int32_t count, mcmi_cdf **out, void *stream);
 
+/* mcmi_build_cdf_batched with a row schedule (opts->order_cell; alpha and
+ * drop_frac must be 0, as one norm or cut over the whole batch would couple the
+ * matrices). The cells never cross matrices, so the schedule lists each matrix's
+ * rows in its own slice; the batched launch then deals 64 consecutive positions
+ * of the schedule at a time. */
+mcmi_status mcmi_build_cdf_batched_ex(const mcmi_csr_in *Bs, int32_t count, const mcmi_cdf_opts *opts,
+                                      mcmi_cdf **out, void *stream);
+
 /* Number of matrices of a record set (0 for a single-matrix set), their first
  * rows (count + 1 values; for a single matrix {0, n}) and ||Chat_k||_inf. */
 mcmi_status mcmi_cdf_batch_info(const mcmi_cdf *cdf, int32_t *count, int64_t *row_base_host, double *norm_host);

@@ -24,6 +24,8 @@ hipError_t collect_failed(int64_t n_slots, const int64_t *row_start, const uint3
                           unsigned long long *ctr, hipStream_t s);
 hipError_t validate_rows(const int32_t *rows, int64_t n_rows, const int32_t *cpr, int64_t n, uint32_t *bad,
                          hipStream_t s);
+hipError_t expand_blocks(int64_t nblocks, const int32_t *start, const int32_t *cnt, const int64_t *pos,
+                         const int32_t *order, int32_t *out, hipStream_t s);
 hipError_t spmv(int64_t n, int64_t nnz, const int64_t *rp, const int32_t *ci, const double *v, const double *x,
                 double *y, hipStream_t s);
 
@@ -250,8 +252,9 @@ extern "C" mcmi_status mcmi_spai(const mcmi_cdf *cdf, const mcmi_params *p, cons
     }
 
     // batched record sets: longest-processing-time order. Per-row cost N (L_k + 1)
-    // with L_k the chain-length bound of matrix k; blocks of 64 consecutive rows in
-    // decreasing cost, dealt round-robin to the eight XCD queue slices.
+    // with L_k the chain-length bound of matrix k; blocks of 64 consecutive rows (of
+    // the set's schedule, if it has one) in decreasing cost, dealt round-robin to the
+    // eight XCD queue slices.
     DevBuf lpt;
     const int32_t *task_map = nullptr;
     if (cdf->batch > 0 && !rows_dev) {
@@ -267,21 +270,39 @@ extern "C" mcmi_status mcmi_spai(const mcmi_cdf *cdf, const mcmi_params *p, cons
         std::vector<int> ord(K);
         for (int k = 0; k < K; ++k) ord[k] = k;
         std::stable_sort(ord.begin(), ord.end(), [&](int x, int y) { return cost[x] > cost[y]; });
-        std::vector<std::vector<int32_t>> lists(8);
+        // the host orders blocks (start, count) only; the device expands them to rows
+        std::vector<std::vector<std::pair<int32_t, int32_t>>> lists(8);
         int64_t blk = 0;
         for (int k : ord) {
             for (int64_t r0 = cdf->mat_base_host[k]; r0 < cdf->mat_base_host[k + 1]; r0 += 64, ++blk) {
-                auto &L = lists[blk % 8];
                 const int64_t r1 = std::min<int64_t>(r0 + 64, cdf->mat_base_host[k + 1]);
-                for (int64_t r = r0; r < r1; ++r) L.push_back((int32_t)r);
+                lists[blk % 8].push_back({(int32_t)r0, (int32_t)(r1 - r0)});
             }
         }
-        std::vector<int32_t> all;
-        all.reserve(n_tasks);
-        for (auto &L : lists) all.insert(all.end(), L.begin(), L.end());
-        MCMI_HIP(lpt.alloc(all.size() * sizeof(int32_t), s));
-        MCMI_HIP(hipMemcpyAsync(lpt.p, all.data(), all.size() * sizeof(int32_t), hipMemcpyHostToDevice, s));
-        MCMI_HIP(hipStreamSynchronize(s));
+        std::vector<int32_t> bstart, bcnt;
+        std::vector<int64_t> bpos;
+        bstart.reserve(blk);
+        bcnt.reserve(blk);
+        bpos.reserve(blk);
+        int64_t at = 0;
+        for (auto &L : lists)
+            for (auto &b : L) {
+                bstart.push_back(b.first);
+                bcnt.push_back(b.second);
+                bpos.push_back(at);
+                at += b.second;
+            }
+        DevBuf bdesc;
+        const size_t nb = bstart.size();
+        MCMI_HIP(bdesc.alloc(nb * 16 + 16, s));
+        int32_t *d_start = bdesc.as<int32_t>(), *d_cnt = d_start + nb;
+        int64_t *d_pos = (int64_t *)(bdesc.as<unsigned char>() + ((nb * 8 + 15) / 16) * 16);
+        MCMI_HIP(hipMemcpyAsync(d_start, bstart.data(), nb * 4, hipMemcpyHostToDevice, s));
+        MCMI_HIP(hipMemcpyAsync(d_cnt, bcnt.data(), nb * 4, hipMemcpyHostToDevice, s));
+        MCMI_HIP(hipMemcpyAsync(d_pos, bpos.data(), nb * 8, hipMemcpyHostToDevice, s));
+        MCMI_HIP(lpt.alloc((size_t)n_tasks * sizeof(int32_t), s));
+        MCMI_HIP(expand_blocks((int64_t)nb, d_start, d_cnt, d_pos, cdf->order, lpt.as<int32_t>(), s));
+        MCMI_HIP(hipStreamSynchronize(s));  // the host vectors die at the end of this scope
         task_map = lpt.as<int32_t>();
     } else if (cdf->batch == 0 && !rows_dev && cdf->order) {
         task_map = cdf->order;  // locality schedule of the record set

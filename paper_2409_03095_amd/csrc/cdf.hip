@@ -72,6 +72,15 @@ struct Group {
     __device__ __forceinline__ int first(uint64_t b) const { return (__builtin_ctzll(b)) & (G - 1); }
 };
 
+// Maximum of non-negative doubles kept as their bits (which order like the
+// values). The atomic is skipped when the stored value is already as large:
+// with one call per wave, tens of thousands of atomics on one address would
+// otherwise serialise at its L2 channel.
+__device__ __forceinline__ void atomic_max_bits(unsigned long long *bits, double v) {
+    const unsigned long long b = (unsigned long long)__double_as_longlong(v);
+    if (__atomic_load_n(bits, __ATOMIC_RELAXED) < b) atomicMax(bits, b);
+}
+
 // ||B||_inf for the augmented splitting: each thread sums one row's |b_ij| in
 // column order (one IEEE add at a time, so the sums are those of a sequential
 // loop), the maximum is an integer max on the bits of the non-negative sums.
@@ -85,7 +94,7 @@ __global__ void __launch_bounds__(256) k_row_abs_max(int64_t n, const int64_t *_
         best = sum > best ? sum : best;
     }
     best = wave_max(best);
-    if ((threadIdx.x & 63) == 0) atomicMax(bits, (unsigned long long)__double_as_longlong(best));
+    if ((threadIdx.x & 63) == 0) atomic_max_bits(bits, best);
 }
 
 // Reduction keys: the bits of |c| for every entry of C, all ones for the rest
@@ -283,7 +292,7 @@ __global__ void __launch_bounds__(256) k_fill(int64_t n, const int64_t *__restri
         }
     }
     best = wave_max(best);
-    if ((threadIdx.x & 63) == 0 && best > 0.0) atomicMax(norm_bits, (unsigned long long)__double_as_longlong(best));
+    if ((threadIdx.x & 63) == 0 && best > 0.0) atomic_max_bits(norm_bits, best);
 }
 
 // Alias table of each row (Walker's method, Vose's exact-integer construction;
@@ -682,13 +691,29 @@ __global__ void __launch_bounds__(256) k_concat_cols(const int32_t *col, int64_t
     }
 }
 
+// ||Chat_k||_inf per matrix: the largest Shat64 of its rows (bits of non-negative
+// doubles). A wave whose 64 rows belong to one matrix reduces them first.
 __global__ void __launch_bounds__(256) k_matrix_norms(int64_t n, const uint32_t *rec, const uint32_t *roff,
                                                       const int32_t *row_mat, unsigned long long *bits) {
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < n; r += stride) {
-        const uint32_t *h = rec + (size_t)roff[r] * kUnitWords;
-        const unsigned long long b = ((unsigned long long)h[5] << 32) | h[4];
-        atomicMax(&bits[row_mat[r]], b);
+    for (int64_t r0 = (int64_t)blockIdx.x * blockDim.x; r0 < n; r0 += stride) {  // uniform per wave
+        const int64_t r = r0 + threadIdx.x;
+        const bool ok = r < n;
+        unsigned long long b = 0;
+        int32_t k = -1;
+        if (ok) {
+            const uint32_t *h = rec + (size_t)roff[r] * kUnitWords;
+            b = ((unsigned long long)h[5] << 32) | h[4];
+            k = row_mat[r];
+        }
+        if (!__any(ok)) continue;  // lane 0 holds the wave's first row, so it is in range
+        const int32_t k0 = __shfl(k, 0, 64);
+        if (__all(!ok || k == k0)) {
+            const unsigned long long m = wave_max(b);
+            if ((threadIdx.x & 63) == 0 && __atomic_load_n(&bits[k0], __ATOMIC_RELAXED) < m) atomicMax(&bits[k0], m);
+        } else if (ok && __atomic_load_n(&bits[k], __ATOMIC_RELAXED) < b) {
+            atomicMax(&bits[k], b);
+        }
     }
 }
 
@@ -697,8 +722,15 @@ __global__ void __launch_bounds__(256) k_matrix_norms(int64_t n, const uint32_t 
 }  // namespace mcmi
 
 extern "C" mcmi_status mcmi_build_cdf_batched(const mcmi_csr_in *Bs, int32_t count, mcmi_cdf **out, void *stream) {
+    return mcmi_build_cdf_batched_ex(Bs, count, nullptr, out, stream);
+}
+
+extern "C" mcmi_status mcmi_build_cdf_batched_ex(const mcmi_csr_in *Bs, int32_t count, const mcmi_cdf_opts *opts,
+                                                 mcmi_cdf **out, void *stream) {
     if (out) *out = nullptr;
     if (!Bs || !out || count < 1) return fail(MCMI_ERR_ARG, "mcmi_build_cdf_batched: bad argument");
+    if (opts && (opts->alpha != 0.0 || opts->drop_frac != 0.0 || opts->order_cell < 0 || opts->reserved != 0))
+        return fail(MCMI_ERR_ARG, "mcmi_build_cdf_batched_ex: only order_cell >= 0 applies to a batch");
     hipStream_t s = (hipStream_t)stream;
     std::vector<int64_t> rb(count + 1, 0), zb(count + 1, 0);
     for (int32_t k = 0; k < count; ++k) {
@@ -715,30 +747,27 @@ extern "C" mcmi_status mcmi_build_cdf_batched(const mcmi_csr_in *Bs, int32_t cou
     uint32_t *flags = nullptr;
     int64_t *base_dev = nullptr;
     unsigned long long *nb = nullptr;
-    auto cleanup = [&]() {
-        (void)hipFree(rp);
-        (void)hipFree(col);
-        (void)hipFree(val);
-        (void)hipFree(flags);
-        (void)hipFree(nb);
+    auto cleanup = [&]() {  // stream-ordered: behind the last kernel that reads them
+        for (void *t : {(void *)rp, (void *)col, (void *)val, (void *)flags, (void *)nb})
+            if (t) dev_release(t, s);
     };
 #define TRYB(call)                                                                          \
     do {                                                                                    \
         hipError_t _e = (call);                                                             \
         if (_e != hipSuccess) {                                                             \
             cleanup();                                                                      \
-            (void)hipFree(row_mat);                                                         \
-            (void)hipFree(base_dev);                                                        \
+            dev_release_idle(row_mat);                                                      \
+            dev_release_idle(base_dev);                                                     \
             return fail(MCMI_ERR_HIP, std::string(#call) + ": " + hipGetErrorString(_e));   \
         }                                                                                   \
     } while (0)
-    TRYB(hipMalloc(&rp, (n + 1) * sizeof(int64_t)));
-    TRYB(hipMalloc(&col, nnz * sizeof(int32_t)));
-    TRYB(hipMalloc(&val, nnz * sizeof(double)));
-    TRYB(hipMalloc(&row_mat, n * sizeof(int32_t)));
-    TRYB(hipMalloc(&base_dev, (count + 1) * sizeof(int64_t)));
-    TRYB(hipMalloc(&flags, sizeof(uint32_t)));
-    TRYB(hipMalloc(&nb, count * sizeof(unsigned long long)));
+    TRYB(dev_alloc((void **)&rp, (n + 1) * sizeof(int64_t), s));
+    TRYB(dev_alloc((void **)&col, nnz * sizeof(int32_t), s));
+    TRYB(dev_alloc((void **)&val, nnz * sizeof(double), s));
+    TRYB(dev_alloc((void **)&row_mat, n * sizeof(int32_t), s));
+    TRYB(dev_alloc((void **)&base_dev, (count + 1) * sizeof(int64_t), s));
+    TRYB(dev_alloc((void **)&flags, sizeof(uint32_t), s));
+    TRYB(dev_alloc((void **)&nb, count * sizeof(unsigned long long), s));
     TRYB(hipMemsetAsync(flags, 0, sizeof(uint32_t), s));
     TRYB(hipMemsetAsync(nb, 0, count * sizeof(unsigned long long), s));
     for (int32_t k = 0; k < count; ++k) {
@@ -755,17 +784,17 @@ extern "C" mcmi_status mcmi_build_cdf_batched(const mcmi_csr_in *Bs, int32_t cou
     TRYB(hipStreamSynchronize(s));
     if (hflags & kFlagCsr) {
         cleanup();
-        (void)hipFree(row_mat);
-        (void)hipFree(base_dev);
+        dev_release_idle(row_mat);
+        dev_release_idle(base_dev);
         return fail(MCMI_ERR_CSR, "mcmi_build_cdf_batched: a matrix has bad row pointers or columns");
     }
     mcmi_csr_in all{n, nnz, rp, col, val};
     mcmi_cdf *cdf = nullptr;
-    mcmi_status st = mcmi_build_cdf(&all, &cdf, stream);
+    mcmi_status st = mcmi_build_cdf_ex(&all, opts, &cdf, stream);
     if (st != MCMI_OK) {
         cleanup();
-        (void)hipFree(row_mat);
-        (void)hipFree(base_dev);
+        dev_release_idle(row_mat);
+        dev_release_idle(base_dev);
         return st;
     }
     cdf->batch = count;
@@ -809,8 +838,8 @@ extern "C" mcmi_status mcmi_cdf_batch_info(const mcmi_cdf *cdf, int32_t *count, 
 
 extern "C" void mcmi_cdf_free(mcmi_cdf *cdf) {
     if (!cdf) return;
-    (void)hipFree(cdf->row_mat);
-    (void)hipFree(cdf->mat_base);
+    dev_release_idle(cdf->row_mat);
+    dev_release_idle(cdf->mat_base);
     dev_release_idle(cdf->rec);
     dev_release_idle(cdf->roff);
     dev_release_idle(cdf->diag);

@@ -63,7 +63,8 @@ __global__ void __launch_bounds__(256) k_grow(int64_t n, const int64_t *__restri
         }
         if (sub == 0) lout[r] = v;
     }
-    if (__any(any) && (threadIdx.x & 63) == 0) changed[level] = 1u;
+    if (__any(any) && (threadIdx.x & 63) == 0 && __atomic_load_n(&changed[level], __ATOMIC_RELAXED) == 0u)
+        changed[level] = 1u;
 }
 
 __global__ void __launch_bounds__(256) k_order_keys(int64_t n, uint32_t *lab, int32_t *idx) {

@@ -171,6 +171,27 @@ __global__ void __launch_bounds__(256) k_validate(const int32_t *rows, int64_t n
     }
 }
 
+// Task map of the batched launch from its row blocks: block b lists `cnt[b]`
+// consecutive positions from `start[b]`, written at `pos[b]`; a position is a row,
+// or, with a schedule, the row the schedule puts there.
+__global__ void __launch_bounds__(64) k_expand_blocks(int64_t nblocks, const int32_t *__restrict__ start,
+                                                      const int32_t *__restrict__ cnt, const int64_t *__restrict__ pos,
+                                                      const int32_t *__restrict__ order, int32_t *__restrict__ out) {
+    for (int64_t b = blockIdx.x; b < nblocks; b += gridDim.x)
+        for (int t = threadIdx.x; t < cnt[b]; t += blockDim.x) {
+            const int32_t p = start[b] + t;
+            out[pos[b] + t] = order ? order[p] : p;
+        }
+}
+
+hipError_t expand_blocks(int64_t nblocks, const int32_t *start, const int32_t *cnt, const int64_t *pos,
+                         const int32_t *order, int32_t *out, hipStream_t s) {
+    if (nblocks <= 0) return hipSuccess;
+    const int64_t g = nblocks < 65536 ? nblocks : 65536;
+    k_expand_blocks<<<(unsigned)g, 64, 0, s>>>(nblocks, start, cnt, pos, order, out);
+    return hipGetLastError();
+}
+
 hipError_t validate_rows(const int32_t *rows, int64_t n_rows, const int32_t *cpr, int64_t n, uint32_t *bad,
                          hipStream_t s) {
     const int64_t m = n_rows > n ? n_rows : n;

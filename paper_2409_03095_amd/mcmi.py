@@ -84,6 +84,7 @@ _sig = {
     "mcmi_cdf_info": [_v, _P(ctypes.c_int64), _P(ctypes.c_int64), _P(ctypes.c_double), _P(ctypes.c_uint64)],
     "mcmi_cdf_download": [_v, _v, _v, _v, _v],
     "mcmi_build_cdf_batched": [_P(CsrIn), ctypes.c_int32, _P(_v), _v],
+    "mcmi_build_cdf_batched_ex": [_P(CsrIn), ctypes.c_int32, _P(CdfOpts), _P(_v), _v],
     "mcmi_tune": [_v, _P(Params), ctypes.c_int64, ctypes.c_char_p, _P(Params), _P(ctypes.c_double), _v],
     "mcmi_plan_create": [_v, _P(Params), _v, ctypes.c_int64, _P(_v), _v],
     "mcmi_plan_launch": [_v, ctypes.c_uint64, _v],
@@ -129,7 +130,7 @@ EXPORTED = ["mcmi_cache_trim", "mcmi_bicgstab", "mcmi_build_cdf", "mcmi_build_cd
             "mcmi_row_features", "mcmi_pilot_variance", "mcmi_mlp_create", "mcmi_mlp_free",
             "mcmi_mlp_set_params", "mcmi_mlp_get_params", "mcmi_mlp_set_adam_state", "mcmi_mlp_fit_normalization",
             "mcmi_mlp_predict", "mcmi_mlp_gradient", "mcmi_mlp_train", "mcmi_allocate",
-            "mcmi_build_cdf_batched", "mcmi_cdf_batch_info", "mcmi_tune", "mcmi_plan_create", "mcmi_plan_launch",
+            "mcmi_build_cdf_batched", "mcmi_build_cdf_batched_ex", "mcmi_cdf_batch_info", "mcmi_tune", "mcmi_plan_create", "mcmi_plan_launch",
             "mcmi_plan_result", "mcmi_plan_free", "mcmi_gather_probe"]
 
 
@@ -194,8 +195,13 @@ class Cdf:
                 _check(_lib.mcmi_build_cdf(ctypes.byref(s), ctypes.byref(self._h), _stream(stream)))
         else:
             arr = (CsrIn * len(_batch))(*[m._struct() for m in _batch])
-            _check(_lib.mcmi_build_cdf_batched(arr, ctypes.c_int32(len(_batch)), ctypes.byref(self._h),
-                                               _stream(stream)))
+            if order_cell:
+                opts = CdfOpts(0.0, 0.0, int(order_cell), 0)
+                _check(_lib.mcmi_build_cdf_batched_ex(arr, ctypes.c_int32(len(_batch)), ctypes.byref(opts),
+                                                      ctypes.byref(self._h), _stream(stream)))
+            else:
+                _check(_lib.mcmi_build_cdf_batched(arr, ctypes.c_int32(len(_batch)), ctypes.byref(self._h),
+                                                   _stream(stream)))
         n, nnz_c, nrm, units = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_double(), ctypes.c_uint64()
         _check(_lib.mcmi_cdf_info(self._h, ctypes.byref(n), ctypes.byref(nnz_c), ctypes.byref(nrm),
                                   ctypes.byref(units)))
@@ -214,8 +220,8 @@ class Cdf:
         return out
 
     @staticmethod
-    def batched(mats, stream=None):
-        return Cdf(None, stream, _batch=list(mats))
+    def batched(mats, stream=None, order_cell=0):
+        return Cdf(None, stream, _batch=list(mats), order_cell=order_cell)
 
     def batch_info(self):
         k = ctypes.c_int32()

@@ -19,12 +19,19 @@ def mc():
     return mcmi
 
 
-@pytest.mark.parametrize("prec,kw", [(64, {}), (32, {}), (32, {"lanes_per_row": 256}),
-                                     (64, {"hash_slots": 128})])
-def test_batched_blocks_equal_single_matrix_runs(mc, prec, kw):
+@pytest.mark.parametrize("prec,kw,cell", [(64, {}, 0), (32, {}, 0), (32, {"lanes_per_row": 256}, 0),
+                                          (64, {"hash_slots": 128}, 0), (32, {}, 256), (64, {}, 64)])
+def test_batched_blocks_equal_single_matrix_runs(mc, prec, kw, cell):
     mats, meta = I.convdiff_batch(count=12, seed=3, nmin=200, nmax=2500)
-    print(f"[gpu] batched {[m.n for m in mats]} prec={prec} {kw}", flush=True)
-    cdf = mc.Cdf.batched([mc.DeviceCsr.from_host(B) for B in mats])
+    print(f"[gpu] batched {[m.n for m in mats]} prec={prec} {kw} cell={cell}", flush=True)
+    cdf = mc.Cdf.batched([mc.DeviceCsr.from_host(B) for B in mats], order_cell=cell)
+    if cell:
+        # the schedule keeps each matrix's rows in the matrix's own slice
+        order = cdf.order()
+        _, base0, _ = cdf.batch_info()
+        for i in range(len(mats)):
+            part = np.sort(order[base0[i]:base0[i + 1]])
+            assert np.array_equal(part, np.arange(base0[i], base0[i + 1], dtype=np.int32))
     k, base, nrm = cdf.batch_info()
     assert k == len(mats) and base[-1] == sum(m.n for m in mats)
     N = 300 if kw.get("lanes_per_row") else 64
@@ -43,6 +50,19 @@ def test_batched_blocks_equal_single_matrix_runs(mc, prec, kw):
         sub_val = val[rp[r0]:rp[r1]]
         compare_spai((sub_rp, sub_col, sub_val), orc, o.diag, N)
     assert res.stats.transitions == total
+
+
+def test_batched_schedule_rejects_pre_pass_options(mc):
+    import ctypes
+    mats, _ = I.convdiff_batch(count=3, seed=4, nmin=200, nmax=400)
+    devs = [mc.DeviceCsr.from_host(B) for B in mats]
+    arr = (mc.CsrIn * 3)(*[d._struct() for d in devs])
+    h = ctypes.c_void_p()
+    for alpha, frac, cell in ((1.0, 0.0, 0), (0.0, 0.1, 0), (0.0, 0.0, -5)):
+        opts = mc.CdfOpts(alpha, frac, cell, 0)
+        st = mc._lib.mcmi_build_cdf_batched_ex(arr, ctypes.c_int32(3), ctypes.byref(opts), ctypes.byref(h),
+                                                mc._stream(None))
+        assert st == -1 and not h.value  # MCMI_ERR_ARG
 
 
 # ------------------------------------------------------------ autotuner
