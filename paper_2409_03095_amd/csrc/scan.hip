@@ -106,9 +106,11 @@ hipError_t scan_exclusive_u32_to_i64(const uint32_t *in, int64_t *out, int64_t n
 // Copy each row's survivors from its pool into the CSR arrays at row_ptr. One
 // wave per row, lanes over entries (coalesced). row_start holds the position in
 // the low 56 bits and the pool index above.
-__global__ void __launch_bounds__(256) k_gather_rows(int64_t n_rows, const int64_t *row_start,
-                                                     const uint32_t *row_cnt, const int64_t *row_ptr, PoolSet pools,
-                                                     int32_t *col, double *val) {
+__global__ void __launch_bounds__(256) k_gather_rows(int64_t n_rows, const int64_t *__restrict__ row_start,
+                                                     const uint32_t *__restrict__ row_cnt,
+                                                     const int64_t *__restrict__ row_ptr, PoolSet pools,
+                                                     int32_t *__restrict__ col, double *__restrict__ val) {
+    constexpr int U = 4;  // entries per lane in flight
     const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
     const int lane = threadIdx.x & 63;
     const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
@@ -118,11 +120,23 @@ __global__ void __launch_bounds__(256) k_gather_rows(int64_t n_rows, const int64
         const int pool = (int)(tagged >> kPoolShift);
         const int64_t src = tagged & kPosMask;
         const uint32_t cnt = row_cnt[r];
-        const int32_t *pc = pools.col[pool];
-        const double *pv = pools.val[pool];
-        for (uint32_t k = lane; k < cnt; k += 64) {
-            col[dst + k] = pc[src + k];
-            val[dst + k] = pv[src + k];
+        const int32_t *__restrict__ pc = pools.col[pool] + src;
+        const double *__restrict__ pv = pools.val[pool] + src;
+        for (uint32_t k0 = lane; k0 < cnt; k0 += 64 * U) {
+            int32_t c[U];
+            double w[U];
+#pragma unroll
+            for (int j = 0; j < U; ++j) {
+                const uint32_t k = k0 + 64u * j < cnt ? k0 + 64u * j : cnt - 1u;
+                c[j] = pc[k];
+                w[j] = pv[k];
+            }
+#pragma unroll
+            for (int j = 0; j < U; ++j)
+                if (k0 + 64u * j < cnt) {
+                    col[dst + k0 + 64u * j] = c[j];
+                    val[dst + k0 + 64u * j] = w[j];
+                }
         }
     }
 }
@@ -205,16 +219,33 @@ hipError_t validate_rows(const int32_t *rows, int64_t n_rows, const int32_t *cpr
 // ------------------------------------------------------------------ SpMV
 // y = M x, float64. A group of G lanes per row (G from the average row length:
 // about one lane per entry, 8 to 64), strided partial sums then a butterfly
-// reduction inside the group; grid-stride over rows.
+// reduction inside the group; grid-stride over rows. Each lane issues the loads
+// of four of its entries before it adds them (in the same order as one at a time).
 template <int G>
-__global__ void __launch_bounds__(256) k_spmv(int64_t n, const int64_t *rp, const int32_t *ci, const double *v,
-                                              const double *x, double *y) {
+__global__ void __launch_bounds__(256) k_spmv(int64_t n, const int64_t *__restrict__ rp, const int32_t *__restrict__ ci,
+                                              const double *__restrict__ v, const double *__restrict__ x,
+                                              double *__restrict__ y) {
+    constexpr int U = 4;
     const int sub = threadIdx.x & (G - 1);
     const int64_t groups = ((int64_t)gridDim.x * blockDim.x) / G;
     for (int64_t row = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / G; row < n; row += groups) {
         const int64_t b = rp[row], e = rp[row + 1];
         double acc = 0.0;
-        for (int64_t k = b + sub; k < e; k += G) acc += v[k] * x[ci[k]];
+        for (int64_t k0 = b + sub; k0 < e; k0 += (int64_t)G * U) {
+            int32_t c[U];
+            double w[U], xv[U];
+#pragma unroll
+            for (int j = 0; j < U; ++j) {
+                const int64_t k = k0 + (int64_t)j * G < e ? k0 + (int64_t)j * G : e - 1;
+                c[j] = ci[k];
+                w[j] = v[k];
+            }
+#pragma unroll
+            for (int j = 0; j < U; ++j) xv[j] = x[c[j]];
+#pragma unroll
+            for (int j = 0; j < U; ++j)
+                if (k0 + (int64_t)j * G < e) acc += w[j] * xv[j];
+        }
 #pragma unroll
         for (int off = G / 2; off > 0; off >>= 1) acc += __shfl_xor(acc, off, G);
         if (sub == 0) y[row] = acc;
