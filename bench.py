@@ -35,7 +35,7 @@ METRIC = "MC transitions/s; time to ‖I−MB‖_F≤0.3, learned vs uniform cha
 HBM_PEAK_GBS = 8000.0
 # rocprofv3 FETCH_SIZE/WRITE_SIZE of the walk kernel, in bytes per launch, for
 # the default workload (None until measured for the current kernel)
-TRAFFIC_BYTES = 4.00e11  # calibrated FETCH_SIZE + WRITE_SIZE of one walk launch (rocprofv3 --pmc)
+TRAFFIC_BYTES = 3.94e11  # calibrated FETCH_SIZE + WRITE_SIZE of one walk launch (rocprofv3 --pmc)
 
 
 def algorithmic_bytes_per_transition(B, fp32: bool) -> float:
