@@ -351,12 +351,26 @@ def learned_main(args):
     ut = L.crossing([p["uniform"] for p in pts], "transitions")
     ls = L.crossing([p["learned"] for p in pts], "wall_s")
     us = L.crossing([p["uniform"] for p in pts], "wall_s")
+    # control: a family whose rows differ in path variance at equal cost (a
+    # deterministic-path cycle block next to random rows), where the best
+    # allocation is far from uniform
+    cmats = [I.cycle_plus_random(1000 + s) for s in range(40)]
+    cnet, cinfo = L.train_allocator(cmats, delta, steps=args.train_steps)
+    CB = I.cycle_plus_random(99, scale=200)
+    cpts = L.compare(cnet, CB, delta, eps, [1, 2, 4, 8, 16])
+    for p in cpts:
+        print(f"[learned] control budget {p['mean_chains']}: learned r={p['learned']['r_norm']:.4f} "
+              f"| uniform r={p['uniform']['r_norm']:.4f} at T={p['uniform']['transitions']}", flush=True)
+    control = {"workload": f"cycle + random blocks, 40 training matrices, held-out n={CB.n}", "train": cinfo,
+               "learned_transitions_to_0.3": L.crossing([p["learned"] for p in cpts], "transitions"),
+               "uniform_transitions_to_0.3": L.crossing([p["uniform"] for p in cpts], "transitions"),
+               "points": cpts}
     out = {"metric": METRIC, "value": lt, "unit": "transitions to ||I-MB||_F/sqrt(n) <= 0.3 (learned)",
            "uniform_value": ut, "learned_seconds": ls, "uniform_seconds": us,
            "higher_is_better": False, "n_gpus": 1, "dtype": "f64", "data": "synthetic",
            "config": {"workload": f"5-point family with smooth rho field: {args.train_mats} training matrices, "
                                   f"held-out {args.heldout}x{args.heldout}", "n": B.n, "train": info},
-           "points": pts}
+           "points": pts, "control": control}
     print(json.dumps(out), flush=True)
 
 

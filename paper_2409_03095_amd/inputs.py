@@ -18,6 +18,8 @@ available, so these families stand in for them with similar row densities:
                         per-row contraction field (learned-allocation family)
 * ``aniso27``         - 3D 27-point anisotropic Q1 stencil (sym_r6_a11-like,
                         about 27 entries/row)
+* ``cycle_plus_random`` - allocation control: a deterministic-path block next to
+                        a random block
 * small pin matrices  - diagonal-only, nilpotent shift, scaled cycle, torus,
                         tiny dense.
 """
@@ -253,6 +255,19 @@ def aniso27(nx: int = 160, kx: float = 1.0, ky: float = 10.0, kz: float = 100.0,
     rows, cols, vals = map(np.concatenate, (rows, cols, vals))
     vals = vals * (1.0 + noise * rng.uniform(-1.0, 1.0, size=vals.size))
     return _with_uniform_diagonal(n, rows, cols, vals, rho)
+
+
+def cycle_plus_random(seed: int, scale: int = 1) -> Csr:
+    """Allocation control family: two decoupled blocks, a scaled cycle (one entry
+    per row of C: every chain from such a row follows the same path) and random
+    nonsymmetric rows (5..30 entries), n1, n2 ~ scale * U{500..1499}, common
+    ||C||_inf = a ~ U[0.5, 0.8]. Rows differ in how much a chain's path varies at
+    equal cost, which is what a per-row chain allocation can exploit."""
+    rng = np.random.default_rng(seed)
+    n1 = int(rng.integers(500, 1500)) * scale
+    n2 = int(rng.integers(500, 1500)) * scale
+    a = float(rng.uniform(0.5, 0.8))
+    return block_diag([scaled_cycle(n1, a), random_nonsym(n2, rho=a, seed=seed + 7)])
 
 
 def block_diag(mats) -> Csr:

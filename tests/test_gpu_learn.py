@@ -1,4 +1,6 @@
-"""GPU parity of the learned-allocation inputs: row features and pilot variance."""
+"""GPU parity of the learned-allocation parts (row features, pilot variance, the
+BF16 network's forward, gradient and training, the allocation, the quality
+sample) and what the trained network gains over uniform chains."""
 import numpy as np
 import pytest
 
@@ -175,3 +177,37 @@ def test_quality_sample_matches_oracle_residual(mc):
     Msub = sp.csr_matrix((sval, scol, srp), shape=(rows.size, B.n))
     ref = O.residual_rows(B, Msub, rows)
     assert np.allclose(got, ref, rtol=1e-12, atol=1e-15)
+
+
+# ------------------------------------------------ what the network gains
+@pytest.mark.parametrize("family", ["cycle_plus_random", "family_5pt"])
+def test_learned_allocation_against_uniform(mc, family):
+    """Train the network on pilot variance of 40 matrices of a family and compare
+    learned vs uniform chains on a held-out matrix at equal total transitions
+    (||I - M B||_F / sqrt(n) on a 4000-row sample, 95 % intervals).
+    cycle_plus_random (half the rows follow one deterministic path, so one chain
+    estimates them exactly): the learned allocation moves chains to the random
+    rows and wins with disjoint intervals at every budget. family_5pt (the
+    grid family of the learned-allocation workload: per-row variance and chain
+    cost both grow like 1 / (1 - rho_i), so the best allocation is nearly
+    uniform): the two agree within their intervals."""
+    from paper_2409_03095_amd import learned as L
+    gen = I.cycle_plus_random if family == "cycle_plus_random" else I.family_5pt
+    train = [gen(1000 + s) for s in range(40)]
+    held = I.cycle_plus_random(99, scale=20) if family == "cycle_plus_random" else I.family_5pt(555, 200, 200)
+    print(f"[gpu] learned vs uniform on {family}: train rows {sum(m.n for m in train)}, held-out n={held.n}",
+          flush=True)
+    net, info = L.train_allocator(train, 1e-3, steps=3000)
+    assert info["loss_last"] < info["loss_first"]
+    pts = L.compare(net, held, 1e-3, 1e-3, [2, 8], n_sample=4000)
+    for p in pts:
+        lr, ur = p["learned"], p["uniform"]
+        print(f"  mean chains {p['mean_chains']}: learned {lr['r_norm']:.4f} [{lr['r_norm_lo']:.4f}, "
+              f"{lr['r_norm_hi']:.4f}] at {lr['transitions']} | uniform {ur['r_norm']:.4f} "
+              f"[{ur['r_norm_lo']:.4f}, {ur['r_norm_hi']:.4f}] at {ur['transitions']}", flush=True)
+        assert not p["fallback"]
+        assert abs(lr["transitions"] - ur["transitions"]) <= 0.01 * ur["transitions"]
+        if family == "cycle_plus_random":
+            assert lr["r_norm_hi"] < ur["r_norm_lo"]
+        else:
+            assert lr["r_norm_lo"] <= ur["r_norm_hi"] and ur["r_norm_lo"] <= lr["r_norm_hi"]

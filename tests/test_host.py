@@ -118,3 +118,16 @@ def test_crossing_interpolates_a_power_law_exactly():
     pts = [{"transitions": t, "r_norm": 3.0 * t ** -0.5} for t in (10.0, 50.0, 400.0, 1000.0)]
     assert L.crossing(pts, "transitions") == pytest.approx(100.0, rel=1e-12)
     assert L.crossing([{"transitions": 1.0, "r_norm": 0.1}], "transitions") is None
+
+
+def test_cycle_plus_random_recipe():
+    B = I.cycle_plus_random(5)
+    check_csr(B)
+    m = np.diff(B.row_ptr) - 1
+    S = B.to_scipy().tocsr()
+    n1 = int(np.argmax(m > 1))  # the cycle block comes first: one entry of C per row
+    assert n1 >= 500 and np.all(m[:n1] == 1) and np.all(m[n1:] >= 5)
+    assert S[:n1, n1:].nnz == 0 and S[n1:, :n1].nnz == 0  # decoupled blocks
+    sums = c_abs_row_sums(B)
+    np.testing.assert_allclose(sums, sums[0], rtol=1e-12)  # one ||C||_inf for both blocks
+    assert 0.5 <= sums[0] <= 0.8
