@@ -89,6 +89,10 @@ def main():
     ap.add_argument("--nx", type=int, default=160, help="grid side of the aniso27 workload")
     ap.add_argument("--order-cell", type=int, default=None,
                     help="row schedule cells (rows per cell; 0 = natural order). Default: 4096 for aniso27, else 0")
+    ap.add_argument("--learned-alloc", action="store_true",
+                    help="aniso27: chains per row from the allocation network (trained on small 27-point "
+                         "matrices), same mean budget, uniform fallback; features, inference and allocation "
+                         "are inside the timed step")
     ap.add_argument("--bicgstab", action="store_true", help="aniso27: device BiCGstab iterations with and without M")
     ap.add_argument("--learned", action="store_true",
                     help="learned vs uniform chains to ||I-MB||_F/sqrt(n) <= 0.3 (allocation-network workload)")
@@ -99,8 +103,8 @@ def main():
                     help="first run one plain 1 GiB device copy (reference for rocprofv3 byte counters)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py measures one GPU: the Monte Carlo rows shard across GPUs without communication "
-              "(see the design notes), but this build runs and reports a single MI355X only.", file=sys.stderr)
+        print("bench.py measures one GPU: the Monte Carlo rows would shard across GPUs without communication, "
+              "but the benchmark runs and reports a single MI355X only.", file=sys.stderr)
         sys.exit(2)
 
     import torch
@@ -225,16 +229,38 @@ def aniso_main(args):
     x = torch.ones(B.n, dtype=torch.float64, device="cuda")
     y = torch.empty(B.n, dtype=torch.float64, device="cuda")
     cell = 4096 if args.order_cell is None else args.order_cell
+    net, alloc = None, None
+    if args.learned_alloc:
+        from paper_2409_03095_amd import learned as L
+        rng = np.random.default_rng(77)
+        train = [I.aniso27(int(rng.integers(12, 21)), seed=1000 + k) for k in range(40)]
+        net, tinfo = L.train_allocator(train, 1e-4, steps=3000)
+        alloc = {"train": tinfo}
+        print(f"[aniso27] allocation network trained: {json.dumps(tinfo)}", flush=True)
+
+    def chains_for(cdf):
+        # learned allocation: features -> network -> chains per row for the same
+        # mean budget (cost 1 + ceil(f7) per chain), uniform fallback inside mcmi_allocate
+        if net is None:
+            return None
+        feat = mcmi.row_features(cdf, 1e-4)
+        pred = net.predict(feat)
+        cost = (1.0 + torch.ceil(feat[:, 7])).to(torch.int32)
+        cpr, lam, fb = mcmi.allocate(pred, cost, int(chains * int(cost.sum().item())))
+        alloc.update({"lambda": lam, "fallback": fb})
+        return cpr
+
     for _ in range(args.warmup):
         cdf = mcmi.Cdf(dB, order_cell=cell)
-        res = mcmi.spai(cdf, p)
+        res = mcmi.spai(cdf, p, chains_per_row=chains_for(cdf))
         del cdf, res
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     walk_ms = []
     for _ in range(args.steps):
         cdf = mcmi.Cdf(dB, order_cell=cell)
-        res = mcmi.spai(cdf, p)
+        cpr = chains_for(cdf)
+        res = mcmi.spai(cdf, p, chains_per_row=cpr)
         res.apply(x, y)
         walk_ms.append(res.stats.ms_walk)
         last = res
@@ -258,6 +284,21 @@ def aniso_main(args):
                         "unit": "GB/s", "frac": round(bpt * st.transitions / walk_s / 1e9 / HBM_PEAK_GBS, 4),
                         "bytes_per_transition": round(bpt, 2), "walk_ms": round(walk_s * 1e3, 3),
                         "walk_transitions_per_s": st.transitions / walk_s, "gather_ceiling_steps_per_s": ceiling}}
+    if net is not None:
+        # quality at the same budget: learned vs uniform chains, 10^4-row sample
+        cdf = mcmi.Cdf(dB, order_cell=cell)
+        cpr = chains_for(cdf)
+        rows = np.sort(np.random.default_rng(12345).choice(B.n, 10000, replace=False))
+        ql = L.evaluate(B, cpr, 1e-4, 1e-3, 0, rows, args.prec, cdf)
+        qu = L.evaluate(B, torch.full((B.n,), chains, dtype=torch.int32, device="cuda"), 1e-4, 1e-3, 0, rows,
+                        args.prec, cdf)
+        alloc.update({"chains_min": int(cpr.min().item()), "chains_max": int(cpr.max().item()),
+                      "learned": ql, "uniform": qu})
+        out["config"]["allocation"] = "learned"
+        out["learned_allocation"] = alloc
+        print(f"[aniso27] learned r={ql['r_norm']:.4f} T={ql['transitions']} | uniform r={qu['r_norm']:.4f} "
+              f"T={qu['transitions']}", flush=True)
+        del cdf
     if args.bicgstab:
         # device BiCGstab (b = B 1, x0 = 0, rtol 1e-8): no preconditioner vs M
         Bs_ones = torch.from_numpy(B.to_scipy() @ np.ones(B.n)).cuda()

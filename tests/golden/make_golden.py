@@ -7,7 +7,7 @@ weights c / p are exact rationals, so the expectation of every entry, and of its
 square, can be enumerated over all paths with Python's ``fractions``. This script
 uses no oracle code and no floating point for the expectations.
 
-Conventions (the readings fixed for this build):
+Conventions (the readings of the paper this implementation takes):
 * the start state contributes W_0 = 1 (the identity term of the Neumann series);
 * before each draw the chain stops if the row of C is empty or the next weight
   |W * sum_k |c_sk|| is strictly below delta;
