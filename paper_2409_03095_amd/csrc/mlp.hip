@@ -535,11 +535,24 @@ extern "C" mcmi_status mcmi_mlp_train(mcmi_mlp *net, const float *feat_dev, cons
 
 // ------------------------------------------------------------ allocation
 // N_r = max(1, rint(lambda * exp(pred_r))) with lambda found by bisection so that
-// sum_r N_r cost_r is the largest total not above the budget. One workgroup;
-// exp(pred) is computed once. Non-finite predictions fall back to the uniform
-// allocation N_r = max(1, floor(budget / sum_r cost_r)).
+// sum_r N_r cost_r is the largest total not above the budget: hi doubles from 1
+// while total(hi) <= budget (and hi < 1e30), then 100 halvings of [0, hi] keep
+// total(lo) <= budget < total(hi); lambda = lo. Every total is an exact integer
+// sum, so the grid-wide evaluation below (one pass over the rows per step, the
+// step's decision taken on the device, no host round trip) makes the same
+// decisions as a sequential loop. Non-finite predictions fall back to the
+// uniform allocation N_r = max(1, floor(budget / sum_r cost_r)).
 namespace mcmi {
 namespace {
+
+struct AllocState {
+    double lo, hi;
+    long long total;  // of the current candidate
+    long long bad;    // non-finite predictions
+    long long csum;   // sum of costs
+    int32_t phase;    // 0: doubling hi, 1: halving, 2: done
+    int32_t halvings;
+};
 
 __device__ __forceinline__ long long block_sum_ll(long long v, long long *red) {
     v = wave_sum(v);
@@ -552,12 +565,19 @@ __device__ __forceinline__ long long block_sum_ll(long long v, long long *red) {
     return t;
 }
 
-__global__ void __launch_bounds__(1024) k_allocate(const float *pred, const int32_t *cost, int64_t n,
-                                                   long long budget, double *e, int32_t *chains, double *lam_out,
-                                                   int32_t *fallback_out) {
-    __shared__ long long red[16];
+__device__ __forceinline__ long long chains_of(double lam, double e) {
+    double k = rint(lam * e);
+    if (!(k >= 1.0)) k = 1.0;
+    if (k > 2147483647.0) k = 2147483647.0;
+    return (long long)k;
+}
+
+__global__ void __launch_bounds__(256) k_alloc_prep(const float *pred, const int32_t *cost, int64_t n, double *e,
+                                                    AllocState *st) {
+    __shared__ long long red[4];
     long long bad = 0, csum = 0;
-    for (int64_t r = threadIdx.x; r < n; r += blockDim.x) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < n; r += stride) {
         const float p = pred[r];
         bad += isfinite(p) ? 0 : 1;
         e[r] = exp((double)p);
@@ -565,43 +585,57 @@ __global__ void __launch_bounds__(1024) k_allocate(const float *pred, const int3
     }
     bad = block_sum_ll(bad, red);
     csum = block_sum_ll(csum, red);
-    auto total = [&](double lam) {
-        long long t = 0;
-        for (int64_t r = threadIdx.x; r < n; r += blockDim.x) {
-            double k = rint(lam * e[r]);
-            if (!(k >= 1.0)) k = 1.0;
-            if (k > 2147483647.0) k = 2147483647.0;
-            t += (long long)k * (long long)cost[r];
-        }
-        return block_sum_ll(t, red);
-    };
-    double lam = 0.0;
-    bool fb = bad > 0 || csum <= 0;
-    if (!fb) {
-        double lo = 0.0, hi = 1.0;
-        while (total(hi) <= budget && hi < 1e30) hi *= 2.0;
-        for (int it = 0; it < 100; ++it) {
-            const double mid = 0.5 * (lo + hi);
-            if (total(mid) <= budget)
-                lo = mid;
-            else
-                hi = mid;
-        }
-        lam = lo;
-        fb = !(lam > 0.0);
-    }
-    const long long uni = csum > 0 ? (budget / csum > 1 ? budget / csum : 1) : 1;
-    for (int64_t r = threadIdx.x; r < n; r += blockDim.x) {
-        if (fb) {
-            chains[r] = (int32_t)(uni < 2147483647LL ? uni : 2147483647LL);
-        } else {
-            double k = rint(lam * e[r]);
-            if (!(k >= 1.0)) k = 1.0;
-            if (k > 2147483647.0) k = 2147483647.0;
-            chains[r] = (int32_t)k;
-        }
-    }
     if (threadIdx.x == 0) {
+        if (bad) atomicAdd((unsigned long long *)&st->bad, (unsigned long long)bad);
+        atomicAdd((unsigned long long *)&st->csum, (unsigned long long)csum);
+    }
+}
+
+// total(candidate) into st->total; the candidate is hi while doubling, else the midpoint
+__global__ void __launch_bounds__(256) k_alloc_total(const double *e, const int32_t *cost, int64_t n,
+                                                     AllocState *st) {
+    __shared__ long long red[4];
+    const int32_t phase = st->phase;
+    if (phase == 2) return;
+    const double lam = phase == 0 ? st->hi : 0.5 * (st->lo + st->hi);
+    long long t = 0;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < n; r += stride)
+        t += chains_of(lam, e[r]) * (long long)cost[r];
+    t = block_sum_ll(t, red);
+    if (threadIdx.x == 0) atomicAdd((unsigned long long *)&st->total, (unsigned long long)t);
+}
+
+// the step's decision (one thread)
+__global__ void k_alloc_update(AllocState *st, long long budget) {
+    if (st->phase == 0) {
+        if (st->total <= budget && st->hi < 1e30)
+            st->hi *= 2.0;
+        else
+            st->phase = 1;
+    } else if (st->phase == 1) {
+        const double mid = 0.5 * (st->lo + st->hi);
+        if (st->total <= budget)
+            st->lo = mid;
+        else
+            st->hi = mid;
+        if (++st->halvings == 100) st->phase = 2;
+    }
+    st->total = 0;
+}
+
+__global__ void __launch_bounds__(256) k_alloc_write(const double *e, int64_t n, long long budget,
+                                                     const AllocState *st, int32_t *chains, double *lam_out,
+                                                     int32_t *fallback_out) {
+    const bool fb0 = st->bad > 0 || st->csum <= 0;
+    const double lam = fb0 ? 0.0 : st->lo;
+    const bool fb = fb0 || !(lam > 0.0);
+    const long long csum = st->csum;
+    const long long uni = csum > 0 ? (budget / csum > 1 ? budget / csum : 1) : 1;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < n; r += stride)
+        chains[r] = fb ? (int32_t)(uni < 2147483647LL ? uni : 2147483647LL) : (int32_t)chains_of(lam, e[r]);
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
         *lam_out = lam;
         *fallback_out = fb ? 1 : 0;
     }
@@ -618,19 +652,38 @@ extern "C" mcmi_status mcmi_allocate(const float *pred_dev, const int32_t *cost_
     hipStream_t s = (hipStream_t)stream;
     double *e = nullptr, *lam = nullptr;
     int32_t *fbk = nullptr;
-    MCMI_HIP(hipMallocAsync((void **)&e, (size_t)n * sizeof(double), s));
-    MCMI_HIP(hipMallocAsync((void **)&lam, sizeof(double), s));
-    MCMI_HIP(hipMallocAsync((void **)&fbk, sizeof(int32_t), s));
-    k_allocate<<<1, 1024, 0, s>>>(pred_dev, cost_dev, n, (long long)budget, e, chains_dev, lam, fbk);
-    MCMI_HIP(hipGetLastError());
+    AllocState *st = nullptr;
+    MCMI_HIP(dev_alloc((void **)&e, (size_t)n * sizeof(double), s));
+    MCMI_HIP(dev_alloc((void **)&lam, sizeof(double) + sizeof(int32_t) * 2 + sizeof(AllocState), s));
+    fbk = (int32_t *)(lam + 1);
+    st = (AllocState *)(fbk + 2);
+    const AllocState init{0.0, 1.0, 0, 0, 0, 0, 0};
+    int64_t blocks = (n + 255) / 256;
+    if (blocks > 2048) blocks = 2048;
+    hipError_t err = hipMemcpyAsync(st, &init, sizeof(init), hipMemcpyHostToDevice, s);
+    if (err == hipSuccess) {
+        k_alloc_prep<<<(unsigned)blocks, 256, 0, s>>>(pred_dev, cost_dev, n, e, st);
+        err = hipGetLastError();
+    }
+    // at most 101 doublings (hi reaches 2^100 > 1e30) and exactly 100 halvings;
+    // steps after the search has ended return at once
+    for (int it = 0; err == hipSuccess && it < 201; ++it) {
+        k_alloc_total<<<(unsigned)blocks, 256, 0, s>>>(e, cost_dev, n, st);
+        k_alloc_update<<<1, 1, 0, s>>>(st, (long long)budget);
+        err = hipGetLastError();
+    }
+    if (err == hipSuccess) {
+        k_alloc_write<<<(unsigned)blocks, 256, 0, s>>>(e, n, (long long)budget, st, chains_dev, lam, fbk);
+        err = hipGetLastError();
+    }
     double hl = 0.0;
     int32_t hf = 0;
-    MCMI_HIP(hipMemcpyAsync(&hl, lam, sizeof(double), hipMemcpyDeviceToHost, s));
-    MCMI_HIP(hipMemcpyAsync(&hf, fbk, sizeof(int32_t), hipMemcpyDeviceToHost, s));
-    MCMI_HIP(hipFreeAsync(e, s));
-    MCMI_HIP(hipFreeAsync(lam, s));
-    MCMI_HIP(hipFreeAsync(fbk, s));
-    MCMI_HIP(hipStreamSynchronize(s));
+    if (err == hipSuccess) err = hipMemcpyAsync(&hl, lam, sizeof(double), hipMemcpyDeviceToHost, s);
+    if (err == hipSuccess) err = hipMemcpyAsync(&hf, fbk, sizeof(int32_t), hipMemcpyDeviceToHost, s);
+    if (err == hipSuccess) err = hipStreamSynchronize(s);
+    dev_release(e, s);
+    dev_release(lam, s);
+    if (err != hipSuccess) return fail(MCMI_ERR_HIP, std::string("mcmi_allocate: ") + hipGetErrorString(err));
     if (lambda_host) *lambda_host = hl;
     if (fallback_host) *fallback_host = hf;
     return MCMI_OK;

@@ -139,9 +139,10 @@ def test_mlp_training_reduces_loss_and_checkpoints(mc):
     assert np.array_equal(y1, y2)
 
 
-def test_allocation_matches_reference(mc):
+@pytest.mark.parametrize("n", [1, 5000, 400000])
+def test_allocation_matches_reference(mc, n):
+    """Grid-wide bisection on the device vs the sequential numpy reference."""
     rng = np.random.default_rng(9)
-    n = 5000
     pred = rng.normal(0, 0.7, size=n).astype(np.float32)
     cost = rng.integers(5, 40, size=n).astype(np.int32)
     budget = int(24 * cost.sum())
@@ -153,7 +154,7 @@ def test_allocation_matches_reference(mc):
     assert abs(lam - rlam) <= 1e-9 * rlam
     assert np.mean(chains != ref) < 1e-3 and np.max(np.abs(chains - ref)) <= 1
     bad = pred.copy()
-    bad[7] = np.nan
+    bad[min(7, n - 1)] = np.nan
     chains, lam, fb = mc.allocate(torch.from_numpy(bad).cuda(), torch.from_numpy(cost).cuda(), budget)
     assert fb and np.all(chains.cpu().numpy() == budget // cost.sum())
 
