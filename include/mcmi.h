@@ -14,7 +14,7 @@
  *                                       the inverse diagonal, since B^-1 =
  *                                       (I - C)^-1 D^-1)
  *   keep (r, c) iff c == r or |N_rc| >= eps   (the filter that makes M sparse,
- *                                       Section III-A "parallel filter")
+ *                                       named at the end of Section III-A)
  *
  * Sampling: transition probabilities p_ij proportional to |c_ij| (the paper
  * leaves P undefined), quantized to integer weights per row so that every

@@ -11,7 +11,7 @@
  * phases 2-4; Section IV-A for the column scaling):
  *   O1  iteration matrix   C = I - D^-1 B, c_ij = (-b_ij) / b_ii, zeros dropped
  *   O2  transition CDF     p_ij proportional to |c_ij| (the paper never defines P;
- *                          this is the "almost optimal" choice), quantized to
+ *                          this is the almost-optimal choice), quantized to
  *                          integer weights so both sides sample the same Chat
  *   O3  random numbers     Philox4x32-10 (Salmon et al., SC'11), counter-based;
  *                          a word picks the next state by the alias method
