@@ -68,13 +68,23 @@ int device_cus() {
 
 // Kernel shape of a run: lanes per row (64 = wavefront kernel), LDS hash slots,
 // count-sketch buckets and heavy threshold tau (0 = track every contribution).
-mcmi_status choose_shape(const mcmi_cdf *cdf, const mcmi_params *p, int lmax, KernelShape &out) {
+// n_max: the largest chain count of a row.
+mcmi_status choose_shape(const mcmi_cdf *cdf, const mcmi_params *p, int lmax, int n_max, KernelShape &out) {
     const double m_bar = cdf->n > 0 ? (double)cdf->nnz_c / (double)cdf->n : 0.0;
     const int n_hint = p->chains >= 1 ? p->chains : 64;
     int lanes = p->lanes_per_row;
     if (lanes == 0) lanes = n_hint >= 384 ? 512 : (n_hint >= 192 ? 256 : 64);
     const bool block_kernel = lanes > 64;
-    int H = p->hash_slots ? p->hash_slots : (block_kernel ? 4096 : 1024);
+    int H = p->hash_slots;
+    if (!H && block_kernel) H = 4096;
+    if (!H) {
+        // wavefront kernel: a row's chains reach at most N (L + 1) columns; a table of
+        // that size (128 to 1024 slots) lets more wavefronts share a CU's LDS, which is
+        // what keeps enough rows in flight when rows have few chains
+        const double reach = (double)std::max(n_max, 1) * ((double)std::max(lmax, 0) + 1.0);
+        H = 128;
+        while (H < 1024 && (double)H < reach) H *= 2;
+    }
     if (block_kernel && !walk_block_supported(lanes, H))
         return fail(MCMI_ERR_ARG, "mcmi_spai: unsupported (lanes_per_row, hash_slots) for the workgroup kernel");
     int sketch = 0;
@@ -197,12 +207,25 @@ extern "C" mcmi_status mcmi_spai(const mcmi_cdf *cdf, const mcmi_params *p, cons
         }
     } evg{ev0, ev1, ev2};
 
-    // ---- kernel shape and heavy threshold
+    // ---- row list and chain counts (one synchronisation), then the kernel shape
+    int n_max = p->chains;
+    if (rows_dev || chains_per_row_dev) {
+        uint32_t hv[2] = {0, 0};
+        DevBuf vb;
+        MCMI_HIP(vb.alloc(sizeof(hv), s));
+        MCMI_HIP(hipMemsetAsync(vb.p, 0, sizeof(hv), s));
+        MCMI_HIP(validate_rows(rows_dev, rows_dev ? n_rows : 0, chains_per_row_dev, cdf->n, vb.as<uint32_t>(), s));
+        MCMI_HIP(hipMemcpyAsync(hv, vb.p, sizeof(hv), hipMemcpyDeviceToHost, s));
+        MCMI_HIP(hipStreamSynchronize(s));
+        if (hv[0] & 1u) return fail(MCMI_ERR_ARG, "mcmi_spai: a row index is outside [0, n)");
+        if (hv[0] & 2u) return fail(MCMI_ERR_ARG, "mcmi_spai: chains_per_row holds a value < 1");
+        if (chains_per_row_dev) n_max = (int)std::min<uint32_t>(hv[1], 1u << 30);
+    }
     const int cus = device_cus();
     const int n_hint = p->chains >= 1 ? p->chains : 64;
     KernelShape shape;
     {
-        const mcmi_status sst = choose_shape(cdf, p, lmax, shape);
+        const mcmi_status sst = choose_shape(cdf, p, lmax, n_max, shape);
         if (sst != MCMI_OK) return sst;
     }
     const int lanes = shape.lanes;
@@ -211,11 +234,18 @@ extern "C" mcmi_status mcmi_spai(const mcmi_cdf *cdf, const mcmi_params *p, cons
     const int sketch = shape.sketch;
     const double tau = shape.tau;
     int waves = 4;
-    int spill_slots = p->spill_slots ? p->spill_slots : (block_kernel ? 16384 : 4096);
+    int spill_slots = p->spill_slots;
+    if (!spill_slots) {
+        // wavefront kernel: room for every column a row's chains can reach (a row with
+        // many more chains than its neighbours would otherwise overflow and be rerun)
+        spill_slots = block_kernel ? 16384 : 4096;
+        const double reach = (double)std::max(n_max, 1) * ((double)std::max(lmax, 0) + 1.0);
+        while (!block_kernel && spill_slots < 32768 && (double)spill_slots < reach) spill_slots *= 2;
+    }
     // first guess of the output size; rows that do not fit are rerun into a new pool
     // a quarter of the row table per row: rows that overflow the first pool are
     // walked again, so a generous first guess (HBM is large) is the cheap side
-    int64_t per_row = p->pool_per_row ? p->pool_per_row : std::max(H / 4, 64);
+    int64_t per_row = p->pool_per_row ? p->pool_per_row : std::max(H / 4, std::min(H, 256));
     if (!p->pool_per_row && p->topk > 0) per_row = std::min<int64_t>(per_row, p->topk);  // exact bound
     int64_t pool_cap = n_tasks * per_row;
     pool_cap = std::min<int64_t>(pool_cap, (int64_t)1 << 31);
@@ -243,15 +273,6 @@ extern "C" mcmi_status mcmi_spai(const mcmi_cdf *cdf, const mcmi_params *p, cons
     uint32_t *flags = (uint32_t *)(ctrl.as<unsigned char>() + 72);
     unsigned long long *collect = (unsigned long long *)(ctrl.as<unsigned char>() + 80);
 
-    if (rows_dev || chains_per_row_dev) {
-        uint32_t hbad = 0;
-        MCMI_HIP(hipMemsetAsync(flags, 0, sizeof(uint32_t), s));
-        MCMI_HIP(validate_rows(rows_dev, rows_dev ? n_rows : 0, chains_per_row_dev, cdf->n, flags, s));
-        MCMI_HIP(hipMemcpyAsync(&hbad, flags, sizeof(hbad), hipMemcpyDeviceToHost, s));
-        MCMI_HIP(hipStreamSynchronize(s));
-        if (hbad & 1u) return fail(MCMI_ERR_ARG, "mcmi_spai: a row index is outside [0, n)");
-        if (hbad & 2u) return fail(MCMI_ERR_ARG, "mcmi_spai: chains_per_row holds a value < 1");
-    }
 
     // batched record sets: longest-processing-time order. Per-row cost N (L_k + 1)
     // with L_k the chain-length bound of matrix k; blocks of 64 consecutive rows (of

@@ -157,7 +157,7 @@ struct KernelShape {
 };
 struct mcmi_cdf;
 namespace mcmi {
-mcmi_status choose_shape(const mcmi_cdf *cdf, const mcmi_params *p, int lmax, KernelShape &out);
+mcmi_status choose_shape(const mcmi_cdf *cdf, const mcmi_params *p, int lmax, int n_max, KernelShape &out);
 }
 
 // Device-memory cache (alloc.hip): dev_alloc reuses a block released on the

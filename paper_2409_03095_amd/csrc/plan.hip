@@ -239,7 +239,8 @@ extern "C" mcmi_status mcmi_plan_create(const mcmi_cdf *cdf, const mcmi_params *
     pl->cap = nnz_capacity;
     pl->pool_cap = nnz_capacity;
     pl->lmax = lmax;
-    mcmi_status sst = choose_shape(cdf, p, lmax, pl->shape);
+    // per-row chain counts are not read back here: size the table for long rows
+    mcmi_status sst = choose_shape(cdf, p, lmax, chains_per_row_dev ? (1 << 20) : p->chains, pl->shape);
     if (sst != MCMI_OK) {
         delete pl;
         return sst;

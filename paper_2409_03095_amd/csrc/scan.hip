@@ -175,14 +175,22 @@ hipError_t collect_failed(int64_t n_slots, const int64_t *row_start, const uint3
 }
 
 // ------------------------------------------------------------ validation
-// rows[i] in [0, n) and chains_per_row[r] >= 1; sets bit 1 / bit 2 of *bad.
+// rows[i] in [0, n) and chains_per_row[r] >= 1; sets bit 1 / bit 2 of bad[0] and
+// the largest chains_per_row value in bad[1] (both cleared by the caller).
 __global__ void __launch_bounds__(256) k_validate(const int32_t *rows, int64_t n_rows, const int32_t *cpr,
                                                   int64_t n, uint32_t *bad) {
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    uint32_t most = 0;  // largest chain count seen, into bad[1] (one atomic per wave at most)
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n_rows || i < n; i += stride) {
         if (rows && i < n_rows && (rows[i] < 0 || (int64_t)rows[i] >= n)) atomicOr(bad, 1u);
-        if (cpr && i < n && cpr[i] < 1) atomicOr(bad, 2u);
+        if (cpr && i < n) {
+            const int32_t c = cpr[i];
+            if (c < 1) atomicOr(bad, 2u);
+            most = c > (int32_t)most ? (uint32_t)c : most;
+        }
     }
+    most = wave_max(most);
+    if ((threadIdx.x & 63) == 0 && most > __atomic_load_n(&bad[1], __ATOMIC_RELAXED)) atomicMax(&bad[1], most);
 }
 
 // Task map of the batched launch from its row blocks: block b lists `cnt[b]`
