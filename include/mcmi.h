@@ -92,7 +92,8 @@ typedef struct {
                              (one IEEE product per step); required when ||Chat||_inf >= 1 */
     uint32_t stream_tag;  /* fourth Philox counter word (distinguishes independent runs) */
     int32_t filter;       /* MCMI_FILTER_N: |N_rc| >= eps; MCMI_FILTER_M: |M_rc| >= eps */
-    int32_t lanes_per_row;/* 0 = automatic; 64 = one wavefront per row; 256, 512 or 1024 =
+    int32_t lanes_per_row;/* 0 = automatic; 64 = one wavefront per row; 8, 16 or 32 = 64 / that
+                             many rows share a wavefront (and its tables); 256, 512 or 1024 =
                              one workgroup of that many lanes per row */
     int32_t hash_slots;   /* 0 = automatic; else LDS hash slots per row (power of two) */
     int32_t sketch_slots; /* 0 = automatic; else count-sketch buckets per row (64..16384) */

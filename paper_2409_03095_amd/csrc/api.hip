@@ -69,21 +69,36 @@ int device_cus() {
 // Kernel shape of a run: lanes per row (64 = wavefront kernel), LDS hash slots,
 // count-sketch buckets and heavy threshold tau (0 = track every contribution).
 // n_max: the largest chain count of a row.
-mcmi_status choose_shape(const mcmi_cdf *cdf, const mcmi_params *p, int lmax, int n_max, KernelShape &out) {
+mcmi_status choose_shape(const mcmi_cdf *cdf, const mcmi_params *p, int lmax, int n_max, int n_typ,
+                         KernelShape &out) {
     const double m_bar = cdf->n > 0 ? (double)cdf->nnz_c / (double)cdf->n : 0.0;
     const int n_hint = p->chains >= 1 ? p->chains : 64;
     int lanes = p->lanes_per_row;
+    // One row per wavefront by default. Rows of few chains can share a wavefront
+    // (lanes_per_row 8, 16 or 32), but measured slower on the learned-allocation
+    // workloads: the rows of a wavefront finish together, so one row with many
+    // chains holds the others, and the shared table leaves fewer wavefronts per CU
+    // than small one-row tables do.
     if (lanes == 0) lanes = n_hint >= 384 ? 512 : (n_hint >= 192 ? 256 : 64);
     const bool block_kernel = lanes > 64;
     int H = p->hash_slots;
     if (!H && block_kernel) H = 4096;
-    if (!H) {
-        // wavefront kernel: a row's chains reach at most N (L + 1) columns; a table of
-        // that size (128 to 1024 slots) lets more wavefronts share a CU's LDS, which is
-        // what keeps enough rows in flight when rows have few chains
+    if (!H && lanes == 64) {
+        // one row per wavefront: a row's chains reach at most N (L + 1) columns; a
+        // table of that size (128 to 1024 slots) lets more wavefronts share a CU's
+        // LDS, which is what keeps enough rows in flight when rows have few chains
         const double reach = (double)std::max(n_max, 1) * ((double)std::max(lmax, 0) + 1.0);
         H = 128;
         while (H < 1024 && (double)H < reach) H *= 2;
+    }
+    if (!H) {
+        // 64 / lanes rows per wavefront, each with a table for its typical reach; at
+        // most 2048 slots (24 KB of LDS) per wavefront, so long chains mean fewer rows
+        const double reach = (double)std::max(n_typ, 1) * ((double)std::max(lmax, 0) + 1.0);
+        int Hg = 64;
+        while (Hg < 1024 && (double)Hg < reach) Hg *= 2;
+        while (lanes < 64 && Hg * (64 / lanes) > 2048) lanes *= 2;
+        H = lanes == 64 ? std::max(Hg, 128) : Hg * (64 / lanes);
     }
     if (block_kernel && !walk_block_supported(lanes, H))
         return fail(MCMI_ERR_ARG, "mcmi_spai: unsupported (lanes_per_row, hash_slots) for the workgroup kernel");
@@ -179,9 +194,9 @@ extern "C" mcmi_status mcmi_spai(const mcmi_cdf *cdf, const mcmi_params *p, cons
         return fail(MCMI_ERR_ARG, "mcmi_spai: hash_slots must be a power of two in [64, 8192]");
     if (p->sketch_slots && (p->sketch_slots < 64 || p->sketch_slots > 16384))
         return fail(MCMI_ERR_ARG, "mcmi_spai: sketch_slots must be in [64, 16384]");
-    if (p->lanes_per_row && p->lanes_per_row != 64 && p->lanes_per_row != 256 && p->lanes_per_row != 512 &&
-        p->lanes_per_row != 1024)
-        return fail(MCMI_ERR_ARG, "mcmi_spai: lanes_per_row must be 0, 64, 256, 512 or 1024");
+    if (p->lanes_per_row && p->lanes_per_row != 8 && p->lanes_per_row != 16 && p->lanes_per_row != 32 &&
+        p->lanes_per_row != 64 && p->lanes_per_row != 256 && p->lanes_per_row != 512 && p->lanes_per_row != 1024)
+        return fail(MCMI_ERR_ARG, "mcmi_spai: lanes_per_row must be 0, 8, 16, 32, 64, 256, 512 or 1024");
     if (!(p->heavy_weight <= 1.0)) return fail(MCMI_ERR_ARG, "mcmi_spai: heavy_weight must be <= 1");
     const int64_t n_tasks = rows_dev ? n_rows : cdf->n;
     if (rows_dev && (n_rows < 1 || n_rows > cdf->n)) return fail(MCMI_ERR_ARG, "mcmi_spai: bad n_rows");
@@ -208,9 +223,9 @@ extern "C" mcmi_status mcmi_spai(const mcmi_cdf *cdf, const mcmi_params *p, cons
     } evg{ev0, ev1, ev2};
 
     // ---- row list and chain counts (one synchronisation), then the kernel shape
-    int n_max = p->chains;
+    int n_max = p->chains, n_typ = p->chains;  // largest and mean chains of a row
     if (rows_dev || chains_per_row_dev) {
-        uint32_t hv[2] = {0, 0};
+        uint32_t hv[4] = {0, 0, 0, 0};
         DevBuf vb;
         MCMI_HIP(vb.alloc(sizeof(hv), s));
         MCMI_HIP(hipMemsetAsync(vb.p, 0, sizeof(hv), s));
@@ -219,33 +234,55 @@ extern "C" mcmi_status mcmi_spai(const mcmi_cdf *cdf, const mcmi_params *p, cons
         MCMI_HIP(hipStreamSynchronize(s));
         if (hv[0] & 1u) return fail(MCMI_ERR_ARG, "mcmi_spai: a row index is outside [0, n)");
         if (hv[0] & 2u) return fail(MCMI_ERR_ARG, "mcmi_spai: chains_per_row holds a value < 1");
-        if (chains_per_row_dev) n_max = (int)std::min<uint32_t>(hv[1], 1u << 30);
+        if (chains_per_row_dev) {
+            unsigned long long sum = 0;
+            ::memcpy(&sum, hv + 2, sizeof(sum));
+            n_max = (int)std::min<uint32_t>(hv[1], 1u << 30);
+            n_typ = (int)std::min<unsigned long long>((sum + (unsigned long long)cdf->n - 1) / (unsigned long long)cdf->n,
+                                                       1ull << 30);
+        }
     }
     const int cus = device_cus();
     const int n_hint = p->chains >= 1 ? p->chains : 64;
     KernelShape shape;
     {
-        const mcmi_status sst = choose_shape(cdf, p, lmax, n_max, shape);
+        const mcmi_status sst = choose_shape(cdf, p, lmax, n_max, n_typ, shape);
         if (sst != MCMI_OK) return sst;
     }
-    const int lanes = shape.lanes;
+    int lanes = shape.lanes;
     const bool block_kernel = lanes > 64;
     int H = shape.hash;
     const int sketch = shape.sketch;
     const double tau = shape.tau;
     int waves = 4;
+    int rows_per_wave = block_kernel ? 1 : 64 / lanes;
     int spill_slots = p->spill_slots;
     if (!spill_slots) {
         // wavefront kernel: room for every column a row's chains can reach (a row with
-        // many more chains than its neighbours would otherwise overflow and be rerun)
-        spill_slots = block_kernel ? 16384 : 4096;
+        // many more chains than its neighbours would otherwise overflow and be rerun);
+        // the wave's table is shared out among its rows
         const double reach = (double)std::max(n_max, 1) * ((double)std::max(lmax, 0) + 1.0);
-        while (!block_kernel && spill_slots < 32768 && (double)spill_slots < reach) spill_slots *= 2;
+        if (block_kernel) {
+            spill_slots = 16384;
+        } else if (rows_per_wave == 1) {
+            spill_slots = 4096;
+            while (spill_slots < 32768 && (double)spill_slots < reach) spill_slots *= 2;
+        } else {
+            int sg = 1024;
+            while (sg < 32768 / rows_per_wave && (double)sg < reach) sg *= 2;
+            spill_slots = sg * rows_per_wave;
+        }
+    }
+    // fewer rows per wavefront when given tables are too small to share out
+    while (!block_kernel && rows_per_wave > 1 && (spill_slots / rows_per_wave < 16 || H / rows_per_wave < 64)) {
+        lanes *= 2;
+        rows_per_wave /= 2;
     }
     // first guess of the output size; rows that do not fit are rerun into a new pool
     // a quarter of the row table per row: rows that overflow the first pool are
     // walked again, so a generous first guess (HBM is large) is the cheap side
-    int64_t per_row = p->pool_per_row ? p->pool_per_row : std::max(H / 4, std::min(H, 256));
+    const int h_row = H / rows_per_wave;
+    int64_t per_row = p->pool_per_row ? p->pool_per_row : std::max(h_row / 4, std::min(h_row, 256));
     if (!p->pool_per_row && p->topk > 0) per_row = std::min<int64_t>(per_row, p->topk);  // exact bound
     int64_t pool_cap = n_tasks * per_row;
     pool_cap = std::min<int64_t>(pool_cap, (int64_t)1 << 31);
@@ -393,6 +430,7 @@ extern "C" mcmi_status mcmi_spai(const mcmi_cdf *cdf, const mcmi_params *p, cons
         a.topk = p->topk;
         a.hash_slots = H;
         a.hash_shift = 32 - __builtin_ctz((unsigned)H);
+        a.row_lanes = block_kernel ? 0 : lanes;
         a.queue_ctr = qctr;
         a.row_start = row_start.as<int64_t>();
         a.row_cnt = row_cnt.as<uint32_t>();
@@ -444,10 +482,16 @@ extern "C" mcmi_status mcmi_spai(const mcmi_cdf *cdf, const mcmi_params *p, cons
             if (block_kernel) {
                 if (!walk_block_supported(lanes, H * 2))
                     return fail(MCMI_ERR_CAPACITY, "mcmi_spai: more survivors per row than the workgroup table holds");
-            } else if (H >= 8192) {
-                return fail(MCMI_ERR_CAPACITY, "mcmi_spai: more survivors per row than 8192 slots");
+                H *= 2;
+            } else if (rows_per_wave > 1) {
+                // the rerun gives each row a wavefront and twice its table
+                H = 2 * (H / rows_per_wave);
+                lanes = 64;
+                rows_per_wave = 1;
+            } else {
+                if (H >= 8192) return fail(MCMI_ERR_CAPACITY, "mcmi_spai: more survivors per row than 8192 slots");
+                H *= 2;
             }
-            H *= 2;
         }
     }
     MCMI_HIP(hipEventElapsedTime(&ms_walk, ev1, ev2));

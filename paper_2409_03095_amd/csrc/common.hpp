@@ -157,7 +157,8 @@ struct KernelShape {
 };
 struct mcmi_cdf;
 namespace mcmi {
-mcmi_status choose_shape(const mcmi_cdf *cdf, const mcmi_params *p, int lmax, int n_max, KernelShape &out);
+mcmi_status choose_shape(const mcmi_cdf *cdf, const mcmi_params *p, int lmax, int n_max, int n_typ,
+                         KernelShape &out);
 }
 
 // Device-memory cache (alloc.hip): dev_alloc reuses a block released on the

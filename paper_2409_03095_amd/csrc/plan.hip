@@ -240,7 +240,8 @@ extern "C" mcmi_status mcmi_plan_create(const mcmi_cdf *cdf, const mcmi_params *
     pl->pool_cap = nnz_capacity;
     pl->lmax = lmax;
     // per-row chain counts are not read back here: size the table for long rows
-    mcmi_status sst = choose_shape(cdf, p, lmax, chains_per_row_dev ? (1 << 20) : p->chains, pl->shape);
+    mcmi_status sst = choose_shape(cdf, p, lmax, chains_per_row_dev ? (1 << 20) : p->chains,
+                                   chains_per_row_dev ? 64 : p->chains, pl->shape);
     if (sst != MCMI_OK) {
         delete pl;
         return sst;
@@ -300,6 +301,7 @@ extern "C" mcmi_status mcmi_plan_create(const mcmi_cdf *cdf, const mcmi_params *
     a.roff = cdf->roff;
     a.diag = cdf->diag;
     a.n_tasks = pl->n;
+    a.row_lanes = block_kernel ? 0 : pl->shape.lanes;
     a.task_map = cdf->batch == 0 ? cdf->order : nullptr;  // locality schedule, if the set has one
     a.chains_per_row = chains_per_row_dev;
     a.chains = p->chains;

@@ -175,22 +175,51 @@ hipError_t collect_failed(int64_t n_slots, const int64_t *row_start, const uint3
 }
 
 // ------------------------------------------------------------ validation
-// rows[i] in [0, n) and chains_per_row[r] >= 1; sets bit 1 / bit 2 of bad[0] and
-// the largest chains_per_row value in bad[1] (both cleared by the caller).
+// rows[i] in [0, n) and chains_per_row[r] >= 1; sets bit 1 / bit 2 of bad[0], the
+// largest chains_per_row value in bad[1] and their sum in bad[2..3] (a u64); all
+// cleared by the caller. One atomic per workgroup and quantity.
 __global__ void __launch_bounds__(256) k_validate(const int32_t *rows, int64_t n_rows, const int32_t *cpr,
                                                   int64_t n, uint32_t *bad) {
+    __shared__ uint32_t red_max[4];
+    __shared__ unsigned long long red_sum[4];
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    uint32_t most = 0;  // largest chain count seen, into bad[1] (one atomic per wave at most)
+    uint32_t most = 0;
+    unsigned long long sum = 0;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n_rows || i < n; i += stride) {
         if (rows && i < n_rows && (rows[i] < 0 || (int64_t)rows[i] >= n)) atomicOr(bad, 1u);
         if (cpr && i < n) {
             const int32_t c = cpr[i];
             if (c < 1) atomicOr(bad, 2u);
             most = c > (int32_t)most ? (uint32_t)c : most;
+            sum += c > 0 ? (unsigned long long)c : 0ull;
         }
     }
     most = wave_max(most);
-    if ((threadIdx.x & 63) == 0 && most > __atomic_load_n(&bad[1], __ATOMIC_RELAXED)) atomicMax(&bad[1], most);
+    sum = wave_sum(sum);
+    const int w = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0) {
+        red_max[w] = most;
+        red_sum[w] = sum;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0 && cpr) {
+        for (int k = 1; k < (int)(blockDim.x >> 6); ++k) {
+            most = red_max[k] > most ? red_max[k] : most;
+            sum += red_sum[k];
+        }
+        if (most > __atomic_load_n(&bad[1], __ATOMIC_RELAXED)) atomicMax(&bad[1], most);
+        if (sum) atomicAdd((unsigned long long *)(bad + 2), sum);
+    }
+}
+
+hipError_t validate_rows(const int32_t *rows, int64_t n_rows, const int32_t *cpr, int64_t n, uint32_t *bad,
+                         hipStream_t s) {
+    const int64_t m = n_rows > n ? n_rows : n;
+    int64_t blocks = (m + 255) / 256;
+    if (blocks > 1024) blocks = 1024;
+    if (blocks < 1) blocks = 1;
+    k_validate<<<(unsigned)blocks, 256, 0, s>>>(rows, n_rows, cpr, n, bad);
+    return hipGetLastError();
 }
 
 // Task map of the batched launch from its row blocks: block b lists `cnt[b]`
@@ -211,16 +240,6 @@ hipError_t expand_blocks(int64_t nblocks, const int32_t *start, const int32_t *c
     if (nblocks <= 0) return hipSuccess;
     const int64_t g = nblocks < 65536 ? nblocks : 65536;
     k_expand_blocks<<<(unsigned)g, 64, 0, s>>>(nblocks, start, cnt, pos, order, out);
-    return hipGetLastError();
-}
-
-hipError_t validate_rows(const int32_t *rows, int64_t n_rows, const int32_t *cpr, int64_t n, uint32_t *bad,
-                         hipStream_t s) {
-    const int64_t m = n_rows > n ? n_rows : n;
-    int64_t blocks = (m + 255) / 256;
-    if (blocks > 4096) blocks = 4096;
-    if (blocks < 1) blocks = 1;
-    k_validate<<<(unsigned)blocks, 256, 0, s>>>(rows, n_rows, cpr, n, bad);
     return hipGetLastError();
 }
 

@@ -6,7 +6,8 @@
 // Section IV-A, phase 4 scales column c by 1 / d_c, and the filter keeps the
 // diagonal and every entry with |N_rc| >= eps.
 //
-// Design (one wavefront owns one row at a time, persistent grid):
+// Design (one wavefront owns one row at a time, or 64 / G rows of G lanes each when
+// rows have few chains; persistent grid):
 //  * rows come from eight work queues, one per XCD (workgroups are dispatched
 //    round-robin over the XCDs, so blockIdx % 8 picks the XCD), each a contiguous
 //    slice of the rows so that neighbouring rows share their L2; a wave whose
@@ -16,9 +17,10 @@
 //    other;
 //  * a step draws one Philox word and reads the 64-byte alias bucket it names,
 //    which also carries the next state's header: one random line per step;
-//  * contributions go to an open-addressing hash per wave in LDS (key = column,
-//    value = float64 sum, LDS float64 atomics); a full neighbourhood spills to a
-//    per-wave hash in HBM;
+//  * contributions go to an open-addressing hash per row in LDS (key = column,
+//    value = float64 sum, LDS float64 atomics; the wave's table split among its
+//    rows); a full neighbourhood spills to a per-row share of the wave's HBM hash;
+//  * the rows of a wave start together and are finalized one after the other;
 //  * at the end of the row the wave filters the slots with a ballot, compacts the
 //    survivors in place, scales them by 1 / d_c, sorts them by column with a
 //    bitonic network in LDS and appends them to an output pool.
@@ -88,27 +90,41 @@ __device__ __forceinline__ void row_hdr(const WalkArgs &a, RowPre &p) {
     if (p.task >= 0) load_header<kF32>(a.rec, p.r_off, p.h0);
 }
 
-template <bool kF32>
-__device__ __forceinline__ void walk_row(const WalkArgs &a, const RowPre &cur, RowPre &nxt, int &queue, int64_t &tlo,
+// The 64 / kG rows of one wave (one per group of kG lanes; cur and nxt hold each
+// lane's own group's row).
+template <bool kF32, int kG>
+__device__ __forceinline__ void walk_rows(const WalkArgs &a, const RowPre &cur, RowPre &nxt, int &queue, int64_t &tlo,
                          int64_t &thi, int32_t *keys, double *vals, int *spill_cnt,
                          int32_t *skeys, double *svals, int32_t *sused, uint32_t k0, uint32_t k1,
                          unsigned long long &pcur, unsigned long long &pend, unsigned long long *wstats) {
+    constexpr int P = 64 / kG;  // rows per wave
+    constexpr int kLogP = P == 1 ? 0 : P == 2 ? 1 : P == 4 ? 2 : 3;
     const int lane = lane_id();
-    const uint32_t hmask = (uint32_t)a.hash_slots - 1u;
-    const uint32_t smask = (uint32_t)a.spill_slots - 1u;
-    const int64_t slot = cur.slot;
-    const int32_t r = cur.r;
-    const int32_t N = cur.N;
-    const uint32_t r_off = cur.r_off;
-    uint32_t prow, ptag;
-    philox_ids(a, r, prow, ptag);
+    const int grp = lane / kG;
+    const int sub = lane & (kG - 1);
+    const int Hg = a.hash_slots / P;  // slots per row
+    const int hshift = a.hash_shift + kLogP;
+    const uint32_t hmask = (uint32_t)Hg - 1u;
+    const int Sg = a.spill_slots / P;
+    const uint32_t smask = (uint32_t)Sg - 1u;
+    int32_t *gkeys = keys + grp * Hg;
+    double *gvals = vals + grp * Hg;
+    int32_t *gskeys = skeys + (size_t)grp * Sg;
+    double *gsvals = svals + (size_t)grp * Sg;
+    int32_t *gsused = sused + (size_t)grp * Sg;
+    const bool has = cur.task >= 0;
+    const int32_t r = has ? cur.r : 0;
+    const int32_t N = has ? cur.N : 0;
+    const uint32_t r_off = has ? cur.r_off : 0u;
+    uint32_t prow = 0, ptag = 0;
+    if (has) philox_ids(a, r, prow, ptag);
 
     // j = 0: every chain contributes W_0 = 1 at (r, r); N ones sum exactly to N.
-    if (lane == 0) lds_add(keys, vals, hmask, hash_key(r, a.hash_shift), r, (double)N);
+    if (sub == 0 && has) lds_add(gkeys, gvals, hmask, hash_key(r, hshift), r, (double)N);
     wave_sync();
 
-    int32_t c = lane;
-    bool active = c < N;
+    int32_t c = sub;
+    bool active = has && c < N;
     uint32_t off = r_off;
     uint32_t j = 0;
     double w64 = 1.0;
@@ -128,9 +144,9 @@ __device__ __forceinline__ void walk_row(const WalkArgs &a, const RowPre &cur, R
             if (j > 0) {
                 const int32_t key = (int32_t)h.x;
                 const double w = kF32 ? (double)w32 : w64;
-                if (!lds_add(keys, vals, hmask, hash_key(key, a.hash_shift), key, w)) {
+                if (!lds_add(gkeys, gvals, hmask, hash_key(key, hshift), key, w)) {
                     ++spilled;
-                    if (!spill_add(skeys, svals, sused, spill_cnt, smask, key, w)) spill_full = true;
+                    if (!spill_add(gskeys, gsvals, gsused, spill_cnt + grp, smask, key, w)) spill_full = true;
                 }
             }
             bool stop = (h.y == 0u) || (j >= (uint32_t)a.lmax);
@@ -145,7 +161,7 @@ __device__ __forceinline__ void walk_row(const WalkArgs &a, const RowPre &cur, R
             }
             if (stop) {
                 trans += j;
-                c += 64;
+                c += kG;
                 if (c < N) {
                     off = r_off;
                     H = H0;
@@ -176,194 +192,221 @@ __device__ __forceinline__ void walk_row(const WalkArgs &a, const RowPre &cur, R
         }
     }
     wave_sync();
-    // the next row's ids and record offset load now, its header during the
-    // finalize: both latencies hide behind this row's finalize
-    row_ids(a, next_task(a, queue, tlo, thi), nxt);
-
-    // ---------------------------------------------------------- finalize
-    const double nd = (double)N;
-    int K = 0;
-    for (int base = 0; base < a.hash_slots; base += 64) {
-        const int s = base + lane;
-        const int32_t key = keys[s];
-        const double acc = vals[s];
-        bool keep = false;
-        double nhat = 0.0;
-        if (key != kEmpty) {
-            nhat = acc / nd;  // N_rc; scaled by 1 / d_c once the kept set is final
-            const double test = a.filter_m ? fabs(nhat / a.diag[key]) : fabs(nhat);
-            keep = key == r || (nhat != 0.0 && test >= a.eps);
-        }
-        const uint64_t km = ballot(keep);
-        wave_sync();
-        if (keep) {
-            const int pos = K + mask_rank(km);
-            keys[pos] = key;
-            vals[pos] = nhat;
-        }
-        K += __popcll(km);
+    // the next rows' ids and record offsets load now, their headers during the
+    // finalize: both latencies hide behind these rows' finalize
+#pragma unroll
+    for (int g = 0; g < P; ++g) {
+        const int64_t t = next_task(a, queue, tlo, thi);
+        if (grp == g) row_ids(a, t, nxt);
     }
-    wave_sync();
-    row_hdr<kF32>(a, nxt);
-    const int nsp = *spill_cnt;
-    bool stage_full = false;
-    for (int base = 0; base < nsp; base += 64) {
-        const int u = base + lane;
-        bool keep = false;
-        int32_t key = kEmpty;
-        double nhat = 0.0;
-        if (u < nsp) {
-            const int32_t slot = sused[u];
-            key = skeys[slot];
-            nhat = svals[slot] / nd;
-            const double test = a.filter_m ? fabs(nhat / a.diag[key]) : fabs(nhat);
-            keep = key == r || (nhat != 0.0 && test >= a.eps);
-            skeys[slot] = kEmpty;
-            svals[slot] = 0.0;
-        }
-        const uint64_t km = ballot(keep);
-        if (keep) {
-            const int pos = K + mask_rank(km);
-            if (pos < a.hash_slots) {
-                keys[pos] = key;
-                vals[pos] = nhat;
-            } else {
-                stage_full = true;
+
+    // ---------------------------------------------------------- finalize, row by row
+    bool hdr_issued = false;
+#pragma unroll 1
+    for (int g = 0; g < P; ++g) {
+        if (__shfl((int)has, g * kG, 64) == 0) continue;  // no row in this group
+        const int32_t rg = __shfl(r, g * kG, 64);
+        const int32_t Ng = __shfl(N, g * kG, 64);
+        const int64_t slot = (int64_t)(((uint64_t)(uint32_t)__shfl((int)(cur.slot >> 32), g * kG, 64) << 32) |
+                                       (uint32_t)__shfl((int)(uint32_t)cur.slot, g * kG, 64));
+        int32_t *tk = keys + g * Hg;
+        double *tv = vals + g * Hg;
+        int32_t *tsk = skeys + (size_t)g * Sg;
+        double *tsv = svals + (size_t)g * Sg;
+        const int32_t *tsu = sused + (size_t)g * Sg;
+        const double nd = (double)Ng;
+        int K = 0;
+        for (int base = 0; base < Hg; base += 64) {
+            const int s = base + lane;
+            int32_t key = kEmpty;
+            double acc = 0.0;
+            if (s < Hg) {
+                key = tk[s];
+                acc = tv[s];
             }
-        }
-        K += __popcll(km);
-    }
-    if (K > a.hash_slots) K = a.hash_slots;
-    wave_sync();
-
-    // top-k retention: bitonic sort in retention order, keep the first topk,
-    // then turn N_rc into M_rc = N_rc / d_c
-    if (a.topk > 0) {
-        if (K > a.topk) {
-            int PT = 1;
-            while (PT < K) PT <<= 1;
-            for (int s = K + lane; s < PT; s += 64) keys[s] = INT32_MAX;
+            bool keep = false;
+            double nhat = 0.0;
+            if (key != kEmpty) {
+                nhat = acc / nd;  // N_rc; scaled by 1 / d_c once the kept set is final
+                const double test = a.filter_m ? fabs(nhat / a.diag[key]) : fabs(nhat);
+                keep = key == rg || (nhat != 0.0 && test >= a.eps);
+            }
+            const uint64_t km = ballot(keep);
             wave_sync();
-            for (int k = 2; k <= PT; k <<= 1) {
-                for (int jj = k >> 1; jj > 0; jj >>= 1) {
-                    for (int i = lane; i < PT; i += 64) {
-                        const int ixj = i ^ jj;
-                        if (ixj > i) {
-                            const int32_t ka = keys[i], kb = keys[ixj];
-                            const double va = vals[i], vb = vals[ixj];
-                            if (top_after(a, r, ka, va, kb, vb) == ((i & k) == 0)) {
-                                keys[i] = kb;
-                                keys[ixj] = ka;
-                                vals[i] = vb;
-                                vals[ixj] = va;
+            if (keep) {
+                const int pos = K + mask_rank(km);
+                tk[pos] = key;
+                tv[pos] = nhat;
+            }
+            K += __popcll(km);
+        }
+        wave_sync();
+        if (!hdr_issued) {
+            row_hdr<kF32>(a, nxt);
+            hdr_issued = true;
+        }
+        const int nsp = spill_cnt[g];
+        bool stage_full = false;
+        for (int base = 0; base < nsp; base += 64) {
+            const int u = base + lane;
+            bool keep = false;
+            int32_t key = kEmpty;
+            double nhat = 0.0;
+            if (u < nsp) {
+                const int32_t sl = tsu[u];
+                key = tsk[sl];
+                nhat = tsv[sl] / nd;
+                const double test = a.filter_m ? fabs(nhat / a.diag[key]) : fabs(nhat);
+                keep = key == rg || (nhat != 0.0 && test >= a.eps);
+                tsk[sl] = kEmpty;
+                tsv[sl] = 0.0;
+            }
+            const uint64_t km = ballot(keep);
+            if (keep) {
+                const int pos = K + mask_rank(km);
+                if (pos < Hg) {
+                    tk[pos] = key;
+                    tv[pos] = nhat;
+                } else {
+                    stage_full = true;
+                }
+            }
+            K += __popcll(km);
+        }
+        if (K > Hg) K = Hg;
+        wave_sync();
+
+        // top-k retention: bitonic sort in retention order, keep the first topk,
+        // then turn N_rc into M_rc = N_rc / d_c
+        if (a.topk > 0) {
+            if (K > a.topk) {
+                int PT = 1;
+                while (PT < K) PT <<= 1;
+                for (int s = K + lane; s < PT; s += 64) tk[s] = INT32_MAX;
+                wave_sync();
+                for (int k = 2; k <= PT; k <<= 1) {
+                    for (int jj = k >> 1; jj > 0; jj >>= 1) {
+                        for (int i = lane; i < PT; i += 64) {
+                            const int ixj = i ^ jj;
+                            if (ixj > i) {
+                                const int32_t ka = tk[i], kb = tk[ixj];
+                                const double va = tv[i], vb = tv[ixj];
+                                if (top_after(a, rg, ka, va, kb, vb) == ((i & k) == 0)) {
+                                    tk[i] = kb;
+                                    tk[ixj] = ka;
+                                    tv[i] = vb;
+                                    tv[ixj] = va;
+                                }
                             }
                         }
-                    }
-                    wave_sync();
-                }
-            }
-            K = a.topk;
-        }
-    }
-    // M_rc = N_rc / d_c for the kept entries only, four independent loads per lane
-    // in flight (the eps test on N_rc needs no diagonal)
-    for (int i0 = lane; i0 < K; i0 += 256) {
-        double d[4];
-#pragma unroll
-        for (int q = 0; q < 4; ++q) d[q] = i0 + 64 * q < K ? a.diag[keys[i0 + 64 * q]] : 1.0;
-#pragma unroll
-        for (int q = 0; q < 4; ++q)
-            if (i0 + 64 * q < K) vals[i0 + 64 * q] = vals[i0 + 64 * q] / d[q];
-    }
-    wave_sync();
-
-    // bitonic sort of keys[0..P) by column, padding with INT32_MAX
-    int P = 1;
-    while (P < K) P <<= 1;
-    for (int s = K + lane; s < P; s += 64) keys[s] = INT32_MAX;
-    wave_sync();
-    for (int k = 2; k <= P; k <<= 1) {
-        for (int jj = k >> 1; jj > 0; jj >>= 1) {
-            for (int i = lane; i < P; i += 64) {
-                const int ixj = i ^ jj;
-                if (ixj > i) {
-                    const int32_t ka = keys[i], kb = keys[ixj];
-                    const bool up = (i & k) == 0;
-                    if ((ka > kb) == up) {
-                        const double va = vals[i], vb = vals[ixj];
-                        keys[i] = kb;
-                        keys[ixj] = ka;
-                        vals[i] = vb;
-                        vals[ixj] = va;
+                        wave_sync();
                     }
                 }
+                K = a.topk;
             }
-            wave_sync();
         }
-    }
+        // M_rc = N_rc / d_c for the kept entries only, four independent loads per lane
+        // in flight (the eps test on N_rc needs no diagonal)
+        for (int i0 = lane; i0 < K; i0 += 256) {
+            double d[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) d[q] = i0 + 64 * q < K ? a.diag[tk[i0 + 64 * q]] : 1.0;
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+                if (i0 + 64 * q < K) tv[i0 + 64 * q] = tv[i0 + 64 * q] / d[q];
+        }
+        wave_sync();
 
-    // append to the pool unless a table overflowed for this row (then it is rerun)
-    const bool row_spill_full = __any(spill_full);
-    const bool row_stage_full = __any(stage_full);
-    unsigned long long pos0 = 0;
-    if (lane == 0 && !row_spill_full && !row_stage_full) {
-        if (a.pool_chunk > 0) {
-            // the wave's reservation: one global atomic per pool_chunk entries
-            if (pcur + (unsigned long long)K > pend) {
-                const unsigned long long grab = (unsigned long long)(K > a.pool_chunk ? K : a.pool_chunk);
-                pcur = atomicAdd(a.pool_used, grab);
-                pend = pcur + grab;
+        // bitonic sort of tk[0..PS) by column, padding with INT32_MAX
+        int PS = 1;
+        while (PS < K) PS <<= 1;
+        for (int s = K + lane; s < PS; s += 64) tk[s] = INT32_MAX;
+        wave_sync();
+        for (int k = 2; k <= PS; k <<= 1) {
+            for (int jj = k >> 1; jj > 0; jj >>= 1) {
+                for (int i = lane; i < PS; i += 64) {
+                    const int ixj = i ^ jj;
+                    if (ixj > i) {
+                        const int32_t ka = tk[i], kb = tk[ixj];
+                        const bool up = (i & k) == 0;
+                        if ((ka > kb) == up) {
+                            const double va = tv[i], vb = tv[ixj];
+                            tk[i] = kb;
+                            tk[ixj] = ka;
+                            tv[i] = vb;
+                            tv[ixj] = va;
+                        }
+                    }
+                }
+                wave_sync();
             }
-            pos0 = pcur;
-            pcur += (unsigned long long)K;
-        } else {
-            pos0 = atomicAdd(a.pool_used, (unsigned long long)K);
         }
-    }
-    pos0 = __shfl(pos0, 0, 64);
-    const bool fits = (int64_t)(pos0 + (unsigned long long)K) <= a.pool_cap;
-    const bool ok = fits && !row_spill_full && !row_stage_full;
-    if (ok) {
-        for (int i = lane; i < K; i += 64) {
-            a.pool_col[pos0 + i] = keys[i];
-            a.pool_val[pos0 + i] = vals[i];
+
+        // append to the pool unless a table overflowed for this row (then it is rerun)
+        const bool row_spill_full = __any(spill_full && grp == g);
+        const bool row_stage_full = __any(stage_full);
+        unsigned long long pos0 = 0;
+        if (lane == 0 && !row_spill_full && !row_stage_full) {
+            if (a.pool_chunk > 0) {
+                // the wave's reservation: one global atomic per pool_chunk entries
+                if (pcur + (unsigned long long)K > pend) {
+                    const unsigned long long grab = (unsigned long long)(K > a.pool_chunk ? K : a.pool_chunk);
+                    pcur = atomicAdd(a.pool_used, grab);
+                    pend = pcur + grab;
+                }
+                pos0 = pcur;
+                pcur += (unsigned long long)K;
+            } else {
+                pos0 = atomicAdd(a.pool_used, (unsigned long long)K);
+            }
         }
-    }
-    trans = wave_sum(trans);
-    spilled = wave_sum(spilled);
-    if (lane == 0) {
-        a.row_start[slot] = ok ? ((int64_t)pos0 | a.pool_tag) : -1;
-        a.row_cnt[slot] = (uint32_t)K;
-        uint32_t f = 0;
-        if (!fits && !row_spill_full && !row_stage_full) f |= kFlagPool;
-        if (row_spill_full) f |= kFlagSpill;
-        if (row_stage_full) f |= kFlagStage;
-        if (f) atomicOr(a.flags, f);
+        pos0 = __shfl(pos0, 0, 64);
+        const bool fits = (int64_t)(pos0 + (unsigned long long)K) <= a.pool_cap;
+        const bool ok = fits && !row_spill_full && !row_stage_full;
         if (ok) {
-            wstats[0] += trans;
-            wstats[2] += (unsigned long long)N;
+            for (int i = lane; i < K; i += 64) {
+                a.pool_col[pos0 + i] = tk[i];
+                a.pool_val[pos0 + i] = tv[i];
+            }
         }
-        wstats[1] += spilled;
+        const unsigned long long tg = wave_sum(grp == g ? trans : 0ull);
+        const unsigned long long sg = wave_sum(grp == g ? spilled : 0ull);
+        if (lane == 0) {
+            a.row_start[slot] = ok ? ((int64_t)pos0 | a.pool_tag) : -1;
+            a.row_cnt[slot] = (uint32_t)K;
+            uint32_t f = 0;
+            if (!fits && !row_spill_full && !row_stage_full) f |= kFlagPool;
+            if (row_spill_full) f |= kFlagSpill;
+            if (row_stage_full) f |= kFlagStage;
+            if (f) atomicOr(a.flags, f);
+            if (ok) {
+                wstats[0] += tg;
+                wstats[2] += (unsigned long long)Ng;
+            }
+            wstats[1] += sg;
+        }
+        // clear this row's table for the next row of its group
+        wave_sync();
+        for (int s = lane; s < Hg; s += 64) {
+            tk[s] = kEmpty;
+            tv[s] = 0.0;
+        }
+        if (lane == 0) spill_cnt[g] = 0;
+        wave_sync();
     }
-    // clear for the next row
-    wave_sync();
-    for (int s = lane; s < a.hash_slots; s += 64) {
-        keys[s] = kEmpty;
-        vals[s] = 0.0;
-    }
-    if (lane == 0) *spill_cnt = 0;
-    wave_sync();
+    if (!hdr_issued) row_hdr<kF32>(a, nxt);
 }
 
-template <bool kF32>
+template <bool kF32, int kG>
 __global__ void __launch_bounds__(256) k_walk(WalkArgs a) {
+    constexpr int P = 64 / kG;
     extern __shared__ __align__(16) unsigned char smem[];
     const int waves = blockDim.x >> 6;
     const int w = threadIdx.x >> 6;
     const int lane = lane_id();
     const int H = a.hash_slots;
-    // per wave: vals[H] (f64), keys[H] (i32), spill counter
-    const size_t per_wave = (size_t)H * 12u + 16u;
+    // per wave: vals[H] (f64), keys[H] (i32), one spill counter per row (64 bytes)
+    const size_t per_wave = (size_t)H * 12u + 64u;
     unsigned char *mine = smem + (size_t)w * per_wave;
     double *vals = (double *)mine;
     int32_t *keys = (int32_t *)(mine + (size_t)H * 8u);
@@ -372,7 +415,7 @@ __global__ void __launch_bounds__(256) k_walk(WalkArgs a) {
         keys[s] = kEmpty;
         vals[s] = 0.0;
     }
-    if (lane == 0) *spill_cnt = 0;
+    if (lane < P) spill_cnt[lane] = 0;
     wave_sync();
     const int64_t gw = (int64_t)blockIdx.x * waves + w;
     int32_t *skeys = a.spill_keys + gw * a.spill_slots;
@@ -383,13 +426,18 @@ __global__ void __launch_bounds__(256) k_walk(WalkArgs a) {
     const uint32_t k1 = a.keys_dev ? a.keys_dev[1] : a.key1;
     unsigned long long pcur = 0, pend = 0, wstats[3] = {0, 0, 0};
     int64_t tlo = 0, thi = 0;
+    const int grp = lane / kG;
     RowPre cur;
-    row_ids(a, next_task(a, queue, tlo, thi), cur);
+#pragma unroll
+    for (int g = 0; g < P; ++g) {
+        const int64_t t = next_task(a, queue, tlo, thi);
+        if (grp == g) row_ids(a, t, cur);
+    }
     row_hdr<kF32>(a, cur);
-    while (cur.task >= 0) {
+    while (__any(cur.task >= 0)) {
         RowPre nxt;
-        walk_row<kF32>(a, cur, nxt, queue, tlo, thi, keys, vals, spill_cnt, skeys, svals, sused, k0, k1, pcur, pend,
-                       wstats);
+        walk_rows<kF32, kG>(a, cur, nxt, queue, tlo, thi, keys, vals, spill_cnt, skeys, svals, sused, k0, k1, pcur,
+                            pend, wstats);
         cur = nxt;
     }
     // statistics: one set of atomics per wave
@@ -402,21 +450,31 @@ __global__ void __launch_bounds__(256) k_walk(WalkArgs a) {
 
 }  // namespace
 
-size_t walk_lds_bytes(int hash_slots, int waves) { return (size_t)waves * ((size_t)hash_slots * 12u + 16u); }
+size_t walk_lds_bytes(int hash_slots, int waves) { return (size_t)waves * ((size_t)hash_slots * 12u + 64u); }
 
-hipError_t launch_walk(const WalkArgs &a, bool f32, int blocks, int waves, hipStream_t s) {
+template <bool kF32>
+hipError_t launch_walk_t(const WalkArgs &a, int blocks, int waves, hipStream_t s) {
     const size_t lds = walk_lds_bytes(a.hash_slots, waves);
-    if (f32)
-        k_walk<true><<<blocks, waves * 64, lds, s>>>(a);
-    else
-        k_walk<false><<<blocks, waves * 64, lds, s>>>(a);
+    switch (a.row_lanes) {
+        case 8: k_walk<kF32, 8><<<blocks, waves * 64, lds, s>>>(a); break;
+        case 16: k_walk<kF32, 16><<<blocks, waves * 64, lds, s>>>(a); break;
+        case 32: k_walk<kF32, 32><<<blocks, waves * 64, lds, s>>>(a); break;
+        default: k_walk<kF32, 64><<<blocks, waves * 64, lds, s>>>(a); break;
+    }
     return hipGetLastError();
 }
 
+hipError_t launch_walk(const WalkArgs &a, bool f32, int blocks, int waves, hipStream_t s) {
+    if (a.row_lanes != 0 && a.row_lanes != 8 && a.row_lanes != 16 && a.row_lanes != 32 && a.row_lanes != 64)
+        return hipErrorInvalidValue;
+    return f32 ? launch_walk_t<true>(a, blocks, waves, s) : launch_walk_t<false>(a, blocks, waves, s);
+}
+
 hipError_t walk_occupancy(bool f32, int hash_slots, int waves, int *blocks_per_cu) {
+    // the instances differ only in loop bounds; the 64-lane one stands for all
     const size_t lds = walk_lds_bytes(hash_slots, waves);
-    if (f32) return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k_walk<true>, waves * 64, lds);
-    return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k_walk<false>, waves * 64, lds);
+    if (f32) return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k_walk<true, 64>, waves * 64, lds);
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k_walk<false, 64>, waves * 64, lds);
 }
 
 }  // namespace mcmi

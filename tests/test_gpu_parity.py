@@ -318,3 +318,38 @@ def test_memory_cache_reuse_across_streams_and_trim(mc):
             assert np.array_equal(a, b), it
         if it == 3:
             mc.cache_trim()
+
+
+# ------------------------------------------- several rows per wavefront (a4-a6)
+@pytest.mark.parametrize("prec", [64, 32])
+@pytest.mark.parametrize("chains", [1, 5, 8, 16, 32])
+def test_rows_sharing_a_wavefront_match_oracle(mc, chains, prec):
+    """Rows with few chains sharing a wavefront (lanes_per_row G < 64: 64 / G rows of
+    G lanes, the LDS and HBM tables split among them) give the oracle's estimate."""
+    B = I.random_nonsym(2500, seed=71)
+    lanes = 8 if chains <= 8 else 16 if chains <= 16 else 32
+    (rp, col, val), res, _ = run(mc, B, seed=5, chains=chains, delta=1e-4, eps=1e-3, prec=prec, lanes_per_row=lanes)
+    assert res.stats.lanes_per_row == lanes
+    orc, o = oracle_run(B, seed=5, chains=chains, delta=1e-4, eps=1e-3, prec=prec)
+    assert orc["guard"] == 0 and res.stats.transitions == orc["transitions"]
+    compare_spai((rp, col, val), orc, o.diag, chains)
+
+
+def test_shared_wavefronts_with_per_row_chains_and_forced_widths(mc):
+    """Per-row chain counts (mean 4, some rows far above the group width) and every
+    forced row width give the oracle's estimate; a forced width that leaves rows too
+    small a table overflows, and the rerun (one row per wavefront, larger table)
+    still lands on the oracle's result."""
+    B = I.cfg1()
+    rng = np.random.default_rng(12)
+    cpr = rng.integers(1, 8, size=B.n).astype(np.int32)
+    cpr[::97] = 150
+    orc, o = oracle_run(B, seed=8, chains=1, delta=1e-3, eps=1e-3, chains_per_row=cpr)
+    assert orc["guard"] == 0
+    for kw in ({}, {"lanes_per_row": 8}, {"lanes_per_row": 16}, {"lanes_per_row": 32}, {"lanes_per_row": 64},
+               {"lanes_per_row": 8, "hash_slots": 512}):
+        (rp, col, val), res, _ = run(mc, B, seed=8, chains=1, delta=1e-3, eps=1e-3, chains_per_row=cpr, **kw)
+        assert res.stats.transitions == orc["transitions"], kw
+        compare_spai((rp, col, val), orc, o.diag, cpr)
+        if kw.get("hash_slots") == 512:
+            assert res.stats.retries >= 1, "the 64-slot row tables should have overflowed"
