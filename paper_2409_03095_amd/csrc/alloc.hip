@@ -23,7 +23,8 @@ namespace {
 struct Cached {
     void *p;
     size_t bytes;
-    hipStream_t stream;  // nullptr: idle, reusable on any stream
+    hipStream_t stream;  // the stream of a stream-ordered release (the null stream too)
+    bool idle;           // released after a device synchronisation: reusable on any stream
     int device;
 };
 
@@ -79,7 +80,7 @@ void release(void *p, hipStream_t s, bool idle) {
         (void)hipFree(p);  // synchronises the device: every earlier use has completed
         return;
     }
-    c.free_blocks.push_back({p, bytes, idle ? nullptr : s, dev});
+    c.free_blocks.push_back({p, bytes, s, idle, dev});
     c.cached_bytes += bytes;
 }
 
@@ -96,7 +97,7 @@ hipError_t dev_alloc(void **p, size_t bytes, hipStream_t s) {
         std::lock_guard<std::mutex> lk(c.mu);
         for (size_t i = c.free_blocks.size(); i-- > 0;) {
             Cached &b = c.free_blocks[i];
-            if (b.bytes == cls && b.device == dev && (b.stream == nullptr || b.stream == s)) {
+            if (b.bytes == cls && b.device == dev && (b.idle || b.stream == s)) {
                 *p = b.p;
                 c.cached_bytes -= b.bytes;
                 c.free_blocks[i] = c.free_blocks.back();
