@@ -83,7 +83,7 @@ def main():
     ap.add_argument("--lanes", type=int, default=0)
     ap.add_argument("--sketch-slots", type=int, default=0)
     ap.add_argument("--heavy-weight", type=float, default=0.0)
-    ap.add_argument("--workload", default="random", choices=["random", "aniso27", "batched"],
+    ap.add_argument("--workload", default="random", choices=["random", "aniso27", "batched", "next"],
                     help="random: n=262144 random nonsymmetric (default); aniso27: 160^3 27-point anisotropic; "
                          "batched: 256 3D 7-point convection-diffusion matrices in one launch")
     ap.add_argument("--nx", type=int, default=160, help="grid side of the aniso27 workload")
@@ -116,6 +116,8 @@ def main():
         return learned_main(args)
 
     delta, eps, seed = 1e-4, 1e-3, 0
+    if args.workload == "next":
+        return next_main(args)
     if args.workload == "aniso27":
         return aniso_main(args)
     if args.workload == "batched":
@@ -412,6 +414,59 @@ def learned_main(args):
            "config": {"workload": f"5-point family with smooth rho field: {args.train_mats} training matrices, "
                                   f"held-out {args.heldout}x{args.heldout}", "n": B.n, "train": info},
            "points": pts, "control": control}
+    print(json.dumps(out), flush=True)
+
+
+def next_main(args):
+    """The pre-pass and output variants on a 64^3 27-point anisotropic matrix
+    (1:10:100, +-10 % noise, ||C||_inf = 0.95; 32 chains/row, delta = eps = 1e-3, FP32
+    walks): matrix reduction (drop shares 0-10 %), top-k retention (k = 16, 32 vs the
+    eps filter), and the augmented splitting on the same stencil made non-contractive
+    (||C||_inf = 1.3, alpha = 1, 2, 5). Per setting: walk time, transitions, nnz(M),
+    ||I - MB||_F / sqrt(n) on a 10^4-row sample and device BiCGstab iterations on
+    B x = B 1 (rtol 1e-8) with M on the right."""
+    import torch
+
+    from paper_2409_03095_amd import inputs as I
+    from paper_2409_03095_amd import learned as L
+    from paper_2409_03095_amd import mcmi
+    nx = 64
+    rows = np.sort(np.random.default_rng(12345).choice(nx ** 3, 10000, replace=False))
+
+    def measure(B, dB, cdf_kw, p_kw, label):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        cdf = mcmi.Cdf(dB, **cdf_kw)
+        p = mcmi.params(seed=0, chains=32, delta=1e-3, eps=1e-3, walk_prec=32, **p_kw)
+        res = mcmi.spai(cdf, p)
+        torch.cuda.synchronize()
+        build_s = time.perf_counter() - t0
+        sq = L.residual_sample(B, *L.sample_rows(res, rows), rows)
+        b = torch.from_numpy(B.to_scipy() @ np.ones(B.n)).cuda()
+        _, sn = mcmi.bicgstab(dB, None, b, rtol=1e-8, maxiter=5000)
+        _, sm = mcmi.bicgstab(dB, res, b, rtol=1e-8, maxiter=5000)
+        out = {"setting": label, "walk_ms": res.stats.ms_walk, "transitions": int(res.stats.transitions),
+               "transitions_per_s": res.stats.transitions / (res.stats.ms_walk * 1e-3), "nnz_M": int(res.nnz),
+               "r_norm": float(math.sqrt(sq.mean())), "build_and_walk_ms": build_s * 1e3,
+               "bicgstab_none": {"iterations": int(sn.iterations), "converged": int(sn.converged), "ms": sn.ms},
+               "bicgstab_M": {"iterations": int(sm.iterations), "converged": int(sm.converged), "ms": sm.ms}}
+        print(f"[next] {label}: walk {out['walk_ms']:.2f} ms, nnz(M) {out['nnz_M']}, r {out['r_norm']:.4f}, "
+              f"BiCGstab {sn.iterations} -> {sm.iterations} iterations", flush=True)
+        return out
+
+    B = I.aniso27(nx, rho=0.95, seed=5)
+    dB = mcmi.DeviceCsr.from_host(B)
+    results = {"reduction": [], "topk": [], "augmentation": []}
+    for frac in (0.0, 0.02, 0.06, 0.10):
+        results["reduction"].append(measure(B, dB, {"drop_frac": frac}, {}, f"drop {frac:.2f}"))
+    for k in (16, 32):
+        results["topk"].append(measure(B, dB, {}, {"topk": k}, f"top-{k}"))
+    Bn = I.aniso27(nx, rho=1.3, seed=5)
+    dBn = mcmi.DeviceCsr.from_host(Bn)
+    for alpha in (1.0, 2.0, 5.0):
+        results["augmentation"].append(measure(Bn, dBn, {"alpha": alpha}, {}, f"alpha {alpha:g} (||C||_inf 1.3)"))
+    out = {"metric": METRIC, "workload": f"pre-pass and output variants, 27-point {nx}^3", "n": B.n,
+           "data": "synthetic", "n_gpus": 1, "results": results}
     print(json.dumps(out), flush=True)
 
 
