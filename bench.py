@@ -93,6 +93,7 @@ def main():
                     help="aniso27: chains per row from the allocation network (trained on small 27-point "
                          "matrices), same mean budget, uniform fallback; features, inference and allocation "
                          "are inside the timed step")
+    ap.add_argument("--tune", action="store_true", help="batched: kernel shape from the autotuner")
     ap.add_argument("--bicgstab", action="store_true", help="aniso27: device BiCGstab iterations with and without M")
     ap.add_argument("--learned", action="store_true",
                     help="learned vs uniform chains to ||I-MB||_F/sqrt(n) <= 0.3 (allocation-network workload)")
@@ -332,6 +333,17 @@ def batched_main(args):
     chains = args.chains if args.chains != 512 else 128
     p = mcmi.params(seed=0, chains=chains, delta=1e-4, eps=1e-3, walk_prec=args.prec)
     cell = 0 if args.order_cell is None else args.order_cell
+    tuned = None
+    if args.tune:
+        # the autotuner times candidate kernel shapes on a row sample of the set (outside
+        # the timed steps; cached in a JSON file in the temporary directory)
+        import tempfile
+        t0 = time.perf_counter()
+        p, tms = mcmi.tune(mcmi.Cdf.batched(devs, order_cell=cell), p, sample_rows=65536,
+                           cache_path=os.path.join(tempfile.gettempdir(), "mcmi_tune_batched.json"))
+        tuned = {"lanes_per_row": p.lanes_per_row, "hash_slots": p.hash_slots, "sketch_slots": p.sketch_slots,
+                 "sample_walk_ms": tms, "tuning_s": time.perf_counter() - t0}
+        print(f"[batched] tuned: {json.dumps(tuned)}", flush=True)
     for _ in range(args.warmup):
         res = mcmi.spai(mcmi.Cdf.batched(devs, order_cell=cell), p)
         del res
@@ -364,7 +376,8 @@ def batched_main(args):
            "config": {"workload": "batched 256 x 3D 7-point convection-diffusion", "matrices": len(mats),
                       "rows": int(sum(m.n for m in mats)), "chains_per_row": chains,
                       "transitions_per_step": int(st.transitions), "nnz_M": int(last.nnz),
-                      "lanes_per_row": st.lanes_per_row, "hash_slots": st.hash_slots, "order_cell": cell},
+                      "lanes_per_row": st.lanes_per_row, "hash_slots": st.hash_slots, "order_cell": cell,
+                      "tuned": tuned},
            "walk_ms": float(np.mean(walk_ms)),
            "one_launch_per_matrix": {"seconds": single_s, "transitions": int(single_trans),
                                      "transitions_per_s": single_trans / single_s}}

@@ -1,6 +1,7 @@
 // Autotuner and captured plans (gfx950).
 //
-// mcmi_tune: times candidate kernel shapes (lanes per row, LDS hash slots,
+// mcmi_tune: times candidate kernel shapes (lanes per row, rows sharing a
+// wavefront, LDS hash slots,
 // count-sketch buckets, heavy threshold) on a strided sample of rows and keeps the
 // fastest walk; results are cached in a JSON file keyed by the workload class
 // (architecture, log2 buckets of n, mean entries per row, chains, chain length,
@@ -149,7 +150,8 @@ extern "C" mcmi_status mcmi_tune(const mcmi_cdf *cdf, const mcmi_params *base, i
         int lanes, hash, sketch;
         double tau;
     };
-    std::vector<Cand> cands = {{64, 512, 0, 0}, {64, 1024, 0, 0}, {64, 2048, 0, 0}};
+    std::vector<Cand> cands = {{64, 512, 0, 0},  {64, 1024, 0, 0}, {64, 2048, 0, 0},
+                               {32, 1024, 0, 0}, {32, 2048, 0, 0}, {16, 1024, 0, 0}, {8, 1024, 0, 0}};
     for (int lanes : {256, 512, 1024})
         for (int hash : {2048, 4096})
             if (walk_block_supported(lanes, hash))
