@@ -63,6 +63,8 @@ CASES = {
     "cycle_50000_cell4096": (lambda: I.scaled_cycle(50000, 0.5), 4096),  # most rows beyond 64 levels
     "diag_only_cell8": (lambda: I.diag_only(3000, seed=2), 8),          # no edges: every row alone
     "grid32_cell1": (I.cfg1, 1),                                         # every row a seed
+    "single_row": (lambda: I.diag_only(1, seed=3), 4096),               # n = 1
+    "grid2x2": (lambda: I.grid2d_5pt(2, 2), 2),
 }
 
 
