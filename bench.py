@@ -331,7 +331,8 @@ def batched_main(args):
           f"{time.perf_counter() - t0:.1f} s", flush=True)
     devs = [mcmi.DeviceCsr.from_host(B) for B in mats]
     chains = args.chains if args.chains != 512 else 128
-    p = mcmi.params(seed=0, chains=chains, delta=1e-4, eps=1e-3, walk_prec=args.prec)
+    p = mcmi.params(seed=0, chains=chains, delta=1e-4, eps=1e-3, walk_prec=args.prec, lanes_per_row=args.lanes,
+                    hash_slots=args.hash_slots)
     cell = 0 if args.order_cell is None else args.order_cell
     tuned = None
     if args.tune:
