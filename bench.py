@@ -94,6 +94,8 @@ def main():
                          "matrices), same mean budget, uniform fallback; features, inference and allocation "
                          "are inside the timed step")
     ap.add_argument("--tune", action="store_true", help="batched: kernel shape from the autotuner")
+    ap.add_argument("--graph", action="store_true",
+                    help="batched: also time hipGraph replays of the launch on the last step's records")
     ap.add_argument("--bicgstab", action="store_true", help="aniso27: device BiCGstab iterations with and without M")
     ap.add_argument("--learned", action="store_true",
                     help="learned vs uniform chains to ||I-MB||_F/sqrt(n) <= 0.3 (allocation-network workload)")
@@ -357,7 +359,7 @@ def batched_main(args):
         walk_ms.append(res.stats.ms_walk)
         trans += res.stats.transitions
         last = res
-        del cdf
+        cdf_last = cdf
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     # one launch per matrix (records built once per matrix), same chains and seed
@@ -371,6 +373,23 @@ def batched_main(args):
     torch.cuda.synchronize()
     single_s = time.perf_counter() - t1
     st = last.stats
+    # the same launch captured in a hipGraph plan on the last step's records: each
+    # replay (new seed) resets the counters, walks, finalizes and assembles M
+    graph = None
+    if args.graph:
+        plan = mcmi.Plan(cdf_last, p, nnz_capacity=int(last.nnz * 1.25) + (1 << 20))
+        plan.launch(1000)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for k in range(args.steps):
+            plan.launch(1001 + k)
+        torch.cuda.synchronize()
+        g_s = (time.perf_counter() - t0) / args.steps
+        gst, ovf, gnnz = plan.stats()
+        graph = {"ms_per_replay": g_s * 1e3, "transitions_per_replay": int(gst.transitions),
+                 "transitions_per_s": gst.transitions / g_s, "overflow": ovf, "nnz_M": gnnz}
+        print(f"[batched] graph replays: {json.dumps(graph)}", flush=True)
+        del plan
     out = {"metric": METRIC, "value": trans / elapsed, "unit": "transitions/s", "n_gpus": 1, "steps": args.steps,
            "warmup": args.warmup, "ms_per_step": elapsed / args.steps * 1e3, "higher_is_better": True,
            "dtype": "f32" if args.prec == 32 else "f64", "data": "synthetic",
@@ -379,7 +398,7 @@ def batched_main(args):
                       "transitions_per_step": int(st.transitions), "nnz_M": int(last.nnz),
                       "lanes_per_row": st.lanes_per_row, "hash_slots": st.hash_slots, "order_cell": cell,
                       "tuned": tuned},
-           "walk_ms": float(np.mean(walk_ms)),
+           "walk_ms": float(np.mean(walk_ms)), "graph_replay": graph,
            "one_launch_per_matrix": {"seconds": single_s, "transitions": int(single_trans),
                                      "transitions_per_s": single_trans / single_s}}
     print(json.dumps(out), flush=True)

@@ -455,6 +455,12 @@ class Plan:
         torch.cuda.current_stream().synchronize()
         return (rp.cpu().numpy(), col[:out.nnz].cpu().numpy(), val[:out.nnz].cpu().numpy()), st, False
 
+    def stats(self, stream=None):
+        """(stats, overflow flag, nnz) of the last launch, without copying M."""
+        out, st, ovf = CsrOut(), Stats(), ctypes.c_int32()
+        _check(_lib.mcmi_plan_result(self._h, ctypes.byref(out), ctypes.byref(st), ctypes.byref(ovf), _stream(stream)))
+        return st, bool(ovf.value), int(out.nnz)
+
     def free(self):
         if self._h:
             _lib.mcmi_plan_free(self._h)
