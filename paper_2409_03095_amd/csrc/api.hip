@@ -140,6 +140,9 @@ mcmi_status choose_shape(const mcmi_cdf *cdf, const mcmi_params *p, int lmax, in
     out.hash = H;
     out.sketch = sketch;
     out.tau = tau;
+    // one row per wavefront with more chains than lanes: each lane keeps two of the
+    // row's chains in flight (two independent bucket loads per step, same table)
+    out.lane_chains = (lanes == 64 && n_typ > 64) ? 2 : 1;
     return MCMI_OK;
 }
 
@@ -431,6 +434,7 @@ extern "C" mcmi_status mcmi_spai(const mcmi_cdf *cdf, const mcmi_params *p, cons
         a.hash_slots = H;
         a.hash_shift = 32 - __builtin_ctz((unsigned)H);
         a.row_lanes = block_kernel ? 0 : lanes;
+        a.lane_chains = (!block_kernel && lanes == 64) ? shape.lane_chains : 1;
         a.queue_ctr = qctr;
         a.row_start = row_start.as<int64_t>();
         a.row_cnt = row_cnt.as<uint32_t>();

@@ -153,6 +153,7 @@ hipError_t scan_exclusive_u32_to_i64(const uint32_t *in, int64_t *out, int64_t n
 // Kernel shape of a walk launch (api.hip: choose_shape)
 struct KernelShape {
     int lanes = 64, hash = 1024, sketch = 0;
+    int lane_chains = 1;  // wavefront kernel: chains a lane keeps in flight
     double tau = 0.0;
 };
 struct mcmi_cdf;

@@ -304,6 +304,7 @@ extern "C" mcmi_status mcmi_plan_create(const mcmi_cdf *cdf, const mcmi_params *
     a.diag = cdf->diag;
     a.n_tasks = pl->n;
     a.row_lanes = block_kernel ? 0 : pl->shape.lanes;
+    a.lane_chains = (!block_kernel && pl->shape.lanes == 64) ? pl->shape.lane_chains : 1;
     a.task_map = cdf->batch == 0 ? cdf->order : nullptr;  // locality schedule, if the set has one
     a.chains_per_row = chains_per_row_dev;
     a.chains = p->chains;

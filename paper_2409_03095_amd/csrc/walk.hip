@@ -90,9 +90,81 @@ __device__ __forceinline__ void row_hdr(const WalkArgs &a, RowPre &p) {
     if (p.task >= 0) load_header<kF32>(a.rec, p.r_off, p.h0);
 }
 
+// One chain of a lane: its index in the row, state, weight and Philox block.
+struct ChainSt {
+    int32_t c;
+    bool active;
+    uint32_t off, j;
+    double w64;
+    float w32;
+    StepHdr H;
+    u32x4 blk;
+};
+
+// One step of a chain: add the current state's weight (j > 0), then stop (and
+// start the lane's next chain of the row, `stride` further on) or draw the next
+// state, whose bucket load is left in flight.
+template <bool kF32>
+__device__ __forceinline__ void chain_step(const WalkArgs &a, ChainSt &ch, int stride, int32_t N, uint32_t r_off,
+                                           const StepHdr &H0, uint32_t prow, uint32_t ptag, uint32_t k0, uint32_t k1,
+                                           int32_t *gkeys, double *gvals, uint32_t hmask, int hshift, int32_t *gskeys,
+                                           double *gsvals, int32_t *gsused, int *gspill, uint32_t smask,
+                                           unsigned long long &trans, unsigned long long &spilled, bool &spill_full) {
+    const uint4 h = ch.H.h0;  // row, m, W, Shat32
+    const double s64 = kF32 ? 0.0 : header_shat64(ch.H);
+    if (ch.j > 0) {
+        const int32_t key = (int32_t)h.x;
+        const double w = kF32 ? (double)ch.w32 : ch.w64;
+        if (!lds_add(gkeys, gvals, hmask, hash_key(key, hshift), key, w)) {
+            ++spilled;
+            if (!spill_add(gskeys, gsvals, gsused, gspill, smask, key, w)) spill_full = true;
+        }
+    }
+    bool stop = (h.y == 0u) || (ch.j >= (uint32_t)a.lmax);
+    double wn64 = 0.0;
+    float wn32 = 0.0f;
+    if (kF32) {
+        wn32 = ch.w32 * __uint_as_float(h.w);
+        stop = stop || (fabsf(wn32) < a.delta32);
+    } else {
+        wn64 = ch.w64 * s64;
+        stop = stop || (fabs(wn64) < a.delta);
+    }
+    if (stop) {
+        trans += ch.j;
+        ch.c += stride;
+        if (ch.c < N) {
+            ch.off = r_off;
+            ch.H = H0;
+            ch.j = 0;
+            ch.w64 = 1.0;
+            ch.w32 = 1.0f;
+        } else {
+            ch.active = false;
+        }
+    } else {
+        // step j + 1 takes word j mod 4 of block j / 4: consume words in order
+        if ((ch.j & 3u) == 0u) ch.blk = philox4x32_10(ch.j >> 2, (uint32_t)ch.c, prow, ptag, k0, k1);
+        const uint32_t u = ch.blk.x;
+        ch.blk.x = ch.blk.y;
+        ch.blk.y = ch.blk.z;
+        ch.blk.z = ch.blk.w;
+        StepHdr Nx;
+        const uint32_t tgt = draw_next<kF32>(a.rec, ch.off, ch.H, u, Nx);
+        const bool neg = (tgt & kSignBit) != 0u;
+        if (kF32)
+            ch.w32 = neg ? -wn32 : wn32;
+        else
+            ch.w64 = neg ? -wn64 : wn64;
+        ch.off = tgt & ~kSignBit;
+        ch.H = Nx;
+        ++ch.j;
+    }
+}
+
 // The 64 / kG rows of one wave (one per group of kG lanes; cur and nxt hold each
-// lane's own group's row).
-template <bool kF32, int kG>
+// lane's own group's row); each lane keeps kC of its row's chains in flight.
+template <bool kF32, int kG, int kC>
 __device__ __forceinline__ void walk_rows(const WalkArgs &a, const RowPre &cur, RowPre &nxt, int &queue, int64_t &tlo,
                          int64_t &thi, int32_t *keys, double *vals, int *spill_cnt,
                          int32_t *skeys, double *svals, int32_t *sused, uint32_t k0, uint32_t k1,
@@ -123,73 +195,34 @@ __device__ __forceinline__ void walk_rows(const WalkArgs &a, const RowPre &cur, 
     if (sub == 0 && has) lds_add(gkeys, gvals, hmask, hash_key(r, hshift), r, (double)N);
     wave_sync();
 
-    int32_t c = sub;
-    bool active = has && c < N;
-    uint32_t off = r_off;
-    uint32_t j = 0;
-    double w64 = 1.0;
-    float w32 = 1.0f;
     // the row's own header (every chain starts there, loaded ahead); later
     // states' headers arrive with the bucket of the step that reaches them
     const StepHdr H0 = cur.h0;
-    StepHdr H = H0;
-    u32x4 blk = {0, 0, 0, 0};
+    ChainSt ch[kC];
+#pragma unroll
+    for (int k = 0; k < kC; ++k) {
+        ch[k].c = sub + k * kG;
+        ch[k].active = has && ch[k].c < N;
+        ch[k].off = r_off;
+        ch[k].j = 0;
+        ch[k].w64 = 1.0;
+        ch[k].w32 = 1.0f;
+        ch[k].H = H0;
+        ch[k].blk = {0, 0, 0, 0};
+    }
     unsigned long long trans = 0, spilled = 0;
     bool spill_full = false;
 
-    while (__any(active)) {
-        if (active) {
-            const uint4 h = H.h0;  // row, m, W, Shat32
-            const double s64 = kF32 ? 0.0 : header_shat64(H);
-            if (j > 0) {
-                const int32_t key = (int32_t)h.x;
-                const double w = kF32 ? (double)w32 : w64;
-                if (!lds_add(gkeys, gvals, hmask, hash_key(key, hshift), key, w)) {
-                    ++spilled;
-                    if (!spill_add(gskeys, gsvals, gsused, spill_cnt + grp, smask, key, w)) spill_full = true;
-                }
-            }
-            bool stop = (h.y == 0u) || (j >= (uint32_t)a.lmax);
-            double wn64 = 0.0;
-            float wn32 = 0.0f;
-            if (kF32) {
-                wn32 = w32 * __uint_as_float(h.w);
-                stop = stop || (fabsf(wn32) < a.delta32);
-            } else {
-                wn64 = w64 * s64;
-                stop = stop || (fabs(wn64) < a.delta);
-            }
-            if (stop) {
-                trans += j;
-                c += kG;
-                if (c < N) {
-                    off = r_off;
-                    H = H0;
-                    j = 0;
-                    w64 = 1.0;
-                    w32 = 1.0f;
-                } else {
-                    active = false;
-                }
-            } else {
-                // step j + 1 takes word j mod 4 of block j / 4: consume words in order
-                if ((j & 3u) == 0u) blk = philox4x32_10(j >> 2, (uint32_t)c, prow, ptag, k0, k1);
-                const uint32_t u = blk.x;
-                blk.x = blk.y;
-                blk.y = blk.z;
-                blk.z = blk.w;
-                StepHdr Nx;
-                const uint32_t tgt = draw_next<kF32>(a.rec, off, H, u, Nx);
-                const bool neg = (tgt & kSignBit) != 0u;
-                if (kF32)
-                    w32 = neg ? -wn32 : wn32;
-                else
-                    w64 = neg ? -wn64 : wn64;
-                off = tgt & ~kSignBit;
-                H = Nx;
-                ++j;
-            }
-        }
+    while (true) {
+        bool any = false;
+#pragma unroll
+        for (int k = 0; k < kC; ++k) any |= ch[k].active;
+        if (!__any(any)) break;
+#pragma unroll
+        for (int k = 0; k < kC; ++k)
+            if (ch[k].active)
+                chain_step<kF32>(a, ch[k], kG * kC, N, r_off, H0, prow, ptag, k0, k1, gkeys, gvals, hmask, hshift,
+                                 gskeys, gsvals, gsused, spill_cnt + grp, smask, trans, spilled, spill_full);
     }
     wave_sync();
     // the next rows' ids and record offsets load now, their headers during the
@@ -397,7 +430,7 @@ __device__ __forceinline__ void walk_rows(const WalkArgs &a, const RowPre &cur, 
     if (!hdr_issued) row_hdr<kF32>(a, nxt);
 }
 
-template <bool kF32, int kG>
+template <bool kF32, int kG, int kC>
 __global__ void __launch_bounds__(256) k_walk(WalkArgs a) {
     constexpr int P = 64 / kG;
     extern __shared__ __align__(16) unsigned char smem[];
@@ -436,8 +469,8 @@ __global__ void __launch_bounds__(256) k_walk(WalkArgs a) {
     row_hdr<kF32>(a, cur);
     while (__any(cur.task >= 0)) {
         RowPre nxt;
-        walk_rows<kF32, kG>(a, cur, nxt, queue, tlo, thi, keys, vals, spill_cnt, skeys, svals, sused, k0, k1, pcur,
-                            pend, wstats);
+        walk_rows<kF32, kG, kC>(a, cur, nxt, queue, tlo, thi, keys, vals, spill_cnt, skeys, svals, sused, k0, k1,
+                                pcur, pend, wstats);
         cur = nxt;
     }
     // statistics: one set of atomics per wave
@@ -456,10 +489,15 @@ template <bool kF32>
 hipError_t launch_walk_t(const WalkArgs &a, int blocks, int waves, hipStream_t s) {
     const size_t lds = walk_lds_bytes(a.hash_slots, waves);
     switch (a.row_lanes) {
-        case 8: k_walk<kF32, 8><<<blocks, waves * 64, lds, s>>>(a); break;
-        case 16: k_walk<kF32, 16><<<blocks, waves * 64, lds, s>>>(a); break;
-        case 32: k_walk<kF32, 32><<<blocks, waves * 64, lds, s>>>(a); break;
-        default: k_walk<kF32, 64><<<blocks, waves * 64, lds, s>>>(a); break;
+        case 8: k_walk<kF32, 8, 1><<<blocks, waves * 64, lds, s>>>(a); break;
+        case 16: k_walk<kF32, 16, 1><<<blocks, waves * 64, lds, s>>>(a); break;
+        case 32: k_walk<kF32, 32, 1><<<blocks, waves * 64, lds, s>>>(a); break;
+        default:
+            if (a.lane_chains == 2)
+                k_walk<kF32, 64, 2><<<blocks, waves * 64, lds, s>>>(a);
+            else
+                k_walk<kF32, 64, 1><<<blocks, waves * 64, lds, s>>>(a);
+            break;
     }
     return hipGetLastError();
 }
@@ -467,14 +505,15 @@ hipError_t launch_walk_t(const WalkArgs &a, int blocks, int waves, hipStream_t s
 hipError_t launch_walk(const WalkArgs &a, bool f32, int blocks, int waves, hipStream_t s) {
     if (a.row_lanes != 0 && a.row_lanes != 8 && a.row_lanes != 16 && a.row_lanes != 32 && a.row_lanes != 64)
         return hipErrorInvalidValue;
+    if (a.lane_chains == 2 && a.row_lanes != 0 && a.row_lanes != 64) return hipErrorInvalidValue;
     return f32 ? launch_walk_t<true>(a, blocks, waves, s) : launch_walk_t<false>(a, blocks, waves, s);
 }
 
 hipError_t walk_occupancy(bool f32, int hash_slots, int waves, int *blocks_per_cu) {
     // the instances differ only in loop bounds; the 64-lane one stands for all
     const size_t lds = walk_lds_bytes(hash_slots, waves);
-    if (f32) return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k_walk<true, 64>, waves * 64, lds);
-    return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k_walk<false, 64>, waves * 64, lds);
+    if (f32) return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k_walk<true, 64, 1>, waves * 64, lds);
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k_walk<false, 64, 1>, waves * 64, lds);
 }
 
 }  // namespace mcmi

@@ -353,3 +353,26 @@ def test_shared_wavefronts_with_per_row_chains_and_forced_widths(mc):
         compare_spai((rp, col, val), orc, o.diag, cpr)
         if kw.get("hash_slots") == 512:
             assert res.stats.retries >= 1, "the 64-slot row tables should have overflowed"
+
+
+# ------------------------------------- two chains in flight per lane (a4-a6)
+@pytest.mark.parametrize("prec", [64, 32])
+@pytest.mark.parametrize("chains", [65, 100, 128, 160])
+def test_two_chains_per_lane_match_oracle(mc, chains, prec):
+    """One row per wavefront with more chains than lanes: each lane keeps two of
+    the row's chains in flight; the estimate equals the oracle's."""
+    B = I.random_nonsym(2000, seed=73)
+    (rp, col, val), res, _ = run(mc, B, seed=6, chains=chains, delta=1e-4, eps=1e-3, prec=prec)
+    assert res.stats.lanes_per_row == 64
+    orc, o = oracle_run(B, seed=6, chains=chains, delta=1e-4, eps=1e-3, prec=prec)
+    assert orc["guard"] == 0 and res.stats.transitions == orc["transitions"]
+    compare_spai((rp, col, val), orc, o.diag, chains)
+
+
+def test_two_chains_per_lane_with_per_row_chains(mc):
+    B = I.aniso27(12, seed=4)
+    cpr = np.random.default_rng(14).integers(40, 200, size=B.n).astype(np.int32)
+    (rp, col, val), res, _ = run(mc, B, seed=9, chains=1, delta=1e-4, eps=1e-3, prec=32, chains_per_row=cpr)
+    orc, o = oracle_run(B, seed=9, chains=1, delta=1e-4, eps=1e-3, prec=32, chains_per_row=cpr)
+    assert orc["guard"] == 0 and res.stats.transitions == orc["transitions"]
+    compare_spai((rp, col, val), orc, o.diag, cpr)
