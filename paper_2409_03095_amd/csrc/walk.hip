@@ -101,9 +101,11 @@ struct ChainSt {
     u32x4 blk;
 };
 
-// One step of a chain: add the current state's weight (j > 0), then stop (and
-// start the lane's next chain of the row, `stride` further on) or draw the next
-// state, whose bucket load is left in flight.
+// One step of a chain: stop (and start the lane's next chain of the row, `stride`
+// further on) or draw the next state, and add the current state's weight (j > 0).
+// The next bucket's loads go out first; the weight's accumulation and the Philox
+// block of the next four steps run while they are in flight. `blk` holds the
+// words of the chain's next draws (step j + 1 takes word j mod 4 of block j / 4).
 template <bool kF32>
 __device__ __forceinline__ void chain_step(const WalkArgs &a, ChainSt &ch, int stride, int32_t N, uint32_t r_off,
                                            const StepHdr &H0, uint32_t prow, uint32_t ptag, uint32_t k0, uint32_t k1,
@@ -112,14 +114,7 @@ __device__ __forceinline__ void chain_step(const WalkArgs &a, ChainSt &ch, int s
                                            unsigned long long &trans, unsigned long long &spilled, bool &spill_full) {
     const uint4 h = ch.H.h0;  // row, m, W, Shat32
     const double s64 = kF32 ? 0.0 : header_shat64(ch.H);
-    if (ch.j > 0) {
-        const int32_t key = (int32_t)h.x;
-        const double w = kF32 ? (double)ch.w32 : ch.w64;
-        if (!lds_add(gkeys, gvals, hmask, hash_key(key, hshift), key, w)) {
-            ++spilled;
-            if (!spill_add(gskeys, gsvals, gsused, gspill, smask, key, w)) spill_full = true;
-        }
-    }
+    const double wcur = kF32 ? (double)ch.w32 : ch.w64;
     bool stop = (h.y == 0u) || (ch.j >= (uint32_t)a.lmax);
     double wn64 = 0.0;
     float wn32 = 0.0f;
@@ -130,6 +125,23 @@ __device__ __forceinline__ void chain_step(const WalkArgs &a, ChainSt &ch, int s
         wn64 = ch.w64 * s64;
         stop = stop || (fabs(wn64) < a.delta);
     }
+    BucketLd bl;
+    if (!stop) {
+        const uint32_t u = ch.blk.x;
+        ch.blk.x = ch.blk.y;
+        ch.blk.y = ch.blk.z;
+        ch.blk.z = ch.blk.w;
+        bucket_issue<kF32>(a.rec, ch.off, ch.H, u, bl);
+        // the last word of the block went to this draw: the next block now
+        if ((ch.j & 3u) == 3u) ch.blk = philox4x32_10((ch.j + 1u) >> 2, (uint32_t)ch.c, prow, ptag, k0, k1);
+    }
+    if (ch.j > 0) {
+        const int32_t key = (int32_t)h.x;
+        if (!lds_add(gkeys, gvals, hmask, hash_key(key, hshift), key, wcur)) {
+            ++spilled;
+            if (!spill_add(gskeys, gsvals, gsused, gspill, smask, key, wcur)) spill_full = true;
+        }
+    }
     if (stop) {
         trans += ch.j;
         ch.c += stride;
@@ -139,18 +151,13 @@ __device__ __forceinline__ void chain_step(const WalkArgs &a, ChainSt &ch, int s
             ch.j = 0;
             ch.w64 = 1.0;
             ch.w32 = 1.0f;
+            ch.blk = philox4x32_10(0u, (uint32_t)ch.c, prow, ptag, k0, k1);
         } else {
             ch.active = false;
         }
     } else {
-        // step j + 1 takes word j mod 4 of block j / 4: consume words in order
-        if ((ch.j & 3u) == 0u) ch.blk = philox4x32_10(ch.j >> 2, (uint32_t)ch.c, prow, ptag, k0, k1);
-        const uint32_t u = ch.blk.x;
-        ch.blk.x = ch.blk.y;
-        ch.blk.y = ch.blk.z;
-        ch.blk.z = ch.blk.w;
         StepHdr Nx;
-        const uint32_t tgt = draw_next<kF32>(a.rec, ch.off, ch.H, u, Nx);
+        const uint32_t tgt = bucket_resolve<kF32>(bl, Nx);
         const bool neg = (tgt & kSignBit) != 0u;
         if (kF32)
             ch.w32 = neg ? -wn32 : wn32;
@@ -208,7 +215,7 @@ __device__ __forceinline__ void walk_rows(const WalkArgs &a, const RowPre &cur, 
         ch[k].w64 = 1.0;
         ch[k].w32 = 1.0f;
         ch[k].H = H0;
-        ch[k].blk = {0, 0, 0, 0};
+        ch[k].blk = ch[k].active ? philox4x32_10(0u, (uint32_t)ch[k].c, prow, ptag, k0, k1) : u32x4{0, 0, 0, 0};
     }
     unsigned long long trans = 0, spilled = 0;
     bool spill_full = false;

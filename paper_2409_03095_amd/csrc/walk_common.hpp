@@ -169,5 +169,35 @@ __device__ __forceinline__ uint32_t draw_next(const uint32_t *rec, uint32_t off,
     return own ? q0.y : q0.z;
 }
 
+// draw_next in two halves, so that other work can run while the bucket is in
+// flight: bucket_issue picks the bucket and position and issues its loads,
+// bucket_resolve picks the entry once they have arrived.
+struct BucketLd {
+    uint4 q0, q1, q2, q3;
+    uint32_t r;
+};
+
+template <bool kF32>
+__device__ __forceinline__ void bucket_issue(const uint32_t *rec, uint32_t off, const StepHdr &H, uint32_t u,
+                                             BucketLd &b) {
+    const uint32_t m = H.h0.y, W = H.h0.z;
+    const uint32_t j = __umulhi(u, m);
+    const uint32_t f = u * m;
+    b.r = __umulhi(f, W);
+    const uint4 *p = (const uint4 *)(rec + ((size_t)off + 1u + j) * kUnitWords);
+    b.q0 = p[0];
+    b.q1 = p[1];
+    b.q2 = p[2];
+    b.q3 = kF32 ? make_uint4(0u, 0u, 0u, 0u) : p[3];
+}
+
+template <bool kF32>
+__device__ __forceinline__ uint32_t bucket_resolve(const BucketLd &b, StepHdr &N) {
+    const bool own = b.r < b.q0.x;
+    N.h0 = own ? b.q1 : b.q2;
+    N.s64 = own ? make_uint2(b.q3.x, b.q3.y) : make_uint2(b.q3.z, b.q3.w);
+    return own ? b.q0.y : b.q0.z;
+}
+
 }  // namespace walkdev
 }  // namespace mcmi
