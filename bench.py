@@ -36,6 +36,8 @@ HBM_PEAK_GBS = 8000.0
 # rocprofv3 FETCH_SIZE/WRITE_SIZE of the walk kernel, in bytes per launch, for
 # the default workload (None until measured for the current kernel)
 TRAFFIC_BYTES = 3.94e11  # calibrated FETCH_SIZE + WRITE_SIZE of one walk launch (rocprofv3 --pmc)
+# the same for the 160^3 27-point workload's wavefront walk (cells of 4096 rows, FP32)
+TRAFFIC_BYTES_ANISO27 = 5.50e11
 
 
 def algorithmic_bytes_per_transition(B, fp32: bool) -> float:
@@ -287,6 +289,9 @@ def aniso_main(args):
                       "retries": int(st.retries), "record_bytes": int(rec_units) * 64, "order_cell": cell},
            "roofline": {"bound": "hbm", "achieved": round(bpt * st.transitions / walk_s / 1e9, 1), "peak": HBM_PEAK_GBS,
                         "unit": "GB/s", "frac": round(bpt * st.transitions / walk_s / 1e9 / HBM_PEAK_GBS, 4),
+                        "traffic": (TRAFFIC_BYTES_ANISO27 if (args.nx == 160 and args.prec == 32 and cell == 4096
+                                                              and net is None) else None),
+                        "kernel": "k_walk",
                         "bytes_per_transition": round(bpt, 2), "walk_ms": round(walk_s * 1e3, 3),
                         "walk_transitions_per_s": st.transitions / walk_s, "gather_ceiling_steps_per_s": ceiling}}
     if net is not None:
