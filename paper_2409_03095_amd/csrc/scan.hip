@@ -244,19 +244,31 @@ hipError_t expand_blocks(int64_t nblocks, const int32_t *start, const int32_t *c
 }
 
 // ------------------------------------------------------------------ SpMV
-// y = M x, float64. A group of G lanes per row (G from the average row length:
-// about one lane per entry, 8 to 64), strided partial sums then a butterfly
-// reduction inside the group; grid-stride over rows. Each lane issues the loads
-// of four of its entries before it adds them (in the same order as one at a time).
-template <int G>
+// y = M x, float64. A group of G lanes per row (G and the loads per lane U from
+// the average row length, so that G U covers a typical row in one pass), strided
+// partial sums then a butterfly reduction inside the group; grid-stride over
+// rows. Each lane issues the loads of its U entries before it adds them (in the
+// same order as one at a time), and the next row's bounds load while the current
+// row is summed, so a row costs two dependent memory latencies, not three.
+template <int G, int U>
 __global__ void __launch_bounds__(256) k_spmv(int64_t n, const int64_t *__restrict__ rp, const int32_t *__restrict__ ci,
                                               const double *__restrict__ v, const double *__restrict__ x,
                                               double *__restrict__ y) {
-    constexpr int U = 4;
     const int sub = threadIdx.x & (G - 1);
     const int64_t groups = ((int64_t)gridDim.x * blockDim.x) / G;
-    for (int64_t row = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / G; row < n; row += groups) {
-        const int64_t b = rp[row], e = rp[row + 1];
+    int64_t row = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / G;
+    int64_t b = 0, e = 0;
+    if (row < n) {
+        b = rp[row];
+        e = rp[row + 1];
+    }
+    for (; row < n; row += groups) {
+        const int64_t nrow = row + groups;
+        int64_t nb = 0, ne = 0;
+        if (nrow < n) {
+            nb = rp[nrow];
+            ne = rp[nrow + 1];
+        }
         double acc = 0.0;
         for (int64_t k0 = b + sub; k0 < e; k0 += (int64_t)G * U) {
             int32_t c[U];
@@ -276,15 +288,17 @@ __global__ void __launch_bounds__(256) k_spmv(int64_t n, const int64_t *__restri
 #pragma unroll
         for (int off = G / 2; off > 0; off >>= 1) acc += __shfl_xor(acc, off, G);
         if (sub == 0) y[row] = acc;
+        b = nb;
+        e = ne;
     }
 }
 
-template <int G>
+template <int G, int U>
 hipError_t launch_spmv(int64_t n, const int64_t *rp, const int32_t *ci, const double *v, const double *x, double *y,
                        hipStream_t s) {
     int64_t blocks = (n * G + 255) / 256;
     if (blocks > 65536) blocks = 65536;
-    k_spmv<G><<<(unsigned)blocks, 256, 0, s>>>(n, rp, ci, v, x, y);
+    k_spmv<G, U><<<(unsigned)blocks, 256, 0, s>>>(n, rp, ci, v, x, y);
     return hipGetLastError();
 }
 
@@ -292,10 +306,11 @@ hipError_t spmv(int64_t n, int64_t nnz, const int64_t *rp, const int32_t *ci, co
                 double *y, hipStream_t s) {
     if (n <= 0) return hipSuccess;
     const double per_row = (double)nnz / (double)n;
-    if (per_row < 12.0) return launch_spmv<8>(n, rp, ci, v, x, y, s);
-    if (per_row < 24.0) return launch_spmv<16>(n, rp, ci, v, x, y, s);
-    if (per_row < 96.0) return launch_spmv<32>(n, rp, ci, v, x, y, s);
-    return launch_spmv<64>(n, rp, ci, v, x, y, s);
+    if (per_row < 12.0) return launch_spmv<8, 4>(n, rp, ci, v, x, y, s);
+    if (per_row < 24.0) return launch_spmv<16, 4>(n, rp, ci, v, x, y, s);
+    if (per_row < 96.0) return launch_spmv<32, 4>(n, rp, ci, v, x, y, s);
+    if (per_row < 192.0) return launch_spmv<32, 6>(n, rp, ci, v, x, y, s);
+    return launch_spmv<64, 4>(n, rp, ci, v, x, y, s);
 }
 
 }  // namespace mcmi

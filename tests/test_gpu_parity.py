@@ -195,6 +195,41 @@ def test_apply_matches_oracle(mc):
     assert np.allclose(y, ref, rtol=1e-13, atol=1e-14 * np.abs(ref).max())
 
 
+@pytest.mark.parametrize("mean_len", [3, 15, 50, 150, 300])
+def test_apply_row_length_regimes(mc, mean_len):
+    """y = M x for every lane-group width the kernel picks from the mean row length
+    (8 to 64 lanes, 4 or 6 loads per lane), on ragged rows with empty ones, a row far
+    longer than the group covers in one pass, and a row count that leaves a partial
+    last group: against the oracle's sequential sum."""
+    import ctypes
+    rng = np.random.default_rng(mean_len)
+    n = 3001
+    lens = rng.integers(0, 2 * mean_len + 1, n)
+    lens[::97] = 0
+    lens[5] = min(n, 8 * mean_len + 7)
+    rp = np.zeros(n + 1, dtype=np.int64)
+    rp[1:] = np.cumsum(lens)
+    col = np.concatenate([np.sort(rng.choice(n, int(k), replace=False)) for k in lens]).astype(np.int32)
+    val = rng.standard_normal(col.size)
+    print(f"[gpu] apply regime mean_len={mean_len} nnz={col.size}", flush=True)
+    rpt, cit, vvt = (torch.from_numpy(a).cuda() for a in (rp, col, val))
+    Mo = mc.CsrOut(n, int(col.size), rpt.data_ptr(), cit.data_ptr(), vvt.data_ptr())
+    x = rng.standard_normal(n)
+    xt = torch.from_numpy(x).cuda()
+    yt = torch.full((n,), np.nan, dtype=torch.float64, device="cuda")
+    mc._check(mc._lib.mcmi_apply(ctypes.byref(Mo), ctypes.c_int64(n), ctypes.c_void_p(xt.data_ptr()),
+                                 ctypes.c_void_p(yt.data_ptr()), mc._stream(None)))
+    torch.cuda.synchronize()
+    y = yt.cpu().numpy()
+    ref = O.apply(rp, col, val, x)
+    # summation-order bound: |sum| error <= 2 k u sum |m x| per row
+    bound = 2.0 * (lens + 1) * 2.0 ** -53 * np.array([np.abs(val[rp[i]:rp[i + 1]] * x[col[rp[i]:rp[i + 1]]]).sum()
+                                                      for i in range(n)])
+    assert np.all(np.isfinite(y))
+    assert np.all(np.abs(y - ref) <= bound + 1e-300)
+    assert np.all(y[lens == 0] == 0.0)
+
+
 # ------------------------------------------------------ full-size samples
 def test_cfg2_full_size_sampled_rows(mc):
     """Random nonsymmetric n = 262144, 512 chains, FP32 walks + FP64 sums,
