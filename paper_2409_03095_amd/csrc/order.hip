@@ -38,10 +38,13 @@ __global__ void __launch_bounds__(256) k_seed(int64_t n, uint32_t thr, uint32_t 
     for (int64_t r = gid; r < n; r += stride) lab[r] = mix32((uint32_t)r ^ 0x6A09E667u) < thr ? (uint32_t)r : kUnset;
 }
 
-// One level of the search, eight lanes per row. A level runs only if the one
-// before it labelled a row; when a level labels nothing, its output equals its
-// input, so after the search both buffers hold the final labels (or, if all
-// kMaxGrow levels ran, the buffer the last level wrote).
+// One level of the search, eight lanes per row, each lane issuing the loads of
+// four of the row's columns before their labels (a row of up to 32 entries costs
+// two dependent loads; past the end a lane re-reads the row's last column, which
+// leaves the minimum as it is). A level runs only if the one before it labelled
+// a row; when a level labels nothing, its output equals its input, so after the
+// search both buffers hold the final labels (or, if all kMaxGrow levels ran, the
+// buffer the last level wrote).
 __global__ void __launch_bounds__(256) k_grow(int64_t n, const int64_t *__restrict__ rp, const int32_t *__restrict__ col,
                                               const uint32_t *__restrict__ lin, uint32_t *__restrict__ lout,
                                               uint32_t *changed, int level) {
@@ -53,8 +56,14 @@ __global__ void __launch_bounds__(256) k_grow(int64_t n, const int64_t *__restri
         uint32_t v = lin[r];
         if (v == kUnset) {  // uniform over the row's eight lanes
             uint32_t m = kUnset;
-            const int64_t e = rp[r + 1];
-            for (int64_t k = rp[r] + sub; k < e; k += 8) m = min(m, lin[col[k]]);
+            const int64_t b = rp[r], e = rp[r + 1];
+            for (int64_t k0 = b + sub; k0 < e; k0 += 32) {
+                int32_t c[4];
+#pragma unroll
+                for (int j = 0; j < 4; ++j) c[j] = col[k0 + 8 * j < e ? k0 + 8 * j : e - 1];
+#pragma unroll
+                for (int j = 0; j < 4; ++j) m = min(m, lin[c[j]]);
+            }
             m = min(m, (uint32_t)__shfl_xor((int)m, 1, 8));
             m = min(m, (uint32_t)__shfl_xor((int)m, 2, 8));
             m = min(m, (uint32_t)__shfl_xor((int)m, 4, 8));
