@@ -3,6 +3,7 @@
 import ctypes
 import os
 import re
+import subprocess
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
@@ -42,3 +43,33 @@ def test_oracle_shares_no_code_with_the_library():
     for fn in os.listdir(os.path.join(ROOT, "paper_2409_03095_amd", "csrc")):
         text = open(os.path.join(ROOT, "paper_2409_03095_amd", "csrc", fn)).read()
         assert "oracle" not in text.lower(), fn
+
+
+STRUCTS = {"mcmi_csr_in": "CsrIn", "mcmi_csr_out": "CsrOut", "mcmi_params": "Params", "mcmi_stats": "Stats",
+           "mcmi_cdf_opts": "CdfOpts", "mcmi_solve_stats": "SolveStats"}
+
+
+def test_binding_structs_match_the_header(tmp_path):
+    """Every struct the binding passes has the header's size and field offsets, as
+    a C compiler lays them out (gcc on the header, no library code)."""
+    from paper_2409_03095_amd import mcmi
+    lines = ["#include <stdio.h>", "#include <stddef.h>", '#include "mcmi.h"', "int main(void) {"]
+    for cname, pyname in STRUCTS.items():
+        cls = getattr(mcmi, pyname)
+        lines.append(f'printf("{cname} sizeof %zu\\n", sizeof({cname}));')
+        for f, _ in cls._fields_:
+            lines.append(f'printf("{cname} {f} %zu\\n", offsetof({cname}, {f}));')
+    lines.append("return 0; }")
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    subprocess.check_call(["gcc", "-std=c99", "-Wall", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)])
+    got = {}
+    for line in subprocess.check_output([str(exe)], text=True).splitlines():
+        a, b, c = line.split()
+        got[(a, b)] = int(c)
+    for cname, pyname in STRUCTS.items():
+        cls = getattr(mcmi, pyname)
+        assert got[(cname, "sizeof")] == ctypes.sizeof(cls), cname
+        for f, _ in cls._fields_:
+            assert got[(cname, f)] == getattr(cls, f).offset, (cname, f)
