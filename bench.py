@@ -67,9 +67,17 @@ def cpu_baseline(B, chains, delta, eps, fp32, budget_s=20.0):
     t0 = time.perf_counter()
     r = o.spai(seed=0, chains=chains, delta=delta, eps=eps, fp32=fp32, rows=rows, threads=threads)
     dt = time.perf_counter() - t0
+    # one thread on a sample of about a fifth of the all-core run's time
+    n1 = int(min(nrows, max(64, nrows * 0.2 / max(threads, 1))))
+    t1 = time.perf_counter()
+    r1 = o.spai(seed=0, chains=chains, delta=delta, eps=eps, fp32=fp32, rows=rows[:n1], threads=1)
+    dt1 = time.perf_counter() - t1
     return {"value": r["transitions"] / dt, "unit": "transitions/s", "cores": threads, "kind": "oracle",
             "sample": f"{nrows} uniformly sampled rows of the same matrix ({r['transitions']} transitions, "
-                      f"{dt:.1f} s, {threads} threads)"}
+                      f"{dt:.1f} s, {threads} threads)",
+            "single_core_value": r1["transitions"] / dt1,
+            "single_core_sample": f"the first {n1} of those rows on one thread ({r1['transitions']} transitions, "
+                                  f"{dt1:.1f} s)"}
 
 
 def main():
