@@ -668,27 +668,39 @@ extern "C" mcmi_status mcmi_cdf_download(const mcmi_cdf *cdf, uint32_t *rec_host
 namespace mcmi {
 namespace {
 
-// rows of matrix k into the block-diagonal row space; checks its row pointers
-__global__ void __launch_bounds__(256) k_concat_rows(const int64_t *rp, int64_t nk, int64_t nnzk, int64_t row_base,
-                                                     int64_t nnz_base, int32_t k, int64_t *rp_out, int32_t *row_mat,
-                                                     uint32_t *flags) {
-    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nk; i += stride) {
-        rp_out[row_base + i] = rp[i] + nnz_base;
-        row_mat[row_base + i] = k;
-        if (i == 0 && (rp[0] != 0 || rp[nk] != nnzk)) atomicOr(flags, kFlagCsr);
-    }
-}
+// One matrix of a batch: its CSR (device) and where it starts in the
+// block-diagonal row and entry spaces.
+struct BatchPart {
+    const int64_t *rp;
+    const int32_t *col;
+    const double *val;
+    int64_t n, nnz, row_base, nnz_base;
+};
 
-// columns of matrix k shifted by its first row; each must lie in [0, n_k)
-__global__ void __launch_bounds__(256) k_concat_cols(const int32_t *col, int64_t nnzk, int64_t nk, int64_t row_base,
-                                                     int64_t nnz_base, int32_t *col_out, uint32_t *flags) {
+// All matrices of a batch into one block-diagonal CSR in one launch: the blocks
+// of row y of the grid take matrix y. Row pointers are shifted by the matrix's
+// first entry, columns by its first row (each must lie in [0, n_k)), values
+// copied; row_mat records each row's matrix. Matrix k = k_first + blockIdx.y.
+__global__ void __launch_bounds__(256) k_concat(const BatchPart *parts, int32_t k_first, int64_t *rp_out,
+                                                int32_t *col_out, double *val_out, int32_t *row_mat,
+                                                uint32_t *flags) {
+    const int32_t k = k_first + (int32_t)blockIdx.y;
+    const BatchPart p = parts[k];
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < nnzk; j += stride) {
-        const int32_t c = col[j];
-        if (c < 0 || (int64_t)c >= nk) atomicOr(flags, kFlagCsr);
-        col_out[nnz_base + j] = (int32_t)(c + row_base);
+    const int64_t t0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    bool bad = false;
+    for (int64_t i = t0; i < p.n; i += stride) {
+        rp_out[p.row_base + i] = p.rp[i] + p.nnz_base;
+        row_mat[p.row_base + i] = k;
+        if (i == 0) bad |= p.rp[0] != 0 || p.rp[p.n] != p.nnz;
     }
+    for (int64_t j = t0; j < p.nnz; j += stride) {
+        const int32_t c = p.col[j];
+        bad |= c < 0 || (int64_t)c >= p.n;
+        col_out[p.nnz_base + j] = (int32_t)(c + p.row_base);
+        val_out[p.nnz_base + j] = p.val[j];
+    }
+    if (__any(bad) && (threadIdx.x & 63) == 0) atomicOr(flags, kFlagCsr);
 }
 
 // ||Chat_k||_inf per matrix: the largest Shat64 of its rows (bits of non-negative
@@ -747,8 +759,9 @@ extern "C" mcmi_status mcmi_build_cdf_batched_ex(const mcmi_csr_in *Bs, int32_t 
     uint32_t *flags = nullptr;
     int64_t *base_dev = nullptr;
     unsigned long long *nb = nullptr;
+    BatchPart *parts_dev = nullptr;
     auto cleanup = [&]() {  // stream-ordered: behind the last kernel that reads them
-        for (void *t : {(void *)rp, (void *)col, (void *)val, (void *)flags, (void *)nb})
+        for (void *t : {(void *)rp, (void *)col, (void *)val, (void *)flags, (void *)nb, (void *)parts_dev})
             if (t) dev_release(t, s);
     };
 #define TRYB(call)                                                                          \
@@ -770,11 +783,22 @@ extern "C" mcmi_status mcmi_build_cdf_batched_ex(const mcmi_csr_in *Bs, int32_t 
     TRYB(dev_alloc((void **)&nb, count * sizeof(unsigned long long), s));
     TRYB(hipMemsetAsync(flags, 0, sizeof(uint32_t), s));
     TRYB(hipMemsetAsync(nb, 0, count * sizeof(unsigned long long), s));
+    // the parts table lives until the synchronisation below, which the copy precedes
+    std::vector<BatchPart> parts(count);
+    int64_t most = 0;
     for (int32_t k = 0; k < count; ++k) {
-        k_concat_rows<<<grid_for(Bs[k].n), 256, 0, s>>>(Bs[k].row_ptr_dev, Bs[k].n, Bs[k].nnz, rb[k], zb[k], k, rp,
-                                                         row_mat, flags);
-        k_concat_cols<<<grid_for(Bs[k].nnz), 256, 0, s>>>(Bs[k].col_dev, Bs[k].nnz, Bs[k].n, rb[k], zb[k], col, flags);
-        TRYB(hipMemcpyAsync(val + zb[k], Bs[k].val_dev, Bs[k].nnz * sizeof(double), hipMemcpyDeviceToDevice, s));
+        parts[k] = {Bs[k].row_ptr_dev, Bs[k].col_dev, Bs[k].val_dev, Bs[k].n, Bs[k].nnz, rb[k], zb[k]};
+        most = std::max(most, Bs[k].nnz);
+    }
+    TRYB(dev_alloc((void **)&parts_dev, count * sizeof(BatchPart), s));
+    TRYB(hipMemcpyAsync(parts_dev, parts.data(), count * sizeof(BatchPart), hipMemcpyHostToDevice, s));
+    {
+        int64_t gx = (most + 255) / 256;
+        if (gx > 64) gx = 64;  // a few blocks per matrix; 256 matrices fill the chip
+        for (int32_t k0 = 0; k0 < count; k0 += 65535) {  // the grid's y extent is at most 65535
+            const int32_t ky = std::min<int32_t>(65535, count - k0);
+            k_concat<<<dim3((unsigned)gx, (unsigned)ky), 256, 0, s>>>(parts_dev, k0, rp, col, val, row_mat, flags);
+        }
     }
     TRYB(hipGetLastError());
     TRYB(hipMemcpyAsync(rp + n, &nnz, sizeof(int64_t), hipMemcpyHostToDevice, s));

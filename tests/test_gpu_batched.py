@@ -52,6 +52,28 @@ def test_batched_blocks_equal_single_matrix_runs(mc, prec, kw, cell):
     assert res.stats.transitions == total
 
 
+@pytest.mark.parametrize("fault", ["col_high", "col_negative", "row_ptr_end"])
+def test_batched_rejects_a_bad_part(mc, fault):
+    """One malformed matrix in a batch (a column outside [0, n_k) or a last row
+    pointer other than nnz_k) fails the whole batch with the CSR status; the same
+    batch with that matrix intact builds."""
+    mats, _ = I.convdiff_batch(count=5, seed=6, nmin=200, nmax=900)
+    devs = [mc.DeviceCsr.from_host(B) for B in mats]
+    mc.Cdf.batched(devs)
+    bad = devs[3]
+    print(f"[gpu] batched bad part {fault} n={bad.n} nnz={bad.nnz}", flush=True)
+    if fault == "col_high":
+        bad.col[bad.nnz // 2] = bad.n
+    elif fault == "col_negative":
+        bad.col[0] = -1
+    else:
+        bad.row_ptr[-1] = bad.nnz - 1
+    torch.cuda.synchronize()
+    with pytest.raises(mc.McmiError) as e:
+        mc.Cdf.batched(devs)
+    assert e.value.status == -2
+
+
 def test_batched_schedule_rejects_pre_pass_options(mc):
     import ctypes
     mats, _ = I.convdiff_batch(count=3, seed=4, nmin=200, nmax=400)
