@@ -310,6 +310,26 @@ def nonddm(n: int, seed: int, k: int = 6) -> Csr:
     return from_coo(n, np.array(rows), np.array(cols), np.array(vals))
 
 
+def wide_rows(n: int, widths: dict, seed: int = 0, rho: float = 0.7) -> Csr:
+    """random_nonsym-style rows (5..30 off-diagonals) except the rows in `widths`,
+    which get that many off-diagonals at distinct uniform columns (n - 1: every
+    other column); per-row diagonal sum_j |b_ij| / rho."""
+    rng = np.random.default_rng(seed)
+    k = rng.integers(5, 31, size=n)
+    for r, m in widths.items():
+        k[r] = m
+    rows, cols = [], []
+    for r in range(n):
+        c = rng.choice(n - 1, size=int(k[r]), replace=False)
+        cols.append(c + (c >= r))
+        rows.append(np.full(int(k[r]), r, dtype=np.int64))
+    rows = np.concatenate(rows)
+    cols = np.concatenate(cols).astype(np.int64)
+    mag = rng.lognormal(0.0, 1.0, size=rows.size)
+    sign = np.where(rng.random(rows.size) < 0.5, -1.0, 1.0)
+    return _with_row_diagonal(n, rows, cols, sign * mag, rho)
+
+
 def diag_only(n: int, seed: int = 0) -> Csr:
     """B diagonal (so C = 0), diagonal values of both signs."""
     rng = np.random.default_rng(seed)

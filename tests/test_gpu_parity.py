@@ -113,7 +113,20 @@ CASES = {
     "tiny_hash_eps0_regrow": (lambda: I.grid2d_5pt(20, 20), dict(chains=100, delta=1e-3, eps=0.0, hash_slots=64)),
     "seed_and_tag": (lambda: I.random_nonsym(1500, seed=11), dict(chains=33, delta=1e-4, eps=1e-3,
                                                                   seed=0xDEADBEEF12345678, tag=77)),
+    # rows of 70000, 40000 and 3000 entries among rows of 5-30: 14 to 19 bits of
+    # weight resolution, alias construction in global scratch, long record runs
+    "wide_rows": (lambda: _wide(), dict(chains=4, delta=1e-4, eps=1e-3)),
 }
+
+
+def _wide():
+    global _WIDE
+    if _WIDE is None:
+        _WIDE = I.wide_rows(70001, {0: 70000, 17: 40000, 5000: 3000}, seed=12)
+    return _WIDE
+
+
+_WIDE = None
 
 
 @pytest.mark.parametrize("prec", [64, 32])
@@ -131,6 +144,20 @@ def test_edge_cases(mc, case, prec):
     assert orc["guard"] == 0
     assert res.stats.transitions == orc["transitions"]
     compare_spai((rp, col, val), orc, o.diag, kw.get("chains", 16))
+
+
+@pytest.mark.parametrize("prec", [64, 32])
+def test_wide_rows_in_the_workgroup_kernel(mc, prec):
+    """The wide rows (70000, 40000 and 3000 entries) and 61 others with 300 chains
+    each on 256-lane workgroups, against the oracle on the same row subset."""
+    B = _wide()
+    rng = np.random.default_rng(5)
+    rows = np.concatenate([[0, 17, 5000], rng.choice(np.arange(20, 4000), 61, replace=False)]).astype(np.int32)
+    (rp, col, val), res, _ = run(mc, B, seed=8, chains=300, delta=1e-4, eps=1e-3, prec=prec, rows=rows,
+                                 lanes_per_row=256)
+    orc, o = oracle_run(B, seed=8, chains=300, delta=1e-4, eps=1e-3, prec=prec, rows=rows)
+    assert orc["guard"] == 0 and res.stats.transitions == orc["transitions"]
+    compare_spai((rp, col, val), orc, o.diag, 300, rows=rows)
 
 
 def test_rows_subset_and_per_row_chains(mc):

@@ -131,3 +131,13 @@ def test_cycle_plus_random_recipe():
     sums = c_abs_row_sums(B)
     np.testing.assert_allclose(sums, sums[0], rtol=1e-12)  # one ||C||_inf for both blocks
     assert 0.5 <= sums[0] <= 0.8
+
+
+def test_wide_rows_recipe():
+    B = I.wide_rows(2001, {0: 2000, 7: 900}, seed=3)
+    check_csr(B)
+    m = np.diff(B.row_ptr) - 1
+    assert m[0] == 2000 and m[7] == 900
+    rest = np.delete(m, [0, 7])
+    assert rest.min() >= 5 and rest.max() <= 30
+    np.testing.assert_allclose(c_abs_row_sums(B), 0.7, rtol=1e-12)
