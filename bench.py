@@ -80,6 +80,29 @@ def cpu_baseline(B, chains, delta, eps, fp32, budget_s=20.0):
                                   f"{dt1:.1f} s)"}
 
 
+def walk_precision(mcmi, dB, n, chains, delta, eps, seed, nrows=4096):
+    """FP32 walks against FP64 walks on the same sampled rows, after the timed
+    steps: the FP64 path is the one the parity tests hold to the FP64 oracle at
+    1e-12, so this is the FP32 path's error against FP64 arithmetic."""
+    import torch
+    rows = np.sort(np.random.default_rng(7).choice(n, min(n, nrows), replace=False)).astype(np.int32)
+    rows_t = torch.from_numpy(rows).cuda()
+    cdf = mcmi.Cdf(dB)
+    keys, vals = {}, {}
+    for prec in (64, 32):
+        p = mcmi.params(seed=seed, chains=chains, delta=delta, eps=eps, walk_prec=prec)
+        rp, col, val = mcmi.spai(cdf, p, rows=rows_t).to_numpy()
+        keys[prec] = np.repeat(rows.astype(np.int64), np.diff(rp)) * n + col
+        vals[prec] = val
+    common, i64, i32 = np.intersect1d(keys[64], keys[32], assume_unique=True, return_indices=True)
+    v64, v32 = vals[64][i64], vals[32][i32]
+    rel = np.abs(v32 - v64) / np.abs(v64)
+    return {"rows": int(rows.size), "entries_f64": int(keys[64].size), "entries_f32": int(keys[32].size),
+            "pattern_differences": int(keys[64].size + keys[32].size - 2 * common.size),
+            "max_rel_diff_f32_vs_f64": float(rel.max()) if rel.size else 0.0,
+            "median_rel_diff_f32_vs_f64": float(np.median(rel)) if rel.size else 0.0}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -201,6 +224,7 @@ def main():
                 "walk_ms": round(walk_s * 1e3, 3), "walk_transitions_per_s": trans[-1] / walk_s,
                 "gather_ceiling_steps_per_s": ceiling, "gather_probe": probe,
                 "frac_of_gather_ceiling": round(trans[-1] / walk_s / ceiling, 4)}
+    precision = walk_precision(mcmi, dB, B.n, args.chains, delta, eps, seed)
     out = {
         "metric": METRIC,
         "value": value,
@@ -221,6 +245,7 @@ def main():
                    "lanes_per_row": lanes, "hash_slots": hslots, "sketch_slots": sslots,
                    "heavy_weight": tau, "rows_replayed": refined, "order_cell": cell},
         "roofline": roofline,
+        "precision": precision,
     }
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(B, args.chains, delta, eps, args.prec == 32)
