@@ -52,6 +52,36 @@ def test_batched_blocks_equal_single_matrix_runs(mc, prec, kw, cell):
     assert res.stats.transitions == total
 
 
+def test_batched_full_size_sampled_rows(mc):
+    """The benchmark's batched set at full size (256 convection-diffusion matrices,
+    5.75M rows, 128 chains, FP32 walks, delta = 1e-4, eps = 1e-3, tag 0) in one
+    launch, as bench.py runs it; 48 rows of each of 8 sampled matrices compared with
+    the oracle's runs of those rows under the matrix's Philox tag."""
+    mats, _ = I.convdiff_batch(256, seed=3)
+    devs = [mc.DeviceCsr.from_host(B) for B in mats]
+    cdf = mc.Cdf.batched(devs)
+    _, base, _ = cdf.batch_info()
+    print(f"[gpu] batched full size: {int(base[-1])} rows", flush=True)
+    res = mc.spai(cdf, mc.params(seed=0, chains=128, delta=1e-4, eps=1e-3, walk_prec=32))
+    rp_t, col_t, val_t = res.to_torch()
+    torch.cuda.synchronize()
+    rp = rp_t.cpu().numpy()
+    rng = np.random.default_rng(17)
+    for k in sorted(int(x) for x in rng.choice(len(mats), 8, replace=False)):
+        B = mats[k]
+        rows = np.sort(rng.choice(B.n, 48, replace=False)).astype(np.int32)
+        g = rows.astype(np.int64) + int(base[k])
+        pos = np.concatenate([np.arange(rp[r], rp[r + 1]) for r in g])
+        idx = torch.from_numpy(pos).cuda()
+        sub_col = col_t[idx].cpu().numpy() - int(base[k])
+        sub_val = val_t[idx].cpu().numpy()
+        sub_rp = np.concatenate([[0], np.cumsum(rp[g + 1] - rp[g])])
+        o = O.Oracle(B)
+        orc = o.spai(seed=0, chains=128, delta=1e-4, eps=1e-3, fp32=True, tag=k, rows=rows)
+        assert orc["guard"] == 0
+        compare_spai((sub_rp, sub_col, sub_val), orc, o.diag, 128, rows=rows)
+
+
 @pytest.mark.parametrize("fault", ["col_high", "col_negative", "row_ptr_end"])
 def test_batched_rejects_a_bad_part(mc, fault):
     """One malformed matrix in a batch (a column outside [0, n_k) or a last row
