@@ -428,6 +428,15 @@ def batched_main(args):
                  "transitions_per_s": gst.transitions / g_s, "overflow": ovf, "nnz_M": gnnz}
         print(f"[batched] graph replays: {json.dumps(graph)}", flush=True)
         del plan
+    # algorithmic bytes per transition, the mean over all rows of the set
+    nrow = np.array([m.n for m in mats], dtype=np.float64)
+    bpt = float(np.dot(nrow, [algorithmic_bytes_per_transition(m, args.prec == 32) for m in mats]) / nrow.sum())
+    walk_s = float(np.mean(walk_ms)) / 1e3
+    achieved = bpt * st.transitions / walk_s / 1e9
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None, "kernel": "k_walk",
+                "bytes_per_transition": round(bpt, 2), "walk_ms": round(walk_s * 1e3, 3),
+                "walk_transitions_per_s": st.transitions / walk_s}
     out = {"metric": METRIC, "value": trans / elapsed, "unit": "transitions/s", "n_gpus": 1, "steps": args.steps,
            "warmup": args.warmup, "ms_per_step": elapsed / args.steps * 1e3, "higher_is_better": True,
            "dtype": "f32" if args.prec == 32 else "f64", "data": "synthetic",
@@ -436,7 +445,7 @@ def batched_main(args):
                       "transitions_per_step": int(st.transitions), "nnz_M": int(last.nnz),
                       "lanes_per_row": st.lanes_per_row, "hash_slots": st.hash_slots, "order_cell": cell,
                       "tuned": tuned},
-           "walk_ms": float(np.mean(walk_ms)), "graph_replay": graph,
+           "walk_ms": float(np.mean(walk_ms)), "roofline": roofline, "graph_replay": graph,
            "one_launch_per_matrix": {"seconds": single_s, "transitions": int(single_trans),
                                      "transitions_per_s": single_trans / single_s}}
     print(json.dumps(out), flush=True)
