@@ -38,6 +38,8 @@ HBM_PEAK_GBS = 8000.0
 TRAFFIC_BYTES = 3.94e11  # calibrated FETCH_SIZE + WRITE_SIZE of one walk launch (rocprofv3 --pmc)
 # the same for the 160^3 27-point workload's wavefront walk (cells of 4096 rows, FP32)
 TRAFFIC_BYTES_ANISO27 = 5.50e11
+# and for the batched launch of the 256 convection-diffusion matrices (128 chains, FP32)
+TRAFFIC_BYTES_BATCHED = 1.049e12
 
 
 def algorithmic_bytes_per_transition(B, fp32: bool) -> float:
@@ -434,7 +436,10 @@ def batched_main(args):
     walk_s = float(np.mean(walk_ms)) / 1e3
     achieved = bpt * st.transitions / walk_s / 1e9
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None, "kernel": "k_walk",
+                "frac": round(achieved / HBM_PEAK_GBS, 4),
+                "traffic": TRAFFIC_BYTES_BATCHED if (args.prec == 32 and chains == 128 and cell == 0 and not args.tune
+                                                     and not args.lanes and not args.hash_slots) else None,
+                "kernel": "k_walk",
                 "bytes_per_transition": round(bpt, 2), "walk_ms": round(walk_s * 1e3, 3),
                 "walk_transitions_per_s": st.transitions / walk_s}
     out = {"metric": METRIC, "value": trans / elapsed, "unit": "transitions/s", "n_gpus": 1, "steps": args.steps,
