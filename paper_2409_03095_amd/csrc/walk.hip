@@ -139,7 +139,7 @@ __device__ __forceinline__ void chain_step(const WalkArgs &a, ChainSt &ch, int s
         const int32_t key = (int32_t)h.x;
         if (!lds_add(gkeys, gvals, hmask, hash_key(key, hshift), key, wcur)) {
             ++spilled;
-            if (!spill_add(gskeys, gsvals, gsused, gspill, smask, key, wcur)) spill_full = true;
+            if (!spill_add_window(gskeys, gsvals, gsused, gspill, smask, key, wcur)) spill_full = true;
         }
     }
     if (stop) {

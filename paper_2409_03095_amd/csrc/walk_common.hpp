@@ -69,6 +69,48 @@ __device__ __forceinline__ bool lds_add(int32_t *keys, double *vals, uint32_t ma
     return false;
 }
 
+// One slot of an HBM hash probe: claim it if empty, add if it holds the key.
+// Returns 1 when w was added, 0 when the slot holds another key.
+__device__ __forceinline__ int spill_try(int32_t *keys, double *vals, int32_t *used, int *used_cnt, uint32_t h,
+                                         int32_t key, double w) {
+    int32_t k = __atomic_load_n(&keys[h], __ATOMIC_RELAXED);
+    if (k == kEmpty) {
+        const int32_t prev = atomicCAS(&keys[h], kEmpty, key);
+        if (prev == kEmpty) {
+            const int u = atomicAdd(used_cnt, 1);
+            used[u] = (int32_t)h;
+            k = key;
+        } else {
+            k = prev;
+        }
+    }
+    if (k != key) return 0;
+    atomicAdd(&vals[h], w);
+    return 1;
+}
+
+// Per-wave HBM hash of the wavefront kernel (nothing else looks keys up in it):
+// a key first tries 16 slots of the table's first kSpillWindow, where a row's
+// overflow usually fits, so that it occupies few cache lines of a table sized for
+// the worst case; then the whole table. Returns false when the table is full.
+constexpr uint32_t kSpillWindow = 2048;
+__device__ __forceinline__ bool spill_add_window(int32_t *keys, double *vals, int32_t *used, int *used_cnt,
+                                                 uint32_t mask, int32_t key, double w) {
+    const uint32_t hk = (uint32_t)key * 0x85EBCA6Bu;
+    const uint32_t wmask = mask < kSpillWindow - 1u ? mask : kSpillWindow - 1u;
+    uint32_t h = hk & wmask;
+    for (int p = 0; p < 16; ++p) {
+        if (spill_try(keys, vals, used, used_cnt, h, key, w)) return true;
+        h = (h + 1) & wmask;
+    }
+    h = hk & mask;
+    for (uint32_t p = 0; p <= mask; ++p) {
+        if (spill_try(keys, vals, used, used_cnt, h, key, w)) return true;
+        h = (h + 1) & mask;
+    }
+    return false;
+}
+
 // per-wave HBM hash; returns false when the table is full
 __device__ __forceinline__ bool spill_add(int32_t *keys, double *vals, int32_t *used, int *used_cnt, uint32_t mask,
                                           int32_t key, double w) {
