@@ -39,7 +39,7 @@ TRAFFIC_BYTES = 3.94e11  # calibrated FETCH_SIZE + WRITE_SIZE of one walk launch
 # the same for the 160^3 27-point workload's wavefront walk (cells of 4096 rows, FP32)
 TRAFFIC_BYTES_ANISO27 = 5.50e11
 # and for the batched launch of the 256 convection-diffusion matrices (128 chains, FP32)
-TRAFFIC_BYTES_BATCHED = 1.049e12
+TRAFFIC_BYTES_BATCHED = 9.93e11
 
 
 def algorithmic_bytes_per_transition(B, fp32: bool) -> float:
