@@ -66,6 +66,65 @@ int device_cus() {
 }
 
 
+// Task order of a batched record set (longest-processing-time first): matrix k
+// costs about N (L_k + 1) per row with L_k its chain-length bound; blocks of 64
+// consecutive rows (of the set's schedule, if it has one) in decreasing cost are
+// dealt round-robin to the eight XCD queue slices. Writes cdf->n row indices to
+// `map` (device); synchronises the stream before it returns.
+hipError_t batched_lpt_map(const mcmi_cdf *cdf, double delta, int lmax, int n_hint, int32_t *map, hipStream_t s) {
+    {  // host tables of the order, freed at the end of this scope
+        const int K = cdf->batch;
+        std::vector<double> cost(K);
+        for (int k = 0; k < K; ++k) {
+            const double S = cdf->mat_norm[k];
+            double L = (double)lmax;
+            if (S > 0.0 && S < 1.0 && delta > 0.0) L = std::min(L, std::ceil(std::log(delta) / std::log(S)));
+            if (S == 0.0) L = 0.0;
+            cost[k] = (double)n_hint * (L + 1.0);
+        }
+        std::vector<int> ord(K);
+        for (int k = 0; k < K; ++k) ord[k] = k;
+        std::stable_sort(ord.begin(), ord.end(), [&](int x, int y) { return cost[x] > cost[y]; });
+        // the host orders blocks (start, count) only; the device expands them to rows
+        std::vector<std::vector<std::pair<int32_t, int32_t>>> lists(8);
+        int64_t blk = 0;
+        for (int k : ord) {
+            for (int64_t r0 = cdf->mat_base_host[k]; r0 < cdf->mat_base_host[k + 1]; r0 += 64, ++blk) {
+                const int64_t r1 = std::min<int64_t>(r0 + 64, cdf->mat_base_host[k + 1]);
+                lists[blk % 8].push_back({(int32_t)r0, (int32_t)(r1 - r0)});
+            }
+        }
+        std::vector<int32_t> bstart, bcnt;
+        std::vector<int64_t> bpos;
+        bstart.reserve(blk);
+        bcnt.reserve(blk);
+        bpos.reserve(blk);
+        int64_t at = 0;
+        for (auto &L : lists)
+            for (auto &b : L) {
+                bstart.push_back(b.first);
+                bcnt.push_back(b.second);
+                bpos.push_back(at);
+                at += b.second;
+            }
+        const size_t nb = bstart.size();
+        void *bdesc = nullptr;
+        hipError_t e = dev_alloc(&bdesc, nb * 16 + 16, s);
+        if (e != hipSuccess) return e;
+        int32_t *d_start = (int32_t *)bdesc, *d_cnt = d_start + nb;
+        int64_t *d_pos = (int64_t *)((unsigned char *)bdesc + ((nb * 8 + 15) / 16) * 16);
+        e = hipMemcpyAsync(d_start, bstart.data(), nb * 4, hipMemcpyHostToDevice, s);
+        if (e == hipSuccess) e = hipMemcpyAsync(d_cnt, bcnt.data(), nb * 4, hipMemcpyHostToDevice, s);
+        if (e == hipSuccess) e = hipMemcpyAsync(d_pos, bpos.data(), nb * 8, hipMemcpyHostToDevice, s);
+        if (e == hipSuccess) e = expand_blocks((int64_t)nb, d_start, d_cnt, d_pos, cdf->order, map, s);
+        // the host vectors die at the end of this scope: nothing may still read them
+        const hipError_t se = hipStreamSynchronize(s);
+        if (e == hipSuccess) e = se;
+        dev_release(bdesc, s);
+        return e;
+    }
+}
+
 // Kernel shape of a run: lanes per row (64 = wavefront kernel), LDS hash slots,
 // count-sketch buckets and heavy threshold tau (0 = track every contribution).
 // n_max: the largest chain count of a row.
@@ -314,58 +373,12 @@ extern "C" mcmi_status mcmi_spai(const mcmi_cdf *cdf, const mcmi_params *p, cons
     unsigned long long *collect = (unsigned long long *)(ctrl.as<unsigned char>() + 80);
 
 
-    // batched record sets: longest-processing-time order. Per-row cost N (L_k + 1)
-    // with L_k the chain-length bound of matrix k; blocks of 64 consecutive rows (of
-    // the set's schedule, if it has one) in decreasing cost, dealt round-robin to the
-    // eight XCD queue slices.
+    // batched record sets: longest-processing-time order (batched_lpt_map)
     DevBuf lpt;
     const int32_t *task_map = nullptr;
     if (cdf->batch > 0 && !rows_dev) {
-        const int K = cdf->batch;
-        std::vector<double> cost(K);
-        for (int k = 0; k < K; ++k) {
-            const double S = cdf->mat_norm[k];
-            double L = (double)lmax;
-            if (S > 0.0 && S < 1.0 && p->delta > 0.0) L = std::min(L, std::ceil(std::log(p->delta) / std::log(S)));
-            if (S == 0.0) L = 0.0;
-            cost[k] = (double)n_hint * (L + 1.0);
-        }
-        std::vector<int> ord(K);
-        for (int k = 0; k < K; ++k) ord[k] = k;
-        std::stable_sort(ord.begin(), ord.end(), [&](int x, int y) { return cost[x] > cost[y]; });
-        // the host orders blocks (start, count) only; the device expands them to rows
-        std::vector<std::vector<std::pair<int32_t, int32_t>>> lists(8);
-        int64_t blk = 0;
-        for (int k : ord) {
-            for (int64_t r0 = cdf->mat_base_host[k]; r0 < cdf->mat_base_host[k + 1]; r0 += 64, ++blk) {
-                const int64_t r1 = std::min<int64_t>(r0 + 64, cdf->mat_base_host[k + 1]);
-                lists[blk % 8].push_back({(int32_t)r0, (int32_t)(r1 - r0)});
-            }
-        }
-        std::vector<int32_t> bstart, bcnt;
-        std::vector<int64_t> bpos;
-        bstart.reserve(blk);
-        bcnt.reserve(blk);
-        bpos.reserve(blk);
-        int64_t at = 0;
-        for (auto &L : lists)
-            for (auto &b : L) {
-                bstart.push_back(b.first);
-                bcnt.push_back(b.second);
-                bpos.push_back(at);
-                at += b.second;
-            }
-        DevBuf bdesc;
-        const size_t nb = bstart.size();
-        MCMI_HIP(bdesc.alloc(nb * 16 + 16, s));
-        int32_t *d_start = bdesc.as<int32_t>(), *d_cnt = d_start + nb;
-        int64_t *d_pos = (int64_t *)(bdesc.as<unsigned char>() + ((nb * 8 + 15) / 16) * 16);
-        MCMI_HIP(hipMemcpyAsync(d_start, bstart.data(), nb * 4, hipMemcpyHostToDevice, s));
-        MCMI_HIP(hipMemcpyAsync(d_cnt, bcnt.data(), nb * 4, hipMemcpyHostToDevice, s));
-        MCMI_HIP(hipMemcpyAsync(d_pos, bpos.data(), nb * 8, hipMemcpyHostToDevice, s));
         MCMI_HIP(lpt.alloc((size_t)n_tasks * sizeof(int32_t), s));
-        MCMI_HIP(expand_blocks((int64_t)nb, d_start, d_cnt, d_pos, cdf->order, lpt.as<int32_t>(), s));
-        MCMI_HIP(hipStreamSynchronize(s));  // the host vectors die at the end of this scope
+        MCMI_HIP(batched_lpt_map(cdf, p->delta, lmax, n_hint, lpt.as<int32_t>(), s));
         task_map = lpt.as<int32_t>();
     } else if (cdf->batch == 0 && !rows_dev && cdf->order) {
         task_map = cdf->order;  // locality schedule of the record set
