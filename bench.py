@@ -282,13 +282,13 @@ def aniso_main(args):
 
     def chains_for(cdf):
         # learned allocation: features -> network -> chains per row for the same
-        # mean budget (cost 1 + ceil(f7) per chain), uniform fallback inside mcmi_allocate
+        # mean budget (chain cost 1 + floor(f7), mcmi_chain_cost), uniform fallback inside mcmi_allocate
         if net is None:
             return None
         feat = mcmi.row_features(cdf, 1e-4)
         pred = net.predict(feat)
-        cost = (1.0 + torch.ceil(feat[:, 7])).to(torch.int32)
-        cpr, lam, fb = mcmi.allocate(pred, cost, int(chains * int(cost.sum().item())))
+        cost, total_cost = mcmi.chain_cost(feat)
+        cpr, lam, fb = mcmi.allocate(pred, cost, int(chains * total_cost))
         alloc.update({"lambda": lam, "fallback": fb})
         return cpr
 

@@ -296,6 +296,29 @@ mcmi_status mcmi_mlp_train(mcmi_mlp *net, const float *feat_dev, const float *ta
 mcmi_status mcmi_allocate(const float *pred_dev, const int32_t *cost_dev, int64_t n, int64_t budget,
                           int32_t *chains_dev, double *lambda_host, int32_t *fallback_host, void *stream);
 
+/* Regression target of the allocation network, per row. Neyman allocation:
+ * minimising the summed variance sum_r v_r / N_r of the row estimates under a
+ * budget sum_r N_r (len_r + 1) = T gives N_r proportional to sqrt(v_r / (len_r +
+ * 1)), so y_dev[r] = (ln max(v_r, 1e-30) - ln(len_r + 1)) / 2 (binary32) from the
+ * float64 var_dev and len_dev of mcmi_pilot_variance (n rows each). The variance
+ * per chain is that of the estimator of Section III-A, eq. (2). Asynchronous. */
+mcmi_status mcmi_neyman_target(const double *var_dev, const double *len_dev, int64_t n, float *y_dev,
+                               void *stream);
+/* Budget units of one chain per row, from the row features (feat_dev n x 8, as
+ * written by mcmi_row_features): cost_dev[r] = 1 + floor(f7_r), the states a
+ * chain from r visits when every row on its path has row r's |C| row sum (exact
+ * when all row sums are equal: a chain then makes floor(f7) transitions). With
+ * total_host non-NULL it receives sum_r cost_r (64-bit) and the call
+ * synchronises the stream; otherwise it is asynchronous. */
+mcmi_status mcmi_chain_cost(const float *feat_dev, int64_t n, int32_t *cost_dev, int64_t *total_host,
+                            void *stream);
+/* One Adam step (beta1 0.9, beta2 0.999, eps 1e-8, bias-corrected moments, as in
+ * mcmi_mlp_train) of the network's FP32 master parameters with a caller-supplied
+ * gradient grad_dev (4801 floats, device, in the parameter order above) and
+ * learning rate lr > 0; the BF16 copies follow. For gradients that the caller
+ * computes or combines itself. Asynchronous. */
+mcmi_status mcmi_mlp_adam_step(mcmi_mlp *net, const float *grad_dev, float lr, void *stream);
+
 /* ------------------------------------------------------ tuning and plans */
 
 /* Autotuner: times candidate kernel shapes (lanes per row, LDS hash slots,

@@ -1031,13 +1031,15 @@ int orc_pilot(const orc_mat *A, const orc_params *p, int32_t pilot, double *var,
 }
 
 /* --------------------------------------------------------- row features */
-/* Eight features per row i (p_ij = w_ij / W_i the quantized transition
- * probabilities, S = Shat, m = entries of the row of C):
+/* Eight features per row i of the sampled matrix Chat (O2: |chat_ij| = S_i w_ij
+ * / W_i with the sign of c_ij; p_ij = w_ij / W_i its transition probabilities,
+ * S = Shat, m = entries of the row of C):
  *   f0 = ln(max(m_i, 1))          f1 = S_i
- *   f2 = a_max,i = max_j |c_ij|    f3 = sum_j p_ij S_j
+ *   f2 = max_j |chat_ij|           f3 = sum_j p_ij S_j
  *   f4 = max_j S_j                 f5 = sum_j p_ij m_j
- *   f6 = |sum_j c_ij| / S_i        f7 = min(L_max, ln(delta) / ln(S_i))
- * with f3..f6 = 0 for an empty row and f7 = 0 when S_i = 0. */
+ *   f6 = |sum_j chat_ij| / S_i     f7 = min(L_max, ln(delta) / ln(S_i))
+ * with f2..f6 = 0 for an empty row, f7 = L_max when S_i >= 1 and f7 = 0 when
+ * S_i = 0. These are inputs of the learned allocation, not part of the paper. */
 void orc_features(const orc_mat *A, double delta, int lmax, double *feat)
 {
     for (int64_t i = 0; i < A->n; ++i) {
@@ -1047,21 +1049,23 @@ void orc_features(const orc_mat *A, double delta, int lmax, double *feat)
         double s = A->shat[i];
         f[0] = log((double)(m > 1 ? m : 1));
         f[1] = s;
-        double amax = 0.0, ps = 0.0, smax = 0.0, pm = 0.0, csum = 0.0;
+        double cmax = 0.0, ps = 0.0, smax = 0.0, pm = 0.0, csum = 0.0;
         uint32_t prev = 0;
         for (int64_t k = b; k < e; ++k) {
-            double pk = (double)(A->cum[k] - prev) / (double)A->wsum[i];
+            uint32_t w = A->cum[k] - prev;
             prev = A->cum[k];
+            double pk = (double)w / (double)A->wsum[i];
+            double chat = s * (double)w / (double)A->wsum[i];
             int64_t j = A->ccol[k];
-            if (fabs(A->cval[k]) > amax)
-                amax = fabs(A->cval[k]);
+            if (chat > cmax)
+                cmax = chat;
             ps += pk * A->shat[j];
             if (A->shat[j] > smax)
                 smax = A->shat[j];
             pm += pk * (double)(A->cptr[j + 1] - A->cptr[j]);
-            csum += A->cval[k];
+            csum += A->cval[k] < 0.0 ? -chat : chat;
         }
-        f[2] = amax;
+        f[2] = cmax;
         f[3] = ps;
         f[4] = smax;
         f[5] = pm;

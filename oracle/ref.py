@@ -400,6 +400,17 @@ def neyman_target(var, mean_len):
     return 0.5 * (np.log(v) - np.log(np.asarray(mean_len, dtype=np.float64) + 1.0))
 
 
+def chain_cost(f7):
+    """Budget units of one chain per row: 1 + floor(f7), with f7 = min(L_max,
+    ln delta / ln S_i) the feature as stored (binary32, so the integer decision is
+    taken in the precision of the stored feature). When every row of C has the
+    same |C| row sum S, a chain makes exactly floor(ln delta / ln S) transitions
+    (it stops before the draw whose weight S^j would fall below delta), so the
+    cost is its number of visited states."""
+    f = np.asarray(f7, dtype=np.float32).astype(np.float64)
+    return (1 + np.floor(np.maximum(f, 0.0))).astype(np.int64)
+
+
 def allocate(pred_log, cost, budget, iters=100):
     """N_r = max(1, round(lam * exp(pred_r))) with lam found by bisection so that
     sum_r N_r cost_r is as close to `budget` as possible without exceeding it."""

@@ -242,6 +242,41 @@ __global__ void __launch_bounds__(64) k_pilot(WalkArgs a, int pilot, int cap, do
     }
 }
 
+// Neyman allocation target of each row: minimising sum_r v_r / N_r under
+// sum_r N_r (len_r + 1) = T gives N_r proportional to sqrt(v_r / (len_r + 1)), so
+// the network regresses y_r = (ln v_r - ln(len_r + 1)) / 2 (v floored at 1e-30 so
+// that rows with a deterministic chain get a finite, very small share).
+__global__ void __launch_bounds__(256) k_neyman_target(int64_t n, const double *__restrict__ var,
+                                                       const double *__restrict__ len, float *__restrict__ y) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < n; r += stride) {
+        const double v = var[r] > 1e-30 ? var[r] : 1e-30;
+        y[r] = (float)(0.5 * (log(v) - log(len[r] + 1.0)));
+    }
+}
+
+// Budget units of one chain of each row: the states it visits when every row on
+// its path has the row's own |C| row sum, 1 + floor(f7) (f7 = min(L_max,
+// ln delta / ln S), the feature the network also sees); exact for matrices with
+// equal row sums. Partial sums of the costs per workgroup, in 64-bit integers.
+__global__ void __launch_bounds__(256) k_chain_cost(int64_t n, const float *__restrict__ feat,
+                                                    int32_t *__restrict__ cost,
+                                                    unsigned long long *__restrict__ total) {
+    __shared__ unsigned long long red[4];
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    unsigned long long sum = 0;
+    for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < n; r += stride) {
+        const float f7 = feat[8 * r + 7];
+        const int32_t c = 1 + (int32_t)floorf(f7 > 0.f ? f7 : 0.f);
+        cost[r] = c;
+        sum += (unsigned long long)c;
+    }
+    for (int off = 32; off > 0; off >>= 1) sum += __shfl_down(sum, off, 64);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = sum;
+    __syncthreads();
+    if (threadIdx.x == 0) atomicAdd(total, red[0] + red[1] + red[2] + red[3]);
+}
+
 }  // namespace
 
 hipError_t launch_features(const mcmi_cdf *cdf, double delta, int lmax, float *feat, hipStream_t s) {
@@ -368,4 +403,41 @@ extern "C" mcmi_status mcmi_pilot_variance(const mcmi_cdf *cdf, const mcmi_param
         if (hflags & kFlagSpill) spill_slots *= 4;
     }
     return fail(MCMI_ERR_CAPACITY, "mcmi_pilot_variance: tables still overflow");
+}
+
+extern "C" mcmi_status mcmi_neyman_target(const double *var_dev, const double *len_dev, int64_t n, float *y_dev,
+                                          void *stream) {
+    if (n < 0 || (n > 0 && (!var_dev || !len_dev || !y_dev)))
+        return fail(MCMI_ERR_ARG, "mcmi_neyman_target: bad argument");
+    if (n == 0) return MCMI_OK;
+    const int64_t blocks = std::min<int64_t>((n + 255) / 256, 8192);
+    k_neyman_target<<<(unsigned)blocks, 256, 0, (hipStream_t)stream>>>(n, var_dev, len_dev, y_dev);
+    MCMI_HIP(hipGetLastError());
+    return MCMI_OK;
+}
+
+extern "C" mcmi_status mcmi_chain_cost(const float *feat_dev, int64_t n, int32_t *cost_dev, int64_t *total_host,
+                                       void *stream) {
+    if (n < 0 || (n > 0 && (!feat_dev || !cost_dev)))
+        return fail(MCMI_ERR_ARG, "mcmi_chain_cost: bad argument");
+    if (total_host) *total_host = 0;
+    if (n == 0) return MCMI_OK;
+    if (n > (int64_t)INT32_MAX * 4) return fail(MCMI_ERR_ARG, "mcmi_chain_cost: too many rows");
+    hipStream_t s = (hipStream_t)stream;
+    unsigned long long *tot = nullptr;
+    MCMI_HIP(hipMallocAsync((void **)&tot, sizeof(unsigned long long), s));
+    hipError_t e = hipMemsetAsync(tot, 0, sizeof(unsigned long long), s);
+    const int64_t blocks = std::min<int64_t>((n + 255) / 256, 4096);
+    if (e == hipSuccess) {
+        k_chain_cost<<<(unsigned)blocks, 256, 0, s>>>(n, feat_dev, cost_dev, tot);
+        e = hipGetLastError();
+    }
+    unsigned long long h = 0;
+    if (e == hipSuccess && total_host) e = hipMemcpyAsync(&h, tot, sizeof(h), hipMemcpyDeviceToHost, s);
+    const hipError_t ef = hipFreeAsync(tot, s);
+    if (e == hipSuccess) e = ef;
+    if (e == hipSuccess && total_host) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return fail(MCMI_ERR_HIP, std::string("mcmi_chain_cost: ") + hipGetErrorString(e));
+    if (total_host) *total_host = (int64_t)h;
+    return MCMI_OK;
 }

@@ -533,6 +533,18 @@ extern "C" mcmi_status mcmi_mlp_train(mcmi_mlp *net, const float *feat_dev, cons
     return MCMI_OK;
 }
 
+extern "C" mcmi_status mcmi_mlp_adam_step(mcmi_mlp *net, const float *grad_dev, float lr, void *stream) {
+    if (!net || !grad_dev || !(lr > 0.f)) return fail(MCMI_ERR_ARG, "mcmi_mlp_adam_step: bad argument");
+    hipStream_t s = (hipStream_t)stream;
+    const float b1 = 0.9f, b2 = 0.999f, eps = 1e-8f;
+    net->t += 1;
+    const float bc1 = 1.f - powf(b1, (float)net->t), bc2 = 1.f - powf(b2, (float)net->t);
+    k_adam<<<(kParams + 255) / 256, 256, 0, s>>>(net->master, net->m, net->v, grad_dev, net->w1b, net->w2b,
+                                                 net->w3b, lr, b1, b2, eps, bc1, bc2, nullptr, 0.f);
+    MCMI_HIP(hipGetLastError());
+    return MCMI_OK;
+}
+
 // ------------------------------------------------------------ allocation
 // N_r = max(1, rint(lambda * exp(pred_r))) with lambda found by bisection so that
 // sum_r N_r cost_r is the largest total not above the budget: hi doubles from 1

@@ -2,17 +2,18 @@
 and compare learned vs uniform chains per row at equal transition budgets.
 
 Pipeline (every numerical step runs in libmcmi.so through the C ABI; torch only
-holds device memory and does elementwise glue):
+holds device memory):
 
 1. training matrices -> records (mcmi_build_cdf) -> row features
    (mcmi_row_features) and pilot variance v_r and mean chain length len_r
    (mcmi_pilot_variance);
-2. regression target y_r = (ln v_r - ln(len_r + 1)) / 2: Neyman allocation
-   (minimise sum_r v_r / N_r subject to sum_r N_r (len_r + 1) = T) gives
-   N_r proportional to exp(y_r);
+2. regression target y_r = (ln v_r - ln(len_r + 1)) / 2 (mcmi_neyman_target):
+   Neyman allocation (minimise sum_r v_r / N_r subject to
+   sum_r N_r (len_r + 1) = T) gives N_r proportional to exp(y_r);
 3. the 8-64-64-1 network is trained on (features, y) with Adam (mcmi_mlp_train);
 4. on a held-out matrix: features -> prediction (mcmi_mlp_predict) -> chains per
-   row (mcmi_allocate, budget in transitions with per-row cost 1 + ceil(f7)),
+   row (mcmi_allocate, budget in visited states with per-row chain cost
+   1 + floor(f7) from mcmi_chain_cost),
    uniform allocation gets the same budget -> mcmi_spai with the per-row chains;
 5. quality: ||I - M B||_F / sqrt(n) on a uniform row sample (exact sparse
    products on the host), with a 95 % interval.
@@ -34,12 +35,10 @@ def _dev(B):
 
 def pilot_targets(B, delta, pilot=64, seed=0, prec=64):
     """Features and Neyman targets of every row of B (device tensors)."""
-    import torch
     cdf = mcmi.Cdf(_dev(B))
     feat = mcmi.row_features(cdf, delta)
     var, ln = mcmi.pilot_variance(cdf, mcmi.params(seed=seed, delta=delta, walk_prec=prec), pilot)
-    y = 0.5 * (torch.log(torch.clamp(var, min=1e-30)) - torch.log(ln + 1.0))
-    return feat, y.to(torch.float32), cdf
+    return feat, mcmi.neyman_target(var, ln), cdf
 
 
 def train_allocator(train_mats, delta, steps=3000, batch=4096, lr=2e-3, seed=0, pilot=64, init_seed=0):
@@ -122,8 +121,9 @@ def evaluate(B, chains_per_row, delta, eps, seed=0, rows_sample=None, prec=64, c
 
 
 def compare(net, B, delta, eps, budgets, seed=0, n_sample=10000, prec=64):
-    """Learned vs uniform at each mean-chains budget. Budget in transitions-cost
-    units: sum_r N_r (1 + ceil(f7_r)) = budget_mean * sum_r (1 + ceil(f7_r))."""
+    """Learned vs uniform at each mean-chains budget. Budget in chain-cost units
+    (mcmi_chain_cost, 1 + floor(f7_r) per chain):
+    sum_r N_r cost_r <= budget_mean * sum_r cost_r."""
     import torch
     cdf = mcmi.Cdf(_dev(B))
     t0 = time.perf_counter()
@@ -131,8 +131,7 @@ def compare(net, B, delta, eps, budgets, seed=0, n_sample=10000, prec=64):
     pred = net.predict(feat)
     torch.cuda.synchronize()
     t_infer = time.perf_counter() - t0
-    cost = (1.0 + torch.ceil(feat[:, 7])).to(torch.int32)
-    total_cost = int(cost.sum().item())
+    cost, total_cost = mcmi.chain_cost(feat)
     rng = np.random.default_rng(12345)
     rows = np.sort(rng.choice(B.n, min(n_sample, B.n), replace=False))
     out = []

@@ -108,6 +108,9 @@ _sig = {
     "mcmi_mlp_train": [_v, _v, _v, ctypes.c_int64, ctypes.c_int32, ctypes.c_int32, ctypes.c_float, ctypes.c_uint64,
                        _v, _v],
     "mcmi_allocate": [_v, _v, ctypes.c_int64, ctypes.c_int64, _v, _P(ctypes.c_double), _P(ctypes.c_int32), _v],
+    "mcmi_neyman_target": [_v, _v, ctypes.c_int64, _v, _v],
+    "mcmi_chain_cost": [_v, ctypes.c_int64, _v, _P(ctypes.c_int64), _v],
+    "mcmi_mlp_adam_step": [_v, _v, ctypes.c_float, _v],
 }
 for _name, _args in _sig.items():
     getattr(_lib, _name).argtypes = _args
@@ -130,6 +133,7 @@ EXPORTED = ["mcmi_cache_trim", "mcmi_bicgstab", "mcmi_build_cdf", "mcmi_build_cd
             "mcmi_row_features", "mcmi_pilot_variance", "mcmi_mlp_create", "mcmi_mlp_free",
             "mcmi_mlp_set_params", "mcmi_mlp_get_params", "mcmi_mlp_set_adam_state", "mcmi_mlp_fit_normalization",
             "mcmi_mlp_predict", "mcmi_mlp_gradient", "mcmi_mlp_train", "mcmi_allocate",
+            "mcmi_neyman_target", "mcmi_chain_cost", "mcmi_mlp_adam_step",
             "mcmi_build_cdf_batched", "mcmi_build_cdf_batched_ex", "mcmi_cdf_batch_info", "mcmi_tune", "mcmi_plan_create", "mcmi_plan_launch",
             "mcmi_plan_result", "mcmi_plan_free", "mcmi_gather_probe"]
 
@@ -395,6 +399,11 @@ class Mlp:
                                    ctypes.c_uint64(seed), losses.ctypes.data_as(_v), _stream(stream)))
         return losses[:steps]
 
+    def adam_step(self, grad, lr=1e-3, stream=None):
+        """mcmi_mlp_adam_step: one Adam step with the float32 device gradient `grad`."""
+        assert grad.numel() == MLP_PARAMS
+        _check(_lib.mcmi_mlp_adam_step(self._h, _ptr(grad), ctypes.c_float(lr), _stream(stream)))
+
     def free(self):
         if self._h:
             _lib.mcmi_mlp_free(self._h)
@@ -405,6 +414,25 @@ class Mlp:
             self.free()
         except Exception:
             pass
+
+
+def neyman_target(var, ln, stream=None):
+    """mcmi_neyman_target: float32 regression target per row from the pilot's
+    float64 variance and mean length (device tensors)."""
+    import torch
+    y = torch.empty(var.numel(), dtype=torch.float32, device=var.device)
+    _check(_lib.mcmi_neyman_target(_ptr(var), _ptr(ln), ctypes.c_int64(var.numel()), _ptr(y), _stream(stream)))
+    return y
+
+
+def chain_cost(feat, stream=None):
+    """mcmi_chain_cost: (int32 cost per row, total) from the (n, 8) features."""
+    import torch
+    cost = torch.empty(feat.shape[0], dtype=torch.int32, device=feat.device)
+    tot = ctypes.c_int64()
+    _check(_lib.mcmi_chain_cost(_ptr(feat), ctypes.c_int64(feat.shape[0]), _ptr(cost), ctypes.byref(tot),
+                                _stream(stream)))
+    return cost, tot.value
 
 
 def allocate(pred, cost, budget, stream=None):

@@ -53,6 +53,65 @@ def test_pilot_variance(mc, name, prec):
     assert np.all(np.abs(var - rv) <= 1e-10 * scale + 1e-12), np.max(np.abs(var - rv) / scale)
 
 
+def test_neyman_target_matches_oracle(mc):
+    """mcmi_neyman_target against the oracle's target on the same float64 inputs,
+    incl. zero and subnormal variances (floored at 1e-30) and zero lengths: the
+    binary32 result is within one rounding (2^-24 relative) of the FP64 value,
+    plus 1e-12 for the last bits of the two logarithms."""
+    rng = np.random.default_rng(4)
+    n = 100003
+    var = rng.lognormal(-2.0, 3.0, size=n)
+    var[:50] = 0.0
+    var[50:60] = 1e-310
+    ln = rng.uniform(0.0, 40.0, size=n)
+    ln[::7] = 0.0
+    y = mc.neyman_target(torch.from_numpy(var).cuda(), torch.from_numpy(ln).cuda()).cpu().numpy()
+    ref = O.neyman_target(var, ln)
+    assert np.all(np.abs(y.astype(np.float64) - ref) <= np.abs(ref) * 2.0 ** -24 + 1e-12)
+
+
+@pytest.mark.parametrize("name", ["family", "nonsym"])
+def test_pilot_target_matches_oracle(mc, name):
+    """Pilot run then target on the device against the oracle's pilot and target:
+    the variances agree to 1e-10 relative (different summation order), so the
+    targets agree to one binary32 rounding plus 1e-10."""
+    B = MATS[name]()
+    cdf = mc.Cdf(mc.DeviceCsr.from_host(B))
+    var, ln = mc.pilot_variance(cdf, mc.params(seed=3, delta=1e-4, tag=2), 64)
+    y = mc.neyman_target(var, ln).cpu().numpy().astype(np.float64)
+    rv, rl = O.Oracle(B).pilot(seed=3, pilot=64, delta=1e-4, tag=2)
+    ref = O.neyman_target(rv, rl)
+    assert np.all(np.abs(y - ref) <= np.abs(ref) * 2.0 ** -24 + 1e-10)
+
+
+@pytest.mark.parametrize("name", sorted(MATS))
+def test_chain_cost_matches_oracle(mc, name):
+    """mcmi_chain_cost against the oracle's chain cost of the same stored f7
+    (the integer decision taken on the binary32 feature on both sides): equal per
+    row and in total."""
+    B = MATS[name]()
+    cdf = mc.Cdf(mc.DeviceCsr.from_host(B))
+    feat = mc.row_features(cdf, 1e-3)
+    cost, total = mc.chain_cost(feat)
+    ref = O.chain_cost(feat[:, 7].cpu().numpy())
+    assert np.array_equal(cost.cpu().numpy().astype(np.int64), ref)
+    assert total == int(ref.sum())
+
+
+def test_chain_cost_total_over_many_rows(mc):
+    """3,000,017 rows (a ragged grid) with f7 spread over [0, 65]: exact 64-bit total."""
+    rng = np.random.default_rng(6)
+    n = 3_000_017
+    feat = np.zeros((n, 8), dtype=np.float32)
+    feat[:, 7] = rng.uniform(0.0, 65.0, size=n).astype(np.float32)
+    feat[::11, 7] = np.floor(feat[::11, 7])
+    cost, total = mc.chain_cost(torch.from_numpy(feat).cuda())
+    ref = O.chain_cost(feat[:, 7])
+    assert np.array_equal(cost.cpu().numpy().astype(np.int64), ref) and total == int(ref.sum())
+    empty, tot0 = mc.chain_cost(torch.zeros((0, 8), dtype=torch.float32, device="cuda"))
+    assert empty.numel() == 0 and tot0 == 0
+
+
 # ---------------------------------------------------------------- MLP (a13)
 def flat(p):
     return np.concatenate([p[k].reshape(-1) for k, _ in O.MLP_SHAPES]).astype(np.float32)
@@ -137,6 +196,51 @@ def test_mlp_training_reduces_loss_and_checkpoints(mc):
     y1 = net.predict(xd).cpu().numpy()
     y2 = net2.predict(xd).cpu().numpy()
     assert np.array_equal(y1, y2)
+
+
+def test_adam_steps_match_oracle(mc):
+    """25 Adam steps of k_adam (FP32 moments and master weights) against the
+    oracle's FP64 Adam on the same gradients (some entries zero at some steps,
+    scales from 1e-3 to 10). Tolerance from FP32 arithmetic, per step t: the
+    stored weight is rounded (2^-24 |p_t|) and the update u_t carries the
+    binary32 rounding of beta2 (|fl(0.999) - 0.999| / (1 - 0.999) = 1.3e-5
+    relative in 1 - beta2 and in the bias correction) plus about ten binary32
+    operations, 3e-5 |u_t| in all; summed over the steps."""
+    rng = np.random.default_rng(21)
+    p0 = O.mlp_init(4)
+    for k in ("b1", "b2", "b3"):
+        p0[k] = rng.normal(0, 0.2, size=p0[k].shape).astype(np.float32)
+    net = mc.Mlp()
+    net.set_params(flat(p0))
+    lr = 3e-3
+    ref = {k: v.astype(np.float64) for k, v in p0.items()}
+    state = {}
+    tol = np.zeros(flat(p0).size)
+    for t in range(25):
+        scale = 10.0 ** rng.uniform(-3, 1, size=flat(p0).size)
+        g = (rng.normal(0, 1, size=scale.size) * scale).astype(np.float32)
+        g[rng.random(g.size) < 0.05] = 0.0
+        net.adam_step(torch.from_numpy(g).cuda(), lr)
+        new = O.adam_step(ref, {k: v.astype(np.float64) for k, v in unflat(g).items()}, state, lr=lr)
+        u = np.abs(flat({k: new[k] - ref[k] for k in ref}).astype(np.float64))
+        ref = new
+        tol += 2.0 ** -24 * np.abs(flat(ref).astype(np.float64)) + 3e-5 * u
+    ck = net.get_params()
+    got = ck["params"].astype(np.float64)
+    want = np.concatenate([ref[k].reshape(-1) for k, _ in O.MLP_SHAPES])
+    err = np.abs(got - want)
+    assert ck["step"] == 25
+    assert np.all(err <= tol + 1e-12), (err.max(), np.argmax(err - tol))
+    m_ref = np.concatenate([state["m_" + k].reshape(-1) for k, _ in O.MLP_SHAPES])
+    v_ref = np.concatenate([state["v_" + k].reshape(-1) for k, _ in O.MLP_SHAPES])
+    assert np.allclose(ck["adam_m"], m_ref, rtol=1e-5, atol=1e-12)
+    assert np.allclose(ck["adam_v"], v_ref, rtol=3e-5, atol=1e-20)
+    # the BF16 copies follow the masters: the network's prediction equals one made
+    # from a fresh network loaded with the same masters
+    x = torch.from_numpy(rng.normal(0, 1, size=(300, 8)).astype(np.float32)).cuda()
+    net2 = mc.Mlp()
+    net2.set_params(ck["params"])
+    assert np.array_equal(net.predict(x).cpu().numpy(), net2.predict(x).cpu().numpy())
 
 
 @pytest.mark.parametrize("n", [1, 5000, 400000])

@@ -2,7 +2,10 @@
 pins catch every one: a dropped term, a wrong sign or index, a transposed
 scaling, a non-strict cutoff, a wrong quantization, a wrong Philox constant,
 a pre-pass that ignores the diagonal's sign, uses another norm or cuts at the
-wrong rank, a top-k selection that keeps the wrong number or the wrong end."""
+wrong rank, a top-k selection that keeps the wrong number or the wrong end, row
+features with the wrong weighting, an allocation that truncates, a Neyman
+target without its square root, an Adam step without bias correction.
+Mutations name the file of the oracle they change (mcmi_oracle.c by default)."""
 import os
 import shutil
 import subprocess
@@ -32,6 +35,22 @@ MUTATIONS = {
     "drop_keeps_ties_out": ("if (fabs(c) < thr) {", "if (fabs(c) <= thr && thr > 0.0) {"),
     "topk_ignores_diagonal_slot": ("int64_t want = (int64_t)p->topk - 1;", "int64_t want = (int64_t)p->topk;"),
     "topk_keeps_smallest": ("return x->test > y->test ? -1 : 1;", "return x->test < y->test ? -1 : 1;"),
+    "features_uniform_weights": ("double pk = (double)w / (double)A->wsum[i];", "double pk = 1.0 / (double)m;"),
+    "features_sign_balance_of_magnitudes": ("csum += A->cval[k] < 0.0 ? -chat : chat;", "csum += chat;"),
+    "features_max_of_weights": ("if (chat > cmax)\n                cmax = chat;",
+                                "if (pk > cmax)\n                cmax = pk;"),
+    "alloc_truncates": ("ref.py", "n_r = np.maximum(1, np.rint(lam * e)).astype(np.int64)",
+                        "n_r = np.maximum(1, np.floor(lam * e)).astype(np.int64)"),
+    "neyman_without_sqrt": ("ref.py", "return 0.5 * (np.log(v) - np.log(np.asarray(mean_len, dtype=np.float64) + 1.0))",
+                            "return np.log(v) - np.log(np.asarray(mean_len, dtype=np.float64) + 1.0)"),
+    "neyman_cost_without_start": ("ref.py",
+                                  "return 0.5 * (np.log(v) - np.log(np.asarray(mean_len, dtype=np.float64) + 1.0))",
+                                  "return 0.5 * (np.log(v) - np.log(np.asarray(mean_len, dtype=np.float64) + 1e-300))"),
+    "chain_cost_ceiling": ("ref.py", "return (1 + np.floor(np.maximum(f, 0.0))).astype(np.int64)",
+                           "return (1 + np.ceil(np.maximum(f, 0.0))).astype(np.int64)"),
+    "adam_no_bias_correction": ("ref.py", "mh = m / (1 - beta1 ** t)", "mh = m"),
+    "adam_second_moment_of_abs": ("ref.py", "v[...] = beta2 * v + (1 - beta2) * g[name] * g[name]",
+                                  "v[...] = beta2 * v + (1 - beta2) * np.abs(g[name])"),
 }
 
 DRIVER = textwrap.dedent('''
@@ -59,6 +78,12 @@ DRIVER = textwrap.dedent('''
         ("reduce", lambda: pins.test_reduction_drops_the_smallest_share_of_the_iteration_matrix()),
         ("compose", lambda: pins.test_augmentation_then_reduction_compose()),
         ("topk", lambda: pins.test_topk_keeps_the_largest_entries_of_the_eps_set()),
+        ("features", lambda: pins.test_features_of_a_hand_built_matrix()),
+        ("alloc_unit", lambda: pins.test_allocation_lambda_by_hand("unit_cost")),
+        ("alloc_floor", lambda: pins.test_allocation_lambda_by_hand("floor_of_one")),
+        ("neyman", lambda: pins.test_neyman_target_gives_the_brute_force_optimum()),
+        ("adam", lambda: pins.test_adam_two_steps_by_hand()),
+        ("cost", lambda: pins.test_chain_cost_counts_the_states_of_every_chain("uniform_0.7")),
     ]
     hipcc = shutil.which("hipcc") or "/opt/rocm/bin/hipcc"
     if os.path.exists(hipcc):
@@ -81,12 +106,13 @@ DRIVER = textwrap.dedent('''
 @pytest.mark.slow
 @pytest.mark.parametrize("name", sorted(MUTATIONS))
 def test_planted_mistake_is_caught(name, tmp_path):
-    old, new = MUTATIONS[name]
+    mut = MUTATIONS[name]
+    fname, old, new = mut if len(mut) == 3 else ("mcmi_oracle.c",) + mut
     dst = tmp_path / "oracle"
     shutil.copytree(os.path.join(ROOT, "oracle"), dst, ignore=shutil.ignore_patterns("*.so", "__pycache__"))
-    src = (dst / "mcmi_oracle.c").read_text()
+    src = (dst / fname).read_text()
     assert src.count(old) >= 1, "mutation anchor not found"
-    (dst / "mcmi_oracle.c").write_text(src.replace(old, new, 1))
+    (dst / fname).write_text(src.replace(old, new, 1))
     drv = tmp_path / "drive.py"
     drv.write_text(DRIVER)
     out = subprocess.run([sys.executable, str(drv), str(tmp_path), ROOT], capture_output=True, text=True,

@@ -112,6 +112,29 @@ def test_p4_uniform_row_sum_matrix_exact_transitions():
         assert np.all(r["row_transitions"] == 32 * 25)
 
 
+@pytest.mark.parametrize("case", ["uniform_0.7", "torus_0.8", "dyadic_0.5"])
+def test_chain_cost_counts_the_states_of_every_chain(case):
+    """With equal |C| row sums S every chain makes exactly floor(ln delta / ln S)
+    transitions, so the chain cost 1 + floor(f7) is the number of states each
+    chain visits: sum over a row's chains of the cost = its transitions + chains.
+    Cases: the random family (S = 0.7, delta = 1e-4: 25 transitions), the periodic
+    torus (S = 0.8, delta = 1e-3: 30) and dyadic rows with S = 1/2 at delta = 1/8,
+    where the weight 1/8 equals delta and the cutoff is strict (3 transitions)."""
+    if case == "uniform_0.7":
+        B, delta, steps = I.random_nonsym(2048, seed=5), 1e-4, 25
+    elif case == "torus_0.8":
+        B, delta, steps = I.grid2d_5pt(8, 8, 5.0, -1.0, periodic=True), 1e-3, 30
+    else:
+        C = np.array([[0, 0.25, 0.25], [0.5, 0, 0], [0.25, 0.25, 0]])
+        B, delta, steps = I.from_dense(np.array([2.0, -1.0, 4.0])[:, None] * (np.eye(3) - C)), 0.125, 3
+    o = O.Oracle(B)
+    cost = O.chain_cost(o.features(delta)[:, 7])
+    assert np.all(cost == steps + 1)
+    rows = np.arange(min(B.n, 200))
+    r = o.spai(seed=4, chains=8, delta=delta, eps=1e-3, rows=rows)
+    assert np.array_equal(cost[rows] * 8, r["row_transitions"] + 8)
+
+
 # ------------------------------------------------- P5: CLT vs the inverse
 @pytest.mark.parametrize("seed", [1, 2])
 def test_p5_converges_to_numpy_inverse(seed):
@@ -392,6 +415,125 @@ def test_neyman_allocation_budget():
     n_r, lam = O.allocate(pred, cost, 3 * 150)
     assert (n_r * cost).sum() <= 450 and n_r.min() >= 1
     assert np.all(np.diff(n_r) >= 0)
+
+
+@pytest.mark.parametrize("case", ["unit_cost", "floor_of_one"])
+def test_allocation_lambda_by_hand(case):
+    """N_r = max(1, rint(lambda e^y_r)) with lambda the largest value whose total
+    sum_r N_r cost_r stays within the budget (rint: nearest, ties to even).
+    unit_cost: e^y = (1, 2, 4), cost 1, budget 14. N(2) = (2, 4, 8) costs 14; the
+    first jump above 2 is rint(4 lambda) at 4 lambda > 8.5 (8.5 itself rounds to
+    8), so lambda = 17/8 and N = (2, 4, 8).
+    floor_of_one: e^y = (1/100, 1, 1), cost (1, 2, 3), budget 21. The first row
+    stays at its floor of one chain; 1 + 5 rint(lambda) <= 21 holds up to
+    lambda = 9/2 (4.5 rounds to 4), so N = (1, 4, 4)."""
+    if case == "unit_cost":
+        pred, cost, budget, lam_ref, n_ref = np.log([1.0, 2.0, 4.0]), [1, 1, 1], 14, 2.125, [2, 4, 8]
+    else:
+        pred, cost, budget, lam_ref, n_ref = np.log([0.01, 1.0, 1.0]), [1, 2, 3], 21, 4.5, [1, 4, 4]
+    n_r, lam = O.allocate(pred, np.array(cost), budget)
+    assert list(n_r) == n_ref
+    assert abs(lam - lam_ref) <= 1e-12 * lam_ref, lam
+
+
+def test_neyman_target_gives_the_brute_force_optimum():
+    """Neyman allocation: with per-chain variance v_r and cost c_r = len_r + 1 per
+    chain, minimising sum_r v_r / N_r under sum_r N_r c_r <= T gives N_r
+    proportional to sqrt(v_r / c_r), i.e. to exp of the target
+    (ln v_r - ln(len_r + 1)) / 2. Here v = (1, 8, 64), len = (0, 1, 3), T = 42: the
+    continuous optimum is N = (2, 4, 8) (objective (sum sqrt(v c))^2 / T = 10.5);
+    the integer optimum found by enumerating every allocation must equal the
+    allocation the target produces."""
+    v = np.array([1.0, 8.0, 64.0])
+    ln = np.array([0.0, 1.0, 3.0])
+    cost = (ln + 1).astype(np.int64)
+    T = 42
+    best, arg = math.inf, None
+    for n0 in range(1, T + 1):
+        for n1 in range(1, T + 1):
+            rest = T - n0 * cost[0] - n1 * cost[1]
+            if rest < cost[2]:
+                continue
+            n2 = rest // cost[2]
+            obj = v[0] / n0 + v[1] / n1 + v[2] / n2
+            if obj < best - 1e-12:
+                best, arg = obj, (n0, n1, n2)
+    assert arg == (2, 4, 8) and abs(best - 10.5) < 1e-12
+    y = O.neyman_target(v, ln)
+    assert np.allclose(np.exp(y), [1.0, 2.0, 4.0], rtol=1e-14)
+    n_r, _ = O.allocate(y, cost, T)
+    assert tuple(int(x) for x in n_r) == arg
+
+
+def test_adam_two_steps_by_hand():
+    """Adam (Kingma and Ba, Algorithm 1; beta1 = 0.9, beta2 = 0.999): with bias
+    correction the first step moves every parameter by lr g / (|g| + eps).
+    Per column of the test, the gradients of steps 1 and 2 and the closed form:
+      (g, g):   m^ = g, v^ = g^2 at both steps: p - 2 lr g / (|g| + eps)
+      (1, -1):  step 2 has m^ = (0.09 - 0.1) / 0.19 = -1/19 and
+                v^ = (0.999e-3 + 1e-3) / (1 - 0.999^2) = 1
+      (0, 3):   step 1 moves nothing; step 2 has m^ = 0.3 / 0.19 = 30/19 and
+                v^ = 9e-3 / 1.999e-3 = 9000/1999."""
+    lr, eps = 1e-3, 1e-8
+    g1 = {k: np.zeros(shape) for k, shape in O.MLP_SHAPES}
+    g2 = {k: np.zeros(shape) for k, shape in O.MLP_SHAPES}
+    p0 = {k: np.full(shape, 0.5, dtype=np.float32) for k, shape in O.MLP_SHAPES}
+    g1["w1"][:] = 2.5
+    g2["w1"][:] = 2.5
+    g1["b1"][:] = 1.0
+    g2["b1"][:] = -1.0
+    g1["w2"][:] = 0.0
+    g2["w2"][:] = 3.0
+    g1["b3"][:] = -0.25
+    g2["b3"][:] = -0.25
+    st = {}
+    p1 = O.adam_step(p0, g1, st, lr=lr)
+    p2 = O.adam_step({k: v.astype(np.float32) for k, v in p1.items()}, g2, st, lr=lr)
+    assert np.allclose(p1["w1"], 0.5 - lr * 2.5 / (2.5 + eps), rtol=0, atol=1e-12)
+    assert np.allclose(p2["w1"], 0.5 - 2 * lr * 2.5 / (2.5 + eps), rtol=0, atol=1e-7)
+    assert np.allclose(p1["b1"], 0.5 - lr / (1 + eps), rtol=0, atol=1e-12)
+    p1b1 = np.float64(np.float32(0.5 - lr / (1 + eps)))
+    assert np.allclose(p2["b1"], p1b1 + lr * (1 / 19) / (1 + eps), rtol=0, atol=1e-12)
+    assert np.array_equal(p1["w2"], np.full((64, 64), 0.5))
+    step = (30 / 19) / (math.sqrt(9000 / 1999) + eps)
+    assert np.allclose(p2["w2"], 0.5 - lr * step, rtol=0, atol=1e-12)
+    assert np.allclose(p2["b3"], 0.5 + 2 * lr * 0.25 / (0.25 + eps), rtol=0, atol=1e-7)
+    assert np.array_equal(p2["w3"], np.full(64, 0.5))
+
+
+def test_features_of_a_hand_built_matrix():
+    """Row features of a 5-row matrix whose iteration matrix has dyadic entries, so
+    the quantized Chat equals C and every feature has a closed form (p = |c| / S):
+      row 0: c = (+1/4, -1/8, +1/8) at columns 1, 2, 3   S = 1/2, p = (1/2, 1/4, 1/4)
+      row 1: c = -3/8 at column 2                        S = 3/8
+      row 2: c = (1/16, 1/16) at columns 0, 1            S = 1/8
+      row 3: c = (-1/2, -1/4, +1/8) at columns 0, 1, 2   S = 7/8, p = (4/7, 2/7, 1/7)
+      row 4: empty (B's row holds only its diagonal)
+    and, for instance, f3 of row 0 = 1/2 * 3/8 + 1/4 * 1/8 + 1/4 * 7/8 = 7/16,
+    f6 of row 3 = |-1/2 - 1/4 + 1/8| / (7/8) = 5/7. L_max = 52, the smallest L with
+    (7/8)^L < 10^-3."""
+    C = np.zeros((5, 5))
+    C[0, 1:4] = [0.25, -0.125, 0.125]
+    C[1, 2] = -0.375
+    C[2, 0:2] = [0.0625, 0.0625]
+    C[3, 0:3] = [-0.5, -0.25, 0.125]
+    d = np.array([2.0, 4.0, 1.0, 8.0, 3.0])
+    B = I.from_dense(d[:, None] * (np.eye(5) - C))
+    delta = 1e-3
+    lmax = next(L for L in range(1, 200) if Fraction(7, 8) ** L < Fraction(1, 1000))
+    assert lmax == 52
+    ld = math.log(delta)
+    ref = np.array([
+        [math.log(3), 1 / 2, 1 / 4, 7 / 16, 7 / 8, 7 / 4, 1 / 2, ld / math.log(1 / 2)],
+        [0.0, 3 / 8, 3 / 8, 1 / 8, 1 / 8, 2.0, 1.0, ld / math.log(3 / 8)],
+        [math.log(2), 1 / 8, 1 / 16, 7 / 16, 1 / 2, 2.0, 1.0, ld / math.log(1 / 8)],
+        [math.log(3), 7 / 8, 1 / 2, 23 / 56, 1 / 2, 16 / 7, 5 / 7, ld / math.log(7 / 8)],
+        [0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0],
+    ])
+    f = O.Oracle(B).features(delta)
+    assert np.allclose(f, ref, rtol=1e-14, atol=0), np.abs(f - ref).max(axis=0)
+    f = O.Oracle(B).features(delta, max_len=8)
+    assert f[3, 7] == 8 and f[0, 7] == 8 and abs(f[1, 7] - ld / math.log(3 / 8)) < 1e-14
 
 
 # ------------------------------------------------- exact rules of the sampler
