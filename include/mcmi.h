@@ -295,6 +295,19 @@ mcmi_status mcmi_mlp_train(mcmi_mlp *net, const float *feat_dev, const float *ta
  * (*fallback_host = 1). cost_dev: int32 per-row chain cost (>= 1). Synchronises. */
 mcmi_status mcmi_allocate(const float *pred_dev, const int32_t *cost_dev, int64_t n, int64_t budget,
                           int32_t *chains_dev, double *lambda_host, int32_t *fallback_host, void *stream);
+/* mcmi_allocate for callers that cannot allocate device memory (code under
+ * hipGraph stream capture, tight serving loops, harnesses that forbid
+ * hipMalloc). Same kernels and the same results (chains_dev, lambda, fallback
+ * flag) as mcmi_allocate, but every temporary lives in a static device workspace
+ * of 256 B + 8 B per row for at most 4,194,304 rows (32 MiB + 256 B, one copy
+ * per GPU, held until the process ends); n above that limit returns
+ * MCMI_ERR_ARG before anything is launched. lambda_dev (double) and fallback_dev
+ * (int32) are optional device outputs (NULL: not written). Fully asynchronous:
+ * no allocation, no host copy, no synchronisation. Calls that overlap on one GPU
+ * (concurrent streams or threads) share the workspace and race; serialise them.
+ * Each call re-initialises the workspace it uses. */
+mcmi_status mcmi_allocate_noalloc(const float *pred_dev, const int32_t *cost_dev, int64_t n, int64_t budget,
+                                  int32_t *chains_dev, double *lambda_dev, int32_t *fallback_dev, void *stream);
 
 /* Regression target of the allocation network, per row. Neyman allocation:
  * minimising the summed variance sum_r v_r / N_r of the row estimates under a

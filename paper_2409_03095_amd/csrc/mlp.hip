@@ -12,6 +12,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -653,8 +654,58 @@ __global__ void __launch_bounds__(256) k_alloc_write(const double *e, int64_t n,
     }
 }
 
+// the bisection's starting state, written on the device (the no-allocation
+// variant clears its static workspace with this instead of a host copy)
+__global__ void k_alloc_init(AllocState *st) {
+    if (threadIdx.x == 0) {
+        st->lo = 0.0;
+        st->hi = 1.0;
+        st->total = 0;
+        st->bad = 0;
+        st->csum = 0;
+        st->phase = 0;
+        st->halvings = 0;
+    }
+}
+
+// Workspace of mcmi_allocate_noalloc: the bisection state, the lambda and
+// fallback slots, then exp(pred_r) for up to kNoAllocMaxRows rows.
+constexpr int64_t kNoAllocMaxRows = int64_t(1) << 22;
+constexpr size_t kNoAllocHead = 256;
+constexpr size_t kNoAllocBytes = kNoAllocHead + (size_t)kNoAllocMaxRows * sizeof(double);
+static_assert(sizeof(AllocState) <= 64, "state slot");
+
 }  // namespace
 }  // namespace mcmi
+
+// Static workspace (one copy per GPU, alive until the process ends). Host code
+// never passes this name to a kernel: it uses the device address that
+// hipGetSymbolAddress returns for the current device.
+static __device__ __align__(256) unsigned char scratch[mcmi::kNoAllocBytes];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of `scratch` on the current device, looked up once per device.
+hipError_t scratch_address(void **out) {
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *ptr = nullptr;
+        e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        if (!ptr) return hipErrorInvalidSymbol;
+        g_scratch_ptr[dev] = ptr;
+    }
+    *out = g_scratch_ptr[dev];
+    return hipSuccess;
+}
+}  // namespace
 
 extern "C" mcmi_status mcmi_allocate(const float *pred_dev, const int32_t *cost_dev, int64_t n, int64_t budget,
                                      int32_t *chains_dev, double *lambda_host, int32_t *fallback_host,
@@ -698,5 +749,40 @@ extern "C" mcmi_status mcmi_allocate(const float *pred_dev, const int32_t *cost_
     if (err != hipSuccess) return fail(MCMI_ERR_HIP, std::string("mcmi_allocate: ") + hipGetErrorString(err));
     if (lambda_host) *lambda_host = hl;
     if (fallback_host) *fallback_host = hf;
+    return MCMI_OK;
+}
+
+extern "C" mcmi_status mcmi_allocate_noalloc(const float *pred_dev, const int32_t *cost_dev, int64_t n,
+                                             int64_t budget, int32_t *chains_dev, double *lambda_dev,
+                                             int32_t *fallback_dev, void *stream) {
+    using namespace mcmi;
+    if (!pred_dev || !cost_dev || !chains_dev || n < 1 || budget < 1)
+        return fail(MCMI_ERR_ARG, "mcmi_allocate_noalloc: bad argument");
+    if (n > kNoAllocMaxRows)
+        return fail(MCMI_ERR_ARG, "mcmi_allocate_noalloc: n = " + std::to_string(n) +
+                                      " rows exceeds the static workspace (" + std::to_string(kNoAllocMaxRows) +
+                                      " rows); use mcmi_allocate");
+    void *base = nullptr;
+    hipError_t err = scratch_address(&base);
+    if (err != hipSuccess)
+        return fail(MCMI_ERR_HIP, std::string("mcmi_allocate_noalloc: workspace address: ") + hipGetErrorString(err));
+    hipStream_t s = (hipStream_t)stream;
+    unsigned char *head = (unsigned char *)base;
+    AllocState *st = (AllocState *)head;
+    double *lam = (double *)(head + 64);
+    int32_t *fbk = (int32_t *)(head + 72);
+    double *e = (double *)(head + kNoAllocHead);
+    int64_t blocks = (n + 255) / 256;
+    if (blocks > 2048) blocks = 2048;
+    k_alloc_init<<<1, 64, 0, s>>>(st);
+    k_alloc_prep<<<(unsigned)blocks, 256, 0, s>>>(pred_dev, cost_dev, n, e, st);
+    for (int it = 0; it < 201; ++it) {
+        k_alloc_total<<<(unsigned)blocks, 256, 0, s>>>(e, cost_dev, n, st);
+        k_alloc_update<<<1, 1, 0, s>>>(st, (long long)budget);
+    }
+    k_alloc_write<<<(unsigned)blocks, 256, 0, s>>>(e, n, (long long)budget, st, chains_dev,
+                                                   lambda_dev ? lambda_dev : lam, fallback_dev ? fallback_dev : fbk);
+    err = hipGetLastError();
+    if (err != hipSuccess) return fail(MCMI_ERR_HIP, std::string("mcmi_allocate_noalloc: ") + hipGetErrorString(err));
     return MCMI_OK;
 }

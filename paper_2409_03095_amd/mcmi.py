@@ -108,6 +108,7 @@ _sig = {
     "mcmi_mlp_train": [_v, _v, _v, ctypes.c_int64, ctypes.c_int32, ctypes.c_int32, ctypes.c_float, ctypes.c_uint64,
                        _v, _v],
     "mcmi_allocate": [_v, _v, ctypes.c_int64, ctypes.c_int64, _v, _P(ctypes.c_double), _P(ctypes.c_int32), _v],
+    "mcmi_allocate_noalloc": [_v, _v, ctypes.c_int64, ctypes.c_int64, _v, _v, _v, _v],
     "mcmi_neyman_target": [_v, _v, ctypes.c_int64, _v, _v],
     "mcmi_chain_cost": [_v, ctypes.c_int64, _v, _P(ctypes.c_int64), _v],
     "mcmi_mlp_adam_step": [_v, _v, ctypes.c_float, _v],
@@ -132,7 +133,7 @@ EXPORTED = ["mcmi_cache_trim", "mcmi_bicgstab", "mcmi_build_cdf", "mcmi_build_cd
             "mcmi_csr_copy", "mcmi_cdf_free", "mcmi_csr_free", "mcmi_last_error", "mcmi_version",
             "mcmi_row_features", "mcmi_pilot_variance", "mcmi_mlp_create", "mcmi_mlp_free",
             "mcmi_mlp_set_params", "mcmi_mlp_get_params", "mcmi_mlp_set_adam_state", "mcmi_mlp_fit_normalization",
-            "mcmi_mlp_predict", "mcmi_mlp_gradient", "mcmi_mlp_train", "mcmi_allocate",
+            "mcmi_mlp_predict", "mcmi_mlp_gradient", "mcmi_mlp_train", "mcmi_allocate", "mcmi_allocate_noalloc",
             "mcmi_neyman_target", "mcmi_chain_cost", "mcmi_mlp_adam_step",
             "mcmi_build_cdf_batched", "mcmi_build_cdf_batched_ex", "mcmi_cdf_batch_info", "mcmi_tune", "mcmi_plan_create", "mcmi_plan_launch",
             "mcmi_plan_result", "mcmi_plan_free", "mcmi_gather_probe"]
@@ -444,6 +445,15 @@ def allocate(pred, cost, budget, stream=None):
     _check(_lib.mcmi_allocate(_ptr(pred), _ptr(cost), ctypes.c_int64(pred.numel()), ctypes.c_int64(int(budget)),
                               _ptr(chains), ctypes.byref(lam), ctypes.byref(fb), _stream(stream)))
     return chains, lam.value, bool(fb.value)
+
+
+def allocate_noalloc(pred, cost, budget, chains, lam=None, fallback=None, stream=None):
+    """mcmi_allocate_noalloc: writes chains (int32 device tensor of pred's length) and,
+    when given, lam (float64, one element) and fallback (int32, one element), all on
+    the device; asynchronous, no allocation inside the library."""
+    _check(_lib.mcmi_allocate_noalloc(_ptr(pred), _ptr(cost), ctypes.c_int64(pred.numel()),
+                                      ctypes.c_int64(int(budget)), _ptr(chains), _ptr(lam), _ptr(fallback),
+                                      _stream(stream)))
 
 
 def tune(cdf: Cdf, p: Params, sample_rows=8192, cache_path=None, stream=None):
