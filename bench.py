@@ -1,21 +1,26 @@
 """Benchmark: Monte Carlo SPAI throughput (transitions/s) on one MI355X.
 
-Workload (default): random nonsymmetric B, n = 262144, 5..30 off-diagonals per
-row at uniform columns, log-normal magnitudes with random signs, per-row
-diagonal so that every row of C = I - D^-1 B has |C| row sum 0.7; 512 chains
-per row, FP32 walk weights with FP64 sums, delta = 1e-4, eps = 1e-3, Philox
-seed 0. Every chain makes exactly 25 transitions, so one step is exactly
-262144 * 512 * 25 = 3,355,443,200 transitions.
+Workload (default): 3D 27-point anisotropic diffusion on a 160^3 grid
+(n = 4,096,000, Q1 tensor stencil with conductivities 1:10:100, +-10 %
+multiplicative noise on the off-diagonals, uniform diagonal so that
+||C||_inf = 0.75); 64 chains per row, FP32 walk weights with FP64 sums,
+delta = 1e-4, eps = 1e-3, Philox seed 0; rows walked cell by cell (cells of
+4096 rows grown on B's pattern).
 
 One step = the whole hot path over the matrix, through the C ABI:
-mcmi_build_cdf (records) + mcmi_spai (walks, accumulation, filter, scaling,
-CSR assembly) + mcmi_apply (one y = M x). Inputs are resident in HBM before the
-timed region starts.
+mcmi_build_cdf (records and the row schedule) + mcmi_spai (walks,
+accumulation, filter, scaling, CSR assembly) + mcmi_apply (one y = M x).
+Inputs are resident in HBM before the timed region starts.
 
-Prints one JSON line with, beside the throughput, the roofline of the walk
-kernel (algorithmic bytes per transition x transitions per launch / the walk
-kernel's event-timed duration, against 8 TB/s HBM) and the CPU oracle's rate on
-a bounded row sample.
+The JSON line carries, beside the throughput:
+* roofline: the walk kernel's algorithmic bytes per transition x transitions
+  per launch / its event-timed duration, against 8 TB/s of HBM;
+* cpu_baseline: the CPU oracle (FP64) timed on a bounded uniform row sample
+  on the host's cores; in the same leg the GPU's result on those rows is
+  compared with the oracle's (precision: error against the FP64 oracle, and
+  identity with the oracle's FP32-weight mode);
+* secondary: the same figures for the random nonsymmetric n = 262144
+  workload (512 chains per row, every chain exactly 25 transitions).
 """
 from __future__ import annotations
 
@@ -33,93 +38,204 @@ sys.path.insert(0, ROOT)
 
 METRIC = "MC transitions/s; time to ‖I−MB‖_F≤0.3, learned vs uniform chains"
 HBM_PEAK_GBS = 8000.0
-# rocprofv3 FETCH_SIZE/WRITE_SIZE of the walk kernel, in bytes per launch, for
-# the default workload (None until measured for the current kernel)
-TRAFFIC_BYTES = 3.94e11  # calibrated FETCH_SIZE + WRITE_SIZE of one walk launch (rocprofv3 --pmc)
-# the same for the 160^3 27-point workload's wavefront walk (cells of 4096 rows, FP32)
-TRAFFIC_BYTES_ANISO27 = 5.50e11
-# and for the batched launch of the 256 convection-diffusion matrices (128 chains, FP32)
-TRAFFIC_BYTES_BATCHED = 9.93e11
+# HBM bytes per walk launch from rocprofv3 DRAM request counters, keyed by the
+# workload and kernel configuration they were measured on; None where no
+# measurement of the current kernel exists
+TRAFFIC_BYTES = {"aniso27": None, "random": None, "batched": None}
+# what a draw of the implemented sampler must read per transition: the alias
+# bucket's threshold and two targets (12 B) and the next state's header (row,
+# m, W, Shat32: 16 B), plus Shat64 (8 B) with FP64 weights
+IMPLEMENTED_DRAW_BYTES = {32: 28.0, 64: 36.0}
 
 
 def algorithmic_bytes_per_transition(B, fp32: bool) -> float:
-    """Bytes one transition must read, independent of the record layout: the
-    state's header (row, m, W, Shat32: 16 B; +8 B Shat64 in FP64 mode), the CDF
-    words a binary search inspects ((ceil(log2 m) + 1) x 4 B) and the chosen
-    target (4 B). For this workload the next state is a uniformly random column,
-    so the mean is taken over rows uniformly."""
+    """Bytes one transition must read by the scope table's definition, which is
+    independent of the record layout: the state's header (row, m, W, Shat32:
+    16 B; +8 B Shat64 in FP64 mode), the CDF words a binary search inspects
+    ((ceil(log2 m) + 1) x 4 B) and the chosen target (4 B), averaged over the
+    rows uniformly."""
     m = np.maximum(np.diff(B.row_ptr) - 1, 1)
     probes = np.ceil(np.log2(m)) + 1.0
     return float(np.mean((16.0 if fp32 else 24.0) + 4.0 * probes + 4.0))
 
 
-def cpu_baseline(B, chains, delta, eps, fp32, budget_s=20.0):
-    """The oracle as it is, on the host cores, on a bounded sample of rows."""
+def roofline_of(bpt, transitions, walk_s, prec, traffic, kernel):
+    achieved = bpt * transitions / walk_s / 1e9
+    impl = IMPLEMENTED_DRAW_BYTES[prec] * transitions / walk_s / 1e9
+    return {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic, "kernel": kernel,
+            "bytes_per_transition": round(bpt, 2),
+            "bytes_basis": "header 16 B + (ceil(log2 m)+1) x 4 B CDF probes + 4 B target"
+                           + ("" if prec == 32 else " + 8 B Shat64"),
+            "implemented_draw": {"bytes_per_transition": IMPLEMENTED_DRAW_BYTES[prec], "achieved": round(impl, 1),
+                                 "frac": round(impl / HBM_PEAK_GBS, 4)},
+            "walk_ms": round(walk_s * 1e3, 3), "walk_transitions_per_s": transitions / walk_s}
+
+
+def gather_probe(units, reqs_per_step=1, steps=256, waves_per_cu=16, loads_per_req=1):
+    """Dependent random-gather ceiling (benchmark tooling, libmcmi_probe.so):
+    (kernel ms, steps per second) of a chase over `units` random 64-byte units."""
+    import ctypes
+    lib = ctypes.CDLL(os.path.join(ROOT, "paper_2409_03095_amd", "bench_probe", "libmcmi_probe.so"))
+    f = lib.probe_gather_chase
+    f.restype = ctypes.c_int
+    f.argtypes = [ctypes.c_uint64, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+                  ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]
+    ms, rate = ctypes.c_double(0.0), ctypes.c_double(0.0)
+    st = f(units, reqs_per_step, loads_per_req, steps, waves_per_cu, ctypes.byref(ms), ctypes.byref(rate))
+    if st != 0:
+        raise RuntimeError(f"probe_gather_chase failed with status {st}")
+    return ms.value, rate.value
+
+
+def gpu_rows(res, rows):
+    """The CSR rows `rows` (sorted) of a device result, on the host."""
+    import torch
+    rp_t, col_t, val_t = res.to_torch()
+    torch.cuda.synchronize()
+    rp = rp_t.cpu().numpy()
+    lens = rp[rows + 1] - rp[rows]
+    starts = rp[rows]
+    sub_rp = np.concatenate([[0], np.cumsum(lens)])
+    pos = np.repeat(starts - sub_rp[:-1], lens) + np.arange(sub_rp[-1])
+    idx = torch.from_numpy(pos).cuda()
+    return sub_rp, col_t[idx].cpu().numpy(), val_t[idx].cpu().numpy()
+
+
+def compare_rows(n, a, b):
+    """Pattern differences and relative value differences on the common
+    pattern of two CSR row sets over the same rows."""
+    (rpa, ca, va), (rpb, cb, vb) = a, b
+    ka = np.repeat(np.arange(rpa.size - 1, dtype=np.int64), np.diff(rpa)) * n + ca
+    kb = np.repeat(np.arange(rpb.size - 1, dtype=np.int64), np.diff(rpb)) * n + cb
+    common, ia, ib = np.intersect1d(ka, kb, assume_unique=True, return_indices=True)
+    rel = np.abs(va[ia] - vb[ib]) / np.abs(vb[ib])
+    return {"entries_gpu": int(ka.size), "entries_oracle": int(kb.size),
+            "pattern_differences": int(ka.size + kb.size - 2 * common.size),
+            "max_rel_err": float(rel.max()) if rel.size else 0.0,
+            "median_rel_err": float(np.median(rel)) if rel.size else 0.0,
+            "entries_beyond_1e-5_rel": int(np.sum(rel > 1e-5))}, (ka, kb, ia, ib)
+
+
+def fp32_weight_bound(n, g, r64, keys, o, rows, chains, eps, delta, rerun):
+    """FP32 walks follow the FP64 walks' paths: a step-j weight differs by at most
+    2 j u32 |W_j| (j binary32 products with Shat rounded to binary32), and a chain
+    whose cutoff test falls inside that band (the oracle counts them per row, D_r)
+    may add or miss one contribution of magnitude at most delta. So a value may
+    differ from the FP64 oracle's by B32 = ((2 L u32 (1 + 2^-10) + 4 (k + 2) u64)
+    sum|W| + D_r delta (1 + 2^-10)) / (N |d_c|). Returns the largest error /
+    max(1e-5 |v64|, B32) over the common entries (<= 1: within the bound) and, for
+    entries kept by one side only, the largest distance of |N64| from eps in units
+    of that band (<= 1: a kept/dropped decision made by rounding), read from the
+    oracle's eps = 0 run of those rows."""
+    u32, u64 = 2.0 ** -24, 2.0 ** -53
+    ka, kb, ia, ib = keys
+    L = int(r64["lmax"])
+    wb = 2.0 * L * u32 * (1.0 + 2.0 ** -10)
+    D = r64["row_border"].astype(np.float64)
+    loc = kb[ib] // n
+    dc = np.abs(o.diag[r64["col"][ib]])
+    b32 = ((wb + 4.0 * (r64["cnt"][ib] + 2.0) * u64) * r64["abssum"][ib] + D[loc] * delta * (1.0 + 2.0 ** -10)) \
+        / chains / dc
+    v64 = r64["val"][ib]
+    ratio = np.abs(g[2][ia] - v64) / np.maximum(1e-5 * np.abs(v64), b32)
+    out = {"max_err_over_bound": float(ratio.max()) if ratio.size else 0.0, "chains_near_cutoff": int(D.sum())}
+    only = np.setxor1d(ka, kb, assume_unique=True)
+    if only.size:
+        local = np.unique(only // n)
+        full = rerun(rows[local])
+        kf = np.repeat(np.arange(local.size, dtype=np.int64), np.diff(full["row_ptr"])) * n + full["col"]
+        want = np.searchsorted(local, only // n) * n + only % n
+        pos = np.minimum(np.searchsorted(kf, want), kf.size - 1)
+        found = kf[pos] == want
+        nh = np.where(found, np.abs(full["val"][pos] * o.diag[only % n]), 0.0)
+        ab = np.where(found, full["abssum"][pos], 0.0)
+        k = np.where(found, full["cnt"][pos], 0.0)
+        band = ((wb + 4.0 * (k + 2.0) * u64) * ab + D[only // n] * delta * (1.0 + 2.0 ** -10)) / chains \
+            + 4.0 * u64 * eps
+        out["pattern_difference_max_distance_over_band"] = float((np.abs(nh - eps) / band).max())
+    return out
+
+
+def cpu_baseline(B, chains, delta, eps, res, gpu_prec, budget_s=20.0, check_rows=4096):
+    """The oracle as it is (FP64 walks, long-double sums), on the host's cores,
+    on a bounded uniform sample of rows; one thread on the first rows of that
+    sample. The same leg then compares the GPU's result `res` on the sampled
+    rows with the oracle's (error against the FP64 oracle) and, for FP32 walks,
+    with the oracle's FP32-weight mode on the first `check_rows` of them (same
+    pattern, same values up to summation order)."""
     import oracle as O
     threads = O.default_threads()
     o = O.Oracle(B)
     rng = np.random.default_rng(123)
-    probe = rng.choice(B.n, 256, replace=False).astype(np.int32)
+    probe = np.sort(rng.choice(B.n, 256, replace=False)).astype(np.int32)
     t0 = time.perf_counter()
-    r = o.spai(seed=0, chains=chains, delta=delta, eps=eps, fp32=fp32, rows=probe, threads=threads)
+    r = o.spai(seed=0, chains=chains, delta=delta, eps=eps, rows=probe, threads=threads)
     dt = time.perf_counter() - t0
     rate = r["transitions"] / max(dt, 1e-9)
-    nrows = int(min(B.n, max(256, rate * budget_s / max(r["transitions"] / 256, 1))))
-    rows = rng.choice(B.n, nrows, replace=False).astype(np.int32)
+    nrows = int(min(B.n, max(check_rows, rate * budget_s / max(r["transitions"] / 256, 1))))
+    rows = np.sort(rng.choice(B.n, nrows, replace=False)).astype(np.int32)
     t0 = time.perf_counter()
-    r = o.spai(seed=0, chains=chains, delta=delta, eps=eps, fp32=fp32, rows=rows, threads=threads)
+    r = o.spai(seed=0, chains=chains, delta=delta, eps=eps, rows=rows, threads=threads)
     dt = time.perf_counter() - t0
-    # one thread on a sample of about a fifth of the all-core run's time
     n1 = int(min(nrows, max(64, nrows * 0.2 / max(threads, 1))))
     t1 = time.perf_counter()
-    r1 = o.spai(seed=0, chains=chains, delta=delta, eps=eps, fp32=fp32, rows=rows[:n1], threads=1)
+    r1 = o.spai(seed=0, chains=chains, delta=delta, eps=eps, rows=rows[:n1], threads=1)
     dt1 = time.perf_counter() - t1
-    return {"value": r["transitions"] / dt, "unit": "transitions/s", "cores": threads, "kind": "oracle",
-            "sample": f"{nrows} uniformly sampled rows of the same matrix ({r['transitions']} transitions, "
-                      f"{dt:.1f} s, {threads} threads)",
+    base = {"value": r["transitions"] / dt, "unit": "transitions/s", "cores": threads, "kind": "oracle",
+            "sample": f"{nrows} uniformly sampled rows of the same matrix, FP64 walks ({r['transitions']} "
+                      f"transitions, {dt:.1f} s, {threads} threads)",
             "single_core_value": r1["transitions"] / dt1,
             "single_core_sample": f"the first {n1} of those rows on one thread ({r1['transitions']} transitions, "
                                   f"{dt1:.1f} s)"}
+    g = gpu_rows(res, rows)
+    cmp, keys = compare_rows(B.n, g, (r["row_ptr"], r["col"], r["val"]))
+    prec = {"vs": "FP64 oracle", "rows": nrows, "guard_band_entries": int(r["guard"]), **cmp}
+    if gpu_prec == 32:
+        prec["fp32_bound"] = fp32_weight_bound(
+            B.n, g, r, keys, o, rows, chains, eps, delta,
+            lambda rr: o.spai(seed=0, chains=chains, delta=delta, eps=0.0, rows=rr, threads=threads))
+        sub = rows[:check_rows]
+        r32 = o.spai(seed=0, chains=chains, delta=delta, eps=eps, fp32=True, rows=sub, threads=threads)
+        k = int(g[0][sub.size])
+        c, _ = compare_rows(B.n, (g[0][:sub.size + 1], g[1][:k], g[2][:k]), (r32["row_ptr"], r32["col"], r32["val"]))
+        prec["fp32_mode"] = {"rows": int(sub.size), "pattern_differences": c["pattern_differences"],
+                             "max_rel_diff": c["max_rel_err"]}
+    return base, prec
 
 
-def walk_precision(mcmi, dB, n, chains, delta, eps, seed, nrows=4096):
-    """FP32 walks against FP64 walks on the same sampled rows, after the timed
-    steps: the FP64 path is the one the parity tests hold to the FP64 oracle at
-    1e-12, so this is the FP32 path's error against FP64 arithmetic."""
+def timed_steps(step, steps, warmup):
+    """W untimed steps, then K steps between device synchronisations."""
     import torch
-    rows = np.sort(np.random.default_rng(7).choice(n, min(n, nrows), replace=False)).astype(np.int32)
-    rows_t = torch.from_numpy(rows).cuda()
-    cdf = mcmi.Cdf(dB)
-    keys, vals = {}, {}
-    for prec in (64, 32):
-        p = mcmi.params(seed=seed, chains=chains, delta=delta, eps=eps, walk_prec=prec)
-        rp, col, val = mcmi.spai(cdf, p, rows=rows_t).to_numpy()
-        keys[prec] = np.repeat(rows.astype(np.int64), np.diff(rp)) * n + col
-        vals[prec] = val
-    common, i64, i32 = np.intersect1d(keys[64], keys[32], assume_unique=True, return_indices=True)
-    v64, v32 = vals[64][i64], vals[32][i32]
-    rel = np.abs(v32 - v64) / np.abs(v64)
-    return {"rows": int(rows.size), "entries_f64": int(keys[64].size), "entries_f32": int(keys[32].size),
-            "pattern_differences": int(keys[64].size + keys[32].size - 2 * common.size),
-            "max_rel_diff_f32_vs_f64": float(rel.max()) if rel.size else 0.0,
-            "median_rel_diff_f32_vs_f64": float(np.median(rel)) if rel.size else 0.0}
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    walk_ms, trans, last = [], [], None
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        last = step()
+        walk_ms.append(last.stats.ms_walk)
+        trans.append(last.stats.transitions)
+    torch.cuda.synchronize()
+    return time.perf_counter() - t0, walk_ms, trans, last
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5)
-    ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--n", type=int, default=262144)
-    ap.add_argument("--chains", type=int, default=512)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--n", type=int, default=262144, help="rows of the random workload")
+    ap.add_argument("--chains", type=int, default=0, help="chains per row (0: the workload's default)")
     ap.add_argument("--prec", type=int, default=32, choices=[32, 64])
-    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline and the precision check")
+    ap.add_argument("--no-secondary", action="store_true", help="aniso27: skip the random-workload line")
     ap.add_argument("--hash-slots", type=int, default=0)
     ap.add_argument("--lanes", type=int, default=0)
     ap.add_argument("--sketch-slots", type=int, default=0)
     ap.add_argument("--heavy-weight", type=float, default=0.0)
-    ap.add_argument("--workload", default="random", choices=["random", "aniso27", "batched", "next"],
-                    help="random: n=262144 random nonsymmetric (default); aniso27: 160^3 27-point anisotropic; "
+    ap.add_argument("--workload", default="aniso27", choices=["random", "aniso27", "batched", "next"],
+                    help="aniso27: 160^3 27-point anisotropic (default); random: n=262144 random nonsymmetric; "
                          "batched: 256 3D 7-point convection-diffusion matrices in one launch")
     ap.add_argument("--nx", type=int, default=160, help="grid side of the aniso27 workload")
     ap.add_argument("--order-cell", type=int, default=None,
@@ -137,121 +253,86 @@ def main():
     ap.add_argument("--train-mats", type=int, default=2000)
     ap.add_argument("--heldout", type=int, default=1024, help="held-out grid side (n = side^2)")
     ap.add_argument("--train-steps", type=int, default=3000)
-    ap.add_argument("--calib-copy", action="store_true",
-                    help="first run one plain 1 GiB device copy (reference for rocprofv3 byte counters)")
+    ap.add_argument("--probe", action="store_true", help="random: also run the dependent-gather ceiling probe")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: the Monte Carlo rows would shard across GPUs without communication, "
               "but the benchmark runs and reports a single MI355X only.", file=sys.stderr)
         sys.exit(2)
 
+    if args.learned:
+        return learned_main(args)
+    if args.workload == "next":
+        return next_main(args)
+    if args.workload == "batched":
+        return batched_main(args)
+    if args.workload == "random":
+        out = random_line(args, args.steps, args.warmup, budget_s=20.0)
+        print(json.dumps(out), flush=True)
+        return
+    out = aniso_main(args)
+    if not args.no_secondary and not args.learned_alloc and not args.bicgstab:
+        sec = random_line(args, args.steps, args.warmup, budget_s=8.0)
+        out["secondary"] = {"random_nonsym_n262144": {k: sec[k] for k in (
+            "value", "unit", "ms_per_step", "dtype", "config", "roofline", "cpu_baseline", "precision") if k in sec}}
+    print(json.dumps(out), flush=True)
+
+
+def random_line(args, steps, warmup, budget_s):
+    """Random nonsymmetric n = 262144 (5..30 off-diagonals per row, ||C||_inf
+    = 0.7 in every row), 512 chains, delta = 1e-4, eps = 1e-3: every chain
+    makes exactly 25 transitions."""
     import torch
 
     from paper_2409_03095_amd import inputs as I
     from paper_2409_03095_amd import mcmi
-
-    if args.learned:
-        return learned_main(args)
-
     delta, eps, seed = 1e-4, 1e-3, 0
-    if args.workload == "next":
-        return next_main(args)
-    if args.workload == "aniso27":
-        return aniso_main(args)
-    if args.workload == "batched":
-        return batched_main(args)
+    chains = args.chains or 512
+    t0 = time.perf_counter()
     B = I.cfg2(args.n)
+    print(f"[random] generated n={B.n} nnz={B.nnz} in {time.perf_counter() - t0:.1f} s", flush=True)
     dB = mcmi.DeviceCsr.from_host(B)
     x = torch.ones(B.n, dtype=torch.float64, device="cuda")
     y = torch.empty(B.n, dtype=torch.float64, device="cuda")
-    p = mcmi.params(seed=seed, chains=args.chains, delta=delta, eps=eps, walk_prec=args.prec,
+    p = mcmi.params(seed=seed, chains=chains, delta=delta, eps=eps, walk_prec=args.prec,
                     hash_slots=args.hash_slots, lanes_per_row=args.lanes, sketch_slots=args.sketch_slots,
                     heavy_weight=args.heavy_weight)
-    torch.cuda.synchronize()
-    if args.calib_copy:
-        src = torch.ones(1 << 27, dtype=torch.float64, device="cuda")
-        dst = torch.empty_like(src)
-        dst.copy_(src)
-        torch.cuda.synchronize()
-        del src, dst
-
     cell = args.order_cell or 0
 
     def step():
         cdf = mcmi.Cdf(dB, order_cell=cell)
         res = mcmi.spai(cdf, p)
         res.apply(x, y)
-        return cdf, res
+        return res
 
-    for _ in range(args.warmup):
-        cdf, res = step()
-        del cdf, res
-    torch.cuda.synchronize()
-    walk_ms, trans = [], []
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        cdf, res = step()
-        walk_ms.append(res.stats.ms_walk)
-        trans.append(res.stats.transitions)
-        retries = res.stats.retries
-        nnz = res.nnz
-        spilled = res.stats.spilled
-        lanes, hslots, sslots = res.stats.lanes_per_row, res.stats.hash_slots, res.stats.sketch_slots
-        tau, refined = res.stats.heavy_weight, res.stats.refined
-        del cdf, res
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
-    total_trans = float(sum(trans))
-    value = total_trans / elapsed
-
-    # memory ceiling of the access pattern: a chase over a buffer of the record
-    # set's size with one dependent random 64-byte block per step (what a step of
-    # the walk reads), fresh randomness each step, read as one 16-byte load
-    # (loads=1) or as four (loads=4; a walk step issues three)
-    probe = {}
-    cdf0 = mcmi.Cdf(dB)
-    for loads in (1, 4):
-        for wpc in (8, 16, 32):
-            ms_p, rate = mcmi.gather_probe(max(1024, cdf0.rec_units), 1, 256, wpc, loads)
-            probe[f"loads{loads}_wpc{wpc}"] = rate
-    del cdf0
-    ceiling = max(v for k, v in probe.items() if k.startswith("loads1_"))
-
-    bpt = algorithmic_bytes_per_transition(B, args.prec == 32)
+    elapsed, walk_ms, trans, last = timed_steps(step, steps, warmup)
+    st = last.stats
+    print(f"[random] {steps} steps in {elapsed:.3f} s, walk {np.mean(walk_ms):.2f} ms", flush=True)
     walk_s = float(np.mean(walk_ms)) / 1e3
-    achieved = bpt * trans[-1] / walk_s / 1e9
-    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": TRAFFIC_BYTES,
-                "kernel": "k_walk_block", "bytes_per_transition": round(bpt, 2),
-                "walk_ms": round(walk_s * 1e3, 3), "walk_transitions_per_s": trans[-1] / walk_s,
-                "gather_ceiling_steps_per_s": ceiling, "gather_probe": probe,
-                "frac_of_gather_ceiling": round(trans[-1] / walk_s / ceiling, 4)}
-    precision = walk_precision(mcmi, dB, B.n, args.chains, delta, eps, seed)
-    out = {
-        "metric": METRIC,
-        "value": value,
-        "unit": "transitions/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": elapsed / args.steps * 1e3,
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "f32" if args.prec == 32 else "f64",
-        "data": "synthetic",
-        "config": {"workload": f"random nonsymmetric n={B.n}, 5-30 off-diagonals/row, ||C||_inf=0.7, "
-                               f"{args.chains} chains/row, delta=1e-4, eps=1e-3, FP{args.prec} walks + FP64 sums",
-                   "n": B.n, "nnz_B": B.nnz, "chains_per_row": args.chains, "transitions_per_step": trans[-1],
-                   "nnz_M": nnz, "spilled_contributions": spilled, "retries": retries,
-                   "lanes_per_row": lanes, "hash_slots": hslots, "sketch_slots": sslots,
-                   "heavy_weight": tau, "rows_replayed": refined, "order_cell": cell},
-        "roofline": roofline,
-        "precision": precision,
-    }
+    bpt = algorithmic_bytes_per_transition(B, args.prec == 32)
+    roofline = roofline_of(bpt, trans[-1], walk_s, args.prec, TRAFFIC_BYTES["random"], "k_walk_block")
+    if args.probe:
+        # memory ceiling of the access pattern: a chase over a buffer of the
+        # record set's size with one dependent random 64-byte block per step
+        cdf0 = mcmi.Cdf(dB)
+        probe = {f"wpc{w}": gather_probe(max(1024, cdf0.rec_units), 1, 256, w, 1)[1] for w in (8, 16, 32)}
+        roofline["gather_probe_steps_per_s"] = probe
+        del cdf0
+    out = {"metric": METRIC, "value": float(sum(trans)) / elapsed, "unit": "transitions/s", "n_gpus": 1,
+           "steps": steps, "warmup": warmup, "ms_per_step": elapsed / steps * 1e3, "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": "f32" if args.prec == 32 else "f64", "data": "synthetic",
+           "config": {"workload": f"random nonsymmetric n={B.n}, 5-30 off-diagonals/row, ||C||_inf=0.7, "
+                                  f"{chains} chains/row, delta=1e-4, eps=1e-3, FP{args.prec} walks + FP64 sums",
+                      "n": B.n, "nnz_B": B.nnz, "chains_per_row": chains, "transitions_per_step": trans[-1],
+                      "nnz_M": last.nnz, "spilled_contributions": st.spilled, "retries": st.retries,
+                      "lanes_per_row": st.lanes_per_row, "hash_slots": st.hash_slots,
+                      "sketch_slots": st.sketch_slots, "heavy_weight": st.heavy_weight,
+                      "rows_replayed": st.refined, "order_cell": cell},
+           "roofline": roofline}
     if not args.no_cpu:
-        out["cpu_baseline"] = cpu_baseline(B, args.chains, delta, eps, args.prec == 32)
-    print(json.dumps(out), flush=True)
+        out["cpu_baseline"], out["precision"] = cpu_baseline(B, chains, delta, eps, last, args.prec, budget_s)
+        print(f"[random] precision {json.dumps(out['precision'])}", flush=True)
+    return out
 
 
 def aniso_main(args):
@@ -265,8 +346,9 @@ def aniso_main(args):
     B = I.cfg5(args.nx)
     print(f"[aniso27] generated n={B.n} nnz={B.nnz} in {time.perf_counter() - t0:.1f} s", flush=True)
     dB = mcmi.DeviceCsr.from_host(B)
-    chains = args.chains if args.chains != 512 else 64
-    p = mcmi.params(seed=0, chains=chains, delta=1e-4, eps=1e-3, walk_prec=args.prec, lanes_per_row=args.lanes,
+    chains = args.chains or 64
+    delta, eps = 1e-4, 1e-3
+    p = mcmi.params(seed=0, chains=chains, delta=delta, eps=eps, walk_prec=args.prec, lanes_per_row=args.lanes,
                     hash_slots=args.hash_slots, sketch_slots=args.sketch_slots, heavy_weight=args.heavy_weight)
     x = torch.ones(B.n, dtype=torch.float64, device="cuda")
     y = torch.empty(B.n, dtype=torch.float64, device="cuda")
@@ -276,7 +358,7 @@ def aniso_main(args):
         from paper_2409_03095_amd import learned as L
         rng = np.random.default_rng(77)
         train = [I.aniso27(int(rng.integers(12, 21)), seed=1000 + k) for k in range(40)]
-        net, tinfo = L.train_allocator(train, 1e-4, steps=3000)
+        net, tinfo = L.train_allocator(train, delta, steps=3000)
         alloc = {"train": tinfo}
         print(f"[aniso27] allocation network trained: {json.dumps(tinfo)}", flush=True)
 
@@ -285,57 +367,49 @@ def aniso_main(args):
         # mean budget (chain cost 1 + floor(f7), mcmi_chain_cost), uniform fallback inside mcmi_allocate
         if net is None:
             return None
-        feat = mcmi.row_features(cdf, 1e-4)
+        feat = mcmi.row_features(cdf, delta)
         pred = net.predict(feat)
         cost, total_cost = mcmi.chain_cost(feat)
         cpr, lam, fb = mcmi.allocate(pred, cost, int(chains * total_cost))
         alloc.update({"lambda": lam, "fallback": fb})
         return cpr
 
-    for _ in range(args.warmup):
+    rec = {}
+
+    def step():
         cdf = mcmi.Cdf(dB, order_cell=cell)
         res = mcmi.spai(cdf, p, chains_per_row=chains_for(cdf))
-        del cdf, res
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    walk_ms = []
-    for _ in range(args.steps):
-        cdf = mcmi.Cdf(dB, order_cell=cell)
-        cpr = chains_for(cdf)
-        res = mcmi.spai(cdf, p, chains_per_row=cpr)
         res.apply(x, y)
-        walk_ms.append(res.stats.ms_walk)
-        last = res
-        rec_units = cdf.rec_units
-        del cdf
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
+        rec["units"] = cdf.rec_units
+        return res
+
+    elapsed, walk_ms, trans, last = timed_steps(step, args.steps, args.warmup)
     st = last.stats
-    ms_p, ceiling = mcmi.gather_probe(max(1024, rec_units), 1, 128, 16)
-    m = np.maximum(np.diff(B.row_ptr) - 1, 1)
-    bpt = float(np.mean((16.0 if args.prec == 32 else 24.0) + 4.0 * (np.ceil(np.log2(m)) + 1.0) + 4.0))
+    print(f"[aniso27] {args.steps} steps in {elapsed:.3f} s, walk {np.mean(walk_ms):.2f} ms", flush=True)
     walk_s = float(np.mean(walk_ms)) / 1e3
-    out = {"metric": METRIC, "value": st.transitions * args.steps / elapsed, "unit": "transitions/s", "n_gpus": 1,
+    bpt = algorithmic_bytes_per_transition(B, args.prec == 32)
+    traffic = TRAFFIC_BYTES["aniso27"] if (args.nx == 160 and args.prec == 32 and cell == 4096 and net is None
+                                           and chains == 64 and not args.lanes and not args.hash_slots) else None
+    out = {"metric": METRIC, "value": float(sum(trans)) / elapsed, "unit": "transitions/s", "n_gpus": 1,
            "steps": args.steps, "warmup": args.warmup, "ms_per_step": elapsed / args.steps * 1e3,
-           "higher_is_better": True, "dtype": "f32" if args.prec == 32 else "f64", "data": "synthetic",
-           "config": {"workload": f"3D 27-point anisotropic {args.nx}^3", "n": B.n, "nnz_B": B.nnz,
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+           "dtype": "f32" if args.prec == 32 else "f64", "data": "synthetic",
+           "config": {"workload": f"3D 27-point anisotropic diffusion {args.nx}^3 (1:10:100, +-10% noise, "
+                                  f"||C||_inf=0.75), {chains} chains/row"
+                                  f"{' (learned allocation, same mean)' if net is not None else ''}, delta=1e-4, "
+                                  f"eps=1e-3, FP{args.prec} walks + FP64 sums",
+                      "n": B.n, "nnz_B": B.nnz,
                       "chains_per_row": chains, "transitions_per_step": int(st.transitions), "nnz_M": int(last.nnz),
                       "lanes_per_row": st.lanes_per_row, "hash_slots": st.hash_slots, "spilled": int(st.spilled),
-                      "retries": int(st.retries), "record_bytes": int(rec_units) * 64, "order_cell": cell},
-           "roofline": {"bound": "hbm", "achieved": round(bpt * st.transitions / walk_s / 1e9, 1), "peak": HBM_PEAK_GBS,
-                        "unit": "GB/s", "frac": round(bpt * st.transitions / walk_s / 1e9 / HBM_PEAK_GBS, 4),
-                        "traffic": (TRAFFIC_BYTES_ANISO27 if (args.nx == 160 and args.prec == 32 and cell == 4096
-                                                              and net is None) else None),
-                        "kernel": "k_walk",
-                        "bytes_per_transition": round(bpt, 2), "walk_ms": round(walk_s * 1e3, 3),
-                        "walk_transitions_per_s": st.transitions / walk_s, "gather_ceiling_steps_per_s": ceiling}}
+                      "retries": int(st.retries), "record_bytes": int(rec["units"]) * 64, "order_cell": cell},
+           "roofline": roofline_of(bpt, st.transitions, walk_s, args.prec, traffic, "k_walk")}
     if net is not None:
         # quality at the same budget: learned vs uniform chains, 10^4-row sample
         cdf = mcmi.Cdf(dB, order_cell=cell)
         cpr = chains_for(cdf)
         rows = np.sort(np.random.default_rng(12345).choice(B.n, 10000, replace=False))
-        ql = L.evaluate(B, cpr, 1e-4, 1e-3, 0, rows, args.prec, cdf)
-        qu = L.evaluate(B, torch.full((B.n,), chains, dtype=torch.int32, device="cuda"), 1e-4, 1e-3, 0, rows,
+        ql = L.evaluate(B, cpr, delta, eps, 0, rows, args.prec, cdf)
+        qu = L.evaluate(B, torch.full((B.n,), chains, dtype=torch.int32, device="cuda"), delta, eps, 0, rows,
                         args.prec, cdf)
         alloc.update({"chains_min": int(cpr.min().item()), "chains_max": int(cpr.max().item()),
                       "learned": ql, "uniform": qu})
@@ -344,6 +418,9 @@ def aniso_main(args):
         print(f"[aniso27] learned r={ql['r_norm']:.4f} T={ql['transitions']} | uniform r={qu['r_norm']:.4f} "
               f"T={qu['transitions']}", flush=True)
         del cdf
+    elif not args.no_cpu:
+        out["cpu_baseline"], out["precision"] = cpu_baseline(B, chains, delta, eps, last, args.prec, 20.0)
+        print(f"[aniso27] precision {json.dumps(out['precision'])}", flush=True)
     if args.bicgstab:
         # device BiCGstab (b = B 1, x0 = 0, rtol 1e-8): no preconditioner vs M
         Bs_ones = torch.from_numpy(B.to_scipy() @ np.ones(B.n)).cuda()
@@ -355,7 +432,7 @@ def aniso_main(args):
             print(f"[aniso27] bicgstab {name}: {res_it[name]}", flush=True)
         res_it["mcmi"]["preconditioner_plus_solve_ms"] = elapsed / args.steps * 1e3 + res_it["mcmi"]["solve_ms"]
         out["bicgstab"] = res_it
-    print(json.dumps(out), flush=True)
+    return out
 
 
 def batched_main(args):
@@ -372,7 +449,7 @@ def batched_main(args):
     print(f"[batched] generated {len(mats)} matrices, {sum(m.n for m in mats)} rows in "
           f"{time.perf_counter() - t0:.1f} s", flush=True)
     devs = [mcmi.DeviceCsr.from_host(B) for B in mats]
-    chains = args.chains if args.chains != 512 else 128
+    chains = args.chains or 128
     p = mcmi.params(seed=0, chains=chains, delta=1e-4, eps=1e-3, walk_prec=args.prec, lanes_per_row=args.lanes,
                     hash_slots=args.hash_slots)
     cell = 0 if args.order_cell is None else args.order_cell
@@ -434,14 +511,9 @@ def batched_main(args):
     nrow = np.array([m.n for m in mats], dtype=np.float64)
     bpt = float(np.dot(nrow, [algorithmic_bytes_per_transition(m, args.prec == 32) for m in mats]) / nrow.sum())
     walk_s = float(np.mean(walk_ms)) / 1e3
-    achieved = bpt * st.transitions / walk_s / 1e9
-    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4),
-                "traffic": TRAFFIC_BYTES_BATCHED if (args.prec == 32 and chains == 128 and cell == 0 and not args.tune
-                                                     and not args.lanes and not args.hash_slots) else None,
-                "kernel": "k_walk",
-                "bytes_per_transition": round(bpt, 2), "walk_ms": round(walk_s * 1e3, 3),
-                "walk_transitions_per_s": st.transitions / walk_s}
+    traffic = TRAFFIC_BYTES["batched"] if (args.prec == 32 and chains == 128 and cell == 0 and not args.tune
+                                           and not args.lanes and not args.hash_slots) else None
+    roofline = roofline_of(bpt, st.transitions, walk_s, args.prec, traffic, "k_walk")
     out = {"metric": METRIC, "value": trans / elapsed, "unit": "transitions/s", "n_gpus": 1, "steps": args.steps,
            "warmup": args.warmup, "ms_per_step": elapsed / args.steps * 1e3, "higher_is_better": True,
            "dtype": "f32" if args.prec == 32 else "f64", "data": "synthetic",

@@ -353,23 +353,19 @@ mcmi_status mcmi_tune(const mcmi_cdf *cdf, const mcmi_params *base, int64_t samp
  * returns a view of the plan-owned CSR (valid until the next launch or
  * mcmi_plan_free) and *overflow = 1 when a table or the capacity overflowed (the
  * view is then empty: rerun with mcmi_spai or a larger plan). Rows are not rerun
- * inside a plan. The cdf must outlive the plan. */
+ * inside a plan. The cdf must outlive the plan. mcmi_plan_create checks p as
+ * mcmi_spai does (MCMI_ERR_ARG before any allocation or kernel), reads the
+ * per-row chain counts once (one synchronisation: each must be >= 1; the tables
+ * are sized for the largest, so a later change of the array must keep every
+ * count between 1 and that largest value), sizes the HBM overflow tables from the
+ * rows' reach as mcmi_spai does, and walks a batched record set in the eager
+ * launch's longest-processing-time order. */
 typedef struct mcmi_plan mcmi_plan;
 mcmi_status mcmi_plan_create(const mcmi_cdf *cdf, const mcmi_params *p, const int32_t *chains_per_row_dev,
                              int64_t nnz_capacity, mcmi_plan **out, void *stream);
 mcmi_status mcmi_plan_launch(mcmi_plan *plan, uint64_t seed, void *stream);
 mcmi_status mcmi_plan_result(mcmi_plan *plan, mcmi_csr_out *M_view, mcmi_stats *st, int32_t *overflow, void *stream);
 void mcmi_plan_free(mcmi_plan *plan);
-
-/* Memory ceiling of the walk's access pattern: a pointer chase over `units`
- * random 64-byte units (a buffer the size of a record set) in which every step
- * makes reqs_per_step dependent reads of one unit each, a read being
- * loads_per_req (1..4) 16-byte loads of that unit, on waves_per_cu wavefronts per
- * CU, without the method's arithmetic. Returns the kernel time and the steps per
- * second (the rate a walk with that many dependent requests and loads per
- * transition can at most reach). Allocates and synchronises. */
-mcmi_status mcmi_gather_probe(uint64_t units, int32_t reqs_per_step, int32_t loads_per_req, int32_t steps,
-                              int32_t waves_per_cu, double *ms_out, double *steps_per_s_out);
 
 /* Result of mcmi_bicgstab. */
 typedef struct {

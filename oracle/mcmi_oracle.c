@@ -499,13 +499,29 @@ int64_t orc_draw(const orc_mat *A, int64_t s, uint32_t u)
  * Returns the number of transitions (draws). */
 typedef void (*visit_fn)(void *ctx, int64_t s, double w);
 
+/* Is the cutoff test of step j (|wn| < delta) within the rounding band of a walk
+ * with binary32 weights? Such a walk follows the same path, and its step-j weight
+ * differs from this one by at most 2 j products' rounding of 2^-24 each (Shat
+ * rounded to binary32, then the product), its delta by one more: a test inside
+ * the band may go the other way there. Test instrumentation only: the count of
+ * such chains bounds how many contributions of magnitude about delta a
+ * binary32-weight run can add or miss. */
+static int near_cutoff(double wn, double delta, int j)
+{
+    const double u32 = ldexp(1.0, -24);
+    double a = fabs(wn);
+    double big = a > delta ? a : delta;
+    return fabs(a - delta) <= (2.0 * (double)j + 1.0) * u32 * (1.0 + ldexp(1.0, -10)) * big;
+}
+
 static int64_t run_chain(const orc_mat *A, const orc_params *p, int lmax, int64_t r,
-                         uint32_t chain, uint32_t tag, visit_fn visit, void *ctx)
+                         uint32_t chain, uint32_t tag, visit_fn visit, void *ctx, int *border)
 {
     orc_stream st;
     stream_init(&st, p->seed, chain, (uint32_t)r, tag);
     int64_t s = r;
     int64_t steps = 0;
+    int near = 0;
     if (!p->fp32) {
         double w = 1.0;
         visit(ctx, s, w);
@@ -513,6 +529,7 @@ static int64_t run_chain(const orc_mat *A, const orc_params *p, int lmax, int64_
             if (A->cptr[s + 1] == A->cptr[s])
                 break;
             double wn = w * A->shat[s];
+            near |= near_cutoff(wn, p->delta, j);
             if (fabs(wn) < p->delta)
                 break;
             int64_t k = draw_entry(A, s, stream_word(&st, j));
@@ -530,6 +547,7 @@ static int64_t run_chain(const orc_mat *A, const orc_params *p, int lmax, int64_
                 break;
             float s32 = (float)A->shat[s];
             float wn = w * s32;
+            near |= near_cutoff((double)wn, p->delta, j);
             if (fabsf(wn) < delta32)
                 break;
             int64_t k = draw_entry(A, s, stream_word(&st, j));
@@ -539,6 +557,8 @@ static int64_t run_chain(const orc_mat *A, const orc_params *p, int lmax, int64_
             ++steps;
         }
     }
+    if (border)
+        *border = near;
     return steps;
 }
 
@@ -575,6 +595,7 @@ typedef struct {
     uint32_t *cnt;
     int64_t guard;
     int64_t transitions;
+    int64_t border;
     int32_t ambig;
 } row_out;
 
@@ -707,12 +728,16 @@ static void *spai_worker(void *arg)
             int64_t r = job->rows ? job->rows[t] : t;
             int32_t nr = job->chains_per_row ? job->chains_per_row[r] : p->chains;
             ra.ntouched = 0;
-            int64_t steps = 0;
-            for (int32_t c = 0; c < nr; ++c)
-                steps += run_chain(A, p, job->lmax, r, (uint32_t)c, p->tag, accum_visit, &ra);
+            int64_t steps = 0, border = 0;
+            for (int32_t c = 0; c < nr; ++c) {
+                int near = 0;
+                steps += run_chain(A, p, job->lmax, r, (uint32_t)c, p->tag, accum_visit, &ra, &near);
+                border += near;
+            }
             qsort(ra.touched, (size_t)ra.ntouched, sizeof(int32_t), cmp_i32);
             row_out *ro = &job->out[t];
             ro->transitions = steps;
+            ro->border = border;
             ro->guard = 0;
             ro->col = (int32_t *)malloc((size_t)(ra.ntouched + 1) * sizeof(int32_t));
             ro->val = (double *)malloc((size_t)(ra.ntouched + 1) * sizeof(double));
@@ -782,6 +807,7 @@ typedef struct {
     int64_t guard;
     int32_t lmax;
     int32_t *row_ambig;   /* nrows: 1 where the top-k boundary is order-dependent */
+    int64_t *row_border;  /* nrows: chains with a cutoff test inside the binary32 band (near_cutoff) */
 } orc_result;
 
 static int run_threads(void *(*fn)(void *), void *job, int threads)
@@ -857,8 +883,9 @@ int orc_spai(const orc_mat *A, const orc_params *p, const int32_t *rows, int64_t
     res->cnt = (uint32_t *)malloc((size_t)(total + 1) * sizeof(uint32_t));
     res->row_transitions = (int64_t *)malloc((size_t)(nrows + 1) * sizeof(int64_t));
     res->row_ambig = (int32_t *)malloc((size_t)(nrows + 1) * sizeof(int32_t));
+    res->row_border = (int64_t *)malloc((size_t)(nrows + 1) * sizeof(int64_t));
     if (!res->row_ptr || !res->col || !res->val || !res->abssum || !res->cnt || !res->row_transitions ||
-        !res->row_ambig)
+        !res->row_ambig || !res->row_border)
         status = ORC_ERR_NOMEM;
     int64_t pos = 0;
     for (int64_t t = 0; t < nrows; ++t) {
@@ -874,6 +901,7 @@ int orc_spai(const orc_mat *A, const orc_params *p, const int32_t *rows, int64_t
             pos += ro->nnz;
             res->row_transitions[t] = ro->transitions;
             res->row_ambig[t] = ro->ambig;
+            res->row_border[t] = ro->border;
             res->transitions += (uint64_t)ro->transitions;
             res->guard += ro->guard;
         }
@@ -898,6 +926,7 @@ void orc_result_free(orc_result *res)
     free(res->abssum);
     free(res->cnt);
     free(res->row_transitions);
+    free(res->row_border);
     free(res->row_ambig);
     memset(res, 0, sizeof(*res));
 }
@@ -979,7 +1008,7 @@ static void *pilot_worker(void *arg)
         for (int32_t c = 0; c < job->pilot; ++c) {
             cl.n = 0;
             steps += run_chain(A, job->p, job->lmax, r, (uint32_t)c, job->p->tag | 0x80000000u,
-                               list_visit, &cl);
+                               list_visit, &cl, NULL);
             for (int64_t k = 0; k < cl.n; ++k) {
                 int64_t s = cl.cols[k];
                 sq += (long double)cl.vals[k] * (long double)cl.vals[k];

@@ -91,7 +91,8 @@ class _Result(ctypes.Structure):
                 ("col", ctypes.POINTER(ctypes.c_int32)), ("val", ctypes.POINTER(ctypes.c_double)),
                 ("abssum", ctypes.POINTER(ctypes.c_double)), ("cnt", ctypes.POINTER(ctypes.c_uint32)),
                 ("row_transitions", ctypes.POINTER(ctypes.c_int64)), ("transitions", ctypes.c_uint64),
-                ("guard", ctypes.c_int64), ("lmax", ctypes.c_int32), ("row_ambig", ctypes.POINTER(ctypes.c_int32))]
+                ("guard", ctypes.c_int64), ("lmax", ctypes.c_int32), ("row_ambig", ctypes.POINTER(ctypes.c_int32)),
+                ("row_border", ctypes.POINTER(ctypes.c_int64))]
 
 
 class OracleError(RuntimeError):
@@ -202,7 +203,8 @@ class Oracle:
 
         Returns a dict: row_ptr, col, val (M rows), abssum/cnt (per kept entry: sum of
         |W| and number of contributions), row_transitions, transitions, guard, lmax,
-        row_ambig (top-k boundary order-dependent, per row)."""
+        row_ambig (top-k boundary order-dependent, per row), row_border (per row: chains
+        with a cutoff test inside the rounding band of binary32 weights)."""
         prm = self._params(seed, chains, delta, eps, fp32, max_len, tag, threads, filter_on_m, topk)
         rows_arr = None if rows is None else np.ascontiguousarray(rows, dtype=np.int32)
         cpr = None if chains_per_row is None else np.ascontiguousarray(chains_per_row, dtype=np.int32)
@@ -227,6 +229,7 @@ class Oracle:
                 "guard": int(res.guard),
                 "lmax": int(res.lmax),
                 "row_ambig": np.ctypeslib.as_array(res.row_ambig, shape=(max(nr, 1),))[:nr].copy(),
+                "row_border": np.ctypeslib.as_array(res.row_border, shape=(max(nr, 1),))[:nr].copy(),
             }
         finally:
             lib().orc_result_free(ctypes.byref(res))

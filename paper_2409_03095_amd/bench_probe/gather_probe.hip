@@ -1,5 +1,7 @@
 // Dependent random-gather probe (gfx950): the memory ceiling of the walk's
-// access pattern without the method's arithmetic.
+// access pattern without the method's arithmetic. Benchmark tooling, built into
+// its own library (libmcmi_probe.so) and loaded only by the benchmark script;
+// it is not part of the library's C ABI.
 //
 // A buffer of `units` 64-byte units is read by a chase in which every step
 // issues `reqs` dependent reads of one random unit each, a read being `loads`
@@ -11,17 +13,17 @@
 // caches). The measured steps per second is the ceiling a walk with the same
 // number of dependent random blocks per transition can reach on this chip for a
 // record set of the same size.
-#include <string>
+#include <hip/hip_runtime.h>
+#include <stdint.h>
 
-#include "common.hpp"
+#include "../csrc/common.hpp"
 
-namespace mcmi {
 namespace {
 
 __global__ void k_probe_fill(uint4 *buf, uint64_t units, uint32_t seed) {
     const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
     for (uint64_t u = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; u < units; u += stride) {
-        const u32x4 r = philox4x32_10((uint32_t)u, (uint32_t)(u >> 32), 0x50524F42u, 0u, seed, 0x9E3779B9u);
+        const mcmi::u32x4 r = mcmi::philox4x32_10((uint32_t)u, (uint32_t)(u >> 32), 0x50524F42u, 0u, seed, 0x9E3779B9u);
         const uint32_t next = (uint32_t)(((uint64_t)r.x * units) >> 32);
         uint4 *p = buf + u * 4;
         p[0] = make_uint4(next, r.y, r.z, r.w);
@@ -57,24 +59,27 @@ __global__ void __launch_bounds__(256) k_probe_chase(const uint4 *buf, uint64_t 
 }
 
 }  // namespace
-}  // namespace mcmi
 
-using namespace mcmi;
-
-extern "C" mcmi_status mcmi_gather_probe(uint64_t units, int32_t reqs_per_step, int32_t loads_per_req, int32_t steps,
-                                         int32_t waves_per_cu, double *ms_out, double *steps_per_s_out) {
+// Returns 0 on success, -1 for a bad argument, or the HIP error code.
+extern "C" int probe_gather_chase(uint64_t units, int32_t reqs_per_step, int32_t loads_per_req, int32_t steps,
+                                  int32_t waves_per_cu, double *ms_out, double *steps_per_s_out) {
     if (units < 1024 || units >= (1ull << 32) || reqs_per_step < 1 || loads_per_req < 1 || loads_per_req > 4 ||
         steps < 1 || waves_per_cu < 1)
-        return fail(MCMI_ERR_ARG, "mcmi_gather_probe: bad argument");
+        return -1;
+    int dev = 0, cus = 0;
+    (void)hipGetDevice(&dev);
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1) cus = 256;
     uint4 *buf = nullptr;
     unsigned long long *sink = nullptr;
-    MCMI_HIP(hipMalloc(&buf, units * 64));
-    if (hipMalloc(&sink, 8) != hipSuccess) {
+    hipError_t e = hipMalloc(&buf, units * 64);
+    if (e != hipSuccess) return (int)e;
+    e = hipMalloc(&sink, 8);
+    if (e != hipSuccess) {
         (void)hipFree(buf);
-        return fail(MCMI_ERR_NOMEM, "mcmi_gather_probe: alloc");
+        return (int)e;
     }
     k_probe_fill<<<4096, 256>>>(buf, units, 12345u);
-    const int blocks = device_cus() * waves_per_cu / 4;
+    const int blocks = cus * waves_per_cu / 4;
     hipEvent_t a, b;
     (void)hipEventCreate(&a);
     (void)hipEventCreate(&b);
@@ -82,15 +87,15 @@ extern "C" mcmi_status mcmi_gather_probe(uint64_t units, int32_t reqs_per_step, 
     (void)hipEventRecord(a, nullptr);
     k_probe_chase<<<blocks, 256>>>(buf, units, reqs_per_step, loads_per_req, steps, sink);
     (void)hipEventRecord(b, nullptr);
-    hipError_t e = hipEventSynchronize(b);
+    e = hipEventSynchronize(b);
     float ms = 0.f;
     (void)hipEventElapsedTime(&ms, a, b);
     (void)hipEventDestroy(a);
     (void)hipEventDestroy(b);
     (void)hipFree(buf);
     (void)hipFree(sink);
-    if (e != hipSuccess) return fail(MCMI_ERR_HIP, std::string("mcmi_gather_probe: ") + hipGetErrorString(e));
+    if (e != hipSuccess) return (int)e;
     if (ms_out) *ms_out = ms;
     if (steps_per_s_out) *steps_per_s_out = (double)blocks * 256.0 * (double)steps / (ms * 1e-3);
-    return MCMI_OK;
+    return 0;
 }

@@ -14,7 +14,10 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libmcmi.so")
-SOURCES = ["cdf.hip", "walk.hip", "walk_block.hip", "learn.hip", "mlp.hip", "plan.hip", "probe.hip", "krylov.hip", "alloc.hip", "order.hip", "scan.hip", "api.hip"]
+# benchmark tooling, not part of the library's ABI: the dependent-gather probe
+PROBE_SRC = os.path.join(HERE, "bench_probe", "gather_probe.hip")
+PROBE_LIB = os.path.join(HERE, "bench_probe", "libmcmi_probe.so")
+SOURCES = ["cdf.hip", "walk.hip", "walk_block.hip", "learn.hip", "mlp.hip", "plan.hip", "krylov.hip", "alloc.hip", "order.hip", "scan.hip", "api.hip"]
 ARCH = os.environ.get("MCMI_ARCH", "gfx950")
 
 
@@ -42,6 +45,10 @@ def build(verbose: bool = False, jobs: int = 4) -> str:
         if verbose:
             print(" ".join(cmd), flush=True)
         procs.append((src, subprocess.Popen(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT)))
+    probe_tmp = PROBE_LIB + ".tmp"
+    procs.append((os.path.basename(PROBE_SRC),
+                  subprocess.Popen([hipcc()] + FLAGS + ["-shared", PROBE_SRC, "-o", probe_tmp],
+                                   stdout=subprocess.PIPE, stderr=subprocess.STDOUT)))
     failed = []
     for src, p in procs:
         out = p.communicate()[0].decode(errors="replace")
@@ -56,6 +63,7 @@ def build(verbose: bool = False, jobs: int = 4) -> str:
     tmp = LIB + ".tmp"
     subprocess.check_call([hipcc(), f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp] + objs)
     os.replace(tmp, LIB)
+    os.replace(probe_tmp, PROBE_LIB)
     return LIB
 
 

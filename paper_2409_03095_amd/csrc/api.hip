@@ -237,29 +237,101 @@ int pow2_at_least(int v) {
 
 }  // namespace
 
+namespace mcmi {
+
+// Checks of a walk's parameters, shared by mcmi_spai and mcmi_plan_create.
+mcmi_status check_walk_params(const mcmi_params *p, bool per_row_chains, const char *who) {
+    auto bad = [who](const char *m) { return fail(MCMI_ERR_ARG, std::string(who) + ": " + m); };
+    if (p->chains < 1 && !per_row_chains) return bad("chains must be >= 1");
+    if (p->walk_prec != MCMI_WALK_F64 && p->walk_prec != MCMI_WALK_F32) return bad("walk_prec must be 64 or 32");
+    if (!(p->eps >= 0.0) || !(p->delta >= 0.0)) return bad("eps and delta must be >= 0");
+    if (p->filter != MCMI_FILTER_N && p->filter != MCMI_FILTER_M) return bad("bad filter");
+    if (p->topk < 0) return bad("topk < 0");
+    if (p->pool_per_row < 0) return bad("pool_per_row must be >= 0");
+    if (p->spill_slots && (p->spill_slots < 16 || (p->spill_slots & (p->spill_slots - 1))))
+        return bad("spill_slots must be a power of two >= 16");
+    if (p->hash_slots && (p->hash_slots < 64 || p->hash_slots > 8192 || (p->hash_slots & (p->hash_slots - 1))))
+        return bad("hash_slots must be a power of two in [64, 8192]");
+    if (p->sketch_slots && (p->sketch_slots < 64 || p->sketch_slots > 16384))
+        return bad("sketch_slots must be in [64, 16384]");
+    if (p->lanes_per_row && p->lanes_per_row != 8 && p->lanes_per_row != 16 && p->lanes_per_row != 32 &&
+        p->lanes_per_row != 64 && p->lanes_per_row != 256 && p->lanes_per_row != 512 && p->lanes_per_row != 1024)
+        return bad("lanes_per_row must be 0, 8, 16, 32, 64, 256, 512 or 1024");
+    if (!(p->heavy_weight <= 1.0)) return bad("heavy_weight must be <= 1");
+    return MCMI_OK;
+}
+
+// Largest and mean chain count of a row, with the row list and the per-row
+// counts checked on the device (one synchronisation when either is given).
+mcmi_status read_chain_counts(const mcmi_cdf *cdf, const mcmi_params *p, const int32_t *rows_dev, int64_t n_rows,
+                              const int32_t *cpr_dev, int &n_max, int &n_typ, hipStream_t s, const char *who) {
+    n_max = p->chains;
+    n_typ = p->chains;
+    if (!rows_dev && !cpr_dev) return MCMI_OK;
+    uint32_t hv[4] = {0, 0, 0, 0};
+    DevBuf vb;
+    MCMI_HIP(vb.alloc(sizeof(hv), s));
+    MCMI_HIP(hipMemsetAsync(vb.p, 0, sizeof(hv), s));
+    MCMI_HIP(validate_rows(rows_dev, rows_dev ? n_rows : 0, cpr_dev, cdf->n, vb.as<uint32_t>(), s));
+    MCMI_HIP(hipMemcpyAsync(hv, vb.p, sizeof(hv), hipMemcpyDeviceToHost, s));
+    MCMI_HIP(hipStreamSynchronize(s));
+    if (hv[0] & 1u) return fail(MCMI_ERR_ARG, std::string(who) + ": a row index is outside [0, n)");
+    if (hv[0] & 2u) return fail(MCMI_ERR_ARG, std::string(who) + ": chains_per_row holds a value < 1");
+    if (cpr_dev) {
+        unsigned long long sum = 0;
+        ::memcpy(&sum, hv + 2, sizeof(sum));
+        n_max = (int)std::min<uint32_t>(hv[1], 1u << 30);
+        n_typ = (int)std::min<unsigned long long>((sum + (unsigned long long)cdf->n - 1) / (unsigned long long)cdf->n,
+                                                   1ull << 30);
+    }
+    return MCMI_OK;
+}
+
+// Rows per wavefront and HBM overflow slots per region of a launch. Unless
+// given, the wavefront kernel's overflow table has room for every column a
+// row's chains can reach, N_max (L + 1), shared out among the rows of a
+// wavefront (a row with many more chains than its neighbours would otherwise
+// overflow and be rerun); rows stop sharing a wavefront when given tables are
+// too small to share out.
+WaveLayout wave_layout(const KernelShape &shape, int spill_given, int n_max, int lmax) {
+    WaveLayout w;
+    w.lanes = shape.lanes;
+    const bool block_kernel = w.lanes > 64;
+    w.rows_per_wave = block_kernel ? 1 : 64 / w.lanes;
+    w.spill_slots = spill_given;
+    if (!w.spill_slots) {
+        const double reach = (double)std::max(n_max, 1) * ((double)std::max(lmax, 0) + 1.0);
+        if (block_kernel) {
+            w.spill_slots = 16384;
+        } else if (w.rows_per_wave == 1) {
+            w.spill_slots = 4096;
+            while (w.spill_slots < 32768 && (double)w.spill_slots < reach) w.spill_slots *= 2;
+        } else {
+            int sg = 1024;
+            while (sg < 32768 / w.rows_per_wave && (double)sg < reach) sg *= 2;
+            w.spill_slots = sg * w.rows_per_wave;
+        }
+    }
+    while (!block_kernel && w.rows_per_wave > 1 &&
+           (w.spill_slots / w.rows_per_wave < 16 || shape.hash / w.rows_per_wave < 64)) {
+        w.lanes *= 2;
+        w.rows_per_wave /= 2;
+    }
+    return w;
+}
+
+}  // namespace mcmi
+
 extern "C" mcmi_status mcmi_spai(const mcmi_cdf *cdf, const mcmi_params *p, const int32_t *chains_per_row_dev,
                                  const int32_t *rows_dev, int64_t n_rows, mcmi_csr_out *M, mcmi_stats *st,
                                  void *stream) {
     if (M) memset(M, 0, sizeof(*M));
     if (st) memset(st, 0, sizeof(*st));
     if (!cdf || !p || !M) return fail(MCMI_ERR_ARG, "mcmi_spai: null argument");
-    if (p->chains < 1 && !chains_per_row_dev) return fail(MCMI_ERR_ARG, "mcmi_spai: chains must be >= 1");
-    if (p->walk_prec != MCMI_WALK_F64 && p->walk_prec != MCMI_WALK_F32)
-        return fail(MCMI_ERR_ARG, "mcmi_spai: walk_prec must be 64 or 32");
-    if (!(p->eps >= 0.0) || !(p->delta >= 0.0)) return fail(MCMI_ERR_ARG, "mcmi_spai: eps and delta must be >= 0");
-    if (p->filter != MCMI_FILTER_N && p->filter != MCMI_FILTER_M) return fail(MCMI_ERR_ARG, "mcmi_spai: bad filter");
-    if (p->topk < 0) return fail(MCMI_ERR_ARG, "mcmi_spai: topk < 0");
-    if (p->pool_per_row < 0) return fail(MCMI_ERR_ARG, "mcmi_spai: pool_per_row must be >= 0");
-    if (p->spill_slots && (p->spill_slots < 16 || (p->spill_slots & (p->spill_slots - 1))))
-        return fail(MCMI_ERR_ARG, "mcmi_spai: spill_slots must be a power of two >= 16");
-    if (p->hash_slots && (p->hash_slots < 64 || p->hash_slots > 8192 || (p->hash_slots & (p->hash_slots - 1))))
-        return fail(MCMI_ERR_ARG, "mcmi_spai: hash_slots must be a power of two in [64, 8192]");
-    if (p->sketch_slots && (p->sketch_slots < 64 || p->sketch_slots > 16384))
-        return fail(MCMI_ERR_ARG, "mcmi_spai: sketch_slots must be in [64, 16384]");
-    if (p->lanes_per_row && p->lanes_per_row != 8 && p->lanes_per_row != 16 && p->lanes_per_row != 32 &&
-        p->lanes_per_row != 64 && p->lanes_per_row != 256 && p->lanes_per_row != 512 && p->lanes_per_row != 1024)
-        return fail(MCMI_ERR_ARG, "mcmi_spai: lanes_per_row must be 0, 8, 16, 32, 64, 256, 512 or 1024");
-    if (!(p->heavy_weight <= 1.0)) return fail(MCMI_ERR_ARG, "mcmi_spai: heavy_weight must be <= 1");
+    {
+        const mcmi_status cst = check_walk_params(p, chains_per_row_dev != nullptr, "mcmi_spai");
+        if (cst != MCMI_OK) return cst;
+    }
     const int64_t n_tasks = rows_dev ? n_rows : cdf->n;
     if (rows_dev && (n_rows < 1 || n_rows > cdf->n)) return fail(MCMI_ERR_ARG, "mcmi_spai: bad n_rows");
     const int lmax = derive_lmax(cdf->norm_inf, p->delta, p->max_len);
@@ -286,23 +358,10 @@ extern "C" mcmi_status mcmi_spai(const mcmi_cdf *cdf, const mcmi_params *p, cons
 
     // ---- row list and chain counts (one synchronisation), then the kernel shape
     int n_max = p->chains, n_typ = p->chains;  // largest and mean chains of a row
-    if (rows_dev || chains_per_row_dev) {
-        uint32_t hv[4] = {0, 0, 0, 0};
-        DevBuf vb;
-        MCMI_HIP(vb.alloc(sizeof(hv), s));
-        MCMI_HIP(hipMemsetAsync(vb.p, 0, sizeof(hv), s));
-        MCMI_HIP(validate_rows(rows_dev, rows_dev ? n_rows : 0, chains_per_row_dev, cdf->n, vb.as<uint32_t>(), s));
-        MCMI_HIP(hipMemcpyAsync(hv, vb.p, sizeof(hv), hipMemcpyDeviceToHost, s));
-        MCMI_HIP(hipStreamSynchronize(s));
-        if (hv[0] & 1u) return fail(MCMI_ERR_ARG, "mcmi_spai: a row index is outside [0, n)");
-        if (hv[0] & 2u) return fail(MCMI_ERR_ARG, "mcmi_spai: chains_per_row holds a value < 1");
-        if (chains_per_row_dev) {
-            unsigned long long sum = 0;
-            ::memcpy(&sum, hv + 2, sizeof(sum));
-            n_max = (int)std::min<uint32_t>(hv[1], 1u << 30);
-            n_typ = (int)std::min<unsigned long long>((sum + (unsigned long long)cdf->n - 1) / (unsigned long long)cdf->n,
-                                                       1ull << 30);
-        }
+    {
+        const mcmi_status rst = read_chain_counts(cdf, p, rows_dev, n_rows, chains_per_row_dev, n_max, n_typ, s,
+                                                  "mcmi_spai");
+        if (rst != MCMI_OK) return rst;
     }
     const int cus = device_cus();
     const int n_hint = p->chains >= 1 ? p->chains : 64;
@@ -311,35 +370,15 @@ extern "C" mcmi_status mcmi_spai(const mcmi_cdf *cdf, const mcmi_params *p, cons
         const mcmi_status sst = choose_shape(cdf, p, lmax, n_max, n_typ, shape);
         if (sst != MCMI_OK) return sst;
     }
-    int lanes = shape.lanes;
-    const bool block_kernel = lanes > 64;
+    const bool block_kernel = shape.lanes > 64;
     int H = shape.hash;
     const int sketch = shape.sketch;
     const double tau = shape.tau;
     int waves = 4;
-    int rows_per_wave = block_kernel ? 1 : 64 / lanes;
-    int spill_slots = p->spill_slots;
-    if (!spill_slots) {
-        // wavefront kernel: room for every column a row's chains can reach (a row with
-        // many more chains than its neighbours would otherwise overflow and be rerun);
-        // the wave's table is shared out among its rows
-        const double reach = (double)std::max(n_max, 1) * ((double)std::max(lmax, 0) + 1.0);
-        if (block_kernel) {
-            spill_slots = 16384;
-        } else if (rows_per_wave == 1) {
-            spill_slots = 4096;
-            while (spill_slots < 32768 && (double)spill_slots < reach) spill_slots *= 2;
-        } else {
-            int sg = 1024;
-            while (sg < 32768 / rows_per_wave && (double)sg < reach) sg *= 2;
-            spill_slots = sg * rows_per_wave;
-        }
-    }
-    // fewer rows per wavefront when given tables are too small to share out
-    while (!block_kernel && rows_per_wave > 1 && (spill_slots / rows_per_wave < 16 || H / rows_per_wave < 64)) {
-        lanes *= 2;
-        rows_per_wave /= 2;
-    }
+    const WaveLayout layout = wave_layout(shape, p->spill_slots, n_max, lmax);
+    int lanes = layout.lanes;
+    int rows_per_wave = layout.rows_per_wave;
+    int spill_slots = layout.spill_slots;
     // first guess of the output size; rows that do not fit are rerun into a new pool
     // a quarter of the row table per row: rows that overflow the first pool are
     // walked again, so a generous first guess (HBM is large) is the cheap side

@@ -160,6 +160,14 @@ struct mcmi_cdf;
 namespace mcmi {
 mcmi_status choose_shape(const mcmi_cdf *cdf, const mcmi_params *p, int lmax, int n_max, int n_typ,
                          KernelShape &out);
+// Checks shared by every walk launch (api.hip).
+mcmi_status check_walk_params(const mcmi_params *p, bool per_row_chains, const char *who);
+mcmi_status read_chain_counts(const mcmi_cdf *cdf, const mcmi_params *p, const int32_t *rows_dev, int64_t n_rows,
+                              const int32_t *cpr_dev, int &n_max, int &n_typ, hipStream_t s, const char *who);
+struct WaveLayout {
+    int lanes = 64, rows_per_wave = 1, spill_slots = 0;
+};
+WaveLayout wave_layout(const KernelShape &shape, int spill_given, int n_max, int lmax);
 }
 
 // Device-memory cache (alloc.hip): dev_alloc reuses a block released on the

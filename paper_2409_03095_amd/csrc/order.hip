@@ -11,7 +11,7 @@
 // one. Rows that no seed reaches within kMaxGrow levels are cells of their own.
 // The order lists the rows by (seed, row), which a stable radix sort on the seed
 // gives directly.
-#include <hipcub/hipcub.hpp>
+#include <rocprim/device/device_radix_sort.hpp>
 
 #include "common.hpp"
 
@@ -103,8 +103,10 @@ hipError_t build_locality_order(int64_t n, const int64_t *row_ptr, const int32_t
     size_t tmp_bytes = 0;
     int end_bit = 1;
     while (end_bit < 32 && ((uint64_t)(n - 1) >> end_bit) != 0) ++end_bit;
-    hipError_t e = hipcub::DeviceRadixSort::SortPairs(nullptr, tmp_bytes, (const uint32_t *)nullptr, (uint32_t *)nullptr,
-                                                      (const int32_t *)nullptr, (int32_t *)nullptr, (int)n, 0, end_bit, s);
+    // rocPRIM's LSD radix sort (stable) on the labels' low end_bit bits
+    hipError_t e = rocprim::radix_sort_pairs(nullptr, tmp_bytes, (const uint32_t *)nullptr, (uint32_t *)nullptr,
+                                             (const int32_t *)nullptr, (int32_t *)nullptr, (size_t)n, 0u,
+                                             (unsigned)end_bit, s);
     if (e == hipSuccess) e = dev_alloc((void **)&lab0, (size_t)n * 4, s);
     if (e == hipSuccess) e = dev_alloc((void **)&lab1, (size_t)n * 4, s);
     if (e == hipSuccess) e = dev_alloc((void **)&idx, (size_t)n * 4, s);
@@ -129,8 +131,8 @@ hipError_t build_locality_order(int64_t n, const int64_t *row_ptr, const int32_t
         e = hipGetLastError();
     }
     if (e == hipSuccess)
-        e = hipcub::DeviceRadixSort::SortPairs(tmp, tmp_bytes, (const uint32_t *)lab0, lab1, (const int32_t *)idx, order,
-                                               (int)n, 0, end_bit, s);
+        e = rocprim::radix_sort_pairs(tmp, tmp_bytes, (const uint32_t *)lab0, lab1, (const int32_t *)idx, order,
+                                      (size_t)n, 0u, (unsigned)end_bit, s);
     for (void *t : {(void *)lab0, (void *)lab1, (void *)idx, (void *)changed, tmp})
         if (t) dev_release(t, s);
     return e;

@@ -32,6 +32,7 @@ hipError_t walk_occupancy(bool f32, int hash_slots, int waves, int *blocks_per_c
 bool walk_block_supported(int lanes, int hash_slots);
 hipError_t launch_walk_block(const WalkArgs &a, bool f32, int lanes, int blocks, hipStream_t s);
 hipError_t walk_block_occupancy(bool f32, int lanes, int hash_slots, int sketch_slots, int *bpc);
+hipError_t batched_lpt_map(const mcmi_cdf *cdf, double delta, int lmax, int n_hint, int32_t *map, hipStream_t s);
 
 namespace {
 
@@ -209,6 +210,7 @@ struct mcmi_plan {
     double *pool_val = nullptr, *val = nullptr, *sv = nullptr;
     uint64_t *seed = nullptr;
     void *scan_tmp = nullptr;
+    int32_t *lpt = nullptr;     // batched sets: longest-processing-time task order
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     int lmax = 0;
@@ -221,7 +223,7 @@ extern "C" void mcmi_plan_free(mcmi_plan *pl) {
     if (pl->graph) (void)hipGraphDestroy(pl->graph);
     for (void *p : {(void *)pl->ctrl, (void *)pl->row_start, (void *)pl->row_ptr, (void *)pl->row_cnt,
                     (void *)pl->pool_col, (void *)pl->col, (void *)pl->sk, (void *)pl->su, (void *)pl->pool_val,
-                    (void *)pl->val, (void *)pl->sv, (void *)pl->seed, pl->scan_tmp})
+                    (void *)pl->val, (void *)pl->sv, (void *)pl->seed, pl->scan_tmp, (void *)pl->lpt})
         (void)hipFree(p);
     delete pl;
 }
@@ -230,24 +232,35 @@ extern "C" mcmi_status mcmi_plan_create(const mcmi_cdf *cdf, const mcmi_params *
                                         int64_t nnz_capacity, mcmi_plan **out, void *stream) {
     if (out) *out = nullptr;
     if (!cdf || !p || !out || nnz_capacity < 1) return fail(MCMI_ERR_ARG, "mcmi_plan_create: bad argument");
-    if (p->chains < 1 && !chains_per_row_dev) return fail(MCMI_ERR_ARG, "mcmi_plan_create: chains must be >= 1");
-    if (p->walk_prec != MCMI_WALK_F64 && p->walk_prec != MCMI_WALK_F32)
-        return fail(MCMI_ERR_ARG, "mcmi_plan_create: walk_prec must be 64 or 32");
+    {
+        const mcmi_status cst = check_walk_params(p, chains_per_row_dev != nullptr, "mcmi_plan_create");
+        if (cst != MCMI_OK) return cst;
+    }
     const int lmax = derive_lmax(cdf->norm_inf, p->delta, p->max_len);
     if (lmax < 0) return fail(MCMI_ERR_ARG, "mcmi_plan_create: bad delta / max_len or not contractive");
+    hipStream_t s = (hipStream_t)stream;
+    // the per-row chain counts are read once here (checked, largest and mean); a
+    // replay walks the counts the array holds at that time, which must stay >= 1
+    // and at most the largest seen here (the tables are sized for it)
+    int n_max = p->chains, n_typ = p->chains;
+    {
+        const mcmi_status rst = read_chain_counts(cdf, p, nullptr, 0, chains_per_row_dev, n_max, n_typ, s,
+                                                  "mcmi_plan_create");
+        if (rst != MCMI_OK) return rst;
+    }
     mcmi_plan *pl = new mcmi_plan();
     pl->cdf = cdf;
     pl->n = cdf->n;
     pl->cap = nnz_capacity;
     pl->pool_cap = nnz_capacity;
     pl->lmax = lmax;
-    // per-row chain counts are not read back here: size the table for long rows
-    mcmi_status sst = choose_shape(cdf, p, lmax, chains_per_row_dev ? (1 << 20) : p->chains,
-                                   chains_per_row_dev ? 64 : p->chains, pl->shape);
+    mcmi_status sst = choose_shape(cdf, p, lmax, n_max, n_typ, pl->shape);
     if (sst != MCMI_OK) {
         delete pl;
         return sst;
     }
+    const WaveLayout layout = wave_layout(pl->shape, p->spill_slots, n_max, lmax);
+    pl->shape.lanes = layout.lanes;
     const bool f32 = p->walk_prec == MCMI_WALK_F32;
     const bool block_kernel = pl->shape.lanes > 64;
     const int waves = 4;
@@ -267,9 +280,8 @@ extern "C" mcmi_status mcmi_plan_create(const mcmi_cdf *cdf, const mcmi_params *
         if (blocks * waves > pl->n) blocks = std::max<int64_t>(1, (pl->n + waves - 1) / waves);
         regions = blocks * waves;
     }
-    const int spill_slots = p->spill_slots ? p->spill_slots : (block_kernel ? 16384 : 4096);
+    const int spill_slots = layout.spill_slots;
     const size_t ctrl_bytes = 128;
-    hipStream_t s = (hipStream_t)stream;
 #define TRYP(call)                                                                           \
     do {                                                                                     \
         hipError_t _e = (call);                                                              \
@@ -291,6 +303,11 @@ extern "C" mcmi_status mcmi_plan_create(const mcmi_cdf *cdf, const mcmi_params *
     TRYP(hipMalloc(&pl->su, (size_t)regions * spill_slots * sizeof(int32_t)));
     TRYP(hipMalloc(&pl->seed, sizeof(uint64_t)));
     TRYP(hipMalloc(&pl->scan_tmp, scan_tmp_bytes(pl->n)));
+    if (cdf->batch > 0) {
+        // the eager launch's order of a batched set, computed once for every replay
+        TRYP(hipMalloc(&pl->lpt, pl->n * sizeof(int32_t)));
+        TRYP(batched_lpt_map(cdf, p->delta, lmax, p->chains >= 1 ? p->chains : 64, pl->lpt, s));
+    }
     // overflow tables start clean once; every walk leaves them clean again
     TRYP(hipMemsetAsync(pl->sk, 0xFF, (size_t)regions * spill_slots * sizeof(int32_t), s));
     TRYP(hipMemsetAsync(pl->sv, 0, (size_t)regions * spill_slots * sizeof(double), s));
@@ -305,7 +322,7 @@ extern "C" mcmi_status mcmi_plan_create(const mcmi_cdf *cdf, const mcmi_params *
     a.n_tasks = pl->n;
     a.row_lanes = block_kernel ? 0 : pl->shape.lanes;
     a.lane_chains = (!block_kernel && pl->shape.lanes == 64) ? pl->shape.lane_chains : 1;
-    a.task_map = cdf->batch == 0 ? cdf->order : nullptr;  // locality schedule, if the set has one
+    a.task_map = cdf->batch == 0 ? cdf->order : pl->lpt;  // locality schedule or LPT order, if any
     a.chains_per_row = chains_per_row_dev;
     a.chains = p->chains;
     a.keys_dev = (const uint32_t *)(ctrl + 96);

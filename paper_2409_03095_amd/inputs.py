@@ -395,3 +395,12 @@ def cfg4_train(count: int = 2000, seed0: int = 1000):
 
 def cfg4_heldout(nx: int = 1024, seed: int = 999_999) -> Csr:
     return family_5pt(seed, nx, nx)
+
+
+def chain_counts(n: int, mean: float = 12.0, seed: int = 41, lo: int = 1, hi: int = 96) -> np.ndarray:
+    """Per-row chain counts shaped like an allocation that moves chains between
+    rows: log-normal with sigma 0.6 scaled to the given mean, rounded, clipped to
+    [lo, hi] (int32). A test input only: both sides read the same array."""
+    rng = np.random.default_rng(seed)
+    x = rng.lognormal(0.0, 0.6, size=n)
+    return np.clip(np.rint(x * (mean / x.mean())), lo, hi).astype(np.int32)

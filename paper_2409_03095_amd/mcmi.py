@@ -89,9 +89,6 @@ _sig = {
     "mcmi_plan_create": [_v, _P(Params), _v, ctypes.c_int64, _P(_v), _v],
     "mcmi_plan_launch": [_v, ctypes.c_uint64, _v],
     "mcmi_plan_result": [_v, _P(CsrOut), _P(Stats), _P(ctypes.c_int32), _v],
-    "mcmi_gather_probe": [ctypes.c_uint64, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
-                          _P(ctypes.c_double),
-                          _P(ctypes.c_double)],
     "mcmi_cdf_batch_info": [_v, _P(ctypes.c_int32), _v, _v],
     "mcmi_spai": [_v, _P(Params), _v, _v, ctypes.c_int64, _P(CsrOut), _P(Stats), _v],
     "mcmi_apply": [_P(CsrOut), ctypes.c_int64, _v, _v, _v],
@@ -136,7 +133,7 @@ EXPORTED = ["mcmi_cache_trim", "mcmi_bicgstab", "mcmi_build_cdf", "mcmi_build_cd
             "mcmi_mlp_predict", "mcmi_mlp_gradient", "mcmi_mlp_train", "mcmi_allocate", "mcmi_allocate_noalloc",
             "mcmi_neyman_target", "mcmi_chain_cost", "mcmi_mlp_adam_step",
             "mcmi_build_cdf_batched", "mcmi_build_cdf_batched_ex", "mcmi_cdf_batch_info", "mcmi_tune", "mcmi_plan_create", "mcmi_plan_launch",
-            "mcmi_plan_result", "mcmi_plan_free", "mcmi_gather_probe"]
+            "mcmi_plan_result", "mcmi_plan_free"]
 
 
 def _check(st):
@@ -509,15 +506,6 @@ class Plan:
             self.free()
         except Exception:
             pass
-
-
-def gather_probe(units, reqs_per_step=2, steps=256, waves_per_cu=16, loads_per_req=1):
-    """mcmi_gather_probe: (kernel ms, dependent-gather steps per second)."""
-    ms, rate = ctypes.c_double(), ctypes.c_double()
-    _check(_lib.mcmi_gather_probe(ctypes.c_uint64(units), ctypes.c_int32(reqs_per_step),
-                                  ctypes.c_int32(loads_per_req), ctypes.c_int32(steps),
-                                  ctypes.c_int32(waves_per_cu), ctypes.byref(ms), ctypes.byref(rate)))
-    return ms.value, rate.value
 
 
 def bicgstab(B: DeviceCsr, M=None, b=None, x0=None, rtol=1e-8, maxiter=5000, stream=None):

@@ -95,3 +95,68 @@ def compare_topk(gpu, orc, diag, chains):
         tol = np.maximum(1e-12 * np.abs(ov[ib]), bound)
         assert np.all(np.abs(gv[ia] - ov[ib]) <= tol), ("ambiguous row values", r)
     return err, int(amb.sum())
+
+
+U32 = 2.0 ** -24
+
+
+def fp32_walks_against_fp64(n, gpu, rows, orc64, o, chains, eps, delta, rerun):
+    """FP32 walks (binary32 weights and Shat32, binary64 sums) against the FP64
+    oracle on sampled rows. The draws do not depend on the weights, so the two
+    walks follow the same paths and differ in two ways only:
+      * a step-j weight by at most 2 j u32 |W_j| (j binary32 products, each with
+        the rounding of Shat to binary32);
+      * a chain whose cutoff test lies inside that band (the oracle counts them
+        per row: row_border = D_r) may stop one step earlier or later, adding or
+        missing one contribution of magnitude at most delta (1 + 2^-10) (one step,
+        as ||Chat||_inf < 1 - 2^-16 takes the next weight below delta).
+    So an entry may differ by B32 = ((2 L u32 (1 + 2^-10) + 4 (k + 2) u64) sum|W|
+    + D_r delta (1 + 2^-10)) / (N |d_c|) (L: the longest chain, k: contributions),
+    which where contributions cancel exceeds any relative bar. Checked:
+      * every common entry within max(1e-5 |v64|, B32);
+      * an entry kept by one side only lies within B32 |d_c| of eps (kept or
+        dropped by rounding): `rerun(rows)` must give the FP64 oracle's run of
+        those rows with eps = 0, from which such entries' sums are read (an entry
+        no FP64 chain reached counts as 0 with no contributions).
+    Returns (common entries, worst relative error, entries beyond 1e-5 relative,
+    pattern differences, chains near the cutoff)."""
+    rp, col, val = gpu
+    L = int(orc64["lmax"])
+    N = np.broadcast_to(np.asarray(chains, dtype=np.float64), (n,))
+    rows = np.asarray(rows)
+    D = orc64["row_border"].astype(np.float64)
+    assert o.norm_inf < 1.0 - 2.0 ** -16
+    wb = 2.0 * L * U32 * (1.0 + 2.0 ** -10)
+
+    def keyed(r_p, c):
+        return np.repeat(np.arange(r_p.size - 1, dtype=np.int64), np.diff(r_p)) * n + c
+
+    kg, ko = keyed(rp, col), keyed(orc64["row_ptr"], orc64["col"])
+    common, ig, io = np.intersect1d(kg, ko, assume_unique=True, return_indices=True)
+    loc = ko[io] // n
+    dcol = np.abs(o.diag[orc64["col"][io]])
+    b32 = ((wb + 4.0 * (orc64["cnt"][io] + 2.0) * U64) * orc64["abssum"][io] + D[loc] * delta * (1.0 + 2.0 ** -10)) \
+        / N[rows[loc]] / dcol
+    v64 = orc64["val"][io]
+    err = np.abs(val[ig] - v64)
+    rel = err / np.abs(v64)
+    bad = np.nonzero(err > np.maximum(1e-5 * np.abs(v64), b32))[0]
+    assert bad.size == 0, f"{bad.size} FP32 values beyond the bound, worst {err[bad].max()}"
+    only = np.setxor1d(kg, ko, assume_unique=True)
+    if only.size:
+        local = np.unique(only // n)
+        full = rerun(rows[local])
+        kf = keyed(full["row_ptr"], full["col"])
+        want = np.searchsorted(local, only // n) * n + only % n
+        pos = np.minimum(np.searchsorted(kf, want), max(kf.size - 1, 0))
+        found = kf[pos] == want  # (never empty: the diagonal is always kept)
+        c = only % n
+        nh = np.where(found, np.abs(full["val"][pos] * o.diag[c]), 0.0)
+        ab = np.where(found, full["abssum"][pos], 0.0)
+        k = np.where(found, full["cnt"][pos], 0.0)
+        Dr = D[only // n]
+        band = (((wb + 4.0 * (k + 2.0) * U64) * ab + Dr * delta * (1.0 + 2.0 ** -10)) / N[rows[only // n]]
+                + 4.0 * U64 * eps)
+        assert np.all(np.abs(nh - eps) <= band), "a pattern difference away from eps"
+    return (int(common.size), float(rel.max()) if rel.size else 0.0, int(np.sum(rel > 1e-5)), int(only.size),
+            int(D.sum()))

@@ -5,7 +5,7 @@ import pytest
 
 import oracle as O
 from paper_2409_03095_amd import inputs as I
-from parity import compare_spai
+from parity import compare_spai, fp32_walks_against_fp64
 
 pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
@@ -80,6 +80,12 @@ def test_batched_full_size_sampled_rows(mc):
         orc = o.spai(seed=0, chains=128, delta=1e-4, eps=1e-3, fp32=True, tag=k, rows=rows)
         assert orc["guard"] == 0
         compare_spai((sub_rp, sub_col, sub_val), orc, o.diag, 128, rows=rows)
+        # the FP32 walks' error against the FP64 oracle (1e-5 relative, or the FP32
+        # weight-rounding bound where contributions cancel)
+        orc64 = o.spai(seed=0, chains=128, delta=1e-4, eps=1e-3, tag=k, rows=rows)
+        out = fp32_walks_against_fp64(B.n, (sub_rp, sub_col, sub_val), rows, orc64, o, 128, 1e-3, 1e-4,
+                                      lambda r: o.spai(seed=0, chains=128, delta=1e-4, eps=0.0, tag=k, rows=r))
+        print(f"  matrix {k}: FP32 vs FP64 oracle {out}", flush=True)
 
 
 @pytest.mark.parametrize("fault", ["col_high", "col_negative", "row_ptr_end"])
@@ -161,6 +167,54 @@ def test_plan_replays_match_eager_runs(mc, chains):
         assert np.allclose(got[2], val, rtol=1e-12, atol=1e-15)
     orc = O.Oracle(B).spai(seed=13, chains=chains, delta=1e-4, eps=1e-3)
     compare_spai(got, orc, O.Oracle(B).diag, chains)
+
+
+def test_plan_batched_lpt_and_per_row_chains_match_eager(mc):
+    """A plan over a batched record set walks the eager launch's LPT order; a
+    plan with per-row chain counts sizes its tables from the largest count. Every
+    replay equals the eager mcmi_spai result for its seed."""
+    mats, _ = I.convdiff_batch(count=10, seed=8, nmin=300, nmax=3000)
+    cdf = mc.Cdf.batched([mc.DeviceCsr.from_host(B) for B in mats])
+    nrow = int(cdf.batch_info()[1][-1])
+    cpr = torch.from_numpy(I.chain_counts(nrow, mean=24.0, seed=9, hi=160)).cuda()
+    print(f"[gpu] batched plan: {nrow} rows, chains per row {int(cpr.min())}..{int(cpr.max())}", flush=True)
+    for prec, per_row in ((32, False), (64, True)):
+        base = mc.params(seed=0, chains=48, delta=1e-4, eps=1e-3, walk_prec=prec)
+        plan = mc.Plan(cdf, base, nnz_capacity=nrow * 300, chains_per_row=cpr if per_row else None)
+        for seed in (21, 22):
+            plan.launch(seed)
+            got, st, ovf = plan.result()
+            assert not ovf
+            eager = mc.spai(cdf, mc.params(seed=seed, chains=48, delta=1e-4, eps=1e-3, walk_prec=prec),
+                            chains_per_row=cpr if per_row else None)
+            rp, col, val = eager.to_numpy()
+            torch.cuda.synchronize()
+            assert st.transitions == eager.stats.transitions
+            assert np.array_equal(got[0], rp) and np.array_equal(got[1], col)
+            assert np.allclose(got[2], val, rtol=1e-12, atol=1e-15)
+        del plan
+
+
+@pytest.mark.parametrize("bad", ["spill_below_16", "hash_not_pow2", "lanes_odd", "chains_zero_row"])
+def test_plan_create_rejects_what_spai_rejects(mc, bad):
+    """mcmi_plan_create applies mcmi_spai's parameter checks (before any kernel
+    runs): overflow tables below 16 slots, a hash size that is not a power of two,
+    an unsupported lane count, a per-row chain count below 1."""
+    B = I.random_nonsym(2000, seed=54)
+    cdf = mc.Cdf(mc.DeviceCsr.from_host(B))
+    kw = {"spill_below_16": dict(lanes_per_row=8, spill_slots=4), "hash_not_pow2": dict(hash_slots=96),
+          "lanes_odd": dict(lanes_per_row=48), "chains_zero_row": {}}[bad]
+    cpr = None
+    if bad == "chains_zero_row":
+        c = np.full(B.n, 8, dtype=np.int32)
+        c[1234] = 0
+        cpr = torch.from_numpy(c).cuda()
+    p = mc.params(seed=0, chains=32, delta=1e-4, eps=1e-3, **kw)
+    for call in (lambda: mc.Plan(cdf, p, nnz_capacity=B.n * 100, chains_per_row=cpr),
+                 lambda: mc.spai(cdf, p, chains_per_row=cpr)):
+        with pytest.raises(mc.McmiError) as ei:
+            call()
+        assert ei.value.status == -1
 
 
 def test_plan_reports_overflow(mc):

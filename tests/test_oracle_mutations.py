@@ -29,6 +29,9 @@ MUTATIONS = {
     "alias_bucket_off_by_one": ("uint64_t j = um >> 32;", "uint64_t j = ((uint64_t)u * (m - 1)) >> 32;"),
     "shat_is_amax": ("shat[i] = ldexp(amax * (double)run, -q);", "shat[i] = amax;"),
     "philox_multiplier": ("0xD2511F53u", "0xD2511F55u"),
+    "near_cutoff_band_per_step_missing": ("return fabs(a - delta) <= (2.0 * (double)j + 1.0) * u32",
+                                          "return fabs(a - delta) <= u32"),
+    "near_cutoff_not_counted": ("                border += near;", "                border += 0 * near;"),
     "aug_ignores_sign": ("d = d + (d < 0.0 ? -aug : aug);", "d = d + aug;"),
     "aug_norm_is_max_entry": ("s += fabs(v[k]);", "s = fabs(v[k]) > s ? fabs(v[k]) : s;"),
     "drop_cut_off_by_one": ("thr = mag[K];", "thr = mag[K > 0 ? K - 1 : 0];"),
@@ -84,6 +87,9 @@ DRIVER = textwrap.dedent('''
         ("neyman", lambda: pins.test_neyman_target_gives_the_brute_force_optimum()),
         ("adam", lambda: pins.test_adam_two_steps_by_hand()),
         ("cost", lambda: pins.test_chain_cost_counts_the_states_of_every_chain("uniform_0.7")),
+        ("near0", lambda: pins.test_near_cutoff_count_is_zero_far_from_delta()),
+        ("near1", lambda: pins.test_near_cutoff_count_at_a_weight_equal_or_next_to_delta(1.0e-6, True, 9)),
+        ("near3", lambda: pins.test_near_cutoff_count_at_a_weight_equal_or_next_to_delta(3.0e-6, False, 9)),
     ]
     hipcc = shutil.which("hipcc") or "/opt/rocm/bin/hipcc"
     if os.path.exists(hipcc):

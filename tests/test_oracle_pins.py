@@ -112,6 +112,37 @@ def test_p4_uniform_row_sum_matrix_exact_transitions():
         assert np.all(r["row_transitions"] == 32 * 25)
 
 
+def test_near_cutoff_count_is_zero_far_from_delta():
+    """The per-row count of chains whose cutoff test lies inside the rounding band
+    of binary32 weights ((2j + 1) 2^-24 relative at step j) is zero when every
+    weight is far from delta: on the random family every |W_j| is within 1e-7 of
+    0.7^j, and 0.7^25 = 1.34e-4 and 0.7^26 = 0.94e-4 are far from 1e-4."""
+    B = I.random_nonsym(4096, seed=2)
+    o = O.Oracle(B)
+    rows = np.random.default_rng(1).choice(4096, 200, replace=False)
+    for fp32 in (False, True):
+        r = o.spai(seed=0, chains=16, delta=1e-4, eps=1e-3, rows=rows, fp32=fp32)
+        assert not r["row_border"].any()
+
+
+@pytest.mark.parametrize("rel,counted,steps", [(0.0, True, 10), (1.0e-6, True, 9), (3.0e-6, False, 9)])
+def test_near_cutoff_count_at_a_weight_equal_or_next_to_delta(rel, counted, steps):
+    """Torus (every weight of step j is the same FP64 product of j factors Shat =
+    0.8): with delta equal to the step-10 weight the test at step 10 passes
+    (strict cutoff) and lies in the band; delta 1e-6 above it (band at step 10:
+    21 x 2^-24 = 1.25e-6) stops the chains at step 10 and still counts them; 3e-6
+    above it stops them without counting."""
+    B = I.grid2d_5pt(6, 6, 5.0, -1.0, periodic=True)
+    o = O.Oracle(B)
+    w = 1.0
+    for _ in range(10):
+        w = w * float(o.shat[0])
+    delta = w * (1.0 + rel)
+    r = o.spai(seed=2, chains=7, delta=delta, eps=1e-3)
+    assert np.all(r["row_transitions"] == 7 * steps)
+    assert np.all(r["row_border"] == (7 if counted else 0))
+
+
 @pytest.mark.parametrize("case", ["uniform_0.7", "torus_0.8", "dyadic_0.5"])
 def test_chain_cost_counts_the_states_of_every_chain(case):
     """With equal |C| row sums S every chain makes exactly floor(ln delta / ln S)
