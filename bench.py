@@ -72,20 +72,40 @@ def roofline_of(bpt, transitions, walk_s, prec, traffic, kernel):
             "walk_ms": round(walk_s * 1e3, 3), "walk_transitions_per_s": transitions / walk_s}
 
 
-def gather_probe(units, reqs_per_step=1, steps=256, waves_per_cu=16, loads_per_req=1):
+def gather_probe(units, reqs_per_step=1, steps=256, waves_per_cu=16, loads_per_req=1, mode=0):
     """Dependent random-gather ceiling (benchmark tooling, libmcmi_probe.so):
-    (kernel ms, steps per second) of a chase over `units` random 64-byte units."""
+    (kernel ms, steps per second) of a chase over `units` random 64-byte units;
+    mode 0: ordinary device memory, 1: non-temporal loads, 2: uncached memory."""
     import ctypes
     lib = ctypes.CDLL(os.path.join(ROOT, "paper_2409_03095_amd", "bench_probe", "libmcmi_probe.so"))
-    f = lib.probe_gather_chase
+    f = lib.probe_gather_chase_mode
     f.restype = ctypes.c_int
-    f.argtypes = [ctypes.c_uint64, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+    f.argtypes = [ctypes.c_uint64, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
                   ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]
     ms, rate = ctypes.c_double(0.0), ctypes.c_double(0.0)
-    st = f(units, reqs_per_step, loads_per_req, steps, waves_per_cu, ctypes.byref(ms), ctypes.byref(rate))
+    st = f(units, reqs_per_step, loads_per_req, steps, waves_per_cu, mode, ctypes.byref(ms), ctypes.byref(rate))
     if st != 0:
-        raise RuntimeError(f"probe_gather_chase failed with status {st}")
+        raise RuntimeError(f"probe_gather_chase_mode failed with status {st}")
     return ms.value, rate.value
+
+
+def probe_main(args):
+    """The dependent-gather ceiling by buffer size, load width and memory kind:
+    one dependent random 64-byte unit per step, read as one 16-byte load or four,
+    from ordinary memory, with non-temporal loads, or from uncached memory."""
+    import torch
+    torch.cuda.init()
+    out = {"workload": "dependent random gather probe", "unit_bytes": 64, "waves_per_cu": 16, "results": []}
+    for mb in (64, 512, 4096):
+        units = mb * (1 << 20) // 64
+        for mode, kind in ((0, "cached"), (1, "nontemporal"), (2, "uncached")):
+            for loads in (1, 2, 4):
+                ms, rate = gather_probe(units, 1, 128, 16, loads, mode)
+                r = {"buffer_mb": mb, "memory": kind, "bytes_read_per_step": 16 * loads, "steps_per_s": rate,
+                     "ms": ms}
+                out["results"].append(r)
+                print(f"[probe] {json.dumps(r)}", flush=True)
+    print(json.dumps(out), flush=True)
 
 
 def gpu_rows(res, rows):
@@ -234,7 +254,7 @@ def main():
     ap.add_argument("--lanes", type=int, default=0)
     ap.add_argument("--sketch-slots", type=int, default=0)
     ap.add_argument("--heavy-weight", type=float, default=0.0)
-    ap.add_argument("--workload", default="aniso27", choices=["random", "aniso27", "batched", "next"],
+    ap.add_argument("--workload", default="aniso27", choices=["random", "aniso27", "batched", "next", "probe"],
                     help="aniso27: 160^3 27-point anisotropic (default); random: n=262144 random nonsymmetric; "
                          "batched: 256 3D 7-point convection-diffusion matrices in one launch")
     ap.add_argument("--nx", type=int, default=160, help="grid side of the aniso27 workload")
@@ -254,16 +274,27 @@ def main():
     ap.add_argument("--heldout", type=int, default=1024, help="held-out grid side (n = side^2)")
     ap.add_argument("--train-steps", type=int, default=3000)
     ap.add_argument("--probe", action="store_true", help="random: also run the dependent-gather ceiling probe")
+    ap.add_argument("--calib-copy", action="store_true",
+                    help="first run one plain 1 GiB device copy (the reference of rocprofv3's byte counters)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: the Monte Carlo rows would shard across GPUs without communication, "
               "but the benchmark runs and reports a single MI355X only.", file=sys.stderr)
         sys.exit(2)
 
+    if args.calib_copy:
+        import torch
+        src = torch.ones(1 << 27, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     if args.learned:
         return learned_main(args)
     if args.workload == "next":
         return next_main(args)
+    if args.workload == "probe":
+        return probe_main(args)
     if args.workload == "batched":
         return batched_main(args)
     if args.workload == "random":

@@ -215,6 +215,17 @@ mcmi_status mcmi_cdf_batch_info(const mcmi_cdf *cdf, int32_t *count, int64_t *ro
 mcmi_status mcmi_cdf_download(const mcmi_cdf *cdf, uint32_t *rec_host, uint32_t *roff_host, double *diag_host,
                               void *stream);
 
+/* Copy the compact records (the draw data of walks with binary32 weights) to
+ * host memory: rec_units * 8 uint32 words, record offsets as for the full
+ * records but in 32-byte units (synchronises the stream). Record of a row with m
+ * entries: the header {row, m, W, Shat32}, {Shat64 (2 words), b_ii (2 words)},
+ * then bucket j: {T'_j, target_j, m of target_j, Shat32 of target_j},
+ * {w_j, target of A_j, m of that row, its Shat32}, where T'_j = ceil(T_j 2^32 / W)
+ * (the draw with word u takes target_j iff (u m mod 2^32) < T'_j, the same entry
+ * as the full record's rule) and a bucket with T_j = W has T'_j = 2^32 - 1 and
+ * the alias half equal to its own. */
+mcmi_status mcmi_cdf_download_compact(const mcmi_cdf *cdf, uint32_t *rec32_host, void *stream);
+
 /* ||Chat||_inf, n, nnz(C) and the size in 64-byte units of built records. */
 mcmi_status mcmi_cdf_info(const mcmi_cdf *cdf, int64_t *n, int64_t *nnz_c, double *norm_inf,
                           uint64_t *rec_units);

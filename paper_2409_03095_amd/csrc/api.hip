@@ -464,6 +464,7 @@ extern "C" mcmi_status mcmi_spai(const mcmi_cdf *cdf, const mcmi_params *p, cons
         WalkArgs a;
         memset(&a, 0, sizeof(a));
         a.rec = cdf->rec;
+        a.rec32 = cdf->rec32;
         a.roff = cdf->roff;
         a.diag = cdf->diag;
         a.rows = rows_dev;

@@ -216,7 +216,8 @@ __global__ void __launch_bounds__(256) k_fill(int64_t n, const int64_t *__restri
                                               const int64_t *__restrict__ roff64, const int64_t *__restrict__ cptr,
                                               const unsigned long long *__restrict__ cut,
                                               uint32_t *__restrict__ roff32, uint32_t *__restrict__ rec,
-                                              uint2 *__restrict__ sorted, unsigned long long *__restrict__ norm_bits) {
+                                              uint32_t *__restrict__ rec32, uint2 *__restrict__ sorted,
+                                              unsigned long long *__restrict__ norm_bits) {
     const Group<G> g;
     const int sub = g.sub;
     const int64_t grp = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / G;
@@ -228,6 +229,7 @@ __global__ void __launch_bounds__(256) k_fill(int64_t n, const int64_t *__restri
         const double d = diag[r];
         const uint32_t off = (uint32_t)roff64[r];
         uint32_t *hdr = rec + (size_t)off * kUnitWords;
+        uint32_t *hdc = rec32 + (size_t)off * kUnitWords32;
         if (sub == 0) roff32[r] = off;
         if (m == 0) {
             if (sub == 0) {
@@ -237,6 +239,8 @@ __global__ void __launch_bounds__(256) k_fill(int64_t n, const int64_t *__restri
                 hdr[3] = __float_as_uint(0.0f);
                 *(double *)(hdr + 4) = 0.0;
                 for (int z = 6; z < kUnitWords; ++z) hdr[z] = 0u;
+                *(uint4 *)hdc = make_uint4((uint32_t)r, 0u, 0u, __float_as_uint(0.0f));
+                *(double2 *)(hdc + 4) = make_double2(0.0, d);
             }
             continue;
         }
@@ -288,6 +292,8 @@ __global__ void __launch_bounds__(256) k_fill(int64_t n, const int64_t *__restri
             hdr[3] = __float_as_uint((float)shat);
             *(double *)(hdr + 4) = shat;
             for (int z = 6; z < kUnitWords; ++z) hdr[z] = 0u;
+            *(uint4 *)hdc = make_uint4((uint32_t)r, m, carry, __float_as_uint((float)shat));
+            *(double2 *)(hdc + 4) = make_double2(shat, d);
             best = shat > best ? shat : best;
         }
     }
@@ -431,6 +437,78 @@ __global__ void __launch_bounds__(256) k_buckets(int64_t n, const uint32_t *__re
                 if (dst[j] != ~(size_t)0) *(uint4 *)(rec + dst[j]) = v[j];
         }
         // the row table is rewritten by the next batch only after every lane is done with it
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    }
+}
+
+// The compact buckets (8 words each, see common.hpp): a wave takes 64
+// consecutive rows as in k_buckets, two lanes per bucket (its own half, its alias
+// half) and 32 buckets per pass; the targets' m and Shat32 come from the compact
+// header units written by k_fill.
+__global__ void __launch_bounds__(256) k_buckets32(int64_t n, const uint32_t *__restrict__ mrow,
+                                                   const uint32_t *__restrict__ roff32,
+                                                   const int64_t *__restrict__ cptr, const uint2 *__restrict__ sorted,
+                                                   const uint32_t *__restrict__ thr_g,
+                                                   const int32_t *__restrict__ ali_g, uint32_t *__restrict__ rec32) {
+    __shared__ uint32_t pm_s[4][65];
+    __shared__ int64_t pb_s[4][64];
+    __shared__ uint32_t po_s[4][64];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    uint32_t *pm = pm_s[wv];
+    int64_t *pb = pb_s[wv];
+    uint32_t *po = po_s[wv];
+    const int64_t wstride = (int64_t)gridDim.x * 4 * 64;
+    for (int64_t r0 = ((int64_t)blockIdx.x * 4 + wv) * 64; r0 < n; r0 += wstride) {
+        const int64_t r = r0 + lane;
+        const uint32_t m = r < n ? mrow[r] : 0u;
+        const uint32_t incl = wave_incl_scan(m);
+        pm[lane + 1] = incl;
+        if (lane == 0) pm[0] = 0u;
+        pb[lane] = r < n ? cptr[r] : 0;
+        po[lane] = r < n ? roff32[r] : 0u;
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        const uint32_t total = (uint32_t)__shfl((int)incl, 63, 64);
+        const int half = lane & 1;
+        int row[kBucketSlots];
+#pragma unroll
+        for (int j = 0; j < kBucketSlots; ++j) row[j] = 0;
+        for (uint32_t t0 = 0; t0 < total; t0 += 32 * kBucketSlots) {
+            uint4 v[kBucketSlots];
+            size_t dst[kBucketSlots];
+#pragma unroll
+            for (int j = 0; j < kBucketSlots; ++j) {
+                const uint32_t t = t0 + (uint32_t)(j * 32 + (lane >> 1));
+                dst[j] = ~(size_t)0;
+                if (t >= total) continue;
+                while (pm[row[j] + 1] <= t) ++row[j];
+                const int i = row[j];
+                const uint32_t k = t - pm[i];
+                const int64_t e = pb[i] + k;
+                const uint2 own = sorted[e];
+                const uint32_t W = sorted[pb[i] + pm[i + 1] - pm[i] - 1].x;
+                const uint32_t T = thr_g[e];
+                const bool full = T >= W;  // no alias: both halves lead to target_j
+                const uint32_t tgt = (half == 0 || full) ? own.y : sorted[pb[i] + ali_g[e]].y;
+                const uint4 th = *(const uint4 *)(rec32 + (size_t)(tgt & ~kSignBit) * kUnitWords32);
+                uint32_t first;
+                if (half == 0) {
+                    // T' = ceil(T 2^32 / W) (< 2^32 when T < W)
+                    first = full ? 0xFFFFFFFFu : (uint32_t)((((uint64_t)T << 32) + (uint64_t)W - 1u) / (uint64_t)W);
+                } else {
+                    const uint32_t prev = k > 0 ? sorted[e - 1].x : 0u;
+                    first = own.x - prev;  // w_j
+                }
+                v[j] = make_uint4(first, tgt, th.y, th.w);
+                dst[j] = ((size_t)po[i] + 1u + k) * kUnitWords32 + (size_t)half * 4u;
+            }
+#pragma unroll
+            for (int j = 0; j < kBucketSlots; ++j)
+                if (dst[j] != ~(size_t)0) *(uint4 *)(rec32 + dst[j]) = v[j];
+        }
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
@@ -588,16 +666,17 @@ extern "C" mcmi_status mcmi_build_cdf_ex(const mcmi_csr_in *B, const mcmi_cdf_op
     cdf->rec_units = (uint64_t)htot[0];
     cdf->nnz_c = htot[1];
     TRY(dev_alloc((void **)&cdf->rec, (size_t)htot[0] * kUnitWords * 4u + 64u, s));
+    TRY(dev_alloc((void **)&cdf->rec32, (size_t)htot[0] * kUnitWords32 * 4u + 32u, s));
     TRY(dev_alloc((void **)&sorted, (size_t)(htot[1] > 0 ? htot[1] : 1) * sizeof(uint2), s));
     if (lanes == 16)
         k_fill<16><<<grid, 256, 0, s>>>(n, B->row_ptr_dev, B->col_dev, B->val_dev, cdf->diag, cdf->mrow, roff64, cptr,
-                                        cut, cdf->roff, cdf->rec, sorted, norm_bits);
+                                        cut, cdf->roff, cdf->rec, cdf->rec32, sorted, norm_bits);
     else if (lanes == 32)
         k_fill<32><<<grid, 256, 0, s>>>(n, B->row_ptr_dev, B->col_dev, B->val_dev, cdf->diag, cdf->mrow, roff64, cptr,
-                                        cut, cdf->roff, cdf->rec, sorted, norm_bits);
+                                        cut, cdf->roff, cdf->rec, cdf->rec32, sorted, norm_bits);
     else
         k_fill<64><<<grid, 256, 0, s>>>(n, B->row_ptr_dev, B->col_dev, B->val_dev, cdf->diag, cdf->mrow, roff64, cptr,
-                                        cut, cdf->roff, cdf->rec, sorted, norm_bits);
+                                        cut, cdf->roff, cdf->rec, cdf->rec32, sorted, norm_bits);
     TRY(hipGetLastError());
     TRY(dev_alloc((void **)&qs, (size_t)(htot[1] > 0 ? htot[1] : 1) * sizeof(uint32_t), s));
     TRY(dev_alloc((void **)&stk, (size_t)(htot[1] > 0 ? 2 * htot[1] : 2) * sizeof(int32_t), s));
@@ -610,6 +689,8 @@ extern "C" mcmi_status mcmi_build_cdf_ex(const mcmi_csr_in *B, const mcmi_cdf_op
         int64_t bb = (n + 255) / 256;
         if (bb > 16384) bb = 16384;
         k_buckets<<<(unsigned)bb, 256, 0, s>>>(n, cdf->mrow, cdf->roff, cptr, sorted, qs, ali, cdf->rec);
+        TRY(hipGetLastError());
+        k_buckets32<<<(unsigned)bb, 256, 0, s>>>(n, cdf->mrow, cdf->roff, cptr, sorted, qs, ali, cdf->rec32);
     }
     TRY(hipGetLastError());
     unsigned long long hnorm = 0;
@@ -649,6 +730,15 @@ extern "C" mcmi_status mcmi_cdf_info(const mcmi_cdf *cdf, int64_t *n, int64_t *n
     if (nnz_c) *nnz_c = cdf->nnz_c;
     if (norm_inf) *norm_inf = cdf->norm_inf;
     if (rec_units) *rec_units = cdf->rec_units;
+    return MCMI_OK;
+}
+
+extern "C" mcmi_status mcmi_cdf_download_compact(const mcmi_cdf *cdf, uint32_t *rec32_host, void *stream) {
+    if (!cdf || !rec32_host) return fail(MCMI_ERR_ARG, "mcmi_cdf_download_compact: null argument");
+    hipStream_t s = (hipStream_t)stream;
+    MCMI_HIP(hipMemcpyAsync(rec32_host, cdf->rec32, (size_t)cdf->rec_units * kUnitWords32 * 4u, hipMemcpyDeviceToHost,
+                            s));
+    MCMI_HIP(hipStreamSynchronize(s));
     return MCMI_OK;
 }
 
@@ -865,6 +955,7 @@ extern "C" void mcmi_cdf_free(mcmi_cdf *cdf) {
     dev_release_idle(cdf->row_mat);
     dev_release_idle(cdf->mat_base);
     dev_release_idle(cdf->rec);
+    dev_release_idle(cdf->rec32);
     dev_release_idle(cdf->roff);
     dev_release_idle(cdf->diag);
     dev_release_idle(cdf->mrow);

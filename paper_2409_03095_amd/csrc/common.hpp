@@ -42,6 +42,21 @@ mcmi_status fail(mcmi_status st, const std::string &msg);
 // only when a chain starts.
 constexpr int kUnitWords = 16;
 constexpr uint32_t kSignBit = 0x80000000u;
+//
+// Compact records (the wavefront kernel's FP32 walks): the same unit offsets in
+// units of 32 bytes (8 words), so a row of m entries again takes 1 + m units:
+//   unit 0    {row s, m, W, Shat32}, {Shat64 (2 words), d_s (2 words)}
+//   unit 1+j  {T'_j, target_j, m of target_j, Shat32 of target_j},
+//             {w_j, target_{A_j}, m of target_{A_j}, Shat32 of target_{A_j}}
+// with the threshold moved onto the draw's word: the entry is target_j iff
+// f < T'_j, where f = u m mod 2^32 and T'_j = ceil(T_j 2^32 / W) (exactly the
+// r < T_j test of the full record, as floor(f W / 2^32) < T_j <=> f W < T_j 2^32);
+// a bucket that keeps all W units has T'_j = 2^32 - 1 and target_{A_j} =
+// target_j, so f = 2^32 - 1 leads to the same state. A draw reads 32 bytes
+// (two 16-byte loads) of a record half the size; the state's key in the walk is
+// its record offset (unique and increasing with the row), turned into the row at
+// the finalize from the header unit.
+constexpr int kUnitWords32 = 8;
 
 __host__ __device__ inline uint32_t record_units(uint32_t m) { return 1u + m; }
 
@@ -76,8 +91,10 @@ __device__ __forceinline__ u32x4 philox4x32_10(uint32_t c0, uint32_t c1, uint32_
     constexpr uint32_t kWeylA = 0x9E3779B9u, kWeylB = 0xBB67AE85u;
 #pragma unroll
     for (int round = 0; round < 10; ++round) {
-        const uint32_t hiA = __umulhi(kMulA, c0), loA = kMulA * c0;
-        const uint32_t hiB = __umulhi(kMulB, c2), loB = kMulB * c2;
+        // one 32 x 32 -> 64-bit product per multiplier (both halves from one instruction)
+        const uint64_t pA = (uint64_t)kMulA * c0, pB = (uint64_t)kMulB * c2;
+        const uint32_t hiA = (uint32_t)(pA >> 32), loA = (uint32_t)pA;
+        const uint32_t hiB = (uint32_t)(pB >> 32), loB = (uint32_t)pB;
         const uint32_t n0 = hiB ^ c1 ^ k0;
         const uint32_t n2 = hiA ^ c3 ^ k1;
         c0 = n0;
@@ -193,6 +210,7 @@ struct mcmi_cdf {
     int64_t dropped = 0;    // entries of C removed by the reduction
     uint64_t rec_units = 0;
     uint32_t *rec = nullptr;       // records, 16 words per unit
+    uint32_t *rec32 = nullptr;     // compact records, 8 words per unit (same offsets)
     uint32_t *roff = nullptr;      // n: record offset (64-byte units) of each row
     double *diag = nullptr;        // n: b_ii
     uint32_t *mrow = nullptr;      // n: entries of each row of C

@@ -317,6 +317,7 @@ extern "C" mcmi_status mcmi_plan_create(const mcmi_cdf *cdf, const mcmi_params *
     WalkArgs a;
     memset(&a, 0, sizeof(a));
     a.rec = cdf->rec;
+    a.rec32 = cdf->rec32;
     a.roff = cdf->roff;
     a.diag = cdf->diag;
     a.n_tasks = pl->n;

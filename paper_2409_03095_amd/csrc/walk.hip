@@ -85,9 +85,13 @@ __device__ __forceinline__ void row_ids(const WalkArgs &a, int64_t task, RowPre 
     p.r_off = a.roff[p.r];
 }
 
-template <bool kF32>
+template <bool kF32, bool kCmp>
 __device__ __forceinline__ void row_hdr(const WalkArgs &a, RowPre &p) {
-    if (p.task >= 0) load_header<kF32>(a.rec, p.r_off, p.h0);
+    if (p.task < 0) return;
+    if (kCmp)
+        load_header_c(a.rec32, p.r_off, p.h0);
+    else
+        load_header<kF32>(a.rec, p.r_off, p.h0);
 }
 
 // One chain of a lane: its index in the row, state, weight and Philox block.
@@ -106,7 +110,7 @@ struct ChainSt {
 // The next bucket's loads go out first; the weight's accumulation and the Philox
 // block of the next four steps run while they are in flight. `blk` holds the
 // words of the chain's next draws (step j + 1 takes word j mod 4 of block j / 4).
-template <bool kF32>
+template <bool kF32, bool kCmp>
 __device__ __forceinline__ void chain_step(const WalkArgs &a, ChainSt &ch, int stride, int32_t N, uint32_t r_off,
                                            const StepHdr &H0, uint32_t prow, uint32_t ptag, uint32_t k0, uint32_t k1,
                                            int32_t *gkeys, double *gvals, uint32_t hmask, int hshift, int32_t *gskeys,
@@ -131,12 +135,15 @@ __device__ __forceinline__ void chain_step(const WalkArgs &a, ChainSt &ch, int s
         ch.blk.x = ch.blk.y;
         ch.blk.y = ch.blk.z;
         ch.blk.z = ch.blk.w;
-        bucket_issue<kF32>(a.rec, ch.off, ch.H, u, bl);
+        if (kCmp)
+            bucket_issue_c(a.rec32, ch.off, ch.H, u, bl);
+        else
+            bucket_issue<kF32>(a.rec, ch.off, ch.H, u, bl);
         // the last word of the block went to this draw: the next block now
         if ((ch.j & 3u) == 3u) ch.blk = philox4x32_10((ch.j + 1u) >> 2, (uint32_t)ch.c, prow, ptag, k0, k1);
     }
     if (ch.j > 0) {
-        const int32_t key = (int32_t)h.x;
+        const int32_t key = (int32_t)h.x;  // the row, or its compact record offset
         if (!lds_add(gkeys, gvals, hmask, hash_key(key, hshift), key, wcur)) {
             ++spilled;
             if (!spill_add_window(gskeys, gsvals, gsused, gspill, smask, key, wcur)) spill_full = true;
@@ -157,7 +164,7 @@ __device__ __forceinline__ void chain_step(const WalkArgs &a, ChainSt &ch, int s
         }
     } else {
         StepHdr Nx;
-        const uint32_t tgt = bucket_resolve<kF32>(bl, Nx);
+        const uint32_t tgt = kCmp ? bucket_resolve_c(bl, Nx) : bucket_resolve<kF32>(bl, Nx);
         const bool neg = (tgt & kSignBit) != 0u;
         if (kF32)
             ch.w32 = neg ? -wn32 : wn32;
@@ -171,7 +178,7 @@ __device__ __forceinline__ void chain_step(const WalkArgs &a, ChainSt &ch, int s
 
 // The 64 / kG rows of one wave (one per group of kG lanes; cur and nxt hold each
 // lane's own group's row); each lane keeps kC of its row's chains in flight.
-template <bool kF32, int kG, int kC>
+template <bool kF32, int kG, int kC, bool kCmp>
 __device__ __forceinline__ void walk_rows(const WalkArgs &a, const RowPre &cur, RowPre &nxt, int &queue, int64_t &tlo,
                          int64_t &thi, int32_t *keys, double *vals, int *spill_cnt,
                          int32_t *skeys, double *svals, int32_t *sused, uint32_t k0, uint32_t k1,
@@ -199,7 +206,10 @@ __device__ __forceinline__ void walk_rows(const WalkArgs &a, const RowPre &cur, 
     if (has) philox_ids(a, r, prow, ptag);
 
     // j = 0: every chain contributes W_0 = 1 at (r, r); N ones sum exactly to N.
-    if (sub == 0 && has) lds_add(gkeys, gvals, hmask, hash_key(r, hshift), r, (double)N);
+    // Keys are rows, or record offsets with compact records (turned into rows once
+    // the kept set is known).
+    const int32_t rkey = kCmp ? (int32_t)r_off : r;
+    if (sub == 0 && has) lds_add(gkeys, gvals, hmask, hash_key(rkey, hshift), rkey, (double)N);
     wave_sync();
 
     // the row's own header (every chain starts there, loaded ahead); later
@@ -228,7 +238,7 @@ __device__ __forceinline__ void walk_rows(const WalkArgs &a, const RowPre &cur, 
 #pragma unroll
         for (int k = 0; k < kC; ++k)
             if (ch[k].active)
-                chain_step<kF32>(a, ch[k], kG * kC, N, r_off, H0, prow, ptag, k0, k1, gkeys, gvals, hmask, hshift,
+                chain_step<kF32, kCmp>(a, ch[k], kG * kC, N, r_off, H0, prow, ptag, k0, k1, gkeys, gvals, hmask, hshift,
                                  gskeys, gsvals, gsused, spill_cnt + grp, smask, trans, spilled, spill_full);
     }
     wave_sync();
@@ -246,6 +256,7 @@ __device__ __forceinline__ void walk_rows(const WalkArgs &a, const RowPre &cur, 
     for (int g = 0; g < P; ++g) {
         if (__shfl((int)has, g * kG, 64) == 0) continue;  // no row in this group
         const int32_t rg = __shfl(r, g * kG, 64);
+        const int32_t kg = kCmp ? __shfl(rkey, g * kG, 64) : rg;  // the row's own key
         const int32_t Ng = __shfl(N, g * kG, 64);
         const int64_t slot = (int64_t)(((uint64_t)(uint32_t)__shfl((int)(cur.slot >> 32), g * kG, 64) << 32) |
                                        (uint32_t)__shfl((int)(uint32_t)cur.slot, g * kG, 64));
@@ -268,8 +279,9 @@ __device__ __forceinline__ void walk_rows(const WalkArgs &a, const RowPre &cur, 
             double nhat = 0.0;
             if (key != kEmpty) {
                 nhat = acc / nd;  // N_rc; scaled by 1 / d_c once the kept set is final
-                const double test = a.filter_m ? fabs(nhat / a.diag[key]) : fabs(nhat);
-                keep = key == rg || (nhat != 0.0 && test >= a.eps);
+                const double test =
+                    a.filter_m ? fabs(nhat / (kCmp ? diag_of_c(a.rec32, (uint32_t)key) : a.diag[key])) : fabs(nhat);
+                keep = key == kg || (nhat != 0.0 && test >= a.eps);
             }
             const uint64_t km = ballot(keep);
             wave_sync();
@@ -282,7 +294,7 @@ __device__ __forceinline__ void walk_rows(const WalkArgs &a, const RowPre &cur, 
         }
         wave_sync();
         if (!hdr_issued) {
-            row_hdr<kF32>(a, nxt);
+            row_hdr<kF32, kCmp>(a, nxt);
             hdr_issued = true;
         }
         const int nsp = spill_cnt[g];
@@ -296,8 +308,9 @@ __device__ __forceinline__ void walk_rows(const WalkArgs &a, const RowPre &cur, 
                 const int32_t sl = tsu[u];
                 key = tsk[sl];
                 nhat = tsv[sl] / nd;
-                const double test = a.filter_m ? fabs(nhat / a.diag[key]) : fabs(nhat);
-                keep = key == rg || (nhat != 0.0 && test >= a.eps);
+                const double test =
+                    a.filter_m ? fabs(nhat / (kCmp ? diag_of_c(a.rec32, (uint32_t)key) : a.diag[key])) : fabs(nhat);
+                keep = key == kg || (nhat != 0.0 && test >= a.eps);
                 tsk[sl] = kEmpty;
                 tsv[sl] = 0.0;
             }
@@ -315,6 +328,18 @@ __device__ __forceinline__ void walk_rows(const WalkArgs &a, const RowPre &cur, 
         }
         if (K > Hg) K = Hg;
         wave_sync();
+        if (kCmp) {
+            // record offsets -> rows (header units), four independent loads per lane in flight
+            for (int i0 = lane; i0 < K; i0 += 256) {
+                int32_t rw[4];
+#pragma unroll
+                for (int q = 0; q < 4; ++q) rw[q] = i0 + 64 * q < K ? row_of_c(a.rec32, (uint32_t)tk[i0 + 64 * q]) : 0;
+#pragma unroll
+                for (int q = 0; q < 4; ++q)
+                    if (i0 + 64 * q < K) tk[i0 + 64 * q] = rw[q];
+            }
+            wave_sync();
+        }
 
         // top-k retention: bitonic sort in retention order, keep the first topk,
         // then turn N_rc into M_rc = N_rc / d_c
@@ -326,17 +351,16 @@ __device__ __forceinline__ void walk_rows(const WalkArgs &a, const RowPre &cur, 
                 wave_sync();
                 for (int k = 2; k <= PT; k <<= 1) {
                     for (int jj = k >> 1; jj > 0; jj >>= 1) {
-                        for (int i = lane; i < PT; i += 64) {
-                            const int ixj = i ^ jj;
-                            if (ixj > i) {
-                                const int32_t ka = tk[i], kb = tk[ixj];
-                                const double va = tv[i], vb = tv[ixj];
-                                if (top_after(a, rg, ka, va, kb, vb) == ((i & k) == 0)) {
-                                    tk[i] = kb;
-                                    tk[ixj] = ka;
-                                    tv[i] = vb;
-                                    tv[ixj] = va;
-                                }
+                        for (int pr = lane; pr < (PT >> 1); pr += 64) {
+                            const int i = ((pr & ~(jj - 1)) << 1) | (pr & (jj - 1));
+                            const int ixj = i | jj;
+                            const int32_t ka = tk[i], kb = tk[ixj];
+                            const double va = tv[i], vb = tv[ixj];
+                            if (top_after(a, rg, ka, va, kb, vb) == ((i & k) == 0)) {
+                                tk[i] = kb;
+                                tk[ixj] = ka;
+                                tv[i] = vb;
+                                tv[ixj] = va;
                             }
                         }
                         wave_sync();
@@ -357,25 +381,26 @@ __device__ __forceinline__ void walk_rows(const WalkArgs &a, const RowPre &cur, 
         }
         wave_sync();
 
-        // bitonic sort of tk[0..PS) by column, padding with INT32_MAX
+        // bitonic sort of tk[0..PS) by column, padding with INT32_MAX; a pass has PS / 2
+        // compare-exchange pairs, pair p joining i (p with a zero bit inserted at jj)
+        // and i | jj, so every lane has a pair
         int PS = 1;
         while (PS < K) PS <<= 1;
         for (int s = K + lane; s < PS; s += 64) tk[s] = INT32_MAX;
         wave_sync();
         for (int k = 2; k <= PS; k <<= 1) {
             for (int jj = k >> 1; jj > 0; jj >>= 1) {
-                for (int i = lane; i < PS; i += 64) {
-                    const int ixj = i ^ jj;
-                    if (ixj > i) {
-                        const int32_t ka = tk[i], kb = tk[ixj];
-                        const bool up = (i & k) == 0;
-                        if ((ka > kb) == up) {
-                            const double va = tv[i], vb = tv[ixj];
-                            tk[i] = kb;
-                            tk[ixj] = ka;
-                            tv[i] = vb;
-                            tv[ixj] = va;
-                        }
+                for (int pr = lane; pr < (PS >> 1); pr += 64) {
+                    const int i = ((pr & ~(jj - 1)) << 1) | (pr & (jj - 1));
+                    const int ixj = i | jj;
+                    const int32_t ka = tk[i], kb = tk[ixj];
+                    const bool up = (i & k) == 0;
+                    if ((ka > kb) == up) {
+                        const double va = tv[i], vb = tv[ixj];
+                        tk[i] = kb;
+                        tk[ixj] = ka;
+                        tv[i] = vb;
+                        tv[ixj] = va;
                     }
                 }
                 wave_sync();
@@ -434,10 +459,10 @@ __device__ __forceinline__ void walk_rows(const WalkArgs &a, const RowPre &cur, 
         if (lane == 0) spill_cnt[g] = 0;
         wave_sync();
     }
-    if (!hdr_issued) row_hdr<kF32>(a, nxt);
+    if (!hdr_issued) row_hdr<kF32, kCmp>(a, nxt);
 }
 
-template <bool kF32, int kG, int kC>
+template <bool kF32, int kG, int kC, bool kCmp>
 __global__ void __launch_bounds__(256) k_walk(WalkArgs a) {
     constexpr int P = 64 / kG;
     extern __shared__ __align__(16) unsigned char smem[];
@@ -473,11 +498,11 @@ __global__ void __launch_bounds__(256) k_walk(WalkArgs a) {
         const int64_t t = next_task(a, queue, tlo, thi);
         if (grp == g) row_ids(a, t, cur);
     }
-    row_hdr<kF32>(a, cur);
+    row_hdr<kF32, kCmp>(a, cur);
     while (__any(cur.task >= 0)) {
         RowPre nxt;
-        walk_rows<kF32, kG, kC>(a, cur, nxt, queue, tlo, thi, keys, vals, spill_cnt, skeys, svals, sused, k0, k1,
-                                pcur, pend, wstats);
+        walk_rows<kF32, kG, kC, kCmp>(a, cur, nxt, queue, tlo, thi, keys, vals, spill_cnt, skeys, svals, sused, k0,
+                                      k1, pcur, pend, wstats);
         cur = nxt;
     }
     // statistics: one set of atomics per wave
@@ -492,35 +517,38 @@ __global__ void __launch_bounds__(256) k_walk(WalkArgs a) {
 
 size_t walk_lds_bytes(int hash_slots, int waves) { return (size_t)waves * ((size_t)hash_slots * 12u + 64u); }
 
-template <bool kF32>
+template <bool kF32, bool kCmp>
 hipError_t launch_walk_t(const WalkArgs &a, int blocks, int waves, hipStream_t s) {
     const size_t lds = walk_lds_bytes(a.hash_slots, waves);
     switch (a.row_lanes) {
-        case 8: k_walk<kF32, 8, 1><<<blocks, waves * 64, lds, s>>>(a); break;
-        case 16: k_walk<kF32, 16, 1><<<blocks, waves * 64, lds, s>>>(a); break;
-        case 32: k_walk<kF32, 32, 1><<<blocks, waves * 64, lds, s>>>(a); break;
+        case 8: k_walk<kF32, 8, 1, kCmp><<<blocks, waves * 64, lds, s>>>(a); break;
+        case 16: k_walk<kF32, 16, 1, kCmp><<<blocks, waves * 64, lds, s>>>(a); break;
+        case 32: k_walk<kF32, 32, 1, kCmp><<<blocks, waves * 64, lds, s>>>(a); break;
         default:
             if (a.lane_chains == 2)
-                k_walk<kF32, 64, 2><<<blocks, waves * 64, lds, s>>>(a);
+                k_walk<kF32, 64, 2, kCmp><<<blocks, waves * 64, lds, s>>>(a);
             else
-                k_walk<kF32, 64, 1><<<blocks, waves * 64, lds, s>>>(a);
+                k_walk<kF32, 64, 1, kCmp><<<blocks, waves * 64, lds, s>>>(a);
             break;
     }
     return hipGetLastError();
 }
 
+// FP32 walks read the compact records, FP64 walks the full ones (which carry Shat64).
 hipError_t launch_walk(const WalkArgs &a, bool f32, int blocks, int waves, hipStream_t s) {
     if (a.row_lanes != 0 && a.row_lanes != 8 && a.row_lanes != 16 && a.row_lanes != 32 && a.row_lanes != 64)
         return hipErrorInvalidValue;
     if (a.lane_chains == 2 && a.row_lanes != 0 && a.row_lanes != 64) return hipErrorInvalidValue;
-    return f32 ? launch_walk_t<true>(a, blocks, waves, s) : launch_walk_t<false>(a, blocks, waves, s);
+    if (f32 && !a.rec32) return hipErrorInvalidValue;
+    return f32 ? launch_walk_t<true, true>(a, blocks, waves, s) : launch_walk_t<false, false>(a, blocks, waves, s);
 }
 
 hipError_t walk_occupancy(bool f32, int hash_slots, int waves, int *blocks_per_cu) {
     // the instances differ only in loop bounds; the 64-lane one stands for all
     const size_t lds = walk_lds_bytes(hash_slots, waves);
-    if (f32) return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k_walk<true, 64, 1>, waves * 64, lds);
-    return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k_walk<false, 64, 1>, waves * 64, lds);
+    if (f32)
+        return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k_walk<true, 64, 1, true>, waves * 64, lds);
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k_walk<false, 64, 1, false>, waves * 64, lds);
 }
 
 }  // namespace mcmi

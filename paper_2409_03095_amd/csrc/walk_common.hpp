@@ -241,5 +241,41 @@ __device__ __forceinline__ uint32_t bucket_resolve(const BucketLd &b, StepHdr &N
     return own ? b.q0.y : b.q0.z;
 }
 
+// ---------------------------------------------------- compact records (FP32)
+// A chain's state in compact records: h0 = {record offset (the accumulation
+// key), m, 0, Shat32}.
+__device__ __forceinline__ void load_header_c(const uint32_t *rec32, uint32_t off, StepHdr &H) {
+    const uint4 h = *(const uint4 *)(rec32 + (size_t)off * kUnitWords32);
+    H.h0 = make_uint4(off, h.y, 0u, h.w);
+    H.s64 = make_uint2(0u, 0u);
+}
+
+// A compact draw: bucket j = (u m) >> 32, f = u m mod 2^32; target_j iff f < T'_j.
+__device__ __forceinline__ void bucket_issue_c(const uint32_t *rec32, uint32_t off, const StepHdr &H, uint32_t u,
+                                               BucketLd &b) {
+    const uint64_t um = (uint64_t)u * H.h0.y;
+    const uint32_t j = (uint32_t)(um >> 32);
+    b.r = (uint32_t)um;
+    const uint4 *p = (const uint4 *)(rec32 + ((size_t)off + 1u + j) * kUnitWords32);
+    b.q0 = p[0];
+    b.q1 = p[1];
+}
+
+__device__ __forceinline__ uint32_t bucket_resolve_c(const BucketLd &b, StepHdr &N) {
+    const bool own = b.r < b.q0.x;
+    const uint32_t tgt = own ? b.q0.y : b.q1.y;
+    N.h0 = make_uint4(tgt & ~kSignBit, own ? b.q0.z : b.q1.z, 0u, own ? b.q0.w : b.q1.w);
+    N.s64 = make_uint2(0u, 0u);
+    return tgt;
+}
+
+// Row (column index) and d of the row whose compact record starts at unit `off`.
+__device__ __forceinline__ int32_t row_of_c(const uint32_t *rec32, uint32_t off) {
+    return (int32_t)rec32[(size_t)off * kUnitWords32];
+}
+__device__ __forceinline__ double diag_of_c(const uint32_t *rec32, uint32_t off) {
+    return *(const double *)(rec32 + (size_t)off * kUnitWords32 + 6);
+}
+
 }  // namespace walkdev
 }  // namespace mcmi

@@ -83,6 +83,7 @@ _sig = {
     "mcmi_cdf_order": [_v, _v, _v],
     "mcmi_cdf_info": [_v, _P(ctypes.c_int64), _P(ctypes.c_int64), _P(ctypes.c_double), _P(ctypes.c_uint64)],
     "mcmi_cdf_download": [_v, _v, _v, _v, _v],
+    "mcmi_cdf_download_compact": [_v, _v, _v],
     "mcmi_build_cdf_batched": [_P(CsrIn), ctypes.c_int32, _P(_v), _v],
     "mcmi_build_cdf_batched_ex": [_P(CsrIn), ctypes.c_int32, _P(CdfOpts), _P(_v), _v],
     "mcmi_tune": [_v, _P(Params), ctypes.c_int64, ctypes.c_char_p, _P(Params), _P(ctypes.c_double), _v],
@@ -126,7 +127,7 @@ _lib.mcmi_csr_free.restype = None
 _lib.mcmi_last_error.restype = ctypes.c_char_p
 _lib.mcmi_version.restype = ctypes.c_char_p
 
-EXPORTED = ["mcmi_cache_trim", "mcmi_bicgstab", "mcmi_build_cdf", "mcmi_build_cdf_ex", "mcmi_cdf_prep_info", "mcmi_cdf_order", "mcmi_cdf_info", "mcmi_cdf_download", "mcmi_spai", "mcmi_apply",
+EXPORTED = ["mcmi_cache_trim", "mcmi_bicgstab", "mcmi_build_cdf", "mcmi_build_cdf_ex", "mcmi_cdf_prep_info", "mcmi_cdf_order", "mcmi_cdf_info", "mcmi_cdf_download", "mcmi_cdf_download_compact", "mcmi_spai", "mcmi_apply",
             "mcmi_csr_copy", "mcmi_cdf_free", "mcmi_csr_free", "mcmi_last_error", "mcmi_version",
             "mcmi_row_features", "mcmi_pilot_variance", "mcmi_mlp_create", "mcmi_mlp_free",
             "mcmi_mlp_set_params", "mcmi_mlp_get_params", "mcmi_mlp_set_adam_state", "mcmi_mlp_fit_normalization",
@@ -241,6 +242,11 @@ class Cdf:
         _check(_lib.mcmi_cdf_download(self._h, rec.ctypes.data_as(_v), roff.ctypes.data_as(_v),
                                       diag.ctypes.data_as(_v), _stream(stream)))
         return rec, roff, diag
+
+    def download_compact(self, stream=None):
+        rec32 = np.zeros(self.rec_units * 8, dtype=np.uint32)
+        _check(_lib.mcmi_cdf_download_compact(self._h, rec32.ctypes.data_as(_v), _stream(stream)))
+        return rec32
 
     def free(self):
         if self._h:

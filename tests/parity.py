@@ -160,3 +160,61 @@ def fp32_walks_against_fp64(n, gpu, rows, orc64, o, chains, eps, delta, rerun):
         assert np.all(np.abs(nh - eps) <= band), "a pattern difference away from eps"
     return (int(common.size), float(rel.max()) if rel.size else 0.0, int(np.sum(rel > 1e-5)), int(only.size),
             int(D.sum()))
+
+
+def check_compact_records(rec32, roff, o, rng, draws=64):
+    """Compact records (8 words per unit: header {row, m, W, Shat32}, {Shat64,
+    b_ii}; bucket j {T'_j, target_j, m_j, Shat32_j}, {w_j, alias target, its m, its
+    Shat32}) against the oracle's arrays: T'_j = ceil(T_j 2^32 / W) (2^32 - 1 and
+    the alias half equal to the own half when T_j = W), targets as record offsets
+    with the sign of c, the targets' m and Shat32, w_j. Then the draw rule
+    'target_j iff (u m mod 2^32) < T'_j' picks the oracle's entry for random words
+    and for the words on both sides of every threshold of a sample of rows."""
+    n = o.n
+    cm = np.diff(o.cptr)
+    inv = {int(x): i for i, x in enumerate(roff)}
+    for i in range(n):
+        base = int(roff[i]) * 8
+        h = rec32[base:base + 8]
+        b, e = int(o.cptr[i]), int(o.cptr[i + 1])
+        m = e - b
+        assert int(h[0]) == i and int(h[1]) == m and int(h[2]) == int(o.wsum[i]), ("compact header", i)
+        assert h[3:4].view(np.float32)[0] == np.float32(o.shat[i])
+        assert h[4:6].view(np.float64)[0] == o.shat[i] and h[6:8].view(np.float64)[0] == o.diag[i]
+        if m == 0:
+            continue
+        W = int(o.wsum[i])
+        ent = rec32[base + 8:base + 8 + 8 * m].reshape(m, 8).astype(np.int64)
+        cum = o.cum[b:e].astype(np.int64)
+        w = np.diff(np.concatenate([[0], cum]))
+        thr = o.athr[b:e].astype(np.int64)
+        ali = o.aidx[b:e]
+        for k in range(m):
+            full = thr[k] >= W
+            tp = 0xFFFFFFFF if full else -((-(thr[k] << 32)) // W)
+            assert int(ent[k, 0]) == tp, ("T'", i, k)
+            assert int(ent[k, 4]) == int(w[k]), ("w", i, k)
+            for half, kk in ((0, k), (1, k if full else int(ali[k]))):
+                tg = int(ent[k, 4 * half + 1])
+                col = int(o.ccol[b + kk])
+                assert inv[tg & 0x7FFFFFFF] == col and ((tg >> 31) & 1) == int(o.cval[b + kk] < 0), ("target", i, k)
+                assert int(ent[k, 4 * half + 2]) == int(cm[col]), ("target m", i, k)
+                assert np.uint32(ent[k, 4 * half + 3]).view(np.float32) == np.float32(o.shat[col]), ("target S", i, k)
+    rows = rng.choice(n, min(n, 40), replace=False)
+    for i in rows:
+        b, e = int(o.cptr[i]), int(o.cptr[i + 1])
+        m = e - b
+        if m == 0:
+            continue
+        ent = rec32[int(roff[i]) * 8 + 8:int(roff[i]) * 8 + 8 + 8 * m].reshape(m, 8).astype(np.int64)
+        words = [int(x) for x in rng.integers(0, 2 ** 32, size=draws)]
+        for k in range(m):
+            # the last word below T'_k and the first at or above it, inside bucket k
+            u_hi = -(-((k << 32) + int(ent[k, 0])) // m)
+            words += [u for u in (u_hi - 1, u_hi) if 0 <= u < 2 ** 32 and (u * m) >> 32 == k]
+        for u in words:
+            j = (u * m) >> 32
+            f = (u * m) & 0xFFFFFFFF
+            full = int(o.athr[b + j]) >= int(o.wsum[i])
+            pick = j if (f < int(ent[j, 0]) or full) else int(o.aidx[b + j])
+            assert pick == o.draw(int(i), u), ("draw", i, u)

@@ -10,7 +10,7 @@ import pytest
 
 import oracle as O
 from paper_2409_03095_amd import inputs as I
-from parity import common_entries, compare_spai, decode_records, fp32_walks_against_fp64
+from parity import check_compact_records, common_entries, compare_spai, decode_records, fp32_walks_against_fp64
 
 pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
@@ -70,6 +70,8 @@ def test_records_bit_identical(mc, name):
         ai = o.aidx[b:e]
         assert np.array_equal(acol, o.ccol[b:e][ai])
         assert np.array_equal(aneg, o.cval[b:e][ai] < 0)
+    # the compact records of walks with binary32 weights
+    check_compact_records(cdf.download_compact(), roff, o, np.random.default_rng(3))
 
 
 # ------------------------------------------------------------ cfg1 in full
@@ -181,7 +183,7 @@ def test_wavefront_kernel_reruns_bit_identical(mc, case):
     HBM, the 32x32 grid, the 27-point stencil with FP32 walks, rows sharing a
     wavefront, two chains per lane)."""
     B, kw = {"random_spill": (lambda: I.random_nonsym(5000, seed=13), dict(chains=64, hash_slots=128)),
-             "cfg1": (I.cfg1, dict(chains=500)),
+             "cfg1": (I.cfg1, dict(chains=500, lanes_per_row=64)),
              "aniso_f32": (lambda: I.aniso27(14, seed=3), dict(chains=64, prec=32)),
              "shared_wave": (lambda: I.aniso27(10, seed=4), dict(chains=12, lanes_per_row=16)),
              "two_per_lane": (lambda: I.aniso27(10, seed=4), dict(chains=100))}[case]
