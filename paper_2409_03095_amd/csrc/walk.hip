@@ -144,7 +144,7 @@ __device__ __forceinline__ void chain_step(const WalkArgs &a, ChainSt &ch, int s
     }
     if (ch.j > 0) {
         const int32_t key = (int32_t)h.x;  // the row, or its compact record offset
-        if (!lds_add(gkeys, gvals, hmask, hash_key(key, hshift), key, wcur)) {
+        if (!lds_add<true>(gkeys, gvals, hmask, hash_key(key, hshift), key, wcur)) {
             ++spilled;
             if (!spill_add_window(gskeys, gsvals, gsused, gspill, smask, key, wcur)) spill_full = true;
         }
@@ -209,7 +209,7 @@ __device__ __forceinline__ void walk_rows(const WalkArgs &a, const RowPre &cur, 
     // Keys are rows, or record offsets with compact records (turned into rows once
     // the kept set is known).
     const int32_t rkey = kCmp ? (int32_t)r_off : r;
-    if (sub == 0 && has) lds_add(gkeys, gvals, hmask, hash_key(rkey, hshift), rkey, (double)N);
+    if (sub == 0 && has) lds_add<true>(gkeys, gvals, hmask, hash_key(rkey, hshift), rkey, (double)N);
     wave_sync();
 
     // the row's own header (every chain starts there, loaded ahead); later
@@ -266,6 +266,23 @@ __device__ __forceinline__ void walk_rows(const WalkArgs &a, const RowPre &cur, 
         double *tsv = svals + (size_t)g * Sg;
         const int32_t *tsu = sused + (size_t)g * Sg;
         const double nd = (double)Ng;
+        // The eps test needs N_rc = fl(acc / N) only near the cutoff: |acc| above
+        // hi = fl(fl(eps N) (1 + 2^-50)) gives fl(acc / N) >= eps for certain, below lo
+        // = fl(fl(eps N) (1 - 2^-50)) gives < eps; in between (and for the M filter or
+        // eps = 0) the quotient itself decides. Survivors keep acc until the kept set
+        // is known.
+        const bool exact = a.filter_m || !(a.eps > 0.0);
+        const double en = a.eps * nd;
+        const double hi = en * (1.0 + 0x1p-50), lo = en * (1.0 - 0x1p-50);
+        auto keep_test = [&](int32_t key, double acc) -> bool {
+            const double aa = fabs(acc);
+            if (key == kg || (!exact && aa > hi)) return true;
+            if (!exact && !(aa >= lo)) return false;
+            const double nhat = acc / nd;
+            const double test =
+                a.filter_m ? fabs(nhat / (kCmp ? diag_of_c(a.rec32, (uint32_t)key) : a.diag[key])) : fabs(nhat);
+            return nhat != 0.0 && test >= a.eps;
+        };
         int K = 0;
         for (int base = 0; base < Hg; base += 64) {
             const int s = base + lane;
@@ -275,20 +292,13 @@ __device__ __forceinline__ void walk_rows(const WalkArgs &a, const RowPre &cur, 
                 key = tk[s];
                 acc = tv[s];
             }
-            bool keep = false;
-            double nhat = 0.0;
-            if (key != kEmpty) {
-                nhat = acc / nd;  // N_rc; scaled by 1 / d_c once the kept set is final
-                const double test =
-                    a.filter_m ? fabs(nhat / (kCmp ? diag_of_c(a.rec32, (uint32_t)key) : a.diag[key])) : fabs(nhat);
-                keep = key == kg || (nhat != 0.0 && test >= a.eps);
-            }
+            const bool keep = key != kEmpty && keep_test(key, acc);
             const uint64_t km = ballot(keep);
             wave_sync();
             if (keep) {
                 const int pos = K + mask_rank(km);
                 tk[pos] = key;
-                tv[pos] = nhat;
+                tv[pos] = acc;
             }
             K += __popcll(km);
         }
@@ -303,14 +313,12 @@ __device__ __forceinline__ void walk_rows(const WalkArgs &a, const RowPre &cur, 
             const int u = base + lane;
             bool keep = false;
             int32_t key = kEmpty;
-            double nhat = 0.0;
+            double acc = 0.0;
             if (u < nsp) {
                 const int32_t sl = tsu[u];
                 key = tsk[sl];
-                nhat = tsv[sl] / nd;
-                const double test =
-                    a.filter_m ? fabs(nhat / (kCmp ? diag_of_c(a.rec32, (uint32_t)key) : a.diag[key])) : fabs(nhat);
-                keep = key == kg || (nhat != 0.0 && test >= a.eps);
+                acc = tsv[sl];
+                keep = keep_test(key, acc);
                 tsk[sl] = kEmpty;
                 tsv[sl] = 0.0;
             }
@@ -319,7 +327,7 @@ __device__ __forceinline__ void walk_rows(const WalkArgs &a, const RowPre &cur, 
                 const int pos = K + mask_rank(km);
                 if (pos < Hg) {
                     tk[pos] = key;
-                    tv[pos] = nhat;
+                    tv[pos] = acc;
                 } else {
                     stage_full = true;
                 }
@@ -328,22 +336,43 @@ __device__ __forceinline__ void walk_rows(const WalkArgs &a, const RowPre &cur, 
         }
         if (K > Hg) K = Hg;
         wave_sync();
-        if (kCmp) {
-            // record offsets -> rows (header units), four independent loads per lane in flight
-            for (int i0 = lane; i0 < K; i0 += 256) {
-                int32_t rw[4];
+        // the survivors: record offsets -> rows (compact records: row and d from the
+        // header unit, loaded together), N_rc = acc / N, and without top-k at once
+        // M_rc = N_rc / d_c; four entries per lane in flight
+        const bool scale_now = a.topk <= 0;
+        for (int i0 = lane; i0 < K; i0 += 256) {
+            int32_t rw[4];
+            double d[4];
 #pragma unroll
-                for (int q = 0; q < 4; ++q) rw[q] = i0 + 64 * q < K ? row_of_c(a.rec32, (uint32_t)tk[i0 + 64 * q]) : 0;
-#pragma unroll
-                for (int q = 0; q < 4; ++q)
-                    if (i0 + 64 * q < K) tk[i0 + 64 * q] = rw[q];
+            for (int q = 0; q < 4; ++q) {
+                const int i = i0 + 64 * q;
+                rw[q] = i < K ? tk[i] : 0;
+                d[q] = 1.0;
+                if (i < K) {
+                    if (kCmp) {
+                        const uint32_t *h = a.rec32 + (size_t)(uint32_t)rw[q] * kUnitWords32;
+                        rw[q] = (int32_t)h[0];
+                        if (scale_now) d[q] = *(const double *)(h + 6);
+                    } else if (scale_now) {
+                        d[q] = a.diag[rw[q]];
+                    }
+                }
             }
-            wave_sync();
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int i = i0 + 64 * q;
+                if (i < K) {
+                    const double nhat = tv[i] / nd;
+                    tk[i] = rw[q];
+                    tv[i] = scale_now ? nhat / d[q] : nhat;
+                }
+            }
         }
+        wave_sync();
 
         // top-k retention: bitonic sort in retention order, keep the first topk,
         // then turn N_rc into M_rc = N_rc / d_c
-        if (a.topk > 0) {
+        if (!scale_now) {
             if (K > a.topk) {
                 int PT = 1;
                 while (PT < K) PT <<= 1;
@@ -368,42 +397,64 @@ __device__ __forceinline__ void walk_rows(const WalkArgs &a, const RowPre &cur, 
                 }
                 K = a.topk;
             }
-        }
-        // M_rc = N_rc / d_c for the kept entries only, four independent loads per lane
-        // in flight (the eps test on N_rc needs no diagonal)
-        for (int i0 = lane; i0 < K; i0 += 256) {
-            double d[4];
+            for (int i0 = lane; i0 < K; i0 += 256) {
+                double d[4];
 #pragma unroll
-            for (int q = 0; q < 4; ++q) d[q] = i0 + 64 * q < K ? a.diag[tk[i0 + 64 * q]] : 1.0;
+                for (int q = 0; q < 4; ++q) d[q] = i0 + 64 * q < K ? a.diag[tk[i0 + 64 * q]] : 1.0;
 #pragma unroll
-            for (int q = 0; q < 4; ++q)
-                if (i0 + 64 * q < K) tv[i0 + 64 * q] = tv[i0 + 64 * q] / d[q];
+                for (int q = 0; q < 4; ++q)
+                    if (i0 + 64 * q < K) tv[i0 + 64 * q] = tv[i0 + 64 * q] / d[q];
+            }
+            wave_sync();
         }
-        wave_sync();
 
-        // bitonic sort of tk[0..PS) by column, padding with INT32_MAX; a pass has PS / 2
-        // compare-exchange pairs, pair p joining i (p with a zero bit inserted at jj)
-        // and i | jj, so every lane has a pair
+        // Bitonic sort by column. A pass has PS / 2 compare-exchange pairs, pair p
+        // joining i (p with a zero bit inserted at jj) and i | jj, so every lane has a
+        // pair. When the value slots past the survivors have room, the sort moves
+        // one word per entry, (column << 13) | position, in that free part of the
+        // value table, and the values stay where they are; otherwise it moves
+        // (column, value) pairs, padding with INT32_MAX.
         int PS = 1;
         while (PS < K) PS <<= 1;
-        for (int s = K + lane; s < PS; s += 64) tk[s] = INT32_MAX;
-        wave_sync();
-        for (int k = 2; k <= PS; k <<= 1) {
-            for (int jj = k >> 1; jj > 0; jj >>= 1) {
-                for (int pr = lane; pr < (PS >> 1); pr += 64) {
-                    const int i = ((pr & ~(jj - 1)) << 1) | (pr & (jj - 1));
-                    const int ixj = i | jj;
-                    const int32_t ka = tk[i], kb = tk[ixj];
-                    const bool up = (i & k) == 0;
-                    if ((ka > kb) == up) {
-                        const double va = tv[i], vb = tv[ixj];
-                        tk[i] = kb;
-                        tk[ixj] = ka;
-                        tv[i] = vb;
-                        tv[ixj] = va;
+        const bool packed = K + PS <= Hg;
+        uint64_t *pk = (uint64_t *)(tv + (Hg - PS));
+        if (packed) {
+            for (int s = lane; s < PS; s += 64) pk[s] = s < K ? ((uint64_t)(uint32_t)tk[s] << 13) | (uint64_t)s : ~0ull;
+            wave_sync();
+            for (int k = 2; k <= PS; k <<= 1) {
+                for (int jj = k >> 1; jj > 0; jj >>= 1) {
+                    for (int pr = lane; pr < (PS >> 1); pr += 64) {
+                        const int i = ((pr & ~(jj - 1)) << 1) | (pr & (jj - 1));
+                        const int ixj = i | jj;
+                        const uint64_t ea = pk[i], eb = pk[ixj];
+                        if ((ea > eb) == ((i & k) == 0)) {
+                            pk[i] = eb;
+                            pk[ixj] = ea;
+                        }
                     }
+                    wave_sync();
                 }
-                wave_sync();
+            }
+        } else {
+            for (int s = K + lane; s < PS; s += 64) tk[s] = INT32_MAX;
+            wave_sync();
+            for (int k = 2; k <= PS; k <<= 1) {
+                for (int jj = k >> 1; jj > 0; jj >>= 1) {
+                    for (int pr = lane; pr < (PS >> 1); pr += 64) {
+                        const int i = ((pr & ~(jj - 1)) << 1) | (pr & (jj - 1));
+                        const int ixj = i | jj;
+                        const int32_t ka = tk[i], kb = tk[ixj];
+                        const bool up = (i & k) == 0;
+                        if ((ka > kb) == up) {
+                            const double va = tv[i], vb = tv[ixj];
+                            tk[i] = kb;
+                            tk[ixj] = ka;
+                            tv[i] = vb;
+                            tv[ixj] = va;
+                        }
+                    }
+                    wave_sync();
+                }
             }
         }
 
@@ -430,8 +481,14 @@ __device__ __forceinline__ void walk_rows(const WalkArgs &a, const RowPre &cur, 
         const bool ok = fits && !row_spill_full && !row_stage_full;
         if (ok) {
             for (int i = lane; i < K; i += 64) {
-                a.pool_col[pos0 + i] = tk[i];
-                a.pool_val[pos0 + i] = tv[i];
+                if (packed) {
+                    const uint64_t e = pk[i];
+                    a.pool_col[pos0 + i] = (int32_t)(e >> 13);
+                    a.pool_val[pos0 + i] = tv[e & 8191u];
+                } else {
+                    a.pool_col[pos0 + i] = tk[i];
+                    a.pool_val[pos0 + i] = tv[i];
+                }
             }
         }
         const unsigned long long tg = wave_sum(grp == g ? trans : 0ull);

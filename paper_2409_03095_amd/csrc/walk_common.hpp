@@ -14,7 +14,7 @@ __device__ __forceinline__ uint32_t hash_key(int32_t key, int shift) {
 }
 
 // The LDS hash is probed a bucket of 4 slots at a time (two relaxed 64-bit
-// reads), so a lookup in a table at moderate load ends after about one read
+// reads, or one 16-byte read where one wavefront owns the table), so a lookup in a table at moderate load ends after about one read
 // instead of walking a run of slots one by one; in a wavefront the slowest lane's
 // probe sets the time. Slots fill lowest first within a bucket and never empty
 // during a phase, so a bucket with an empty slot ends every search, and a full
@@ -26,6 +26,19 @@ __device__ __forceinline__ void read_bucket(const int32_t *keys, uint32_t b, int
     k[1] = (int32_t)(uint32_t)(lo >> 32);
     k[2] = (int32_t)(uint32_t)hi;
     k[3] = (int32_t)(uint32_t)(hi >> 32);
+}
+
+// The same as one 16-byte LDS read (buckets are 16-byte aligned), for tables that
+// only one wavefront updates (its LDS operations take effect in program order; a
+// probe that finds the bucket taken by another lane's compare-and-swap reads it
+// again).
+typedef int i32x4v __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ void read_bucket_wave(const int32_t *keys, uint32_t b, int32_t k[4]) {
+    const i32x4v q = *(const i32x4v *)(keys + b);
+    k[0] = q.x;
+    k[1] = q.y;
+    k[2] = q.z;
+    k[3] = q.w;
 }
 
 // index in the bucket of `key` (-1 if absent) and of its lowest empty slot (-1 if full)
@@ -41,13 +54,18 @@ __device__ __forceinline__ void scan_bucket(const int32_t k[4], int32_t key, int
 
 // Adds w to key's slot, inserting the key if absent; false when the kMaxLdsProbe
 // slots from the key's bucket on are all held by other keys.
+// kWave: the table belongs to one wavefront (16-byte bucket reads)
+template <bool kWave = false>
 __device__ __forceinline__ bool lds_add(int32_t *keys, double *vals, uint32_t mask, uint32_t h, int32_t key,
                                         double w) {
     uint32_t b = h & ~3u;
     int nb = 0;
     while (nb < kMaxLdsProbe / 4) {
         int32_t k[4];
-        read_bucket(keys, b, k);
+        if (kWave)
+            read_bucket_wave(keys, b, k);
+        else
+            read_bucket(keys, b, k);
         int hit, emp;
         scan_bucket(k, key, hit, emp);
         if (hit >= 0) {
