@@ -215,8 +215,8 @@ __global__ void __launch_bounds__(256) k_fill(int64_t n, const int64_t *__restri
                                               const double *__restrict__ diag, const uint32_t *__restrict__ mrow,
                                               const int64_t *__restrict__ roff64, const int64_t *__restrict__ cptr,
                                               const unsigned long long *__restrict__ cut,
-                                              uint32_t *__restrict__ roff32, uint32_t *__restrict__ rec,
-                                              uint32_t *__restrict__ rec32, uint2 *__restrict__ sorted,
+                                              uint32_t *__restrict__ roff32, uint32_t *__restrict__ rec32,
+                                              uint2 *__restrict__ sorted,
                                               unsigned long long *__restrict__ norm_bits) {
     const Group<G> g;
     const int sub = g.sub;
@@ -228,17 +228,10 @@ __global__ void __launch_bounds__(256) k_fill(int64_t n, const int64_t *__restri
         const uint32_t m = mrow[r];
         const double d = diag[r];
         const uint32_t off = (uint32_t)roff64[r];
-        uint32_t *hdr = rec + (size_t)off * kUnitWords;
         uint32_t *hdc = rec32 + (size_t)off * kUnitWords32;
         if (sub == 0) roff32[r] = off;
         if (m == 0) {
             if (sub == 0) {
-                hdr[0] = (uint32_t)r;
-                hdr[1] = 0u;
-                hdr[2] = 0u;
-                hdr[3] = __float_as_uint(0.0f);
-                *(double *)(hdr + 4) = 0.0;
-                for (int z = 6; z < kUnitWords; ++z) hdr[z] = 0u;
                 *(uint4 *)hdc = make_uint4((uint32_t)r, 0u, 0u, __float_as_uint(0.0f));
                 *(double2 *)(hdc + 4) = make_double2(0.0, d);
             }
@@ -286,12 +279,6 @@ __global__ void __launch_bounds__(256) k_fill(int64_t n, const int64_t *__restri
         }
         if (sub == 0) {
             const double shat = ldexp(amax * (double)carry, -q);
-            hdr[0] = (uint32_t)r;
-            hdr[1] = m;
-            hdr[2] = carry;
-            hdr[3] = __float_as_uint((float)shat);
-            *(double *)(hdr + 4) = shat;
-            for (int z = 6; z < kUnitWords; ++z) hdr[z] = 0u;
             *(uint4 *)hdc = make_uint4((uint32_t)r, m, carry, __float_as_uint((float)shat));
             *(double2 *)(hdc + 4) = make_double2(shat, d);
             best = shat > best ? shat : best;
@@ -367,34 +354,46 @@ __global__ void __launch_bounds__(64) k_alias(int64_t n, const uint32_t *__restr
     }
 }
 
-// The buckets: a wave takes 64 consecutive rows and writes their buckets as one
-// run, four lanes per 64-byte bucket and 64 buckets per pass (each store
-// instruction writes 16 buckets, nearly all consecutive in the records; the loads
-// of a lane's four buckets are issued together). Each bucket is {T_j, target_j,
-// target_{A_j}, w_j} followed by copies of the headers of the two rows it can
-// lead to (written by k_fill, a previous launch) and their Shat64.
 constexpr int kBucketSlots = 4;
 
-__global__ void __launch_bounds__(256) k_buckets(int64_t n, const uint32_t *__restrict__ mrow,
-                                                 const uint32_t *__restrict__ roff32, const int64_t *__restrict__ cptr,
-                                                 const uint2 *__restrict__ sorted, const uint32_t *__restrict__ thr_g,
-                                                 const int32_t *__restrict__ ali_g, uint32_t *__restrict__ rec) {
+// Full records from the compact ones (see common.hpp). Header units: thread per
+// row. Buckets: a wave takes 64 consecutive rows and writes their buckets as one
+// run, four lanes per 64-byte bucket, 64 buckets per pass: {T_j, target_j,
+// target_{A_j}, w_j} with T_j = floor(T'_j W / 2^32) (T_j = W where T'_j = 2^32 - 1;
+// T is the only integer in ((T' - 1) W / 2^32, T' W / 2^32], an interval shorter
+// than 1 as W <= 2^31), then the two targets' header words and their Shat64.
+__global__ void __launch_bounds__(256) k_expand_headers(int64_t n, const uint32_t *__restrict__ roff32,
+                                                        const uint32_t *__restrict__ rec32,
+                                                        uint32_t *__restrict__ rec) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < n; r += stride) {
+        const uint32_t off = roff32[r];
+        const uint4 h = *(const uint4 *)(rec32 + (size_t)off * kUnitWords32);
+        const uint2 s64 = *(const uint2 *)(rec32 + (size_t)off * kUnitWords32 + 4);
+        uint4 *u = (uint4 *)(rec + (size_t)off * kUnitWords);
+        u[0] = h;
+        u[1] = make_uint4(s64.x, s64.y, 0u, 0u);
+        u[2] = make_uint4(0u, 0u, 0u, 0u);
+        u[3] = make_uint4(0u, 0u, 0u, 0u);
+    }
+}
+
+__global__ void __launch_bounds__(256) k_expand_buckets(int64_t n, const uint32_t *__restrict__ mrow,
+                                                        const uint32_t *__restrict__ roff32,
+                                                        const uint32_t *__restrict__ rec32,
+                                                        uint32_t *__restrict__ rec) {
     __shared__ uint32_t pm_s[4][65];
-    __shared__ int64_t pb_s[4][64];
     __shared__ uint32_t po_s[4][64];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     uint32_t *pm = pm_s[wv];
-    int64_t *pb = pb_s[wv];
     uint32_t *po = po_s[wv];
     const int64_t wstride = (int64_t)gridDim.x * 4 * 64;
     for (int64_t r0 = ((int64_t)blockIdx.x * 4 + wv) * 64; r0 < n; r0 += wstride) {
         const int64_t r = r0 + lane;
         const uint32_t m = r < n ? mrow[r] : 0u;
-        // the 64 rows' buckets as one run: row i owns [pm[i], pm[i + 1])
         const uint32_t incl = wave_incl_scan(m);
         pm[lane + 1] = incl;
         if (lane == 0) pm[0] = 0u;
-        pb[lane] = r < n ? cptr[r] : 0;
         po[lane] = r < n ? roff32[r] : 0u;
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
@@ -415,19 +414,19 @@ __global__ void __launch_bounds__(256) k_buckets(int64_t n, const uint32_t *__re
                 while (pm[row[j] + 1] <= t) ++row[j];
                 const int i = row[j];
                 const uint32_t k = t - pm[i];
-                const int64_t e = pb[i] + k;
-                const uint2 own = sorted[e];
+                const uint32_t *cb = rec32 + ((size_t)po[i] + 1u + k) * kUnitWords32;
+                const uint4 q0 = *(const uint4 *)cb, q1 = *(const uint4 *)(cb + 4);
                 if (part == 0) {
-                    const uint32_t prev = k > 0 ? sorted[e - 1].x : 0u;
-                    v[j] = make_uint4(thr_g[e], own.y, sorted[pb[i] + ali_g[e]].y, own.x - prev);
+                    const uint32_t W = rec32[(size_t)po[i] * kUnitWords32 + 2];
+                    const uint32_t T = q0.x == 0xFFFFFFFFu ? W : (uint32_t)(((uint64_t)q0.x * W) >> 32);
+                    v[j] = make_uint4(T, q0.y, q1.y, q1.x);
                 } else if (part == 1) {
-                    v[j] = *(const uint4 *)(rec + (size_t)(own.y & ~kSignBit) * kUnitWords);
+                    v[j] = *(const uint4 *)(rec32 + (size_t)(q0.y & ~kSignBit) * kUnitWords32);
                 } else if (part == 2) {
-                    v[j] = *(const uint4 *)(rec + (size_t)(sorted[pb[i] + ali_g[e]].y & ~kSignBit) * kUnitWords);
+                    v[j] = *(const uint4 *)(rec32 + (size_t)(q1.y & ~kSignBit) * kUnitWords32);
                 } else {
-                    const uint2 so = *(const uint2 *)(rec + (size_t)(own.y & ~kSignBit) * kUnitWords + 4);
-                    const uint2 sa =
-                        *(const uint2 *)(rec + (size_t)(sorted[pb[i] + ali_g[e]].y & ~kSignBit) * kUnitWords + 4);
+                    const uint2 so = *(const uint2 *)(rec32 + (size_t)(q0.y & ~kSignBit) * kUnitWords32 + 4);
+                    const uint2 sa = *(const uint2 *)(rec32 + (size_t)(q1.y & ~kSignBit) * kUnitWords32 + 4);
                     v[j] = make_uint4(so.x, so.y, sa.x, sa.y);
                 }
                 dst[j] = ((size_t)po[i] + 1u + k) * kUnitWords + (size_t)part * 4u;
@@ -436,7 +435,6 @@ __global__ void __launch_bounds__(256) k_buckets(int64_t n, const uint32_t *__re
             for (int j = 0; j < kBucketSlots; ++j)
                 if (dst[j] != ~(size_t)0) *(uint4 *)(rec + dst[j]) = v[j];
         }
-        // the row table is rewritten by the next batch only after every lane is done with it
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
@@ -444,7 +442,7 @@ __global__ void __launch_bounds__(256) k_buckets(int64_t n, const uint32_t *__re
 }
 
 // The compact buckets (8 words each, see common.hpp): a wave takes 64
-// consecutive rows as in k_buckets, two lanes per bucket (its own half, its alias
+// consecutive rows as in k_expand_buckets, two lanes per bucket (its own half, its alias
 // half) and 32 buckets per pass; the targets' m and Shat32 come from the compact
 // header units written by k_fill.
 __global__ void __launch_bounds__(256) k_buckets32(int64_t n, const uint32_t *__restrict__ mrow,
@@ -529,6 +527,31 @@ unsigned grid_for_rows(int64_t n) {
 }
 
 }  // namespace
+
+hipError_t ensure_full_records(const mcmi_cdf *cdf_c, hipStream_t s) {
+    mcmi_cdf *cdf = const_cast<mcmi_cdf *>(cdf_c);
+    std::lock_guard<std::mutex> guard(cdf->full_lock);
+    if (cdf->rec) return hipSuccess;
+    uint32_t *rec = nullptr;
+    hipError_t e = dev_alloc((void **)&rec, (size_t)cdf->rec_units * kUnitWords * 4u + 64u, s);
+    if (e != hipSuccess) return e;
+    k_expand_headers<<<grid_for(cdf->n), 256, 0, s>>>(cdf->n, cdf->roff, cdf->rec32, rec);
+    e = hipGetLastError();
+    if (e == hipSuccess) {
+        int64_t bb = (cdf->n + 255) / 256;
+        if (bb > 16384) bb = 16384;
+        k_expand_buckets<<<(unsigned)bb, 256, 0, s>>>(cdf->n, cdf->mrow, cdf->roff, cdf->rec32, rec);
+        e = hipGetLastError();
+    }
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) {
+        dev_release_idle(rec);
+        return e;
+    }
+    cdf->rec = rec;
+    return hipSuccess;
+}
+
 }  // namespace mcmi
 
 using namespace mcmi;
@@ -665,18 +688,17 @@ extern "C" mcmi_status mcmi_build_cdf_ex(const mcmi_csr_in *B, const mcmi_cdf_op
     if (htot[0] >= (int64_t)kSignBit) return bail(MCMI_ERR_CAPACITY, "mcmi_build_cdf: records exceed 128 GiB");
     cdf->rec_units = (uint64_t)htot[0];
     cdf->nnz_c = htot[1];
-    TRY(dev_alloc((void **)&cdf->rec, (size_t)htot[0] * kUnitWords * 4u + 64u, s));
     TRY(dev_alloc((void **)&cdf->rec32, (size_t)htot[0] * kUnitWords32 * 4u + 32u, s));
     TRY(dev_alloc((void **)&sorted, (size_t)(htot[1] > 0 ? htot[1] : 1) * sizeof(uint2), s));
     if (lanes == 16)
         k_fill<16><<<grid, 256, 0, s>>>(n, B->row_ptr_dev, B->col_dev, B->val_dev, cdf->diag, cdf->mrow, roff64, cptr,
-                                        cut, cdf->roff, cdf->rec, cdf->rec32, sorted, norm_bits);
+                                        cut, cdf->roff, cdf->rec32, sorted, norm_bits);
     else if (lanes == 32)
         k_fill<32><<<grid, 256, 0, s>>>(n, B->row_ptr_dev, B->col_dev, B->val_dev, cdf->diag, cdf->mrow, roff64, cptr,
-                                        cut, cdf->roff, cdf->rec, cdf->rec32, sorted, norm_bits);
+                                        cut, cdf->roff, cdf->rec32, sorted, norm_bits);
     else
         k_fill<64><<<grid, 256, 0, s>>>(n, B->row_ptr_dev, B->col_dev, B->val_dev, cdf->diag, cdf->mrow, roff64, cptr,
-                                        cut, cdf->roff, cdf->rec, cdf->rec32, sorted, norm_bits);
+                                        cut, cdf->roff, cdf->rec32, sorted, norm_bits);
     TRY(hipGetLastError());
     TRY(dev_alloc((void **)&qs, (size_t)(htot[1] > 0 ? htot[1] : 1) * sizeof(uint32_t), s));
     TRY(dev_alloc((void **)&stk, (size_t)(htot[1] > 0 ? 2 * htot[1] : 2) * sizeof(int32_t), s));
@@ -688,8 +710,6 @@ extern "C" mcmi_status mcmi_build_cdf_ex(const mcmi_csr_in *B, const mcmi_cdf_op
         TRY(hipGetLastError());
         int64_t bb = (n + 255) / 256;
         if (bb > 16384) bb = 16384;
-        k_buckets<<<(unsigned)bb, 256, 0, s>>>(n, cdf->mrow, cdf->roff, cptr, sorted, qs, ali, cdf->rec);
-        TRY(hipGetLastError());
         k_buckets32<<<(unsigned)bb, 256, 0, s>>>(n, cdf->mrow, cdf->roff, cptr, sorted, qs, ali, cdf->rec32);
     }
     TRY(hipGetLastError());
@@ -746,8 +766,10 @@ extern "C" mcmi_status mcmi_cdf_download(const mcmi_cdf *cdf, uint32_t *rec_host
                                          double *diag_host, void *stream) {
     if (!cdf) return fail(MCMI_ERR_ARG, "mcmi_cdf_download: null cdf");
     hipStream_t s = (hipStream_t)stream;
-    if (rec_host)
+    if (rec_host) {
+        MCMI_HIP(ensure_full_records(cdf, s));
         MCMI_HIP(hipMemcpyAsync(rec_host, cdf->rec, (size_t)cdf->rec_units * kUnitWords * 4u, hipMemcpyDeviceToHost, s));
+    }
     if (roff_host) MCMI_HIP(hipMemcpyAsync(roff_host, cdf->roff, (size_t)cdf->n * 4u, hipMemcpyDeviceToHost, s));
     if (diag_host) MCMI_HIP(hipMemcpyAsync(diag_host, cdf->diag, (size_t)cdf->n * 8u, hipMemcpyDeviceToHost, s));
     MCMI_HIP(hipStreamSynchronize(s));
@@ -795,7 +817,7 @@ __global__ void __launch_bounds__(256) k_concat(const BatchPart *parts, int32_t 
 
 // ||Chat_k||_inf per matrix: the largest Shat64 of its rows (bits of non-negative
 // doubles). A wave whose 64 rows belong to one matrix reduces them first.
-__global__ void __launch_bounds__(256) k_matrix_norms(int64_t n, const uint32_t *rec, const uint32_t *roff,
+__global__ void __launch_bounds__(256) k_matrix_norms(int64_t n, const uint32_t *rec32, const uint32_t *roff,
                                                       const int32_t *row_mat, unsigned long long *bits) {
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (int64_t r0 = (int64_t)blockIdx.x * blockDim.x; r0 < n; r0 += stride) {  // uniform per wave
@@ -804,7 +826,7 @@ __global__ void __launch_bounds__(256) k_matrix_norms(int64_t n, const uint32_t 
         unsigned long long b = 0;
         int32_t k = -1;
         if (ok) {
-            const uint32_t *h = rec + (size_t)roff[r] * kUnitWords;
+            const uint32_t *h = rec32 + (size_t)roff[r] * kUnitWords32;  // Shat64 in words 4-5
             b = ((unsigned long long)h[5] << 32) | h[4];
             k = row_mat[r];
         }
@@ -915,7 +937,7 @@ extern "C" mcmi_status mcmi_build_cdf_batched_ex(const mcmi_csr_in *Bs, int32_t 
     cdf->row_mat = row_mat;
     cdf->mat_base = base_dev;
     cdf->mat_base_host = rb;
-    k_matrix_norms<<<grid_for(n), 256, 0, s>>>(n, cdf->rec, cdf->roff, row_mat, nb);
+    k_matrix_norms<<<grid_for(n), 256, 0, s>>>(n, cdf->rec32, cdf->roff, row_mat, nb);
     std::vector<unsigned long long> hb(count);
     hipError_t e = hipMemcpyAsync(hb.data(), nb, count * sizeof(unsigned long long), hipMemcpyDeviceToHost, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);

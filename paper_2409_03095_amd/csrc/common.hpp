@@ -187,6 +187,14 @@ struct WaveLayout {
 WaveLayout wave_layout(const KernelShape &shape, int spill_given, int n_max, int lmax);
 }
 
+// Full records from the compact ones (cdf.hip), once per record set: every
+// consumer other than the FP32 walks of the wavefront kernel calls this first
+// (FP64 walks, the workgroup kernel, row features, pilot walks, downloads).
+// Synchronises the stream the first time, so that every stream sees them.
+namespace mcmi {
+hipError_t ensure_full_records(const mcmi_cdf *cdf, hipStream_t s);
+}
+
 // Device-memory cache (alloc.hip): dev_alloc reuses a block released on the
 // same stream (dev_release, stream-ordered) or released idle (dev_release_idle,
 // which synchronises the device first); otherwise it calls hipMalloc.
@@ -200,6 +208,7 @@ hipError_t build_locality_order(int64_t n, const int64_t *row_ptr, const int32_t
 }  // namespace mcmi
 
 // The opaque record set.
+#include <mutex>
 #include <vector>
 struct mcmi_cdf {
     int64_t n = 0;
@@ -209,8 +218,9 @@ struct mcmi_cdf {
     double drop_thr = 0.0;  // reduction cut on |c| (0: none)
     int64_t dropped = 0;    // entries of C removed by the reduction
     uint64_t rec_units = 0;
-    uint32_t *rec = nullptr;       // records, 16 words per unit
+    uint32_t *rec = nullptr;       // full records, 16 words per unit (built on first use)
     uint32_t *rec32 = nullptr;     // compact records, 8 words per unit (same offsets)
+    std::mutex full_lock;          // guards the first build of the full records
     uint32_t *roff = nullptr;      // n: record offset (64-byte units) of each row
     double *diag = nullptr;        // n: b_ii
     uint32_t *mrow = nullptr;      // n: entries of each row of C

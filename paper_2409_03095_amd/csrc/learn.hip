@@ -280,6 +280,8 @@ __global__ void __launch_bounds__(256) k_chain_cost(int64_t n, const float *__re
 }  // namespace
 
 hipError_t launch_features(const mcmi_cdf *cdf, double delta, int lmax, float *feat, hipStream_t s) {
+    const hipError_t fe = ensure_full_records(cdf, s);
+    if (fe != hipSuccess) return fe;
     int64_t blocks = (cdf->n + 3) / 4;
     if (blocks > 16384) blocks = 16384;
     k_features<<<(unsigned)blocks, 256, 0, s>>>(cdf->n, cdf->rec, cdf->roff, delta, lmax, feat);
@@ -344,6 +346,11 @@ extern "C" mcmi_status mcmi_pilot_variance(const mcmi_cdf *cdf, const mcmi_param
         sk = su = nullptr;
         sv = nullptr;
     };
+    // the pilot walks read the full records: build them before the arguments take their address
+    {
+        const hipError_t fe = ensure_full_records(cdf, s);
+        if (fe != hipSuccess) return fail(MCMI_ERR_HIP, std::string("mcmi_pilot_variance: ") + hipGetErrorString(fe));
+    }
     for (int attempt = 0; attempt < 6; ++attempt) {
         int bpc = 0;
         hipError_t e = pilot_occupancy(f32, H, cap, &bpc);

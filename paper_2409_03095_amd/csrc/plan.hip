@@ -263,6 +263,13 @@ extern "C" mcmi_status mcmi_plan_create(const mcmi_cdf *cdf, const mcmi_params *
     pl->shape.lanes = layout.lanes;
     const bool f32 = p->walk_prec == MCMI_WALK_F32;
     const bool block_kernel = pl->shape.lanes > 64;
+    if (block_kernel || !f32) {
+        const hipError_t fe = ensure_full_records(cdf, s);
+        if (fe != hipSuccess) {
+            delete pl;
+            return fail(MCMI_ERR_HIP, std::string("mcmi_plan_create: ") + hipGetErrorString(fe));
+        }
+    }
     const int waves = 4;
     int bpc = 0;
     hipError_t e = block_kernel ? walk_block_occupancy(f32, pl->shape.lanes, pl->shape.hash, pl->shape.sketch, &bpc)
