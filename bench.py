@@ -41,7 +41,14 @@ HBM_PEAK_GBS = 8000.0
 # HBM bytes per walk launch from rocprofv3 DRAM request counters, keyed by the
 # workload and kernel configuration they were measured on; None where no
 # measurement of the current kernel exists
-TRAFFIC_BYTES = {"aniso27": None, "random": None, "batched": None}
+TRAFFIC_BYTES = {
+    # FETCH_SIZE x 2.000 + WRITE_SIZE x 1.000 (the factors that make a plain 1 GiB
+    # device copy read 1 GiB), KiB -> bytes, one walk launch of the default
+    # configuration of each workload
+    "aniso27": (1.774e8 * 2.0 + 8.527e6) * 1024.0,
+    "random": (1.913e8 * 2.0 + 1.967e6) * 1024.0,
+    "batched": (2.389e8 * 2.0 + 5.799e7) * 1024.0,
+}
 # what a draw of the implemented sampler must read per transition: the alias
 # bucket's threshold and two targets (12 B) and the next state's header (row,
 # m, W, Shat32: 16 B), plus Shat64 (8 B) with FP64 weights
