@@ -19,7 +19,7 @@ bool walk_block_supported(int lanes, int hash_slots);
 hipError_t launch_walk_block(const WalkArgs &a, bool f32, int lanes, int blocks, hipStream_t s);
 hipError_t walk_block_occupancy(bool f32, int lanes, int hash_slots, int sketch_slots, int *bpc);
 hipError_t gather_rows(int64_t n_rows, const int64_t *row_start, const uint32_t *row_cnt, const int64_t *row_ptr,
-                       const PoolSet &pools, int32_t *col, double *val, hipStream_t s);
+                       const PoolSet &pools, int64_t cap, int32_t *col, double *val, hipStream_t s);
 hipError_t collect_failed(int64_t n_slots, const int64_t *row_start, const uint32_t *row_cnt, int32_t *list,
                           unsigned long long *ctr, hipStream_t s);
 hipError_t validate_rows(const int32_t *rows, int64_t n_rows, const int32_t *cpr, int64_t n, uint32_t *bad,
@@ -578,7 +578,7 @@ extern "C" mcmi_status mcmi_spai(const mcmi_cdf *cdf, const mcmi_params *p, cons
     }
     hipError_t ge = hipMemcpyAsync(rp, row_ptr.p, (size_t)(n_tasks + 1) * sizeof(int64_t), hipMemcpyDeviceToDevice, s);
     if (ge == hipSuccess)
-        ge = gather_rows(n_tasks, row_start.as<int64_t>(), row_cnt.as<uint32_t>(), rp, pools, col, val, s);
+        ge = gather_rows(n_tasks, row_start.as<int64_t>(), row_cnt.as<uint32_t>(), rp, pools, nnz, col, val, s);
     if (ge == hipSuccess) ge = hipEventRecord(ev3, s);
     if (ge == hipSuccess) ge = hipEventSynchronize(ev3);
     if (ge != hipSuccess) {

@@ -11,7 +11,10 @@
 // work captured in a hipGraph (counter reset kernel -> walk -> row-count scan ->
 // gather into fixed-capacity CSR buffers); each launch replays the graph with a
 // new seed. No memset node is recorded: counters are cleared by a kernel, and the
-// walk leaves its HBM overflow tables clean.
+// walk leaves its HBM overflow tables clean. The walk runs as the eager launch
+// does: the same task order (locality schedule, or LPT order on batched sets) and
+// wavefronts reserving output space kPlanChunk entries at a time in a pool of the
+// plan's own, sized for the caller's capacity plus those reservations.
 #include <string.h>
 
 #include <algorithm>
@@ -33,6 +36,8 @@ bool walk_block_supported(int lanes, int hash_slots);
 hipError_t launch_walk_block(const WalkArgs &a, bool f32, int lanes, int blocks, hipStream_t s);
 hipError_t walk_block_occupancy(bool f32, int lanes, int hash_slots, int sketch_slots, int *bpc);
 hipError_t batched_lpt_map(const mcmi_cdf *cdf, double delta, int lmax, int n_hint, int32_t *map, hipStream_t s);
+hipError_t gather_rows(int64_t n_rows, const int64_t *row_start, const uint32_t *row_cnt, const int64_t *row_ptr,
+                       const PoolSet &pools, int64_t cap, int32_t *col, double *val, hipStream_t s);
 
 namespace {
 
@@ -48,26 +53,9 @@ __global__ void k_set_keys(const uint64_t *seed, uint32_t *keys) {
     }
 }
 
-// Gather for plans: rows that could not be written (row_start < 0) and rows past
-// the output capacity are skipped (the result then reports an overflow).
-__global__ void __launch_bounds__(256) k_gather_capped(int64_t n_rows, const int64_t *row_start,
-                                                       const uint32_t *row_cnt, const int64_t *row_ptr,
-                                                       const int32_t *pool_col, const double *pool_val,
-                                                       int64_t cap, int32_t *col, double *val) {
-    const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
-    const int lane = threadIdx.x & 63;
-    const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
-    for (int64_t r = wave; r < n_rows; r += nwaves) {
-        const int64_t src = row_start[r], dst = row_ptr[r];
-        const uint32_t cnt = row_cnt[r];
-        if (src < 0 || dst + (int64_t)cnt > cap) continue;
-        const int64_t pos = src & (((int64_t)1 << kPoolShift) - 1);
-        for (uint32_t k = lane; k < cnt; k += 64) {
-            col[dst + k] = pool_col[pos + k];
-            val[dst + k] = pool_val[pos + k];
-        }
-    }
-}
+// entries a wavefront reserves in the plan's pool with one atomic (as the
+// eager launch's first pass does)
+constexpr int kPlanChunk = 2048;
 
 std::string tune_key(const mcmi_cdf *cdf, const mcmi_params *p, int lmax) {
     auto lg = [](double x) { return x > 0 ? (int)std::floor(std::log2(x)) : -1; };
@@ -286,6 +274,11 @@ extern "C" mcmi_status mcmi_plan_create(const mcmi_cdf *cdf, const mcmi_params *
     } else {
         if (blocks * waves > pl->n) blocks = std::max<int64_t>(1, (pl->n + waves - 1) / waves);
         regions = blocks * waves;
+        // chunked reservations leave the tail of each wavefront's last chunk and
+        // the ends of chunks too short for the next row unused: an eighth of the
+        // capacity plus one chunk per wavefront covers them (a pool that still
+        // runs out is reported as an overflow, like the output capacity)
+        pl->pool_cap = nnz_capacity + nnz_capacity / 8 + regions * kPlanChunk;
     }
     const int spill_slots = layout.spill_slots;
     const size_t ctrl_bytes = 128;
@@ -351,7 +344,7 @@ extern "C" mcmi_status mcmi_plan_create(const mcmi_cdf *cdf, const mcmi_params *
     a.pool_col = pl->pool_col;
     a.pool_val = pl->pool_val;
     a.pool_cap = pl->pool_cap;
-    a.pool_chunk = 0;
+    a.pool_chunk = block_kernel ? 0 : kPlanChunk;
     a.pool_used = (unsigned long long *)(ctrl + 32);
     a.spill_keys = pl->sk;
     a.spill_vals = pl->sv;
@@ -375,10 +368,12 @@ extern "C" mcmi_status mcmi_plan_create(const mcmi_cdf *cdf, const mcmi_params *
             ce = launch_walk(a, f32, (int)blocks, waves, cs);
         if (ce == hipSuccess)
             ce = scan_exclusive_u32_to_i64(pl->row_cnt, pl->row_ptr, pl->n, pl->row_ptr + pl->n, pl->scan_tmp, cs);
-        int64_t gb = (pl->n + 3) / 4;
-        if (gb > 65536) gb = 65536;
-        k_gather_capped<<<(unsigned)gb, 256, 0, cs>>>(pl->n, pl->row_start, pl->row_cnt, pl->row_ptr, pl->pool_col,
-                                                     pl->pool_val, pl->cap, pl->col, pl->val);
+        PoolSet pools;
+        memset(&pools, 0, sizeof(pools));
+        pools.col[0] = pl->pool_col;
+        pools.val[0] = pl->pool_val;
+        if (ce == hipSuccess)
+            ce = gather_rows(pl->n, pl->row_start, pl->row_cnt, pl->row_ptr, pools, pl->cap, pl->col, pl->val, cs);
         hipError_t ee = hipStreamEndCapture(cs, &pl->graph);
         if (ce == hipSuccess) ce = ee;
     }

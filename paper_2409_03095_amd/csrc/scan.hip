@@ -105,11 +105,14 @@ hipError_t scan_exclusive_u32_to_i64(const uint32_t *in, int64_t *out, int64_t n
 // ------------------------------------------------------------- assembly
 // Copy each row's survivors from its pool into the CSR arrays at row_ptr. One
 // wave per row, lanes over entries (coalesced). row_start holds the position in
-// the low 56 bits and the pool index above.
+// the low 56 bits and the pool index above. Rows without a pool position
+// (row_start < 0) and rows that would end past `cap` output entries are skipped
+// (captured plans report them as an overflow).
 __global__ void __launch_bounds__(256) k_gather_rows(int64_t n_rows, const int64_t *__restrict__ row_start,
                                                      const uint32_t *__restrict__ row_cnt,
                                                      const int64_t *__restrict__ row_ptr, PoolSet pools,
-                                                     int32_t *__restrict__ col, double *__restrict__ val) {
+                                                     int64_t cap, int32_t *__restrict__ col,
+                                                     double *__restrict__ val) {
     constexpr int U = 4;  // entries per lane in flight
     const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
     const int lane = threadIdx.x & 63;
@@ -117,9 +120,10 @@ __global__ void __launch_bounds__(256) k_gather_rows(int64_t n_rows, const int64
     constexpr int64_t kPosMask = ((int64_t)1 << kPoolShift) - 1;
     for (int64_t r = wave; r < n_rows; r += nwaves) {
         const int64_t tagged = row_start[r], dst = row_ptr[r];
+        const uint32_t cnt = row_cnt[r];
+        if (tagged < 0 || dst + (int64_t)cnt > cap) continue;
         const int pool = (int)(tagged >> kPoolShift);
         const int64_t src = tagged & kPosMask;
-        const uint32_t cnt = row_cnt[r];
         const int32_t *__restrict__ pc = pools.col[pool] + src;
         const double *__restrict__ pv = pools.val[pool] + src;
         for (uint32_t k0 = lane; k0 < cnt; k0 += 64 * U) {
@@ -142,11 +146,11 @@ __global__ void __launch_bounds__(256) k_gather_rows(int64_t n_rows, const int64
 }
 
 hipError_t gather_rows(int64_t n_rows, const int64_t *row_start, const uint32_t *row_cnt, const int64_t *row_ptr,
-                       const PoolSet &pools, int32_t *col, double *val, hipStream_t s) {
+                       const PoolSet &pools, int64_t cap, int32_t *col, double *val, hipStream_t s) {
     if (n_rows <= 0) return hipSuccess;
     int64_t blocks = (n_rows + 3) / 4;
     if (blocks > 65536) blocks = 65536;
-    k_gather_rows<<<(unsigned)blocks, 256, 0, s>>>(n_rows, row_start, row_cnt, row_ptr, pools, col, val);
+    k_gather_rows<<<(unsigned)blocks, 256, 0, s>>>(n_rows, row_start, row_cnt, row_ptr, pools, cap, col, val);
     return hipGetLastError();
 }
 
