@@ -439,7 +439,8 @@ def aniso_main(args):
                       "n": B.n, "nnz_B": B.nnz,
                       "chains_per_row": chains, "transitions_per_step": int(st.transitions), "nnz_M": int(last.nnz),
                       "lanes_per_row": st.lanes_per_row, "hash_slots": st.hash_slots, "spilled": int(st.spilled),
-                      "retries": int(st.retries), "record_bytes": int(rec["units"]) * 64, "order_cell": cell},
+                      "retries": int(st.retries), "record_bytes": int(rec["units"]) * (32 if args.prec == 32 else 64),
+                      "order_cell": cell},
            "roofline": roofline_of(bpt, st.transitions, walk_s, args.prec, traffic, "k_walk")}
     if net is not None:
         # quality at the same budget: learned vs uniform chains, 10^4-row sample
@@ -449,7 +450,10 @@ def aniso_main(args):
         ql = L.evaluate(B, cpr, delta, eps, 0, rows, args.prec, cdf)
         qu = L.evaluate(B, torch.full((B.n,), chains, dtype=torch.int32, device="cuda"), delta, eps, 0, rows,
                         args.prec, cdf)
+        cq = np.percentile(cpr.cpu().numpy(), [10, 50, 90])
         alloc.update({"chains_min": int(cpr.min().item()), "chains_max": int(cpr.max().item()),
+                      "chains_p10_p50_p90": [float(v) for v in cq],
+                      "rows_over_64_chains": float((cpr > 64).float().mean().item()),
                       "learned": ql, "uniform": qu})
         out["config"]["allocation"] = "learned"
         out["learned_allocation"] = alloc

@@ -175,18 +175,20 @@ def test_rows_subset_and_per_row_chains(mc):
         compare_spai((rp, col, val), orc, o.diag, cpr, rows=rows)
 
 
-@pytest.mark.parametrize("case", ["random_spill", "cfg1", "aniso_f32", "shared_wave", "two_per_lane"])
+@pytest.mark.parametrize("case", ["random_spill", "cfg1", "aniso_f32", "shared_wave", "two_per_lane", "refill_per_row"])
 def test_wavefront_kernel_reruns_bit_identical(mc, case):
     """The wavefront kernel is deterministic: a row's chains run in one
     wavefront, whose LDS and HBM-table additions follow its instruction stream,
     so a rerun with the same seed gives the same bits (random rows with spills to
     HBM, the 32x32 grid, the 27-point stencil with FP32 walks, rows sharing a
-    wavefront, two chains per lane)."""
+    wavefront, two chains per lane, per-row chain counts of 23 to 77)."""
     B, kw = {"random_spill": (lambda: I.random_nonsym(5000, seed=13), dict(chains=64, hash_slots=128)),
              "cfg1": (I.cfg1, dict(chains=500, lanes_per_row=64)),
              "aniso_f32": (lambda: I.aniso27(14, seed=3), dict(chains=64, prec=32)),
              "shared_wave": (lambda: I.aniso27(10, seed=4), dict(chains=12, lanes_per_row=16)),
-             "two_per_lane": (lambda: I.aniso27(10, seed=4), dict(chains=100))}[case]
+             "two_per_lane": (lambda: I.aniso27(10, seed=4), dict(chains=100)),
+             "refill_per_row": (lambda: I.aniso27(10, seed=4), dict(chains=1, chains_per_row=np.random.default_rng(
+                 3).integers(23, 78, size=1000).astype(np.int32)))}[case]
     B = B()
     a, ra, _ = run(mc, B, seed=1, delta=1e-4, eps=1e-3, **kw)
     b, rb, _ = run(mc, B, seed=1, delta=1e-4, eps=1e-3, **kw)
@@ -522,16 +524,32 @@ def test_shared_wavefronts_with_per_row_chains_and_forced_widths(mc):
 
 # ------------------------------------- two chains in flight per lane (a4-a6)
 @pytest.mark.parametrize("prec", [64, 32])
-@pytest.mark.parametrize("chains", [65, 100, 128, 160])
+@pytest.mark.parametrize("chains", [65, 80, 100, 128, 160])
 def test_two_chains_per_lane_match_oracle(mc, chains, prec):
     """One row per wavefront with more chains than lanes: each lane keeps two of
-    the row's chains in flight; the estimate equals the oracle's."""
+    the row's chains in flight (past 128 chains a lane whose chain stops starts the
+    one 128 further on); the estimate equals the oracle's."""
     B = I.random_nonsym(2000, seed=73)
     (rp, col, val), res, _ = run(mc, B, seed=6, chains=chains, delta=1e-4, eps=1e-3, prec=prec)
     assert res.stats.lanes_per_row == 64
     orc, o = oracle_run(B, seed=6, chains=chains, delta=1e-4, eps=1e-3, prec=prec)
     assert orc["guard"] == 0 and res.stats.transitions == orc["transitions"]
     compare_spai((rp, col, val), orc, o.diag, chains)
+
+
+def test_one_chain_per_lane_with_per_row_chains(mc):
+    """Per-row chain counts of 23 to 77 (the range a learned allocation gives on
+    the 27-point stencil; mean 50, so one chain in flight per lane): a lane whose
+    chain stops starts the row's chain 64 further on; equal to the oracle's
+    estimate, transitions exact."""
+    B = I.aniso27(12, seed=4)
+    cpr = np.random.default_rng(15).integers(23, 78, size=B.n).astype(np.int32)
+    for prec in (32, 64):
+        (rp, col, val), res, _ = run(mc, B, seed=9, chains=1, delta=1e-4, eps=1e-3, prec=prec, chains_per_row=cpr)
+        assert res.stats.lanes_per_row == 64
+        orc, o = oracle_run(B, seed=9, chains=1, delta=1e-4, eps=1e-3, prec=prec, chains_per_row=cpr)
+        assert orc["guard"] == 0 and res.stats.transitions == orc["transitions"]
+        compare_spai((rp, col, val), orc, o.diag, cpr)
 
 
 def test_two_chains_per_lane_with_per_row_chains(mc):
