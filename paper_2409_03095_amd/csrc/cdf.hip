@@ -207,8 +207,10 @@ __global__ void __launch_bounds__(256) k_count(int64_t n, int64_t nnz, const int
     }
 }
 
-// Write each row's header and its sorted {cum, target} nodes into `sorted`
-// (C-row order, at cptr[r]), and the row's record offset as 32 bits.
+// Write each row's header and its sorted {cum, target row} nodes into `sorted`
+// (C-row order, at cptr[r]; the target's sign bit set for a negative c), the
+// row's record offset as 32 bits, and {offset, m, Shat32} into the dense per-row
+// table `tinfo` (what a bucket copies of its targets).
 template <int G>
 __global__ void __launch_bounds__(256) k_fill(int64_t n, const int64_t *__restrict__ rp,
                                               const int32_t *__restrict__ ci, const double *__restrict__ v,
@@ -216,7 +218,7 @@ __global__ void __launch_bounds__(256) k_fill(int64_t n, const int64_t *__restri
                                               const int64_t *__restrict__ roff64, const int64_t *__restrict__ cptr,
                                               const unsigned long long *__restrict__ cut,
                                               uint32_t *__restrict__ roff32, uint32_t *__restrict__ rec32,
-                                              uint2 *__restrict__ sorted,
+                                              uint2 *__restrict__ sorted, uint4 *__restrict__ tinfo,
                                               unsigned long long *__restrict__ norm_bits) {
     const Group<G> g;
     const int sub = g.sub;
@@ -232,6 +234,7 @@ __global__ void __launch_bounds__(256) k_fill(int64_t n, const int64_t *__restri
         if (sub == 0) roff32[r] = off;
         if (m == 0) {
             if (sub == 0) {
+                tinfo[r] = make_uint4(off, 0u, __float_as_uint(0.0f), 0u);
                 *(uint4 *)hdc = make_uint4((uint32_t)r, 0u, 0u, __float_as_uint(0.0f));
                 *(double2 *)(hdc + 4) = make_double2(0.0, d);
             }
@@ -264,7 +267,7 @@ __global__ void __launch_bounds__(256) k_fill(int64_t n, const int64_t *__restri
                         valid = true;
                         const double scaled = floor(ldexp(fabs(cv) / amax, q));
                         w = scaled < 1.0 ? 1u : (uint32_t)scaled;
-                        tgt = (uint32_t)roff64[c] | (cv < 0.0 ? kSignBit : 0u);
+                        tgt = (uint32_t)c | (cv < 0.0 ? kSignBit : 0u);
                     }
                 }
             }
@@ -279,6 +282,7 @@ __global__ void __launch_bounds__(256) k_fill(int64_t n, const int64_t *__restri
         }
         if (sub == 0) {
             const double shat = ldexp(amax * (double)carry, -q);
+            tinfo[r] = make_uint4(off, m, __float_as_uint((float)shat), 0u);
             *(uint4 *)hdc = make_uint4((uint32_t)r, m, carry, __float_as_uint((float)shat));
             *(double2 *)(hdc + 4) = make_double2(shat, d);
             best = shat > best ? shat : best;
@@ -443,13 +447,16 @@ __global__ void __launch_bounds__(256) k_expand_buckets(int64_t n, const uint32_
 
 // The compact buckets (8 words each, see common.hpp): a wave takes 64
 // consecutive rows as in k_expand_buckets, two lanes per bucket (its own half, its alias
-// half) and 32 buckets per pass; the targets' m and Shat32 come from the compact
-// header units written by k_fill.
+// half) and 32 buckets per pass; the targets' record offsets, m and Shat32 come
+// from the dense per-row table k_fill writes (16 bytes a row, so that neighbouring
+// targets share cache lines, which their header units spread over the records
+// do not).
 __global__ void __launch_bounds__(256) k_buckets32(int64_t n, const uint32_t *__restrict__ mrow,
                                                    const uint32_t *__restrict__ roff32,
                                                    const int64_t *__restrict__ cptr, const uint2 *__restrict__ sorted,
                                                    const uint32_t *__restrict__ thr_g,
-                                                   const int32_t *__restrict__ ali_g, uint32_t *__restrict__ rec32) {
+                                                   const int32_t *__restrict__ ali_g, const uint4 *__restrict__ tinfo,
+                                                   uint32_t *__restrict__ rec32) {
     __shared__ uint32_t pm_s[4][65];
     __shared__ int64_t pb_s[4][64];
     __shared__ uint32_t po_s[4][64];
@@ -490,8 +497,9 @@ __global__ void __launch_bounds__(256) k_buckets32(int64_t n, const uint32_t *__
                 const uint32_t W = sorted[pb[i] + pm[i + 1] - pm[i] - 1].x;
                 const uint32_t T = thr_g[e];
                 const bool full = T >= W;  // no alias: both halves lead to target_j
-                const uint32_t tgt = (half == 0 || full) ? own.y : sorted[pb[i] + ali_g[e]].y;
-                const uint4 th = *(const uint4 *)(rec32 + (size_t)(tgt & ~kSignBit) * kUnitWords32);
+                const uint32_t trow = (half == 0 || full) ? own.y : sorted[pb[i] + ali_g[e]].y;
+                const uint4 ti = tinfo[trow & ~kSignBit];
+                const uint32_t tgt = ti.x | (trow & kSignBit);
                 uint32_t first;
                 if (half == 0) {
                     // T' = ceil(T 2^32 / W) (< 2^32 when T < W)
@@ -500,7 +508,7 @@ __global__ void __launch_bounds__(256) k_buckets32(int64_t n, const uint32_t *__
                     const uint32_t prev = k > 0 ? sorted[e - 1].x : 0u;
                     first = own.x - prev;  // w_j
                 }
-                v[j] = make_uint4(first, tgt, th.y, th.w);
+                v[j] = make_uint4(first, tgt, ti.y, ti.z);
                 dst[j] = ((size_t)po[i] + 1u + k) * kUnitWords32 + (size_t)half * 4u;
             }
 #pragma unroll
@@ -583,6 +591,7 @@ extern "C" mcmi_status mcmi_build_cdf_ex(const mcmi_csr_in *B, const mcmi_cdf_op
     unsigned long long *norm_bits = nullptr;
     void *tmp = nullptr;
     uint2 *sorted = nullptr;
+    uint4 *tinfo = nullptr;
     uint32_t *qs = nullptr;
     int32_t *stk = nullptr;
     unsigned long long *cut_keys = nullptr, *sel = nullptr;
@@ -590,7 +599,8 @@ extern "C" mcmi_status mcmi_build_cdf_ex(const mcmi_csr_in *B, const mcmi_cdf_op
     auto cleanup = [&]() {
         // temporaries are stream-ordered: released behind the last kernel that uses them
         for (void *t : {(void *)cut_keys, (void *)sel, (void *)units, (void *)flags, (void *)roff64, (void *)cptr,
-                        (void *)totals, (void *)norm_bits, tmp, (void *)sorted, (void *)qs, (void *)stk})
+                        (void *)totals, (void *)norm_bits, tmp, (void *)sorted, (void *)tinfo, (void *)qs,
+                        (void *)stk})
             if (t) dev_release(t, s);
     };
     auto bail = [&](mcmi_status code, const std::string &msg) {
@@ -690,15 +700,16 @@ extern "C" mcmi_status mcmi_build_cdf_ex(const mcmi_csr_in *B, const mcmi_cdf_op
     cdf->nnz_c = htot[1];
     TRY(dev_alloc((void **)&cdf->rec32, (size_t)htot[0] * kUnitWords32 * 4u + 32u, s));
     TRY(dev_alloc((void **)&sorted, (size_t)(htot[1] > 0 ? htot[1] : 1) * sizeof(uint2), s));
+    TRY(dev_alloc((void **)&tinfo, (size_t)n * sizeof(uint4), s));
     if (lanes == 16)
         k_fill<16><<<grid, 256, 0, s>>>(n, B->row_ptr_dev, B->col_dev, B->val_dev, cdf->diag, cdf->mrow, roff64, cptr,
-                                        cut, cdf->roff, cdf->rec32, sorted, norm_bits);
+                                        cut, cdf->roff, cdf->rec32, sorted, tinfo, norm_bits);
     else if (lanes == 32)
         k_fill<32><<<grid, 256, 0, s>>>(n, B->row_ptr_dev, B->col_dev, B->val_dev, cdf->diag, cdf->mrow, roff64, cptr,
-                                        cut, cdf->roff, cdf->rec32, sorted, norm_bits);
+                                        cut, cdf->roff, cdf->rec32, sorted, tinfo, norm_bits);
     else
         k_fill<64><<<grid, 256, 0, s>>>(n, B->row_ptr_dev, B->col_dev, B->val_dev, cdf->diag, cdf->mrow, roff64, cptr,
-                                        cut, cdf->roff, cdf->rec32, sorted, norm_bits);
+                                        cut, cdf->roff, cdf->rec32, sorted, tinfo, norm_bits);
     TRY(hipGetLastError());
     TRY(dev_alloc((void **)&qs, (size_t)(htot[1] > 0 ? htot[1] : 1) * sizeof(uint32_t), s));
     TRY(dev_alloc((void **)&stk, (size_t)(htot[1] > 0 ? 2 * htot[1] : 2) * sizeof(int32_t), s));
@@ -710,7 +721,7 @@ extern "C" mcmi_status mcmi_build_cdf_ex(const mcmi_csr_in *B, const mcmi_cdf_op
         TRY(hipGetLastError());
         int64_t bb = (n + 255) / 256;
         if (bb > 16384) bb = 16384;
-        k_buckets32<<<(unsigned)bb, 256, 0, s>>>(n, cdf->mrow, cdf->roff, cptr, sorted, qs, ali, cdf->rec32);
+        k_buckets32<<<(unsigned)bb, 256, 0, s>>>(n, cdf->mrow, cdf->roff, cptr, sorted, qs, ali, tinfo, cdf->rec32);
     }
     TRY(hipGetLastError());
     unsigned long long hnorm = 0;
