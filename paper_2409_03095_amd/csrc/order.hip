@@ -20,6 +20,7 @@ namespace {
 
 constexpr uint32_t kUnset = 0xFFFFFFFFu;
 constexpr int kMaxGrow = 64;
+constexpr int kGrowBatch = 16;
 
 __device__ __forceinline__ uint32_t mix32(uint32_t x) {
     // MurmurHash3's 32-bit finaliser
@@ -117,15 +118,23 @@ hipError_t build_locality_order(int64_t n, const int64_t *row_ptr, const int32_t
         const uint32_t thr = p >= 1.0 ? 0xFFFFFFFFu : (uint32_t)(p * 4294967296.0);
         k_seed<<<grid_rows(n, 1, 65536), 256, 0, s>>>(n, thr, lab0, changed);
         e = hipGetLastError();
+        // levels go out kGrowBatch at a time; the search stops after a batch whose
+        // last level labelled nothing (a level after the first empty one returns at
+        // once, and the empty one copied the final labels into both buffers)
         for (int level = 0; e == hipSuccess && level < kMaxGrow; ++level) {
             const bool even = (level & 1) == 0;
-            // a modest grid: the levels after the last one that labels a row return at once
             k_grow<<<grid_rows(n, 8, 4096), 256, 0, s>>>(n, row_ptr, col, even ? lab0 : lab1, even ? lab1 : lab0, changed,
                                                    level);
             e = hipGetLastError();
+            if (e == hipSuccess && (level + 1) % kGrowBatch == 0 && level + 1 < kMaxGrow) {
+                uint32_t last = 1u;
+                e = hipMemcpyAsync(&last, changed + level, sizeof(last), hipMemcpyDeviceToHost, s);
+                if (e == hipSuccess) e = hipStreamSynchronize(s);
+                if (e == hipSuccess && last == 0u) break;
+            }
         }
     }
-    // kMaxGrow is even: the last level that can run writes lab0
+    // kMaxGrow and kGrowBatch are even: the last level that runs writes lab0
     if (e == hipSuccess) {
         k_order_keys<<<grid_rows(n, 1, 65536), 256, 0, s>>>(n, lab0, idx);
         e = hipGetLastError();
