@@ -49,6 +49,20 @@ TRAFFIC_BYTES = {
     "random": (1.913e8 * 2.0 + 1.967e6) * 1024.0,
     "batched": (2.389e8 * 2.0 + 5.799e7) * 1024.0,
 }
+# Instruction issue of the 160^3 walk (k_walk<true, 64, 1, true>) from rocprofv3 SQ
+# counters of one launch (wave-summed quad cycles over SQ_WAVE_CYCLES = 1.2108e11,
+# 3072 waves, 3 per SIMD, the LDS tables allowing no more): the walk is bound by
+# each wave's issue and waits, not by HBM (with every bucket read served from a
+# 128 MB region the walk was not faster per transition)
+ISSUE = {
+    "aniso27": {"waves_per_simd": 3, "valu_busy_per_simd": round(2.1811e10 / 1.2108e11 * 3, 3),
+                "salu_busy_per_simd": round(1.6866e10 / 1.2108e11 * 3, 3),
+                "wave_issuing": round(4.9478e10 / 1.2108e11, 3), "wave_waiting_on_memory_or_lds": round(
+                    6.0313e10 / 1.2108e11, 3), "valu_insts_per_transition": 3.29, "salu_insts_per_transition": 2.55,
+                "lds_insts_per_transition": 0.41,
+                "counters": "SQ_ACTIVE_INST_VALU, SQ_ACTIVE_INST_SCA, SQ_ACTIVE_INST_ANY, SQ_WAIT_ANY, "
+                            "SQ_WAVE_CYCLES, SQ_INSTS_VALU, SQ_INSTS_SALU, SQ_INSTS_LDS"},
+}
 # what a draw of the implemented sampler must read per transition: the alias
 # bucket's threshold and two targets (12 B) and the next state's header (row,
 # m, W, Shat32: 16 B), plus Shat64 (8 B) with FP64 weights
@@ -66,10 +80,10 @@ def algorithmic_bytes_per_transition(B, fp32: bool) -> float:
     return float(np.mean((16.0 if fp32 else 24.0) + 4.0 * probes + 4.0))
 
 
-def roofline_of(bpt, transitions, walk_s, prec, traffic, kernel):
+def roofline_of(bpt, transitions, walk_s, prec, traffic, kernel, issue=None):
     achieved = bpt * transitions / walk_s / 1e9
     impl = IMPLEMENTED_DRAW_BYTES[prec] * transitions / walk_s / 1e9
-    return {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+    out = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic, "kernel": kernel,
             "bytes_per_transition": round(bpt, 2),
             "bytes_basis": "header 16 B + (ceil(log2 m)+1) x 4 B CDF probes + 4 B target"
@@ -77,6 +91,9 @@ def roofline_of(bpt, transitions, walk_s, prec, traffic, kernel):
             "implemented_draw": {"bytes_per_transition": IMPLEMENTED_DRAW_BYTES[prec], "achieved": round(impl, 1),
                                  "frac": round(impl / HBM_PEAK_GBS, 4)},
             "walk_ms": round(walk_s * 1e3, 3), "walk_transitions_per_s": transitions / walk_s}
+    if issue is not None:
+        out["issue"] = issue
+    return out
 
 
 def gather_probe(units, reqs_per_step=1, steps=256, waves_per_cu=16, loads_per_req=1, mode=0):
@@ -441,7 +458,8 @@ def aniso_main(args):
                       "lanes_per_row": st.lanes_per_row, "hash_slots": st.hash_slots, "spilled": int(st.spilled),
                       "retries": int(st.retries), "record_bytes": int(rec["units"]) * (32 if args.prec == 32 else 64),
                       "order_cell": cell},
-           "roofline": roofline_of(bpt, st.transitions, walk_s, args.prec, traffic, "k_walk")}
+           "roofline": roofline_of(bpt, st.transitions, walk_s, args.prec, traffic, "k_walk",
+                                   ISSUE["aniso27"] if traffic is not None else None)}
     if net is not None:
         # quality at the same budget: learned vs uniform chains, 10^4-row sample
         cdf = mcmi.Cdf(dB, order_cell=cell)
