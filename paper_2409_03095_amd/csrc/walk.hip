@@ -103,11 +103,14 @@ struct ChainSt {
     float w32;
     StepHdr H;
     u32x4 blk;
+    int32_t pk[4];  // the home bucket of the next contribution's key, read ahead
+    uint32_t pb;
 };
 
 // One step of a chain: stop (and start the lane's next chain of the row, `stride`
 // further on) or draw the next state, and add the current state's weight (j > 0).
-// The next bucket's loads go out first; the weight's accumulation and the Philox
+// The next bucket's loads go out first; the weight's accumulation (from the copy of
+// its key's home bucket read at the end of the previous step) and the Philox
 // block of the next four steps run while they are in flight. `blk` holds the
 // words of the chain's next draws (step j + 1 takes word j mod 4 of block j / 4).
 template <bool kF32, bool kCmp>
@@ -144,7 +147,7 @@ __device__ __forceinline__ void chain_step(const WalkArgs &a, ChainSt &ch, int s
     }
     if (ch.j > 0) {
         const int32_t key = (int32_t)h.x;  // the row, or its compact record offset
-        if (!lds_add<true>(gkeys, gvals, hmask, hash_key(key, hshift), key, wcur)) {
+        if (!lds_add_pre(gkeys, gvals, hmask, ch.pb, ch.pk, key, wcur)) {
             ++spilled;
             if (!spill_add_window(gskeys, gsvals, gsused, gspill, smask, key, wcur)) spill_full = true;
         }
@@ -173,6 +176,10 @@ __device__ __forceinline__ void chain_step(const WalkArgs &a, ChainSt &ch, int s
         ch.off = tgt & ~kSignBit;
         ch.H = Nx;
         ++ch.j;
+        // the next step adds this state's weight: its key's home bucket is read
+        // now, so that the read has a whole bucket load's latency to complete
+        ch.pb = hash_key((int32_t)Nx.h0.x, hshift) & ~3u;
+        read_bucket_wave(gkeys, ch.pb, ch.pk);
     }
 }
 
@@ -340,75 +347,102 @@ __device__ __forceinline__ void walk_rows(const WalkArgs &a, const RowPre &cur, 
         // header unit, loaded together), N_rc = acc / N, and without top-k at once
         // M_rc = N_rc / d_c; four entries per lane in flight
         const bool scale_now = a.topk <= 0;
-        for (int i0 = lane; i0 < K; i0 += 256) {
-            int32_t rw[4];
-            double d[4];
+        // Compact records: record offsets order like the rows they start, so the
+        // survivors (up to 256, no top-k) are sorted by their keys while the loads
+        // of their rows and d_c are in flight; the rows and M_rc = (acc / N) / d_c
+        // replace the keys and sums after the sort.
+        int PS0 = 1;
+        while (PS0 < K) PS0 <<= 1;
+        const bool early = kCmp && scale_now && K <= 256 && K + PS0 <= Hg;
+        int32_t erw[4];
+        double ed[4];
 #pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                const int i = i0 + 64 * q;
-                rw[q] = i < K ? tk[i] : 0;
-                d[q] = 1.0;
-                if (i < K) {
-                    if (kCmp) {
-                        const uint32_t *h = a.rec32 + (size_t)(uint32_t)rw[q] * kUnitWords32;
-                        rw[q] = (int32_t)h[0];
-                        if (scale_now) d[q] = *(const double *)(h + 6);
-                    } else if (scale_now) {
-                        d[q] = a.diag[rw[q]];
-                    }
-                }
-            }
-#pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                const int i = i0 + 64 * q;
-                if (i < K) {
-                    const double nhat = tv[i] / nd;
-                    tk[i] = rw[q];
-                    tv[i] = scale_now ? nhat / d[q] : nhat;
-                }
-            }
+        for (int q = 0; q < 4; ++q) {
+            erw[q] = 0;
+            ed[q] = 1.0;
         }
-        wave_sync();
-
-        // top-k retention: bitonic sort in retention order, keep the first topk,
-        // then turn N_rc into M_rc = N_rc / d_c
-        if (!scale_now) {
-            if (K > a.topk) {
-                int PT = 1;
-                while (PT < K) PT <<= 1;
-                for (int s = K + lane; s < PT; s += 64) tk[s] = INT32_MAX;
-                wave_sync();
-                for (int k = 2; k <= PT; k <<= 1) {
-                    for (int jj = k >> 1; jj > 0; jj >>= 1) {
-                        for (int pr = lane; pr < (PT >> 1); pr += 64) {
-                            const int i = ((pr & ~(jj - 1)) << 1) | (pr & (jj - 1));
-                            const int ixj = i | jj;
-                            const int32_t ka = tk[i], kb = tk[ixj];
-                            const double va = tv[i], vb = tv[ixj];
-                            if (top_after(a, rg, ka, va, kb, vb) == ((i & k) == 0)) {
-                                tk[i] = kb;
-                                tk[ixj] = ka;
-                                tv[i] = vb;
-                                tv[ixj] = va;
-                            }
-                        }
-                        wave_sync();
-                    }
+        if (early) {
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int i = lane + 64 * q;
+                if (i < K) {
+                    const uint32_t *h = a.rec32 + (size_t)(uint32_t)tk[i] * kUnitWords32;
+                    erw[q] = (int32_t)h[0];
+                    ed[q] = *(const double *)(h + 6);
                 }
-                K = a.topk;
             }
+        } else {
             for (int i0 = lane; i0 < K; i0 += 256) {
+                int32_t rw[4];
                 double d[4];
 #pragma unroll
-                for (int q = 0; q < 4; ++q) d[q] = i0 + 64 * q < K ? a.diag[tk[i0 + 64 * q]] : 1.0;
+                for (int q = 0; q < 4; ++q) {
+                    const int i = i0 + 64 * q;
+                    rw[q] = i < K ? tk[i] : 0;
+                    d[q] = 1.0;
+                    if (i < K) {
+                        if (kCmp) {
+                            const uint32_t *h = a.rec32 + (size_t)(uint32_t)rw[q] * kUnitWords32;
+                            rw[q] = (int32_t)h[0];
+                            if (scale_now) d[q] = *(const double *)(h + 6);
+                        } else if (scale_now) {
+                            d[q] = a.diag[rw[q]];
+                        }
+                    }
+                }
 #pragma unroll
-                for (int q = 0; q < 4; ++q)
-                    if (i0 + 64 * q < K) tv[i0 + 64 * q] = tv[i0 + 64 * q] / d[q];
+                for (int q = 0; q < 4; ++q) {
+                    const int i = i0 + 64 * q;
+                    if (i < K) {
+                        const double nhat = tv[i] / nd;
+                        tk[i] = rw[q];
+                        tv[i] = scale_now ? nhat / d[q] : nhat;
+                    }
+                }
             }
             wave_sync();
+
+            // top-k retention: bitonic sort in retention order, keep the first topk,
+            // then turn N_rc into M_rc = N_rc / d_c
+            if (!scale_now) {
+                if (K > a.topk) {
+                    int PT = 1;
+                    while (PT < K) PT <<= 1;
+                    for (int s = K + lane; s < PT; s += 64) tk[s] = INT32_MAX;
+                    wave_sync();
+                    for (int k = 2; k <= PT; k <<= 1) {
+                        for (int jj = k >> 1; jj > 0; jj >>= 1) {
+                            for (int pr = lane; pr < (PT >> 1); pr += 64) {
+                                const int i = ((pr & ~(jj - 1)) << 1) | (pr & (jj - 1));
+                                const int ixj = i | jj;
+                                const int32_t ka = tk[i], kb = tk[ixj];
+                                const double va = tv[i], vb = tv[ixj];
+                                if (top_after(a, rg, ka, va, kb, vb) == ((i & k) == 0)) {
+                                    tk[i] = kb;
+                                    tk[ixj] = ka;
+                                    tv[i] = vb;
+                                    tv[ixj] = va;
+                                }
+                            }
+                            wave_sync();
+                        }
+                    }
+                    K = a.topk;
+                }
+                for (int i0 = lane; i0 < K; i0 += 256) {
+                    double d[4];
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) d[q] = i0 + 64 * q < K ? a.diag[tk[i0 + 64 * q]] : 1.0;
+#pragma unroll
+                    for (int q = 0; q < 4; ++q)
+                        if (i0 + 64 * q < K) tv[i0 + 64 * q] = tv[i0 + 64 * q] / d[q];
+                }
+                wave_sync();
+            }
         }
 
-        // Bitonic sort by column. A pass has PS / 2 compare-exchange pairs, pair p
+        // Bitonic sort by column (on the early path by record offset, which orders
+        // the same way). A pass has PS / 2 compare-exchange pairs, pair p
         // joining i (p with a zero bit inserted at jj) and i | jj, so every lane has a
         // pair. When the value slots past the survivors have room, the sort moves
         // one word per entry, (column << 13) | position, in that free part of the
@@ -458,6 +492,19 @@ __device__ __forceinline__ void walk_rows(const WalkArgs &a, const RowPre &cur, 
             }
         }
 
+        if (early) {
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int i = lane + 64 * q;
+                if (i < K) {
+                    const double nhat = tv[i] / nd;
+                    tk[i] = erw[q];
+                    tv[i] = nhat / ed[q];
+                }
+            }
+            wave_sync();
+        }
+
         // append to the pool unless a table overflowed for this row (then it is rerun)
         const bool row_spill_full = __any(spill_full && grp == g);
         const bool row_stage_full = __any(stage_full);
@@ -483,7 +530,7 @@ __device__ __forceinline__ void walk_rows(const WalkArgs &a, const RowPre &cur, 
             for (int i = lane; i < K; i += 64) {
                 if (packed) {
                     const uint64_t e = pk[i];
-                    a.pool_col[pos0 + i] = (int32_t)(e >> 13);
+                    a.pool_col[pos0 + i] = tk[e & 8191u];
                     a.pool_val[pos0 + i] = tv[e & 8191u];
                 } else {
                     a.pool_col[pos0 + i] = tk[i];

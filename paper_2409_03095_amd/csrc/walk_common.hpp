@@ -52,6 +52,48 @@ __device__ __forceinline__ void scan_bucket(const int32_t k[4], int32_t key, int
     }
 }
 
+// lds_add for a table one wavefront owns, whose bucket b0 (the key's home bucket)
+// was read into kp earlier, while the previous step's bucket load was in flight.
+// A copy that has gone stale is safe: keys never move, slots fill lowest first,
+// so a key missing from the copy is either absent or in a slot the copy shows
+// empty, and the compare-and-swap of the copy's first empty slot then reports it.
+__device__ __forceinline__ bool lds_add_pre(int32_t *keys, double *vals, uint32_t mask, uint32_t b0,
+                                            const int32_t kp[4], int32_t key, double w) {
+    uint32_t b = b0;
+    int nb = 0;
+    bool first = true;
+    while (nb < kMaxLdsProbe / 4) {
+        int32_t k[4];
+        if (first) {
+            k[0] = kp[0];
+            k[1] = kp[1];
+            k[2] = kp[2];
+            k[3] = kp[3];
+        } else {
+            read_bucket_wave(keys, b, k);
+        }
+        first = false;
+        int hit, emp;
+        scan_bucket(k, key, hit, emp);
+        if (hit >= 0) {
+            atomicAdd(&vals[b + hit], w);
+            return true;
+        }
+        if (emp < 0) {
+            b = (b + 4u) & mask;
+            ++nb;
+            continue;
+        }
+        const int32_t prev = atomicCAS(&keys[b + emp], kEmpty, key);
+        if (prev == kEmpty || prev == key) {
+            atomicAdd(&vals[b + emp], w);
+            return true;
+        }
+        // another key took the slot: read the bucket again
+    }
+    return false;
+}
+
 // Adds w to key's slot, inserting the key if absent; false when the kMaxLdsProbe
 // slots from the key's bucket on are all held by other keys.
 // kWave: the table belongs to one wavefront (16-byte bucket reads)
