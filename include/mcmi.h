@@ -372,9 +372,10 @@ mcmi_status mcmi_tune(const mcmi_cdf *cdf, const mcmi_params *base, int64_t samp
  * rows' reach as mcmi_spai does, and walks a batched record set in the eager
  * launch's longest-processing-time order. Besides the output (nnz_capacity
  * entries) a plan of the wavefront kernel holds a staging pool of nnz_capacity
- * * 9/8 + 2048 entries per wavefront of its grid (12 bytes each), in which
- * wavefronts reserve space 2048 entries at a time; a pool that runs out is
- * reported as an overflow. */
+ * * 9/8 + c entries per wavefront of its grid (12 bytes each), in which
+ * wavefronts reserve space c entries at a time, c = nnz_capacity / (4 x the
+ * wavefronts) clamped to [256, 32768]; a pool that runs out is reported as an
+ * overflow. */
 typedef struct mcmi_plan mcmi_plan;
 mcmi_status mcmi_plan_create(const mcmi_cdf *cdf, const mcmi_params *p, const int32_t *chains_per_row_dev,
                              int64_t nnz_capacity, mcmi_plan **out, void *stream);

@@ -497,7 +497,8 @@ extern "C" mcmi_status mcmi_spai(const mcmi_cdf *cdf, const mcmi_params *p, cons
         a.pool_val = pool_val[pass].as<double>();
         a.pool_cap = pool_cap;
         a.pool_used = pool_used;
-        a.pool_chunk = (pass == 0 && !block_kernel) ? 2048 : 0;  // reruns size their pool exactly
+        // reruns size their pool exactly and reserve per row
+        a.pool_chunk = (pass == 0 && !block_kernel) ? pool_chunk_for(pool_cap, regions) : 0;
         a.spill_keys = sk.as<int32_t>();
         a.spill_vals = sv.as<double>();
         a.spill_used = su.as<int32_t>();

@@ -181,6 +181,18 @@ mcmi_status choose_shape(const mcmi_cdf *cdf, const mcmi_params *p, int lmax, in
 mcmi_status check_walk_params(const mcmi_params *p, bool per_row_chains, const char *who);
 mcmi_status read_chain_counts(const mcmi_cdf *cdf, const mcmi_params *p, const int32_t *rows_dev, int64_t n_rows,
                               const int32_t *cpr_dev, int &n_max, int &n_typ, hipStream_t s, const char *who);
+// Entries a wavefront of the wavefront kernel reserves in the output pool with one
+// atomic: a quarter of the pool spread over the wavefronts, between 256 and 32768.
+// The reservation is a device-wide atomic on one counter with a return value the
+// wavefront waits for; on the 160^3 27-point walk, chunks of 2048 entries (one
+// atomic per 12 rows) cost 3 % of the walk against chunks of 32768.
+inline int32_t pool_chunk_for(int64_t pool_cap, int64_t wavefronts) {
+    int64_t c = wavefronts > 0 ? pool_cap / (4 * wavefronts) : 32768;
+    if (c > 32768) c = 32768;
+    if (c < 256) c = 256;
+    return (int32_t)c;
+}
+
 struct WaveLayout {
     int lanes = 64, rows_per_wave = 1, spill_slots = 0;
 };

@@ -13,7 +13,7 @@
 // new seed. No memset node is recorded: counters are cleared by a kernel, and the
 // walk leaves its HBM overflow tables clean. The walk runs as the eager launch
 // does: the same task order (locality schedule, or LPT order on batched sets) and
-// wavefronts reserving output space kPlanChunk entries at a time in a pool of the
+// wavefronts reserving output space in chunks (pool_chunk_for) in a pool of the
 // plan's own, sized for the caller's capacity plus those reservations.
 #include <string.h>
 
@@ -52,10 +52,6 @@ __global__ void k_set_keys(const uint64_t *seed, uint32_t *keys) {
         keys[1] = (uint32_t)(*seed >> 32);
     }
 }
-
-// entries a wavefront reserves in the plan's pool with one atomic (as the
-// eager launch's first pass does)
-constexpr int kPlanChunk = 2048;
 
 std::string tune_key(const mcmi_cdf *cdf, const mcmi_params *p, int lmax) {
     auto lg = [](double x) { return x > 0 ? (int)std::floor(std::log2(x)) : -1; };
@@ -202,6 +198,7 @@ struct mcmi_plan {
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     int lmax = 0;
+    int32_t chunk = 0;  // pool entries a wavefront reserves at a time
     KernelShape shape;
 };
 
@@ -274,11 +271,13 @@ extern "C" mcmi_status mcmi_plan_create(const mcmi_cdf *cdf, const mcmi_params *
     } else {
         if (blocks * waves > pl->n) blocks = std::max<int64_t>(1, (pl->n + waves - 1) / waves);
         regions = blocks * waves;
-        // chunked reservations leave the tail of each wavefront's last chunk and
-        // the ends of chunks too short for the next row unused: an eighth of the
-        // capacity plus one chunk per wavefront covers them (a pool that still
-        // runs out is reported as an overflow, like the output capacity)
-        pl->pool_cap = nnz_capacity + nnz_capacity / 8 + regions * kPlanChunk;
+        // chunked reservations (as the eager launch's first pass makes them) leave
+        // the tail of each wavefront's last chunk and the ends of chunks too short
+        // for the next row unused: an eighth of the capacity plus one chunk per
+        // wavefront covers them (a pool that still runs out is reported as an
+        // overflow, like the output capacity)
+        pl->chunk = pool_chunk_for(nnz_capacity, regions);
+        pl->pool_cap = nnz_capacity + nnz_capacity / 8 + regions * (int64_t)pl->chunk;
     }
     const int spill_slots = layout.spill_slots;
     const size_t ctrl_bytes = 128;
@@ -344,7 +343,7 @@ extern "C" mcmi_status mcmi_plan_create(const mcmi_cdf *cdf, const mcmi_params *
     a.pool_col = pl->pool_col;
     a.pool_val = pl->pool_val;
     a.pool_cap = pl->pool_cap;
-    a.pool_chunk = block_kernel ? 0 : kPlanChunk;
+    a.pool_chunk = block_kernel ? 0 : pl->chunk;
     a.pool_used = (unsigned long long *)(ctrl + 32);
     a.spill_keys = pl->sk;
     a.spill_vals = pl->sv;
