@@ -45,20 +45,20 @@ TRAFFIC_BYTES = {
     # FETCH_SIZE x 2.000 + WRITE_SIZE x 1.000 (the factors that make a plain 1 GiB
     # device copy read 1 GiB), KiB -> bytes, one walk launch of the default
     # configuration of each workload
-    "aniso27": (1.7701e8 * 2.0 + 8.5247e6) * 1024.0,
-    "random": (1.913e8 * 2.0 + 1.967e6) * 1024.0,
-    "batched": (2.4118e8 * 2.0 + 5.7927e7) * 1024.0,
+    "aniso27": (1.1485e8 * 2.0 + 8.5646e6) * 1024.0,
+    "random": (1.9135e8 * 2.0 + 1.9680e6) * 1024.0,
+    "batched": (1.0880e8 * 2.0 + 5.7872e7) * 1024.0,
 }
 # Instruction issue of the 160^3 walk (k_walk<true, 64, 1, true>) from rocprofv3 SQ
-# counters of one launch (wave-summed quad cycles over SQ_WAVE_CYCLES = 1.1435e11,
+# counters of one launch (wave-summed quad cycles over SQ_WAVE_CYCLES = 1.1237e11,
 # 3072 waves, 3 per SIMD, the LDS tables allowing no more): the walk is bound by
 # each wave's issue and waits, not by HBM (with every bucket read served from a
 # 128 MB region the walk was not faster per transition)
 ISSUE = {
-    "aniso27": {"waves_per_simd": 3, "valu_busy_per_simd": round(2.2273e10 / 1.1435e11 * 3, 3),
-                "salu_busy_per_simd": round(1.6197e10 / 1.1435e11 * 3, 3),
-                "wave_issuing": round(4.9163e10 / 1.1435e11, 3), "wave_waiting_on_memory_or_lds": round(
-                    5.4104e10 / 1.1435e11, 3), "valu_insts_per_transition": 3.36, "salu_insts_per_transition": 2.45,
+    "aniso27": {"waves_per_simd": 3, "valu_busy_per_simd": round(2.2294e10 / 1.1237e11 * 3, 3),
+                "salu_busy_per_simd": round(1.6211e10 / 1.1237e11 * 3, 3),
+                "wave_issuing": round(4.9211e10 / 1.1237e11, 3), "wave_waiting_on_memory_or_lds": round(
+                    5.1968e10 / 1.1237e11, 3), "valu_insts_per_transition": 3.36, "salu_insts_per_transition": 2.45,
                 "lds_insts_per_transition": 0.42,
                 "counters": "SQ_ACTIVE_INST_VALU, SQ_ACTIVE_INST_SCA, SQ_ACTIVE_INST_ANY, SQ_WAIT_ANY, "
                             "SQ_WAVE_CYCLES, SQ_INSTS_VALU, SQ_INSTS_SALU, SQ_INSTS_LDS"},

@@ -400,18 +400,18 @@ extern "C" mcmi_status mcmi_spai(const mcmi_cdf *cdf, const mcmi_params *p, cons
 
     DevBuf row_start, row_cnt, sk, sv, su, ctrl, row_ptr, scan_tmp, failed;
     DevBuf pool_col[kMaxPools], pool_val[kMaxPools];
-    // ctrl: [0..7] queue counters (u32), then u64 pool_used, u64 stats[4], u32 flags, u64 collect[2]
-    const size_t ctrl_bytes = 8 * 4 + 8 + 4 * 8 + 8 + 16;
+    // the control block (kCtrl* offsets): queue counters, pool position, stats, flags, collect
+    const size_t ctrl_bytes = kCtrlBytes;
     MCMI_HIP(ctrl.alloc(ctrl_bytes, s));
     MCMI_HIP(row_start.alloc(n_tasks * sizeof(int64_t), s));
     MCMI_HIP(row_cnt.alloc(n_tasks * sizeof(uint32_t), s));
     MCMI_HIP(row_ptr.alloc((n_tasks + 1) * sizeof(int64_t), s));
     MCMI_HIP(scan_tmp.alloc(scan_tmp_bytes(n_tasks), s));
     uint32_t *qctr = ctrl.as<uint32_t>();
-    unsigned long long *pool_used = (unsigned long long *)(ctrl.as<unsigned char>() + 32);
-    unsigned long long *stats = (unsigned long long *)(ctrl.as<unsigned char>() + 40);
-    uint32_t *flags = (uint32_t *)(ctrl.as<unsigned char>() + 72);
-    unsigned long long *collect = (unsigned long long *)(ctrl.as<unsigned char>() + 80);
+    unsigned long long *pool_used = (unsigned long long *)(ctrl.as<unsigned char>() + kCtrlPool);
+    unsigned long long *stats = (unsigned long long *)(ctrl.as<unsigned char>() + kCtrlStats);
+    uint32_t *flags = (uint32_t *)(ctrl.as<unsigned char>() + kCtrlFlags);
+    unsigned long long *collect = (unsigned long long *)(ctrl.as<unsigned char>() + kCtrlCollect);
 
 
     // batched record sets: longest-processing-time order (batched_lpt_map)

@@ -181,6 +181,19 @@ mcmi_status choose_shape(const mcmi_cdf *cdf, const mcmi_params *p, int lmax, in
 mcmi_status check_walk_params(const mcmi_params *p, bool per_row_chains, const char *who);
 mcmi_status read_chain_counts(const mcmi_cdf *cdf, const mcmi_params *p, const int32_t *rows_dev, int64_t n_rows,
                               const int32_t *cpr_dev, int &n_max, int &n_typ, hipStream_t s, const char *who);
+// Control block of a walk launch. Every counter that wavefronts update with
+// device-wide atomics (the eight row queues, the pool position, statistics, flags)
+// sits on a 4 KB line of its own: atomics on one cache line are performed one
+// after the other, so counters sharing a line would queue behind each other.
+constexpr size_t kCtrlLine = 4096;
+constexpr int kQueueStride = (int)(kCtrlLine / 4);  // uint32 elements between queue counters
+constexpr size_t kCtrlPool = 8 * kCtrlLine;         // u64 pool position
+constexpr size_t kCtrlStats = 9 * kCtrlLine;        // u64 stats[4]
+constexpr size_t kCtrlFlags = 10 * kCtrlLine;       // u32 flags
+constexpr size_t kCtrlCollect = 11 * kCtrlLine;     // u64 collect[2] (failed rows of a pass)
+constexpr size_t kCtrlKeys = 12 * kCtrlLine;        // u32 Philox keys (captured plans)
+constexpr size_t kCtrlBytes = 13 * kCtrlLine;
+
 // Entries a wavefront of the wavefront kernel reserves in the output pool with one
 // atomic: a quarter of the pool spread over the wavefronts, between 256 and 32768.
 // The reservation is a device-wide atomic on one counter with a return value the

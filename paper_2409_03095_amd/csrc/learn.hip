@@ -112,8 +112,8 @@ __global__ void __launch_bounds__(64) k_pilot(WalkArgs a, int pilot, int cap, do
             for (int tries = 0; tries < 8; ++tries) {
                 const int q = (queue + tries) & 7;
                 const int64_t lo = a.n_tasks * q / 8, hi = a.n_tasks * (q + 1) / 8;
-                if (hi > lo && __atomic_load_n(&a.queue_ctr[q], __ATOMIC_RELAXED) < (uint32_t)(hi - lo)) {
-                    const uint32_t idx = atomicAdd(&a.queue_ctr[q], 1u);
+                if (hi > lo && __atomic_load_n(&a.queue_ctr[q * kQueueStride], __ATOMIC_RELAXED) < (uint32_t)(hi - lo)) {
+                    const uint32_t idx = atomicAdd(&a.queue_ctr[q * kQueueStride], 1u);
                     if ((int64_t)idx < hi - lo) {
                         task = lo + idx;
                         queue = q;
@@ -336,7 +336,7 @@ extern "C" mcmi_status mcmi_pilot_variance(const mcmi_cdf *cdf, const mcmi_param
     unsigned char *ctrl = nullptr;
     int32_t *sk = nullptr, *su = nullptr;
     double *sv = nullptr;
-    const size_t ctrl_bytes = 32 + 8 + 32 + 8;
+    const size_t ctrl_bytes = kCtrlBytes;
     auto cleanup = [&]() {
         (void)hipFree(ctrl);
         (void)hipFree(sk);
@@ -389,8 +389,8 @@ extern "C" mcmi_status mcmi_pilot_variance(const mcmi_cdf *cdf, const mcmi_param
         a.hash_slots = H;
         a.hash_shift = 32 - __builtin_ctz((unsigned)H);
         a.queue_ctr = (uint32_t *)ctrl;
-        a.stats = (unsigned long long *)(ctrl + 40);
-        a.flags = (uint32_t *)(ctrl + 72);
+        a.stats = (unsigned long long *)(ctrl + kCtrlStats);
+        a.flags = (uint32_t *)(ctrl + kCtrlFlags);
         a.spill_keys = sk;
         a.spill_vals = sv;
         a.spill_used = su;

@@ -280,7 +280,7 @@ extern "C" mcmi_status mcmi_plan_create(const mcmi_cdf *cdf, const mcmi_params *
         pl->pool_cap = nnz_capacity + nnz_capacity / 8 + regions * (int64_t)pl->chunk;
     }
     const int spill_slots = layout.spill_slots;
-    const size_t ctrl_bytes = 128;
+    const size_t ctrl_bytes = kCtrlBytes;
 #define TRYP(call)                                                                           \
     do {                                                                                     \
         hipError_t _e = (call);                                                              \
@@ -325,7 +325,7 @@ extern "C" mcmi_status mcmi_plan_create(const mcmi_cdf *cdf, const mcmi_params *
     a.task_map = cdf->batch == 0 ? cdf->order : pl->lpt;  // locality schedule or LPT order, if any
     a.chains_per_row = chains_per_row_dev;
     a.chains = p->chains;
-    a.keys_dev = (const uint32_t *)(ctrl + 96);
+    a.keys_dev = (const uint32_t *)(ctrl + kCtrlKeys);
     a.tag = p->stream_tag;
     a.row_mat = cdf->batch > 0 ? cdf->row_mat : nullptr;
     a.mat_base = cdf->batch > 0 ? cdf->mat_base : nullptr;
@@ -344,13 +344,13 @@ extern "C" mcmi_status mcmi_plan_create(const mcmi_cdf *cdf, const mcmi_params *
     a.pool_val = pl->pool_val;
     a.pool_cap = pl->pool_cap;
     a.pool_chunk = block_kernel ? 0 : pl->chunk;
-    a.pool_used = (unsigned long long *)(ctrl + 32);
+    a.pool_used = (unsigned long long *)(ctrl + kCtrlPool);
     a.spill_keys = pl->sk;
     a.spill_vals = pl->sv;
     a.spill_used = pl->su;
     a.spill_slots = spill_slots;
-    a.stats = (unsigned long long *)(ctrl + 40);
-    a.flags = (uint32_t *)(ctrl + 72);
+    a.stats = (unsigned long long *)(ctrl + kCtrlStats);
+    a.flags = (uint32_t *)(ctrl + kCtrlFlags);
     a.tau = pl->shape.tau;
     a.tau32 = (float)pl->shape.tau;
     a.sketch_slots = pl->shape.sketch;
@@ -359,8 +359,9 @@ extern "C" mcmi_status mcmi_plan_create(const mcmi_cdf *cdf, const mcmi_params *
     TRYP(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
     hipError_t ce = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
     if (ce == hipSuccess) {
-        k_zero_words<<<1, 64, 0, cs>>>((uint32_t *)ctrl, 24);  // counters, stats, flags (not the keys)
-        k_set_keys<<<1, 64, 0, cs>>>(pl->seed, (uint32_t *)(ctrl + 96));
+        // counters, stats and flags (everything before the keys)
+        k_zero_words<<<1, 256, 0, cs>>>((uint32_t *)ctrl, (int)(kCtrlKeys / 4));
+        k_set_keys<<<1, 64, 0, cs>>>(pl->seed, (uint32_t *)(ctrl + kCtrlKeys));
         if (block_kernel)
             ce = launch_walk_block(a, f32, pl->shape.lanes, (int)blocks, cs);
         else
@@ -399,15 +400,14 @@ extern "C" mcmi_status mcmi_plan_result(mcmi_plan *pl, mcmi_csr_out *M_view, mcm
                                         void *stream) {
     if (!pl) return fail(MCMI_ERR_ARG, "mcmi_plan_result: bad plan");
     hipStream_t s = (hipStream_t)stream;
-    unsigned char h[128];
+    const unsigned char *ctrl = (const unsigned char *)pl->ctrl;
     int64_t nnz = 0;
-    MCMI_HIP(hipMemcpyAsync(h, pl->ctrl, sizeof(h), hipMemcpyDeviceToHost, s));
+    uint32_t flags = 0;
+    unsigned long long stats[4] = {0, 0, 0, 0};
+    MCMI_HIP(hipMemcpyAsync(&flags, ctrl + kCtrlFlags, sizeof(flags), hipMemcpyDeviceToHost, s));
+    MCMI_HIP(hipMemcpyAsync(stats, ctrl + kCtrlStats, sizeof(stats), hipMemcpyDeviceToHost, s));
     MCMI_HIP(hipMemcpyAsync(&nnz, pl->row_ptr + pl->n, sizeof(nnz), hipMemcpyDeviceToHost, s));
     MCMI_HIP(hipStreamSynchronize(s));
-    uint32_t flags;
-    unsigned long long stats[4];
-    memcpy(&flags, h + 72, 4);
-    memcpy(stats, h + 40, sizeof(stats));
     const int ovf = (flags & (kFlagPool | kFlagSpill | kFlagStage)) || nnz > pl->cap ? 1 : 0;
     if (overflow) *overflow = ovf;
     if (M_view) {

@@ -32,7 +32,7 @@ struct WalkArgs {
     int32_t hash_shift;            // 32 - log2(hash_slots)
     int32_t row_lanes;             // wavefront kernel: lanes per row (8, 16, 32 or 64; 0 = 64)
     int32_t lane_chains;           // wavefront kernel, 64 lanes per row: chains a lane keeps in flight (1 or 2)
-    uint32_t *queue_ctr;           // 8 counters
+    uint32_t *queue_ctr;           // 8 counters, kQueueStride elements apart
     int64_t *row_start;            // pool position | pool_tag, or -1 when the row must be rerun
     uint32_t *row_cnt;
     int32_t *pool_col;

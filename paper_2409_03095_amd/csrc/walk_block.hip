@@ -270,8 +270,8 @@ __device__ __forceinline__ int64_t grab_task(const WalkArgs &a, int &queue) {
     for (int tries = 0; tries < 8; ++tries) {
         const int q = (queue + tries) & 7;
         const int64_t lo = a.n_tasks * q / 8, hi = a.n_tasks * (q + 1) / 8;
-        if (hi > lo && __atomic_load_n(&a.queue_ctr[q], __ATOMIC_RELAXED) < (uint32_t)(hi - lo)) {
-            const uint32_t idx = atomicAdd(&a.queue_ctr[q], 1u);
+        if (hi > lo && __atomic_load_n(&a.queue_ctr[q * kQueueStride], __ATOMIC_RELAXED) < (uint32_t)(hi - lo)) {
+            const uint32_t idx = atomicAdd(&a.queue_ctr[q * kQueueStride], 1u);
             if ((int64_t)idx < hi - lo) {
                 queue = q;
                 return lo + idx;
