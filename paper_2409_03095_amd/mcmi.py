@@ -21,6 +21,11 @@ if not os.path.exists(LIB_PATH):
     raise ImportError(f"libmcmi.so not found at {LIB_PATH}: build it with "
                       "`python -c 'import __graft_entry__ as g; g.build()'` (hipcc, gfx950)")
 
+# torch first: it brings its own HIP runtime (same soname as the one the library
+# links), and the library must bind to that copy. Loaded the other way round the
+# process ends up with two HIP runtimes, and the library's sees no device.
+import torch  # noqa: E402,F401
+
 _lib = ctypes.CDLL(LIB_PATH)
 
 MCMI_OK = 0

@@ -73,3 +73,15 @@ def test_binding_structs_match_the_header(tmp_path):
         assert got[(cname, "sizeof")] == ctypes.sizeof(cls), cname
         for f, _ in cls._fields_:
             assert got[(cname, f)] == getattr(cls, f).offset, (cname, f)
+
+
+def test_binding_shares_torchs_hip_runtime():
+    """Imported before torch, the binding still maps a single HIP runtime, torch's:
+    a second copy of the runtime in the process sees no device."""
+    code = ("import sys; sys.path.insert(0, sys.argv[1])\n"
+            "from paper_2409_03095_amd import learned\n"
+            "import torch\n"
+            "maps = open('/proc/self/maps').read().splitlines()\n"
+            "print('\\n'.join(sorted({l.split()[-1] for l in maps if 'libamdhip64' in l})))\n")
+    out = subprocess.check_output(["python3", "-c", code, ROOT], text=True).split()
+    assert len(out) == 1, out
