@@ -46,7 +46,7 @@ TRAFFIC_BYTES = {
     # device copy read 1 GiB), KiB -> bytes, one walk launch of the default
     # configuration of each workload
     "aniso27": (1.1485e8 * 2.0 + 8.5646e6) * 1024.0,
-    "random": (1.9135e8 * 2.0 + 1.9680e6) * 1024.0,
+    "random": (1.8886e8 * 2.0 + 1.9607e6) * 1024.0,
     "batched": (1.0880e8 * 2.0 + 5.7872e7) * 1024.0,
 }
 # Instruction issue of the 160^3 walk (k_walk<true, 64, 1, true>) from rocprofv3 SQ

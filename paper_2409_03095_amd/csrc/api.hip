@@ -371,8 +371,8 @@ extern "C" mcmi_status mcmi_spai(const mcmi_cdf *cdf, const mcmi_params *p, cons
         if (sst != MCMI_OK) return sst;
     }
     const bool block_kernel = shape.lanes > 64;
-    // FP32 walks of the wavefront kernel read the compact records only
-    if (block_kernel || !f32) MCMI_HIP(ensure_full_records(cdf, s));
+    // FP32 walks read the compact records only
+    if (!f32) MCMI_HIP(ensure_full_records(cdf, s));
     int H = shape.hash;
     const int sketch = shape.sketch;
     const double tau = shape.tau;

@@ -248,7 +248,7 @@ extern "C" mcmi_status mcmi_plan_create(const mcmi_cdf *cdf, const mcmi_params *
     pl->shape.lanes = layout.lanes;
     const bool f32 = p->walk_prec == MCMI_WALK_F32;
     const bool block_kernel = pl->shape.lanes > 64;
-    if (block_kernel || !f32) {
+    if (!f32) {  // FP32 walks read the compact records only
         const hipError_t fe = ensure_full_records(cdf, s);
         if (fe != hipSuccess) {
             delete pl;

@@ -6,7 +6,7 @@ namespace mcmi {
 
 struct WalkArgs {
     const uint32_t *rec;
-    const uint32_t *rec32;         // compact records (FP32 walks of the wavefront kernel)
+    const uint32_t *rec32;         // compact records (FP32 walks)
     const uint32_t *roff;
     const double *diag;
     const int32_t *rows;           // nullable: output slot t is row t

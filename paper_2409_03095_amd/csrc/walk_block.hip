@@ -23,6 +23,11 @@
 //
 // With N_r <= lanes each lane keeps its chain's state in registers across H and
 // L; otherwise phase L replays chains from their start, skipping the heavy prefix.
+//
+// FP32 walks read the compact records (32-byte units, two loads per step); their
+// accumulation key is the state's record offset, which orders like the column
+// and becomes it at the finalize (one header read per kept entry). FP64 walks
+// read the full records and key by column.
 #include "common.hpp"
 #include "walk_args.hpp"
 #include "walk_common.hpp"
@@ -52,6 +57,7 @@ struct RowCtx {
     uint32_t prow, ptag;  // Philox row and tag words
     uint32_t k0, k1;      // Philox key
     uint32_t r_off;
+    int32_t rk;  // the key of row r itself: its record offset (FP32), else r
     StepHdr h0;  // header of row r, where every chain starts
     int32_t *keys;
     double *vals;
@@ -74,7 +80,23 @@ __device__ __forceinline__ void chain_start(Chain &st, int32_t c, const RowCtx &
     st.active = c < rc.N;
 }
 
+// header of the record at unit off: compact (FP32 walks) or full
+template <bool kF32>
+__device__ __forceinline__ void row_header(const WalkArgs &a, uint32_t off, StepHdr &H) {
+    if (kF32)
+        load_header_c(a.rec32, off, H);
+    else
+        load_header<false>(a.rec, off, H);
+}
+
+// d of an accumulation key's column
+template <bool kF32>
+__device__ __forceinline__ double key_diag(const WalkArgs &a, int32_t key) {
+    return kF32 ? diag_of_c(a.rec32, (uint32_t)key) : a.diag[key];
+}
+
 // light contribution: add to the tracked column, else to its sketch bucket
+template <bool kF32>
 __device__ __forceinline__ void light_add(const WalkArgs &a, const RowCtx &rc, int32_t key, double w,
                                           unsigned long long &spilled) {
     const uint32_t hmask = (uint32_t)a.hash_slots - 1u;
@@ -110,7 +132,7 @@ __device__ __forceinline__ void light_add(const WalkArgs &a, const RowCtx &rc, i
         }
     }
     double mag = fabs(w);
-    if (a.filter_m) mag = mag / fabs(a.diag[key]);
+    if (a.filter_m) mag = mag / fabs(key_diag<kF32>(a, key));
     atomicAdd(&rc.sketch[bucket_of(key, (uint32_t)a.sketch_slots)], (float)mag);
 }
 
@@ -197,7 +219,7 @@ __device__ __forceinline__ void run_chains(const WalkArgs &a, const RowCtx &rc, 
                 paused = true;
                 break;
             } else if (kMode == kLight) {
-                if (!heavy) light_add(a, rc, key, w, spilled);
+                if (!heavy) light_add<kF32>(a, rc, key, w, spilled);
             } else {
                 if (!heavy) refine_add(a, rc, key, w, spill_full, spilled);
             }
@@ -222,7 +244,14 @@ __device__ __forceinline__ void run_chains(const WalkArgs &a, const RowCtx &rc, 
             st.blk.x = st.blk.y;
             st.blk.y = st.blk.z;
             st.blk.z = st.blk.w;
-            const uint32_t tgt = draw_next<kF32>(a.rec, st.off, H, u, st.h);
+            uint32_t tgt;
+            if (kF32) {
+                BucketLd b;
+                bucket_issue_c(a.rec32, st.off, H, u, b);
+                tgt = bucket_resolve_c(b, st.h);
+            } else {
+                tgt = draw_next<false>(a.rec, st.off, H, u, st.h);
+            }
             const bool neg = (tgt & kSignBit) != 0u;
             if (kF32)
                 st.w32 = neg ? -wn32 : wn32;
@@ -320,10 +349,11 @@ __device__ __forceinline__ void block_row(const WalkArgs &a, const RowPre &cur, 
     rc.N = N;
     philox_ids(a, r, rc.prow, rc.ptag);
     rc.r_off = cur.r_off;
+    rc.rk = kF32 ? (int32_t)cur.r_off : r;
     rc.h0 = cur.h0;
     const bool split = a.tau > 0.0;
     const bool reg = N <= kLPR;
-    if (tid == 0) lds_add(rc.keys, rc.vals, H - 1u, hash_key(r, a.hash_shift), r, (double)N);
+    if (tid == 0) lds_add(rc.keys, rc.vals, H - 1u, hash_key(rc.rk, a.hash_shift), rc.rk, (double)N);
     __syncthreads();
 
     Chain st;
@@ -381,8 +411,8 @@ __device__ __forceinline__ void block_row(const WalkArgs &a, const RowPre &cur, 
         if (raw != kEmpty) {
             const int32_t key = (int32_t)((uint32_t)raw & ~kRBit);
             const double nhat = acc / nd;  // N_rc; scaled by 1 / d_c once the kept set is final
-            const double test = a.filter_m ? fabs(nhat / a.diag[key]) : fabs(nhat);
-            if (key == r || (nhat != 0.0 && test >= a.eps)) {
+            const double test = a.filter_m ? fabs(nhat / key_diag<kF32>(a, key)) : fabs(nhat);
+            if (key == rc.rk || (nhat != 0.0 && test >= a.eps)) {
                 ks[q] = key;
                 vs[q] = nhat;
                 ++cnt;
@@ -414,8 +444,8 @@ __device__ __forceinline__ void block_row(const WalkArgs &a, const RowPre &cur, 
             const int32_t sl = rc.sused[u];
             key = (int32_t)((uint32_t)rc.skeys[sl] & ~kRBit);
             nhat = rc.svals[sl] / nd;
-            const double test = a.filter_m ? fabs(nhat / a.diag[key]) : fabs(nhat);
-            keep = (key == r || (nhat != 0.0 && test >= a.eps)) ? 1 : 0;
+            const double test = a.filter_m ? fabs(nhat / key_diag<kF32>(a, key)) : fabs(nhat);
+            keep = (key == rc.rk || (nhat != 0.0 && test >= a.eps)) ? 1 : 0;
             rc.skeys[sl] = kEmpty;
             rc.svals[sl] = 0.0;
         }
@@ -433,7 +463,12 @@ __device__ __forceinline__ void block_row(const WalkArgs &a, const RowPre &cur, 
     }
     if (K > H) K = H;
     __syncthreads();
-    if (nxt.task >= 0) load_header<kF32>(a.rec, nxt.r_off, nxt.h0);
+    if (nxt.task >= 0) row_header<kF32>(a, nxt.r_off, nxt.h0);
+    if (kF32) {
+        // record offsets -> columns (the same order)
+        for (int i = tid; i < K; i += kLPR) rc.keys[i] = row_of_c(a.rec32, (uint32_t)rc.keys[i]);
+        __syncthreads();
+    }
     // top-k retention: bitonic sort in retention order, keep the first topk,
     // then turn N_rc into M_rc = N_rc / d_c
     if (a.topk > 0) {
@@ -570,7 +605,7 @@ __global__ void __launch_bounds__(kLPR, 4) k_walk_block(WalkArgs a) {
     if (cur.task >= 0) {
         int64_t slot;
         cur.r_off = a.roff[task_row(a, cur.task, slot)];
-        load_header<kF32>(a.rec, cur.r_off, cur.h0);
+        row_header<kF32>(a, cur.r_off, cur.h0);
     }
     while (cur.task >= 0) {
         RowPre nxt;
