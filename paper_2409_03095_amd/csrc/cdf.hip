@@ -359,6 +359,9 @@ __global__ void __launch_bounds__(64) k_alias(int64_t n, const uint32_t *__restr
 }
 
 constexpr int kBucketSlots = 4;
+// buckets per lane in flight in k_buckets32: fewer registers, more waves (on the
+// 160^3 27-point records 1.83 ms with 2, 1.93 ms with 4, 2.60 ms with 8)
+constexpr int kBucketSlots32 = 2;
 
 // Full records from the compact ones (see common.hpp). Header units: thread per
 // row. Buckets: a wave takes 64 consecutive rows and writes their buckets as one
@@ -478,14 +481,14 @@ __global__ void __launch_bounds__(256) k_buckets32(int64_t n, const uint32_t *__
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
         const uint32_t total = (uint32_t)__shfl((int)incl, 63, 64);
         const int half = lane & 1;
-        int row[kBucketSlots];
+        int row[kBucketSlots32];
 #pragma unroll
-        for (int j = 0; j < kBucketSlots; ++j) row[j] = 0;
-        for (uint32_t t0 = 0; t0 < total; t0 += 32 * kBucketSlots) {
-            uint4 v[kBucketSlots];
-            size_t dst[kBucketSlots];
+        for (int j = 0; j < kBucketSlots32; ++j) row[j] = 0;
+        for (uint32_t t0 = 0; t0 < total; t0 += 32 * kBucketSlots32) {
+            uint4 v[kBucketSlots32];
+            size_t dst[kBucketSlots32];
 #pragma unroll
-            for (int j = 0; j < kBucketSlots; ++j) {
+            for (int j = 0; j < kBucketSlots32; ++j) {
                 const uint32_t t = t0 + (uint32_t)(j * 32 + (lane >> 1));
                 dst[j] = ~(size_t)0;
                 if (t >= total) continue;
@@ -512,7 +515,7 @@ __global__ void __launch_bounds__(256) k_buckets32(int64_t n, const uint32_t *__
                 dst[j] = ((size_t)po[i] + 1u + k) * kUnitWords32 + (size_t)half * 4u;
             }
 #pragma unroll
-            for (int j = 0; j < kBucketSlots; ++j)
+            for (int j = 0; j < kBucketSlots32; ++j)
                 if (dst[j] != ~(size_t)0) *(uint4 *)(rec32 + dst[j]) = v[j];
         }
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -640,14 +643,22 @@ extern "C" mcmi_status mcmi_build_cdf_ex(const mcmi_csr_in *B, const mcmi_cdf_op
     }
     uint32_t hflags = 0;
     int64_t htot[2] = {0, 0};
-    // lanes per row in k_count and k_fill: about one lane per entry of an average row
+    // lanes per row: k_count about one lane per three entries of an average row,
+    // k_fill (two passes over the row, a scan per G entries) one per two. More
+    // rows per wave hide more of each row's dependent loads: on the 160^3
+    // 27-point matrix k_count 0.87 -> 0.60 ms (32 -> 8 lanes), k_fill 1.43 ->
+    // 1.13 ms (32 -> 16 lanes; 8 lanes: 1.23 ms)
     const double per_row = (double)B->nnz / (double)n;
-    const int lanes = per_row <= 12.0 ? 16 : per_row <= 40.0 ? 32 : 64;
+    const int lanes_c = per_row <= 40.0 ? 8 : per_row <= 80.0 ? 16 : per_row <= 160.0 ? 32 : 64;
+    const int lanes_f = per_row <= 12.0 ? 8 : per_row <= 48.0 ? 16 : per_row <= 96.0 ? 32 : 64;
     auto count_pass = [&](const unsigned long long *cut) -> hipError_t {
-        if (lanes == 16)
+        if (lanes_c == 8)
+            k_count<8><<<grid, 256, 0, s>>>(n, B->nnz, B->row_ptr_dev, B->col_dev, B->val_dev, aug, cut, cdf->mrow,
+                                            units, cdf->diag, flags);
+        else if (lanes_c == 16)
             k_count<16><<<grid, 256, 0, s>>>(n, B->nnz, B->row_ptr_dev, B->col_dev, B->val_dev, aug, cut, cdf->mrow,
                                              units, cdf->diag, flags);
-        else if (lanes == 32)
+        else if (lanes_c == 32)
             k_count<32><<<grid, 256, 0, s>>>(n, B->nnz, B->row_ptr_dev, B->col_dev, B->val_dev, aug, cut, cdf->mrow,
                                              units, cdf->diag, flags);
         else
@@ -701,10 +712,13 @@ extern "C" mcmi_status mcmi_build_cdf_ex(const mcmi_csr_in *B, const mcmi_cdf_op
     TRY(dev_alloc((void **)&cdf->rec32, (size_t)htot[0] * kUnitWords32 * 4u + 32u, s));
     TRY(dev_alloc((void **)&sorted, (size_t)(htot[1] > 0 ? htot[1] : 1) * sizeof(uint2), s));
     TRY(dev_alloc((void **)&tinfo, (size_t)n * sizeof(uint4), s));
-    if (lanes == 16)
+    if (lanes_f == 8)
+        k_fill<8><<<grid, 256, 0, s>>>(n, B->row_ptr_dev, B->col_dev, B->val_dev, cdf->diag, cdf->mrow, roff64, cptr,
+                                       cut, cdf->roff, cdf->rec32, sorted, tinfo, norm_bits);
+    else if (lanes_f == 16)
         k_fill<16><<<grid, 256, 0, s>>>(n, B->row_ptr_dev, B->col_dev, B->val_dev, cdf->diag, cdf->mrow, roff64, cptr,
                                         cut, cdf->roff, cdf->rec32, sorted, tinfo, norm_bits);
-    else if (lanes == 32)
+    else if (lanes_f == 32)
         k_fill<32><<<grid, 256, 0, s>>>(n, B->row_ptr_dev, B->col_dev, B->val_dev, cdf->diag, cdf->mrow, roff64, cptr,
                                         cut, cdf->roff, cdf->rec32, sorted, tinfo, norm_bits);
     else
