@@ -300,61 +300,67 @@ __global__ void __launch_bounds__(256) k_fill(int64_t n, const int64_t *__restri
 // q_l -= W - q_s), and l goes back on small if q_l < W, else on large. Leftover
 // buckets keep all W units (T = W, A = self). Every entry's final q is its
 // threshold. Both stacks live in one scratch array of the row's length (small
-// grows up from the front, large down from the back), q and A in two more; the
-// scratch is in LDS for rows of up to kAliasLds entries (in the row's slice of a
-// global scratch otherwise). The thresholds and alias indices end in thr_g and
-// ali_g, indexed like the entries of C.
+// grows up from the front, large down from the back), q and A in two more, at
+// stride sc (vose_row); the scratch is in LDS for rows of up to kAliasLds
+// entries (in the row's slice of a global scratch otherwise). The thresholds and
+// alias indices end in thr_g and ali_g, indexed like the entries of C.
 constexpr int kAliasLds = 32;    // rows up to this long keep their scratch in LDS
 constexpr int kAliasPitch = 65;  // LDS words per entry index: the lanes of a wave hit distinct banks
 
+template <typename I>
+__device__ __forceinline__ void vose_row(uint32_t m, const uint2 *__restrict__ row, uint32_t *q, I *st, I *al,
+                                         int sc) {
+    const uint32_t W = row[m - 1].x;
+    int ns = 0, nl = 0;
+    uint32_t prev = 0;
+    for (uint32_t k = 0; k < m; ++k) {
+        const uint32_t cum = row[k].x;
+        const uint32_t qk = m * (cum - prev);  // m w_k <= m 2^Q <= 2^31
+        prev = cum;
+        q[k * sc] = qk;
+        al[k * sc] = (I)k;
+        if (qk < W)
+            st[(ns++) * sc] = (I)k;
+        else
+            st[(m - 1 - nl++) * sc] = (I)k;
+    }
+    while (ns > 0 && nl > 0) {
+        const int sm = (int)st[(--ns) * sc];
+        const int lg = (int)st[(m - nl--) * sc];
+        al[sm * sc] = (I)lg;
+        const uint32_t ql = q[lg * sc] - (W - q[sm * sc]);
+        q[lg * sc] = ql;
+        if (ql < W)
+            st[(ns++) * sc] = (I)lg;
+        else
+            st[(m - 1 - nl++) * sc] = (I)lg;
+    }
+}
+
+// LDS rows keep their stack and alias indices in bytes (entry indices < 32):
+// 12.5 KB per wave instead of 25 KB, twice the waves per CU.
 __global__ void __launch_bounds__(64) k_alias(int64_t n, const uint32_t *__restrict__ mrow,
                                               const int64_t *__restrict__ cptr, const uint2 *__restrict__ sorted,
                                               uint32_t *__restrict__ thr_g, int32_t *__restrict__ stk_g,
                                               int32_t *__restrict__ ali_g) {
     __shared__ uint32_t q_l[kAliasLds * kAliasPitch];
-    __shared__ int32_t st_l[kAliasLds * kAliasPitch];
-    __shared__ int32_t al_l[kAliasLds * kAliasPitch];
+    __shared__ uint8_t st_l[kAliasLds * kAliasPitch];
+    __shared__ uint8_t al_l[kAliasLds * kAliasPitch];
     const int lane = threadIdx.x;
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (int64_t r = (int64_t)blockIdx.x * blockDim.x + lane; r < n; r += stride) {
         const uint32_t m = mrow[r];
         if (m == 0) continue;
         const int64_t base = cptr[r];
-        const bool lds = m <= (uint32_t)kAliasLds;
-        uint32_t *q = lds ? q_l + lane : thr_g + base;
-        int32_t *st = lds ? st_l + lane : stk_g + base;
-        int32_t *al = lds ? al_l + lane : ali_g + base;
-        const int sc = lds ? kAliasPitch : 1;
-        const uint32_t W = sorted[base + m - 1].x;
-        int ns = 0, nl = 0;
-        uint32_t prev = 0;
-        for (uint32_t k = 0; k < m; ++k) {
-            const uint32_t cum = sorted[base + k].x;
-            const uint32_t qk = m * (cum - prev);  // m w_k <= m 2^Q <= 2^31
-            prev = cum;
-            q[k * sc] = qk;
-            al[k * sc] = (int32_t)k;
-            if (qk < W)
-                st[(ns++) * sc] = (int32_t)k;
-            else
-                st[(m - 1 - nl++) * sc] = (int32_t)k;
-        }
-        while (ns > 0 && nl > 0) {
-            const int32_t sm = st[(--ns) * sc];
-            const int32_t lg = st[(m - nl--) * sc];
-            al[sm * sc] = lg;
-            const uint32_t ql = q[lg * sc] - (W - q[sm * sc]);
-            q[lg * sc] = ql;
-            if (ql < W)
-                st[(ns++) * sc] = lg;
-            else
-                st[(m - 1 - nl++) * sc] = lg;
-        }
-        if (lds)
+        if (m <= (uint32_t)kAliasLds) {
+            vose_row<uint8_t>(m, sorted + base, q_l + lane, st_l + lane, al_l + lane, kAliasPitch);
             for (uint32_t k = 0; k < m; ++k) {
-                thr_g[base + k] = q[k * sc];
-                ali_g[base + k] = al[k * sc];
+                thr_g[base + k] = q_l[k * kAliasPitch + lane];
+                ali_g[base + k] = (int32_t)al_l[k * kAliasPitch + lane];
             }
+        } else {
+            vose_row<int32_t>(m, sorted + base, thr_g + base, stk_g + base, ali_g + base, 1);
+        }
     }
 }
 

@@ -21,6 +21,10 @@ namespace {
 constexpr uint32_t kUnset = 0xFFFFFFFFu;
 constexpr int kMaxGrow = 64;
 constexpr int kGrowBatch = 16;
+// lanes per row in a level (fewer lanes, more rows per wave in flight: on the
+// 160^3 27-point matrix 60 us per level with 8 lanes, 44 us with 4, 50 and 52 us
+// with 2 and 1)
+constexpr int kGrowLanes = 4;
 
 __device__ __forceinline__ uint32_t mix32(uint32_t x) {
     // MurmurHash3's 32-bit finaliser
@@ -39,35 +43,36 @@ __global__ void __launch_bounds__(256) k_seed(int64_t n, uint32_t thr, uint32_t 
     for (int64_t r = gid; r < n; r += stride) lab[r] = mix32((uint32_t)r ^ 0x6A09E667u) < thr ? (uint32_t)r : kUnset;
 }
 
-// One level of the search, eight lanes per row, each lane issuing the loads of
-// four of the row's columns before their labels (a row of up to 32 entries costs
-// two dependent loads; past the end a lane re-reads the row's last column, which
+// One level of the search, G lanes per row, each lane issuing the loads of 32 / G
+// of the row's columns before their labels (a row of up to 32 entries costs two
+// dependent loads; past the end a lane re-reads the row's last column, which
 // leaves the minimum as it is). A level runs only if the one before it labelled
 // a row; when a level labels nothing, its output equals its input, so after the
 // search both buffers hold the final labels (or, if all kMaxGrow levels ran, the
 // buffer the last level wrote).
+template <int G>
 __global__ void __launch_bounds__(256) k_grow(int64_t n, const int64_t *__restrict__ rp, const int32_t *__restrict__ col,
                                               const uint32_t *__restrict__ lin, uint32_t *__restrict__ lout,
                                               uint32_t *changed, int level) {
+    constexpr int U = 32 / G;
     if (level > 0 && changed[level - 1] == 0u) return;
-    const int sub = threadIdx.x & 7;
-    const int64_t groups = ((int64_t)gridDim.x * blockDim.x) >> 3;
+    const int sub = threadIdx.x & (G - 1);
+    const int64_t groups = ((int64_t)gridDim.x * blockDim.x) / G;
     bool any = false;
-    for (int64_t r = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 3; r < n; r += groups) {
+    for (int64_t r = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / G; r < n; r += groups) {
         uint32_t v = lin[r];
-        if (v == kUnset) {  // uniform over the row's eight lanes
+        if (v == kUnset) {  // uniform over the row's G lanes
             uint32_t m = kUnset;
             const int64_t b = rp[r], e = rp[r + 1];
             for (int64_t k0 = b + sub; k0 < e; k0 += 32) {
-                int32_t c[4];
+                int32_t c[U];
 #pragma unroll
-                for (int j = 0; j < 4; ++j) c[j] = col[k0 + 8 * j < e ? k0 + 8 * j : e - 1];
+                for (int j = 0; j < U; ++j) c[j] = col[k0 + G * j < e ? k0 + G * j : e - 1];
 #pragma unroll
-                for (int j = 0; j < 4; ++j) m = min(m, lin[c[j]]);
+                for (int j = 0; j < U; ++j) m = min(m, lin[c[j]]);
             }
-            m = min(m, (uint32_t)__shfl_xor((int)m, 1, 8));
-            m = min(m, (uint32_t)__shfl_xor((int)m, 2, 8));
-            m = min(m, (uint32_t)__shfl_xor((int)m, 4, 8));
+#pragma unroll
+            for (int off = 1; off < G; off <<= 1) m = min(m, (uint32_t)__shfl_xor((int)m, off, G));
             v = m;
             any |= m != kUnset;
         }
@@ -123,8 +128,8 @@ hipError_t build_locality_order(int64_t n, const int64_t *row_ptr, const int32_t
         // once, and the empty one copied the final labels into both buffers)
         for (int level = 0; e == hipSuccess && level < kMaxGrow; ++level) {
             const bool even = (level & 1) == 0;
-            k_grow<<<grid_rows(n, 8, 4096), 256, 0, s>>>(n, row_ptr, col, even ? lab0 : lab1, even ? lab1 : lab0, changed,
-                                                   level);
+            k_grow<kGrowLanes><<<grid_rows(n, kGrowLanes, 4096), 256, 0, s>>>(n, row_ptr, col, even ? lab0 : lab1,
+                                                                           even ? lab1 : lab0, changed, level);
             e = hipGetLastError();
             if (e == hipSuccess && (level + 1) % kGrowBatch == 0 && level + 1 < kMaxGrow) {
                 uint32_t last = 1u;
