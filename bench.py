@@ -365,7 +365,11 @@ def random_line(args, steps, warmup, budget_s):
     print(f"[random] {steps} steps in {elapsed:.3f} s, walk {np.mean(walk_ms):.2f} ms", flush=True)
     walk_s = float(np.mean(walk_ms)) / 1e3
     bpt = algorithmic_bytes_per_transition(B, args.prec == 32)
-    roofline = roofline_of(bpt, trans[-1], walk_s, args.prec, TRAFFIC_BYTES["random"], "k_walk_block")
+    # the counters were taken on the default configuration only
+    measured = (args.n == 262144 and args.prec == 32 and chains == 512 and not cell and not args.hash_slots
+                and not args.lanes and not args.sketch_slots and args.heavy_weight == 0.0)
+    roofline = roofline_of(bpt, trans[-1], walk_s, args.prec, TRAFFIC_BYTES["random"] if measured else None,
+                           "k_walk_block")
     if args.probe:
         # memory ceiling of the access pattern: a chase over a buffer of the
         # record set's size with one dependent random 64-byte block per step
