@@ -415,6 +415,15 @@ BLOCK_CASES = {
     "m_filter_split": (lambda: I.random_nonsym(2500, seed=25), 512,
                        dict(lanes_per_row=512, heavy_weight=0.2, sketch_slots=128, filter=1), False),
     "lanes1024": (lambda: I.random_nonsym(2000, seed=26), 1024, dict(lanes_per_row=1024), True),
+    # FP32 walks key the workgroup's tables by record offset: the M filter, spilled
+    # columns, replays and full tracking on those keys
+    "replay_mode_forced_tau_f32": (lambda: I.random_nonsym(3000, seed=22), 700,
+                                   dict(lanes_per_row=256, heavy_weight=0.3), True),
+    "spill_and_refine_f32": (lambda: I.random_nonsym(3000, seed=24), 300,
+                             dict(lanes_per_row=256, hash_slots=1024, heavy_weight=0.05, sketch_slots=64), True),
+    "track_all_block_f32": (lambda: I.cfg1(), 1000, dict(lanes_per_row=512, heavy_weight=-1.0), True),
+    "m_filter_split_f32": (lambda: I.random_nonsym(2500, seed=25), 512,
+                           dict(lanes_per_row=512, heavy_weight=0.2, sketch_slots=128, filter=1), True),
 }
 
 

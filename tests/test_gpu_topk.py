@@ -28,6 +28,8 @@ CASES = {
                                 {"lanes_per_row": 512, "walk_prec": 32}),
     "nonsym_wave_k12_eps0": (lambda: I.random_nonsym(800, kmin=3, kmax=6, seed=33), 32, 1e-3, 0.0, 12, {}),
     "filter_m_k16": (lambda: I.random_nonsym(900, seed=34), 128, 1e-4, 1e-3, 16, {"filter": 1}),
+    "filter_m_block_k16_f32": (lambda: I.random_nonsym(900, seed=35), 256, 1e-4, 1e-3, 16,
+                               {"lanes_per_row": 256, "walk_prec": 32, "filter": 1}),
 }
 
 
