@@ -42,6 +42,14 @@ using namespace walkdev;
 // 2, 3, 4, 8 and 16 rows took 63.0, 61.9, 61.7, 62.2 and 71.5 ms.
 constexpr int kTaskChunk = 4;
 
+// Compare-exchange of a bitonic pass: a keeps the smaller word of an ascending
+// pair (up), the larger of a descending one.
+__device__ __forceinline__ void exch(uint64_t &a, uint64_t &b, bool up) {
+    const uint64_t lo = a < b ? a : b, hi = a < b ? b : a;
+    a = up ? lo : hi;
+    b = up ? hi : lo;
+}
+
 __device__ __forceinline__ int64_t next_task(const WalkArgs &a, int &queue, int64_t &lo, int64_t &hi) {
     if (lo < hi) return lo++;
     const int lane = lane_id();
@@ -459,15 +467,35 @@ __device__ __forceinline__ void walk_rows(const WalkArgs &a, const RowPre &cur, 
             for (int s = lane; s < PS; s += 64) pk[s] = s < K ? ((uint64_t)(uint32_t)tk[s] << 13) | (uint64_t)s : ~0ull;
             wave_sync();
             for (int k = 2; k <= PS; k <<= 1) {
-                for (int jj = k >> 1; jj > 0; jj >>= 1) {
+                int jj = k >> 1;
+                // two passes per LDS round trip: a lane takes the four words b, b + h,
+                // b + jj, b + jj + h (h = jj / 2; b with bits h and jj clear) and
+                // applies the exchanges at distance jj, then at distance h
+                for (; jj >= 2; jj >>= 2) {
+                    const int h = jj >> 1;
+                    const int ph = __builtin_ctz((unsigned)h);
+                    for (int g = lane; g < (PS >> 2); g += 64) {
+                        const int b = ((g >> ph) << (ph + 2)) | (g & (h - 1));
+                        const bool up = (b & k) == 0;
+                        uint64_t e0 = pk[b], e1 = pk[b + h], e2 = pk[b + jj], e3 = pk[b + jj + h];
+                        exch(e0, e2, up);
+                        exch(e1, e3, up);
+                        exch(e0, e1, up);
+                        exch(e2, e3, up);
+                        pk[b] = e0;
+                        pk[b + h] = e1;
+                        pk[b + jj] = e2;
+                        pk[b + jj + h] = e3;
+                    }
+                    wave_sync();
+                }
+                if (jj == 1) {
                     for (int pr = lane; pr < (PS >> 1); pr += 64) {
-                        const int i = ((pr & ~(jj - 1)) << 1) | (pr & (jj - 1));
-                        const int ixj = i | jj;
-                        const uint64_t ea = pk[i], eb = pk[ixj];
-                        if ((ea > eb) == ((i & k) == 0)) {
-                            pk[i] = eb;
-                            pk[ixj] = ea;
-                        }
+                        const int i = pr << 1;
+                        uint64_t ea = pk[i], eb = pk[i + 1];
+                        exch(ea, eb, (i & k) == 0);
+                        pk[i] = ea;
+                        pk[i + 1] = eb;
                     }
                     wave_sync();
                 }
