@@ -263,6 +263,19 @@ __device__ __forceinline__ void run_chains(const WalkArgs &a, const RowCtx &rc, 
     }
 }
 
+// Compare-exchange of a bitonic pass on (column, value) pairs: the first keeps
+// the smaller column of an ascending pair (up), the larger of a descending one.
+__device__ __forceinline__ void exch_kv(int32_t &ka, double &va, int32_t &kb, double &vb, bool up) {
+    if ((ka > kb) == up) {
+        const int32_t tk = ka;
+        ka = kb;
+        kb = tk;
+        const double tv = va;
+        va = vb;
+        vb = tv;
+    }
+}
+
 template <int kLPR>
 __device__ __forceinline__ float block_max(float v, float *red) {
     const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -506,21 +519,44 @@ __device__ __forceinline__ void block_row(const WalkArgs &a, const RowPre &cur, 
     while (P < K) P <<= 1;
     for (int s = K + tid; s < P; s += kLPR) rc.keys[s] = INT32_MAX;
     __syncthreads();
+    // two bitonic passes per barrier: a thread takes the entries b, b + h, b + jj,
+    // b + jj + h (h = jj / 2; b with bits h and jj clear) and applies the
+    // exchanges at distance jj, then at distance h
     for (int k = 2; k <= P; k <<= 1) {
-        for (int jj = k >> 1; jj > 0; jj >>= 1) {
-            for (int i = tid; i < P; i += kLPR) {
-                const int ixj = i ^ jj;
-                if (ixj > i) {
-                    const int32_t ka = rc.keys[i], kb = rc.keys[ixj];
-                    const bool up = (i & k) == 0;
-                    if ((ka > kb) == up) {
-                        const double va = rc.vals[i], vb = rc.vals[ixj];
-                        rc.keys[i] = kb;
-                        rc.keys[ixj] = ka;
-                        rc.vals[i] = vb;
-                        rc.vals[ixj] = va;
-                    }
-                }
+        int jj = k >> 1;
+        for (; jj >= 2; jj >>= 2) {
+            const int h = jj >> 1;
+            const int ph = __builtin_ctz((unsigned)h);
+            for (int g = tid; g < (P >> 2); g += kLPR) {
+                const int b = ((g >> ph) << (ph + 2)) | (g & (h - 1));
+                const bool up = (b & k) == 0;
+                int32_t k0 = rc.keys[b], k1 = rc.keys[b + h], k2 = rc.keys[b + jj], k3 = rc.keys[b + jj + h];
+                double v0 = rc.vals[b], v1 = rc.vals[b + h], v2 = rc.vals[b + jj], v3 = rc.vals[b + jj + h];
+                exch_kv(k0, v0, k2, v2, up);
+                exch_kv(k1, v1, k3, v3, up);
+                exch_kv(k0, v0, k1, v1, up);
+                exch_kv(k2, v2, k3, v3, up);
+                rc.keys[b] = k0;
+                rc.keys[b + h] = k1;
+                rc.keys[b + jj] = k2;
+                rc.keys[b + jj + h] = k3;
+                rc.vals[b] = v0;
+                rc.vals[b + h] = v1;
+                rc.vals[b + jj] = v2;
+                rc.vals[b + jj + h] = v3;
+            }
+            __syncthreads();
+        }
+        if (jj == 1) {
+            for (int pr = tid; pr < (P >> 1); pr += kLPR) {
+                const int i = pr << 1;
+                int32_t ka = rc.keys[i], kb = rc.keys[i + 1];
+                double va = rc.vals[i], vb = rc.vals[i + 1];
+                exch_kv(ka, va, kb, vb, (i & k) == 0);
+                rc.keys[i] = ka;
+                rc.keys[i + 1] = kb;
+                rc.vals[i] = va;
+                rc.vals[i + 1] = vb;
             }
             __syncthreads();
         }
