@@ -45,21 +45,21 @@ TRAFFIC_BYTES = {
     # FETCH_SIZE x 2.000 + WRITE_SIZE x 1.000 (the factors that make a plain 1 GiB
     # device copy read 1 GiB), KiB -> bytes, one walk launch of the default
     # configuration of each workload
-    "aniso27": None,  # k_walk changed (finalize sort) since the last counters
+    "aniso27": (1.1611e8 * 2.0 + 8.5626e6) * 1024.0,
     "random": (1.8886e8 * 2.0 + 1.9607e6) * 1024.0,
-    "batched": None,
+    "batched": (1.1050e8 * 2.0 + 5.8260e7) * 1024.0,
 }
 # Instruction issue of the 160^3 walk (k_walk<true, 64, 1, true>) from rocprofv3 SQ
-# counters of one launch (wave-summed quad cycles over SQ_WAVE_CYCLES = 1.1237e11,
+# counters of one launch (wave-summed quad cycles over SQ_WAVE_CYCLES = 1.035e11,
 # 3072 waves, 3 per SIMD, the LDS tables allowing no more): the walk is bound by
 # each wave's issue and waits, not by HBM (with every bucket read served from a
 # 128 MB region the walk was not faster per transition)
 ISSUE = {
-    "aniso27": {"waves_per_simd": 3, "valu_busy_per_simd": round(2.2294e10 / 1.1237e11 * 3, 3),
-                "salu_busy_per_simd": round(1.6211e10 / 1.1237e11 * 3, 3),
-                "wave_issuing": round(4.9211e10 / 1.1237e11, 3), "wave_waiting_on_memory_or_lds": round(
-                    5.1968e10 / 1.1237e11, 3), "valu_insts_per_transition": 3.36, "salu_insts_per_transition": 2.45,
-                "lds_insts_per_transition": 0.42,
+    "aniso27": {"waves_per_simd": 3, "valu_busy_per_simd": round(2.286e10 / 1.035e11 * 3, 3),
+                "salu_busy_per_simd": round(1.462e10 / 1.035e11 * 3, 3),
+                "wave_issuing": round(4.626e10 / 1.035e11, 3), "wave_waiting_on_memory_or_lds": round(
+                    4.471e10 / 1.035e11, 3), "valu_insts_per_transition": 3.45, "salu_insts_per_transition": 2.21,
+                "lds_insts_per_transition": 0.33,
                 "counters": "SQ_ACTIVE_INST_VALU, SQ_ACTIVE_INST_SCA, SQ_ACTIVE_INST_ANY, SQ_WAIT_ANY, "
                             "SQ_WAVE_CYCLES, SQ_INSTS_VALU, SQ_INSTS_SALU, SQ_INSTS_LDS"},
 }
